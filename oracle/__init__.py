@@ -1,0 +1,293 @@
+"""Python access to the FP64 reference of the reverse ray tracer.
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the CPU-baseline
+leg of the benchmark use this package; the product library never does.  All
+arithmetic lives in ``oracle.c`` (plain C, FP64, serial per source particle)
+plus the short plain-Python slab solvers below; nothing here is shared with the
+HIP path, which it checks.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+GCC_FLAGS = ["-O2", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+             "-Wall"]
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into liboracle.so beside it."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", *GCC_FLAGS, "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        L = C.CDLL(_LIB)
+        d, i32, i64, vp = C.c_double, C.c_int32, C.c_int64, C.c_void_p
+        L.orc_kernel_constants.argtypes = [vp]
+        L.orc_Gt.argtypes = [d, d]; L.orc_Gt.restype = d
+        L.orc_M4.argtypes = [d, d]; L.orc_M4.restype = d
+        L.orc_chord_closed.argtypes = [d, d, d, d]; L.orc_chord_closed.restype = d
+        L.orc_chord_quad.argtypes = [d, d, d, d, d]; L.orc_chord_quad.restype = d
+        L.orc_gk15_poly.argtypes = [d, d, d, vp, vp]
+        L.orc_kernel_norm.argtypes = [d, i32]; L.orc_kernel_norm.restype = d
+        L.orc_columns.argtypes = [i64, vp, vp, vp, vp, i32, vp, d, d, i64, vp, d, i32,
+                                  vp, vp, vp, vp, vp, i32]
+        L.orc_columns.restype = C.c_int
+        L.orc_gamma.argtypes = [i64, i32, vp, i32, vp, vp, vp, vp, vp]
+        for f in ("orc_alpha_A", "orc_alpha_B", "orc_gamma_coll"):
+            getattr(L, f).argtypes = [d]; getattr(L, f).restype = d
+        L.orc_xeq.argtypes = [d, d, d, d, d]; L.orc_xeq.restype = d
+        L.orc_solve.argtypes = [i64, vp, vp, vp, vp, vp, i32, vp, i32, vp, vp, d, d, d, i32,
+                                vp, d, i32, vp, vp, vp, vp, vp]
+        L.orc_solve.restype = C.c_int
+        L.orc_morton.argtypes = [i64, vp, vp]
+        L.orc_lbvh.argtypes = [i64, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]
+        L.orc_lbvh.restype = i64
+        _lib = L
+    return _lib
+
+
+def _p(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _c(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+DEFAULT_RTOL = 1e-13
+# threads the oracle may spread independent source particles over (0 = OpenMP default)
+N_THREADS = int(os.environ.get("RRT_ORACLE_THREADS", "0"))
+
+
+# ----------------------------------------------------------------------------
+# kernel (Sec. 4.1.1)
+# ----------------------------------------------------------------------------
+def kernel_constants() -> dict:
+    out = np.zeros(4)
+    lib().orc_kernel_constants(_p(out))
+    return dict(t=out[0], A2h2=out[1], sigma_over_h=out[2], Nh3=out[3])
+
+
+def Gt(r: float, h: float) -> float:
+    return lib().orc_Gt(float(r), float(h))
+
+
+def M4(r: float, h: float) -> float:
+    return lib().orc_M4(float(r), float(h))
+
+
+def chord_closed(h, b, z1, z2) -> float:
+    return lib().orc_chord_closed(float(h), float(b), float(z1), float(z2))
+
+
+def chord_quad(h, b, z1, z2, rtol=DEFAULT_RTOL) -> float:
+    return lib().orc_chord_quad(float(h), float(b) ** 2, float(z1), float(z2), float(rtol))
+
+
+def gk15_poly(p, a, b):
+    k, e = np.zeros(1), np.zeros(1)
+    lib().orc_gk15_poly(float(p), float(a), float(b), _p(k), _p(e))
+    return float(k[0]), float(e[0])
+
+
+def kernel_norm(h: float, which: str = "Gt") -> float:
+    return lib().orc_kernel_norm(float(h), 0 if which == "Gt" else 1)
+
+
+# ----------------------------------------------------------------------------
+# columns, rates, equilibrium (Sec. 3.3, 4.1.1, Appendix C.3)
+# ----------------------------------------------------------------------------
+def columns(wl, x: np.ndarray, sources=None, hits: bool = False, rtol=DEFAULT_RTOL,
+            n_threads: int = None):
+    """Columns N[src, k] in cm^-2 for the given source particles (all by default).
+
+    With ``hits=True`` also returns (row_off, hit_j, hit_img): the hit list of
+    ray (src_i, k) is hit_j[row_off[i*n_ray+k] : row_off[i*n_ray+k+1]] with the
+    periodic image code (sx+8) | (sy+8)<<4 | (sz+8)<<8 in hit_img.
+    """
+    L = lib()
+    n = wl.n
+    src = _c(np.arange(n) if sources is None else sources, np.int64)
+    pos, h, mu = _c(wl.pos, np.float32), _c(wl.h, np.float32), _c(wl.mu, np.float32)
+    xx, dirs = _c(x, np.float64), _c(wl.dirs, np.float64)
+    nt = N_THREADS if n_threads is None else n_threads
+    N = np.zeros((src.size, wl.n_ray), np.float64)
+    if not hits:
+        rc = L.orc_columns(n, _p(pos), _p(h), _p(mu), _p(xx), wl.n_ray, _p(dirs), wl.l_ray,
+                           wl.box, src.size, _p(src), rtol, 1, _p(N), None, None, None, None, nt)
+        assert rc == 0
+        return N
+    cnt = np.zeros(src.size * wl.n_ray, np.int64)
+    rc = L.orc_columns(n, _p(pos), _p(h), _p(mu), _p(xx), wl.n_ray, _p(dirs), wl.l_ray, wl.box,
+                       src.size, _p(src), rtol, 0, None, _p(cnt), None, None, None, nt)
+    assert rc == 0
+    off = np.zeros(cnt.size + 1, np.int64)
+    off[1:] = np.cumsum(cnt)
+    hj = np.zeros(max(1, int(off[-1])), np.int32)
+    hi = np.zeros(max(1, int(off[-1])), np.int32)
+    rc = L.orc_columns(n, _p(pos), _p(h), _p(mu), _p(xx), wl.n_ray, _p(dirs), wl.l_ray, wl.box,
+                       src.size, _p(src), rtol, 1, _p(N), None, _p(off[:-1].copy()), _p(hj),
+                       _p(hi), nt)
+    assert rc == 0
+    return N, off, hj[: off[-1]], hi[: off[-1]]
+
+
+def gamma(N: np.ndarray, sigma: np.ndarray, w: np.ndarray):
+    """(ln Gamma, Gamma, tau_eff) per source from columns N[src, k]."""
+    N = _c(N, np.float64)
+    ns, nr = N.shape
+    lnG, G, tau = np.zeros(ns), np.zeros(ns), np.zeros(ns)
+    lib().orc_gamma(ns, nr, _p(N), sigma.size, _p(_c(sigma, np.float64)), _p(_c(w, np.float64)),
+                    _p(lnG), _p(G), _p(tau))
+    return lnG, G, tau
+
+
+def alpha_A(T):
+    return np.array([lib().orc_alpha_A(float(t)) for t in np.atleast_1d(T)])
+
+
+def alpha_B(T):
+    return np.array([lib().orc_alpha_B(float(t)) for t in np.atleast_1d(T)])
+
+
+def gamma_coll(T):
+    return np.array([lib().orc_gamma_coll(float(t)) for t in np.atleast_1d(T)])
+
+
+def xeq(Gamma, nH, alpha, gcoll, y=0.0):
+    f = lib().orc_xeq
+    G, n, a, g = np.broadcast_arrays(np.asarray(Gamma, float), np.asarray(nH, float),
+                                     np.asarray(alpha, float), np.asarray(gcoll, float))
+    return np.array([f(float(G.flat[i]), float(n.flat[i]), float(a.flat[i]), float(g.flat[i]),
+                       float(y)) for i in range(G.size)]).reshape(G.shape)
+
+
+def gamma_thin(wl) -> float:
+    return float(np.sum(wl.w * wl.sigma))
+
+
+def x_thin(wl) -> np.ndarray:
+    T = wl.T.astype(np.float64)
+    return xeq(gamma_thin(wl), wl.n_H.astype(np.float64), alpha_A(T), gamma_coll(T))
+
+
+def step(wl, x: np.ndarray, sources=None, rtol=DEFAULT_RTOL):
+    """One order-independent update for the given sources from the state x.
+
+    Returns dict with N, lnG, G, tau, x_new for those sources."""
+    src = np.arange(wl.n) if sources is None else np.asarray(sources)
+    N = columns(wl, x, src, rtol=rtol)
+    lnG, G, tau = gamma(N, wl.sigma, wl.w)
+    T = wl.T[src].astype(np.float64)
+    xn = xeq(G, wl.n_H[src].astype(np.float64), alpha_A(T), gamma_coll(T))
+    return dict(N=N, lnG=lnG, G=G, tau=tau, x_new=xn)
+
+
+def solve(wl, max_iter: int = None, tol: float = None, x_init=None, rtol=DEFAULT_RTOL,
+          n_threads: int = None):
+    """The full fixed point.  Returns dict(x_hist, lnG_hist, N_last, iters, maxdx)."""
+    n = wl.n
+    mi = wl.max_iter if max_iter is None else max_iter
+    tl = wl.tol if tol is None else tol
+    xh = np.zeros((mi + 1, n))
+    lh = np.zeros((mi, n))
+    Nl = np.zeros((n, wl.n_ray))
+    it = np.zeros(1, np.int32)
+    md = np.zeros(max(1, mi))
+    xi = None if x_init is None else _c(x_init, np.float64)
+    nt = N_THREADS if n_threads is None else n_threads
+    rc = lib().orc_solve(n, _p(_c(wl.pos, np.float32)), _p(_c(wl.h, np.float32)),
+                         _p(_c(wl.mu, np.float32)), _p(_c(wl.n_H, np.float32)),
+                         _p(_c(wl.T, np.float32)), wl.n_ray, _p(_c(wl.dirs, np.float64)),
+                         wl.n_bins, _p(_c(wl.sigma, np.float64)), _p(_c(wl.w, np.float64)),
+                         wl.l_ray, wl.box, tl, mi, _p(xi), rtol, nt, _p(xh), _p(lh), _p(Nl),
+                         _p(it), _p(md))
+    assert rc == 0
+    k = int(it[0])
+    return dict(x_hist=xh[: k + 1], lnG_hist=lh[:k], N_last=Nl, iters=k, maxdx=md[:k])
+
+
+# ----------------------------------------------------------------------------
+# reference tree
+# ----------------------------------------------------------------------------
+def morton(pos: np.ndarray) -> np.ndarray:
+    pos = _c(pos, np.float32)
+    out = np.zeros(pos.shape[0], np.uint64)
+    lib().orc_morton(pos.shape[0], _p(pos), _p(out))
+    return out
+
+
+def lbvh(pos: np.ndarray, h: np.ndarray, leaf_max: int) -> dict:
+    pos, h = _c(pos, np.float32), _c(h, np.float32)
+    n = pos.shape[0]
+    m = 2 * n
+    perm = np.zeros(n, np.int32)
+    codes = np.zeros(n, np.uint64)
+    lo = np.zeros((m, 3), np.float32)
+    hi = np.zeros((m, 3), np.float32)
+    skip = np.zeros(m, np.int32)
+    first = np.zeros(m, np.int32)
+    count = np.zeros(m, np.int32)
+    nn = lib().orc_lbvh(n, _p(pos), _p(h), leaf_max, _p(perm), _p(codes), _p(lo), _p(hi),
+                        _p(skip), _p(first), _p(count))
+    assert nn > 0
+    return dict(perm=perm, codes=codes, lo=lo[:nn], hi=hi[:nn], skip=skip[:nn],
+                first=first[:nn], count=count[:nn], n_nodes=int(nn))
+
+
+# ----------------------------------------------------------------------------
+# plane-parallel slab (Appendix C.4 and the slab solver of Sec. 5.1)
+# ----------------------------------------------------------------------------
+def slab_depth_analytic(x, x0, x_ce, nH, sigma):
+    """Depth z at which the neutral fraction is x (Appendix C.4, eq. analytic_slab_eqn):
+    z n_H sigma = (1/x0 - 1/x) + ln[x(1-x0)/(x0(1-x))] + (1/x_ce) ln[x(x_ce-x0)/(x0(x_ce-x))]."""
+    x = np.asarray(x, dtype=np.float64)
+    t = (1.0 / x0 - 1.0 / x) + np.log(x * (1.0 - x0) / (x0 * (1.0 - x))) + \
+        (1.0 / x_ce) * np.log(x * (x_ce - x0) / (x0 * (x_ce - x)))
+    return t / (nH * sigma)
+
+
+def slab_numerical(Gamma0, nH, T, sigma, depth, n_slices):
+    """Monochromatic plane-parallel radiation on a uniform slab, solved slice by
+    slice from the surface inwards (the slab solver of Sec. 5.1): the HI optical
+    depth above a slice attenuates the surface rate, and the slice takes the
+    equilibrium root for that rate.  Returns slice-centre depths and x."""
+    a = float(alpha_A(T)[0])
+    g = float(gamma_coll(T)[0])
+    dz = depth / n_slices
+    z = (np.arange(n_slices) + 0.5) * dz
+    xs = np.zeros(n_slices)
+    tau = 0.0
+    f = lib().orc_xeq
+    for i in range(n_slices):
+        # the slice's own half-depth: solve x = x_-(Gamma0 exp(-(tau + x nH sigma dz/2)))
+        xi = f(Gamma0 * math.exp(-tau), nH, a, g, 0.0)
+        for _ in range(200):
+            xn = f(Gamma0 * math.exp(-(tau + 0.5 * xi * nH * sigma * dz)), nH, a, g, 0.0)
+            if abs(xn - xi) <= 1e-15 * max(xn, 1e-300):
+                xi = xn
+                break
+            xi = xn
+        xs[i] = xi
+        tau += xi * nH * sigma * dz
+    return z, xs

@@ -1,0 +1,544 @@
+/*
+ * FP64 reference ("oracle") for the reverse ray tracer of Altay & Theuns,
+ * "URCHIN: A Reverse Ray Tracer for Astrophysical Applications".
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark may load this library.  It shares no code with
+ * the HIP library: every quantity is recomputed here from the paper's
+ * definitions, serially per source particle (OpenMP only spreads independent
+ * source particles over threads; the arithmetic of each is unchanged).
+ *
+ * Build: gcc -O2 -fPIC -shared -ffp-contract=off -fno-fast-math -fopenmp
+ * (no FMA contraction: the segment-sphere predicate below must round exactly
+ * like the device predicate, operation for operation).
+ *
+ * What is computed, by section of the paper:
+ *  - G_t, the truncated Gaussian kernel and its constants (Sec. 4.1.1, eq. Gt)
+ *  - line integrals of G_t along a clipped chord by adaptive Gauss-Kronrod
+ *    quadrature (the definition behind the closed form I(h,b,z1,z2), Sec. 4.1.1)
+ *  - HI columns along every ray: sum over *every* particle and every periodic
+ *    image whose kernel sphere the ray segment enters (Sec. 4.1.1, eq. colden)
+ *  - the shielded rate Gamma from the per-ray columns (Sec. 3.3, eq. gamma_shld)
+ *  - the equilibrium neutral fraction, physical root x_- (Appendix C.3, eq. xroots)
+ *  - the fixed-point iteration x -> tau -> Gamma -> x (Sec. 3.3 and Sec. 4)
+ *  - a reference binary radix tree over 63-bit Morton keys, built top-down, for
+ *    the bit-exact comparison of the device tree.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#include "oracle.h"
+
+/* ------------------------------------------------------------------------- */
+/* Kernel constants, Sec. 4.1.1 (eq. Gt): sigma^2 = h^2/(8 pi^(1/3)),          */
+/* A^2 = 4 pi^(1/3)/h^2, t = 2 pi^(1/6), N = 8/(pi h^3) / [erf t - 2t e^-t^2/sqrt(pi)] */
+/* ------------------------------------------------------------------------- */
+static double c_t(void) { return 2.0 * pow(M_PI, 1.0 / 6.0); }
+static double c_A2h2(void) { return 4.0 * pow(M_PI, 1.0 / 3.0); }
+static double c_Nh3(void)
+{
+    double t = c_t();
+    return (8.0 / M_PI) / (erf(t) - 2.0 * t * exp(-t * t) / sqrt(M_PI));
+}
+
+void orc_kernel_constants(double* out4)
+{
+    double t = c_t();
+    out4[0] = t;                                 /* t                        */
+    out4[1] = c_A2h2();                          /* A^2 h^2                  */
+    out4[2] = sqrt(1.0 / (8.0 * pow(M_PI, 1.0 / 3.0)));  /* sigma / h        */
+    out4[3] = c_Nh3();                           /* N h^3                    */
+}
+
+/* G_t(r; h): the truncated Gaussian, zero beyond r = h. */
+double orc_Gt(double r, double h)
+{
+    if (r > h) return 0.0;
+    double A2 = c_A2h2() / (h * h);
+    return c_Nh3() / (h * h * h) * exp(-A2 * r * r);
+}
+
+/* M4 cubic spline with support h (Sec. 4.1.1, eq. spline). */
+double orc_M4(double r, double h)
+{
+    double q = r / h, f;
+    if (q <= 0.5) f = 1.0 - 6.0 * q * q + 6.0 * q * q * q;
+    else if (q <= 1.0) f = 2.0 * (1.0 - q) * (1.0 - q) * (1.0 - q);
+    else f = 0.0;
+    return 8.0 / (M_PI * h * h * h) * f;
+}
+
+/* The printed closed form I(h,b,z1,z2) for the untruncated Gaussian between z1, z2. */
+double orc_chord_closed(double h, double b, double z1, double z2)
+{
+    double A = sqrt(c_A2h2()) / h;
+    double N = c_Nh3() / (h * h * h);
+    return N * sqrt(M_PI) * exp(-A * A * b * b) / (2.0 * A) * (erf(A * z2) - erf(A * z1));
+}
+
+/* ------------------------------------------------------------------------- */
+/* Adaptive Gauss-Kronrod (7-point Gauss / 15-point Kronrod) quadrature.      */
+/* Nodes and weights are the standard published G7/K15 pair.                 */
+/* ------------------------------------------------------------------------- */
+static const double XGK[8] = {
+    0.991455371120812639206854697526329, 0.949107912342758524526189684047851,
+    0.864864423359769072789712788640926, 0.741531185599394439863864773280788,
+    0.586087235467691130294144845693013, 0.405845151377397166906606412076961,
+    0.207784955007898467600689403773245, 0.000000000000000000000000000000000};
+static const double WGK[8] = {
+    0.022935322010529224963732008058970, 0.063092092629978553290700663189204,
+    0.104790010322250183839876322541518, 0.140653259715525918745189590510238,
+    0.169004726639267902826583426598550, 0.190350578064785409913256402421014,
+    0.204432940075298892414161999234649, 0.209482141084727828012999174891714};
+static const double WG[4] = {
+    0.129484966168869693270611432679082, 0.279705391489276667901467771423780,
+    0.381830050505118944950369775488975, 0.417959183673469387755102040816327};
+
+typedef double (*orc_fn)(double z, const double* prm);
+
+static void gk15(orc_fn f, const double* prm, double a, double b, double* kr, double* err)
+{
+    double c = 0.5 * (a + b), hw = 0.5 * (b - a);
+    double fc = f(c, prm);
+    double rk = WGK[7] * fc, rg = WG[3] * fc;
+    for (int i = 0; i < 7; ++i) {
+        double dx = hw * XGK[i];
+        double s = f(c - dx, prm) + f(c + dx, prm);
+        rk += WGK[i] * s;
+        if (i & 1) rg += WG[i / 2] * s;   /* odd Kronrod nodes are the Gauss nodes */
+    }
+    *kr = rk * hw;
+    *err = fabs((rk - rg) * hw);
+}
+
+static double adapt(orc_fn f, const double* prm, double a, double b, double tol_abs, int depth)
+{
+    double k, e;
+    gk15(f, prm, a, b, &k, &e);
+    if (e <= tol_abs || depth >= 40) return k;
+    double m = 0.5 * (a + b);
+    return adapt(f, prm, a, m, 0.5 * tol_abs, depth + 1) +
+           adapt(f, prm, m, b, 0.5 * tol_abs, depth + 1);
+}
+
+double orc_integrate(orc_fn f, const double* prm, double a, double b, double tol_abs)
+{
+    if (!(b > a)) return 0.0;
+    return adapt(f, prm, a, b, tol_abs, 0);
+}
+
+/* integrand along the ray: G_t at distance sqrt(b^2 + z^2) from the centre */
+static double chord_integrand(double z, const double* prm)
+{
+    /* prm[0] = h, prm[1] = b^2 */
+    return orc_Gt(sqrt(prm[1] + z * z), prm[0]);
+}
+
+/* Line integral of G_t(.; h) at impact parameter^2 b2 from z1 to z2 (z along the
+ * ray, measured from the point of closest approach), to relative accuracy rtol of
+ * the full central chord.  Points beyond h contribute nothing (truncation). */
+double orc_chord_quad(double h, double b2, double z1, double z2, double rtol)
+{
+    double prm[2] = {h, b2};
+    double scale = c_Nh3() / (h * h);     /* order of the full central chord */
+    return orc_integrate(chord_integrand, prm, z1, z2, rtol * scale);
+}
+
+/* Polynomial integrand for pinning the quadrature rule itself. */
+static double poly_integrand(double z, const double* prm)
+{
+    return pow(z, prm[0]);
+}
+
+void orc_gk15_poly(double p, double a, double b, double* k15, double* err)
+{
+    double prm[1] = {p};
+    gk15(poly_integrand, prm, a, b, k15, err);
+}
+
+static double shell_integrand(double r, const double* prm)
+{
+    /* prm[0] = h, prm[1] = 0 for G_t, 1 for M4 */
+    return 4.0 * M_PI * r * r * (prm[1] == 0.0 ? orc_Gt(r, prm[0]) : orc_M4(r, prm[0]));
+}
+
+/* 4 pi int_0^h r^2 W(r) dr for W = G_t (which = 0) or M4 (which = 1). */
+double orc_kernel_norm(double h, int32_t which)
+{
+    double prm[2] = {h, (double)which};
+    /* M4 has a kink at h/2: integrate the two smooth pieces separately */
+    return orc_integrate(shell_integrand, prm, 0.0, 0.5 * h, 1e-15) +
+           orc_integrate(shell_integrand, prm, 0.5 * h, h, 1e-15);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Segment / kernel-sphere predicate.                                        */
+/* d = (r_j - r_p) + s B, s_par = d.u, t = clamp(s_par, 0, L),               */
+/* c = d - t u, hit <=> |c|^2 < h_j^2.  Fixed operation order, no FMA.       */
+/* ------------------------------------------------------------------------- */
+static inline int seg_hit(const double d[3], const double u[3], double L, double h,
+                          double* s_par)
+{
+    double sp = d[0] * u[0] + d[1] * u[1] + d[2] * u[2];
+    double t = sp < 0.0 ? 0.0 : (sp > L ? L : sp);
+    double cx = d[0] - t * u[0];
+    double cy = d[1] - t * u[1];
+    double cz = d[2] - t * u[2];
+    double D2 = cx * cx + cy * cy + cz * cz;
+    *s_par = sp;
+    return D2 < h * h;
+}
+
+/* Range of periodic image shifts along one axis that can bring a particle within
+ * h_max of the segment's extent [smin, smax]; particles lie in [plo, phi]. */
+static void image_range(double smin, double smax, double plo, double phi, double hmax,
+                        double B, int* lo, int* hi)
+{
+    double a = (smin - hmax - phi) / B, b = (smax + hmax - plo) / B;
+    *lo = (int)ceil(a - 1e-9);
+    *hi = (int)floor(b + 1e-9);
+}
+
+/* The HI column contributed by particle j with offset d from the ray origin. */
+static double hit_column(const double d[3], const double u[3], double sp, double L, double h,
+                         double mux, double rtol)
+{
+    double px = d[0] - sp * u[0], py = d[1] - sp * u[1], pz = d[2] - sp * u[2];
+    double b2 = px * px + py * py + pz * pz;           /* impact parameter^2   */
+    double l2 = h * h - b2;
+    double l = l2 > 0.0 ? sqrt(l2) : 0.0;              /* half chord in sphere */
+    double z1 = (-sp > -l) ? -sp : -l;                 /* clip to the segment  */
+    double z2 = (L - sp < l) ? L - sp : l;
+    if (!(z2 > z1)) return 0.0;
+    return mux * orc_chord_quad(h, b2, z1, z2, rtol);
+}
+
+/* Columns N[src][k] for selected source particles.  mu*x gives atoms/kpc_cm^2 and
+ * the kernel integral is in kpc^-2, so N is in cm^-2.
+ *   mode 0: count hits only (row_hits), no integrals
+ *   mode 1: columns (N_out), optional hit lists written at row offsets row_off */
+int orc_columns(int64_t n, const float* pos, const float* h, const float* mu, const double* x,
+                int32_t n_ray, const double* dirs, double L, double box,
+                int64_t n_src, const int64_t* src, double rtol, int32_t mode,
+                double* N_out, int64_t* row_hits, const int64_t* row_off,
+                int32_t* hit_j, int32_t* hit_img, int32_t n_threads)
+{
+    if (n <= 0 || n_ray <= 0 || n_src < 0) return -1;
+    double plo[3] = {INFINITY, INFINITY, INFINITY}, phi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    double hmax = 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+        for (int a = 0; a < 3; ++a) {
+            double v = pos[3 * j + a];
+            if (v < plo[a]) plo[a] = v;
+            if (v > phi[a]) phi[a] = v;
+        }
+        if (h[j] > hmax) hmax = h[j];
+    }
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#else
+    (void)n_threads;
+#endif
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t si = 0; si < n_src; ++si) {
+        int64_t p = src[si];
+        double rp[3] = {pos[3 * p], pos[3 * p + 1], pos[3 * p + 2]};
+        for (int k = 0; k < n_ray; ++k) {
+            const double* u = dirs + 3 * k;
+            int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+            if (box > 0.0) {
+                for (int a = 0; a < 3; ++a) {
+                    double e = rp[a] + L * u[a];
+                    double smin = rp[a] < e ? rp[a] : e, smax = rp[a] < e ? e : rp[a];
+                    image_range(smin, smax, plo[a], phi[a], hmax, box, &lo[a], &hi[a]);
+                }
+            }
+            double col = 0.0;
+            int64_t cnt = 0;
+            int64_t w = row_off ? row_off[si * n_ray + k] : 0;
+            for (int sx = lo[0]; sx <= hi[0]; ++sx)
+            for (int sy = lo[1]; sy <= hi[1]; ++sy)
+            for (int sz = lo[2]; sz <= hi[2]; ++sz) {
+                double sh[3] = {(double)sx * box, (double)sy * box, (double)sz * box};
+                if (box <= 0.0) sh[0] = sh[1] = sh[2] = 0.0;
+                for (int64_t j = 0; j < n; ++j) {
+                    double d[3];
+                    for (int a = 0; a < 3; ++a)
+                        d[a] = ((double)pos[3 * j + a] - rp[a]) + sh[a];
+                    double sp;
+                    double hj = (double)h[j];
+                    if (!seg_hit(d, u, L, hj, &sp)) continue;
+                    ++cnt;
+                    if (mode == 1) {
+                        col += hit_column(d, u, sp, L, hj, (double)mu[j] * x[j], rtol);
+                        if (hit_j) {
+                            hit_j[w] = (int32_t)j;
+                            if (hit_img)
+                                hit_img[w] = (sx + 8) | ((sy + 8) << 4) | ((sz + 8) << 8);
+                            ++w;
+                        }
+                    }
+                }
+            }
+            if (row_hits) row_hits[si * n_ray + k] = cnt;
+            if (mode == 1 && N_out) N_out[si * n_ray + k] = col;
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Shielded photoionisation rate, Sec. 3.3 eq. gamma_shld with the frequency  */
+/* integral done over bins: Gamma = (1/N_ray) sum_k sum_b w_b sigma_b         */
+/* exp(-sigma_b N_k).  ln Gamma by a log-sum-exp over all (k, b) terms.       */
+/* ------------------------------------------------------------------------- */
+void orc_gamma(int64_t n_src, int32_t n_ray, const double* N, int32_t n_bins,
+               const double* sigma, const double* w, double* lnG, double* G, double* tau)
+{
+    double thin = 0.0;
+    for (int b = 0; b < n_bins; ++b) thin += w[b] * sigma[b];
+    double lnthin = log(thin);
+    for (int64_t p = 0; p < n_src; ++p) {
+        double m = -INFINITY;
+        for (int k = 0; k < n_ray; ++k)
+            for (int b = 0; b < n_bins; ++b) {
+                double v = log(w[b] * sigma[b]) - sigma[b] * N[p * n_ray + k];
+                if (v > m) m = v;
+            }
+        double s = 0.0;
+        for (int k = 0; k < n_ray; ++k)
+            for (int b = 0; b < n_bins; ++b)
+                s += exp(log(w[b] * sigma[b]) - sigma[b] * N[p * n_ray + k] - m);
+        double l = m + log(s) - log((double)n_ray);
+        if (lnG) lnG[p] = l;
+        if (G) G[p] = exp(l);
+        if (tau) tau[p] = lnthin - l;
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Rates.  The paper defers to published fits (Appendix C.3); this reading    */
+/* takes the Hui & Gnedin (1997) case A / case B recombination fits and the   */
+/* Cen (1992) collisional ionisation fit, all in cm^3 s^-1.                   */
+/* ------------------------------------------------------------------------- */
+double orc_alpha_A(double T)
+{
+    double lam = 2.0 * 157807.0 / T;
+    return 1.269e-13 * pow(lam, 1.503) / pow(1.0 + pow(lam / 0.522, 0.470), 1.923);
+}
+
+double orc_alpha_B(double T)
+{
+    double lam = 2.0 * 157807.0 / T;
+    return 2.753e-14 * pow(lam, 1.500) / pow(1.0 + pow(lam / 2.740, 0.407), 2.242);
+}
+
+double orc_gamma_coll(double T)
+{
+    return 5.85e-11 * sqrt(T) * exp(-157809.1 / T) / (1.0 + sqrt(T / 1e5));
+}
+
+/* Physical root x_- of R x^2 + Q x + P = 0 (Appendix C.3, eq. xroots) with
+ * R = (gamma + alpha) n_H, Q = -[Gamma + alpha n_H + R (1 + y)],
+ * P = alpha n_H (1 + y).  Evaluated as 2P / (-Q + sqrt(Q^2 - 4PR)), which equals
+ * (-Q - sqrt(Q^2 - 4PR)) / (2R) exactly (Vieta) without its cancellation. */
+double orc_xeq(double Gamma, double nH, double alpha, double gcoll, double y)
+{
+    double R = (gcoll + alpha) * nH;
+    double Q = -(Gamma + alpha * nH + R * (1.0 + y));
+    double P = alpha * nH * (1.0 + y);
+    double D = Q * Q - 4.0 * P * R;
+    if (D < 0.0) D = 0.0;
+    return 2.0 * P / (-Q + sqrt(D));
+}
+
+/* ------------------------------------------------------------------------- */
+/* The fixed point (Sec. 3.3, Sec. 4): x0 = x_thin (or x_init); each iteration */
+/* computes every column from the current x, then Gamma, then every x at once  */
+/* (the order-independent update the paper describes for parallel use).       */
+/* Stops when max|dx| < tol or after max_iter iterations.                      */
+/* ------------------------------------------------------------------------- */
+int orc_solve(int64_t n, const float* pos, const float* h, const float* mu, const float* nH,
+              const float* T, int32_t n_ray, const double* dirs, int32_t n_bins,
+              const double* sigma, const double* w, double L, double box, double tol,
+              int32_t max_iter, const double* x_init, double rtol, int32_t n_threads,
+              double* x_hist /*[(max_iter+1)][n]*/, double* lnG_hist /*[max_iter][n]*/,
+              double* N_last /*[n][n_ray]*/, int32_t* iters_done, double* maxdx_hist)
+{
+    double thin = 0.0;
+    for (int b = 0; b < n_bins; ++b) thin += w[b] * sigma[b];
+    double* x = (double*)malloc(sizeof(double) * n);
+    double* Nc = (double*)malloc(sizeof(double) * n * n_ray);
+    double* lnG = (double*)malloc(sizeof(double) * n);
+    double* G = (double*)malloc(sizeof(double) * n);
+    int64_t* src = (int64_t*)malloc(sizeof(int64_t) * n);
+    double* al = (double*)malloc(sizeof(double) * n);
+    double* ga = (double*)malloc(sizeof(double) * n);
+    if (!x || !Nc || !lnG || !G || !src || !al || !ga) return -2;
+    for (int64_t p = 0; p < n; ++p) {
+        src[p] = p;
+        al[p] = orc_alpha_A((double)T[p]);
+        ga[p] = orc_gamma_coll((double)T[p]);
+        x[p] = x_init ? x_init[p] : orc_xeq(thin, (double)nH[p], al[p], ga[p], 0.0);
+    }
+    if (x_hist) memcpy(x_hist, x, sizeof(double) * n);
+    int it = 0;
+    for (it = 0; it < max_iter; ++it) {
+        orc_columns(n, pos, h, mu, x, n_ray, dirs, L, box, n, src, rtol, 1, Nc, NULL, NULL,
+                    NULL, NULL, n_threads);
+        orc_gamma(n, n_ray, Nc, n_bins, sigma, w, lnG, G, NULL);
+        double mdx = 0.0;
+        for (int64_t p = 0; p < n; ++p) {
+            double xn = orc_xeq(G[p], (double)nH[p], al[p], ga[p], 0.0);
+            double dx = fabs(xn - x[p]);
+            if (dx > mdx) mdx = dx;
+            x[p] = xn;
+        }
+        if (x_hist) memcpy(x_hist + (size_t)(it + 1) * n, x, sizeof(double) * n);
+        if (lnG_hist) memcpy(lnG_hist + (size_t)it * n, lnG, sizeof(double) * n);
+        if (maxdx_hist) maxdx_hist[it] = mdx;
+        if (mdx < tol) { ++it; break; }
+    }
+    if (N_last) memcpy(N_last, Nc, sizeof(double) * n * n_ray);
+    if (iters_done) *iters_done = it;
+    free(x); free(Nc); free(lnG); free(G); free(src); free(al); free(ga);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Reference radix tree.  Keys: 63-bit Morton codes (21 bits per axis, x in   */
+/* the highest position of each triple) of positions quantised over the      */
+/* cube of side max extent anchored at the minimum corner; ties broken by the */
+/* position in the sorted order.  Built top-down: a range splits where the    */
+/* highest differing bit of its first and last (key, position) changes.      */
+/* Ranges of at most leaf_max particles become leaves.  Nodes are emitted in  */
+/* depth-first pre-order; skip = index of the first node after the subtree.   */
+/* Boxes are exact FP32 min/max of (r - h, r + h).                            */
+/* ------------------------------------------------------------------------- */
+static uint64_t spread21(uint64_t v)
+{
+    uint64_t r = 0;
+    for (int i = 0; i < 21; ++i) r |= ((v >> i) & 1ull) << (3 * i);
+    return r;
+}
+
+void orc_morton(int64_t n, const float* pos, uint64_t* codes)
+{
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t j = 0; j < n; ++j)
+        for (int a = 0; a < 3; ++a) {
+            float v = pos[3 * j + a];
+            if (v < lo[a]) lo[a] = v;
+            if (v > hi[a]) hi[a] = v;
+        }
+    double ext = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        double e = (double)hi[a] - (double)lo[a];
+        if (e > ext) ext = e;
+    }
+    double scale = ext > 0.0 ? 2097152.0 / ext : 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+        uint64_t q[3];
+        for (int a = 0; a < 3; ++a) {
+            double v = floor(((double)pos[3 * j + a] - (double)lo[a]) * scale);
+            if (v < 0.0) v = 0.0;
+            if (v > 2097151.0) v = 2097151.0;
+            q[a] = (uint64_t)v;
+        }
+        codes[j] = (spread21(q[0]) << 2) | (spread21(q[1]) << 1) | spread21(q[2]);
+    }
+}
+
+typedef struct { uint64_t code; int64_t idx; } keyidx;
+
+static int cmp_keyidx(const void* a, const void* b)
+{
+    const keyidx* x = (const keyidx*)a;
+    const keyidx* y = (const keyidx*)b;
+    if (x->code != y->code) return x->code < y->code ? -1 : 1;
+    return x->idx < y->idx ? -1 : (x->idx > y->idx ? 1 : 0);
+}
+
+typedef struct {
+    const uint64_t* code;  /* sorted codes */
+    const float* pos;      /* sorted positions [n][3] */
+    const float* h;        /* sorted h */
+    int32_t leaf_max;
+    int64_t cnt;
+    float* lo; float* hi;
+    int32_t* skip; int32_t* first; int32_t* count;
+} tree_ctx;
+
+static int64_t split_of(const tree_ctx* c, int64_t f, int64_t l)
+{
+    uint64_t a = c->code[f], b = c->code[l];
+    if (a != b) {
+        int bit = 63 - __builtin_clzll(a ^ b);
+        /* last position in [f, l] whose code has this bit clear */
+        int64_t s = f;
+        for (int64_t i = f; i <= l; ++i)
+            if (((c->code[i] >> bit) & 1ull) == 0) s = i;
+        return s;
+    }
+    int bit = 63 - __builtin_clzll((uint64_t)(f ^ l));
+    return ((l >> bit) << bit) - 1;
+}
+
+static void build_rec(tree_ctx* c, int64_t f, int64_t l)
+{
+    int64_t me = c->cnt++;
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t i = f; i <= l; ++i)
+        for (int a = 0; a < 3; ++a) {
+            float x = c->pos[3 * i + a], hh = c->h[i];
+            float m0 = x - hh, m1 = x + hh;
+            if (m0 < lo[a]) lo[a] = m0;
+            if (m1 > hi[a]) hi[a] = m1;
+        }
+    for (int a = 0; a < 3; ++a) { c->lo[3 * me + a] = lo[a]; c->hi[3 * me + a] = hi[a]; }
+    int64_t n = l - f + 1;
+    if (n <= c->leaf_max) {
+        c->first[me] = (int32_t)f;
+        c->count[me] = (int32_t)n;
+    } else {
+        int64_t s = split_of(c, f, l);
+        c->first[me] = (int32_t)f;
+        c->count[me] = 0;                 /* internal */
+        build_rec(c, f, s);
+        build_rec(c, s + 1, l);
+    }
+    c->skip[me] = (int32_t)c->cnt;
+}
+
+/* Outputs: perm[n] (sorted position -> original index), codes_sorted[n],
+ * node arrays sized for 2n - 1 nodes.  Returns the node count. */
+int64_t orc_lbvh(int64_t n, const float* pos, const float* h, int32_t leaf_max,
+                 int32_t* perm, uint64_t* codes_sorted, float* node_lo, float* node_hi,
+                 int32_t* node_skip, int32_t* node_first, int32_t* node_count)
+{
+    if (n <= 0 || leaf_max < 1) return -1;
+    uint64_t* codes = (uint64_t*)malloc(sizeof(uint64_t) * n);
+    keyidx* ki = (keyidx*)malloc(sizeof(keyidx) * n);
+    float* sp = (float*)malloc(sizeof(float) * 3 * n);
+    float* sh = (float*)malloc(sizeof(float) * n);
+    orc_morton(n, pos, codes);
+    for (int64_t j = 0; j < n; ++j) { ki[j].code = codes[j]; ki[j].idx = j; }
+    qsort(ki, (size_t)n, sizeof(keyidx), cmp_keyidx);
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t j = ki[i].idx;
+        perm[i] = (int32_t)j;
+        codes_sorted[i] = ki[i].code;
+        sp[3 * i] = pos[3 * j]; sp[3 * i + 1] = pos[3 * j + 1]; sp[3 * i + 2] = pos[3 * j + 2];
+        sh[i] = h[j];
+    }
+    tree_ctx c = {codes_sorted, sp, sh, leaf_max, 0, node_lo, node_hi, node_skip, node_first,
+                  node_count};
+    build_rec(&c, 0, n - 1);
+    free(codes); free(ki); free(sp); free(sh);
+    return c.cnt;
+}
