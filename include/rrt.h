@@ -1,0 +1,190 @@
+/*
+ * rrt.h -- C ABI of the MI355X reverse ray tracer (librrt.so).
+ *
+ * The library computes the self-shielded hydrogen photoionisation rate and the
+ * equilibrium neutral fraction of every SPH gas particle by reverse ray tracing
+ * (Altay & Theuns, "URCHIN: A Reverse Ray Tracer for Astrophysical
+ * Applications", Sec. 3.3 and Sec. 4):
+ *
+ *   1. every particle casts n_ray rays of length l_ray (HEALPix directions,
+ *      Sec. 3.3) -- the directions are an input array;
+ *   2. each ray's HI column is the sum, over every particle whose kernel sphere
+ *      the segment enters, of mu_j x_j times the line integral of the truncated
+ *      Gaussian kernel G_t along the part of the chord inside the segment
+ *      (Sec. 4.1.1, eq. colden and eq. Gt, closed form I(h,b,z1,z2));
+ *   3. Gamma = (1/n_ray) sum_k sum_b w_b sigma_b exp(-sigma_b N_k)
+ *      (Sec. 3.3, eq. gamma_shld, frequency integral done over bins with
+ *      w_b = 4 pi J_b dnu_b / (h nu_b));
+ *   4. x = x_-(Gamma, n_H, T), the physical root of the equilibrium quadratic
+ *      (Appendix C.3, eq. xroots, y = 0);
+ *   5. steps 2-4 repeat to a fixed point; every particle is updated from the
+ *      same previous state (the order-independent update of Sec. 4).
+ *
+ * Units: positions and h in kpc; mu = hydrogen atoms / (kpc in cm)^2, so that
+ * mu * x * (kernel line integral in kpc^-2) is a column in cm^-2; n_H in
+ * cm^-3; T in K; sigma in cm^2; w in photons cm^-2 s^-1; Gamma in s^-1.
+ *
+ * Conventions for every entry point:
+ *  - Return value: RRT_OK (0) on success, a negative RRT_E_* code on error,
+ *    RRT_NOT_CONVERGED (> 0) as a warning.  rrt_last_error() gives text.
+ *    No C++ exception crosses the ABI.
+ *  - Pointers marked "device" are caller-owned device memory on the GPU the
+ *    context was created on; "host" pointers are caller-owned host memory.
+ *    The library copies what it keeps; it never frees caller memory.
+ *  - Work is enqueued on the stream given to rrt_create (NULL = the null
+ *    stream).  Calls that return a scalar to the host synchronise that stream.
+ *  - The library allocates its own device buffers (tree, sorted particle
+ *    arrays, columns, scratch) with hipMalloc, sized by the particle count,
+ *    and releases them in rrt_destroy.
+ *  - A context is not thread-safe; use one context per host thread.
+ */
+#ifndef RRT_H
+#define RRT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    RRT_OK = 0,
+    RRT_NOT_CONVERGED = 1,    /* warning: max_iter reached before tolerance   */
+    RRT_E_ARG = -1,           /* invalid argument (null, size, range)          */
+    RRT_E_HIP = -2,           /* HIP runtime error                             */
+    RRT_E_INPUT = -3,         /* non-finite or out-of-range particle data      */
+    RRT_E_STATE = -4,         /* call out of order (e.g. columns before tree)  */
+    RRT_E_NOMEM = -5,         /* device allocation failed                      */
+    RRT_E_CAPACITY = -6       /* caller buffer too small                       */
+};
+
+typedef struct rrt_ctx rrt_ctx;
+
+typedef struct {
+    double l_ray;          /* ray length in kpc, >= 0 (Sec. 3.3: l_ray)              */
+    double box;            /* periodic box side in kpc; 0 = isolated (no images)    */
+    int32_t leaf_size;     /* max particles per tree leaf, 1..8 (0 = default 4)     */
+    int32_t block_size;    /* threads per block of the traversal (0 = default 256)  */
+    int32_t reserved[4];   /* must be zero                                           */
+} rrt_params;
+
+/* Library version as major*10000 + minor*100 + patch. */
+int rrt_version(void);
+
+/* Create a context on the current HIP device.  stream: a hipStream_t (may be
+ * NULL).  *out receives the context; on failure *out is NULL. */
+int rrt_create(rrt_ctx** out, const rrt_params* params, void* stream);
+
+/* Release every device buffer the context owns. Safe on NULL. */
+void rrt_destroy(rrt_ctx* ctx);
+
+/* Text of the last error on this context (or of the last failed create when
+ * ctx is NULL).  Valid until the next call on the context. */
+const char* rrt_last_error(const rrt_ctx* ctx);
+
+/* Particle data (Sec. 4.1.1, eq. nhi: m_i, x_i, h_i; plus n_H and T for the
+ * rates of Appendix C.3).  All device pointers, n entries each:
+ *   pos  float[n][3]  positions in kpc
+ *   h    float[n]     smoothing length in kpc, > 0 (kernel support radius)
+ *   mu   float[n]     hydrogen atoms / kpc_cm^2, >= 0
+ *   n_H  float[n]     hydrogen density in cm^-3, > 0
+ *   T    float[n]     temperature in K, > 0
+ * x_init: device double[n] initial neutral fractions, or NULL for the optically
+ * thin state x_thin = x_-(Gamma_thin) (Sec. 4).  Copied; validated by
+ * rrt_build_tree, which must follow. n >= 1. */
+int rrt_set_particles(rrt_ctx* ctx, int64_t n, const float* pos, const float* h,
+                      const float* mu, const float* n_H, const float* T,
+                      const double* x_init);
+
+/* Ray directions (Sec. 3.3: HEALPix pixel centres): host double[n_ray][3] unit
+ * vectors, 1 <= n_ray <= 3072.  Every particle casts the same directions. */
+int rrt_set_rays(rrt_ctx* ctx, int32_t n_ray, const double* dirs);
+
+/* HEALPix RING-order pixel-centre directions for n_side (1..16): writes
+ * 12 n_side^2 unit vectors into host double[12 n_side^2][3]. */
+int rrt_healpix_dirs(int32_t n_side, double* dirs_out);
+
+/* Binned optically thin spectrum (Sec. 2 eq. gamma; Sec. 3.3 eq. gamma_shld):
+ * host double sigma[n_bins] (cm^2, > 0) and w[n_bins] (>= 0) with
+ * Gamma_thin = sum_b w_b sigma_b > 0.  1 <= n_bins <= 4096. */
+int rrt_set_spectrum(rrt_ctx* ctx, int32_t n_bins, const double* sigma, const double* w);
+
+/* Build the bounding-volume tree over the particles: scene bounds, 63-bit
+ * Morton keys, radix sort by (key, index), binary radix tree, box refit,
+ * depth-first layout with skip links; gathers particle data into tree order,
+ * evaluates the per-particle rates and sets the initial state.  Synchronises
+ * (the key quantisation needs the scene bounds on the host). */
+int rrt_build_tree(rrt_ctx* ctx);
+
+/* Columns for the current state x (Sec. 4.1.1, eq. colden): N[p][k] in cm^-2.
+ * N_out: device double[n][n_ray] in input particle order, or NULL to keep the
+ * columns internal.  n_hits_out: host, total ray-particle intersections of this
+ * call (counting each periodic image separately), or NULL (then no sync). */
+int rrt_compute_columns(rrt_ctx* ctx, double* N_out, int64_t* n_hits_out);
+
+/* Shielded rate from the current columns (Sec. 3.3, eq. gamma_shld):
+ * ln Gamma, Gamma and tau_eff = ln Gamma_thin - ln Gamma per particle.
+ * Device outputs in input order, each nullable: double lnG[n], double G[n],
+ * float tau[n]. */
+int rrt_compute_gamma(rrt_ctx* ctx, double* lnG_out, double* G_out, float* tau_out);
+
+/* One equilibrium update from the current Gamma (Appendix C.3, physical root
+ * x_-): x <- x_-(Gamma, n_H, T).  x_out: device double[n] (nullable);
+ * max_dx_out: host max |x_new - x_old| (nullable, syncs). */
+int rrt_update_equilibrium(rrt_ctx* ctx, double* x_out, double* max_dx_out);
+
+/* The fixed point (Sec. 3.3, Sec. 4): repeat columns -> Gamma -> x until
+ * max |dx| < tol or max_iter iterations.  x_out: device double[n] (nullable).
+ * iters_done, max_dx_out: host (nullable).  Returns RRT_NOT_CONVERGED if
+ * max_iter was reached with max|dx| >= tol.  Synchronises once per iteration
+ * (8 bytes) for the convergence test. */
+int rrt_iterate_equilibrium(rrt_ctx* ctx, int32_t max_iter, double tol, double* x_out,
+                            int32_t* iters_done, double* max_dx_out);
+
+/* Replace the state: x device double[n] in input order (checkpoint / resume,
+ * or a given iterate); NULL resets to x_thin. */
+int rrt_set_state(rrt_ctx* ctx, const double* x);
+
+/* Read the state: device outputs in input order, each nullable. */
+int rrt_get_state(rrt_ctx* ctx, double* x_out, double* lnG_out, double* G_out,
+                  float* tau_out);
+
+/* Tree export for inspection (host outputs).  Node i of the depth-first layout:
+ * box lo[i][3], hi[i][3] (exact FP32 min/max of r -/+ h over its particles),
+ * skip[i] (first node after its subtree), first[i] (first particle in tree
+ * order), count[i] (particles in a leaf, 0 for internal nodes).  perm[n]: tree
+ * order -> input index; codes[n]: sorted 63-bit Morton keys.  cap: capacity
+ * in nodes; *n_nodes receives the node count (RRT_E_CAPACITY if cap is too
+ * small).  Any output may be NULL. */
+int rrt_get_tree(rrt_ctx* ctx, int64_t cap, int64_t* n_nodes, float* lo, float* hi,
+                 int32_t* skip, int32_t* first, int32_t* count, int32_t* perm,
+                 uint64_t* codes);
+
+/* Hit lists for the current geometry (host outputs): the intersections of ray
+ * (p, k) are hit_j[row_off[p*n_ray+k] .. row_off[p*n_ray+k+1]) as input
+ * particle indices, with the periodic image of each in hit_img as
+ * (sx+8) | (sy+8)<<4 | (sz+8)<<8 (the image of particle j sits at r_j + s*box).
+ * row_off: int64[n*n_ray + 1].  cap: capacity of hit_j/hit_img; if the total
+ * exceeds it, row_off is still filled and RRT_E_CAPACITY is returned. */
+int rrt_get_hits(rrt_ctx* ctx, int64_t cap, int64_t* row_off, int32_t* hit_j,
+                 int32_t* hit_img);
+
+/* Accumulated device time (ms, HIP events on the context's stream) of the
+ * last rrt_iterate_equilibrium / rrt_compute_columns calls per phase:
+ * out[0] traversal+column kernels, out[1] rate+equilibrium kernels,
+ * out[2] tree build, out[3] number of traversal launches timed.
+ * Timing is recorded only after rrt_enable_timing(ctx, 1). */
+int rrt_enable_timing(rrt_ctx* ctx, int32_t on);
+int rrt_get_timing(rrt_ctx* ctx, double* out4);
+int rrt_reset_timing(rrt_ctx* ctx);
+
+/* Intersection counters (host): out2[0] = intersections of the last iteration
+ * of rrt_iterate_equilibrium, out2[1] = intersections summed over every
+ * iteration since the last rrt_reset_timing. */
+int rrt_get_counters(rrt_ctx* ctx, int64_t* out2);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RRT_H */

@@ -1,0 +1,155 @@
+// Internal declarations of librrt: the context, device buffers and the host
+// launchers of every kernel.  Not part of the public ABI (see include/rrt.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "rrt.h"
+
+namespace rrt {
+
+constexpr int kTabIntervals = 256;        // cubic pieces per kernel table
+constexpr int kMaxRays = 3072;
+constexpr int kMaxBins = 4096;
+constexpr int kDefaultLeaf = 4;
+
+// One node of the depth-first tree layout: two 16-byte words.
+//   a = (lo.x, lo.y, lo.z, skip as int bits)
+//   b = (hi.x, hi.y, hi.z, leaf word as int bits)
+// leaf word: -1 for an internal node (its first child is the next node);
+// (first << 3) | (count - 1) for a leaf holding particles first..first+count-1.
+struct Node {
+    float4 a;
+    float4 b;
+};
+
+// Geometry of one ray family: everything the traversal needs besides the tree.
+struct TraceGeom {
+    double L;              // segment length
+    double box;            // periodic side, 0 = isolated
+    double plo[3], phi[3]; // bounds of particle positions
+    double hmax;           // largest smoothing length
+    float pad;             // outward pad of every box test (absorbs FP32 rounding)
+    int32_t n;             // particles
+    int32_t n_ray;
+    int32_t n_nodes;
+};
+
+// Table of cubic pieces on [0, 1]: piece i covers [i/256, (i+1)/256], value
+// c.x + c.y u + c.z u^2 + c.w u^3 in the local coordinate u.
+struct KernelTables {
+    float4 chord_full[kTabIntervals];   // G(w) = F(q)/sqrt(w), w = 1 - q^2
+    float4 gauss[kTabIntervals];        // E(q^2) = C exp(-t^2 q^2)
+    float4 erf_t[kTabIntervals];        // erf(t zeta), zeta in [0, 1]
+};
+
+struct Ctx {
+    rrt_params prm{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    std::string err;
+
+    // sizes
+    int64_t n = 0, n_cap = 0;
+    int32_t n_ray = 0, n_bins = 0;
+    int32_t leaf = kDefaultLeaf;
+    int64_t n_nodes = 0;
+    bool have_particles = false, have_rays = false, have_spectrum = false, have_tree = false;
+    bool have_columns = false, have_gamma = false;
+    bool x_init_given = false;
+
+    // inputs in input order (device)
+    float* pos_in = nullptr;     // [n][3]
+    float* h_in = nullptr;
+    float* mu_in = nullptr;
+    float* nH_in = nullptr;
+    float* T_in = nullptr;
+    double* x_init = nullptr;
+
+    // tree-order particle data (device)
+    float4* p4 = nullptr;        // x, y, z, h
+    float* mu_s = nullptr;
+    float* nH_s = nullptr;
+    double* alpha_s = nullptr;   // case A recombination
+    double* gcoll_s = nullptr;   // collisional ionisation
+    double* x_s = nullptr;       // state
+    float* mux_s = nullptr;      // mu * x for the traversal
+    double* lnG_s = nullptr;
+    double* G_s = nullptr;
+    float* tau_s = nullptr;
+    double* N_s = nullptr;       // columns [n_ray][n] in tree order
+    int32_t* perm = nullptr;     // tree order -> input index
+    uint64_t* codes = nullptr;   // sorted keys
+
+    // tree
+    Node* nodes = nullptr;
+    // build scratch
+    uint64_t* keys_b = nullptr;
+    int32_t* vals_b = nullptr;
+    uint32_t* hist = nullptr;
+    size_t hist_cap = 0;
+    void* scan_tmp = nullptr;
+    size_t scan_tmp_bytes = 0;
+    int32_t* k_left = nullptr;   // radix tree children (>= 0 internal, < 0 leaf ~i)
+    int32_t* k_right = nullptr;
+    int32_t* k_parent = nullptr; // [2n-1]: internal 0..n-2, leaves n-1..2n-2
+    int32_t* k_first = nullptr;  // range of internal nodes
+    int32_t* k_last = nullptr;
+    float* k_lo = nullptr;       // [n-1][3]
+    float* k_hi = nullptr;
+    int32_t* k_cnt = nullptr;    // particles below
+    int32_t* k_dfs = nullptr;    // depth-first nodes below (with leaf collapse)
+    int32_t* k_flag = nullptr;
+
+    // spectrum and rays (device)
+    double* dirs = nullptr;      // [n_ray][3]
+    double* ws = nullptr;        // w_b sigma_b
+    float* dsig_l2 = nullptr;    // (sigma_b - sigma_min) * log2(e)
+    float* ws_rel = nullptr;     // w_b sigma_b / max_b(w_b sigma_b)
+    double sigma_min = 0.0, ln_ws_max = 0.0, gamma_thin = 0.0;
+    KernelTables* tables = nullptr;
+
+    // reductions (device) and a host mirror
+    unsigned long long* red = nullptr;   // [0] max|dx| bits, [1] hits, [2] input error flags
+    unsigned long long* red_host = nullptr;  // pinned
+
+    // geometry
+    TraceGeom geom{};
+
+    // counters: intersections of the last iteration and since the last reset
+    int64_t last_hits = 0, total_hits = 0;
+
+    // timing
+    bool timing = false;
+    double t_trace = 0, t_rate = 0, t_build = 0, n_trace = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+// ---- launchers (tree.hip) ----
+hipError_t launch_bounds(Ctx& c, float* part_out /*[nb][8]*/, int nb);
+hipError_t launch_morton(Ctx& c, const double lo[3], double scale);
+hipError_t radix_sort_pairs(Ctx& c, uint64_t* keys, int32_t* vals, int64_t n);
+hipError_t build_radix_tree(Ctx& c);
+hipError_t launch_gather(Ctx& c);
+hipError_t scan_exclusive_u64(Ctx& c, const uint64_t* in, uint64_t* out, int64_t m);
+
+// ---- launchers (trace.hip) ----
+void fill_kernel_tables(KernelTables* host);
+hipError_t launch_columns(Ctx& c);
+hipError_t launch_count_hits(Ctx& c, uint64_t* row_cnt);
+hipError_t launch_record_hits(Ctx& c, const uint64_t* row_off, int32_t* hit_j, int32_t* hit_img,
+                              uint64_t cap);
+
+// ---- launchers (rate.hip) ----
+hipError_t launch_init_state(Ctx& c, bool use_given);
+hipError_t launch_gamma(Ctx& c, bool update_x);
+hipError_t launch_update_x(Ctx& c);
+hipError_t launch_to_input_order_d(Ctx& c, const double* src, double* dst, int32_t stride);
+hipError_t launch_to_input_order_f(Ctx& c, const float* src, float* dst);
+hipError_t launch_from_input_order_d(Ctx& c, const double* src, double* dst);
+hipError_t launch_mux(Ctx& c);
+
+}  // namespace rrt

@@ -1,0 +1,228 @@
+// Shielded photoionisation rate and the equilibrium update.
+//
+// Gamma_p = (1/n_ray) sum_k sum_b w_b sigma_b exp(-sigma_b N_pk)   (Sec. 3.3,
+// eq. gamma_shld, frequency integral over bins).  Each ray's frequency sum is
+// formed relative to its least-absorbed bin,
+//   S_k = sum_b (w_b sigma_b / max w sigma) exp(-(sigma_b - sigma_min) N_k),
+// whose exponents are bounded and can run in FP32 (exp2 on the transcendental
+// unit); the leading -sigma_min N_k stays in FP64, and the rays combine by a
+// log-sum-exp in FP64, so ln Gamma stays exact far past where Gamma itself
+// underflows.
+//
+// x = x_-(Gamma): the physical root of R x^2 + Q x + P (Appendix C.3, eq.
+// xroots, y = 0) with R = (gamma + alpha) n_H, P = alpha n_H, Q = -(Gamma + P + R),
+// evaluated as 2P / (-Q + sqrt(D)).  The discriminant is formed as
+// D = (Gamma + gamma n_H)^2 + 4 Gamma P, which equals Q^2 - 4PR exactly but has
+// no cancellation when Gamma is small.
+//
+// Rates: case A recombination (Hui & Gnedin 1997 fit) and collisional
+// ionisation (Cen 1992 fit); the paper refers to published fits without
+// printing them.
+#include "internal.h"
+
+namespace rrt {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ double alpha_caseA(double T)
+{
+    double lam = 2.0 * 157807.0 / T;
+    return 1.269e-13 * pow(lam, 1.503) / pow(1.0 + pow(lam / 0.522, 0.470), 1.923);
+}
+
+__device__ __forceinline__ double gamma_collisional(double T)
+{
+    return 5.85e-11 * sqrt(T) * exp(-157809.1 / T) / (1.0 + sqrt(T * 1e-5));
+}
+
+__device__ __forceinline__ double x_minus(double G, double nH, double al, double gc)
+{
+    double P = al * nH;
+    double R = (gc + al) * nH;
+    double negQ = G + P + R;
+    double s = G + gc * nH;
+    double D = s * s + 4.0 * G * P;
+    return 2.0 * P / (negQ + sqrt(D));
+}
+
+__global__ void k_init_state(const int32_t* __restrict__ perm, const float* __restrict__ T,
+                             const double* __restrict__ x_init, const float* __restrict__ nH_s,
+                             const float* __restrict__ mu_s, int64_t n, double gthin,
+                             double* __restrict__ alpha, double* __restrict__ gcoll,
+                             double* __restrict__ x_s, float* __restrict__ mux)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int64_t j = perm[i];
+    double Tj = (double)T[j];
+    double al = alpha_caseA(Tj), gc = gamma_collisional(Tj);
+    alpha[i] = al;
+    gcoll[i] = gc;
+    double x = x_init ? x_init[j] : x_minus(gthin, (double)nH_s[i], al, gc);
+    x_s[i] = x;
+    mux[i] = (float)((double)mu_s[i] * x);
+}
+
+// One thread per particle: rays, then bins; optionally the equilibrium update.
+__global__ void __launch_bounds__(256)
+k_gamma(const double* __restrict__ N, int64_t n, int n_ray, int n_bins,
+        const float* __restrict__ ws_rel, const float* __restrict__ dsig_l2, double sigma_min,
+        double ln_ws_max, double ln_gthin, double* __restrict__ lnG, double* __restrict__ G,
+        float* __restrict__ tau, int update_x, const float* __restrict__ nH_s,
+        const float* __restrict__ mu_s, const double* __restrict__ alpha,
+        const double* __restrict__ gcoll, double* __restrict__ x_s, float* __restrict__ mux,
+        unsigned long long* __restrict__ maxdx_bits)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    double dx = 0.0;
+    if (i < n) {
+        double m = -INFINITY, s = 0.0;
+        for (int k = 0; k < n_ray; ++k) {
+            double Nk = N[(int64_t)k * n + i];
+            float Nf = (float)Nk;
+            float S0 = 0.f, S1 = 0.f, S2 = 0.f, S3 = 0.f;
+            int b = 0;
+            for (; b + 3 < n_bins; b += 4) {
+                S0 = fmaf(ws_rel[b], exp2f(-dsig_l2[b] * Nf), S0);
+                S1 = fmaf(ws_rel[b + 1], exp2f(-dsig_l2[b + 1] * Nf), S1);
+                S2 = fmaf(ws_rel[b + 2], exp2f(-dsig_l2[b + 2] * Nf), S2);
+                S3 = fmaf(ws_rel[b + 3], exp2f(-dsig_l2[b + 3] * Nf), S3);
+            }
+            for (; b < n_bins; ++b) S0 = fmaf(ws_rel[b], exp2f(-dsig_l2[b] * Nf), S0);
+            float S = (S0 + S1) + (S2 + S3);
+            if (!(S > 0.f)) continue;                     // this ray carries nothing
+            double v = -sigma_min * Nk + log((double)S);
+            if (v > m) {
+                s = s * exp(m - v) + 1.0;
+                m = v;
+            } else {
+                s += exp(v - m);
+            }
+        }
+        double l = (s > 0.0) ? (ln_ws_max + m + log(s / (double)n_ray)) : -INFINITY;
+        double g = exp(l);
+        if (lnG) lnG[i] = l;
+        if (G) G[i] = g;
+        if (tau) tau[i] = (float)(ln_gthin - l);
+        if (update_x) {
+            double xn = x_minus(g, (double)nH_s[i], alpha[i], gcoll[i]);
+            dx = fabs(xn - x_s[i]);
+            x_s[i] = xn;
+            mux[i] = (float)((double)mu_s[i] * xn);
+        }
+    }
+    if (update_x) {
+        for (int off = 32; off > 0; off >>= 1) dx = fmax(dx, __shfl_xor(dx, off, 64));
+        if ((threadIdx.x & 63) == 0)
+            atomicMax(maxdx_bits, (unsigned long long)__double_as_longlong(dx));
+    }
+}
+
+__global__ void k_update_x(const double* __restrict__ G, int64_t n, const float* __restrict__ nH_s,
+                           const float* __restrict__ mu_s, const double* __restrict__ alpha,
+                           const double* __restrict__ gcoll, double* __restrict__ x_s,
+                           float* __restrict__ mux, unsigned long long* __restrict__ maxdx_bits)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    double dx = 0.0;
+    if (i < n) {
+        double xn = x_minus(G[i], (double)nH_s[i], alpha[i], gcoll[i]);
+        dx = fabs(xn - x_s[i]);
+        x_s[i] = xn;
+        mux[i] = (float)((double)mu_s[i] * xn);
+    }
+    for (int off = 32; off > 0; off >>= 1) dx = fmax(dx, __shfl_xor(dx, off, 64));
+    if ((threadIdx.x & 63) == 0)
+        atomicMax(maxdx_bits, (unsigned long long)__double_as_longlong(dx));
+}
+
+__global__ void k_mux(const float* __restrict__ mu_s, const double* __restrict__ x_s, int64_t n,
+                      float* __restrict__ mux)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) mux[i] = (float)((double)mu_s[i] * x_s[i]);
+}
+
+// tree order -> input order; src is [stride][n] (one column per stride index)
+__global__ void k_scatter_d(const int32_t* __restrict__ perm, const double* __restrict__ src,
+                            int64_t n, int stride, double* __restrict__ dst)
+{
+    int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= n * stride) return;
+    int64_t k = g / n, i = g - k * n;
+    dst[(int64_t)perm[i] * stride + k] = src[g];
+}
+
+__global__ void k_scatter_f(const int32_t* __restrict__ perm, const float* __restrict__ src,
+                            int64_t n, float* __restrict__ dst)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) dst[perm[i]] = src[i];
+}
+
+__global__ void k_gather_d(const int32_t* __restrict__ perm, const double* __restrict__ src,
+                           int64_t n, double* __restrict__ dst)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[perm[i]];
+}
+
+inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+hipError_t launch_init_state(Ctx& c, bool use_given)
+{
+    hipLaunchKernelGGL(k_init_state, dim3(nblk(c.n)), dim3(kBlock), 0, c.stream, c.perm, c.T_in,
+                       use_given ? c.x_init : nullptr, c.nH_s, c.mu_s, c.n, c.gamma_thin,
+                       c.alpha_s, c.gcoll_s, c.x_s, c.mux_s);
+    return hipGetLastError();
+}
+
+hipError_t launch_gamma(Ctx& c, bool update_x)
+{
+    hipLaunchKernelGGL(k_gamma, dim3(nblk(c.n)), dim3(kBlock), 0, c.stream, c.N_s, c.n, c.n_ray,
+                       c.n_bins, c.ws_rel, c.dsig_l2, c.sigma_min, c.ln_ws_max,
+                       std::log(c.gamma_thin), c.lnG_s, c.G_s, c.tau_s, update_x ? 1 : 0, c.nH_s,
+                       c.mu_s, c.alpha_s, c.gcoll_s, c.x_s, c.mux_s, c.red);
+    return hipGetLastError();
+}
+
+hipError_t launch_update_x(Ctx& c)
+{
+    hipLaunchKernelGGL(k_update_x, dim3(nblk(c.n)), dim3(kBlock), 0, c.stream, c.G_s, c.n, c.nH_s,
+                       c.mu_s, c.alpha_s, c.gcoll_s, c.x_s, c.mux_s, c.red);
+    return hipGetLastError();
+}
+
+hipError_t launch_mux(Ctx& c)
+{
+    hipLaunchKernelGGL(k_mux, dim3(nblk(c.n)), dim3(kBlock), 0, c.stream, c.mu_s, c.x_s, c.n,
+                       c.mux_s);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_input_order_d(Ctx& c, const double* src, double* dst, int32_t stride)
+{
+    hipLaunchKernelGGL(k_scatter_d, dim3(nblk(c.n * stride)), dim3(kBlock), 0, c.stream, c.perm,
+                       src, c.n, stride, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_input_order_f(Ctx& c, const float* src, float* dst)
+{
+    hipLaunchKernelGGL(k_scatter_f, dim3(nblk(c.n)), dim3(kBlock), 0, c.stream, c.perm, src, c.n,
+                       dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_from_input_order_d(Ctx& c, const double* src, double* dst)
+{
+    hipLaunchKernelGGL(k_gather_d, dim3(nblk(c.n)), dim3(kBlock), 0, c.stream, c.perm, src, c.n,
+                       dst);
+    return hipGetLastError();
+}
+
+}  // namespace rrt

@@ -1,0 +1,662 @@
+// Host side of librrt: the C ABI declared in include/rrt.h.
+#include "internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+using namespace rrt;
+
+struct rrt_ctx {
+    Ctx c;
+};
+
+namespace {
+
+thread_local std::string g_create_err;
+
+int fail(Ctx& c, int code, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+int fail(Ctx& c, int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    c.err = buf;
+    return code;
+}
+
+#define HIP_OK(expr)                                                                       \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(c, RRT_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));      \
+    } while (0)
+
+template <typename T>
+hipError_t dalloc(T** p, size_t count)
+{
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+    if (count == 0) count = 1;
+    return hipMalloc((void**)p, count * sizeof(T));
+}
+
+void free_particles(Ctx& c)
+{
+    void* bufs[] = {c.pos_in, c.h_in, c.mu_in, c.nH_in, c.T_in, c.x_init, c.p4, c.mu_s, c.nH_s,
+                    c.alpha_s, c.gcoll_s, c.x_s, c.mux_s, c.lnG_s, c.G_s, c.tau_s, c.N_s,
+                    c.perm, c.codes, c.nodes, c.keys_b, c.vals_b, c.k_left, c.k_right,
+                    c.k_parent, c.k_first, c.k_last, c.k_lo, c.k_hi, c.k_cnt, c.k_dfs, c.k_flag};
+    for (void* b : bufs)
+        if (b) (void)hipFree(b);
+    c.pos_in = c.h_in = c.mu_in = c.nH_in = c.T_in = nullptr;
+    c.x_init = nullptr;
+    c.p4 = nullptr;
+    c.mu_s = c.nH_s = c.mux_s = c.tau_s = nullptr;
+    c.alpha_s = c.gcoll_s = c.x_s = c.lnG_s = c.G_s = c.N_s = nullptr;
+    c.perm = nullptr;
+    c.codes = nullptr;
+    c.nodes = nullptr;
+    c.keys_b = nullptr;
+    c.vals_b = nullptr;
+    c.k_left = c.k_right = c.k_parent = c.k_first = c.k_last = nullptr;
+    c.k_lo = c.k_hi = nullptr;
+    c.k_cnt = c.k_dfs = c.k_flag = nullptr;
+    c.n_cap = 0;
+}
+
+int alloc_particles(Ctx& c, int64_t n)
+{
+    if (n <= c.n_cap && c.N_s) return RRT_OK;
+    free_particles(c);
+    const size_t m = (size_t)n;
+    const size_t mi = m > 1 ? m - 1 : 1;
+    hipError_t e = hipSuccess;
+#define A(p, cnt)                                                    \
+    if (e == hipSuccess) e = dalloc(&(p), (cnt));
+    A(c.pos_in, 3 * m) A(c.h_in, m) A(c.mu_in, m) A(c.nH_in, m) A(c.T_in, m) A(c.x_init, m)
+    A(c.p4, m) A(c.mu_s, m) A(c.nH_s, m) A(c.alpha_s, m) A(c.gcoll_s, m) A(c.x_s, m)
+    A(c.mux_s, m) A(c.lnG_s, m) A(c.G_s, m) A(c.tau_s, m) A(c.perm, m) A(c.codes, m)
+    A(c.nodes, 2 * m) A(c.keys_b, m) A(c.vals_b, m) A(c.k_left, mi) A(c.k_right, mi)
+    A(c.k_parent, 2 * m) A(c.k_first, mi) A(c.k_last, mi) A(c.k_lo, 3 * mi) A(c.k_hi, 3 * mi)
+    A(c.k_cnt, mi) A(c.k_dfs, mi) A(c.k_flag, mi)
+#undef A
+    if (e != hipSuccess) {
+        free_particles(c);
+        return fail(c, RRT_E_NOMEM, "device allocation for %lld particles failed: %s",
+                    (long long)n, hipGetErrorString(e));
+    }
+    c.n_cap = n;
+    return RRT_OK;
+}
+
+int alloc_columns(Ctx& c)
+{
+    if (c.N_s) (void)hipFree(c.N_s);
+    c.N_s = nullptr;
+    hipError_t e = dalloc(&c.N_s, (size_t)c.n * (size_t)c.n_ray);
+    if (e != hipSuccess)
+        return fail(c, RRT_E_NOMEM, "column buffer allocation failed: %s", hipGetErrorString(e));
+    return RRT_OK;
+}
+
+void ev_begin(Ctx& c)
+{
+    if (c.timing) (void)hipEventRecord(c.ev0, c.stream);
+}
+
+double ev_end(Ctx& c)
+{
+    if (!c.timing) return 0.0;
+    (void)hipEventRecord(c.ev1, c.stream);
+    (void)hipEventSynchronize(c.ev1);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, c.ev0, c.ev1);
+    return ms;
+}
+
+int need_tree(Ctx& c)
+{
+    if (!c.have_tree) return fail(c, RRT_E_STATE, "rrt_build_tree has not been called");
+    if (!c.have_rays) return fail(c, RRT_E_STATE, "rrt_set_rays has not been called");
+    if (!c.have_spectrum) return fail(c, RRT_E_STATE, "rrt_set_spectrum has not been called");
+    return RRT_OK;
+}
+
+int columns_impl(Ctx& c)
+{
+    ev_begin(c);
+    HIP_OK(launch_columns(c));
+    if (c.timing) {
+        c.t_trace += ev_end(c);
+        c.n_trace += 1;
+    }
+    c.have_columns = true;
+    return RRT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rrt_version(void) { return 1 * 10000 + 0 * 100 + 0; }
+
+int rrt_create(rrt_ctx** out, const rrt_params* params, void* stream)
+{
+    if (!out || !params) {
+        g_create_err = "rrt_create: null argument";
+        return RRT_E_ARG;
+    }
+    *out = nullptr;
+    if (!(params->l_ray >= 0.0) || !std::isfinite(params->l_ray) || !(params->box >= 0.0) ||
+        !std::isfinite(params->box) || params->leaf_size < 0 || params->leaf_size > 8 ||
+        params->block_size < 0 || params->block_size > 1024 || (params->block_size % 64) != 0) {
+        g_create_err = "rrt_create: invalid params (l_ray >= 0, box >= 0, leaf_size 0..8, "
+                       "block_size a multiple of 64 up to 1024)";
+        return RRT_E_ARG;
+    }
+    for (int i = 0; i < 4; ++i)
+        if (params->reserved[i] != 0) {
+            g_create_err = "rrt_create: reserved fields must be zero";
+            return RRT_E_ARG;
+        }
+    rrt_ctx* x = new (std::nothrow) rrt_ctx;
+    if (!x) {
+        g_create_err = "rrt_create: out of host memory";
+        return RRT_E_NOMEM;
+    }
+    Ctx& c = x->c;
+    c.prm = *params;
+    c.leaf = params->leaf_size ? params->leaf_size : kDefaultLeaf;
+    c.stream = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = hipGetDevice(&c.device);
+    if (e == hipSuccess) e = hipMalloc((void**)&c.tables, sizeof(KernelTables));
+    if (e == hipSuccess) e = hipMalloc((void**)&c.red, 4 * sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipHostMalloc((void**)&c.red_host, 4 * sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipEventCreate(&c.ev0);
+    if (e == hipSuccess) e = hipEventCreate(&c.ev1);
+    if (e == hipSuccess) {
+        KernelTables host;
+        fill_kernel_tables(&host);
+        e = hipMemcpy(c.tables, &host, sizeof host, hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) {
+        g_create_err = std::string("rrt_create: HIP error: ") + hipGetErrorString(e);
+        rrt_destroy(x);
+        return RRT_E_HIP;
+    }
+    *out = x;
+    return RRT_OK;
+}
+
+void rrt_destroy(rrt_ctx* x)
+{
+    if (!x) return;
+    Ctx& c = x->c;
+    if (c.stream) (void)hipStreamSynchronize(c.stream);
+    else (void)hipDeviceSynchronize();
+    free_particles(c);
+    void* bufs[] = {c.tables, c.red, c.dirs, c.ws, c.dsig_l2, c.ws_rel, c.hist, c.scan_tmp};
+    for (void* b : bufs)
+        if (b) (void)hipFree(b);
+    if (c.red_host) (void)hipHostFree(c.red_host);
+    if (c.ev0) (void)hipEventDestroy(c.ev0);
+    if (c.ev1) (void)hipEventDestroy(c.ev1);
+    delete x;
+}
+
+const char* rrt_last_error(const rrt_ctx* x)
+{
+    return x ? x->c.err.c_str() : g_create_err.c_str();
+}
+
+int rrt_set_particles(rrt_ctx* x, int64_t n, const float* pos, const float* h, const float* mu,
+                      const float* n_H, const float* T, const double* x_init)
+{
+    if (!x) return RRT_E_ARG;
+    Ctx& c = x->c;
+    if (n < 1 || n > (int64_t(1) << 28))
+        return fail(c, RRT_E_ARG, "particle count %lld outside 1..2^28", (long long)n);
+    if (!pos || !h || !mu || !n_H || !T) return fail(c, RRT_E_ARG, "null particle array");
+    int r = alloc_particles(c, n);
+    if (r) return r;
+    c.n = n;
+    HIP_OK(hipMemcpyAsync(c.pos_in, pos, sizeof(float) * 3 * n, hipMemcpyDeviceToDevice, c.stream));
+    HIP_OK(hipMemcpyAsync(c.h_in, h, sizeof(float) * n, hipMemcpyDeviceToDevice, c.stream));
+    HIP_OK(hipMemcpyAsync(c.mu_in, mu, sizeof(float) * n, hipMemcpyDeviceToDevice, c.stream));
+    HIP_OK(hipMemcpyAsync(c.nH_in, n_H, sizeof(float) * n, hipMemcpyDeviceToDevice, c.stream));
+    HIP_OK(hipMemcpyAsync(c.T_in, T, sizeof(float) * n, hipMemcpyDeviceToDevice, c.stream));
+    c.x_init_given = x_init != nullptr;
+    if (x_init)
+        HIP_OK(hipMemcpyAsync(c.x_init, x_init, sizeof(double) * n, hipMemcpyDeviceToDevice,
+                              c.stream));
+    c.have_particles = true;
+    c.have_tree = c.have_columns = c.have_gamma = false;
+    if (c.have_rays) return alloc_columns(c);
+    return RRT_OK;
+}
+
+int rrt_set_rays(rrt_ctx* x, int32_t n_ray, const double* dirs)
+{
+    if (!x) return RRT_E_ARG;
+    Ctx& c = x->c;
+    if (n_ray < 1 || n_ray > kMaxRays || !dirs)
+        return fail(c, RRT_E_ARG, "n_ray must be 1..%d with a direction array", kMaxRays);
+    for (int k = 0; k < n_ray; ++k) {
+        double a = dirs[3 * k], b = dirs[3 * k + 1], d = dirs[3 * k + 2];
+        double nn = a * a + b * b + d * d;
+        if (!std::isfinite(nn) || std::fabs(nn - 1.0) > 1e-6)
+            return fail(c, RRT_E_ARG, "direction %d is not a unit vector", k);
+    }
+    HIP_OK(dalloc(&c.dirs, (size_t)3 * n_ray));
+    HIP_OK(hipMemcpy(c.dirs, dirs, sizeof(double) * 3 * n_ray, hipMemcpyHostToDevice));
+    bool changed = n_ray != c.n_ray;
+    c.n_ray = n_ray;
+    c.geom.n_ray = n_ray;
+    c.have_rays = true;
+    c.have_columns = c.have_gamma = false;
+    if (c.have_particles && (changed || !c.N_s)) return alloc_columns(c);
+    return RRT_OK;
+}
+
+int rrt_healpix_dirs(int32_t n_side, double* out)
+{
+    if (n_side < 1 || n_side > 16 || !out) return RRT_E_ARG;
+    const double pi = 3.14159265358979323846;
+    const int ns = n_side;
+    int64_t w = 0;
+    for (int i = 1; i < 4 * ns; ++i) {
+        double z;
+        int cnt;
+        double phi0, dphi;
+        if (i < ns) {
+            z = 1.0 - (double)i * i / (3.0 * ns * ns);
+            cnt = 4 * i;
+            dphi = pi / (2.0 * i);
+            phi0 = 0.5 * dphi;
+        } else if (i <= 3 * ns) {
+            z = 4.0 / 3.0 - 2.0 * i / (3.0 * ns);
+            cnt = 4 * ns;
+            dphi = pi / (2.0 * ns);
+            int s = (i - ns + 1) % 2;
+            phi0 = dphi * (1.0 - 0.5 * s);
+        } else {
+            int ii = 4 * ns - i;
+            z = -(1.0 - (double)ii * ii / (3.0 * ns * ns));
+            cnt = 4 * ii;
+            dphi = pi / (2.0 * ii);
+            phi0 = 0.5 * dphi;
+        }
+        double st = std::sqrt(std::max(0.0, (1.0 - z) * (1.0 + z)));
+        for (int j = 0; j < cnt; ++j) {
+            double phi = phi0 + dphi * j;
+            out[3 * w] = st * std::cos(phi);
+            out[3 * w + 1] = st * std::sin(phi);
+            out[3 * w + 2] = z;
+            ++w;
+        }
+    }
+    return RRT_OK;
+}
+
+int rrt_set_spectrum(rrt_ctx* x, int32_t n_bins, const double* sigma, const double* w)
+{
+    if (!x) return RRT_E_ARG;
+    Ctx& c = x->c;
+    if (n_bins < 1 || n_bins > kMaxBins || !sigma || !w)
+        return fail(c, RRT_E_ARG, "n_bins must be 1..%d with sigma and w arrays", kMaxBins);
+    double smin = INFINITY, wsmax = 0.0, thin = 0.0;
+    for (int b = 0; b < n_bins; ++b) {
+        if (!(sigma[b] > 0.0) || !std::isfinite(sigma[b]) || !(w[b] >= 0.0) ||
+            !std::isfinite(w[b]))
+            return fail(c, RRT_E_ARG, "bin %d: need sigma > 0 and w >= 0, finite", b);
+        if (w[b] > 0.0) {
+            smin = std::min(smin, sigma[b]);
+            wsmax = std::max(wsmax, w[b] * sigma[b]);
+            thin += w[b] * sigma[b];
+        }
+    }
+    if (!(thin > 0.0)) return fail(c, RRT_E_ARG, "the optically thin rate sum(w*sigma) is zero");
+    // keep the bins that carry photons; rays see them relative to the least-absorbed one
+    std::vector<float> rel, dsl;
+    const double log2e = 1.4426950408889634;
+    for (int b = 0; b < n_bins; ++b) {
+        if (!(w[b] > 0.0)) continue;
+        rel.push_back((float)(w[b] * sigma[b] / wsmax));
+        dsl.push_back((float)((sigma[b] - smin) * log2e));
+    }
+    int m = (int)rel.size();
+    HIP_OK(dalloc(&c.ws_rel, m));
+    HIP_OK(dalloc(&c.dsig_l2, m));
+    HIP_OK(hipMemcpy(c.ws_rel, rel.data(), sizeof(float) * m, hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(c.dsig_l2, dsl.data(), sizeof(float) * m, hipMemcpyHostToDevice));
+    c.n_bins = m;
+    c.sigma_min = smin;
+    c.ln_ws_max = std::log(wsmax);
+    c.gamma_thin = thin;
+    c.have_spectrum = true;
+    c.have_gamma = false;
+    return RRT_OK;
+}
+
+int rrt_build_tree(rrt_ctx* x)
+{
+    if (!x) return RRT_E_ARG;
+    Ctx& c = x->c;
+    if (!c.have_particles) return fail(c, RRT_E_STATE, "rrt_set_particles has not been called");
+    if (!c.have_spectrum) return fail(c, RRT_E_STATE, "rrt_set_spectrum must precede the build");
+    ev_begin(c);
+    // bounds and validation
+    const int nb = (int)std::min<int64_t>(1024, (c.n + 255) / 256);
+    float* part = nullptr;
+    HIP_OK(hipMalloc(&part, sizeof(float) * 8 * nb));
+    hipError_t e = launch_bounds(c, part, nb);
+    std::vector<float> hp(8 * nb);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(hp.data(), part, sizeof(float) * 8 * nb, hipMemcpyDeviceToHost,
+                           c.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
+    (void)hipFree(part);
+    HIP_OK(e);
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    float hmax = 0.f, bad = 0.f;
+    for (int b = 0; b < nb; ++b) {
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = std::min(lo[a], hp[8 * b + a]);
+            hi[a] = std::max(hi[a], hp[8 * b + 3 + a]);
+        }
+        hmax = std::max(hmax, hp[8 * b + 6]);
+        bad = std::max(bad, hp[8 * b + 7]);
+    }
+    if (bad > 0.f)
+        return fail(c, RRT_E_INPUT, "particle data must be finite with h, n_H, T > 0, mu >= 0");
+    double dlo[3], ext = 0.0, maxabs = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        dlo[a] = (double)lo[a];
+        ext = std::max(ext, (double)hi[a] - (double)lo[a]);
+        maxabs = std::max({maxabs, std::fabs((double)lo[a]), std::fabs((double)hi[a])});
+    }
+    const double scale = ext > 0.0 ? 2097152.0 / ext : 0.0;
+    HIP_OK(hipMemsetAsync(c.red + 2, 0, sizeof(unsigned long long), c.stream));
+    HIP_OK(launch_morton(c, dlo, scale));
+    HIP_OK(radix_sort_pairs(c, c.codes, c.perm, c.n));
+    HIP_OK(build_radix_tree(c));
+    int32_t nn = 1;
+    if (c.n > 1)
+        HIP_OK(hipMemcpyAsync(&nn, c.k_dfs, sizeof(int32_t), hipMemcpyDeviceToHost, c.stream));
+    HIP_OK(hipMemcpyAsync(c.red_host + 2, c.red + 2, sizeof(unsigned long long),
+                          hipMemcpyDeviceToHost, c.stream));
+    HIP_OK(hipStreamSynchronize(c.stream));
+    if (c.red_host[2] != 0 || nn < 1 || nn > 2 * c.n - 1)
+        return fail(c, RRT_E_HIP, "tree construction inconsistent (flags %llu, %d nodes)",
+                    (unsigned long long)c.red_host[2], nn);
+    c.n_nodes = nn;
+    TraceGeom& g = c.geom;
+    g.L = c.prm.l_ray;
+    g.box = c.prm.box;
+    for (int a = 0; a < 3; ++a) {
+        g.plo[a] = lo[a];
+        g.phi[a] = hi[a];
+    }
+    g.hmax = hmax;
+    g.pad = (float)(4e-6 * 2.0 * (maxabs + g.L + (double)hmax + g.box));
+    g.n = (int32_t)c.n;
+    g.n_ray = c.n_ray;
+    g.n_nodes = nn;
+    HIP_OK(launch_init_state(c, c.x_init_given));
+    if (c.timing) c.t_build += ev_end(c);
+    c.have_tree = true;
+    c.have_columns = c.have_gamma = false;
+    return RRT_OK;
+}
+
+int rrt_compute_columns(rrt_ctx* x, double* N_out, int64_t* n_hits_out)
+{
+    if (!x) return RRT_E_ARG;
+    Ctx& c = x->c;
+    if (int r = need_tree(c)) return r;
+    if (n_hits_out) HIP_OK(hipMemsetAsync(c.red + 1, 0, sizeof(unsigned long long), c.stream));
+    if (int r = columns_impl(c)) return r;
+    if (N_out) HIP_OK(launch_to_input_order_d(c, c.N_s, N_out, c.n_ray));
+    if (n_hits_out) {
+        HIP_OK(hipMemcpyAsync(c.red_host + 1, c.red + 1, sizeof(unsigned long long),
+                              hipMemcpyDeviceToHost, c.stream));
+        HIP_OK(hipStreamSynchronize(c.stream));
+        *n_hits_out = (int64_t)c.red_host[1];
+    }
+    return RRT_OK;
+}
+
+int rrt_compute_gamma(rrt_ctx* x, double* lnG_out, double* G_out, float* tau_out)
+{
+    if (!x) return RRT_E_ARG;
+    Ctx& c = x->c;
+    if (int r = need_tree(c)) return r;
+    if (!c.have_columns) return fail(c, RRT_E_STATE, "no columns: call rrt_compute_columns");
+    HIP_OK(launch_gamma(c, false));
+    c.have_gamma = true;
+    if (lnG_out) HIP_OK(launch_to_input_order_d(c, c.lnG_s, lnG_out, 1));
+    if (G_out) HIP_OK(launch_to_input_order_d(c, c.G_s, G_out, 1));
+    if (tau_out) HIP_OK(launch_to_input_order_f(c, c.tau_s, tau_out));
+    return RRT_OK;
+}
+
+int rrt_update_equilibrium(rrt_ctx* x, double* x_out, double* max_dx_out)
+{
+    if (!x) return RRT_E_ARG;
+    Ctx& c = x->c;
+    if (int r = need_tree(c)) return r;
+    if (!c.have_gamma) return fail(c, RRT_E_STATE, "no rate: call rrt_compute_gamma");
+    HIP_OK(hipMemsetAsync(c.red, 0, sizeof(unsigned long long), c.stream));
+    HIP_OK(launch_update_x(c));
+    c.have_columns = c.have_gamma = false;
+    if (x_out) HIP_OK(launch_to_input_order_d(c, c.x_s, x_out, 1));
+    if (max_dx_out) {
+        HIP_OK(hipMemcpyAsync(c.red_host, c.red, sizeof(unsigned long long),
+                              hipMemcpyDeviceToHost, c.stream));
+        HIP_OK(hipStreamSynchronize(c.stream));
+        double d;
+        std::memcpy(&d, &c.red_host[0], sizeof d);
+        *max_dx_out = d;
+    }
+    return RRT_OK;
+}
+
+int rrt_iterate_equilibrium(rrt_ctx* x, int32_t max_iter, double tol, double* x_out,
+                            int32_t* iters_done, double* max_dx_out)
+{
+    if (!x) return RRT_E_ARG;
+    Ctx& c = x->c;
+    if (int r = need_tree(c)) return r;
+    if (max_iter < 0 || !(tol >= 0.0)) return fail(c, RRT_E_ARG, "max_iter >= 0 and tol >= 0");
+    int it = 0;
+    double mdx = INFINITY;
+    for (it = 0; it < max_iter;) {
+        HIP_OK(hipMemsetAsync(c.red, 0, 2 * sizeof(unsigned long long), c.stream));
+        if (int r = columns_impl(c)) return r;
+        ev_begin(c);
+        HIP_OK(launch_gamma(c, true));
+        HIP_OK(hipMemcpyAsync(c.red_host, c.red, 2 * sizeof(unsigned long long),
+                              hipMemcpyDeviceToHost, c.stream));
+        if (c.timing) c.t_rate += ev_end(c);
+        HIP_OK(hipStreamSynchronize(c.stream));
+        ++it;
+        std::memcpy(&mdx, &c.red_host[0], sizeof mdx);
+        c.last_hits = (int64_t)c.red_host[1];
+        c.total_hits += c.last_hits;
+        if (mdx < tol) break;
+    }
+    c.have_columns = c.have_gamma = false;
+    if (x_out) HIP_OK(launch_to_input_order_d(c, c.x_s, x_out, 1));
+    if (iters_done) *iters_done = it;
+    if (max_dx_out) *max_dx_out = mdx;
+    if (x_out) HIP_OK(hipStreamSynchronize(c.stream));
+    return (max_iter > 0 && !(mdx < tol)) ? RRT_NOT_CONVERGED : RRT_OK;
+}
+
+int rrt_set_state(rrt_ctx* x, const double* xs)
+{
+    if (!x) return RRT_E_ARG;
+    Ctx& c = x->c;
+    if (!c.have_tree) return fail(c, RRT_E_STATE, "rrt_build_tree has not been called");
+    if (xs) {
+        HIP_OK(launch_from_input_order_d(c, xs, c.x_s));
+        HIP_OK(launch_mux(c));
+    } else {
+        HIP_OK(launch_init_state(c, false));
+    }
+    c.have_columns = c.have_gamma = false;
+    return RRT_OK;
+}
+
+int rrt_get_state(rrt_ctx* x, double* x_out, double* lnG_out, double* G_out, float* tau_out)
+{
+    if (!x) return RRT_E_ARG;
+    Ctx& c = x->c;
+    if (!c.have_tree) return fail(c, RRT_E_STATE, "rrt_build_tree has not been called");
+    if (x_out) HIP_OK(launch_to_input_order_d(c, c.x_s, x_out, 1));
+    if (lnG_out) HIP_OK(launch_to_input_order_d(c, c.lnG_s, lnG_out, 1));
+    if (G_out) HIP_OK(launch_to_input_order_d(c, c.G_s, G_out, 1));
+    if (tau_out) HIP_OK(launch_to_input_order_f(c, c.tau_s, tau_out));
+    return RRT_OK;
+}
+
+int rrt_get_tree(rrt_ctx* x, int64_t cap, int64_t* n_nodes, float* lo, float* hi, int32_t* skip,
+                 int32_t* first, int32_t* count, int32_t* perm, uint64_t* codes)
+{
+    if (!x) return RRT_E_ARG;
+    Ctx& c = x->c;
+    if (!c.have_tree) return fail(c, RRT_E_STATE, "rrt_build_tree has not been called");
+    if (n_nodes) *n_nodes = c.n_nodes;
+    if (perm)
+        HIP_OK(hipMemcpyAsync(perm, c.perm, sizeof(int32_t) * c.n, hipMemcpyDeviceToHost, c.stream));
+    if (codes)
+        HIP_OK(hipMemcpyAsync(codes, c.codes, sizeof(uint64_t) * c.n, hipMemcpyDeviceToHost,
+                              c.stream));
+    if (lo || hi || skip || first || count) {
+        if (cap < c.n_nodes) {
+            HIP_OK(hipStreamSynchronize(c.stream));
+            return fail(c, RRT_E_CAPACITY, "tree has %lld nodes, capacity %lld",
+                        (long long)c.n_nodes, (long long)cap);
+        }
+        std::vector<Node> h(c.n_nodes);
+        HIP_OK(hipMemcpyAsync(h.data(), c.nodes, sizeof(Node) * c.n_nodes, hipMemcpyDeviceToHost,
+                              c.stream));
+        HIP_OK(hipStreamSynchronize(c.stream));
+        for (int64_t i = 0; i < c.n_nodes; ++i) {
+            const Node& d = h[i];
+            if (lo) { lo[3 * i] = d.a.x; lo[3 * i + 1] = d.a.y; lo[3 * i + 2] = d.a.z; }
+            if (hi) { hi[3 * i] = d.b.x; hi[3 * i + 1] = d.b.y; hi[3 * i + 2] = d.b.z; }
+            int sk, lw;
+            std::memcpy(&sk, &d.a.w, 4);
+            std::memcpy(&lw, &d.b.w, 4);
+            if (skip) skip[i] = sk;
+            if (lw < 0) {
+                if (first) first[i] = -1;
+                if (count) count[i] = 0;
+            } else {
+                if (first) first[i] = lw >> 3;
+                if (count) count[i] = (lw & 7) + 1;
+            }
+        }
+    }
+    HIP_OK(hipStreamSynchronize(c.stream));
+    return RRT_OK;
+}
+
+int rrt_get_hits(rrt_ctx* x, int64_t cap, int64_t* row_off, int32_t* hit_j, int32_t* hit_img)
+{
+    if (!x || !row_off) return x ? fail(x->c, RRT_E_ARG, "row_off is required") : RRT_E_ARG;
+    Ctx& c = x->c;
+    if (int r = need_tree(c)) return r;
+    const int64_t nr = c.n * (int64_t)c.n_ray;
+    uint64_t* cnt = nullptr;
+    HIP_OK(hipMalloc(&cnt, sizeof(uint64_t) * nr));
+    int rc = RRT_OK;
+    std::vector<uint64_t> hc(nr);
+    std::vector<int32_t> perm(c.n);
+    hipError_t e = launch_count_hits(c, cnt);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(hc.data(), cnt, sizeof(uint64_t) * nr, hipMemcpyDeviceToHost, c.stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(perm.data(), c.perm, sizeof(int32_t) * c.n, hipMemcpyDeviceToHost,
+                           c.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
+    if (e != hipSuccess) {
+        (void)hipFree(cnt);
+        return fail(c, RRT_E_HIP, "hit counting failed: %s", hipGetErrorString(e));
+    }
+    // rows in input order (p, k); internal ray id = k * n + tree position
+    std::vector<uint64_t> in_cnt(nr);
+    for (int64_t k = 0; k < c.n_ray; ++k)
+        for (int64_t i = 0; i < c.n; ++i) in_cnt[(int64_t)perm[i] * c.n_ray + k] = hc[k * c.n + i];
+    row_off[0] = 0;
+    for (int64_t r = 0; r < nr; ++r) row_off[r + 1] = row_off[r] + (int64_t)in_cnt[r];
+    const int64_t total = row_off[nr];
+    if (total > cap || !hit_j || !hit_img) {
+        (void)hipFree(cnt);
+        return total > cap ? fail(c, RRT_E_CAPACITY, "%lld hits, capacity %lld",
+                                  (long long)total, (long long)cap)
+                           : RRT_OK;
+    }
+    for (int64_t k = 0; k < c.n_ray; ++k)
+        for (int64_t i = 0; i < c.n; ++i) hc[k * c.n + i] = row_off[(int64_t)perm[i] * c.n_ray + k];
+    int32_t *dj = nullptr, *di = nullptr;
+    e = hipMemcpyAsync(cnt, hc.data(), sizeof(uint64_t) * nr, hipMemcpyHostToDevice, c.stream);
+    if (e == hipSuccess) e = hipMalloc(&dj, sizeof(int32_t) * std::max<int64_t>(total, 1));
+    if (e == hipSuccess) e = hipMalloc(&di, sizeof(int32_t) * std::max<int64_t>(total, 1));
+    if (e == hipSuccess) e = launch_record_hits(c, cnt, dj, di, (uint64_t)total);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(hit_j, dj, sizeof(int32_t) * total, hipMemcpyDeviceToHost, c.stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(hit_img, di, sizeof(int32_t) * total, hipMemcpyDeviceToHost, c.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
+    if (e != hipSuccess) rc = fail(c, RRT_E_HIP, "hit recording failed: %s", hipGetErrorString(e));
+    (void)hipFree(cnt);
+    if (dj) (void)hipFree(dj);
+    if (di) (void)hipFree(di);
+    return rc;
+}
+
+int rrt_enable_timing(rrt_ctx* x, int32_t on)
+{
+    if (!x) return RRT_E_ARG;
+    x->c.timing = on != 0;
+    return RRT_OK;
+}
+
+int rrt_get_timing(rrt_ctx* x, double* out4)
+{
+    if (!x || !out4) return RRT_E_ARG;
+    Ctx& c = x->c;
+    out4[0] = c.t_trace;
+    out4[1] = c.t_rate;
+    out4[2] = c.t_build;
+    out4[3] = c.n_trace;
+    return RRT_OK;
+}
+
+int rrt_reset_timing(rrt_ctx* x)
+{
+    if (!x) return RRT_E_ARG;
+    Ctx& c = x->c;
+    c.t_trace = c.t_rate = c.t_build = c.n_trace = 0.0;
+    c.total_hits = 0;
+    return RRT_OK;
+}
+
+int rrt_get_counters(rrt_ctx* x, int64_t* out2)
+{
+    if (!x || !out2) return RRT_E_ARG;
+    out2[0] = x->c.last_hits;
+    out2[1] = x->c.total_hits;
+    return RRT_OK;
+}
+
+}  // extern "C"

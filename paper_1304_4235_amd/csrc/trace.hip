@@ -1,0 +1,311 @@
+// Ray traversal and HI column accumulation (Sec. 4.1.1, eq. colden).
+//
+// One thread follows one ray: source particle p (tree order), direction k and,
+// in a periodic box, every image shift s whose tiles the segment can reach.
+// Lanes of a wave take consecutive sources in tree order with the same
+// direction, so neighbouring lanes walk nearly the same nodes.
+//
+// Node tests are FP32 slab tests against boxes padded outward by `pad`, which
+// is far larger than any FP32 rounding in the test, so they never reject a
+// particle the exact predicate accepts.  Leaf particles are decided by the
+// FP64 predicate below, with a fixed operation order and no contraction, so
+// that the set of intersected particles is reproducible bit for bit.
+//
+// A hit adds mu_j x_j / h_j^2 times the kernel chord integral K(b/h, z1/h,
+// z2/h) in units of h: for the truncated Gaussian (eq. Gt) the closed form
+// I(h,b,z1,z2) = (N h^3 sqrt(pi) / (2t)) e^{-t^2 q^2} [erf(t z2/h) - erf(t z1/h)] / h^2
+// with t = A h = 2 pi^(1/6), q = b/h, z clipped to the sphere and to [0, L].
+// The three one-dimensional factors come from cubic tables staged in LDS.
+#include "internal.h"
+
+#include <cmath>
+
+namespace rrt {
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// kernel tables (host, FP64)
+// ---------------------------------------------------------------------------
+struct KConst {
+    double t, C;     // C = N h^3 sqrt(pi) / (2 t)
+};
+
+KConst kconst()
+{
+    const double pi = 3.14159265358979323846;
+    double t = 2.0 * std::pow(pi, 1.0 / 6.0);
+    double nh3 = (8.0 / pi) / (std::erf(t) - 2.0 * t * std::exp(-t * t) / std::sqrt(pi));
+    return {t, nh3 * std::sqrt(pi) / (2.0 * t)};
+}
+
+// erf(t sqrt(w)) / sqrt(w): a power series in w near 0 (no 0/0), direct above.
+double erf_over_sqrt(double t, double w)
+{
+    const double pi = 3.14159265358979323846;
+    if (w < 0.01) {
+        double s = 0.0, term = t;   // t^(2n+1) w^n (-1)^n / n!
+        for (int k = 0; k < 30; ++k) {
+            s += term / (2 * k + 1);
+            term *= -t * t * w / (k + 1);
+        }
+        return 2.0 / std::sqrt(pi) * s;
+    }
+    return std::erf(t * std::sqrt(w)) / std::sqrt(w);
+}
+
+template <typename F>
+void fit_cubics(float4* out, F f)
+{
+    // cubic through u = 0, 1/3, 2/3, 1 on each piece, in monomial form in u
+    for (int i = 0; i < kTabIntervals; ++i) {
+        double a = (double)i / kTabIntervals, b = (double)(i + 1) / kTabIntervals;
+        double y0 = f(a), y1 = f(a + (b - a) / 3.0), y2 = f(a + 2.0 * (b - a) / 3.0), y3 = f(b);
+        // Newton divided differences on nodes 0, 1/3, 2/3, 1
+        double d1 = (y1 - y0) * 3.0, d2 = (y2 - y1) * 3.0, d3 = (y3 - y2) * 3.0;
+        double e1 = (d2 - d1) * 1.5, e2 = (d3 - d2) * 1.5;
+        double g1 = (e2 - e1);
+        // p(u) = y0 + d1 u + e1 u (u - 1/3) + g1 u (u - 1/3)(u - 2/3)
+        double c0 = y0;
+        double c1 = d1 - e1 / 3.0 + g1 * (2.0 / 9.0);
+        double c2 = e1 - g1;
+        double c3 = g1;
+        out[i] = make_float4((float)c0, (float)c1, (float)c2, (float)c3);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// device helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float tab_eval(const float4* __restrict__ tb, float x)
+{
+    float s = x * (float)kTabIntervals;
+    int i = (int)s;
+    i = i < 0 ? 0 : (i > kTabIntervals - 1 ? kTabIntervals - 1 : i);
+    float u = s - (float)i;
+    float4 c = tb[i];
+    return fmaf(fmaf(fmaf(c.w, u, c.z), u, c.y), u, c.x);
+}
+
+__device__ __forceinline__ float erf_t_odd(const float4* __restrict__ tb, float z)
+{
+    float a = fminf(fabsf(z), 1.0f);
+    float v = tab_eval(tb, a);
+    return z < 0.f ? -v : v;
+}
+
+enum { kModeColumn = 0, kModeCount = 1, kModeRecord = 2 };
+
+struct RayOut {
+    double* N;              // [n_ray][n] columns (column / record modes)
+    uint64_t* row_cnt;      // [n_ray * n] hits per ray (count mode)
+    const uint64_t* row_off;// [n_ray * n] write offsets (record mode)
+    int32_t* hit_j;         // record mode: input index of each hit
+    int32_t* hit_img;       // record mode: image code of each hit
+    uint64_t hit_cap;       // record mode: capacity of hit_j / hit_img
+    const int32_t* perm;
+    unsigned long long* hits_total;
+};
+
+// The canonical predicate (shared operation order with the FP64 reference):
+// d = (r_j - r_p) + s B ; s_par = d.u ; t = clamp(s_par, 0, L) ; c = d - t u ;
+// hit <=> |c|^2 < h^2.
+#pragma clang fp contract(off)
+template <int MODE>
+__global__ void __launch_bounds__(256)
+k_trace(const Node* __restrict__ nodes, const float4* __restrict__ p4,
+        const float* __restrict__ mux, const double* __restrict__ dirs,
+        const KernelTables* __restrict__ tabs, TraceGeom g, RayOut out)
+{
+    __shared__ float4 tab[3 * kTabIntervals];
+    if (MODE != kModeCount) {
+        const float4* src = reinterpret_cast<const float4*>(tabs);
+        for (int i = threadIdx.x; i < 3 * kTabIntervals; i += blockDim.x) tab[i] = src[i];
+        __syncthreads();
+    }
+    const float4* t_full = tab;
+    const float4* t_gauss = tab + kTabIntervals;
+    const float4* t_erf = tab + 2 * kTabIntervals;
+
+    const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t n_rays = (int64_t)g.n * g.n_ray;
+    uint32_t cnt = 0;
+    if (gid < n_rays) {
+        const int k = (int)(gid / g.n);
+        const int ps = (int)(gid - (int64_t)k * g.n);
+        const float4 P = p4[ps];
+        const double rp[3] = {(double)P.x, (double)P.y, (double)P.z};
+        const double u[3] = {dirs[3 * k], dirs[3 * k + 1], dirs[3 * k + 2]};
+        const double L = g.L, B = g.box;
+        const float Lf = (float)L;
+
+        int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+        if (B > 0.0) {
+            for (int a = 0; a < 3; ++a) {
+                double e = rp[a] + L * u[a];
+                double smin = rp[a] < e ? rp[a] : e, smax = rp[a] < e ? e : rp[a];
+                lo[a] = (int)ceil((smin - g.hmax - g.phi[a]) / B - 1e-6);
+                hi[a] = (int)floor((smax + g.hmax - g.plo[a]) / B + 1e-6);
+            }
+        }
+        float inv[3];
+        for (int a = 0; a < 3; ++a) {
+            float ua = (float)u[a];
+            if (fabsf(ua) < 1e-20f) ua = 1e-20f;
+            inv[a] = 1.0f / ua;
+        }
+        double acc = 0.0;
+        uint64_t w = (MODE == kModeRecord) ? out.row_off[gid] : 0;
+
+        for (int sx = lo[0]; sx <= hi[0]; ++sx)
+        for (int sy = lo[1]; sy <= hi[1]; ++sy)
+        for (int sz = lo[2]; sz <= hi[2]; ++sz) {
+            double sh[3] = {(double)sx * B, (double)sy * B, (double)sz * B};
+            if (!(B > 0.0)) sh[0] = sh[1] = sh[2] = 0.0;
+            // the image of particle j sits at r_j + sB, i.e. the ray meets the
+            // stored particles as if it started from r_p - sB
+            float oai[3], obi[3];
+            for (int a = 0; a < 3; ++a) {
+                double o = rp[a] - sh[a];
+                oai[a] = (float)(o + (double)g.pad) * inv[a];
+                obi[a] = (float)(o - (double)g.pad) * inv[a];
+            }
+            int node = 0;
+            while (node < g.n_nodes) {
+                const Node nd = nodes[node];
+                float tx0 = fmaf(nd.a.x, inv[0], -oai[0]), tx1 = fmaf(nd.b.x, inv[0], -obi[0]);
+                float ty0 = fmaf(nd.a.y, inv[1], -oai[1]), ty1 = fmaf(nd.b.y, inv[1], -obi[1]);
+                float tz0 = fmaf(nd.a.z, inv[2], -oai[2]), tz1 = fmaf(nd.b.z, inv[2], -obi[2]);
+                float tmin = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)),
+                                   fmaxf(fminf(tz0, tz1), 0.0f));
+                float tmax = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)),
+                                   fminf(fmaxf(tz0, tz1), Lf));
+                const int skip = __float_as_int(nd.a.w);
+                const int leafw = __float_as_int(nd.b.w);
+                // skip links always point past the node; max() keeps every walk finite
+                if (!(tmin <= tmax)) { node = max(skip, node + 1); continue; }
+                if (leafw < 0) { node = node + 1; continue; }
+                const int f = leafw >> 3;
+                const int c = (f + (leafw & 7) + 1 <= g.n) ? (leafw & 7) + 1 : 0;
+                for (int q = 0; q < c; ++q) {
+                    const int j = f + q;
+                    const float4 Q = p4[j];
+                    double d0 = ((double)Q.x - rp[0]) + sh[0];
+                    double d1 = ((double)Q.y - rp[1]) + sh[1];
+                    double d2 = ((double)Q.z - rp[2]) + sh[2];
+                    double sp = d0 * u[0] + d1 * u[1] + d2 * u[2];
+                    double tt = sp < 0.0 ? 0.0 : (sp > L ? L : sp);
+                    double c0 = d0 - tt * u[0];
+                    double c1 = d1 - tt * u[1];
+                    double c2 = d2 - tt * u[2];
+                    double D2 = c0 * c0 + c1 * c1 + c2 * c2;
+                    double hj = (double)Q.w;
+                    double h2 = hj * hj;
+                    if (!(D2 < h2)) continue;
+                    ++cnt;
+                    if (MODE == kModeCount) continue;
+                    if (MODE == kModeRecord) {
+                        if (w < out.hit_cap) {
+                            out.hit_j[w] = out.perm[j];
+                            out.hit_img[w] = (sx + 8) | ((sy + 8) << 4) | ((sz + 8) << 8);
+                        }
+                        ++w;
+                    }
+                    double px = d0 - sp * u[0], py = d1 - sp * u[1], pz = d2 - sp * u[2];
+                    double b2 = px * px + py * py + pz * pz;
+                    double l2 = h2 - b2;
+                    if (!(l2 > 0.0)) continue;
+                    const float ih2 = 1.0f / (float)h2;
+                    const float wq = fminf((float)l2 * ih2, 1.0f);
+                    const double Lr = L - sp;
+                    float K;
+                    if (sp >= 0.0 && sp * sp >= l2 && Lr >= 0.0 && Lr * Lr >= l2) {
+                        K = sqrtf(wq) * tab_eval(t_full, wq);
+                    } else {
+                        const float ih = 1.0f / Q.w;
+                        const float lh = sqrtf(wq);
+                        const float z1 = fmaxf((float)(-sp) * ih, -lh);
+                        const float z2 = fminf((float)Lr * ih, lh);
+                        const float q2 = fminf((float)b2 * ih2, 1.0f);
+                        K = z2 > z1 ? tab_eval(t_gauss, q2) *
+                                          (erf_t_odd(t_erf, z2) - erf_t_odd(t_erf, z1))
+                                    : 0.0f;
+                    }
+                    acc += (double)(mux[j] * ih2 * K);
+                }
+                node = max(skip, node + 1);
+            }
+        }
+        if (MODE != kModeCount) out.N[(int64_t)k * g.n + ps] = acc;
+        if (MODE == kModeCount) out.row_cnt[gid] = cnt;
+    }
+    // one atomic per wave for the total intersection count
+    uint64_t c64 = cnt;
+    for (int off = 32; off > 0; off >>= 1) c64 += __shfl_xor(c64, off, 64);
+    if ((threadIdx.x & 63) == 0 && c64) atomicAdd(out.hits_total, (unsigned long long)c64);
+}
+#pragma clang fp contract(on)
+
+}  // namespace
+
+void fill_kernel_tables(KernelTables* host)
+{
+    const KConst kc = kconst();
+    const double t = kc.t, C = kc.C;
+    fit_cubics(host->chord_full, [&](double w) {
+        return 2.0 * C * std::exp(-t * t * (1.0 - w)) * erf_over_sqrt(t, w);
+    });
+    fit_cubics(host->gauss, [&](double q2) { return C * std::exp(-t * t * q2); });
+    fit_cubics(host->erf_t, [&](double z) { return std::erf(t * z); });
+}
+
+static hipError_t launch_mode(Ctx& c, int mode, RayOut o)
+{
+    int bs = c.prm.block_size > 0 ? c.prm.block_size : 256;
+    int64_t n_rays = c.n * (int64_t)c.n_ray;
+    unsigned nb = (unsigned)((n_rays + bs - 1) / bs);
+    if (mode == kModeColumn)
+        hipLaunchKernelGGL(k_trace<kModeColumn>, dim3(nb), dim3(bs), 0, c.stream, c.nodes, c.p4,
+                           c.mux_s, c.dirs, c.tables, c.geom, o);
+    else if (mode == kModeCount)
+        hipLaunchKernelGGL(k_trace<kModeCount>, dim3(nb), dim3(bs), 0, c.stream, c.nodes, c.p4,
+                           c.mux_s, c.dirs, c.tables, c.geom, o);
+    else
+        hipLaunchKernelGGL(k_trace<kModeRecord>, dim3(nb), dim3(bs), 0, c.stream, c.nodes, c.p4,
+                           c.mux_s, c.dirs, c.tables, c.geom, o);
+    return hipGetLastError();
+}
+
+hipError_t launch_columns(Ctx& c)
+{
+    RayOut o{};
+    o.N = c.N_s;
+    o.perm = c.perm;
+    o.hits_total = c.red + 1;
+    return launch_mode(c, kModeColumn, o);
+}
+
+hipError_t launch_count_hits(Ctx& c, uint64_t* row_cnt)
+{
+    RayOut o{};
+    o.row_cnt = row_cnt;
+    o.perm = c.perm;
+    o.hits_total = c.red + 1;
+    return launch_mode(c, kModeCount, o);
+}
+
+hipError_t launch_record_hits(Ctx& c, const uint64_t* row_off, int32_t* hit_j, int32_t* hit_img,
+                              uint64_t cap)
+{
+    RayOut o{};
+    o.hit_cap = cap;
+    o.N = c.N_s;
+    o.row_off = row_off;
+    o.hit_j = hit_j;
+    o.hit_img = hit_img;
+    o.perm = c.perm;
+    o.hits_total = c.red + 1;
+    return launch_mode(c, kModeRecord, o);
+}
+
+}  // namespace rrt

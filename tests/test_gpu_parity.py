@@ -1,0 +1,307 @@
+"""Parity of the HIP path with the FP64 oracle, through the C ABI.
+
+Bars (written in each test):
+  * tree arrays and ray-particle hit sets: bit-exact;
+  * columns: relative 1e-6;
+  * ln Gamma: absolute 1e-4 (= 1e-4 relative Gamma) where tau_eff <= 100;
+    beyond, |d tau_eff| <= 1e-6 tau_eff (Gamma underflows there);
+  * x: relative 1e-4.
+Columns are compared for the same state x on both sides, so each iteration of
+the order-independent update can be checked on a sample of source particles.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+COL_RTOL = 1e-6
+LNG_ATOL = 1e-4
+TAU_RTOL = 1e-6
+X_RTOL = 1e-4
+
+
+def _solver(wl, **kw):
+    from paper_1304_4235_amd import Solver
+    return Solver.from_workload(wl, **kw)
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _check_columns(Ng, No):
+    Ng = np.asarray(Ng)
+    err = np.abs(Ng - No)
+    bad = err > COL_RTOL * np.abs(No) + 1e-300
+    assert not bad.any(), f"columns differ: max rel {np.max(err / np.maximum(No, 1e-300)):.3e}"
+
+
+def _check_rates(lnG_g, lnG_o, tau_o):
+    lnG_g, lnG_o, tau_o = map(np.asarray, (lnG_g, lnG_o, tau_o))
+    thin = tau_o <= 100
+    d = np.abs(lnG_g - lnG_o)
+    assert np.all(d[thin] <= LNG_ATOL), f"ln Gamma differs by {d[thin].max():.3e}"
+    if (~thin).any():
+        assert np.all(d[~thin] <= TAU_RTOL * tau_o[~thin]), "tau_eff differs"
+
+
+def _check_x(xg, xo):
+    xg, xo = np.asarray(xg), np.asarray(xo)
+    rel = np.abs(xg - xo) / np.abs(xo)
+    assert np.all(rel <= X_RTOL), f"x differs: max rel {rel.max():.3e}"
+
+
+def _hitsets(off, hj, hi, rows):
+    return [sorted(zip(hj[off[r]:off[r + 1]].tolist(), hi[off[r]:off[r + 1]].tolist()))
+            for r in rows]
+
+
+# ---------------------------------------------------------------------------
+# tree
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n,leaf,dup", [(1, 4, False), (2, 1, False), (3, 4, False),
+                                        (5, 4, False), (1000, 1, False), (4099, 4, False),
+                                        (10007, 8, False), (3000, 4, True)])
+def test_tree_bit_exact(n, leaf, dup):
+    rng = np.random.default_rng(n + leaf)
+    pos = rng.uniform(-30, 30, (n, 3)).astype(np.float32)
+    if dup:
+        pos[n // 2:] = pos[: n - n // 2]
+    h = rng.uniform(0.5, 3, n).astype(np.float32)
+    wl = W.Workload(name="tree", pos=pos, h=h, mu=np.ones(n, np.float32),
+                    n_H=np.ones(n, np.float32), T=np.full(n, 1e4, np.float32),
+                    dirs=W.healpix_dirs(1), sigma=np.array([W.SIGMA_TH]),
+                    w=np.array([1e-12 / W.SIGMA_TH]), l_ray=10.0, box=0.0, tol=1e-3, max_iter=5)
+    _say("tree", n, leaf, dup)
+    s = _solver(wl, leaf_size=leaf)
+    g = s.tree()
+    o = oracle.lbvh(pos, h, leaf)
+    np.testing.assert_array_equal(g["codes"], o["codes"])
+    np.testing.assert_array_equal(g["perm"], o["perm"])
+    assert g["n_nodes"] == o["n_nodes"]
+    np.testing.assert_array_equal(g["lo"], o["lo"])
+    np.testing.assert_array_equal(g["hi"], o["hi"])
+    np.testing.assert_array_equal(g["skip"], o["skip"])
+    np.testing.assert_array_equal(g["count"], o["count"])
+    leaf_nodes = o["count"] > 0
+    np.testing.assert_array_equal(g["first"][leaf_nodes], o["first"][leaf_nodes])
+
+
+# ---------------------------------------------------------------------------
+# lattice (periodic, single bin): hit sets, columns, one step, full solve
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def lattice():
+    return W.make_config(0)
+
+
+@pytest.fixture(scope="module")
+def lattice_oracle(lattice):
+    _say("oracle solve: uniform lattice 16^3")
+    return oracle.solve(lattice)
+
+
+def test_lattice_hit_sets_exact(lattice):
+    wl = lattice
+    s = _solver(wl)
+    _say("lattice hit sets")
+    off, hj, hi = s.hits()
+    src = np.arange(0, wl.n, 61)
+    N, o_off, o_hj, o_hi = oracle.columns(wl, oracle.x_thin(wl), sources=src, hits=True)
+    for i, p in enumerate(src):
+        rows = [p * wl.n_ray + k for k in range(wl.n_ray)]
+        got = _hitsets(off, hj, hi, rows)
+        want = _hitsets(o_off, o_hj, o_hi, [i * wl.n_ray + k for k in range(wl.n_ray)])
+        assert got == want, f"source {p}"
+    assert off[-1] > 300 * wl.n * wl.n_ray      # ~320 hits per ray
+
+
+def test_lattice_columns_and_step(lattice):
+    wl = lattice
+    s = _solver(wl)
+    rng = np.random.default_rng(0)
+    x = oracle.x_thin(wl) * rng.uniform(1, 50, wl.n)
+    s.set_state(torch.tensor(x))
+    _say("lattice columns for a given state")
+    N, nh = s.compute_columns()
+    lnG, G, tau = s.compute_gamma()
+    xn, mdx = s.update_equilibrium()
+    src = np.arange(0, wl.n, 37)
+    ref = oracle.step(wl, x, sources=src)
+    _check_columns(N.cpu().numpy()[src], ref["N"])
+    _check_rates(lnG.cpu().numpy()[src], ref["lnG"], ref["tau"])
+    _check_x(xn.cpu().numpy()[src], ref["x_new"])
+    assert mdx == pytest.approx(np.max(np.abs(xn.cpu().numpy() - x)), rel=1e-12)
+
+
+def test_lattice_solve_every_iteration(lattice, lattice_oracle):
+    """Each GPU iterate against the oracle's step from the oracle's previous iterate."""
+    wl, ref = lattice, lattice_oracle
+    s = _solver(wl)
+    assert ref["iters"] >= 2
+    src = np.arange(0, wl.n, 53)
+    for k in range(ref["iters"]):
+        _say("lattice iteration", k)
+        s.set_state(torch.tensor(ref["x_hist"][k]))
+        s.compute_columns(want_N=False, count=False)
+        lnG, G, tau = s.compute_gamma()
+        xn, _ = s.update_equilibrium()
+        lnG_o = ref["lnG_hist"][k]
+        tau_o = math.log(oracle.gamma_thin(wl)) - lnG_o
+        _check_rates(lnG.cpu().numpy(), lnG_o, tau_o)
+        _check_x(xn.cpu().numpy(), ref["x_hist"][k + 1])
+
+
+def test_lattice_end_to_end(lattice, lattice_oracle):
+    wl, ref = lattice, lattice_oracle
+    s = _solver(wl)
+    _say("lattice end to end")
+    r = s.iterate(wl.max_iter, wl.tol)
+    assert r["converged"]
+    assert r["iters"] == ref["iters"]
+    _check_x(r["x"].cpu().numpy(), ref["x_hist"][-1])
+
+
+# ---------------------------------------------------------------------------
+# isolated halos with a 128-bin power-law spectrum
+# ---------------------------------------------------------------------------
+def test_small_halo_step_all_sources():
+    wl = W.isothermal_halo(n=8192, seed=11)
+    s = _solver(wl)
+    x = oracle.x_thin(wl) * np.linspace(1.0, 1e3, wl.n)
+    x = np.minimum(x, 0.99)
+    s.set_state(torch.tensor(x))
+    _say("small halo step")
+    N, nh = s.compute_columns()
+    lnG, _, _ = s.compute_gamma()
+    xn, _ = s.update_equilibrium()
+    ref = oracle.step(wl, x)
+    _check_columns(N.cpu().numpy(), ref["N"])
+    _check_rates(lnG.cpu().numpy(), ref["lnG"], ref["tau"])
+    _check_x(xn.cpu().numpy(), ref["x_new"])
+
+
+def test_small_halo_hits_exact():
+    wl = W.isothermal_halo(n=8192, seed=12)
+    s = _solver(wl)
+    _say("small halo hits")
+    off, hj, hi = s.hits()
+    src = np.arange(0, wl.n, 97)
+    _, o_off, o_hj, o_hi = oracle.columns(wl, np.ones(wl.n), sources=src, hits=True)
+    for i, p in enumerate(src):
+        got = _hitsets(off, hj, hi, [p * 12 + k for k in range(12)])
+        want = _hitsets(o_off, o_hj, o_hi, [i * 12 + k for k in range(12)])
+        assert got == want
+
+
+def test_full_halo_sampled_sources():
+    """The 262144-particle halo: the GPU solve's iterates, checked one step at a
+    time on sampled sources against the oracle fed the same state."""
+    wl = W.make_config(1)
+    s = _solver(wl)
+    rng = np.random.default_rng(1)
+    src = np.sort(rng.choice(wl.n, 24, replace=False))
+    x = oracle.x_thin(wl)
+    for k in range(3):
+        _say("full halo iteration", k)
+        s.set_state(torch.tensor(x))
+        N, _ = s.compute_columns()
+        lnG, _, _ = s.compute_gamma()
+        xn, _ = s.update_equilibrium()
+        ref = oracle.step(wl, x, sources=src)
+        _check_columns(N.cpu().numpy()[src], ref["N"])
+        _check_rates(lnG.cpu().numpy()[src], ref["lnG"], ref["tau"])
+        _check_x(xn.cpu().numpy()[src], ref["x_new"])
+        x = xn.cpu().numpy()
+
+
+# ---------------------------------------------------------------------------
+# edge cases and invariances
+# ---------------------------------------------------------------------------
+def _tiny(pos, h, L=10.0, box=0.0, dirs=None):
+    pos = np.asarray(pos, np.float32).reshape(-1, 3)
+    n = pos.shape[0]
+    return W.Workload(name="tiny", pos=pos, h=np.asarray(h, np.float32).reshape(n),
+                      mu=np.full(n, 1e18, np.float32), n_H=np.full(n, 1e-2, np.float32),
+                      T=np.full(n, 1e4, np.float32),
+                      dirs=W.healpix_dirs(1) if dirs is None else dirs,
+                      sigma=np.array([W.SIGMA_TH]), w=np.array([1e-12 / W.SIGMA_TH]),
+                      l_ray=L, box=box, tol=1e-6, max_iter=20)
+
+
+def test_single_particle_self_column():
+    wl = _tiny([(1.0, 2.0, 3.0)], [2.0])
+    s = _solver(wl)
+    x = np.array([0.5])
+    s.set_state(torch.tensor(x))
+    N, nh = s.compute_columns()
+    assert nh == 12
+    _check_columns(N.cpu().numpy(), oracle.columns(wl, x))
+
+
+def test_zero_length_rays_give_thin_rate():
+    wl = _tiny(np.random.default_rng(2).uniform(0, 5, (50, 3)), np.full(50, 1.5), L=0.0)
+    s = _solver(wl)
+    N, nh = s.compute_columns()
+    assert float(N.abs().max()) == 0.0
+    lnG, G, tau = s.compute_gamma()
+    np.testing.assert_allclose(G.cpu().numpy(), 1e-12, rtol=1e-12)
+
+
+def test_periodic_images_small_box():
+    """Rays longer than the box: images up to two boxes away."""
+    rng = np.random.default_rng(3)
+    wl = _tiny(rng.uniform(0, 10, (200, 3)), rng.uniform(0.8, 2.0, 200), L=21.0, box=10.0)
+    s = _solver(wl)
+    off, hj, hi = s.hits()
+    src = np.arange(0, 200, 9)
+    x = np.full(200, 0.3)
+    N_o, o_off, o_hj, o_hi = oracle.columns(wl, x, sources=src, hits=True)
+    for i, p in enumerate(src):
+        assert _hitsets(off, hj, hi, [p * 12 + k for k in range(12)]) == \
+            _hitsets(o_off, o_hj, o_hi, [i * 12 + k for k in range(12)])
+    s.set_state(torch.tensor(x))
+    N, _ = s.compute_columns()
+    _check_columns(N.cpu().numpy()[src], N_o)
+
+
+def test_permutation_invariance_and_determinism():
+    wl = W.isothermal_halo(n=4096, seed=5)
+    perm = np.random.default_rng(9).permutation(wl.n)
+    wl2 = W.Workload(**{**wl.__dict__, "pos": wl.pos[perm], "h": wl.h[perm], "mu": wl.mu[perm],
+                        "n_H": wl.n_H[perm], "T": wl.T[perm]})
+    a = _solver(wl).iterate(10, 0.0)
+    b = _solver(wl2).iterate(10, 0.0)
+    c = _solver(wl).iterate(10, 0.0)
+    np.testing.assert_array_equal(a["x"].cpu().numpy(), c["x"].cpu().numpy())  # run to run
+    np.testing.assert_allclose(a["x"].cpu().numpy()[perm], b["x"].cpu().numpy(), rtol=1e-6)
+
+
+def test_resume_from_state():
+    wl = W.isothermal_halo(n=4096, seed=6)
+    full = _solver(wl).iterate(4, 0.0)
+    s = _solver(wl)
+    half = s.iterate(2, 0.0)
+    s2 = _solver(wl)
+    s2.set_state(half["x"])
+    rest = s2.iterate(2, 0.0)
+    np.testing.assert_array_equal(full["x"].cpu().numpy(), rest["x"].cpu().numpy())
+
+
+def test_bad_input_is_rejected():
+    from paper_1304_4235_amd import RRTError, Solver
+    wl = _tiny([(0, 0, 0), (1, 1, 1)], [1.0, -1.0])
+    with pytest.raises(RRTError, match="RRT_E_INPUT"):
+        Solver.from_workload(wl)
+    wl = _tiny([(0, 0, np.nan), (1, 1, 1)], [1.0, 1.0])
+    with pytest.raises(RRTError, match="RRT_E_INPUT"):
+        Solver.from_workload(wl)
+    s = Solver(10.0)
+    with pytest.raises(RRTError, match="RRT_E_STATE"):
+        s.compute_columns()
