@@ -1,0 +1,175 @@
+"""Throughput of the reverse-ray-tracing fixed point on one MI355X.
+
+One step = one whole solve of the workload: tree build over particles already
+resident in HBM, then the order-independent fixed point (columns -> rate ->
+equilibrium) until max|dx| < tol.  Reported:
+
+  value   ray-particle intersections per second over the timed steps
+          (every iteration's columns sum over all intersections, periodic
+          images counted separately);
+  particles_per_s_per_iteration  N_p * iterations / time;
+  roofline  for the dominant kernel (traversal + column): algorithmic bytes
+          per launch (20 B per intersection: x, y, z, h, mu*x in FP32; plus
+          the 8-byte column per ray) over the average launch duration, timed
+          with HIP events on the library's stream, against 8 TB/s HBM;
+  cpu_baseline  the FP64 oracle on a bounded sample of source particles of
+          the same workload (the update is order-independent, so a sample of
+          sources at the same state is an exact sub-problem).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_HIT = 20.0          # x, y, z, h, mu*x (FP32) of each intersected particle
+BYTES_PER_RAY = 8.0           # the FP64 column written per ray
+METRIC = "ray-particle intersections/s + particles/s per iteration; fwd+adjoint vs plain"
+
+
+def make_workload(name: str):
+    import workloads as W
+    if name == "isothermal_halo_262144":
+        return W.make_config(1)
+    if name == "uniform_lattice_4096":
+        return W.make_config(0)
+    if name == "lognormal_field_2097152":
+        return W.make_config(2)
+    if name.startswith("isothermal_halo_"):
+        return W.isothermal_halo(n=int(name.rsplit("_", 1)[1]))
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(wl, x, budget_s: float = 12.0):
+    """The oracle on a bounded sample of sources, scaled to intersections/s."""
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or min(16, os.cpu_count() or 1)
+    rng = np.random.default_rng(7)
+    m = 32
+    t_used, hits, done = 0.0, 0, 0
+    while True:
+        src = np.sort(rng.choice(wl.n, min(m, wl.n), replace=False))
+        t0 = time.perf_counter()
+        _, cnt = oracle.columns_and_counts(wl, x, src, n_threads=threads)
+        dt = time.perf_counter() - t0
+        t_used += dt
+        hits += int(cnt.sum())
+        done += src.size
+        if t_used > budget_s / 3 or done >= wl.n:
+            break
+        m = int(min(wl.n, max(m * 2, m * (budget_s / 2) / max(dt, 1e-3))))
+    cpu = platform.processor() or platform.machine()
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": hits / t_used, "unit": "intersections/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{done} random source particles x {wl.n_ray} rays, one column pass "
+                      f"(brute force over all {wl.n} particles, adaptive quadrature) at the "
+                      f"optically thin state; {hits} intersections in {t_used:.1f} s on {cpu}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="isothermal_halo_262144")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--leaf", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: this build has no multi-GPU path "
+              f"(asked for --gpus {args.gpus})", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1304_4235_amd import Solver
+    import oracle
+
+    wl = make_workload(args.workload)
+    print(f"workload {wl.name}: n={wl.n} rays={wl.n_ray} bins={wl.n_bins} "
+          f"l_ray={wl.l_ray} box={wl.box}", file=sys.stderr, flush=True)
+    s = Solver.from_workload(wl, leaf_size=args.leaf, block_size=args.block, build=False)
+    torch.cuda.synchronize()
+
+    def step():
+        s.build_tree()
+        return s.iterate(wl.max_iter, wl.tol, want_x=False)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    s.enable_timing(True)
+    s.reset_timing()
+    iters = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r = step()
+        iters.append(r["iters"])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    tm = s.timing()
+    s.enable_timing(False)
+
+    total_hits = tm["total_hits"]
+    n_it = int(np.sum(iters))
+    hits_per_launch = total_hits / max(tm["n_trace"], 1)
+    avg_trace_ms = tm["trace_ms"] / max(tm["n_trace"], 1)
+    alg_bytes = BYTES_PER_HIT * hits_per_launch + BYTES_PER_RAY * wl.n * wl.n_ray
+    achieved = alg_bytes / (avg_trace_ms * 1e-3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": total_hits / dt,
+        "unit": "intersections/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 box tests and kernel terms, f64 predicate and sums",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "particles": wl.n, "rays_per_particle": wl.n_ray,
+                   "frequency_bins": wl.n_bins, "l_ray_kpc": wl.l_ray,
+                   "box_kpc": wl.box or None, "tol_abs_dx": wl.tol,
+                   "iterations_per_step": iters},
+        "particles_per_s_per_iteration": wl.n * n_it / dt,
+        "intersections_per_iteration": hits_per_launch,
+        "phase_ms_per_step": {"traversal": tm["trace_ms"] / args.steps,
+                              "rate_equilibrium": tm["rate_ms"] / args.steps,
+                              "tree_build": tm["build_ms"] / args.steps},
+        "roofline": {"bound": "hbm", "kernel": "k_trace<0> (traversal + column)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "avg_launch_ms": avg_trace_ms,
+                     "algorithmic_bytes_per_launch": alg_bytes},
+    }
+    print(f"timed {args.steps} steps in {dt:.3f} s; iterations {iters}", file=sys.stderr,
+          flush=True)
+    if not args.no_cpu_baseline:
+        print("cpu baseline (oracle sample)...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(wl, oracle.x_thin(wl))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -152,6 +152,21 @@ def columns(wl, x: np.ndarray, sources=None, hits: bool = False, rtol=DEFAULT_RT
     return N, off, hj[: off[-1]], hi[: off[-1]]
 
 
+def columns_and_counts(wl, x: np.ndarray, sources, rtol=DEFAULT_RTOL, n_threads: int = None):
+    """Columns and per-ray intersection counts in one brute-force pass."""
+    L = lib()
+    src = _c(sources, np.int64)
+    nt = N_THREADS if n_threads is None else n_threads
+    N = np.zeros((src.size, wl.n_ray), np.float64)
+    cnt = np.zeros(src.size * wl.n_ray, np.int64)
+    rc = L.orc_columns(wl.n, _p(_c(wl.pos, np.float32)), _p(_c(wl.h, np.float32)),
+                       _p(_c(wl.mu, np.float32)), _p(_c(x, np.float64)), wl.n_ray,
+                       _p(_c(wl.dirs, np.float64)), wl.l_ray, wl.box, src.size, _p(src), rtol, 1,
+                       _p(N), _p(cnt), None, None, None, nt)
+    assert rc == 0
+    return N, cnt.reshape(src.size, wl.n_ray)
+
+
 def gamma(N: np.ndarray, sigma: np.ndarray, w: np.ndarray):
     """(ln Gamma, Gamma, tau_eff) per source from columns N[src, k]."""
     N = _c(N, np.float64)
