@@ -35,6 +35,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_HIT = 20.0          # x, y, z, h, mu*x (FP32) of each intersected particle
 BYTES_PER_RAY = 8.0           # the FP64 column written per ray
+BYTES_PER_PATH_HIT = 8.0      # recorded (particle index, K/h^2) streamed per intersection
+BYTES_PER_ROW = 16.0          # row offset read + FP64 column written per ray
 METRIC = "ray-particle intersections/s + particles/s per iteration; fwd+adjoint vs plain"
 
 
@@ -93,6 +95,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--leaf", type=int, default=0)
+    ap.add_argument("--traversal", type=int, default=0, help="0 wave-cooperative, 1 per lane")
+    ap.add_argument("--paths", type=int, default=-1,
+                    help="-1 record ray paths when they fit (default), 0 traverse every iteration")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this build has no multi-GPU path "
@@ -106,7 +111,8 @@ def main():
     wl = make_workload(args.workload)
     print(f"workload {wl.name}: n={wl.n} rays={wl.n_ray} bins={wl.n_bins} "
           f"l_ray={wl.l_ray} box={wl.box}", file=sys.stderr, flush=True)
-    s = Solver.from_workload(wl, leaf_size=args.leaf, block_size=args.block, build=False)
+    s = Solver.from_workload(wl, leaf_size=args.leaf, block_size=args.block,
+                             record_paths=args.paths, traversal=args.traversal, build=False)
     torch.cuda.synchronize()
 
     def step():
@@ -131,10 +137,33 @@ def main():
 
     total_hits = tm["total_hits"]
     n_it = int(np.sum(iters))
-    hits_per_launch = total_hits / max(tm["n_trace"], 1)
-    avg_trace_ms = tm["trace_ms"] / max(tm["n_trace"], 1)
-    alg_bytes = BYTES_PER_HIT * hits_per_launch + BYTES_PER_RAY * wl.n * wl.n_ray
-    achieved = alg_bytes / (avg_trace_ms * 1e-3) / 1e9
+    hits_per_iter = total_hits / max(n_it, 1)
+    rays = wl.n * wl.n_ray
+    kernels = {}
+    if tm["n_trace"]:
+        avg = tm["trace_ms"] / tm["n_trace"]
+        b = BYTES_PER_HIT * hits_per_iter + BYTES_PER_RAY * rays
+        kernels["traversal"] = dict(kernel="k_trace<0> (traversal + column)", launches=tm["n_trace"],
+                                    total_ms=tm["trace_ms"], avg_launch_ms=avg,
+                                    algorithmic_bytes_per_launch=b,
+                                    achieved=b / (avg * 1e-3) / 1e9)
+    if tm["n_path"]:
+        avg = tm["path_ms"] / tm["n_path"]
+        b = BYTES_PER_PATH_HIT * hits_per_iter + BYTES_PER_ROW * rays
+        kernels["recorded_paths"] = dict(kernel="k_path_columns (columns from recorded paths)",
+                                         launches=tm["n_path"], total_ms=tm["path_ms"],
+                                         avg_launch_ms=avg, algorithmic_bytes_per_launch=b,
+                                         achieved=b / (avg * 1e-3) / 1e9)
+    if tm["record_ms"]:
+        kernels["path_recording"] = dict(kernel="k_trace<1> + k_trace<3> (count, record)",
+                                         total_ms=tm["record_ms"],
+                                         per_step_ms=tm["record_ms"] / args.steps)
+    dom = max((k for k in kernels if "achieved" in kernels[k]),
+              key=lambda k: kernels[k]["total_ms"])
+    achieved = kernels[dom]["achieved"]
+    alg_bytes = kernels[dom]["algorithmic_bytes_per_launch"]
+    avg_trace_ms = kernels[dom]["avg_launch_ms"]
+    hits_per_launch = hits_per_iter
     out = {
         "metric": METRIC,
         "value": total_hits / dt,
@@ -155,13 +184,16 @@ def main():
         "particles_per_s_per_iteration": wl.n * n_it / dt,
         "intersections_per_iteration": hits_per_launch,
         "phase_ms_per_step": {"traversal": tm["trace_ms"] / args.steps,
+                              "path_recording": tm["record_ms"] / args.steps,
+                              "columns_from_paths": tm["path_ms"] / args.steps,
                               "rate_equilibrium": tm["rate_ms"] / args.steps,
                               "tree_build": tm["build_ms"] / args.steps},
-        "roofline": {"bound": "hbm", "kernel": "k_trace<0> (traversal + column)",
+        "roofline": {"bound": "hbm", "kernel": kernels[dom]["kernel"],
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "avg_launch_ms": avg_trace_ms,
                      "algorithmic_bytes_per_launch": alg_bytes},
+        "kernels": kernels,
     }
     print(f"timed {args.steps} steps in {dt:.3f} s; iterations {iters}", file=sys.stderr,
           flush=True)

@@ -64,10 +64,26 @@ typedef struct rrt_ctx rrt_ctx;
 typedef struct {
     double l_ray;          /* ray length in kpc, >= 0 (Sec. 3.3: l_ray)              */
     double box;            /* periodic box side in kpc; 0 = isolated (no images)    */
+    int64_t path_budget;   /* bytes the recorded ray paths may take; 0 = half of the
+                              free device memory at the time of recording           */
     int32_t leaf_size;     /* max particles per tree leaf, 1..8 (0 = default 4)     */
     int32_t block_size;    /* threads per block of the traversal (0 = default 256)  */
-    int32_t reserved[4];   /* must be zero                                           */
+    int32_t record_paths;  /* -1 = record when within path_budget (default),
+                              0 = traverse every iteration, 1 = require recording   */
+    int32_t traversal;     /* 0 = wave-cooperative walk (default), 1 = one
+                              independent walk per lane; identical results          */
+    int32_t reserved[2];   /* must be zero                                           */
 } rrt_params;
+
+/* Ray paths.  The geometry of every ray (which particles it intersects and the
+ * kernel chord factor K/h^2 of each) does not depend on x, because the column
+ * is linear in the neutral fractions (Sec. 4.1.1, eq. colden).  With path
+ * recording the first column evaluation after a tree build traverses the tree
+ * twice (count, then record 8 bytes per intersection: particle index and
+ * factor); every evaluation then forms N = sum (mu x)_j * factor_j by a
+ * streaming product over the recorded paths.  Without it, every evaluation
+ * traverses the tree.  Both give the same intersections and terms; the two
+ * sums differ only in summation order. */
 
 /* Library version as major*10000 + minor*100 + patch. */
 int rrt_version(void);
@@ -170,13 +186,16 @@ int rrt_get_tree(rrt_ctx* ctx, int64_t cap, int64_t* n_nodes, float* lo, float* 
 int rrt_get_hits(rrt_ctx* ctx, int64_t cap, int64_t* row_off, int32_t* hit_j,
                  int32_t* hit_img);
 
-/* Accumulated device time (ms, HIP events on the context's stream) of the
- * last rrt_iterate_equilibrium / rrt_compute_columns calls per phase:
- * out[0] traversal+column kernels, out[1] rate+equilibrium kernels,
- * out[2] tree build, out[3] number of traversal launches timed.
- * Timing is recorded only after rrt_enable_timing(ctx, 1). */
+/* Accumulated device time (ms, HIP events on the context's stream) since the
+ * last rrt_reset_timing, per phase: out8[0] traversal + column launches,
+ * out8[1] rate + equilibrium, out8[2] tree builds, out8[3] number of traversal
+ * launches, out8[4] path recording (count + record traversals), out8[5]
+ * columns from recorded paths, out8[6] number of those launches, out8[7]
+ * intersections held in the recorded paths (-1 when none are valid).
+ * Timing is recorded only after rrt_enable_timing(ctx, 1); each timed phase
+ * synchronises the stream. */
 int rrt_enable_timing(rrt_ctx* ctx, int32_t on);
-int rrt_get_timing(rrt_ctx* ctx, double* out4);
+int rrt_get_timing(rrt_ctx* ctx, double* out8);
 int rrt_reset_timing(rrt_ctx* ctx);
 
 /* Intersection counters (host): out2[0] = intersections of the last iteration

@@ -84,6 +84,14 @@ struct Ctx {
     int32_t* perm = nullptr;     // tree order -> input index
     uint64_t* codes = nullptr;   // sorted keys
 
+    // recorded ray paths (rows = rays in [k][tree position] order)
+    uint64_t* row_off = nullptr;  // [n_ray * n + 1]
+    int2* path = nullptr;         // (tree index, factor K/h^2 bits) per intersection
+    uint64_t path_cap = 0;        // entries allocated
+    int64_t path_hits = 0;        // entries in use
+    bool paths_valid = false;
+    bool paths_unfit = false;     // recording was tried and exceeded the budget
+
     // tree
     Node* nodes = nullptr;
     // build scratch
@@ -125,6 +133,7 @@ struct Ctx {
     // timing
     bool timing = false;
     double t_trace = 0, t_rate = 0, t_build = 0, n_trace = 0;
+    double t_record = 0, t_spmv = 0, n_spmv = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
 };
 
@@ -139,6 +148,8 @@ hipError_t scan_exclusive_u64(Ctx& c, const uint64_t* in, uint64_t* out, int64_t
 // ---- launchers (trace.hip) ----
 void fill_kernel_tables(KernelTables* host);
 hipError_t launch_columns(Ctx& c);
+hipError_t launch_record_paths(Ctx& c, const uint64_t* row_off, int2* path, uint64_t cap);
+hipError_t launch_path_columns(Ctx& c, int group);
 hipError_t launch_count_hits(Ctx& c, uint64_t* row_cnt);
 hipError_t launch_record_hits(Ctx& c, const uint64_t* row_off, int32_t* hit_j, int32_t* hit_img,
                               uint64_t cap);

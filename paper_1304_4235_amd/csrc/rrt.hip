@@ -129,13 +129,88 @@ int need_tree(Ctx& c)
     return RRT_OK;
 }
 
-int columns_impl(Ctx& c)
+void free_paths(Ctx& c)
 {
+    if (c.row_off) (void)hipFree(c.row_off);
+    if (c.path) (void)hipFree(c.path);
+    c.row_off = nullptr;
+    c.path = nullptr;
+    c.path_cap = 0;
+    c.path_hits = 0;
+    c.paths_valid = false;
+    c.paths_unfit = false;
+}
+
+// Count every ray's intersections, scan to row offsets, then record (tree index,
+// K/h^2) per intersection.  Leaves the paths invalid (and traversal in charge)
+// when they would exceed the budget.
+int record_paths(Ctx& c)
+{
+    const int64_t n_rows = c.n * (int64_t)c.n_ray;
     ev_begin(c);
-    HIP_OK(launch_columns(c));
-    if (c.timing) {
-        c.t_trace += ev_end(c);
-        c.n_trace += 1;
+    HIP_OK(dalloc(&c.row_off, (size_t)n_rows + 1));
+    HIP_OK(hipMemsetAsync(c.row_off + n_rows, 0, sizeof(uint64_t), c.stream));
+    HIP_OK(launch_count_hits(c, c.row_off));
+    HIP_OK(scan_exclusive_u64(c, c.row_off, c.row_off, n_rows + 1));
+    uint64_t total = 0;
+    HIP_OK(hipMemcpyAsync(&total, c.row_off + n_rows, sizeof total, hipMemcpyDeviceToHost,
+                          c.stream));
+    HIP_OK(hipStreamSynchronize(c.stream));
+    size_t budget = (size_t)c.prm.path_budget;
+    if (budget == 0) {
+        size_t fr = 0, tot = 0;
+        HIP_OK(hipMemGetInfo(&fr, &tot));
+        budget = fr / 2 + (c.path ? (size_t)c.path_cap * sizeof(int2) / 2 : 0);
+    }
+    if ((size_t)total * sizeof(int2) > budget) {
+        if (c.prm.record_paths == 1)
+            return fail(c, RRT_E_NOMEM, "recorded paths need %llu bytes, budget %zu",
+                        (unsigned long long)total * sizeof(int2), budget);
+        if (c.path) (void)hipFree(c.path);
+        c.path = nullptr;
+        c.path_cap = 0;
+        c.paths_unfit = true;
+        if (c.timing) c.t_record += ev_end(c);
+        return RRT_OK;
+    }
+    if (total > c.path_cap || !c.path) {
+        HIP_OK(dalloc(&c.path, (size_t)std::max<uint64_t>(total, 1)));
+        c.path_cap = std::max<uint64_t>(total, 1);
+    }
+    HIP_OK(launch_record_paths(c, c.row_off, c.path, total));
+    c.path_hits = (int64_t)total;
+    c.paths_valid = true;
+    if (c.timing) c.t_record += ev_end(c);
+    return RRT_OK;
+}
+
+// Columns for the current state.  Returns the intersections of this evaluation
+// through *hits when they are known on the host (recorded paths), else -1 (the
+// traversal counts them into red[1]).
+int columns_impl(Ctx& c, int64_t* hits)
+{
+    *hits = -1;
+    if (c.prm.record_paths != 0 && !c.paths_valid && !c.paths_unfit) {
+        if (int r = record_paths(c)) return r;
+    }
+    if (c.paths_valid) {
+        const int64_t n_rows = c.n * (int64_t)c.n_ray;
+        const double mean = (double)c.path_hits / (double)std::max<int64_t>(n_rows, 1);
+        const int group = mean >= 96 ? 64 : mean >= 40 ? 32 : mean >= 16 ? 16 : 8;
+        ev_begin(c);
+        HIP_OK(launch_path_columns(c, group));
+        if (c.timing) {
+            c.t_spmv += ev_end(c);
+            c.n_spmv += 1;
+        }
+        *hits = c.path_hits;
+    } else {
+        ev_begin(c);
+        HIP_OK(launch_columns(c));
+        if (c.timing) {
+            c.t_trace += ev_end(c);
+            c.n_trace += 1;
+        }
     }
     c.have_columns = true;
     return RRT_OK;
@@ -156,12 +231,15 @@ int rrt_create(rrt_ctx** out, const rrt_params* params, void* stream)
     *out = nullptr;
     if (!(params->l_ray >= 0.0) || !std::isfinite(params->l_ray) || !(params->box >= 0.0) ||
         !std::isfinite(params->box) || params->leaf_size < 0 || params->leaf_size > 8 ||
-        params->block_size < 0 || params->block_size > 1024 || (params->block_size % 64) != 0) {
+        params->block_size < 0 || params->block_size > 1024 || (params->block_size % 64) != 0 ||
+        params->record_paths < -1 || params->record_paths > 1 || params->path_budget < 0 ||
+        params->traversal < 0 || params->traversal > 1) {
         g_create_err = "rrt_create: invalid params (l_ray >= 0, box >= 0, leaf_size 0..8, "
-                       "block_size a multiple of 64 up to 1024)";
+                       "block_size a multiple of 64 up to 1024, record_paths -1..1, "
+                       "path_budget >= 0, traversal 0..1)";
         return RRT_E_ARG;
     }
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 2; ++i)
         if (params->reserved[i] != 0) {
             g_create_err = "rrt_create: reserved fields must be zero";
             return RRT_E_ARG;
@@ -202,6 +280,7 @@ void rrt_destroy(rrt_ctx* x)
     if (c.stream) (void)hipStreamSynchronize(c.stream);
     else (void)hipDeviceSynchronize();
     free_particles(c);
+    free_paths(c);
     void* bufs[] = {c.tables, c.red, c.dirs, c.ws, c.dsig_l2, c.ws_rel, c.hist, c.scan_tmp};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
@@ -238,6 +317,7 @@ int rrt_set_particles(rrt_ctx* x, int64_t n, const float* pos, const float* h, c
                               c.stream));
     c.have_particles = true;
     c.have_tree = c.have_columns = c.have_gamma = false;
+    free_paths(c);
     if (c.have_rays) return alloc_columns(c);
     return RRT_OK;
 }
@@ -261,6 +341,7 @@ int rrt_set_rays(rrt_ctx* x, int32_t n_ray, const double* dirs)
     c.geom.n_ray = n_ray;
     c.have_rays = true;
     c.have_columns = c.have_gamma = false;
+    free_paths(c);
     if (c.have_particles && (changed || !c.N_s)) return alloc_columns(c);
     return RRT_OK;
 }
@@ -411,6 +492,8 @@ int rrt_build_tree(rrt_ctx* x)
     g.n_nodes = nn;
     HIP_OK(launch_init_state(c, c.x_init_given));
     if (c.timing) c.t_build += ev_end(c);
+    c.paths_valid = false;       // new geometry: the recorded paths no longer apply
+    c.paths_unfit = false;
     c.have_tree = true;
     c.have_columns = c.have_gamma = false;
     return RRT_OK;
@@ -421,14 +504,18 @@ int rrt_compute_columns(rrt_ctx* x, double* N_out, int64_t* n_hits_out)
     if (!x) return RRT_E_ARG;
     Ctx& c = x->c;
     if (int r = need_tree(c)) return r;
-    if (n_hits_out) HIP_OK(hipMemsetAsync(c.red + 1, 0, sizeof(unsigned long long), c.stream));
-    if (int r = columns_impl(c)) return r;
+    HIP_OK(hipMemsetAsync(c.red + 1, 0, sizeof(unsigned long long), c.stream));
+    int64_t hits = -1;
+    if (int r = columns_impl(c, &hits)) return r;
     if (N_out) HIP_OK(launch_to_input_order_d(c, c.N_s, N_out, c.n_ray));
     if (n_hits_out) {
-        HIP_OK(hipMemcpyAsync(c.red_host + 1, c.red + 1, sizeof(unsigned long long),
-                              hipMemcpyDeviceToHost, c.stream));
-        HIP_OK(hipStreamSynchronize(c.stream));
-        *n_hits_out = (int64_t)c.red_host[1];
+        if (hits < 0) {
+            HIP_OK(hipMemcpyAsync(c.red_host + 1, c.red + 1, sizeof(unsigned long long),
+                                  hipMemcpyDeviceToHost, c.stream));
+            HIP_OK(hipStreamSynchronize(c.stream));
+            hits = (int64_t)c.red_host[1];
+        }
+        *n_hits_out = hits;
     }
     return RRT_OK;
 }
@@ -479,7 +566,8 @@ int rrt_iterate_equilibrium(rrt_ctx* x, int32_t max_iter, double tol, double* x_
     double mdx = INFINITY;
     for (it = 0; it < max_iter;) {
         HIP_OK(hipMemsetAsync(c.red, 0, 2 * sizeof(unsigned long long), c.stream));
-        if (int r = columns_impl(c)) return r;
+        int64_t hits = -1;
+        if (int r = columns_impl(c, &hits)) return r;
         ev_begin(c);
         HIP_OK(launch_gamma(c, true));
         HIP_OK(hipMemcpyAsync(c.red_host, c.red, 2 * sizeof(unsigned long long),
@@ -488,7 +576,7 @@ int rrt_iterate_equilibrium(rrt_ctx* x, int32_t max_iter, double tol, double* x_
         HIP_OK(hipStreamSynchronize(c.stream));
         ++it;
         std::memcpy(&mdx, &c.red_host[0], sizeof mdx);
-        c.last_hits = (int64_t)c.red_host[1];
+        c.last_hits = hits >= 0 ? hits : (int64_t)c.red_host[1];
         c.total_hits += c.last_hits;
         if (mdx < tol) break;
     }
@@ -631,14 +719,18 @@ int rrt_enable_timing(rrt_ctx* x, int32_t on)
     return RRT_OK;
 }
 
-int rrt_get_timing(rrt_ctx* x, double* out4)
+int rrt_get_timing(rrt_ctx* x, double* out8)
 {
-    if (!x || !out4) return RRT_E_ARG;
+    if (!x || !out8) return RRT_E_ARG;
     Ctx& c = x->c;
-    out4[0] = c.t_trace;
-    out4[1] = c.t_rate;
-    out4[2] = c.t_build;
-    out4[3] = c.n_trace;
+    out8[0] = c.t_trace;
+    out8[1] = c.t_rate;
+    out8[2] = c.t_build;
+    out8[3] = c.n_trace;
+    out8[4] = c.t_record;
+    out8[5] = c.t_spmv;
+    out8[6] = c.n_spmv;
+    out8[7] = c.paths_valid ? (double)c.path_hits : -1.0;
     return RRT_OK;
 }
 
@@ -647,6 +739,7 @@ int rrt_reset_timing(rrt_ctx* x)
     if (!x) return RRT_E_ARG;
     Ctx& c = x->c;
     c.t_trace = c.t_rate = c.t_build = c.n_trace = 0.0;
+    c.t_record = c.t_spmv = c.n_spmv = 0.0;
     c.total_hits = 0;
     return RRT_OK;
 }

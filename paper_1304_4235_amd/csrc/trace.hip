@@ -18,6 +18,7 @@
 // The three one-dimensional factors come from cubic tables staged in LDS.
 #include "internal.h"
 
+#include <climits>
 #include <cmath>
 
 namespace rrt {
@@ -94,12 +95,15 @@ __device__ __forceinline__ float erf_t_odd(const float4* __restrict__ tb, float 
     return z < 0.f ? -v : v;
 }
 
-enum { kModeColumn = 0, kModeCount = 1, kModeRecord = 2 };
+// column: accumulate N; count: hits per ray; record: hit lists for inspection;
+// path: per hit (tree index, K/h^2) for the streaming product
+enum { kModeColumn = 0, kModeCount = 1, kModeRecord = 2, kModePath = 3 };
 
 struct RayOut {
     double* N;              // [n_ray][n] columns (column / record modes)
     uint64_t* row_cnt;      // [n_ray * n] hits per ray (count mode)
-    const uint64_t* row_off;// [n_ray * n] write offsets (record mode)
+    const uint64_t* row_off;// [n_ray * n] write offsets (record / path modes)
+    int2* path;             // path mode: (tree index, factor bits) per hit
     int32_t* hit_j;         // record mode: input index of each hit
     int32_t* hit_img;       // record mode: image code of each hit
     uint64_t hit_cap;       // record mode: capacity of hit_j / hit_img
@@ -118,7 +122,8 @@ k_trace(const Node* __restrict__ nodes, const float4* __restrict__ p4,
         const KernelTables* __restrict__ tabs, TraceGeom g, RayOut out)
 {
     __shared__ float4 tab[3 * kTabIntervals];
-    if (MODE != kModeCount) {
+    constexpr bool kTerms = MODE == kModeColumn || MODE == kModeRecord || MODE == kModePath;
+    if (kTerms) {
         const float4* src = reinterpret_cast<const float4*>(tabs);
         for (int i = threadIdx.x; i < 3 * kTabIntervals; i += blockDim.x) tab[i] = src[i];
         __syncthreads();
@@ -155,7 +160,7 @@ k_trace(const Node* __restrict__ nodes, const float4* __restrict__ p4,
             inv[a] = 1.0f / ua;
         }
         double acc = 0.0;
-        uint64_t w = (MODE == kModeRecord) ? out.row_off[gid] : 0;
+        uint64_t w = (MODE == kModeRecord || MODE == kModePath) ? out.row_off[gid] : 0;
 
         for (int sx = lo[0]; sx <= hi[0]; ++sx)
         for (int sy = lo[1]; sy <= hi[1]; ++sy)
@@ -214,7 +219,171 @@ k_trace(const Node* __restrict__ nodes, const float4* __restrict__ p4,
                     double px = d0 - sp * u[0], py = d1 - sp * u[1], pz = d2 - sp * u[2];
                     double b2 = px * px + py * py + pz * pz;
                     double l2 = h2 - b2;
-                    if (!(l2 > 0.0)) continue;
+                    // factor K/h^2 of this intersection (0 for a tangent touch)
+                    float gk = 0.0f;
+                    if (l2 > 0.0) {
+                        const float ih2 = 1.0f / (float)h2;
+                        const float wq = fminf((float)l2 * ih2, 1.0f);
+                        const double Lr = L - sp;
+                        float K;
+                        if (sp >= 0.0 && sp * sp >= l2 && Lr >= 0.0 && Lr * Lr >= l2) {
+                            K = sqrtf(wq) * tab_eval(t_full, wq);
+                        } else {
+                            const float ih = 1.0f / Q.w;
+                            const float lh = sqrtf(wq);
+                            const float z1 = fmaxf((float)(-sp) * ih, -lh);
+                            const float z2 = fminf((float)Lr * ih, lh);
+                            const float q2 = fminf((float)b2 * ih2, 1.0f);
+                            K = z2 > z1 ? tab_eval(t_gauss, q2) *
+                                              (erf_t_odd(t_erf, z2) - erf_t_odd(t_erf, z1))
+                                        : 0.0f;
+                        }
+                        gk = ih2 * K;
+                    }
+                    if (MODE == kModePath) {
+                        if (w < out.hit_cap) out.path[w] = make_int2(j, __float_as_int(gk));
+                        ++w;
+                    } else {
+                        acc += (double)(mux[j] * gk);
+                    }
+                }
+                node = max(skip, node + 1);
+            }
+        }
+        if (MODE == kModeColumn || MODE == kModeRecord) out.N[(int64_t)k * g.n + ps] = acc;
+        if (MODE == kModeCount) out.row_cnt[gid] = cnt;
+    }
+    // one atomic per wave for the total intersection count
+    uint64_t c64 = cnt;
+    for (int off = 32; off > 0; off >>= 1) c64 += __shfl_xor(c64, off, 64);
+    if ((threadIdx.x & 63) == 0 && c64) atomicAdd(out.hits_total, (unsigned long long)c64);
+}
+// Wave-cooperative variant: the 64 rays of a wave (same direction, sources
+// adjacent in tree order) walk ONE node sequence, the depth-first union of
+// their individual walks.  Node and leaf-particle loads are wave-uniform
+// (scalar loads); each lane tests its own ray, and a ballot decides whether the
+// wave descends or skips.  A lane only tests the particles of leaves its own
+// ray's box test accepted, and sees them in depth-first order, so every lane's
+// hits, counts and recorded paths equal those of its own walk.
+template <int MODE>
+__global__ void __launch_bounds__(256)
+k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
+             const float* __restrict__ mux, const double* __restrict__ dirs,
+             const KernelTables* __restrict__ tabs, TraceGeom g, RayOut out)
+{
+    __shared__ float4 tab[3 * kTabIntervals];
+    constexpr bool kTerms = MODE == kModeColumn || MODE == kModeRecord || MODE == kModePath;
+    if (kTerms) {
+        const float4* src = reinterpret_cast<const float4*>(tabs);
+        for (int i = threadIdx.x; i < 3 * kTabIntervals; i += blockDim.x) tab[i] = src[i];
+        __syncthreads();
+    }
+    const float4* t_full = tab;
+    const float4* t_gauss = tab + kTabIntervals;
+    const float4* t_erf = tab + 2 * kTabIntervals;
+
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int64_t waves_per_dir = (g.n + 63) / 64;
+    const int k = (int)(wave / waves_per_dir);
+    if (k >= g.n_ray) return;                                // whole wave
+    const int ps = (int)((wave - (int64_t)k * waves_per_dir) * 64 + lane);
+    const bool active = ps < g.n;
+    const float4 P = p4[active ? ps : g.n - 1];
+    const double rp[3] = {(double)P.x, (double)P.y, (double)P.z};
+    const double u[3] = {dirs[3 * k], dirs[3 * k + 1], dirs[3 * k + 2]};
+    const double L = g.L, B = g.box;
+    const float Lf = (float)L;
+    const int64_t gid = (int64_t)k * g.n + ps;
+
+    int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    int ulo[3] = {0, 0, 0}, uhi[3] = {0, 0, 0};
+    if (B > 0.0) {
+        for (int a = 0; a < 3; ++a) {
+            double e = rp[a] + L * u[a];
+            double smin = rp[a] < e ? rp[a] : e, smax = rp[a] < e ? e : rp[a];
+            lo[a] = (int)ceil((smin - g.hmax - g.phi[a]) / B - 1e-6);
+            hi[a] = (int)floor((smax + g.hmax - g.plo[a]) / B + 1e-6);
+            int l = active ? lo[a] : INT_MAX, h = active ? hi[a] : INT_MIN;
+            for (int off = 32; off > 0; off >>= 1) {
+                l = min(l, __shfl_xor(l, off, 64));
+                h = max(h, __shfl_xor(h, off, 64));
+            }
+            ulo[a] = l;
+            uhi[a] = h;
+        }
+    }
+    float inv[3];
+    for (int a = 0; a < 3; ++a) {
+        float ua = (float)u[a];
+        if (fabsf(ua) < 1e-20f) ua = 1e-20f;
+        inv[a] = 1.0f / ua;
+    }
+    double acc = 0.0;
+    uint32_t cnt = 0;
+    uint64_t w = ((MODE == kModeRecord || MODE == kModePath) && active) ? out.row_off[gid] : 0;
+
+    for (int sx = ulo[0]; sx <= uhi[0]; ++sx)
+    for (int sy = ulo[1]; sy <= uhi[1]; ++sy)
+    for (int sz = ulo[2]; sz <= uhi[2]; ++sz) {
+        const bool mine = active && sx >= lo[0] && sx <= hi[0] && sy >= lo[1] && sy <= hi[1] &&
+                          sz >= lo[2] && sz <= hi[2];
+        if (__ballot(mine) == 0) continue;
+        double sh[3] = {(double)sx * B, (double)sy * B, (double)sz * B};
+        if (!(B > 0.0)) sh[0] = sh[1] = sh[2] = 0.0;
+        float oai[3], obi[3];
+        for (int a = 0; a < 3; ++a) {
+            double o = rp[a] - sh[a];
+            oai[a] = (float)(o + (double)g.pad) * inv[a];
+            obi[a] = (float)(o - (double)g.pad) * inv[a];
+        }
+        int node = 0;
+        while (node < g.n_nodes) {
+            const Node nd = nodes[node];
+            const int skip = __float_as_int(nd.a.w);
+            const int leafw = __float_as_int(nd.b.w);
+            float tx0 = fmaf(nd.a.x, inv[0], -oai[0]), tx1 = fmaf(nd.b.x, inv[0], -obi[0]);
+            float ty0 = fmaf(nd.a.y, inv[1], -oai[1]), ty1 = fmaf(nd.b.y, inv[1], -obi[1]);
+            float tz0 = fmaf(nd.a.z, inv[2], -oai[2]), tz1 = fmaf(nd.b.z, inv[2], -obi[2]);
+            float tmin = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)),
+                               fmaxf(fminf(tz0, tz1), 0.0f));
+            float tmax = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)),
+                               fminf(fmaxf(tz0, tz1), Lf));
+            const bool hit = mine && tmin <= tmax;
+            if (__ballot(hit) == 0) { node = max(skip, node + 1); continue; }
+            if (leafw < 0) { node = node + 1; continue; }
+            const int f = leafw >> 3;
+            const int c = (f + (leafw & 7) + 1 <= g.n) ? (leafw & 7) + 1 : 0;
+            for (int q = 0; q < c; ++q) {
+                const int j = f + q;
+                const float4 Q = p4[j];
+                if (!hit) continue;
+                double d0 = ((double)Q.x - rp[0]) + sh[0];
+                double d1 = ((double)Q.y - rp[1]) + sh[1];
+                double d2 = ((double)Q.z - rp[2]) + sh[2];
+                double sp = d0 * u[0] + d1 * u[1] + d2 * u[2];
+                double tt = sp < 0.0 ? 0.0 : (sp > L ? L : sp);
+                double c0 = d0 - tt * u[0];
+                double c1 = d1 - tt * u[1];
+                double c2 = d2 - tt * u[2];
+                double D2 = c0 * c0 + c1 * c1 + c2 * c2;
+                double hj = (double)Q.w;
+                double h2 = hj * hj;
+                if (!(D2 < h2)) continue;
+                ++cnt;
+                if (MODE == kModeCount) continue;
+                if (MODE == kModeRecord) {
+                    if (w < out.hit_cap) {
+                        out.hit_j[w] = out.perm[j];
+                        out.hit_img[w] = (sx + 8) | ((sy + 8) << 4) | ((sz + 8) << 8);
+                    }
+                    ++w;
+                }
+                double px = d0 - sp * u[0], py = d1 - sp * u[1], pz = d2 - sp * u[2];
+                double b2 = px * px + py * py + pz * pz;
+                double l2 = h2 - b2;
+                float gk = 0.0f;
+                if (l2 > 0.0) {
                     const float ih2 = 1.0f / (float)h2;
                     const float wq = fminf((float)l2 * ih2, 1.0f);
                     const double Lr = L - sp;
@@ -231,18 +400,25 @@ k_trace(const Node* __restrict__ nodes, const float4* __restrict__ p4,
                                           (erf_t_odd(t_erf, z2) - erf_t_odd(t_erf, z1))
                                     : 0.0f;
                     }
-                    acc += (double)(mux[j] * ih2 * K);
+                    gk = ih2 * K;
                 }
-                node = max(skip, node + 1);
+                if (MODE == kModePath) {
+                    if (w < out.hit_cap) out.path[w] = make_int2(j, __float_as_int(gk));
+                    ++w;
+                } else {
+                    acc += (double)(mux[j] * gk);
+                }
             }
+            node = max(skip, node + 1);
         }
-        if (MODE != kModeCount) out.N[(int64_t)k * g.n + ps] = acc;
+    }
+    if (active) {
+        if (MODE == kModeColumn || MODE == kModeRecord) out.N[gid] = acc;
         if (MODE == kModeCount) out.row_cnt[gid] = cnt;
     }
-    // one atomic per wave for the total intersection count
     uint64_t c64 = cnt;
     for (int off = 32; off > 0; off >>= 1) c64 += __shfl_xor(c64, off, 64);
-    if ((threadIdx.x & 63) == 0 && c64) atomicAdd(out.hits_total, (unsigned long long)c64);
+    if (lane == 0 && c64) atomicAdd(out.hits_total, (unsigned long long)c64);
 }
 #pragma clang fp contract(on)
 
@@ -259,21 +435,70 @@ void fill_kernel_tables(KernelTables* host)
     fit_cubics(host->erf_t, [&](double z) { return std::erf(t * z); });
 }
 
-static hipError_t launch_mode(Ctx& c, int mode, RayOut o)
+template <int MODE>
+static void launch_one(Ctx& c, RayOut o)
 {
     int bs = c.prm.block_size > 0 ? c.prm.block_size : 256;
-    int64_t n_rays = c.n * (int64_t)c.n_ray;
-    unsigned nb = (unsigned)((n_rays + bs - 1) / bs);
-    if (mode == kModeColumn)
-        hipLaunchKernelGGL(k_trace<kModeColumn>, dim3(nb), dim3(bs), 0, c.stream, c.nodes, c.p4,
+    if (c.prm.traversal == 1) {
+        const int64_t n_rays = c.n * (int64_t)c.n_ray;
+        const unsigned nb = (unsigned)((n_rays + bs - 1) / bs);
+        hipLaunchKernelGGL(k_trace<MODE>, dim3(nb), dim3(bs), 0, c.stream, c.nodes, c.p4, c.mux_s,
+                           c.dirs, c.tables, c.geom, o);
+    } else {
+        // one wave per 64 sources of one direction
+        const int64_t waves = ((c.n + 63) / 64) * (int64_t)c.n_ray;
+        const unsigned nb = (unsigned)((waves * 64 + bs - 1) / bs);
+        hipLaunchKernelGGL(k_trace_wave<MODE>, dim3(nb), dim3(bs), 0, c.stream, c.nodes, c.p4,
                            c.mux_s, c.dirs, c.tables, c.geom, o);
-    else if (mode == kModeCount)
-        hipLaunchKernelGGL(k_trace<kModeCount>, dim3(nb), dim3(bs), 0, c.stream, c.nodes, c.p4,
-                           c.mux_s, c.dirs, c.tables, c.geom, o);
-    else
-        hipLaunchKernelGGL(k_trace<kModeRecord>, dim3(nb), dim3(bs), 0, c.stream, c.nodes, c.p4,
-                           c.mux_s, c.dirs, c.tables, c.geom, o);
+    }
+}
+
+static hipError_t launch_mode(Ctx& c, int mode, RayOut o)
+{
+    if (mode == kModeColumn) launch_one<kModeColumn>(c, o);
+    else if (mode == kModeCount) launch_one<kModeCount>(c, o);
+    else if (mode == kModeRecord) launch_one<kModeRecord>(c, o);
+    else launch_one<kModePath>(c, o);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// columns from recorded paths: N_row = sum over the row's hits of mux_j * factor.
+// G lanes share a row; they stride through it (coalesced 8-byte loads) and
+// reduce their partial sums in FP64.
+// ---------------------------------------------------------------------------
+template <int G>
+__global__ void __launch_bounds__(256)
+k_path_columns(const uint64_t* __restrict__ row_off, const int2* __restrict__ path,
+               const float* __restrict__ mux, int64_t n_rows, double* __restrict__ N)
+{
+    const int64_t row = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G;
+    const int lane = threadIdx.x & (G - 1);
+    double acc = 0.0;
+    if (row < n_rows) {
+        const uint64_t a = row_off[row], b = row_off[row + 1];
+        const long long* p = reinterpret_cast<const long long*>(path);
+        uint64_t e = a + lane;
+        // four independent streaming loads in flight per lane before any is used
+        for (; e + 3 * G < b; e += 4 * G) {
+            const long long v0 = __builtin_nontemporal_load(p + e);
+            const long long v1 = __builtin_nontemporal_load(p + e + G);
+            const long long v2 = __builtin_nontemporal_load(p + e + 2 * G);
+            const long long v3 = __builtin_nontemporal_load(p + e + 3 * G);
+            const float m0 = mux[(int)v0], m1 = mux[(int)v1];
+            const float m2 = mux[(int)v2], m3 = mux[(int)v3];
+            acc += (double)(m0 * __int_as_float((int)(v0 >> 32)));
+            acc += (double)(m1 * __int_as_float((int)(v1 >> 32)));
+            acc += (double)(m2 * __int_as_float((int)(v2 >> 32)));
+            acc += (double)(m3 * __int_as_float((int)(v3 >> 32)));
+        }
+        for (; e < b; e += G) {
+            const long long v = __builtin_nontemporal_load(p + e);
+            acc += (double)(mux[(int)v] * __int_as_float((int)(v >> 32)));
+        }
+    }
+    for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
+    if (row < n_rows && lane == 0) N[row] = acc;
 }
 
 hipError_t launch_columns(Ctx& c)
@@ -306,6 +531,37 @@ hipError_t launch_record_hits(Ctx& c, const uint64_t* row_off, int32_t* hit_j, i
     o.perm = c.perm;
     o.hits_total = c.red + 1;
     return launch_mode(c, kModeRecord, o);
+}
+
+hipError_t launch_record_paths(Ctx& c, const uint64_t* row_off, int2* path, uint64_t cap)
+{
+    RayOut o{};
+    o.hit_cap = cap;
+    o.row_off = row_off;
+    o.path = path;
+    o.perm = c.perm;
+    o.hits_total = c.red + 1;
+    return launch_mode(c, kModePath, o);
+}
+
+hipError_t launch_path_columns(Ctx& c, int group)
+{
+    const int64_t n_rows = c.n * (int64_t)c.n_ray;
+    const int bs = 256;
+    const unsigned nb = (unsigned)((n_rows * group + bs - 1) / bs);
+    if (group == 64)
+        hipLaunchKernelGGL(k_path_columns<64>, dim3(nb), dim3(bs), 0, c.stream, c.row_off, c.path,
+                           c.mux_s, n_rows, c.N_s);
+    else if (group == 32)
+        hipLaunchKernelGGL(k_path_columns<32>, dim3(nb), dim3(bs), 0, c.stream, c.row_off, c.path,
+                           c.mux_s, n_rows, c.N_s);
+    else if (group == 16)
+        hipLaunchKernelGGL(k_path_columns<16>, dim3(nb), dim3(bs), 0, c.stream, c.row_off, c.path,
+                           c.mux_s, n_rows, c.N_s);
+    else
+        hipLaunchKernelGGL(k_path_columns<8>, dim3(nb), dim3(bs), 0, c.stream, c.row_off, c.path,
+                           c.mux_s, n_rows, c.N_s);
+    return hipGetLastError();
 }
 
 }  // namespace rrt

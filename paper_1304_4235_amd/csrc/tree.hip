@@ -113,8 +113,7 @@ __device__ T block_exclusive_scan(T v, T* sh, T* total)
 }
 
 template <typename T>
-__global__ void k_scan_tiles(const T* __restrict__ in, T* __restrict__ out, int64_t m,
-                             T* __restrict__ sums)
+__global__ void k_scan_tiles(const T* in, T* out, int64_t m, T* __restrict__ sums)
 {
     __shared__ T sh[kBlock];
     int64_t base = blockIdx.x * (int64_t)kScanTile + threadIdx.x * kScanItems;

@@ -29,8 +29,9 @@ class RRTError(RuntimeError):
 
 
 class Params(C.Structure):
-    _fields_ = [("l_ray", C.c_double), ("box", C.c_double), ("leaf_size", C.c_int32),
-                ("block_size", C.c_int32), ("reserved", C.c_int32 * 4)]
+    _fields_ = [("l_ray", C.c_double), ("box", C.c_double), ("path_budget", C.c_int64),
+                ("leaf_size", C.c_int32), ("block_size", C.c_int32), ("record_paths", C.c_int32),
+                ("traversal", C.c_int32), ("reserved", C.c_int32 * 2)]
 
 
 # every symbol include/rrt.h declares, with its ctypes signature
@@ -100,6 +101,7 @@ class Solver:
     """One reverse-ray-tracing problem on one GPU (a context of librrt)."""
 
     def __init__(self, l_ray: float, box: float = 0.0, leaf_size: int = 0, block_size: int = 0,
+                 record_paths: int = -1, path_budget: int = 0, traversal: int = 0,
                  device=None):
         dev = torch.device("cuda" if device is None else device)
         if dev.type != "cuda":
@@ -109,7 +111,8 @@ class Solver:
         self.device = dev
         torch.cuda.set_device(self.device)
         self.stream = torch.cuda.current_stream(self.device)
-        p = Params(float(l_ray), float(box), int(leaf_size), int(block_size), (C.c_int32 * 4)())
+        p = Params(float(l_ray), float(box), int(path_budget), int(leaf_size), int(block_size),
+                   int(record_paths), int(traversal), (C.c_int32 * 2)())
         h = C.c_void_p()
         rc = _lib.rrt_create(C.byref(h), C.byref(p), C.c_void_p(self.stream.cuda_stream))
         if rc != RRT_OK:
@@ -260,18 +263,22 @@ class Solver:
         self._check(_lib.rrt_reset_timing(self._h), "rrt_reset_timing")
 
     def timing(self) -> dict:
-        out = np.zeros(4)
+        out = np.zeros(8)
         self._check(_lib.rrt_get_timing(self._h, out.ctypes.data), "rrt_get_timing")
         cnt = np.zeros(2, np.int64)
         self._check(_lib.rrt_get_counters(self._h, cnt.ctypes.data), "rrt_get_counters")
         return dict(trace_ms=out[0], rate_ms=out[1], build_ms=out[2], n_trace=int(out[3]),
-                    last_hits=int(cnt[0]), total_hits=int(cnt[1]))
+                    record_ms=out[4], path_ms=out[5], n_path=int(out[6]),
+                    path_hits=int(out[7]), last_hits=int(cnt[0]), total_hits=int(cnt[1]))
 
     # -- convenience ------------------------------------------------------
     @classmethod
-    def from_workload(cls, wl, leaf_size: int = 0, block_size: int = 0, device=None,
-                      x_init=None, build: bool = True) -> "Solver":
-        s = cls(wl.l_ray, wl.box, leaf_size=leaf_size, block_size=block_size, device=device)
+    def from_workload(cls, wl, leaf_size: int = 0, block_size: int = 0, record_paths: int = -1,
+                      path_budget: int = 0, traversal: int = 0, device=None, x_init=None,
+                      build: bool = True) -> "Solver":
+        s = cls(wl.l_ray, wl.box, leaf_size=leaf_size, block_size=block_size,
+                record_paths=record_paths, path_budget=path_budget, traversal=traversal,
+                device=device)
         s.set_particles(wl.pos, wl.h, wl.mu, wl.n_H, wl.T, x_init=x_init)
         s.set_rays(wl.dirs)
         s.set_spectrum(wl.sigma, wl.w)

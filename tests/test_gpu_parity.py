@@ -122,9 +122,10 @@ def test_lattice_hit_sets_exact(lattice):
     assert off[-1] > 300 * wl.n * wl.n_ray      # ~320 hits per ray
 
 
-def test_lattice_columns_and_step(lattice):
+@pytest.mark.parametrize("paths", [-1, 0])
+def test_lattice_columns_and_step(lattice, paths):
     wl = lattice
-    s = _solver(wl)
+    s = _solver(wl, record_paths=paths)
     rng = np.random.default_rng(0)
     x = oracle.x_thin(wl) * rng.uniform(1, 50, wl.n)
     s.set_state(torch.tensor(x))
@@ -171,9 +172,10 @@ def test_lattice_end_to_end(lattice, lattice_oracle):
 # ---------------------------------------------------------------------------
 # isolated halos with a 128-bin power-law spectrum
 # ---------------------------------------------------------------------------
-def test_small_halo_step_all_sources():
+@pytest.mark.parametrize("paths", [-1, 0])
+def test_small_halo_step_all_sources(paths):
     wl = W.isothermal_halo(n=8192, seed=11)
-    s = _solver(wl)
+    s = _solver(wl, record_paths=paths)
     x = oracle.x_thin(wl) * np.linspace(1.0, 1e3, wl.n)
     x = np.minimum(x, 0.99)
     s.set_state(torch.tensor(x))
@@ -305,3 +307,63 @@ def test_bad_input_is_rejected():
     s = Solver(10.0)
     with pytest.raises(RRTError, match="RRT_E_STATE"):
         s.compute_columns()
+
+
+# ---------------------------------------------------------------------------
+# recorded paths vs traversal
+# ---------------------------------------------------------------------------
+def test_recorded_paths_match_traversal():
+    """Recorded paths hold the same intersections and factors as a traversal:
+    the columns agree to summation-order rounding, and the counts exactly."""
+    wl = W.isothermal_halo(n=16384, seed=21)
+    a = _solver(wl, record_paths=1)
+    b = _solver(wl, record_paths=0)
+    x = np.minimum(oracle.x_thin(wl) * np.geomspace(1, 1e4, wl.n), 0.999)
+    for s in (a, b):
+        s.set_state(torch.tensor(x))
+    Na, ha = a.compute_columns()
+    Nb, hb = b.compute_columns()
+    assert ha == hb and ha > 0
+    assert a.timing()["path_hits"] == ha
+    np.testing.assert_allclose(Na.cpu().numpy(), Nb.cpu().numpy(), rtol=1e-12, atol=0)
+    # a second state reuses the recorded paths
+    x2 = np.minimum(x * 3, 0.999)
+    a.set_state(torch.tensor(x2))
+    b.set_state(torch.tensor(x2))
+    np.testing.assert_allclose(a.compute_columns()[0].cpu().numpy(),
+                               b.compute_columns()[0].cpu().numpy(), rtol=1e-12, atol=0)
+
+
+def test_path_budget_fallback_and_error():
+    from paper_1304_4235_amd import RRTError
+    wl = W.isothermal_halo(n=4096, seed=22)
+    small = _solver(wl, record_paths=-1, path_budget=1024)
+    full = _solver(wl, record_paths=1)
+    r1 = small.iterate(6, 0.0)
+    r2 = full.iterate(6, 0.0)
+    assert small.timing()["path_hits"] == -1          # fell back to traversal
+    np.testing.assert_allclose(r1["x"].cpu().numpy(), r2["x"].cpu().numpy(), rtol=1e-10)
+    need = _solver(wl, record_paths=1, path_budget=1024)
+    with pytest.raises(RRTError, match="RRT_E_NOMEM"):
+        need.compute_columns()
+
+
+@pytest.mark.parametrize("which", ["lattice", "halo"])
+def test_wave_and_lane_traversals_agree(which):
+    """The wave-cooperative walk gives every lane exactly its own walk's hits in
+    the same order, so hit lists match and columns match bit for bit."""
+    wl = W.make_config(0) if which == "lattice" else W.isothermal_halo(n=20000, seed=31)
+    a = _solver(wl, traversal=0, record_paths=0)
+    b = _solver(wl, traversal=1, record_paths=0)
+    x = np.minimum(oracle.x_thin(wl) * np.geomspace(1, 1e3, wl.n), 0.999)
+    for s in (a, b):
+        s.set_state(torch.tensor(x))
+    Na, ha = a.compute_columns()
+    Nb, hb = b.compute_columns()
+    assert ha == hb
+    np.testing.assert_array_equal(Na.cpu().numpy(), Nb.cpu().numpy())
+    oa, ja, ia = a.hits()
+    ob, jb, ib = b.hits()
+    np.testing.assert_array_equal(oa, ob)
+    np.testing.assert_array_equal(ja, jb)
+    np.testing.assert_array_equal(ia, ib)
