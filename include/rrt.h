@@ -66,7 +66,7 @@ typedef struct {
     double box;            /* periodic box side in kpc; 0 = isolated (no images)    */
     int64_t path_budget;   /* bytes the recorded ray paths may take; 0 = half of the
                               free device memory at the time of recording           */
-    int32_t leaf_size;     /* max particles per tree leaf, 1..8 (0 = default 4)     */
+    int32_t leaf_size;     /* max particles per tree leaf, 1..8 (0 = default 8)     */
     int32_t block_size;    /* threads per block of the traversal (0 = default 256)  */
     int32_t record_paths;  /* -1 = record when within path_budget (default),
                               0 = traverse every iteration, 1 = require recording   */
@@ -157,6 +157,33 @@ int rrt_update_equilibrium(rrt_ctx* ctx, double* x_out, double* max_dx_out);
  * (8 bytes) for the convergence test. */
 int rrt_iterate_equilibrium(rrt_ctx* ctx, int32_t max_iter, double tol, double* x_out,
                             int32_t* iters_done, double* max_dx_out);
+
+/* ---- reverse mode ------------------------------------------------------
+ * The differentiated map is K unrolled order-independent iterations from the
+ * optically thin state: x^0 = x_-(Gamma_thin), then K times columns -> Gamma ->
+ * x.  Parameters: the bin weights w (rrt_set_spectrum) and the particle
+ * densities n_H; a particle's hydrogen content scales with its density at
+ * fixed smoothing length, mu_j = mu_j(input) * n_H,j / n_H,j(input).  Outputs:
+ * ln Gamma of the last iteration and x^K. */
+
+/* New densities without a new tree (geometry and recorded paths are kept):
+ * n_H device float[n] in input order, > 0. */
+int rrt_set_density(rrt_ctx* ctx, const float* n_H);
+
+/* Exactly K iterations from the optically thin state, keeping every iterate
+ * for rrt_backward (K+1 device vectors of n doubles).  Outputs (device, input
+ * order, nullable): lnG_out double[n] = ln Gamma^K, x_out double[n] = x^K. */
+int rrt_forward(rrt_ctx* ctx, int32_t K, double* lnG_out, double* x_out);
+
+/* Gradients of a scalar loss through the last rrt_forward, given its
+ * derivatives with respect to the outputs (device, input order, nullable =
+ * zero): dL_dlnG double[n], dL_dx double[n].  Writes dL_dw (host double
+ * [n_bins], the spectrum as given; every w_b must be > 0) and dL_dnH (device
+ * double[n], input order).  The transposed column product uses the recorded
+ * paths, or re-traverses the tree when they are not recorded; it accumulates
+ * with FP64 atomics, so dL_dnH can differ between runs in the last bits. */
+int rrt_backward(rrt_ctx* ctx, const double* dL_dlnG, const double* dL_dx, double* dL_dw,
+                 double* dL_dnH);
 
 /* Replace the state: x device double[n] in input order (checkpoint / resume,
  * or a given iterate); NULL resets to x_thin. */

@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "rrt.h"
 
@@ -14,7 +15,7 @@ namespace rrt {
 constexpr int kTabIntervals = 256;        // cubic pieces per kernel table
 constexpr int kMaxRays = 3072;
 constexpr int kMaxBins = 4096;
-constexpr int kDefaultLeaf = 4;
+constexpr int kDefaultLeaf = 8;
 
 // One node of the depth-first tree layout: two 16-byte words.
 //   a = (lo.x, lo.y, lo.z, skip as int bits)
@@ -71,7 +72,9 @@ struct Ctx {
 
     // tree-order particle data (device)
     float4* p4 = nullptr;        // x, y, z, h
-    float* mu_s = nullptr;
+    double* mu_s = nullptr;      // hydrogen content in use (input mu scaled by n_H / n_H input)
+    float* mu0_s = nullptr;      // input mu, tree order
+    float* nH0_s = nullptr;      // input n_H, tree order
     float* nH_s = nullptr;
     double* alpha_s = nullptr;   // case A recombination
     double* gcoll_s = nullptr;   // collisional ionisation
@@ -117,7 +120,25 @@ struct Ctx {
     double* ws = nullptr;        // w_b sigma_b
     float* dsig_l2 = nullptr;    // (sigma_b - sigma_min) * log2(e)
     float* ws_rel = nullptr;     // w_b sigma_b / max_b(w_b sigma_b)
-    double sigma_min = 0.0, ln_ws_max = 0.0, gamma_thin = 0.0;
+    float* srat = nullptr;       // sigma_b / sigma_min
+    double sigma_min = 0.0, ln_ws_max = 0.0, gamma_thin = 0.0, ws_max = 0.0;
+    std::vector<double> sigma_host;   // the spectrum as given
+    bool all_bins_weighted = false;   // every w_b > 0 (no bin dropped)
+
+    // reverse mode: iterates of the last rrt_forward and adjoint work buffers
+    double* xhist = nullptr;     // [(K + 1)][n] tree order
+    int32_t xhist_cap = 0;       // K + 1 slots allocated
+    int32_t fwd_K = -1;          // steps of the last rrt_forward (-1: none)
+    double* adj_lam = nullptr;   // [n] adjoint of x^k
+    double* adj_lup = nullptr;   // [n] upstream adjoint of lnG^K
+    double* adj_nu = nullptr;    // [n_ray][n] adjoint of the columns
+    double* adj_pis = nullptr;   // [n_ray][n] softmax / S per ray
+    double* adj_gnH = nullptr;   // [n] dL/dn_H, tree order
+    double* adj_y = nullptr;     // [n] transposed product
+    double* adj_wpart = nullptr; // [waves][n_bins] per-wave bin partials
+    double* adj_gw = nullptr;    // [n_bins] accumulated over steps
+    double* adj_tpart = nullptr; // [waves] initial-state partials
+    size_t adj_n = 0, adj_nr = 0;  // sizes the adjoint buffers were allocated for
     KernelTables* tables = nullptr;
 
     // reductions (device) and a host mirror
@@ -153,6 +174,16 @@ hipError_t launch_path_columns(Ctx& c, int group);
 hipError_t launch_count_hits(Ctx& c, uint64_t* row_cnt);
 hipError_t launch_record_hits(Ctx& c, const uint64_t* row_off, int32_t* hit_j, int32_t* hit_img,
                               uint64_t cap);
+
+hipError_t launch_scatter_traverse(Ctx& c, const double* nu, double* y);
+
+// ---- launchers (adjoint.hip) ----
+hipError_t launch_set_density(Ctx& c, const float* nH);
+hipError_t launch_adj_rate(Ctx& c, const double* lup);
+hipError_t launch_adj_scatter(Ctx& c);
+hipError_t launch_adj_x(Ctx& c, const double* xprev);
+hipError_t launch_adj_init(Ctx& c, double* part);
+int64_t adj_waves(const Ctx& c);
 
 // ---- launchers (rate.hip) ----
 hipError_t launch_init_state(Ctx& c, bool use_given);

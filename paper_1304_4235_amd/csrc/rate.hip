@@ -19,6 +19,7 @@
 // ionisation (Cen 1992 fit); the paper refers to published fits without
 // printing them.
 #include "internal.h"
+#include "physics.h"
 
 namespace rrt {
 
@@ -26,30 +27,9 @@ namespace {
 
 constexpr int kBlock = 256;
 
-__device__ __forceinline__ double alpha_caseA(double T)
-{
-    double lam = 2.0 * 157807.0 / T;
-    return 1.269e-13 * pow(lam, 1.503) / pow(1.0 + pow(lam / 0.522, 0.470), 1.923);
-}
-
-__device__ __forceinline__ double gamma_collisional(double T)
-{
-    return 5.85e-11 * sqrt(T) * exp(-157809.1 / T) / (1.0 + sqrt(T * 1e-5));
-}
-
-__device__ __forceinline__ double x_minus(double G, double nH, double al, double gc)
-{
-    double P = al * nH;
-    double R = (gc + al) * nH;
-    double negQ = G + P + R;
-    double s = G + gc * nH;
-    double D = s * s + 4.0 * G * P;
-    return 2.0 * P / (negQ + sqrt(D));
-}
-
 __global__ void k_init_state(const int32_t* __restrict__ perm, const float* __restrict__ T,
                              const double* __restrict__ x_init, const float* __restrict__ nH_s,
-                             const float* __restrict__ mu_s, int64_t n, double gthin,
+                             const double* __restrict__ mu_s, int64_t n, double gthin,
                              double* __restrict__ alpha, double* __restrict__ gcoll,
                              double* __restrict__ x_s, float* __restrict__ mux)
 {
@@ -62,7 +42,7 @@ __global__ void k_init_state(const int32_t* __restrict__ perm, const float* __re
     gcoll[i] = gc;
     double x = x_init ? x_init[j] : x_minus(gthin, (double)nH_s[i], al, gc);
     x_s[i] = x;
-    mux[i] = (float)((double)mu_s[i] * x);
+    mux[i] = (float)(mu_s[i] * x);
 }
 
 // One thread per particle: rays, then bins; optionally the equilibrium update.
@@ -71,7 +51,7 @@ k_gamma(const double* __restrict__ N, int64_t n, int n_ray, int n_bins,
         const float* __restrict__ ws_rel, const float* __restrict__ dsig_l2, double sigma_min,
         double ln_ws_max, double ln_gthin, double* __restrict__ lnG, double* __restrict__ G,
         float* __restrict__ tau, int update_x, const float* __restrict__ nH_s,
-        const float* __restrict__ mu_s, const double* __restrict__ alpha,
+        const double* __restrict__ mu_s, const double* __restrict__ alpha,
         const double* __restrict__ gcoll, double* __restrict__ x_s, float* __restrict__ mux,
         unsigned long long* __restrict__ maxdx_bits)
 {
@@ -110,7 +90,7 @@ k_gamma(const double* __restrict__ N, int64_t n, int n_ray, int n_bins,
             double xn = x_minus(g, (double)nH_s[i], alpha[i], gcoll[i]);
             dx = fabs(xn - x_s[i]);
             x_s[i] = xn;
-            mux[i] = (float)((double)mu_s[i] * xn);
+            mux[i] = (float)(mu_s[i] * xn);
         }
     }
     if (update_x) {
@@ -121,7 +101,7 @@ k_gamma(const double* __restrict__ N, int64_t n, int n_ray, int n_bins,
 }
 
 __global__ void k_update_x(const double* __restrict__ G, int64_t n, const float* __restrict__ nH_s,
-                           const float* __restrict__ mu_s, const double* __restrict__ alpha,
+                           const double* __restrict__ mu_s, const double* __restrict__ alpha,
                            const double* __restrict__ gcoll, double* __restrict__ x_s,
                            float* __restrict__ mux, unsigned long long* __restrict__ maxdx_bits)
 {
@@ -131,18 +111,18 @@ __global__ void k_update_x(const double* __restrict__ G, int64_t n, const float*
         double xn = x_minus(G[i], (double)nH_s[i], alpha[i], gcoll[i]);
         dx = fabs(xn - x_s[i]);
         x_s[i] = xn;
-        mux[i] = (float)((double)mu_s[i] * xn);
+        mux[i] = (float)(mu_s[i] * xn);
     }
     for (int off = 32; off > 0; off >>= 1) dx = fmax(dx, __shfl_xor(dx, off, 64));
     if ((threadIdx.x & 63) == 0)
         atomicMax(maxdx_bits, (unsigned long long)__double_as_longlong(dx));
 }
 
-__global__ void k_mux(const float* __restrict__ mu_s, const double* __restrict__ x_s, int64_t n,
+__global__ void k_mux(const double* __restrict__ mu_s, const double* __restrict__ x_s, int64_t n,
                       float* __restrict__ mux)
 {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i < n) mux[i] = (float)((double)mu_s[i] * x_s[i]);
+    if (i < n) mux[i] = (float)(mu_s[i] * x_s[i]);
 }
 
 // tree order -> input order; src is [stride][n] (one column per stride index)

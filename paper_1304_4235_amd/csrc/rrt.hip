@@ -50,15 +50,26 @@ hipError_t dalloc(T** p, size_t count)
 void free_particles(Ctx& c)
 {
     void* bufs[] = {c.pos_in, c.h_in, c.mu_in, c.nH_in, c.T_in, c.x_init, c.p4, c.mu_s, c.nH_s,
+                    c.mu0_s, c.nH0_s,
                     c.alpha_s, c.gcoll_s, c.x_s, c.mux_s, c.lnG_s, c.G_s, c.tau_s, c.N_s,
                     c.perm, c.codes, c.nodes, c.keys_b, c.vals_b, c.k_left, c.k_right,
                     c.k_parent, c.k_first, c.k_last, c.k_lo, c.k_hi, c.k_cnt, c.k_dfs, c.k_flag};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
+    void* adj[] = {c.xhist, c.adj_lam, c.adj_lup, c.adj_nu, c.adj_pis, c.adj_gnH, c.adj_y,
+                   c.adj_wpart, c.adj_gw, c.adj_tpart};
+    for (void* b : adj)
+        if (b) (void)hipFree(b);
+    c.xhist = c.adj_lam = c.adj_lup = c.adj_nu = c.adj_pis = c.adj_gnH = c.adj_y = nullptr;
+    c.adj_wpart = c.adj_gw = c.adj_tpart = nullptr;
+    c.adj_n = c.adj_nr = 0;
+    c.xhist_cap = 0;
+    c.fwd_K = -1;
     c.pos_in = c.h_in = c.mu_in = c.nH_in = c.T_in = nullptr;
     c.x_init = nullptr;
     c.p4 = nullptr;
-    c.mu_s = c.nH_s = c.mux_s = c.tau_s = nullptr;
+    c.nH_s = c.mux_s = c.tau_s = c.mu0_s = c.nH0_s = nullptr;
+    c.mu_s = nullptr;
     c.alpha_s = c.gcoll_s = c.x_s = c.lnG_s = c.G_s = c.N_s = nullptr;
     c.perm = nullptr;
     c.codes = nullptr;
@@ -81,7 +92,7 @@ int alloc_particles(Ctx& c, int64_t n)
 #define A(p, cnt)                                                    \
     if (e == hipSuccess) e = dalloc(&(p), (cnt));
     A(c.pos_in, 3 * m) A(c.h_in, m) A(c.mu_in, m) A(c.nH_in, m) A(c.T_in, m) A(c.x_init, m)
-    A(c.p4, m) A(c.mu_s, m) A(c.nH_s, m) A(c.alpha_s, m) A(c.gcoll_s, m) A(c.x_s, m)
+    A(c.p4, m) A(c.mu_s, m) A(c.mu0_s, m) A(c.nH0_s, m) A(c.nH_s, m) A(c.alpha_s, m) A(c.gcoll_s, m) A(c.x_s, m)
     A(c.mux_s, m) A(c.lnG_s, m) A(c.G_s, m) A(c.tau_s, m) A(c.perm, m) A(c.codes, m)
     A(c.nodes, 2 * m) A(c.keys_b, m) A(c.vals_b, m) A(c.k_left, mi) A(c.k_right, mi)
     A(c.k_parent, 2 * m) A(c.k_first, mi) A(c.k_last, mi) A(c.k_lo, 3 * mi) A(c.k_hi, 3 * mi)
@@ -281,7 +292,8 @@ void rrt_destroy(rrt_ctx* x)
     else (void)hipDeviceSynchronize();
     free_particles(c);
     free_paths(c);
-    void* bufs[] = {c.tables, c.red, c.dirs, c.ws, c.dsig_l2, c.ws_rel, c.hist, c.scan_tmp};
+    void* bufs[] = {c.tables, c.red, c.dirs, c.ws, c.dsig_l2, c.ws_rel, c.srat, c.hist,
+                    c.scan_tmp};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (c.red_host) (void)hipHostFree(c.red_host);
@@ -405,22 +417,34 @@ int rrt_set_spectrum(rrt_ctx* x, int32_t n_bins, const double* sigma, const doub
     }
     if (!(thin > 0.0)) return fail(c, RRT_E_ARG, "the optically thin rate sum(w*sigma) is zero");
     // keep the bins that carry photons; rays see them relative to the least-absorbed one
-    std::vector<float> rel, dsl;
+    std::vector<float> rel, dsl, srt;
     const double log2e = 1.4426950408889634;
     for (int b = 0; b < n_bins; ++b) {
         if (!(w[b] > 0.0)) continue;
         rel.push_back((float)(w[b] * sigma[b] / wsmax));
         dsl.push_back((float)((sigma[b] - smin) * log2e));
+        srt.push_back((float)(sigma[b] / smin));
     }
     int m = (int)rel.size();
-    HIP_OK(dalloc(&c.ws_rel, m));
-    HIP_OK(dalloc(&c.dsig_l2, m));
-    HIP_OK(hipMemcpy(c.ws_rel, rel.data(), sizeof(float) * m, hipMemcpyHostToDevice));
-    HIP_OK(hipMemcpy(c.dsig_l2, dsl.data(), sizeof(float) * m, hipMemcpyHostToDevice));
+    if (m != c.n_bins || !c.ws_rel || !c.srat) {
+        HIP_OK(dalloc(&c.ws_rel, m));
+        HIP_OK(dalloc(&c.dsig_l2, m));
+        HIP_OK(dalloc(&c.srat, m));
+    }
+    HIP_OK(hipMemcpyAsync(c.ws_rel, rel.data(), sizeof(float) * m, hipMemcpyHostToDevice,
+                          c.stream));
+    HIP_OK(hipMemcpyAsync(c.dsig_l2, dsl.data(), sizeof(float) * m, hipMemcpyHostToDevice,
+                          c.stream));
+    HIP_OK(hipMemcpyAsync(c.srat, srt.data(), sizeof(float) * m, hipMemcpyHostToDevice,
+                          c.stream));
+    HIP_OK(hipStreamSynchronize(c.stream));     // host vectors go out of scope
     c.n_bins = m;
     c.sigma_min = smin;
     c.ln_ws_max = std::log(wsmax);
+    c.ws_max = wsmax;
     c.gamma_thin = thin;
+    c.sigma_host.assign(sigma, sigma + n_bins);
+    c.all_bins_weighted = (m == n_bins);
     c.have_spectrum = true;
     c.have_gamma = false;
     return RRT_OK;
@@ -586,6 +610,116 @@ int rrt_iterate_equilibrium(rrt_ctx* x, int32_t max_iter, double tol, double* x_
     if (max_dx_out) *max_dx_out = mdx;
     if (x_out) HIP_OK(hipStreamSynchronize(c.stream));
     return (max_iter > 0 && !(mdx < tol)) ? RRT_NOT_CONVERGED : RRT_OK;
+}
+
+int rrt_set_density(rrt_ctx* x, const float* n_H)
+{
+    if (!x) return RRT_E_ARG;
+    Ctx& c = x->c;
+    if (!c.have_tree) return fail(c, RRT_E_STATE, "rrt_build_tree has not been called");
+    if (!n_H) return fail(c, RRT_E_ARG, "n_H is required");
+    HIP_OK(launch_set_density(c, n_H));
+    HIP_OK(launch_mux(c));
+    c.have_columns = c.have_gamma = false;
+    c.fwd_K = -1;
+    return RRT_OK;
+}
+
+int rrt_forward(rrt_ctx* x, int32_t K, double* lnG_out, double* x_out)
+{
+    if (!x) return RRT_E_ARG;
+    Ctx& c = x->c;
+    if (int r = need_tree(c)) return r;
+    if (K < 1 || K > 100000) return fail(c, RRT_E_ARG, "K must be 1..100000");
+    const size_t n = (size_t)c.n;
+    if (c.xhist_cap < K + 1 || !c.xhist) {
+        HIP_OK(dalloc(&c.xhist, (size_t)(K + 1) * n));
+        c.xhist_cap = K + 1;
+    }
+    c.fwd_K = -1;
+    HIP_OK(launch_init_state(c, false));
+    HIP_OK(hipMemcpyAsync(c.xhist, c.x_s, sizeof(double) * n, hipMemcpyDeviceToDevice,
+                          c.stream));
+    for (int k = 1; k <= K; ++k) {
+        HIP_OK(hipMemsetAsync(c.red, 0, 2 * sizeof(unsigned long long), c.stream));
+        int64_t hits = -1;
+        if (int r = columns_impl(c, &hits)) return r;
+        HIP_OK(launch_gamma(c, true));
+        HIP_OK(hipMemcpyAsync(c.xhist + (size_t)k * n, c.x_s, sizeof(double) * n,
+                              hipMemcpyDeviceToDevice, c.stream));
+    }
+    c.fwd_K = K;
+    c.have_columns = c.have_gamma = false;
+    if (lnG_out) HIP_OK(launch_to_input_order_d(c, c.lnG_s, lnG_out, 1));
+    if (x_out) HIP_OK(launch_to_input_order_d(c, c.x_s, x_out, 1));
+    return RRT_OK;
+}
+
+int rrt_backward(rrt_ctx* x, const double* dL_dlnG, const double* dL_dx, double* dL_dw,
+                 double* dL_dnH)
+{
+    if (!x) return RRT_E_ARG;
+    Ctx& c = x->c;
+    if (int r = need_tree(c)) return r;
+    if (c.fwd_K < 1) return fail(c, RRT_E_STATE, "rrt_forward must precede rrt_backward");
+    if (!c.all_bins_weighted)
+        return fail(c, RRT_E_ARG, "gradients need every bin weight w_b > 0");
+    const size_t n = (size_t)c.n, nr = n * (size_t)c.n_ray;
+    const int64_t waves = adj_waves(c);
+    if (!c.adj_lam || c.adj_n != n || c.adj_nr != nr) {
+        HIP_OK(dalloc(&c.adj_lam, n));
+        HIP_OK(dalloc(&c.adj_lup, n));
+        HIP_OK(dalloc(&c.adj_gnH, n));
+        HIP_OK(dalloc(&c.adj_y, n));
+        HIP_OK(dalloc(&c.adj_nu, nr));
+        HIP_OK(dalloc(&c.adj_pis, nr));
+        HIP_OK(dalloc(&c.adj_tpart, (size_t)waves));
+        c.adj_n = n;
+        c.adj_nr = nr;
+    }
+    HIP_OK(dalloc(&c.adj_wpart, (size_t)waves * c.n_bins));
+    HIP_OK(dalloc(&c.adj_gw, (size_t)c.n_bins));
+    HIP_OK(hipMemsetAsync(c.adj_gw, 0, sizeof(double) * c.n_bins, c.stream));
+    HIP_OK(hipMemsetAsync(c.adj_gnH, 0, sizeof(double) * n, c.stream));
+    if (dL_dx) HIP_OK(launch_from_input_order_d(c, dL_dx, c.adj_lam));
+    else HIP_OK(hipMemsetAsync(c.adj_lam, 0, sizeof(double) * n, c.stream));
+    if (dL_dlnG) HIP_OK(launch_from_input_order_d(c, dL_dlnG, c.adj_lup));
+    const int K = c.fwd_K;
+    for (int k = K; k >= 1; --k) {
+        double* xprev = c.xhist + (size_t)(k - 1) * n;
+        HIP_OK(hipMemcpyAsync(c.x_s, xprev, sizeof(double) * n, hipMemcpyDeviceToDevice,
+                              c.stream));
+        HIP_OK(launch_mux(c));
+        int64_t hits = -1;
+        if (int r = columns_impl(c, &hits)) return r;
+        HIP_OK(launch_adj_rate(c, (k == K && dL_dlnG) ? c.adj_lup : nullptr));
+        if (c.paths_valid) {
+            HIP_OK(launch_adj_scatter(c));
+        } else {
+            HIP_OK(hipMemsetAsync(c.adj_y, 0, sizeof(double) * n, c.stream));
+            HIP_OK(launch_scatter_traverse(c, c.adj_nu, c.adj_y));
+        }
+        HIP_OK(launch_adj_x(c, xprev));
+    }
+    HIP_OK(launch_adj_init(c, c.adj_tpart));
+    std::vector<double> gw(c.n_bins), tp((size_t)waves);
+    HIP_OK(hipMemcpyAsync(gw.data(), c.adj_gw, sizeof(double) * c.n_bins, hipMemcpyDeviceToHost,
+                          c.stream));
+    HIP_OK(hipMemcpyAsync(tp.data(), c.adj_tpart, sizeof(double) * waves, hipMemcpyDeviceToHost,
+                          c.stream));
+    if (dL_dnH) HIP_OK(launch_to_input_order_d(c, c.adj_gnH, dL_dnH, 1));
+    // leave the state at x^K, as after the forward
+    HIP_OK(hipMemcpyAsync(c.x_s, c.xhist + (size_t)K * n, sizeof(double) * n,
+                          hipMemcpyDeviceToDevice, c.stream));
+    HIP_OK(launch_mux(c));
+    HIP_OK(hipStreamSynchronize(c.stream));
+    double thin = 0.0;
+    for (double v : tp) thin += v;
+    if (dL_dw)
+        for (int b = 0; b < c.n_bins; ++b)
+            dL_dw[b] = c.sigma_host[b] / c.ws_max * gw[b] + c.sigma_host[b] * thin;
+    c.have_columns = c.have_gamma = false;
+    return RRT_OK;
 }
 
 int rrt_set_state(rrt_ctx* x, const double* xs)

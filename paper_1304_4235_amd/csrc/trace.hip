@@ -97,13 +97,16 @@ __device__ __forceinline__ float erf_t_odd(const float4* __restrict__ tb, float 
 
 // column: accumulate N; count: hits per ray; record: hit lists for inspection;
 // path: per hit (tree index, K/h^2) for the streaming product
-enum { kModeColumn = 0, kModeCount = 1, kModeRecord = 2, kModePath = 3 };
+// scatter: y_j += (K/h^2) nu_ray for every hit (transposed column product)
+enum { kModeColumn = 0, kModeCount = 1, kModeRecord = 2, kModePath = 3, kModeScatter = 4 };
 
 struct RayOut {
     double* N;              // [n_ray][n] columns (column / record modes)
     uint64_t* row_cnt;      // [n_ray * n] hits per ray (count mode)
     const uint64_t* row_off;// [n_ray * n] write offsets (record / path modes)
     int2* path;             // path mode: (tree index, factor bits) per hit
+    const double* nu;       // scatter mode: adjoint of each ray's column
+    double* y;              // scatter mode: accumulated per tree index
     int32_t* hit_j;         // record mode: input index of each hit
     int32_t* hit_img;       // record mode: image code of each hit
     uint64_t hit_cap;       // record mode: capacity of hit_j / hit_img
@@ -122,7 +125,7 @@ k_trace(const Node* __restrict__ nodes, const float4* __restrict__ p4,
         const KernelTables* __restrict__ tabs, TraceGeom g, RayOut out)
 {
     __shared__ float4 tab[3 * kTabIntervals];
-    constexpr bool kTerms = MODE == kModeColumn || MODE == kModeRecord || MODE == kModePath;
+    constexpr bool kTerms = MODE != kModeCount;
     if (kTerms) {
         const float4* src = reinterpret_cast<const float4*>(tabs);
         for (int i = threadIdx.x; i < 3 * kTabIntervals; i += blockDim.x) tab[i] = src[i];
@@ -161,6 +164,7 @@ k_trace(const Node* __restrict__ nodes, const float4* __restrict__ p4,
         }
         double acc = 0.0;
         uint64_t w = (MODE == kModeRecord || MODE == kModePath) ? out.row_off[gid] : 0;
+        const double nur = (MODE == kModeScatter) ? out.nu[gid] : 0.0;
 
         for (int sx = lo[0]; sx <= hi[0]; ++sx)
         for (int sy = lo[1]; sy <= hi[1]; ++sy)
@@ -243,6 +247,8 @@ k_trace(const Node* __restrict__ nodes, const float4* __restrict__ p4,
                     if (MODE == kModePath) {
                         if (w < out.hit_cap) out.path[w] = make_int2(j, __float_as_int(gk));
                         ++w;
+                    } else if (MODE == kModeScatter) {
+                        if (nur != 0.0) unsafeAtomicAdd(out.y + j, (double)gk * nur);
                     } else {
                         acc += (double)(mux[j] * gk);
                     }
@@ -272,7 +278,7 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
              const KernelTables* __restrict__ tabs, TraceGeom g, RayOut out)
 {
     __shared__ float4 tab[3 * kTabIntervals];
-    constexpr bool kTerms = MODE == kModeColumn || MODE == kModeRecord || MODE == kModePath;
+    constexpr bool kTerms = MODE != kModeCount;
     if (kTerms) {
         const float4* src = reinterpret_cast<const float4*>(tabs);
         for (int i = threadIdx.x; i < 3 * kTabIntervals; i += blockDim.x) tab[i] = src[i];
@@ -322,6 +328,7 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
     double acc = 0.0;
     uint32_t cnt = 0;
     uint64_t w = ((MODE == kModeRecord || MODE == kModePath) && active) ? out.row_off[gid] : 0;
+    const double nur = (MODE == kModeScatter && active) ? out.nu[gid] : 0.0;
 
     for (int sx = ulo[0]; sx <= uhi[0]; ++sx)
     for (int sy = ulo[1]; sy <= uhi[1]; ++sy)
@@ -405,6 +412,8 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
                 if (MODE == kModePath) {
                     if (w < out.hit_cap) out.path[w] = make_int2(j, __float_as_int(gk));
                     ++w;
+                } else if (MODE == kModeScatter) {
+                    if (nur != 0.0) unsafeAtomicAdd(out.y + j, (double)gk * nur);
                 } else {
                     acc += (double)(mux[j] * gk);
                 }
@@ -458,7 +467,8 @@ static hipError_t launch_mode(Ctx& c, int mode, RayOut o)
     if (mode == kModeColumn) launch_one<kModeColumn>(c, o);
     else if (mode == kModeCount) launch_one<kModeCount>(c, o);
     else if (mode == kModeRecord) launch_one<kModeRecord>(c, o);
-    else launch_one<kModePath>(c, o);
+    else if (mode == kModePath) launch_one<kModePath>(c, o);
+    else launch_one<kModeScatter>(c, o);
     return hipGetLastError();
 }
 
@@ -478,23 +488,19 @@ k_path_columns(const uint64_t* __restrict__ row_off, const int2* __restrict__ pa
     if (row < n_rows) {
         const uint64_t a = row_off[row], b = row_off[row + 1];
         const long long* p = reinterpret_cast<const long long*>(path);
-        uint64_t e = a + lane;
-        // four independent streaming loads in flight per lane before any is used
-        for (; e + 3 * G < b; e += 4 * G) {
+        // four independent streaming loads in flight per lane before any is used;
+        // entries past the row end read as (particle 0, factor 0) and add nothing
+        for (uint64_t e = a + lane; e < b; e += 4 * G) {
             const long long v0 = __builtin_nontemporal_load(p + e);
-            const long long v1 = __builtin_nontemporal_load(p + e + G);
-            const long long v2 = __builtin_nontemporal_load(p + e + 2 * G);
-            const long long v3 = __builtin_nontemporal_load(p + e + 3 * G);
+            const long long v1 = e + G < b ? __builtin_nontemporal_load(p + e + G) : 0ll;
+            const long long v2 = e + 2 * G < b ? __builtin_nontemporal_load(p + e + 2 * G) : 0ll;
+            const long long v3 = e + 3 * G < b ? __builtin_nontemporal_load(p + e + 3 * G) : 0ll;
             const float m0 = mux[(int)v0], m1 = mux[(int)v1];
             const float m2 = mux[(int)v2], m3 = mux[(int)v3];
             acc += (double)(m0 * __int_as_float((int)(v0 >> 32)));
             acc += (double)(m1 * __int_as_float((int)(v1 >> 32)));
             acc += (double)(m2 * __int_as_float((int)(v2 >> 32)));
             acc += (double)(m3 * __int_as_float((int)(v3 >> 32)));
-        }
-        for (; e < b; e += G) {
-            const long long v = __builtin_nontemporal_load(p + e);
-            acc += (double)(mux[(int)v] * __int_as_float((int)(v >> 32)));
         }
     }
     for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
@@ -542,6 +548,16 @@ hipError_t launch_record_paths(Ctx& c, const uint64_t* row_off, int2* path, uint
     o.perm = c.perm;
     o.hits_total = c.red + 1;
     return launch_mode(c, kModePath, o);
+}
+
+hipError_t launch_scatter_traverse(Ctx& c, const double* nu, double* y)
+{
+    RayOut o{};
+    o.nu = nu;
+    o.y = y;
+    o.perm = c.perm;
+    o.hits_total = c.red + 1;
+    return launch_mode(c, kModeScatter, o);
 }
 
 hipError_t launch_path_columns(Ctx& c, int group)

@@ -448,14 +448,17 @@ __global__ void k_layout(const float4* __restrict__ p4, int n, int leaf_max,
 __global__ void k_gather_particles(const int32_t* __restrict__ perm, const float* __restrict__ pos,
                                    const float* __restrict__ h, const float* __restrict__ mu,
                                    const float* __restrict__ nH, int64_t n,
-                                   float4* __restrict__ p4, float* __restrict__ mu_s,
+                                   float4* __restrict__ p4, double* __restrict__ mu_s,
+                                   float* __restrict__ mu0_s, float* __restrict__ nH0_s,
                                    float* __restrict__ nH_s)
 {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     int64_t j = perm[i];
     p4[i] = make_float4(pos[3 * j], pos[3 * j + 1], pos[3 * j + 2], h[j]);
-    mu_s[i] = mu[j];
+    mu_s[i] = (double)mu[j];
+    mu0_s[i] = mu[j];
+    nH0_s[i] = nH[j];
     nH_s[i] = nH[j];
 }
 
@@ -523,7 +526,8 @@ hipError_t build_radix_tree(Ctx& c)
     const int n = (int)c.n;
     hipError_t e;
     hipLaunchKernelGGL(k_gather_particles, dim3(nblk(n)), dim3(kBlock), 0, c.stream, c.perm,
-                       c.pos_in, c.h_in, c.mu_in, c.nH_in, (int64_t)n, c.p4, c.mu_s, c.nH_s);
+                       c.pos_in, c.h_in, c.mu_in, c.nH_in, (int64_t)n, c.p4, c.mu_s, c.mu0_s,
+                       c.nH0_s, c.nH_s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (n > 1) {
         hipLaunchKernelGGL(k_radix_tree, dim3(nblk(n - 1)), dim3(kBlock), 0, c.stream, c.codes, n,

@@ -58,6 +58,9 @@ SIGNATURES = {
     "rrt_get_timing": ([_vp, _vp], C.c_int),
     "rrt_reset_timing": ([_vp], C.c_int),
     "rrt_get_counters": ([_vp, _vp], C.c_int),
+    "rrt_set_density": ([_vp, _vp], C.c_int),
+    "rrt_forward": ([_vp, _i32, _vp, _vp], C.c_int),
+    "rrt_backward": ([_vp, _vp, _vp, _vp, _vp], C.c_int),
 }
 
 
@@ -173,6 +176,8 @@ class Solver:
             raise ValueError("sigma and w must have the same length")
         self._check(_lib.rrt_set_spectrum(self._h, s.size, s.ctypes.data, ww.ctypes.data),
                     "rrt_set_spectrum")
+        self.n_bins = s.size
+        self.sigma = s
 
     def build_tree(self):
         self._check(_lib.rrt_build_tree(self._h), "rrt_build_tree")
@@ -210,6 +215,32 @@ class Solver:
                                                       C.byref(it), C.byref(md)),
                          "rrt_iterate_equilibrium")
         return dict(x=x, iters=it.value, max_dx=md.value, converged=(rc == RRT_OK))
+
+    # -- reverse mode -----------------------------------------------------
+    def set_density(self, n_H):
+        nH = self._dev(n_H, torch.float32)
+        if nH.numel() != self.n:
+            raise ValueError("n_H must have n entries")
+        self._check(_lib.rrt_set_density(self._h, _ptr(nH)), "rrt_set_density")
+        torch.cuda.current_stream(self.device).synchronize()
+
+    def forward(self, K: int):
+        """Exactly K iterations from the thin state; keeps the iterates."""
+        lnG = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        x = torch.empty_like(lnG)
+        self._check(_lib.rrt_forward(self._h, int(K), _ptr(lnG), _ptr(x)), "rrt_forward")
+        return lnG, x
+
+    def backward(self, dL_dlnG=None, dL_dx=None):
+        """Returns (dL/dw as float64 numpy [n_bins], dL/dn_H as a float64 tensor [n])."""
+        gl = None if dL_dlnG is None else self._dev(dL_dlnG, torch.float64)
+        gx = None if dL_dx is None else self._dev(dL_dx, torch.float64)
+        nb = self.n_bins
+        dw = np.zeros(nb, np.float64)
+        dn = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        self._check(_lib.rrt_backward(self._h, _ptr(gl), _ptr(gx), dw.ctypes.data, _ptr(dn)),
+                    "rrt_backward")
+        return dw, dn
 
     def set_state(self, x=None):
         xs = None if x is None else self._dev(x, torch.float64)

@@ -1,0 +1,143 @@
+"""Reverse mode through K unrolled iterations: gradients of ln Gamma and x with
+respect to the bin weights and the particle densities.
+
+Checked against central finite differences of the GPU forward itself and of
+the FP64 oracle (the oracle has no adjoint: its gradient is the central
+difference of its own K-step solve)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _setup(wl, K, paths=-1):
+    from paper_1304_4235_amd import Solver
+    s = Solver.from_workload(wl, record_paths=paths)
+    return s
+
+
+def _loss_parts(wl, seed=0):
+    rng = np.random.default_rng(seed)
+    c_x = torch.tensor(rng.uniform(-1, 1, wl.n), dtype=torch.float64, device="cuda")
+    return c_x
+
+
+def _gpu_loss(s, w, nH, K, lnG_t, c_x):
+    s.set_spectrum(s.sigma, w)
+    s.set_density(torch.tensor(nH, dtype=torch.float32))
+    lnG, x = s.forward(K)
+    return float((((lnG - lnG_t) / np.log(10)) ** 2).sum() + (c_x * x).sum())
+
+
+def _adjoint(s, w, nH, K, lnG_t, c_x):
+    s.set_spectrum(s.sigma, w)
+    s.set_density(torch.tensor(nH, dtype=torch.float32))
+    lnG, x = s.forward(K)
+    g_lnG = 2 * (lnG - lnG_t) / np.log(10) ** 2
+    dw, dn = s.backward(g_lnG, c_x)
+    return dw, dn.cpu().numpy()
+
+
+@pytest.mark.parametrize("paths", [-1, 0])
+def test_adjoint_vs_gpu_central_differences(paths):
+    wl = W.isothermal_halo(n=4096, n_bins=16, seed=41, n_peak=3.0)
+    K = 6
+    s = _setup(wl, K, paths)
+    w0 = wl.w.copy()
+    nH0 = wl.n_H.astype(np.float32).copy()
+    # target from 1.2x the weights
+    s.set_spectrum(s.sigma, 1.2 * w0)
+    lnG_t, _ = s.forward(K)
+    c_x = _loss_parts(wl)
+    dw, dn = _adjoint(s, w0, nH0, K, lnG_t, c_x)
+    rng = np.random.default_rng(3)
+    # weights: relative step 1e-3
+    for b in rng.choice(wl.n_bins, 6, replace=False):
+        h = 1e-3 * w0[b]
+        wp, wm = w0.copy(), w0.copy()
+        wp[b] += h
+        wm[b] -= h
+        fd = (_gpu_loss(s, wp, nH0, K, lnG_t, c_x) - _gpu_loss(s, wm, nH0, K, lnG_t, c_x)) / (2 * h)
+        _say("w", b, dw[b], fd)
+        assert abs(dw[b] - fd) <= 2e-3 * abs(fd) + 1e-4 * np.max(np.abs(dw)) 
+    # densities: step of the FP32 representation near 1e-3 relative
+    scale = np.max(np.abs(dn))
+    big = np.argsort(-np.abs(dn))[:4]
+    for j in list(rng.choice(wl.n, 6, replace=False)) + list(big):
+        up = np.float32(nH0[j] * (1 + 1e-3))
+        dn_ = np.float32(nH0[j] * (1 - 1e-3))
+        npl, nmi = nH0.copy(), nH0.copy()
+        npl[j], nmi[j] = up, dn_
+        fd = (_gpu_loss(s, w0, npl, K, lnG_t, c_x) - _gpu_loss(s, w0, nmi, K, lnG_t, c_x)) / \
+            (float(up) - float(dn_))
+        _say("n", j, dn[j], fd)
+        assert abs(dn[j] - fd) <= 5e-3 * abs(fd) + 1e-4 * scale
+
+
+def test_adjoint_vs_oracle_central_differences():
+    """Tiny periodic lattice: GPU adjoint against central differences of the FP64
+    oracle's K-step solve."""
+    wl = W.make_config(0, n_side_lattice=6, box=37.5, max_iter=3)
+    wl.sigma, wl.w = W.power_law_spectrum(6, 1.5, 1e-12)
+    wl.n_H = np.full(wl.n, 5e-3, np.float32)
+    K = 3
+    s = _setup(wl, K)
+    w0 = wl.w.copy()
+    nH0 = wl.n_H.copy()
+    mu0 = wl.mu.copy()
+    s.set_spectrum(s.sigma, 1.2 * w0)
+    lnG_t = s.forward(K)[0].cpu().numpy()
+    rng = np.random.default_rng(5)
+    c_x = rng.uniform(-1, 1, wl.n)
+    dw, dn = _adjoint(s, w0, nH0, K, torch.tensor(lnG_t, device="cuda"),
+                      torch.tensor(c_x, device="cuda"))
+
+    def oloss(w, nH, mu):
+        wl2 = W.Workload(**{**wl.__dict__, "w": w, "n_H": nH, "mu": mu})
+        r = oracle.solve(wl2, max_iter=K, tol=0.0)
+        lnG, x = r["lnG_hist"][-1], r["x_hist"][-1]
+        return np.sum(((lnG - lnG_t) / np.log(10)) ** 2) + np.sum(c_x * x)
+
+    for b in range(wl.n_bins):
+        h = 1e-4 * w0[b]
+        wp, wm = w0.copy(), w0.copy()
+        wp[b] += h
+        wm[b] -= h
+        fd = (oloss(wp, nH0, mu0) - oloss(wm, nH0, mu0)) / (2 * h)
+        _say("oracle w", b, dw[b], fd)
+        assert abs(dw[b] - fd) <= 2e-3 * abs(fd) + 1e-4 * np.max(np.abs(dw))
+    scale = np.max(np.abs(dn))
+    for j in rng.choice(wl.n, 5, replace=False):
+        up, lo = np.float32(nH0[j] * (1 + 1e-3)), np.float32(nH0[j] * (1 - 1e-3))
+        npl, nmi = nH0.copy(), nH0.copy()
+        mpl, mmi = mu0.copy(), mu0.copy()
+        npl[j], nmi[j] = up, lo
+        mpl[j] = np.float32(np.float64(mu0[j]) * np.float64(up) / np.float64(nH0[j]))
+        mmi[j] = np.float32(np.float64(mu0[j]) * np.float64(lo) / np.float64(nH0[j]))
+        fd = (oloss(w0, npl, mpl) - oloss(w0, nmi, mmi)) / (float(up) - float(lo))
+        _say("oracle n", j, dn[j], fd)
+        assert abs(dn[j] - fd) <= 5e-3 * abs(fd) + 1e-4 * scale
+
+
+def test_autograd_function_matches_solver():
+    from paper_1304_4235_amd.autograd import RRTFunction, log10_rate_loss
+    wl = W.isothermal_halo(n=2048, n_bins=8, seed=43)
+    s = _setup(wl, 4)
+    w = torch.tensor(wl.w, dtype=torch.float64, requires_grad=True)
+    nH = torch.tensor(wl.n_H, dtype=torch.float32, device="cuda", requires_grad=True)
+    with torch.no_grad():
+        lnG_t, _ = RRTFunction.apply(w * 1.2, nH, s, 4)
+    lnG, x = RRTFunction.apply(w, nH, s, 4)
+    loss = log10_rate_loss(lnG, lnG_t) + x.sum()
+    loss.backward()
+    assert w.grad is not None and nH.grad is not None
+    assert torch.isfinite(w.grad).all() and torch.isfinite(nH.grad).all()
+    assert float(w.grad.abs().sum()) > 0
