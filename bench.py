@@ -93,6 +93,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="isothermal_halo_262144")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--adjoint", type=int, default=1,
+                    help="also time forward+adjoint against the plain forward (1 = yes)")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--leaf", type=int, default=0)
     ap.add_argument("--traversal", type=int, default=0, help="0 wave-cooperative, 1 per lane")
@@ -197,6 +199,29 @@ def main():
     }
     print(f"timed {args.steps} steps in {dt:.3f} s; iterations {iters}", file=sys.stderr,
           flush=True)
+    if args.adjoint:
+        # forward+adjoint against the plain forward, K frozen at the solve's iterations
+        K = int(iters[-1])
+        w0 = wl.w.copy()
+        s.set_spectrum(wl.sigma, 1.2 * w0)
+        lnG_t, _ = s.forward(K)
+        s.set_spectrum(wl.sigma, w0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lnG, x = s.forward(K)
+        torch.cuda.synchronize()
+        t_fwd = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        lnG, x = s.forward(K)
+        g = 2.0 * (lnG - lnG_t) / np.log(10.0) ** 2
+        s.backward(g, None)
+        torch.cuda.synchronize()
+        t_fb = time.perf_counter() - t0
+        out["forward_adjoint"] = {"K": K, "plain_forward_ms": t_fwd * 1e3,
+                                  "forward_plus_adjoint_ms": t_fb * 1e3,
+                                  "ratio": t_fb / t_fwd,
+                                  "gradients": f"dL/dw over {wl.n_bins} bins and dL/dn_H over "
+                                               f"{wl.n} particles"}
     if not args.no_cpu_baseline:
         print("cpu baseline (oracle sample)...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl, oracle.x_thin(wl))

@@ -94,6 +94,10 @@ struct Ctx {
     int64_t path_hits = 0;        // entries in use
     bool paths_valid = false;
     bool paths_unfit = false;     // recording was tried and exceeded the budget
+    uint64_t* tpath = nullptr;    // transposed paths: (factor bits << 32 | row) by particle
+    uint64_t* tcol_off = nullptr; // [n + 1] start of each particle's entries
+    bool tpaths_valid = false;
+    bool tpaths_unfit = false;
 
     // tree
     Node* nodes = nullptr;
@@ -176,6 +180,10 @@ hipError_t launch_record_hits(Ctx& c, const uint64_t* row_off, int32_t* hit_j, i
                               uint64_t cap);
 
 hipError_t launch_scatter_traverse(Ctx& c, const double* nu, double* y);
+
+// ---- transpose.hip ----
+hipError_t build_transposed_paths(Ctx& c);
+hipError_t launch_gather_cols(Ctx& c);
 
 // ---- launchers (adjoint.hip) ----
 hipError_t launch_set_density(Ctx& c, const float* nH);

@@ -140,8 +140,19 @@ int need_tree(Ctx& c)
     return RRT_OK;
 }
 
+void free_tpaths(Ctx& c)
+{
+    if (c.tpath) (void)hipFree(c.tpath);
+    if (c.tcol_off) (void)hipFree(c.tcol_off);
+    c.tpath = nullptr;
+    c.tcol_off = nullptr;
+    c.tpaths_valid = false;
+    c.tpaths_unfit = false;
+}
+
 void free_paths(Ctx& c)
 {
+    free_tpaths(c);
     if (c.row_off) (void)hipFree(c.row_off);
     if (c.path) (void)hipFree(c.path);
     c.row_off = nullptr;
@@ -518,6 +529,7 @@ int rrt_build_tree(rrt_ctx* x)
     if (c.timing) c.t_build += ev_end(c);
     c.paths_valid = false;       // new geometry: the recorded paths no longer apply
     c.paths_unfit = false;
+    free_tpaths(c);
     c.have_tree = true;
     c.have_columns = c.have_gamma = false;
     return RRT_OK;
@@ -693,7 +705,21 @@ int rrt_backward(rrt_ctx* x, const double* dL_dlnG, const double* dL_dx, double*
         int64_t hits = -1;
         if (int r = columns_impl(c, &hits)) return r;
         HIP_OK(launch_adj_rate(c, (k == K && dL_dlnG) ? c.adj_lup : nullptr));
-        if (c.paths_valid) {
+        if (c.paths_valid && !c.tpaths_valid && !c.tpaths_unfit) {
+            // transposed paths (8 B per intersection) plus sort scratch (24 B)
+            size_t fr = 0, tot = 0;
+            HIP_OK(hipMemGetInfo(&fr, &tot));
+            const size_t need = (size_t)c.path_hits * 32 + (size_t)c.n * 8 + (64u << 20);
+            if (need < fr / 2 + fr / 4) {
+                HIP_OK(build_transposed_paths(c));
+                c.tpaths_valid = true;
+            } else {
+                c.tpaths_unfit = true;
+            }
+        }
+        if (c.paths_valid && c.tpaths_valid) {
+            HIP_OK(launch_gather_cols(c));
+        } else if (c.paths_valid) {
             HIP_OK(launch_adj_scatter(c));
         } else {
             HIP_OK(hipMemsetAsync(c.adj_y, 0, sizeof(double) * n, c.stream));

@@ -141,3 +141,65 @@ def test_autograd_function_matches_solver():
     assert w.grad is not None and nH.grad is not None
     assert torch.isfinite(w.grad).all() and torch.isfinite(nH.grad).all()
     assert float(w.grad.abs().sum()) > 0
+
+
+def test_full_halo_gradient_central_differences():
+    """The 262144-particle halo, 128 bins: K frozen from a converged base run,
+    loss sum (log10 Gamma - log10 Gamma_target)^2 with the target from 1.2x the
+    weights; 32 random coordinates (weights and densities) by central
+    differences with relative step 1e-3."""
+    wl = W.make_config(4)
+    from paper_1304_4235_amd import Solver
+    s = Solver.from_workload(wl)
+    K = s.iterate(wl.max_iter, wl.tol, want_x=False)["iters"]
+    _say("frozen K", K)
+    w0 = wl.w.copy()
+    nH0 = wl.n_H.astype(np.float32).copy()
+    s.set_spectrum(s.sigma, 1.2 * w0)
+    lnG_t, _ = s.forward(K)
+    c_x = torch.zeros(wl.n, dtype=torch.float64, device="cuda")
+    dw, dn = _adjoint(s, w0, nH0, K, lnG_t, c_x)
+    assert np.all(np.isfinite(dw)) and np.all(np.isfinite(dn))
+    rng = np.random.default_rng(11)
+    scale_n = np.max(np.abs(dn))
+    checked = 0
+    for b in rng.choice(wl.n_bins, 8, replace=False):
+        h = 1e-3 * w0[b]
+        wp, wm = w0.copy(), w0.copy()
+        wp[b] += h
+        wm[b] -= h
+        fd = (_gpu_loss(s, wp, nH0, K, lnG_t, c_x) - _gpu_loss(s, wm, nH0, K, lnG_t, c_x)) / (2 * h)
+        _say("w", b, dw[b], fd)
+        assert abs(dw[b] - fd) <= 1e-2 * abs(fd) + 1e-3 * np.max(np.abs(dw))
+        checked += 1
+    # densities: the largest-gradient particles and random ones
+    cand = list(np.argsort(-np.abs(dn))[:12]) + list(rng.choice(wl.n, 12, replace=False))
+    for j in cand:
+        up, lo = np.float32(nH0[j] * (1 + 1e-3)), np.float32(nH0[j] * (1 - 1e-3))
+        npl, nmi = nH0.copy(), nH0.copy()
+        npl[j], nmi[j] = up, lo
+        fd = (_gpu_loss(s, w0, npl, K, lnG_t, c_x) - _gpu_loss(s, w0, nmi, K, lnG_t, c_x)) / \
+            (float(up) - float(lo))
+        _say("n", j, dn[j], fd)
+        assert abs(dn[j] - fd) <= 1e-2 * abs(fd) + 1e-3 * scale_n
+        checked += 1
+    assert checked == 32
+
+
+def test_transposed_paths_deterministic_and_match_scatter():
+    """The gather over transposed paths is deterministic and equals the
+    atomic scatter of a re-traversal to summation-order rounding."""
+    wl = W.isothermal_halo(n=8192, n_bins=16, seed=45)
+    K = 5
+    sa = _setup(wl, K, paths=-1)
+    sb = _setup(wl, K, paths=0)
+    out = []
+    for s in (sa, sa, sb):
+        lnG, x = s.forward(K)
+        g = torch.ones_like(lnG)
+        dw, dn = s.backward(g, None)
+        out.append((dw, dn.cpu().numpy()))
+    np.testing.assert_array_equal(out[0][1], out[1][1])
+    np.testing.assert_array_equal(out[0][0], out[1][0])
+    np.testing.assert_allclose(out[0][1], out[2][1], rtol=1e-9, atol=1e-12 * np.abs(out[2][1]).max())
+    np.testing.assert_allclose(out[0][0], out[2][0], rtol=1e-9)
