@@ -113,6 +113,13 @@ int rrt_set_particles(rrt_ctx* ctx, int64_t n, const float* pos, const float* h,
                       const float* mu, const float* n_H, const float* T,
                       const double* x_init);
 
+/* Independent problems in one context: particles [offsets[h], offsets[h+1])
+ * form halo h, and a halo's rays see only its own particles.  host int64
+ * offsets[n_halo + 1], 0 = offsets[0] < ... < offsets[n_halo] = n, n_halo
+ * 1..4096.  Call after rrt_set_particles (which resets to one halo) and before
+ * rrt_build_tree.  The tree keeps each halo in its own subtree. */
+int rrt_set_halos(rrt_ctx* ctx, int32_t n_halo, const int64_t* offsets);
+
 /* Ray directions (Sec. 3.3: HEALPix pixel centres): host double[n_ray][3] unit
  * vectors, 1 <= n_ray <= 3072.  Every particle casts the same directions. */
 int rrt_set_rays(rrt_ctx* ctx, int32_t n_ray, const double* dirs);
@@ -184,6 +191,19 @@ int rrt_forward(rrt_ctx* ctx, int32_t K, double* lnG_out, double* x_out);
  * with FP64 atomics, so dL_dnH can differ between runs in the last bits. */
 int rrt_backward(rrt_ctx* ctx, const double* dL_dlnG, const double* dL_dx, double* dL_dw,
                  double* dL_dnH);
+
+/* The fixed point of every halo at once: each halo iterates until its own
+ * max|dx| < tol or max_iter iterations, then keeps its state while the others
+ * continue (per-halo masks on the device).  After a first eager iteration
+ * (which records the ray paths when they fit), the iterations run as replays
+ * of a HIP graph of per_launch (1..256) iterations captured once per geometry
+ * and parameters, on a stream the library owns (ordered after the context's
+ * stream by events); the host reads 8 bytes after each replay.  x_out: device
+ * double[n], input order (nullable).  halo_iters_out: host int32[n_halo]
+ * iterations of each halo (nullable).  Returns RRT_NOT_CONVERGED if a halo
+ * reached max_iter.  Works with one halo too. */
+int rrt_iterate_halos(rrt_ctx* ctx, int32_t max_iter, double tol, int32_t per_launch,
+                      double* x_out, int32_t* halo_iters_out);
 
 /* Replace the state: x device double[n] in input order (checkpoint / resume,
  * or a given iterate); NULL resets to x_thin. */

@@ -29,6 +29,13 @@ struct Node {
 
 // Geometry of one ray family: everything the traversal needs besides the tree.
 struct TraceGeom {
+    // independent halos: rays of a particle of halo h walk nodes
+    // [seg_root[h], seg_end[h]); a halo whose seg_active is 0 is skipped.
+    // All null for a single problem (walk the whole tree).
+    const int32_t* seg_of;      // [n] halo of each tree position
+    const int32_t* seg_root;    // [n_halo]
+    const int32_t* seg_end;     // [n_halo]
+    const int32_t* seg_active;  // [n_halo] or null
     double L;              // segment length
     double box;            // periodic side, 0 = isolated
     double plo[3], phi[3]; // bounds of particle positions
@@ -61,6 +68,21 @@ struct Ctx {
     bool have_particles = false, have_rays = false, have_spectrum = false, have_tree = false;
     bool have_columns = false, have_gamma = false;
     bool x_init_given = false;
+
+    // independent halos (segments of the particle arrays)
+    int32_t n_halo = 1;
+    std::vector<int64_t> halo_off_host;
+    int64_t* halo_off = nullptr;  // [n_halo + 1] device
+    int key_bits = 21;            // Morton bits per axis
+    int32_t* seg_of = nullptr;    // [n] halo of each tree position
+    int32_t* k_seg = nullptr;     // [n - 1] halo of an internal node's particles, -1 if mixed
+    int32_t* seg_root = nullptr;  // [n_halo]
+    int32_t* seg_end = nullptr;   // [n_halo]
+    int32_t* seg_active = nullptr;          // [n_halo] 1 while a halo iterates
+    unsigned long long* seg_maxdx = nullptr;  // [n_halo] max|dx| bits of this iteration
+    int32_t* seg_iters = nullptr;           // [n_halo] iterations done
+    int32_t* seg_state = nullptr;           // [4] iteration counter, active halos, ...
+    int32_t* seg_state_host = nullptr;      // pinned mirror
 
     // inputs in input order (device)
     float* pos_in = nullptr;     // [n][3]
@@ -152,6 +174,14 @@ struct Ctx {
     // geometry
     TraceGeom geom{};
 
+    // batched iterations as replays of a captured graph
+    hipStream_t gstream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    int32_t graph_iters = 0, graph_max_iter = 0;
+    double graph_tol = -1.0;
+    hipEvent_t ev_a = nullptr, ev_b = nullptr;
+
     // counters: intersections of the last iteration and since the last reset
     int64_t last_hits = 0, total_hits = 0;
 
@@ -164,7 +194,7 @@ struct Ctx {
 
 // ---- launchers (tree.hip) ----
 hipError_t launch_bounds(Ctx& c, float* part_out /*[nb][8]*/, int nb);
-hipError_t launch_morton(Ctx& c, const double lo[3], double scale);
+hipError_t launch_morton(Ctx& c, const double lo[3], double scale, int bits);
 hipError_t radix_sort_pairs(Ctx& c, uint64_t* keys, int32_t* vals, int64_t n);
 hipError_t build_radix_tree(Ctx& c);
 hipError_t launch_gather(Ctx& c);
@@ -201,5 +231,7 @@ hipError_t launch_to_input_order_d(Ctx& c, const double* src, double* dst, int32
 hipError_t launch_to_input_order_f(Ctx& c, const float* src, float* dst);
 hipError_t launch_from_input_order_d(Ctx& c, const double* src, double* dst);
 hipError_t launch_mux(Ctx& c);
+hipError_t launch_seg_finalize(Ctx& c, double tol, int max_iter);
+hipError_t launch_seg_init(Ctx& c);
 
 }  // namespace rrt

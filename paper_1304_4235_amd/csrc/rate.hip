@@ -53,11 +53,14 @@ k_gamma(const double* __restrict__ N, int64_t n, int n_ray, int n_bins,
         float* __restrict__ tau, int update_x, const float* __restrict__ nH_s,
         const double* __restrict__ mu_s, const double* __restrict__ alpha,
         const double* __restrict__ gcoll, double* __restrict__ x_s, float* __restrict__ mux,
-        unsigned long long* __restrict__ maxdx_bits)
+        unsigned long long* __restrict__ maxdx_bits, const int32_t* __restrict__ seg_of,
+        const int32_t* __restrict__ seg_active, unsigned long long* __restrict__ seg_maxdx)
 {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     double dx = 0.0;
-    if (i < n) {
+    const int h = (seg_of && i < n) ? seg_of[i] : -1;
+    const bool live = !(seg_active && h >= 0 && seg_active[h] == 0);
+    if (i < n && live) {
         double m = -INFINITY, s = 0.0;
         for (int k = 0; k < n_ray; ++k) {
             double Nk = N[(int64_t)k * n + i];
@@ -94,9 +97,72 @@ k_gamma(const double* __restrict__ N, int64_t n, int n_ray, int n_bins,
         }
     }
     if (update_x) {
+        if (seg_maxdx) {
+            // per-halo maximum: one atomic per wave when the wave holds one halo
+            const int h0 = __shfl(h, 0, 64);
+            if (h0 >= 0 && __ballot(h != h0 && h >= 0) == 0) {
+                double m = dx;
+                for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+                if ((threadIdx.x & 63) == 0 && m > 0.0)
+                    atomicMax(seg_maxdx + h0, (unsigned long long)__double_as_longlong(m));
+            } else if (h >= 0 && dx > 0.0) {
+                atomicMax(seg_maxdx + h, (unsigned long long)__double_as_longlong(dx));
+            }
+        }
         for (int off = 32; off > 0; off >>= 1) dx = fmax(dx, __shfl_xor(dx, off, 64));
         if ((threadIdx.x & 63) == 0)
             atomicMax(maxdx_bits, (unsigned long long)__double_as_longlong(dx));
+    }
+}
+
+// Per-halo bookkeeping after an iteration (graph-safe: no memsets needed):
+// count the iteration of every active halo, retire halos whose max|dx| fell
+// below tol (or that reached max_iter), clear the maxima for the next
+// iteration, and publish [iterations launched, halos still active].
+__global__ void k_seg_finalize(int n_halo, double tol, int max_iter, int32_t* __restrict__ active,
+                               unsigned long long* __restrict__ maxdx, int32_t* __restrict__ iters,
+                               int32_t* __restrict__ state, unsigned long long* __restrict__ red)
+{
+    __shared__ int cnt[256];
+    int c = 0;
+    for (int h = threadIdx.x; h < n_halo; h += blockDim.x) {
+        if (active[h]) {
+            const int it = iters[h] + 1;
+            iters[h] = it;
+            const double d = __longlong_as_double((long long)maxdx[h]);
+            if (d < tol || it >= max_iter) active[h] = 0;
+            else ++c;
+        }
+        maxdx[h] = 0ull;
+    }
+    cnt[threadIdx.x] = c;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) cnt[threadIdx.x] += cnt[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        state[0] += 1;
+        state[1] = cnt[0];
+        red[0] = 0ull;
+        red[1] = 0ull;
+    }
+}
+
+__global__ void k_seg_init(int n_halo, int32_t* __restrict__ active,
+                           unsigned long long* __restrict__ maxdx, int32_t* __restrict__ iters,
+                           int32_t* __restrict__ state, unsigned long long* __restrict__ red)
+{
+    for (int h = threadIdx.x; h < n_halo; h += blockDim.x) {
+        active[h] = 1;
+        maxdx[h] = 0ull;
+        iters[h] = 0;
+    }
+    if (threadIdx.x == 0) {
+        state[0] = 0;
+        state[1] = n_halo;
+        red[0] = 0ull;
+        red[1] = 0ull;
     }
 }
 
@@ -166,7 +232,22 @@ hipError_t launch_gamma(Ctx& c, bool update_x)
     hipLaunchKernelGGL(k_gamma, dim3(nblk(c.n)), dim3(kBlock), 0, c.stream, c.N_s, c.n, c.n_ray,
                        c.n_bins, c.ws_rel, c.dsig_l2, c.sigma_min, c.ln_ws_max,
                        std::log(c.gamma_thin), c.lnG_s, c.G_s, c.tau_s, update_x ? 1 : 0, c.nH_s,
-                       c.mu_s, c.alpha_s, c.gcoll_s, c.x_s, c.mux_s, c.red);
+                       c.mu_s, c.alpha_s, c.gcoll_s, c.x_s, c.mux_s, c.red, c.geom.seg_of,
+                       c.geom.seg_active, c.geom.seg_active ? c.seg_maxdx : nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_seg_finalize(Ctx& c, double tol, int max_iter)
+{
+    hipLaunchKernelGGL(k_seg_finalize, dim3(1), dim3(256), 0, c.stream, c.n_halo, tol, max_iter,
+                       c.seg_active, c.seg_maxdx, c.seg_iters, c.seg_state, c.red);
+    return hipGetLastError();
+}
+
+hipError_t launch_seg_init(Ctx& c)
+{
+    hipLaunchKernelGGL(k_seg_init, dim3(1), dim3(256), 0, c.stream, c.n_halo, c.seg_active,
+                       c.seg_maxdx, c.seg_iters, c.seg_state, c.red);
     return hipGetLastError();
 }
 

@@ -53,9 +53,11 @@ void free_particles(Ctx& c)
                     c.mu0_s, c.nH0_s,
                     c.alpha_s, c.gcoll_s, c.x_s, c.mux_s, c.lnG_s, c.G_s, c.tau_s, c.N_s,
                     c.perm, c.codes, c.nodes, c.keys_b, c.vals_b, c.k_left, c.k_right,
-                    c.k_parent, c.k_first, c.k_last, c.k_lo, c.k_hi, c.k_cnt, c.k_dfs, c.k_flag};
+                    c.k_parent, c.k_first, c.k_last, c.k_lo, c.k_hi, c.k_cnt, c.k_dfs, c.k_flag,
+                    c.seg_of, c.k_seg};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
+    c.seg_of = c.k_seg = nullptr;
     void* adj[] = {c.xhist, c.adj_lam, c.adj_lup, c.adj_nu, c.adj_pis, c.adj_gnH, c.adj_y,
                    c.adj_wpart, c.adj_gw, c.adj_tpart};
     for (void* b : adj)
@@ -96,7 +98,7 @@ int alloc_particles(Ctx& c, int64_t n)
     A(c.mux_s, m) A(c.lnG_s, m) A(c.G_s, m) A(c.tau_s, m) A(c.perm, m) A(c.codes, m)
     A(c.nodes, 2 * m) A(c.keys_b, m) A(c.vals_b, m) A(c.k_left, mi) A(c.k_right, mi)
     A(c.k_parent, 2 * m) A(c.k_first, mi) A(c.k_last, mi) A(c.k_lo, 3 * mi) A(c.k_hi, 3 * mi)
-    A(c.k_cnt, mi) A(c.k_dfs, mi) A(c.k_flag, mi)
+    A(c.k_cnt, mi) A(c.k_dfs, mi) A(c.k_flag, mi) A(c.seg_of, m) A(c.k_seg, mi)
 #undef A
     if (e != hipSuccess) {
         free_particles(c);
@@ -150,8 +152,11 @@ void free_tpaths(Ctx& c)
     c.tpaths_unfit = false;
 }
 
+void drop_graph(Ctx& c);
+
 void free_paths(Ctx& c)
 {
+    drop_graph(c);
     free_tpaths(c);
     if (c.row_off) (void)hipFree(c.row_off);
     if (c.path) (void)hipFree(c.path);
@@ -161,6 +166,15 @@ void free_paths(Ctx& c)
     c.path_hits = 0;
     c.paths_valid = false;
     c.paths_unfit = false;
+}
+
+void drop_graph(Ctx& c)
+{
+    if (c.graph_exec) (void)hipGraphExecDestroy(c.graph_exec);
+    if (c.graph) (void)hipGraphDestroy(c.graph);
+    c.graph_exec = nullptr;
+    c.graph = nullptr;
+    c.graph_iters = 0;
 }
 
 // Count every ray's intersections, scan to row offsets, then record (tree index,
@@ -199,6 +213,7 @@ int record_paths(Ctx& c)
         HIP_OK(dalloc(&c.path, (size_t)std::max<uint64_t>(total, 1)));
         c.path_cap = std::max<uint64_t>(total, 1);
     }
+    drop_graph(c);
     HIP_OK(launch_record_paths(c, c.row_off, c.path, total));
     c.path_hits = (int64_t)total;
     c.paths_valid = true;
@@ -303,8 +318,14 @@ void rrt_destroy(rrt_ctx* x)
     else (void)hipDeviceSynchronize();
     free_particles(c);
     free_paths(c);
+    drop_graph(c);
+    if (c.gstream) (void)hipStreamDestroy(c.gstream);
+    if (c.ev_a) (void)hipEventDestroy(c.ev_a);
+    if (c.ev_b) (void)hipEventDestroy(c.ev_b);
     void* bufs[] = {c.tables, c.red, c.dirs, c.ws, c.dsig_l2, c.ws_rel, c.srat, c.hist,
-                    c.scan_tmp};
+                    c.scan_tmp, c.halo_off, c.seg_root, c.seg_end, c.seg_active, c.seg_maxdx,
+                    c.seg_iters, c.seg_state};
+    if (c.seg_state_host) (void)hipHostFree(c.seg_state_host);
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (c.red_host) (void)hipHostFree(c.red_host);
@@ -340,8 +361,38 @@ int rrt_set_particles(rrt_ctx* x, int64_t n, const float* pos, const float* h, c
                               c.stream));
     c.have_particles = true;
     c.have_tree = c.have_columns = c.have_gamma = false;
+    c.n_halo = 1;                 // rrt_set_halos may follow
+    c.halo_off_host.clear();
     free_paths(c);
     if (c.have_rays) return alloc_columns(c);
+    return RRT_OK;
+}
+
+int rrt_set_halos(rrt_ctx* x, int32_t n_halo, const int64_t* offsets)
+{
+    if (!x) return RRT_E_ARG;
+    Ctx& c = x->c;
+    if (!c.have_particles) return fail(c, RRT_E_STATE, "rrt_set_particles must come first");
+    if (n_halo < 1 || n_halo > 4096 || !offsets)
+        return fail(c, RRT_E_ARG, "n_halo must be 1..4096 with n_halo + 1 offsets");
+    if (offsets[0] != 0 || offsets[n_halo] != c.n)
+        return fail(c, RRT_E_ARG, "offsets must run from 0 to n");
+    for (int h = 0; h < n_halo; ++h)
+        if (offsets[h + 1] <= offsets[h])
+            return fail(c, RRT_E_ARG, "halo %d is empty or offsets decrease", h);
+    HIP_OK(dalloc(&c.halo_off, (size_t)n_halo + 1));
+    HIP_OK(dalloc(&c.seg_root, (size_t)n_halo));
+    HIP_OK(dalloc(&c.seg_end, (size_t)n_halo));
+    HIP_OK(dalloc(&c.seg_active, (size_t)n_halo));
+    HIP_OK(dalloc(&c.seg_maxdx, (size_t)n_halo));
+    HIP_OK(dalloc(&c.seg_iters, (size_t)n_halo));
+    if (!c.seg_state) HIP_OK(dalloc(&c.seg_state, 4));
+    if (!c.seg_state_host) HIP_OK(hipHostMalloc((void**)&c.seg_state_host, 4 * sizeof(int32_t)));
+    HIP_OK(hipMemcpy(c.halo_off, offsets, sizeof(int64_t) * (n_halo + 1), hipMemcpyHostToDevice));
+    c.halo_off_host.assign(offsets, offsets + n_halo + 1);
+    c.n_halo = n_halo;
+    c.have_tree = c.have_columns = c.have_gamma = false;
+    free_paths(c);
     return RRT_OK;
 }
 
@@ -449,6 +500,7 @@ int rrt_set_spectrum(rrt_ctx* x, int32_t n_bins, const double* sigma, const doub
     HIP_OK(hipMemcpyAsync(c.srat, srt.data(), sizeof(float) * m, hipMemcpyHostToDevice,
                           c.stream));
     HIP_OK(hipStreamSynchronize(c.stream));     // host vectors go out of scope
+    if (m != c.n_bins) drop_graph(c);
     c.n_bins = m;
     c.sigma_min = smin;
     c.ln_ws_max = std::log(wsmax);
@@ -498,11 +550,29 @@ int rrt_build_tree(rrt_ctx* x)
         ext = std::max(ext, (double)hi[a] - (double)lo[a]);
         maxabs = std::max({maxabs, std::fabs((double)lo[a]), std::fabs((double)hi[a])});
     }
-    const double scale = ext > 0.0 ? 2097152.0 / ext : 0.0;
+    // one halo: 21 bits per axis; several: the halo index takes the top bits
+    int hb = 0;
+    while ((1 << hb) < c.n_halo) ++hb;
+    c.key_bits = c.n_halo > 1 ? (63 - hb) / 3 : 21;
+    const double scale = ext > 0.0 ? (double)(1u << c.key_bits) / ext : 0.0;
     HIP_OK(hipMemsetAsync(c.red + 2, 0, sizeof(unsigned long long), c.stream));
-    HIP_OK(launch_morton(c, dlo, scale));
+    HIP_OK(launch_morton(c, dlo, scale, c.key_bits));
     HIP_OK(radix_sort_pairs(c, c.codes, c.perm, c.n));
+    if (c.n_halo > 1) {
+        std::vector<int32_t> neg(c.n_halo, -1);
+        HIP_OK(hipMemcpyAsync(c.seg_root, neg.data(), sizeof(int32_t) * c.n_halo,
+                              hipMemcpyHostToDevice, c.stream));
+    }
     HIP_OK(build_radix_tree(c));
+    if (c.n_halo > 1) {
+        std::vector<int32_t> roots(c.n_halo);
+        HIP_OK(hipMemcpyAsync(roots.data(), c.seg_root, sizeof(int32_t) * c.n_halo,
+                              hipMemcpyDeviceToHost, c.stream));
+        HIP_OK(hipStreamSynchronize(c.stream));
+        for (int h = 0; h < c.n_halo; ++h)
+            if (roots[h] < 0)
+                return fail(c, RRT_E_HIP, "halo %d has no subtree of its own", h);
+    }
     int32_t nn = 1;
     if (c.n > 1)
         HIP_OK(hipMemcpyAsync(&nn, c.k_dfs, sizeof(int32_t), hipMemcpyDeviceToHost, c.stream));
@@ -525,11 +595,17 @@ int rrt_build_tree(rrt_ctx* x)
     g.n = (int32_t)c.n;
     g.n_ray = c.n_ray;
     g.n_nodes = nn;
+    const bool segmented = c.n_halo > 1;
+    g.seg_of = segmented ? c.seg_of : nullptr;
+    g.seg_root = segmented ? c.seg_root : nullptr;
+    g.seg_end = segmented ? c.seg_end : nullptr;
+    g.seg_active = nullptr;
     HIP_OK(launch_init_state(c, c.x_init_given));
     if (c.timing) c.t_build += ev_end(c);
     c.paths_valid = false;       // new geometry: the recorded paths no longer apply
     c.paths_unfit = false;
     free_tpaths(c);
+    drop_graph(c);
     c.have_tree = true;
     c.have_columns = c.have_gamma = false;
     return RRT_OK;
@@ -746,6 +822,127 @@ int rrt_backward(rrt_ctx* x, const double* dL_dlnG, const double* dL_dx, double*
             dL_dw[b] = c.sigma_host[b] / c.ws_max * gw[b] + c.sigma_host[b] * thin;
     c.have_columns = c.have_gamma = false;
     return RRT_OK;
+}
+
+namespace {
+
+// halo bookkeeping buffers also for a single problem (one halo = whole tree)
+int ensure_seg_buffers(Ctx& c)
+{
+    if (c.n_halo == 1 && (!c.seg_root || !c.seg_active)) {
+        HIP_OK(dalloc(&c.seg_root, 1));
+        HIP_OK(dalloc(&c.seg_end, 1));
+        HIP_OK(dalloc(&c.seg_active, 1));
+        HIP_OK(dalloc(&c.seg_maxdx, 1));
+        HIP_OK(dalloc(&c.seg_iters, 1));
+        if (!c.seg_state) HIP_OK(dalloc(&c.seg_state, 4));
+        if (!c.seg_state_host)
+            HIP_OK(hipHostMalloc((void**)&c.seg_state_host, 4 * sizeof(int32_t)));
+    }
+    if (c.n_halo == 1) {
+        const int32_t zero = 0, nn = (int32_t)c.n_nodes;
+        HIP_OK(hipMemcpyAsync(c.seg_root, &zero, sizeof zero, hipMemcpyHostToDevice, c.stream));
+        HIP_OK(hipMemcpyAsync(c.seg_end, &nn, sizeof nn, hipMemcpyHostToDevice, c.stream));
+        HIP_OK(hipStreamSynchronize(c.stream));
+    }
+    if (!c.gstream) HIP_OK(hipStreamCreateWithFlags(&c.gstream, hipStreamNonBlocking));
+    if (!c.ev_a) HIP_OK(hipEventCreateWithFlags(&c.ev_a, hipEventDisableTiming));
+    if (!c.ev_b) HIP_OK(hipEventCreateWithFlags(&c.ev_b, hipEventDisableTiming));
+    return RRT_OK;
+}
+
+// one iteration of every active halo: columns, rate + equilibrium, bookkeeping
+int halo_iteration(Ctx& c, double tol, int max_iter)
+{
+    int64_t hits = -1;
+    if (int r = columns_impl(c, &hits)) return r;
+    HIP_OK(launch_gamma(c, true));
+    HIP_OK(launch_seg_finalize(c, tol, max_iter));
+    return RRT_OK;
+}
+
+struct SegGuard {
+    Ctx& c;
+    TraceGeom saved;
+    explicit SegGuard(Ctx& cc) : c(cc), saved(cc.geom)
+    {
+        c.geom.seg_of = c.seg_of;
+        c.geom.seg_root = c.seg_root;
+        c.geom.seg_end = c.seg_end;
+        c.geom.seg_active = c.seg_active;
+    }
+    ~SegGuard() { c.geom = saved; }
+};
+
+}  // namespace
+
+int rrt_iterate_halos(rrt_ctx* x, int32_t max_iter, double tol, int32_t per_launch, double* x_out,
+                      int32_t* halo_iters_out)
+{
+    if (!x) return RRT_E_ARG;
+    Ctx& c = x->c;
+    if (int r = need_tree(c)) return r;
+    if (max_iter < 1 || !(tol >= 0.0) || per_launch < 1 || per_launch > 256)
+        return fail(c, RRT_E_ARG, "max_iter >= 1, tol >= 0, per_launch 1..256");
+    if (int r = ensure_seg_buffers(c)) return r;
+    SegGuard guard(c);
+    const bool timing = c.timing;
+    HIP_OK(launch_seg_init(c));
+    // the first iteration runs eagerly: it may record the ray paths
+    if (int r = halo_iteration(c, tol, max_iter)) return r;
+    HIP_OK(hipMemcpyAsync(c.seg_state_host, c.seg_state, 2 * sizeof(int32_t),
+                          hipMemcpyDeviceToHost, c.stream));
+    HIP_OK(hipStreamSynchronize(c.stream));
+    if (c.seg_state_host[1] > 0) {
+        if (!c.graph_exec || c.graph_iters != per_launch || c.graph_tol != tol ||
+            c.graph_max_iter != max_iter) {
+            drop_graph(c);
+            hipStream_t user = c.stream;
+            c.stream = c.gstream;
+            c.timing = false;
+            hipError_t e = hipStreamBeginCapture(c.gstream, hipStreamCaptureModeThreadLocal);
+            int r = RRT_OK;
+            for (int k = 0; k < per_launch && e == hipSuccess && r == RRT_OK; ++k)
+                r = halo_iteration(c, tol, max_iter);
+            hipGraph_t gr = nullptr;
+            hipError_t e2 = hipStreamEndCapture(c.gstream, &gr);
+            c.stream = user;
+            c.timing = timing;
+            if (r != RRT_OK) {
+                if (gr) (void)hipGraphDestroy(gr);
+                return r;
+            }
+            HIP_OK(e);
+            HIP_OK(e2);
+            c.graph = gr;
+            HIP_OK(hipGraphInstantiate(&c.graph_exec, c.graph, nullptr, nullptr, 0));
+            c.graph_iters = per_launch;
+            c.graph_tol = tol;
+            c.graph_max_iter = max_iter;
+        }
+        HIP_OK(hipEventRecord(c.ev_a, c.stream));
+        HIP_OK(hipStreamWaitEvent(c.gstream, c.ev_a, 0));
+        while (c.seg_state_host[1] > 0 && c.seg_state_host[0] < max_iter) {
+            HIP_OK(hipGraphLaunch(c.graph_exec, c.gstream));
+            HIP_OK(hipMemcpyAsync(c.seg_state_host, c.seg_state, 2 * sizeof(int32_t),
+                                  hipMemcpyDeviceToHost, c.gstream));
+            HIP_OK(hipStreamSynchronize(c.gstream));
+        }
+        HIP_OK(hipEventRecord(c.ev_b, c.gstream));
+        HIP_OK(hipStreamWaitEvent(c.stream, c.ev_b, 0));
+    }
+    std::vector<int32_t> its(c.n_halo);
+    HIP_OK(hipMemcpyAsync(its.data(), c.seg_iters, sizeof(int32_t) * c.n_halo,
+                          hipMemcpyDeviceToHost, c.stream));
+    if (x_out) HIP_OK(launch_to_input_order_d(c, c.x_s, x_out, 1));
+    HIP_OK(hipStreamSynchronize(c.stream));
+    c.have_columns = c.have_gamma = false;
+    bool capped = false;
+    for (int h = 0; h < c.n_halo; ++h) {
+        if (halo_iters_out) halo_iters_out[h] = its[h];
+        capped = capped || its[h] >= max_iter;
+    }
+    return capped ? RRT_NOT_CONVERGED : RRT_OK;
 }
 
 int rrt_set_state(rrt_ctx* x, const double* xs)

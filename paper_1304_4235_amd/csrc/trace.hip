@@ -166,6 +166,16 @@ k_trace(const Node* __restrict__ nodes, const float4* __restrict__ p4,
         uint64_t w = (MODE == kModeRecord || MODE == kModePath) ? out.row_off[gid] : 0;
         const double nur = (MODE == kModeScatter) ? out.nu[gid] : 0.0;
 
+        // the subtree this ray's halo owns (the whole tree for one problem)
+        int root = 0, end = g.n_nodes;
+        bool live = true;
+        if (g.seg_root) {
+            const int h = g.seg_of[ps];
+            root = g.seg_root[h];
+            end = g.seg_end[h];
+            live = !g.seg_active || g.seg_active[h] != 0;
+        }
+        if (!live) lo[0] = 1, hi[0] = 0;            // no image loop at all
         for (int sx = lo[0]; sx <= hi[0]; ++sx)
         for (int sy = lo[1]; sy <= hi[1]; ++sy)
         for (int sz = lo[2]; sz <= hi[2]; ++sz) {
@@ -179,8 +189,8 @@ k_trace(const Node* __restrict__ nodes, const float4* __restrict__ p4,
                 oai[a] = (float)(o + (double)g.pad) * inv[a];
                 obi[a] = (float)(o - (double)g.pad) * inv[a];
             }
-            int node = 0;
-            while (node < g.n_nodes) {
+            int node = root;
+            while (node < end) {
                 const Node nd = nodes[node];
                 float tx0 = fmaf(nd.a.x, inv[0], -oai[0]), tx1 = fmaf(nd.b.x, inv[0], -obi[0]);
                 float ty0 = fmaf(nd.a.y, inv[1], -oai[1]), ty1 = fmaf(nd.b.y, inv[1], -obi[1]);
@@ -256,7 +266,7 @@ k_trace(const Node* __restrict__ nodes, const float4* __restrict__ p4,
                 node = max(skip, node + 1);
             }
         }
-        if (MODE == kModeColumn || MODE == kModeRecord) out.N[(int64_t)k * g.n + ps] = acc;
+        if ((MODE == kModeColumn || MODE == kModeRecord) && live) out.N[(int64_t)k * g.n + ps] = acc;
         if (MODE == kModeCount) out.row_cnt[gid] = cnt;
     }
     // one atomic per wave for the total intersection count
@@ -330,10 +340,26 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
     uint64_t w = ((MODE == kModeRecord || MODE == kModePath) && active) ? out.row_off[gid] : 0;
     const double nur = (MODE == kModeScatter && active) ? out.nu[gid] : 0.0;
 
+    // lanes of one wave can belong to two halos (at a halo boundary in tree
+    // order): walk each halo's subtree in turn with that halo's lanes
+    int root = 0, end = g.n_nodes;
+    bool live = active;
+    if (g.seg_root && active) {
+        const int h = g.seg_of[ps];
+        root = g.seg_root[h];
+        end = g.seg_end[h];
+        live = !g.seg_active || g.seg_active[h] != 0;
+    }
+    uint64_t pending = __ballot(live);
+    while (pending) {
+    const int leader = __ffsll((unsigned long long)pending) - 1;
+    const int sroot = __shfl(root, leader, 64), send = __shfl(end, leader, 64);
+    const bool in_seg = live && root == sroot;
+    pending &= ~__ballot(in_seg);
     for (int sx = ulo[0]; sx <= uhi[0]; ++sx)
     for (int sy = ulo[1]; sy <= uhi[1]; ++sy)
     for (int sz = ulo[2]; sz <= uhi[2]; ++sz) {
-        const bool mine = active && sx >= lo[0] && sx <= hi[0] && sy >= lo[1] && sy <= hi[1] &&
+        const bool mine = in_seg && sx >= lo[0] && sx <= hi[0] && sy >= lo[1] && sy <= hi[1] &&
                           sz >= lo[2] && sz <= hi[2];
         if (__ballot(mine) == 0) continue;
         double sh[3] = {(double)sx * B, (double)sy * B, (double)sz * B};
@@ -344,8 +370,8 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
             oai[a] = (float)(o + (double)g.pad) * inv[a];
             obi[a] = (float)(o - (double)g.pad) * inv[a];
         }
-        int node = 0;
-        while (node < g.n_nodes) {
+        int node = sroot;
+        while (node < send) {
             const Node nd = nodes[node];
             const int skip = __float_as_int(nd.a.w);
             const int leafw = __float_as_int(nd.b.w);
@@ -421,8 +447,9 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
             node = max(skip, node + 1);
         }
     }
+    }   // halos of this wave
     if (active) {
-        if (MODE == kModeColumn || MODE == kModeRecord) out.N[gid] = acc;
+        if ((MODE == kModeColumn || MODE == kModeRecord) && live) out.N[gid] = acc;
         if (MODE == kModeCount) out.row_cnt[gid] = cnt;
     }
     uint64_t c64 = cnt;
@@ -480,12 +507,15 @@ static hipError_t launch_mode(Ctx& c, int mode, RayOut o)
 template <int G>
 __global__ void __launch_bounds__(256)
 k_path_columns(const uint64_t* __restrict__ row_off, const int2* __restrict__ path,
-               const float* __restrict__ mux, int64_t n_rows, double* __restrict__ N)
+               const float* __restrict__ mux, int64_t n_rows, double* __restrict__ N, int64_t n,
+               const int32_t* __restrict__ seg_of, const int32_t* __restrict__ seg_active)
 {
     const int64_t row = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G;
     const int lane = threadIdx.x & (G - 1);
     double acc = 0.0;
-    if (row < n_rows) {
+    // rows of halos that have stopped iterating keep their last columns
+    const bool live = row < n_rows && !(seg_active && seg_active[seg_of[row % n]] == 0);
+    if (live) {
         const uint64_t a = row_off[row], b = row_off[row + 1];
         const long long* p = reinterpret_cast<const long long*>(path);
         // four independent streaming loads in flight per lane before any is used;
@@ -504,7 +534,7 @@ k_path_columns(const uint64_t* __restrict__ row_off, const int2* __restrict__ pa
         }
     }
     for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
-    if (row < n_rows && lane == 0) N[row] = acc;
+    if (live && lane == 0) N[row] = acc;
 }
 
 hipError_t launch_columns(Ctx& c)
@@ -567,16 +597,16 @@ hipError_t launch_path_columns(Ctx& c, int group)
     const unsigned nb = (unsigned)((n_rows * group + bs - 1) / bs);
     if (group == 64)
         hipLaunchKernelGGL(k_path_columns<64>, dim3(nb), dim3(bs), 0, c.stream, c.row_off, c.path,
-                           c.mux_s, n_rows, c.N_s);
+                           c.mux_s, n_rows, c.N_s, c.n, c.geom.seg_of, c.geom.seg_active);
     else if (group == 32)
         hipLaunchKernelGGL(k_path_columns<32>, dim3(nb), dim3(bs), 0, c.stream, c.row_off, c.path,
-                           c.mux_s, n_rows, c.N_s);
+                           c.mux_s, n_rows, c.N_s, c.n, c.geom.seg_of, c.geom.seg_active);
     else if (group == 16)
         hipLaunchKernelGGL(k_path_columns<16>, dim3(nb), dim3(bs), 0, c.stream, c.row_off, c.path,
-                           c.mux_s, n_rows, c.N_s);
+                           c.mux_s, n_rows, c.N_s, c.n, c.geom.seg_of, c.geom.seg_active);
     else
         hipLaunchKernelGGL(k_path_columns<8>, dim3(nb), dim3(bs), 0, c.stream, c.row_off, c.path,
-                           c.mux_s, n_rows, c.N_s);
+                           c.mux_s, n_rows, c.N_s, c.n, c.geom.seg_of, c.geom.seg_active);
     return hipGetLastError();
 }
 

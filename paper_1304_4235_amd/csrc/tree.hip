@@ -69,22 +69,42 @@ __device__ __forceinline__ uint64_t spread3(uint64_t v)
     return v;
 }
 
+// Key = (halo << 3*bits) | Morton code with `bits` bits per axis.  A single
+// halo uses 21 bits per axis and no halo field.
 __global__ void k_morton(const float* __restrict__ pos, int64_t n, double lo0, double lo1,
-                         double lo2, double scale, uint64_t* __restrict__ keys,
-                         int32_t* __restrict__ vals)
+                         double lo2, double scale, int bits, const int64_t* __restrict__ halo_off,
+                         int n_halo, uint64_t* __restrict__ keys, int32_t* __restrict__ vals)
 {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     double lo[3] = {lo0, lo1, lo2};
+    const double qmax = (double)((1u << bits) - 1u);
     uint64_t q[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         double v = floor(((double)pos[3 * i + a] - lo[a]) * scale);
-        v = v < 0.0 ? 0.0 : (v > 2097151.0 ? 2097151.0 : v);
+        v = v < 0.0 ? 0.0 : (v > qmax ? qmax : v);
         q[a] = (uint64_t)v;
     }
-    keys[i] = (spread3(q[0]) << 2) | (spread3(q[1]) << 1) | spread3(q[2]);
+    uint64_t key = (spread3(q[0]) << 2) | (spread3(q[1]) << 1) | spread3(q[2]);
+    if (n_halo > 1) {
+        int a = 0, b = n_halo;                    // halo_off[a] <= i < halo_off[b]
+        while (b - a > 1) {
+            int m = (a + b) >> 1;
+            if (halo_off[m] <= i) a = m;
+            else b = m;
+        }
+        key |= (uint64_t)a << (3 * bits);
+    }
+    keys[i] = key;
     vals[i] = (int32_t)i;
+}
+
+__global__ void k_seg_of(const uint64_t* __restrict__ keys, int64_t n, int shift,
+                         int32_t* __restrict__ seg)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) seg[i] = shift >= 64 ? 0 : (int32_t)(keys[i] >> shift);
 }
 
 // ---------------------------------------------------------------------------
@@ -327,12 +347,14 @@ __device__ __forceinline__ void st_i(int32_t* p, int v)
 
 struct ChildInfo {
     float lo[3], hi[3];
-    int cnt, dfs;
+    int cnt, dfs, seg;
 };
 
 __device__ __forceinline__ ChildInfo child_info(int c, const float4* __restrict__ p4,
                                                 const float* klo, const float* khi,
-                                                const int32_t* kcnt, const int32_t* kdfs)
+                                                const int32_t* kcnt, const int32_t* kdfs,
+                                                const int32_t* kseg,
+                                                const int32_t* __restrict__ seg_of)
 {
     ChildInfo r;
     if (c < 0) {
@@ -341,6 +363,7 @@ __device__ __forceinline__ ChildInfo child_info(int c, const float4* __restrict_
         r.hi[0] = p.x + p.w; r.hi[1] = p.y + p.w; r.hi[2] = p.z + p.w;
         r.cnt = 1;
         r.dfs = 1;
+        r.seg = seg_of[~c];
     } else {
         for (int a = 0; a < 3; ++a) {
             r.lo[a] = ld_f(klo + 3 * c + a);
@@ -348,15 +371,24 @@ __device__ __forceinline__ ChildInfo child_info(int c, const float4* __restrict_
         }
         r.cnt = ld_i(kcnt + c);
         r.dfs = ld_i(kdfs + c);
+        r.seg = ld_i(kseg + c);
     }
     return r;
+}
+
+// A subtree becomes one leaf when it holds at most leaf_max particles, all of
+// one halo (so no leaf ever mixes independent problems).
+__device__ __forceinline__ bool collapses(int cnt, int seg, int leaf_max)
+{
+    return cnt <= leaf_max && seg >= 0;
 }
 
 // Bottom-up: the second thread to reach a node combines both children.
 __global__ void k_refit(const float4* __restrict__ p4, int n, int leaf_max,
                         const int32_t* __restrict__ left, const int32_t* __restrict__ right,
                         const int32_t* __restrict__ parent, float* klo, float* khi,
-                        int32_t* kcnt, int32_t* kdfs, int32_t* flag,
+                        int32_t* kcnt, int32_t* kdfs, int32_t* kseg,
+                        const int32_t* __restrict__ seg_of, int32_t* flag,
                         unsigned long long* err)
 {
     int y = blockIdx.x * blockDim.x + threadIdx.x;
@@ -372,15 +404,17 @@ __global__ void k_refit(const float4* __restrict__ p4, int n, int leaf_max,
         int old = atomicAdd(&flag[node], 1);
         if (old == 0) return;
         __threadfence();
-        ChildInfo L = child_info(left[node], p4, klo, khi, kcnt, kdfs);
-        ChildInfo R = child_info(right[node], p4, klo, khi, kcnt, kdfs);
+        ChildInfo L = child_info(left[node], p4, klo, khi, kcnt, kdfs, kseg, seg_of);
+        ChildInfo R = child_info(right[node], p4, klo, khi, kcnt, kdfs, kseg, seg_of);
         for (int a = 0; a < 3; ++a) {
             st_f(klo + 3 * node + a, L.lo[a] < R.lo[a] ? L.lo[a] : R.lo[a]);
             st_f(khi + 3 * node + a, L.hi[a] > R.hi[a] ? L.hi[a] : R.hi[a]);
         }
         int cnt = L.cnt + R.cnt;
+        int seg = (L.seg == R.seg) ? L.seg : -1;
         st_i(kcnt + node, cnt);
-        st_i(kdfs + node, cnt <= leaf_max ? 1 : 1 + L.dfs + R.dfs);
+        st_i(kseg + node, seg);
+        st_i(kdfs + node, collapses(cnt, seg, leaf_max) ? 1 : 1 + L.dfs + R.dfs);
         if (node == 0) return;
         node = parent[node];
     }
@@ -394,6 +428,9 @@ __global__ void k_layout(const float4* __restrict__ p4, int n, int leaf_max,
                          const int32_t* __restrict__ parent, const int32_t* __restrict__ first,
                          const float* __restrict__ klo, const float* __restrict__ khi,
                          const int32_t* __restrict__ kcnt, const int32_t* __restrict__ kdfs,
+                         const int32_t* __restrict__ kseg, const int32_t* __restrict__ klast,
+                         const int32_t* __restrict__ seg_of, const int64_t* __restrict__ halo_off,
+                         int32_t* __restrict__ seg_root, int32_t* __restrict__ seg_end,
                          Node* __restrict__ nodes, unsigned long long* err)
 {
     int v = blockIdx.x * blockDim.x + threadIdx.x;
@@ -404,7 +441,7 @@ __global__ void k_layout(const float4* __restrict__ p4, int n, int leaf_max,
     int self_code = is_leaf ? ~y : v;
     if (n > 1 && v != 0) {
         int p = parent[v];
-        if (kcnt[p] <= leaf_max) return;          // inside a collapsed leaf
+        if (collapses(kcnt[p], kseg[p], leaf_max)) return;   // inside a collapsed leaf
     }
     int idx = 0;
     int cv = v, code = self_code;
@@ -424,22 +461,28 @@ __global__ void k_layout(const float4* __restrict__ p4, int n, int leaf_max,
         code = p;
     }
     Node nd;
-    int cnt, dfs, f;
+    int cnt, dfs, f, la, seg;
     float lo[3], hi[3];
     if (is_leaf) {
         float4 q = p4[y];
         lo[0] = q.x - q.w; lo[1] = q.y - q.w; lo[2] = q.z - q.w;
         hi[0] = q.x + q.w; hi[1] = q.y + q.w; hi[2] = q.z + q.w;
-        cnt = 1; dfs = 1; f = y;
+        cnt = 1; dfs = 1; f = y; la = y; seg = seg_of[y];
     } else {
         for (int a = 0; a < 3; ++a) { lo[a] = klo[3 * v + a]; hi[a] = khi[3 * v + a]; }
-        cnt = kcnt[v]; dfs = kdfs[v]; f = first[v];
+        cnt = kcnt[v]; dfs = kdfs[v]; f = first[v]; la = klast[v]; seg = kseg[v];
     }
-    if (idx < 0 || idx + dfs > total || f < 0 || f + (cnt <= leaf_max ? cnt : 0) > n) {
+    const bool leafy = collapses(cnt, seg, leaf_max);
+    if (idx < 0 || idx + dfs > total || f < 0 || f + (leafy ? cnt : 0) > n) {
         atomicOr(err, 4ull);
         return;
     }
-    int leafw = cnt <= leaf_max ? ((f << 3) | (cnt - 1)) : -1;
+    // the subtree of exactly one halo: where that halo's rays walk
+    if (seg >= 0 && halo_off && f == (int)halo_off[seg] && la == (int)halo_off[seg + 1] - 1) {
+        seg_root[seg] = idx;
+        seg_end[seg] = idx + dfs;
+    }
+    int leafw = leafy ? ((f << 3) | (cnt - 1)) : -1;
     nd.a = make_float4(lo[0], lo[1], lo[2], __int_as_float(idx + dfs));
     nd.b = make_float4(hi[0], hi[1], hi[2], __int_as_float(leafw));
     nodes[idx] = nd;
@@ -478,10 +521,10 @@ hipError_t launch_bounds(Ctx& c, float* part_out, int nb)
     return hipGetLastError();
 }
 
-hipError_t launch_morton(Ctx& c, const double lo[3], double scale)
+hipError_t launch_morton(Ctx& c, const double lo[3], double scale, int bits)
 {
     hipLaunchKernelGGL(k_morton, dim3(nblk(c.n)), dim3(kBlock), 0, c.stream, c.pos_in, c.n,
-                       lo[0], lo[1], lo[2], scale, c.codes, c.perm);
+                       lo[0], lo[1], lo[2], scale, bits, c.halo_off, c.n_halo, c.codes, c.perm);
     return hipGetLastError();
 }
 
@@ -529,6 +572,9 @@ hipError_t build_radix_tree(Ctx& c)
                        c.pos_in, c.h_in, c.mu_in, c.nH_in, (int64_t)n, c.p4, c.mu_s, c.mu0_s,
                        c.nH0_s, c.nH_s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_seg_of, dim3(nblk(n)), dim3(kBlock), 0, c.stream, c.codes, (int64_t)n,
+                       c.n_halo > 1 ? 3 * c.key_bits : 64, c.seg_of);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     if (n > 1) {
         hipLaunchKernelGGL(k_radix_tree, dim3(nblk(n - 1)), dim3(kBlock), 0, c.stream, c.codes, n,
                            c.k_left, c.k_right, c.k_parent, c.k_first, c.k_last);
@@ -537,12 +583,13 @@ hipError_t build_radix_tree(Ctx& c)
             return e;
         hipLaunchKernelGGL(k_refit, dim3(nblk(n)), dim3(kBlock), 0, c.stream, c.p4, n, c.leaf,
                            c.k_left, c.k_right, c.k_parent, c.k_lo, c.k_hi, c.k_cnt, c.k_dfs,
-                           c.k_flag, c.red + 2);
+                           c.k_seg, c.seg_of, c.k_flag, c.red + 2);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_layout, dim3(nblk(2 * n - 1)), dim3(kBlock), 0, c.stream, c.p4, n, c.leaf,
                        c.k_left, c.k_right, c.k_parent, c.k_first, c.k_lo, c.k_hi, c.k_cnt,
-                       c.k_dfs, c.nodes, c.red + 2);
+                       c.k_dfs, c.k_seg, c.k_last, c.seg_of, c.n_halo > 1 ? c.halo_off : nullptr,
+                       c.seg_root, c.seg_end, c.nodes, c.red + 2);
     return hipGetLastError();
 }
 

@@ -59,6 +59,8 @@ SIGNATURES = {
     "rrt_reset_timing": ([_vp], C.c_int),
     "rrt_get_counters": ([_vp, _vp], C.c_int),
     "rrt_set_density": ([_vp, _vp], C.c_int),
+    "rrt_set_halos": ([_vp, _i32, _vp], C.c_int),
+    "rrt_iterate_halos": ([_vp, _i32, _d, _i32, _vp, _vp], C.c_int),
     "rrt_forward": ([_vp, _i32, _vp, _vp], C.c_int),
     "rrt_backward": ([_vp, _vp, _vp, _vp, _vp], C.c_int),
 }
@@ -163,6 +165,19 @@ class Solver:
                                            _ptr(T), _ptr(xi)), "rrt_set_particles")
         self._keep = [pos, h, mu, nH, T, xi]      # copied by the library; kept until synced
         self.n = n
+        self.n_halo = 1
+
+    def set_halos(self, offsets):
+        off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+        self._check(_lib.rrt_set_halos(self._h, off.size - 1, off.ctypes.data), "rrt_set_halos")
+        self.n_halo = off.size - 1
+
+    def iterate_halos(self, max_iter: int, tol: float, per_launch: int = 8, want_x: bool = True):
+        x = torch.empty(self.n, dtype=torch.float64, device=self.device) if want_x else None
+        its = np.zeros(getattr(self, "n_halo", 1), np.int32)
+        rc = self._check(_lib.rrt_iterate_halos(self._h, int(max_iter), float(tol), int(per_launch),
+                                                _ptr(x), its.ctypes.data), "rrt_iterate_halos")
+        return dict(x=x, halo_iters=its, converged=(rc == RRT_OK))
 
     def set_rays(self, dirs):
         d = np.ascontiguousarray(np.asarray(dirs, dtype=np.float64).reshape(-1, 3))
@@ -311,6 +326,8 @@ class Solver:
                 record_paths=record_paths, path_budget=path_budget, traversal=traversal,
                 device=device)
         s.set_particles(wl.pos, wl.h, wl.mu, wl.n_H, wl.T, x_init=x_init)
+        if getattr(wl, "halo_offsets", None) is not None:
+            s.set_halos(wl.halo_offsets)
         s.set_rays(wl.dirs)
         s.set_spectrum(wl.sigma, wl.w)
         if build:

@@ -156,6 +156,13 @@ def smoothing_lengths(pos: np.ndarray, n_ngb: int = 48, box: float = 0.0) -> np.
     """
     from scipy.spatial import cKDTree
     p = np.asarray(pos, dtype=np.float64)
+    if p.shape[0] < n_ngb + 2:
+        # too few particles for the neighbour rule: the largest separation, or
+        # 1 kpc for a lone particle
+        if p.shape[0] < 2:
+            return np.ones(p.shape[0])
+        d = np.sqrt(((p[:, None, :] - p[None, :, :]) ** 2).sum(-1))
+        return np.maximum(d.max(1), 1e-3)
     if box > 0:
         tree = cKDTree(np.mod(p, box), boxsize=box)
         d, _ = tree.query(np.mod(p, box), k=n_ngb + 2, workers=-1)
