@@ -53,6 +53,25 @@ def make_workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_isothermal_halo_262144.json")
+KERNEL_COUNTER_NAMES = {"recorded_paths": "rrt::k_path_columns<64>", "traversal": None}
+
+
+def measured_traffic(workload: str, kernel_key: str):
+    """HBM bytes per launch from the committed counter summary, only while the
+    kernel source is the one the counters were taken with (else None)."""
+    import hashlib
+    if workload != "isothermal_halo_262144" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    d = json.load(open(TRAFFIC_FILE))
+    src = os.path.join(ROOT, d["source"])
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != d["source_sha256"]:
+        return None
+    name = KERNEL_COUNTER_NAMES.get(kernel_key)
+    k = d["kernels"].get(name) if name else None
+    return None if k is None else k["fetch_bytes"] + k["write_bytes"]
+
+
 def cpu_baseline(wl, x, budget_s: float = 12.0):
     """The oracle on a bounded sample of sources, scaled to intersections/s."""
     import oracle
@@ -95,6 +114,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--adjoint", type=int, default=1,
                     help="also time forward+adjoint against the plain forward (1 = yes)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a 1 GiB device-to-device copy (traffic counter reference)")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--leaf", type=int, default=0)
     ap.add_argument("--traversal", type=int, default=0, help="0 wave-cooperative, 1 per lane")
@@ -109,6 +130,15 @@ def main():
     import torch
     from paper_1304_4235_amd import Solver
     import oracle
+
+    if args.calibrate_copy:
+        # a plain device copy of known size: reference for the traffic counters
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)   # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     wl = make_workload(args.workload)
     print(f"workload {wl.name}: n={wl.n} rays={wl.n_ray} bins={wl.n_bins} "
@@ -192,7 +222,10 @@ def main():
                               "tree_build": tm["build_ms"] / args.steps},
         "roofline": {"bound": "hbm", "kernel": kernels[dom]["kernel"],
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(args.workload, dom),
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                                     "copy-calibrated)",
                      "avg_launch_ms": avg_trace_ms,
                      "algorithmic_bytes_per_launch": alg_bytes},
         "kernels": kernels,
