@@ -48,6 +48,10 @@ def make_workload(name: str):
         return W.make_config(0)
     if name == "lognormal_field_2097152":
         return W.make_config(2)
+    if name == "halo_batch_64":
+        return W.make_config(3)
+    if name == "halo_batch_64_small":
+        return W.halo_batch(n_lo=2048, n_hi=32768, name="halo_batch_64_small")
     if name.startswith("isothermal_halo_"):
         return W.isothermal_halo(n=int(name.rsplit("_", 1)[1]))
     raise SystemExit(f"unknown workload {name}")
@@ -105,6 +109,59 @@ def cpu_baseline(wl, x, budget_s: float = 12.0):
                       f"optically thin state; {hits} intersections in {t_used:.1f} s on {cpu}"}
 
 
+def bench_batch(args):
+    """Many independent halos: one batched solve (graph-replayed iterations with
+    per-halo convergence) against one solve per halo, each from its own tree."""
+    import torch
+    from paper_1304_4235_amd import Solver, autotune
+    wl = make_workload(args.workload)
+    n_halo = len(wl.halo_offsets) - 1
+    print(f"workload {wl.name}: {n_halo} halos, n={wl.n}", file=sys.stderr, flush=True)
+    tuned = autotune.tune(wl, verbose=True, reps=2) if args.tune else None
+    best = tuned["best"] if tuned else {}
+    s = Solver.from_workload(wl, build=False)
+    if best:
+        autotune.apply(s, best)
+    per = best.get("per_launch", 8)
+
+    def batched():
+        s.build_tree()
+        return s.iterate_halos(wl.max_iter, wl.tol, per_launch=per, want_x=False)
+
+    for _ in range(args.warmup):
+        batched()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r = batched()
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / args.steps
+    its = r["halo_iters"]
+    print(f"batched: {t_batch * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    # sequential: one solver per halo, data already on the GPU, same knobs
+    subs = []
+    for h in range(n_halo):
+        sh = Solver.from_workload(wl.subset_halo(h), build=False)
+        if best:
+            autotune.apply(sh, best)
+        subs.append(sh)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seq_iters = []
+    for sh in subs:
+        sh.build_tree()
+        seq_iters.append(sh.iterate(wl.max_iter, wl.tol, want_x=False)["iters"])
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    out = {"metric": "batched halo solve time vs sequential solves", "unit": "ms",
+           "workload": wl.name, "halos": n_halo, "particles": wl.n,
+           "batched_ms": t_batch * 1e3, "sequential_ms": t_seq * 1e3,
+           "speedup": t_seq / t_batch, "iterations_per_halo": its.tolist(),
+           "same_iterations_as_sequential": bool(list(its) == seq_iters),
+           "tuned": best or None}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,6 +173,7 @@ def main():
                     help="also time forward+adjoint against the plain forward (1 = yes)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a 1 GiB device-to-device copy (traffic counter reference)")
+    ap.add_argument("--tune", type=int, default=1, help="autotune launch knobs (batched mode)")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--leaf", type=int, default=0)
     ap.add_argument("--traversal", type=int, default=0, help="0 wave-cooperative, 1 per lane")
@@ -126,6 +184,9 @@ def main():
         print(f"bench.py measures one GPU only: this build has no multi-GPU path "
               f"(asked for --gpus {args.gpus})", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload.startswith("halo_batch"):
+        return bench_batch(args)
 
     import torch
     from paper_1304_4235_amd import Solver

@@ -67,7 +67,8 @@ typedef struct {
     int64_t path_budget;   /* bytes the recorded ray paths may take; 0 = half of the
                               free device memory at the time of recording           */
     int32_t leaf_size;     /* max particles per tree leaf, 1..8 (0 = default 8)     */
-    int32_t block_size;    /* threads per block of the traversal (0 = default 256)  */
+    int32_t block_size;    /* threads per block of the traversal: 0 (= 128) or a
+                              multiple of 64 up to 256                               */
     int32_t record_paths;  /* -1 = record when within path_budget (default),
                               0 = traverse every iteration, 1 = require recording   */
     int32_t traversal;     /* 0 = wave-cooperative walk (default), 1 = one
@@ -204,6 +205,16 @@ int rrt_backward(rrt_ctx* ctx, const double* dL_dlnG, const double* dL_dx, doubl
  * reached max_iter.  Works with one halo too. */
 int rrt_iterate_halos(rrt_ctx* ctx, int32_t max_iter, double tol, int32_t per_launch,
                       double* x_out, int32_t* halo_iters_out);
+
+/* Launch knobs for the autotuner (results never change, only speed):
+ *   RRT_TUNE_TRACE_BLOCK  threads per block of the traversal (64, 128, 192, 256)
+ *   RRT_TUNE_PACKET       rays walking one node sequence: 64 (a wave-cooperative
+ *                         packet, default) or 1 (independent lanes)
+ *   RRT_TUNE_PATH_GROUP   lanes per ray in the recorded-path product: 8, 16, 32,
+ *                         64, or 0 = chosen from the mean intersections per ray
+ *   RRT_TUNE_LEAF         particles per tree leaf (1..8), from the next build */
+enum { RRT_TUNE_TRACE_BLOCK = 1, RRT_TUNE_PACKET = 2, RRT_TUNE_PATH_GROUP = 3, RRT_TUNE_LEAF = 4 };
+int rrt_set_tuning(rrt_ctx* ctx, int32_t key, int32_t value);
 
 /* Replace the state: x device double[n] in input order (checkpoint / resume,
  * or a given iterate); NULL resets to x_thin. */

@@ -182,6 +182,8 @@ struct Ctx {
     double graph_tol = -1.0;
     hipEvent_t ev_a = nullptr, ev_b = nullptr;
 
+    int32_t path_group = 0;       // lanes per ray in the path product (0 = automatic)
+
     // counters: intersections of the last iteration and since the last reset
     int64_t last_hits = 0, total_hits = 0;
 

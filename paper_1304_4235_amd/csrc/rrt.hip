@@ -233,7 +233,8 @@ int columns_impl(Ctx& c, int64_t* hits)
     if (c.paths_valid) {
         const int64_t n_rows = c.n * (int64_t)c.n_ray;
         const double mean = (double)c.path_hits / (double)std::max<int64_t>(n_rows, 1);
-        const int group = mean >= 96 ? 64 : mean >= 40 ? 32 : mean >= 16 ? 16 : 8;
+        const int group = c.path_group ? c.path_group
+                          : mean >= 96 ? 64 : mean >= 40 ? 32 : mean >= 16 ? 16 : 8;
         ev_begin(c);
         HIP_OK(launch_path_columns(c, group));
         if (c.timing) {
@@ -268,11 +269,11 @@ int rrt_create(rrt_ctx** out, const rrt_params* params, void* stream)
     *out = nullptr;
     if (!(params->l_ray >= 0.0) || !std::isfinite(params->l_ray) || !(params->box >= 0.0) ||
         !std::isfinite(params->box) || params->leaf_size < 0 || params->leaf_size > 8 ||
-        params->block_size < 0 || params->block_size > 1024 || (params->block_size % 64) != 0 ||
+        params->block_size < 0 || params->block_size > 256 || (params->block_size % 64) != 0 ||
         params->record_paths < -1 || params->record_paths > 1 || params->path_budget < 0 ||
         params->traversal < 0 || params->traversal > 1) {
         g_create_err = "rrt_create: invalid params (l_ray >= 0, box >= 0, leaf_size 0..8, "
-                       "block_size a multiple of 64 up to 1024, record_paths -1..1, "
+                       "block_size a multiple of 64 up to 256, record_paths -1..1, "
                        "path_budget >= 0, traversal 0..1)";
         return RRT_E_ARG;
     }
@@ -943,6 +944,38 @@ int rrt_iterate_halos(rrt_ctx* x, int32_t max_iter, double tol, int32_t per_laun
         capped = capped || its[h] >= max_iter;
     }
     return capped ? RRT_NOT_CONVERGED : RRT_OK;
+}
+
+int rrt_set_tuning(rrt_ctx* x, int32_t key, int32_t value)
+{
+    if (!x) return RRT_E_ARG;
+    Ctx& c = x->c;
+    switch (key) {
+    case RRT_TUNE_TRACE_BLOCK:
+        // the traversal kernels are compiled for at most 256 threads per block
+        if (value < 64 || value > 256 || value % 64)
+            return fail(c, RRT_E_ARG, "traversal block must be 64, 128, 192 or 256");
+        c.prm.block_size = value;
+        break;
+    case RRT_TUNE_PACKET:
+        if (value != 1 && value != 64) return fail(c, RRT_E_ARG, "packet must be 1 or 64");
+        c.prm.traversal = value == 64 ? 0 : 1;
+        break;
+    case RRT_TUNE_PATH_GROUP:
+        if (value != 0 && value != 8 && value != 16 && value != 32 && value != 64)
+            return fail(c, RRT_E_ARG, "path group must be 0, 8, 16, 32 or 64");
+        c.path_group = value;
+        break;
+    case RRT_TUNE_LEAF:
+        if (value < 1 || value > 8) return fail(c, RRT_E_ARG, "leaf size must be 1..8");
+        c.leaf = value;
+        c.have_tree = false;          // takes effect with the next rrt_build_tree
+        break;
+    default:
+        return fail(c, RRT_E_ARG, "unknown tuning key %d", key);
+    }
+    drop_graph(c);                    // launch shapes are baked into a captured graph
+    return RRT_OK;
 }
 
 int rrt_set_state(rrt_ctx* x, const double* xs)

@@ -474,7 +474,7 @@ void fill_kernel_tables(KernelTables* host)
 template <int MODE>
 static void launch_one(Ctx& c, RayOut o)
 {
-    int bs = c.prm.block_size > 0 ? c.prm.block_size : 256;
+    int bs = c.prm.block_size > 0 ? c.prm.block_size : 128;
     if (c.prm.traversal == 1) {
         const int64_t n_rays = c.n * (int64_t)c.n_ray;
         const unsigned nb = (unsigned)((n_rays + bs - 1) / bs);

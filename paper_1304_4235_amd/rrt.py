@@ -18,6 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librrt.so")
 
 RRT_OK, RRT_NOT_CONVERGED = 0, 1
+TUNE_KEYS = {"trace_block": 1, "packet": 2, "path_group": 3, "leaf": 4}
 ERRORS = {-1: "RRT_E_ARG", -2: "RRT_E_HIP", -3: "RRT_E_INPUT", -4: "RRT_E_STATE",
           -5: "RRT_E_NOMEM", -6: "RRT_E_CAPACITY"}
 
@@ -60,6 +61,7 @@ SIGNATURES = {
     "rrt_get_counters": ([_vp, _vp], C.c_int),
     "rrt_set_density": ([_vp, _vp], C.c_int),
     "rrt_set_halos": ([_vp, _i32, _vp], C.c_int),
+    "rrt_set_tuning": ([_vp, _i32, _i32], C.c_int),
     "rrt_iterate_halos": ([_vp, _i32, _d, _i32, _vp, _vp], C.c_int),
     "rrt_forward": ([_vp, _i32, _vp, _vp], C.c_int),
     "rrt_backward": ([_vp, _vp, _vp, _vp, _vp], C.c_int),
@@ -166,6 +168,11 @@ class Solver:
         self._keep = [pos, h, mu, nH, T, xi]      # copied by the library; kept until synced
         self.n = n
         self.n_halo = 1
+
+    def set_tuning(self, **kw):
+        """Launch knobs: trace_block, packet (1 or 64), path_group, leaf."""
+        for k, v in kw.items():
+            self._check(_lib.rrt_set_tuning(self._h, TUNE_KEYS[k], int(v)), f"rrt_set_tuning {k}")
 
     def set_halos(self, offsets):
         off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
