@@ -131,6 +131,7 @@ def bench_batch(args):
     for _ in range(args.warmup):
         batched()
     torch.cuda.synchronize()
+    print(f"tuned {best}; timing the batched solve", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     for _ in range(args.steps):
         r = batched()
@@ -148,9 +149,12 @@ def bench_batch(args):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     seq_iters = []
-    for sh in subs:
+    for i, sh in enumerate(subs):
         sh.build_tree()
         seq_iters.append(sh.iterate(wl.max_iter, wl.tol, want_x=False)["iters"])
+        if i % 8 == 7:
+            print(f"sequential: {i + 1}/{n_halo} halos, {time.perf_counter() - t0:.1f} s",
+                  file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t0
     out = {"metric": "batched halo solve time vs sequential solves", "unit": "ms",

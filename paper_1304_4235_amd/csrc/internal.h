@@ -235,5 +235,8 @@ hipError_t launch_from_input_order_d(Ctx& c, const double* src, double* dst);
 hipError_t launch_mux(Ctx& c);
 hipError_t launch_seg_finalize(Ctx& c, double tol, int max_iter);
 hipError_t launch_seg_init(Ctx& c);
+hipError_t launch_halo_hits(Ctx& c, const uint64_t* row_cnt, unsigned long long* out);
+hipError_t launch_mask_rows(Ctx& c, const uint64_t* row_cnt, const int32_t* mask, uint64_t* row_off);
+hipError_t launch_seg_group_init(Ctx& c, const int32_t* mask);
 
 }  // namespace rrt

@@ -237,6 +237,80 @@ hipError_t launch_gamma(Ctx& c, bool update_x)
     return hipGetLastError();
 }
 
+// intersections per halo from per-ray counts (rows are [direction][tree position])
+__global__ void k_halo_hits(const uint64_t* __restrict__ row_cnt, int64_t n_rows, int64_t n,
+                            const int32_t* __restrict__ seg_of, unsigned long long* __restrict__ out)
+{
+    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int h = r < n_rows ? seg_of[r % n] : -1;
+    unsigned long long v = r < n_rows ? (unsigned long long)row_cnt[r] : 0ull;
+    const int h0 = __shfl(h, 0, 64);
+    if (h0 >= 0 && __ballot(h != h0 && h >= 0) == 0) {
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if ((threadIdx.x & 63) == 0 && v) atomicAdd(out + h0, v);
+    } else if (h >= 0 && v) {
+        atomicAdd(out + h, v);
+    }
+}
+
+// per-ray counts of the halos in `mask`, zero for the others
+__global__ void k_mask_rows(const uint64_t* __restrict__ row_cnt, int64_t n_rows, int64_t n,
+                            const int32_t* __restrict__ seg_of, const int32_t* __restrict__ mask,
+                            uint64_t* __restrict__ row_off)
+{
+    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r < n_rows) row_off[r] = mask[seg_of[r % n]] ? row_cnt[r] : 0ull;
+}
+
+// start a group of halos: only the masked ones iterate; iteration counts kept
+__global__ void k_seg_group_init(int n_halo, const int32_t* __restrict__ mask,
+                                 int32_t* __restrict__ active, unsigned long long* __restrict__ maxdx,
+                                 int32_t* __restrict__ state, unsigned long long* __restrict__ red)
+{
+    __shared__ int cnt[256];
+    int c = 0;
+    for (int h = threadIdx.x; h < n_halo; h += blockDim.x) {
+        active[h] = mask[h] ? 1 : 0;
+        c += active[h];
+        maxdx[h] = 0ull;
+    }
+    cnt[threadIdx.x] = c;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) cnt[threadIdx.x] += cnt[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        state[0] = 0;
+        state[1] = cnt[0];
+        red[0] = 0ull;
+        red[1] = 0ull;
+    }
+}
+
+hipError_t launch_halo_hits(Ctx& c, const uint64_t* row_cnt, unsigned long long* out)
+{
+    const int64_t n_rows = c.n * (int64_t)c.n_ray;
+    hipLaunchKernelGGL(k_halo_hits, dim3(nblk(n_rows)), dim3(kBlock), 0, c.stream, row_cnt, n_rows,
+                       c.n, c.seg_of, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_mask_rows(Ctx& c, const uint64_t* row_cnt, const int32_t* mask, uint64_t* row_off)
+{
+    const int64_t n_rows = c.n * (int64_t)c.n_ray;
+    hipLaunchKernelGGL(k_mask_rows, dim3(nblk(n_rows)), dim3(kBlock), 0, c.stream, row_cnt, n_rows,
+                       c.n, c.seg_of, mask, row_off);
+    return hipGetLastError();
+}
+
+hipError_t launch_seg_group_init(Ctx& c, const int32_t* mask)
+{
+    hipLaunchKernelGGL(k_seg_group_init, dim3(1), dim3(256), 0, c.stream, c.n_halo, mask,
+                       c.seg_active, c.seg_maxdx, c.seg_state, c.red);
+    return hipGetLastError();
+}
+
 hipError_t launch_seg_finalize(Ctx& c, double tol, int max_iter)
 {
     hipLaunchKernelGGL(k_seg_finalize, dim3(1), dim3(256), 0, c.stream, c.n_halo, tol, max_iter,

@@ -877,6 +877,135 @@ struct SegGuard {
 
 }  // namespace
 
+namespace {
+
+// Iterate the currently active halos to convergence: one eager iteration, then
+// replays of the captured graph (captured on first use, reused while the
+// buffers it references stay in place).
+int run_active_halos(Ctx& c, double tol, int32_t max_iter, int32_t per_launch)
+{
+    const bool timing = c.timing;
+    if (int r = halo_iteration(c, tol, max_iter)) return r;
+    HIP_OK(hipMemcpyAsync(c.seg_state_host, c.seg_state, 2 * sizeof(int32_t),
+                          hipMemcpyDeviceToHost, c.stream));
+    HIP_OK(hipStreamSynchronize(c.stream));
+    if (c.seg_state_host[1] <= 0) return RRT_OK;
+    if (!c.graph_exec || c.graph_iters != per_launch || c.graph_tol != tol ||
+        c.graph_max_iter != max_iter) {
+        drop_graph(c);
+        hipStream_t user = c.stream;
+        c.stream = c.gstream;
+        c.timing = false;
+        hipError_t e = hipStreamBeginCapture(c.gstream, hipStreamCaptureModeThreadLocal);
+        int r = RRT_OK;
+        for (int k = 0; k < per_launch && e == hipSuccess && r == RRT_OK; ++k)
+            r = halo_iteration(c, tol, max_iter);
+        hipGraph_t gr = nullptr;
+        hipError_t e2 = hipStreamEndCapture(c.gstream, &gr);
+        c.stream = user;
+        c.timing = timing;
+        if (r != RRT_OK) {
+            if (gr) (void)hipGraphDestroy(gr);
+            return r;
+        }
+        HIP_OK(e);
+        HIP_OK(e2);
+        c.graph = gr;
+        HIP_OK(hipGraphInstantiate(&c.graph_exec, c.graph, nullptr, nullptr, 0));
+        c.graph_iters = per_launch;
+        c.graph_tol = tol;
+        c.graph_max_iter = max_iter;
+    }
+    HIP_OK(hipEventRecord(c.ev_a, c.stream));
+    HIP_OK(hipStreamWaitEvent(c.gstream, c.ev_a, 0));
+    while (c.seg_state_host[1] > 0 && c.seg_state_host[0] < max_iter) {
+        HIP_OK(hipGraphLaunch(c.graph_exec, c.gstream));
+        HIP_OK(hipMemcpyAsync(c.seg_state_host, c.seg_state, 2 * sizeof(int32_t),
+                              hipMemcpyDeviceToHost, c.gstream));
+        HIP_OK(hipStreamSynchronize(c.gstream));
+    }
+    HIP_OK(hipEventRecord(c.ev_b, c.gstream));
+    HIP_OK(hipStreamWaitEvent(c.stream, c.ev_b, 0));
+    return RRT_OK;
+}
+
+// Which halos can share recorded paths: per-halo intersection totals from one
+// count pass, packed first-fit by decreasing size into groups whose paths fit
+// the budget.  A halo too large for the budget alone forms a group that
+// traverses every iteration.  Counts stay in row_cnt for the per-group offsets.
+int plan_groups(Ctx& c, uint64_t* row_cnt, std::vector<std::vector<int>>& groups,
+                std::vector<bool>& recordable, uint64_t& max_group)
+{
+    const int nh = c.n_halo;
+    unsigned long long* d_hits = nullptr;
+    HIP_OK(hipMalloc(&d_hits, sizeof(unsigned long long) * nh));
+    hipError_t e = hipMemsetAsync(d_hits, 0, sizeof(unsigned long long) * nh, c.stream);
+    if (e == hipSuccess) e = launch_count_hits(c, row_cnt);
+    if (e == hipSuccess) e = launch_halo_hits(c, row_cnt, d_hits);
+    std::vector<unsigned long long> hits(nh);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(hits.data(), d_hits, sizeof(unsigned long long) * nh,
+                           hipMemcpyDeviceToHost, c.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
+    (void)hipFree(d_hits);
+    HIP_OK(e);
+    size_t budget = (size_t)c.prm.path_budget;
+    if (budget == 0) {
+        size_t fr = 0, tot = 0;
+        HIP_OK(hipMemGetInfo(&fr, &tot));
+        budget = fr / 2 + (c.path ? (size_t)c.path_cap * sizeof(int2) / 2 : 0);
+    }
+    const uint64_t cap = budget / sizeof(int2);
+    std::vector<int> order(nh);
+    for (int h = 0; h < nh; ++h) order[h] = h;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return hits[a] > hits[b]; });
+    std::vector<uint64_t> load;
+    groups.clear();
+    recordable.clear();
+    max_group = 0;
+    for (int h : order) {
+        if (c.prm.record_paths == 0 || hits[h] > cap) {
+            groups.push_back({h});
+            recordable.push_back(false);
+            load.push_back(0);
+            continue;
+        }
+        size_t g = 0;
+        for (; g < groups.size(); ++g)
+            if (recordable[g] && load[g] + hits[h] <= cap) break;
+        if (g == groups.size()) {
+            groups.push_back({});
+            recordable.push_back(true);
+            load.push_back(0);
+        }
+        groups[g].push_back(h);
+        load[g] += hits[h];
+        max_group = std::max<uint64_t>(max_group, load[g]);
+    }
+    // traversing halos need no memory: run them together as one group
+    std::vector<std::vector<int>> gs;
+    std::vector<bool> rs;
+    std::vector<int> trav;
+    for (size_t g = 0; g < groups.size(); ++g) {
+        if (recordable[g]) {
+            gs.push_back(groups[g]);
+            rs.push_back(true);
+        } else {
+            trav.insert(trav.end(), groups[g].begin(), groups[g].end());
+        }
+    }
+    if (!trav.empty()) {
+        gs.push_back(trav);
+        rs.push_back(false);
+    }
+    groups.swap(gs);
+    recordable.swap(rs);
+    return RRT_OK;
+}
+
+}  // namespace
+
 int rrt_iterate_halos(rrt_ctx* x, int32_t max_iter, double tol, int32_t per_launch, double* x_out,
                       int32_t* halo_iters_out)
 {
@@ -887,50 +1016,78 @@ int rrt_iterate_halos(rrt_ctx* x, int32_t max_iter, double tol, int32_t per_laun
         return fail(c, RRT_E_ARG, "max_iter >= 1, tol >= 0, per_launch 1..256");
     if (int r = ensure_seg_buffers(c)) return r;
     SegGuard guard(c);
-    const bool timing = c.timing;
     HIP_OK(launch_seg_init(c));
-    // the first iteration runs eagerly: it may record the ray paths
-    if (int r = halo_iteration(c, tol, max_iter)) return r;
-    HIP_OK(hipMemcpyAsync(c.seg_state_host, c.seg_state, 2 * sizeof(int32_t),
-                          hipMemcpyDeviceToHost, c.stream));
-    HIP_OK(hipStreamSynchronize(c.stream));
-    if (c.seg_state_host[1] > 0) {
-        if (!c.graph_exec || c.graph_iters != per_launch || c.graph_tol != tol ||
-            c.graph_max_iter != max_iter) {
-            drop_graph(c);
-            hipStream_t user = c.stream;
-            c.stream = c.gstream;
-            c.timing = false;
-            hipError_t e = hipStreamBeginCapture(c.gstream, hipStreamCaptureModeThreadLocal);
-            int r = RRT_OK;
-            for (int k = 0; k < per_launch && e == hipSuccess && r == RRT_OK; ++k)
-                r = halo_iteration(c, tol, max_iter);
-            hipGraph_t gr = nullptr;
-            hipError_t e2 = hipStreamEndCapture(c.gstream, &gr);
-            c.stream = user;
-            c.timing = timing;
-            if (r != RRT_OK) {
-                if (gr) (void)hipGraphDestroy(gr);
-                return r;
+    if (c.paths_valid || c.paths_unfit || c.prm.record_paths == 0 || c.n_halo == 1) {
+        // one group: every halo at once (recording, if any, happens in the first iteration)
+        if (int r = run_active_halos(c, tol, max_iter, per_launch)) return r;
+    } else {
+        const int64_t n_rows = c.n * (int64_t)c.n_ray;
+        uint64_t* row_cnt = nullptr;
+        HIP_OK(hipMalloc(&row_cnt, sizeof(uint64_t) * n_rows));
+        std::vector<std::vector<int>> groups;
+        std::vector<bool> recordable;
+        uint64_t max_group = 0;
+        int r = plan_groups(c, row_cnt, groups, recordable, max_group);
+        if (r == RRT_OK && groups.size() == 1 && recordable[0]) {
+            (void)hipFree(row_cnt);
+            row_cnt = nullptr;
+            r = run_active_halos(c, tol, max_iter, per_launch);   // all paths fit
+        } else if (r == RRT_OK) {
+            // halos in groups whose recorded paths fit, one group after another
+            int32_t* d_mask = nullptr;
+            hipError_t e = hipMalloc(&d_mask, sizeof(int32_t) * c.n_halo);
+            if (e == hipSuccess) e = dalloc(&c.row_off, (size_t)n_rows + 1);
+            if (e == hipSuccess && max_group > 0 && (max_group > c.path_cap || !c.path)) {
+                drop_graph(c);
+                e = dalloc(&c.path, (size_t)max_group);
+                c.path_cap = e == hipSuccess ? max_group : 0;
             }
+            std::vector<int32_t> mask(c.n_halo);
+            for (size_t g = 0; g < groups.size() && e == hipSuccess && r == RRT_OK; ++g) {
+                std::fill(mask.begin(), mask.end(), 0);
+                for (int h : groups[g]) mask[h] = 1;
+                e = hipMemcpyAsync(d_mask, mask.data(), sizeof(int32_t) * c.n_halo,
+                                   hipMemcpyHostToDevice, c.stream);
+                if (e == hipSuccess) e = launch_seg_group_init(c, d_mask);
+                if (e != hipSuccess) break;
+                if (recordable[g]) {
+                    uint64_t total = 0;
+                    e = launch_mask_rows(c, row_cnt, d_mask, c.row_off);
+                    if (e == hipSuccess)
+                        e = hipMemsetAsync(c.row_off + n_rows, 0, sizeof(uint64_t), c.stream);
+                    if (e == hipSuccess) e = scan_exclusive_u64(c, c.row_off, c.row_off, n_rows + 1);
+                    if (e == hipSuccess)
+                        e = hipMemcpyAsync(&total, c.row_off + n_rows, sizeof total,
+                                           hipMemcpyDeviceToHost, c.stream);
+                    if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
+                    if (e == hipSuccess) {
+                        // record only this group's rays: they are the active ones
+                        e = launch_record_paths(c, c.row_off, c.path, total);
+                    }
+                    if (!c.paths_valid) drop_graph(c);     // the graph held traversals
+                    c.paths_valid = true;
+                    c.paths_unfit = false;
+                    c.path_hits = (int64_t)total;
+                } else {
+                    if (c.paths_valid) drop_graph(c);      // the graph held path products
+                    c.paths_valid = false;
+                    c.paths_unfit = true;
+                }
+                if (e == hipSuccess) r = run_active_halos(c, tol, max_iter, per_launch);
+            }
+            // the recorded paths held one group only: not valid for the whole batch
+            c.paths_valid = false;
+            c.paths_unfit = false;
+            c.path_hits = 0;
+            free_tpaths(c);
+            drop_graph(c);
+            if (d_mask) (void)hipFree(d_mask);
+            if (row_cnt) (void)hipFree(row_cnt);
+            row_cnt = nullptr;
             HIP_OK(e);
-            HIP_OK(e2);
-            c.graph = gr;
-            HIP_OK(hipGraphInstantiate(&c.graph_exec, c.graph, nullptr, nullptr, 0));
-            c.graph_iters = per_launch;
-            c.graph_tol = tol;
-            c.graph_max_iter = max_iter;
         }
-        HIP_OK(hipEventRecord(c.ev_a, c.stream));
-        HIP_OK(hipStreamWaitEvent(c.gstream, c.ev_a, 0));
-        while (c.seg_state_host[1] > 0 && c.seg_state_host[0] < max_iter) {
-            HIP_OK(hipGraphLaunch(c.graph_exec, c.gstream));
-            HIP_OK(hipMemcpyAsync(c.seg_state_host, c.seg_state, 2 * sizeof(int32_t),
-                                  hipMemcpyDeviceToHost, c.gstream));
-            HIP_OK(hipStreamSynchronize(c.gstream));
-        }
-        HIP_OK(hipEventRecord(c.ev_b, c.gstream));
-        HIP_OK(hipStreamWaitEvent(c.stream, c.ev_b, 0));
+        if (row_cnt) (void)hipFree(row_cnt);
+        if (r != RRT_OK) return r;
     }
     std::vector<int32_t> its(c.n_halo);
     HIP_OK(hipMemcpyAsync(its.data(), c.seg_iters, sizeof(int32_t) * c.n_halo,

@@ -551,7 +551,7 @@ hipError_t launch_count_hits(Ctx& c, uint64_t* row_cnt)
     RayOut o{};
     o.row_cnt = row_cnt;
     o.perm = c.perm;
-    o.hits_total = c.red + 1;
+    o.hits_total = c.red + 3;        // scratch: counting is not a column evaluation
     return launch_mode(c, kModeCount, o);
 }
 
@@ -576,7 +576,7 @@ hipError_t launch_record_paths(Ctx& c, const uint64_t* row_off, int2* path, uint
     o.row_off = row_off;
     o.path = path;
     o.perm = c.perm;
-    o.hits_total = c.red + 1;
+    o.hits_total = c.red + 3;
     return launch_mode(c, kModePath, o);
 }
 

@@ -102,3 +102,25 @@ def test_replay_length_does_not_change_results():
     s.set_state(None)
     r2 = s.iterate_halos(200, 1e-3, per_launch=5)
     np.testing.assert_array_equal(r1["x"].cpu().numpy(), r2["x"].cpu().numpy())
+
+
+@pytest.mark.parametrize("frac", [0.45, 0.2])
+def test_grouped_recording_under_a_small_budget(frac):
+    """With paths larger than the budget, halos run in groups whose paths fit
+    (and a halo too large for the budget traverses): same results per halo."""
+    wl, parts = _batch(SIZES, PEAKS, seed=12)
+    probe = _solver(wl, record_paths=0)
+    _, hits = probe.compute_columns(want_N=False)
+    budget = int(8 * hits * frac)
+    sb = _solver(wl, record_paths=-1, path_budget=budget)
+    rb = sb.iterate_halos(200, 1e-3, per_launch=4)
+    xb = rb["x"].cpu().numpy()
+    for h, p in enumerate(parts):
+        r = _solver(p).iterate(200, 1e-3)
+        a, b = wl.halo_offsets[h], wl.halo_offsets[h + 1]
+        assert rb["halo_iters"][h] == r["iters"], h
+        np.testing.assert_allclose(xb[a:b], r["x"].cpu().numpy(), rtol=1e-9)
+    # afterwards the batch still gives whole-batch columns
+    N1, h1 = sb.compute_columns()
+    N2, h2 = _solver(wl, record_paths=0).compute_columns()
+    assert h1 == h2
