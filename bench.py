@@ -309,15 +309,22 @@ def main():
         lnG, x = s.forward(K)
         torch.cuda.synchronize()
         t_fwd = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        lnG, x = s.forward(K)
-        g = 2.0 * (lnG - lnG_t) / np.log(10.0) ** 2
-        s.backward(g, None)
-        torch.cuda.synchronize()
-        t_fb = time.perf_counter() - t0
+        t_fb = []
+        for rep in range(2):
+            # the first backward after a tree build also transposes the recorded
+            # paths (once per geometry); the second reuses them
+            print(f"forward+adjoint {rep + 1}/2 (K={K})", file=sys.stderr, flush=True)
+            t0 = time.perf_counter()
+            lnG, x = s.forward(K)
+            g = 2.0 * (lnG - lnG_t) / np.log(10.0) ** 2
+            s.backward(g, None)
+            torch.cuda.synchronize()
+            t_fb.append(time.perf_counter() - t0)
         out["forward_adjoint"] = {"K": K, "plain_forward_ms": t_fwd * 1e3,
-                                  "forward_plus_adjoint_ms": t_fb * 1e3,
-                                  "ratio": t_fb / t_fwd,
+                                  "forward_plus_adjoint_ms": t_fb[1] * 1e3,
+                                  "ratio": t_fb[1] / t_fwd,
+                                  "first_after_build_ms": t_fb[0] * 1e3,
+                                  "first_ratio": t_fb[0] / t_fwd,
                                   "gradients": f"dL/dw over {wl.n_bins} bins and dL/dn_H over "
                                                f"{wl.n} particles"}
     if not args.no_cpu_baseline:

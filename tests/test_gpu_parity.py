@@ -224,6 +224,65 @@ def test_full_halo_sampled_sources():
 
 
 # ---------------------------------------------------------------------------
+# periodic lognormal field: 48 rays, many bins, fixed iteration count
+# ---------------------------------------------------------------------------
+def test_lognormal_small_every_particle():
+    """12^3 particles at the 128^3 field's mean spacing (78 kpc), so that h
+    spans several times l_ray and many kernels cross the periodic boundary;
+    48 rays, 32 bins, 3 fixed iterations, every particle."""
+    wl = W.lognormal_field(n_grid=12, box=937.5, n_bins=32, max_iter=3)
+    _say("oracle solve: lognormal 12^3")
+    ref = oracle.solve(wl)
+    assert ref["iters"] == 3
+    s = _solver(wl)
+    off, hj, hi = s.hits()
+    src = np.arange(0, wl.n, 23)
+    _, o_off, o_hj, o_hi = oracle.columns(wl, np.ones(wl.n), sources=src, hits=True)
+    nr = wl.n_ray
+    for i, p in enumerate(src):
+        got = _hitsets(off, hj, hi, [p * nr + k for k in range(nr)])
+        want = _hitsets(o_off, o_hj, o_hi, [i * nr + k for k in range(nr)])
+        assert got == want, f"source {p}"
+    assert np.any(o_hi != (8 | 8 << 4 | 8 << 8)), "no periodic image was hit"
+    for k in range(3):
+        _say("lognormal iteration", k)
+        s.set_state(torch.tensor(ref["x_hist"][k]))
+        s.compute_columns(want_N=False, count=False)
+        lnG, _, _ = s.compute_gamma()
+        xn, _ = s.update_equilibrium()
+        lnG_o = ref["lnG_hist"][k]
+        _check_rates(lnG.cpu().numpy(), lnG_o, math.log(oracle.gamma_thin(wl)) - lnG_o)
+        _check_x(xn.cpu().numpy(), ref["x_hist"][k + 1])
+    s.set_state(None)
+    r = s.iterate(wl.max_iter, wl.tol)
+    assert r["iters"] == 3 and not r["converged"]
+    _check_x(r["x"].cpu().numpy(), ref["x_hist"][3])
+
+
+def test_lognormal_full_sampled_sources():
+    """The 128^3 field (2097152 particles, 10 Mpc periodic box, 48 rays, 256
+    bins): the GPU iterates checked one step at a time on sampled sources
+    against the oracle fed the same state."""
+    wl = W.make_config(2)
+    s = _solver(wl)
+    rng = np.random.default_rng(3)
+    src = np.sort(rng.choice(wl.n, 8, replace=False))
+    x = oracle.x_thin(wl)
+    for k in range(2):
+        _say("lognormal field iteration", k)
+        s.set_state(torch.tensor(x))
+        N, nh = s.compute_columns()
+        lnG, _, _ = s.compute_gamma()
+        xn, _ = s.update_equilibrium()
+        ref = oracle.step(wl, x, sources=src)
+        _check_columns(N.cpu().numpy()[src], ref["N"])
+        _check_rates(lnG.cpu().numpy()[src], ref["lnG"], ref["tau"])
+        _check_x(xn.cpu().numpy()[src], ref["x_new"])
+        x = xn.cpu().numpy()
+    assert nh > 5e9                      # ~72 intersections per ray
+
+
+# ---------------------------------------------------------------------------
 # edge cases and invariances
 # ---------------------------------------------------------------------------
 def _tiny(pos, h, L=10.0, box=0.0, dirs=None):
