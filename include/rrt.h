@@ -212,8 +212,13 @@ int rrt_iterate_halos(rrt_ctx* ctx, int32_t max_iter, double tol, int32_t per_la
  *                         packet, default) or 1 (independent lanes)
  *   RRT_TUNE_PATH_GROUP   lanes per ray in the recorded-path product: 8, 16, 32,
  *                         64, or 0 = chosen from the mean intersections per ray
- *   RRT_TUNE_LEAF         particles per tree leaf (1..8), from the next build */
-enum { RRT_TUNE_TRACE_BLOCK = 1, RRT_TUNE_PACKET = 2, RRT_TUNE_PATH_GROUP = 3, RRT_TUNE_LEAF = 4 };
+ *   RRT_TUNE_LEAF         particles per tree leaf (1..8), from the next build
+ *   RRT_TUNE_ADJOINT      transposed column product of rrt_backward over
+ *                         recorded paths: 0 (default) = gather over paths
+ *                         transposed once per geometry when memory allows,
+ *                         else atomic scatter; 1 = always atomic scatter */
+enum { RRT_TUNE_TRACE_BLOCK = 1, RRT_TUNE_PACKET = 2, RRT_TUNE_PATH_GROUP = 3, RRT_TUNE_LEAF = 4,
+       RRT_TUNE_ADJOINT = 5 };
 int rrt_set_tuning(rrt_ctx* ctx, int32_t key, int32_t value);
 
 /* Replace the state: x device double[n] in input order (checkpoint / resume,

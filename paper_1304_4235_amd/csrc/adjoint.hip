@@ -121,15 +121,17 @@ __global__ void __launch_bounds__(256)
 k_adj_scatter(const uint64_t* __restrict__ row_off, const int2* __restrict__ path,
               const double* __restrict__ nu, int64_t n_rows, double* __restrict__ y)
 {
-    const int64_t row = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
-    if (row >= n_rows) return;
-    const double v = nu[row];
-    if (v == 0.0) return;
-    const uint64_t a = row_off[row], b = row_off[row + 1];
-    for (uint64_t e = a + lane; e < b; e += 64) {
-        const int2 h = path[e];
-        unsafeAtomicAdd(y + h.x, (double)__int_as_float(h.y) * v);
+    const int64_t stride = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t row = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6; row < n_rows;
+         row += stride) {
+        const double v = nu[row];
+        if (v == 0.0) continue;
+        const uint64_t a = row_off[row], b = row_off[row + 1];
+        for (uint64_t e = a + lane; e < b; e += 64) {
+            const int2 h = path[e];
+            unsafeAtomicAdd(y + h.x, (double)__int_as_float(h.y) * v);
+        }
     }
 }
 
@@ -206,7 +208,7 @@ hipError_t launch_adj_scatter(Ctx& c)
     const int64_t n_rows = c.n * (int64_t)c.n_ray;
     hipError_t e = hipMemsetAsync(c.adj_y, 0, sizeof(double) * c.n, c.stream);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_adj_scatter, dim3((unsigned)((n_rows * 64 + 255) / 256)), dim3(256), 0,
+    hipLaunchKernelGGL(k_adj_scatter, dim3(stride_blocks(n_rows, 4)), dim3(256), 0,
                        c.stream, c.row_off, c.path, c.adj_nu, n_rows, c.adj_y);
     return hipGetLastError();
 }

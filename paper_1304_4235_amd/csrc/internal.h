@@ -16,6 +16,19 @@ constexpr int kTabIntervals = 256;        // cubic pieces per kernel table
 constexpr int kMaxRays = 3072;
 constexpr int kMaxBins = 4096;
 constexpr int kDefaultLeaf = 8;
+// particles x rays: rays are indexed with 32-bit integers on the device
+constexpr int64_t kMaxRows = 2147483647;
+// A dispatch covers fewer than 2^32 work-items per grid dimension (the launch
+// packet's grid size is 32-bit).  Kernels whose index space can exceed that
+// (several lanes per ray or per particle) loop with the grid as stride and are
+// launched with at most kMaxBlocks blocks.
+constexpr int64_t kMaxBlocks = int64_t(1) << 20;
+inline unsigned stride_blocks(int64_t items, int items_per_block)
+{
+    int64_t b = (items + items_per_block - 1) / items_per_block;
+    if (b < 1) b = 1;
+    return (unsigned)(b < kMaxBlocks ? b : kMaxBlocks);
+}
 
 // One node of the depth-first tree layout: two 16-byte words.
 //   a = (lo.x, lo.y, lo.z, skip as int bits)
@@ -183,6 +196,7 @@ struct Ctx {
     hipEvent_t ev_a = nullptr, ev_b = nullptr;
 
     int32_t path_group = 0;       // lanes per ray in the path product (0 = automatic)
+    int32_t adj_scatter = 0;      // 1: reverse mode scatters atomically, never transposes
 
     // counters: intersections of the last iteration and since the last reset
     int64_t last_hits = 0, total_hits = 0;

@@ -113,6 +113,10 @@ int alloc_columns(Ctx& c)
 {
     if (c.N_s) (void)hipFree(c.N_s);
     c.N_s = nullptr;
+    // rays are indexed with 32-bit integers on the device
+    if (c.n * (int64_t)c.n_ray > kMaxRows)
+        return fail(c, RRT_E_ARG, "%lld particles x %d rays exceeds 2^31 - 1 rays",
+                    (long long)c.n, c.n_ray);
     hipError_t e = dalloc(&c.N_s, (size_t)c.n * (size_t)c.n_ray);
     if (e != hipSuccess)
         return fail(c, RRT_E_NOMEM, "column buffer allocation failed: %s", hipGetErrorString(e));
@@ -233,8 +237,10 @@ int columns_impl(Ctx& c, int64_t* hits)
     if (c.paths_valid) {
         const int64_t n_rows = c.n * (int64_t)c.n_ray;
         const double mean = (double)c.path_hits / (double)std::max<int64_t>(n_rows, 1);
+        // measured on MI355X: 32 lanes per ray are fastest from a few tens of
+        // intersections per ray up to hundreds; short rays want fewer lanes
         const int group = c.path_group ? c.path_group
-                          : mean >= 96 ? 64 : mean >= 40 ? 32 : mean >= 16 ? 16 : 8;
+                          : mean >= 40 ? 32 : mean >= 16 ? 16 : 8;
         ev_begin(c);
         HIP_OK(launch_path_columns(c, group));
         if (c.timing) {
@@ -782,7 +788,7 @@ int rrt_backward(rrt_ctx* x, const double* dL_dlnG, const double* dL_dx, double*
         int64_t hits = -1;
         if (int r = columns_impl(c, &hits)) return r;
         HIP_OK(launch_adj_rate(c, (k == K && dL_dlnG) ? c.adj_lup : nullptr));
-        if (c.paths_valid && !c.tpaths_valid && !c.tpaths_unfit) {
+        if (c.paths_valid && !c.tpaths_valid && !c.tpaths_unfit && !c.adj_scatter) {
             // transposed paths (8 B per intersection) plus sort scratch (24 B)
             size_t fr = 0, tot = 0;
             HIP_OK(hipMemGetInfo(&fr, &tot));
@@ -794,7 +800,7 @@ int rrt_backward(rrt_ctx* x, const double* dL_dlnG, const double* dL_dx, double*
                 c.tpaths_unfit = true;
             }
         }
-        if (c.paths_valid && c.tpaths_valid) {
+        if (c.paths_valid && c.tpaths_valid && !c.adj_scatter) {
             HIP_OK(launch_gather_cols(c));
         } else if (c.paths_valid) {
             HIP_OK(launch_adj_scatter(c));
@@ -1122,6 +1128,10 @@ int rrt_set_tuning(rrt_ctx* x, int32_t key, int32_t value)
         if (value != 0 && value != 8 && value != 16 && value != 32 && value != 64)
             return fail(c, RRT_E_ARG, "path group must be 0, 8, 16, 32 or 64");
         c.path_group = value;
+        break;
+    case RRT_TUNE_ADJOINT:
+        if (value != 0 && value != 1) return fail(c, RRT_E_ARG, "adjoint mode must be 0 or 1");
+        c.adj_scatter = value;
         break;
     case RRT_TUNE_LEAF:
         if (value < 1 || value > 8) return fail(c, RRT_E_ARG, "leaf size must be 1..8");

@@ -510,16 +510,19 @@ k_path_columns(const uint64_t* __restrict__ row_off, const int2* __restrict__ pa
                const float* __restrict__ mux, int64_t n_rows, double* __restrict__ N, int64_t n,
                const int32_t* __restrict__ seg_of, const int32_t* __restrict__ seg_active)
 {
-    const int64_t row = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G;
     const int lane = threadIdx.x & (G - 1);
-    double acc = 0.0;
-    // rows of halos that have stopped iterating keep their last columns
-    const bool live = row < n_rows && !(seg_active && seg_active[seg_of[row % n]] == 0);
-    if (live) {
+    const int64_t stride = (int64_t)gridDim.x * (blockDim.x / G);
+    const long long* p = reinterpret_cast<const long long*>(path);
+    // the G lanes of a group share the row, so the loop is uniform per group
+    for (int64_t row = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G; row < n_rows;
+         row += stride) {
+        // rows of halos that have stopped iterating keep their last columns
+        if (seg_active && seg_active[seg_of[row % n]] == 0) continue;
         const uint64_t a = row_off[row], b = row_off[row + 1];
-        const long long* p = reinterpret_cast<const long long*>(path);
-        // four independent streaming loads in flight per lane before any is used;
-        // entries past the row end read as (particle 0, factor 0) and add nothing
+        double acc = 0.0;
+        // four independent streaming loads in flight per lane before any is
+        // used; entries past the row end read as (particle 0, factor 0) and
+        // add nothing
         for (uint64_t e = a + lane; e < b; e += 4 * G) {
             const long long v0 = __builtin_nontemporal_load(p + e);
             const long long v1 = e + G < b ? __builtin_nontemporal_load(p + e + G) : 0ll;
@@ -532,9 +535,9 @@ k_path_columns(const uint64_t* __restrict__ row_off, const int2* __restrict__ pa
             acc += (double)(m2 * __int_as_float((int)(v2 >> 32)));
             acc += (double)(m3 * __int_as_float((int)(v3 >> 32)));
         }
+        for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
+        if (lane == 0) N[row] = acc;
     }
-    for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
-    if (live && lane == 0) N[row] = acc;
 }
 
 hipError_t launch_columns(Ctx& c)
@@ -594,7 +597,7 @@ hipError_t launch_path_columns(Ctx& c, int group)
 {
     const int64_t n_rows = c.n * (int64_t)c.n_ray;
     const int bs = 256;
-    const unsigned nb = (unsigned)((n_rows * group + bs - 1) / bs);
+    const unsigned nb = stride_blocks(n_rows, bs / group);
     if (group == 64)
         hipLaunchKernelGGL(k_path_columns<64>, dim3(nb), dim3(bs), 0, c.stream, c.row_off, c.path,
                            c.mux_s, n_rows, c.N_s, c.n, c.geom.seg_of, c.geom.seg_active);

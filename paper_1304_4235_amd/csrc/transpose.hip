@@ -21,14 +21,16 @@ constexpr int kWaves = kBlock / 64;
 __global__ void k_expand(const uint64_t* __restrict__ row_off, const int2* __restrict__ path,
                          int64_t n_rows, uint32_t* __restrict__ key, uint64_t* __restrict__ val)
 {
-    const int64_t row = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
-    if (row >= n_rows) return;
-    const uint64_t a = row_off[row], b = row_off[row + 1];
-    for (uint64_t e = a + lane; e < b; e += 64) {
-        const int2 h = path[e];
-        key[e] = (uint32_t)h.x;
-        val[e] = ((uint64_t)(uint32_t)h.y << 32) | (uint64_t)(uint32_t)row;
+    const int64_t stride = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t row = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6; row < n_rows;
+         row += stride) {
+        const uint64_t a = row_off[row], b = row_off[row + 1];
+        for (uint64_t e = a + lane; e < b; e += 64) {
+            const int2 h = path[e];
+            key[e] = (uint32_t)h.x;
+            val[e] = ((uint64_t)(uint32_t)h.y << 32) | (uint64_t)(uint32_t)row;
+        }
     }
 }
 
@@ -114,10 +116,11 @@ __global__ void __launch_bounds__(256)
 k_gather_cols(const uint64_t* __restrict__ col_off, const uint64_t* __restrict__ ent,
               const double* __restrict__ nu, int64_t n, double* __restrict__ y)
 {
-    const int64_t col = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
-    double acc = 0.0;
-    if (col < n) {
+    const int64_t stride = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t col = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6; col < n;
+         col += stride) {
+        double acc = 0.0;
         const uint64_t a = col_off[col], b = col_off[col + 1];
         const long long* p = reinterpret_cast<const long long*>(ent);
         for (uint64_t e = a + lane; e < b; e += 4 * 64) {
@@ -132,9 +135,9 @@ k_gather_cols(const uint64_t* __restrict__ col_off, const uint64_t* __restrict__
             acc += (double)__int_as_float((int)(v2 >> 32)) * n2;
             acc += (double)__int_as_float((int)(v3 >> 32)) * n3;
         }
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        if (lane == 0) y[col] = acc;
     }
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-    if (col < n && lane == 0) y[col] = acc;
 }
 
 }  // namespace
@@ -165,7 +168,7 @@ hipError_t build_transposed_paths(Ctx& c)
     if (e == hipSuccess) e = hipMalloc(&vb, sizeof(uint64_t) * mm);
     if (e == hipSuccess) e = hipMalloc(&hist, sizeof(uint64_t) * 2 * hn);
     if (e == hipSuccess && m > 0) {
-        hipLaunchKernelGGL(k_expand, dim3((unsigned)((n_rows * 64 + 255) / 256)), dim3(256), 0,
+        hipLaunchKernelGGL(k_expand, dim3(stride_blocks(n_rows, 4)), dim3(256), 0,
                            c.stream, c.row_off, c.path, n_rows, ka, c.tpath);
         e = hipGetLastError();
     }
@@ -215,7 +218,7 @@ hipError_t build_transposed_paths(Ctx& c)
 
 hipError_t launch_gather_cols(Ctx& c)
 {
-    hipLaunchKernelGGL(k_gather_cols, dim3((unsigned)((c.n * 64 + 255) / 256)), dim3(256), 0,
+    hipLaunchKernelGGL(k_gather_cols, dim3(stride_blocks(c.n, 4)), dim3(256), 0,
                        c.stream, c.tcol_off, c.tpath, c.adj_nu, c.n, c.adj_y);
     return hipGetLastError();
 }

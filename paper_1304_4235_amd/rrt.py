@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librrt.so")
 
 RRT_OK, RRT_NOT_CONVERGED = 0, 1
-TUNE_KEYS = {"trace_block": 1, "packet": 2, "path_group": 3, "leaf": 4}
+TUNE_KEYS = {"trace_block": 1, "packet": 2, "path_group": 3, "leaf": 4, "adjoint_scatter": 5}
 ERRORS = {-1: "RRT_E_ARG", -2: "RRT_E_HIP", -3: "RRT_E_INPUT", -4: "RRT_E_STATE",
           -5: "RRT_E_NOMEM", -6: "RRT_E_CAPACITY"}
 
@@ -170,7 +170,7 @@ class Solver:
         self.n_halo = 1
 
     def set_tuning(self, **kw):
-        """Launch knobs: trace_block, packet (1 or 64), path_group, leaf."""
+        """Launch knobs: trace_block, packet (1 or 64), path_group, leaf, adjoint_scatter (0/1)."""
         for k, v in kw.items():
             self._check(_lib.rrt_set_tuning(self._h, TUNE_KEYS[k], int(v)), f"rrt_set_tuning {k}")
 
