@@ -37,6 +37,8 @@ BYTES_PER_HIT = 20.0          # x, y, z, h, mu*x (FP32) of each intersected part
 BYTES_PER_RAY = 8.0           # the FP64 column written per ray
 BYTES_PER_PATH_HIT = 8.0      # recorded (particle index, K/h^2) streamed per intersection
 BYTES_PER_ROW = 16.0          # row offset read + FP64 column written per ray
+BYTES_PER_TILE_HIT = 6.0      # 16-bit local particle index + FP32 K/h^2 per intersection
+BYTES_PER_TILE_SET = 8.0      # per distinct particle of a tile: its index + its mu*x
 METRIC = "ray-particle intersections/s + particles/s per iteration; fwd+adjoint vs plain"
 
 
@@ -181,6 +183,8 @@ def main():
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--leaf", type=int, default=0)
     ap.add_argument("--traversal", type=int, default=0, help="0 wave-cooperative, 1 per lane")
+    ap.add_argument("--tiles", type=int, default=0,
+                    help="1: columns from row tiles once the recorded paths have been reused")
     ap.add_argument("--paths", type=int, default=-1,
                     help="-1 record ray paths when they fit (default), 0 traverse every iteration")
     args = ap.parse_args()
@@ -210,6 +214,8 @@ def main():
           f"l_ray={wl.l_ray} box={wl.box}", file=sys.stderr, flush=True)
     s = Solver.from_workload(wl, leaf_size=args.leaf, block_size=args.block,
                              record_paths=args.paths, traversal=args.traversal, build=False)
+    if args.tiles:
+        s.set_tuning(tiles=1)
     torch.cuda.synchronize()
 
     def step():
@@ -251,6 +257,16 @@ def main():
                                          launches=tm["n_path"], total_ms=tm["path_ms"],
                                          avg_launch_ms=avg, algorithmic_bytes_per_launch=b,
                                          achieved=b / (avg * 1e-3) / 1e9)
+    if tm["n_tile"]:
+        avg = tm["tile_ms"] / tm["n_tile"]
+        b = (BYTES_PER_TILE_HIT * hits_per_iter + BYTES_PER_ROW * rays
+             + BYTES_PER_TILE_SET * max(tm["tile_set_total"], 0))
+        kernels["row_tiles"] = dict(kernel="k_tile_columns (columns from row tiles, particle "
+                                           "values staged in LDS)",
+                                    launches=tm["n_tile"], total_ms=tm["tile_ms"],
+                                    avg_launch_ms=avg, algorithmic_bytes_per_launch=b,
+                                    achieved=b / (avg * 1e-3) / 1e9,
+                                    build_ms_per_step=tm["tile_build_ms"] / args.steps)
     if tm["record_ms"]:
         kernels["path_recording"] = dict(kernel="k_trace<1> + k_trace<3> (count, record)",
                                          total_ms=tm["record_ms"],
@@ -283,6 +299,8 @@ def main():
         "phase_ms_per_step": {"traversal": tm["trace_ms"] / args.steps,
                               "path_recording": tm["record_ms"] / args.steps,
                               "columns_from_paths": tm["path_ms"] / args.steps,
+                              "columns_from_row_tiles": tm["tile_ms"] / args.steps,
+                              "row_tile_build": tm["tile_build_ms"] / args.steps,
                               "rate_equilibrium": tm["rate_ms"] / args.steps,
                               "tree_build": tm["build_ms"] / args.steps},
         "roofline": {"bound": "hbm", "kernel": kernels[dom]["kernel"],

@@ -216,9 +216,19 @@ int rrt_iterate_halos(rrt_ctx* ctx, int32_t max_iter, double tol, int32_t per_la
  *   RRT_TUNE_ADJOINT      transposed column product of rrt_backward over
  *                         recorded paths: 0 (default) = gather over paths
  *                         transposed once per geometry when memory allows,
- *                         else atomic scatter; 1 = always atomic scatter */
+ *                         else atomic scatter; 1 = always atomic scatter
+ *   RRT_TUNE_TILES        0 (default): columns from the recorded paths as
+ *                         recorded.  1: after a few column evaluations over the
+ *                         same recorded paths (and before the graph of a
+ *                         batched solve is captured), group consecutive rays
+ *                         into tiles whose particle values are staged in LDS,
+ *                         so each intersection streams 6 bytes instead of 8 and
+ *                         needs no global gather; the columns agree to FP64
+ *                         summation order.  The one-time build costs about as
+ *                         much as a hundred evaluations save on long rays, so
+ *                         it pays for long solves with short rays only. */
 enum { RRT_TUNE_TRACE_BLOCK = 1, RRT_TUNE_PACKET = 2, RRT_TUNE_PATH_GROUP = 3, RRT_TUNE_LEAF = 4,
-       RRT_TUNE_ADJOINT = 5 };
+       RRT_TUNE_ADJOINT = 5, RRT_TUNE_TILES = 6 };
 int rrt_set_tuning(rrt_ctx* ctx, int32_t key, int32_t value);
 
 /* Replace the state: x device double[n] in input order (checkpoint / resume,
@@ -250,15 +260,20 @@ int rrt_get_hits(rrt_ctx* ctx, int64_t cap, int64_t* row_off, int32_t* hit_j,
                  int32_t* hit_img);
 
 /* Accumulated device time (ms, HIP events on the context's stream) since the
- * last rrt_reset_timing, per phase: out8[0] traversal + column launches,
- * out8[1] rate + equilibrium, out8[2] tree builds, out8[3] number of traversal
- * launches, out8[4] path recording (count + record traversals), out8[5]
- * columns from recorded paths, out8[6] number of those launches, out8[7]
- * intersections held in the recorded paths (-1 when none are valid).
+ * last rrt_reset_timing, per phase, into host double out12[12]:
+ *   [0] traversal + column launches      [1] rate + equilibrium
+ *   [2] tree builds                      [3] number of traversal launches
+ *   [4] path recording (count + record traversals)
+ *   [5] columns from recorded paths      [6] number of those launches
+ *   [7] intersections held in the recorded paths (-1 when none are valid)
+ *   [8] columns from row tiles           [9] number of those launches
+ *   [10] row-tile builds                 [11] distinct particles summed over
+ *                                             the row tiles (-1 when none)
  * Timing is recorded only after rrt_enable_timing(ctx, 1); each timed phase
- * synchronises the stream. */
+ * synchronises the stream.  Phases of a batched solve replayed from a graph
+ * are not timed. */
 int rrt_enable_timing(rrt_ctx* ctx, int32_t on);
-int rrt_get_timing(rrt_ctx* ctx, double* out8);
+int rrt_get_timing(rrt_ctx* ctx, double* out12);
 int rrt_reset_timing(rrt_ctx* ctx);
 
 /* Intersection counters (host): out2[0] = intersections of the last iteration

@@ -18,6 +18,15 @@ constexpr int kMaxBins = 4096;
 constexpr int kDefaultLeaf = 8;
 // particles x rays: rays are indexed with 32-bit integers on the device
 constexpr int64_t kMaxRows = 2147483647;
+// distinct particles a row tile of the recorded paths may touch (its mu*x is
+// staged in LDS: 64 KiB)
+constexpr int kTileMaxSet = 16384;
+// The column products read recorded entries in aligned groups of four, so the
+// arrays holding them are allocated with this many entries to spare.
+constexpr int kPathPad = 4;
+// column evaluations over one set of recorded paths before its row tiles are
+// built (the build costs about as much as a few evaluations)
+constexpr int kTileAfter = 8;
 // A dispatch covers fewer than 2^32 work-items per grid dimension (the launch
 // packet's grid size is 32-bit).  Kernels whose index space can exceed that
 // (several lanes per ray or per particle) loop with the grid as stride and are
@@ -133,6 +142,20 @@ struct Ctx {
     uint64_t* tcol_off = nullptr; // [n + 1] start of each particle's entries
     bool tpaths_valid = false;
     bool tpaths_unfit = false;
+    // row tiles of the recorded paths (tiles.hip)
+    uint64_t* tile_off = nullptr;  // [n_tiles + 1] start of each tile's particle set
+    uint32_t* tile_set = nullptr;  // sorted distinct particles of each tile
+    uint16_t* tile_idx = nullptr;  // [path_hits] position of the entry's particle in its set
+    float* tile_fac = nullptr;     // [path_hits] K/h^2 of the entry
+    int tile_rows = 0;
+    int64_t n_tiles = 0;
+    int64_t tile_max_u = 0;
+    uint64_t tile_set_total = 0;  // distinct particles summed over the tiles
+    bool tiles_valid = false;
+    bool tiles_unfit = false;
+    int32_t use_tiles = 0;         // 1: build row tiles after kTileAfter evaluations
+    int path_evals = 0;            // column evaluations since the paths were recorded
+    bool capturing = false;        // a graph capture is in progress (no allocation)
 
     // tree
     Node* nodes = nullptr;
@@ -205,6 +228,7 @@ struct Ctx {
     bool timing = false;
     double t_trace = 0, t_rate = 0, t_build = 0, n_trace = 0;
     double t_record = 0, t_spmv = 0, n_spmv = 0;
+    double t_tile = 0, n_tile = 0, t_tile_build = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
 };
 
@@ -221,6 +245,10 @@ void fill_kernel_tables(KernelTables* host);
 hipError_t launch_columns(Ctx& c);
 hipError_t launch_record_paths(Ctx& c, const uint64_t* row_off, int2* path, uint64_t cap);
 hipError_t launch_path_columns(Ctx& c, int group);
+void drop_graph(Ctx& c);
+hipError_t build_tiles(Ctx& c);
+void free_tiles(Ctx& c);
+hipError_t launch_tile_columns(Ctx& c, int group);
 hipError_t launch_count_hits(Ctx& c, uint64_t* row_cnt);
 hipError_t launch_record_hits(Ctx& c, const uint64_t* row_off, int32_t* hit_j, int32_t* hit_img,
                               uint64_t cap);

@@ -15,6 +15,16 @@ struct rrt_ctx {
     Ctx c;
 };
 
+// a captured graph refers to the buffers it was captured with
+void rrt::drop_graph(Ctx& c)
+{
+    if (c.graph_exec) (void)hipGraphExecDestroy(c.graph_exec);
+    if (c.graph) (void)hipGraphDestroy(c.graph);
+    c.graph_exec = nullptr;
+    c.graph = nullptr;
+    c.graph_iters = 0;
+}
+
 namespace {
 
 thread_local std::string g_create_err;
@@ -156,12 +166,12 @@ void free_tpaths(Ctx& c)
     c.tpaths_unfit = false;
 }
 
-void drop_graph(Ctx& c);
-
 void free_paths(Ctx& c)
 {
     drop_graph(c);
     free_tpaths(c);
+    free_tiles(c);
+    c.path_evals = 0;
     if (c.row_off) (void)hipFree(c.row_off);
     if (c.path) (void)hipFree(c.path);
     c.row_off = nullptr;
@@ -172,14 +182,6 @@ void free_paths(Ctx& c)
     c.paths_unfit = false;
 }
 
-void drop_graph(Ctx& c)
-{
-    if (c.graph_exec) (void)hipGraphExecDestroy(c.graph_exec);
-    if (c.graph) (void)hipGraphDestroy(c.graph);
-    c.graph_exec = nullptr;
-    c.graph = nullptr;
-    c.graph_iters = 0;
-}
 
 // Count every ray's intersections, scan to row offsets, then record (tree index,
 // K/h^2) per intersection.  Leaves the paths invalid (and traversal in charge)
@@ -214,10 +216,13 @@ int record_paths(Ctx& c)
         return RRT_OK;
     }
     if (total > c.path_cap || !c.path) {
-        HIP_OK(dalloc(&c.path, (size_t)std::max<uint64_t>(total, 1)));
+        HIP_OK(dalloc(&c.path, (size_t)std::max<uint64_t>(total, 1) + kPathPad));
         c.path_cap = std::max<uint64_t>(total, 1);
     }
     drop_graph(c);
+    free_tpaths(c);                  // both are derived from the previous paths
+    free_tiles(c);
+    c.path_evals = 0;
     HIP_OK(launch_record_paths(c, c.row_off, c.path, total));
     c.path_hits = (int64_t)total;
     c.paths_valid = true;
@@ -241,11 +246,24 @@ int columns_impl(Ctx& c, int64_t* hits)
         // intersections per ray up to hundreds; short rays want fewer lanes
         const int group = c.path_group ? c.path_group
                           : mean >= 40 ? 32 : mean >= 16 ? 16 : 8;
+        if (c.use_tiles && !c.tiles_valid && !c.tiles_unfit && !c.capturing &&
+            ++c.path_evals > kTileAfter) {
+            ev_begin(c);
+            HIP_OK(build_tiles(c));
+            if (c.timing) c.t_tile_build += ev_end(c);
+        }
+        const bool tiles = c.tiles_valid && c.use_tiles;
         ev_begin(c);
-        HIP_OK(launch_path_columns(c, group));
+        if (tiles) HIP_OK(launch_tile_columns(c, group));
+        else HIP_OK(launch_path_columns(c, group));
         if (c.timing) {
-            c.t_spmv += ev_end(c);
-            c.n_spmv += 1;
+            if (tiles) {
+                c.t_tile += ev_end(c);
+                c.n_tile += 1;
+            } else {
+                c.t_spmv += ev_end(c);
+                c.n_spmv += 1;
+            }
         }
         *hits = c.path_hits;
     } else {
@@ -612,6 +630,8 @@ int rrt_build_tree(rrt_ctx* x)
     c.paths_valid = false;       // new geometry: the recorded paths no longer apply
     c.paths_unfit = false;
     free_tpaths(c);
+    free_tiles(c);
+    c.path_evals = 0;
     drop_graph(c);
     c.have_tree = true;
     c.have_columns = c.have_gamma = false;
@@ -899,15 +919,25 @@ int run_active_halos(Ctx& c, double tol, int32_t max_iter, int32_t per_launch)
     if (!c.graph_exec || c.graph_iters != per_launch || c.graph_tol != tol ||
         c.graph_max_iter != max_iter) {
         drop_graph(c);
+        // the replays should use the row tiles when the solve is long enough to
+        // pay for them; nothing may be allocated during the capture
+        if (c.use_tiles && c.paths_valid && !c.tiles_valid && !c.tiles_unfit &&
+            max_iter > kTileAfter) {
+            ev_begin(c);
+            HIP_OK(build_tiles(c));
+            if (timing) c.t_tile_build += ev_end(c);
+        }
         hipStream_t user = c.stream;
         c.stream = c.gstream;
         c.timing = false;
+        c.capturing = true;
         hipError_t e = hipStreamBeginCapture(c.gstream, hipStreamCaptureModeThreadLocal);
         int r = RRT_OK;
         for (int k = 0; k < per_launch && e == hipSuccess && r == RRT_OK; ++k)
             r = halo_iteration(c, tol, max_iter);
         hipGraph_t gr = nullptr;
         hipError_t e2 = hipStreamEndCapture(c.gstream, &gr);
+        c.capturing = false;
         c.stream = user;
         c.timing = timing;
         if (r != RRT_OK) {
@@ -1045,7 +1075,7 @@ int rrt_iterate_halos(rrt_ctx* x, int32_t max_iter, double tol, int32_t per_laun
             if (e == hipSuccess) e = dalloc(&c.row_off, (size_t)n_rows + 1);
             if (e == hipSuccess && max_group > 0 && (max_group > c.path_cap || !c.path)) {
                 drop_graph(c);
-                e = dalloc(&c.path, (size_t)max_group);
+                e = dalloc(&c.path, (size_t)max_group + kPathPad);
                 c.path_cap = e == hipSuccess ? max_group : 0;
             }
             std::vector<int32_t> mask(c.n_halo);
@@ -1067,7 +1097,10 @@ int rrt_iterate_halos(rrt_ctx* x, int32_t max_iter, double tol, int32_t per_laun
                                            hipMemcpyDeviceToHost, c.stream);
                     if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
                     if (e == hipSuccess) {
-                        // record only this group's rays: they are the active ones
+                        // record only this group's rays: they are the active ones;
+                        // tiles and transposed paths of the previous group go
+                        free_tpaths(c);
+                        free_tiles(c);
                         e = launch_record_paths(c, c.row_off, c.path, total);
                     }
                     if (!c.paths_valid) drop_graph(c);     // the graph held traversals
@@ -1086,6 +1119,7 @@ int rrt_iterate_halos(rrt_ctx* x, int32_t max_iter, double tol, int32_t per_laun
             c.paths_unfit = false;
             c.path_hits = 0;
             free_tpaths(c);
+            free_tiles(c);
             drop_graph(c);
             if (d_mask) (void)hipFree(d_mask);
             if (row_cnt) (void)hipFree(row_cnt);
@@ -1128,6 +1162,10 @@ int rrt_set_tuning(rrt_ctx* x, int32_t key, int32_t value)
         if (value != 0 && value != 8 && value != 16 && value != 32 && value != 64)
             return fail(c, RRT_E_ARG, "path group must be 0, 8, 16, 32 or 64");
         c.path_group = value;
+        break;
+    case RRT_TUNE_TILES:
+        if (value != 0 && value != 1) return fail(c, RRT_E_ARG, "tiles must be 0 or 1");
+        c.use_tiles = value;
         break;
     case RRT_TUNE_ADJOINT:
         if (value != 0 && value != 1) return fail(c, RRT_E_ARG, "adjoint mode must be 0 or 1");
@@ -1276,18 +1314,22 @@ int rrt_enable_timing(rrt_ctx* x, int32_t on)
     return RRT_OK;
 }
 
-int rrt_get_timing(rrt_ctx* x, double* out8)
+int rrt_get_timing(rrt_ctx* x, double* out12)
 {
-    if (!x || !out8) return RRT_E_ARG;
+    if (!x || !out12) return RRT_E_ARG;
     Ctx& c = x->c;
-    out8[0] = c.t_trace;
-    out8[1] = c.t_rate;
-    out8[2] = c.t_build;
-    out8[3] = c.n_trace;
-    out8[4] = c.t_record;
-    out8[5] = c.t_spmv;
-    out8[6] = c.n_spmv;
-    out8[7] = c.paths_valid ? (double)c.path_hits : -1.0;
+    out12[0] = c.t_trace;
+    out12[1] = c.t_rate;
+    out12[2] = c.t_build;
+    out12[3] = c.n_trace;
+    out12[4] = c.t_record;
+    out12[5] = c.t_spmv;
+    out12[6] = c.n_spmv;
+    out12[7] = c.paths_valid ? (double)c.path_hits : -1.0;
+    out12[8] = c.t_tile;
+    out12[9] = c.n_tile;
+    out12[10] = c.t_tile_build;
+    out12[11] = c.tiles_valid ? (double)c.tile_set_total : -1.0;
     return RRT_OK;
 }
 
@@ -1297,6 +1339,7 @@ int rrt_reset_timing(rrt_ctx* x)
     Ctx& c = x->c;
     c.t_trace = c.t_rate = c.t_build = c.n_trace = 0.0;
     c.t_record = c.t_spmv = c.n_spmv = 0.0;
+    c.t_tile = c.n_tile = c.t_tile_build = 0.0;
     c.total_hits = 0;
     return RRT_OK;
 }

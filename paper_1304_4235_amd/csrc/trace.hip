@@ -520,9 +520,11 @@ k_path_columns(const uint64_t* __restrict__ row_off, const int2* __restrict__ pa
         if (seg_active && seg_active[seg_of[row % n]] == 0) continue;
         const uint64_t a = row_off[row], b = row_off[row + 1];
         double acc = 0.0;
-        // four independent streaming loads in flight per lane before any is
-        // used; entries past the row end read as (particle 0, factor 0) and
-        // add nothing
+        // Lanes stride through the row one entry at a time, so the particle
+        // gathers of one instruction are consecutive intersections along the
+        // ray and share cache lines (measured: grouping four consecutive
+        // entries per lane is slower here).  Four streaming loads in flight per
+        // lane; entries past the row end read as (particle 0, factor 0).
         for (uint64_t e = a + lane; e < b; e += 4 * G) {
             const long long v0 = __builtin_nontemporal_load(p + e);
             const long long v1 = e + G < b ? __builtin_nontemporal_load(p + e + G) : 0ll;

@@ -18,7 +18,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librrt.so")
 
 RRT_OK, RRT_NOT_CONVERGED = 0, 1
-TUNE_KEYS = {"trace_block": 1, "packet": 2, "path_group": 3, "leaf": 4, "adjoint_scatter": 5}
+TUNE_KEYS = {"trace_block": 1, "packet": 2, "path_group": 3, "leaf": 4, "adjoint_scatter": 5,
+             "tiles": 6}
 ERRORS = {-1: "RRT_E_ARG", -2: "RRT_E_HIP", -3: "RRT_E_INPUT", -4: "RRT_E_STATE",
           -5: "RRT_E_NOMEM", -6: "RRT_E_CAPACITY"}
 
@@ -170,7 +171,8 @@ class Solver:
         self.n_halo = 1
 
     def set_tuning(self, **kw):
-        """Launch knobs: trace_block, packet (1 or 64), path_group, leaf, adjoint_scatter (0/1)."""
+        """Launch knobs: trace_block, packet (1 or 64), path_group, leaf, adjoint_scatter (0/1),
+        tiles (0/1)."""
         for k, v in kw.items():
             self._check(_lib.rrt_set_tuning(self._h, TUNE_KEYS[k], int(v)), f"rrt_set_tuning {k}")
 
@@ -316,13 +318,15 @@ class Solver:
         self._check(_lib.rrt_reset_timing(self._h), "rrt_reset_timing")
 
     def timing(self) -> dict:
-        out = np.zeros(8)
+        out = np.zeros(12)
         self._check(_lib.rrt_get_timing(self._h, out.ctypes.data), "rrt_get_timing")
         cnt = np.zeros(2, np.int64)
         self._check(_lib.rrt_get_counters(self._h, cnt.ctypes.data), "rrt_get_counters")
         return dict(trace_ms=out[0], rate_ms=out[1], build_ms=out[2], n_trace=int(out[3]),
                     record_ms=out[4], path_ms=out[5], n_path=int(out[6]),
-                    path_hits=int(out[7]), last_hits=int(cnt[0]), total_hits=int(cnt[1]))
+                    path_hits=int(out[7]), tile_ms=out[8], n_tile=int(out[9]),
+                    tile_build_ms=out[10], tile_set_total=int(out[11]),
+                    last_hits=int(cnt[0]), total_hits=int(cnt[1]))
 
     # -- convenience ------------------------------------------------------
     @classmethod

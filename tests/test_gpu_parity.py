@@ -393,6 +393,54 @@ def test_recorded_paths_match_traversal():
                                b.compute_columns()[0].cpu().numpy(), rtol=1e-12, atol=0)
 
 
+def _tile_workload(which):
+    if which == "halo_small":
+        return W.isothermal_halo(n=20000, seed=23)
+    if which == "halo_full":
+        return W.make_config(1)
+    if which == "field_small":
+        return W.lognormal_field(n_grid=24, box=1875.0, n_bins=16, max_iter=3)
+    return W.make_config(0)                                   # periodic lattice
+
+
+@pytest.mark.parametrize("which", ["halo_small", "halo_full", "field_small", "lattice"])
+def test_row_tiles_give_identical_columns(which):
+    """After a few evaluations over the same recorded paths the columns come
+    from row tiles (each tile's particle values staged in LDS, 16-bit local
+    indices): the same products as the plain product over the recorded paths,
+    so the columns agree to FP64 summation order, for any state."""
+    wl = _tile_workload(which)
+    s = _solver(wl)
+    rng = np.random.default_rng(9)
+    xs = [np.minimum(oracle.x_thin(wl) * rng.uniform(1, 1e3, wl.n), 0.99) for _ in range(2)]
+    s.set_tuning(tiles=0)
+    ref = []
+    for x in xs:
+        s.set_state(torch.tensor(x))
+        N, _ = s.compute_columns()
+        ref.append(N.clone())
+    s.set_tuning(tiles=1)
+    s.enable_timing(True)
+    for _ in range(10):
+        s.compute_columns(want_N=False, count=False)
+    tm = s.timing()
+    assert tm["tile_set_total"] > 0 and tm["n_tile"] >= 1, "row tiles were not built"
+    _say(which, "tiles: distinct particles staged", tm["tile_set_total"],
+         "of", tm["path_hits"], "intersections")
+    for x, r in zip(xs, ref):
+        s.set_state(torch.tensor(x))
+        N, _ = s.compute_columns()
+        np.testing.assert_allclose(N.cpu().numpy(), r.cpu().numpy(), rtol=1e-13, atol=0)
+    if which == "halo_small":
+        src = np.arange(0, wl.n, 401)
+        x = xs[1]
+        ref_o = oracle.step(wl, x, sources=src)
+        _check_columns(N.cpu().numpy()[src], ref_o["N"])
+    # a new geometry drops the tiles with the recorded paths
+    s.build_tree()
+    assert s.timing()["tile_set_total"] == -1
+
+
 def test_path_budget_fallback_and_error():
     from paper_1304_4235_amd import RRTError
     wl = W.isothermal_halo(n=4096, seed=22)
