@@ -59,6 +59,9 @@ def lib():
         L.orc_solve.argtypes = [i64, vp, vp, vp, vp, vp, i32, vp, i32, vp, vp, d, d, d, i32,
                                 vp, d, i32, vp, vp, vp, vp, vp]
         L.orc_solve.restype = C.c_int
+        L.orc_solve_rule.argtypes = [i64, vp, vp, vp, vp, vp, i32, vp, i32, vp, vp, d, d, d,
+                                     i32, d, d, i32, i32, d, i32, vp, vp, vp, vp, vp]
+        L.orc_solve_rule.restype = C.c_int
         L.orc_morton.argtypes = [i64, vp, vp]
         L.orc_lbvh.argtypes = [i64, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]
         L.orc_lbvh.restype = i64
@@ -240,6 +243,35 @@ def solve(wl, max_iter: int = None, tol: float = None, x_init=None, rtol=DEFAULT
     assert rc == 0
     k = int(it[0])
     return dict(x_hist=xh[: k + 1], lnG_hist=lh[:k], N_last=Nl, iters=k, maxdx=md[:k])
+
+
+def solve_rule(wl, tau_skip: float = 0.0, tau_case_b: float = float("inf"),
+               relative: bool = False, n_blocks: int = 1, max_iter: int = None,
+               tol: float = None, rtol=DEFAULT_RTOL, n_threads: int = None):
+    """The paper's update rule (Sec. 4): tau_skip, case B where tau_eff >=
+    tau_case_b, absolute or relative convergence, and updates in n_blocks
+    blocks of the density-descending order (1 = order-independent).
+    Returns dict(x_hist, lnG_hist, skipped, iters, maxdx)."""
+    n = wl.n
+    mi = wl.max_iter if max_iter is None else max_iter
+    tl = wl.tol if tol is None else tol
+    xh = np.zeros((mi + 1, n))
+    lh = np.zeros((mi, n))
+    sk = np.zeros(n, np.int32)
+    it = np.zeros(1, np.int32)
+    md = np.zeros(max(1, mi))
+    nt = N_THREADS if n_threads is None else n_threads
+    rc = lib().orc_solve_rule(n, _p(_c(wl.pos, np.float32)), _p(_c(wl.h, np.float32)),
+                              _p(_c(wl.mu, np.float32)), _p(_c(wl.n_H, np.float32)),
+                              _p(_c(wl.T, np.float32)), wl.n_ray, _p(_c(wl.dirs, np.float64)),
+                              wl.n_bins, _p(_c(wl.sigma, np.float64)), _p(_c(wl.w, np.float64)),
+                              wl.l_ray, wl.box, tl, mi, float(tau_skip), float(tau_case_b),
+                              int(bool(relative)), int(n_blocks), rtol, nt, _p(xh), _p(lh),
+                              _p(sk), _p(it), _p(md))
+    assert rc == 0, rc
+    k = int(it[0])
+    return dict(x_hist=xh[: k + 1], lnG_hist=lh[:k], skipped=sk.astype(bool), iters=k,
+                maxdx=md[:k])
 
 
 # ----------------------------------------------------------------------------

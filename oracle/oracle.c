@@ -411,6 +411,108 @@ int orc_solve(int64_t n, const float* pos, const float* h, const float* mu, cons
 }
 
 /* ------------------------------------------------------------------------- */
+/* The paper's own update rule (Sec. 4, implementation details):              */
+/*  - every particle starts at its optically thin neutral fraction;           */
+/*  - particles whose first shielded rate gives tau_eff < tau_skip keep that  */
+/*    value for good and are not traced again;                               */
+/*  - case B recombination for particles with tau_eff >= tau_case_b (case A  */
+/*    otherwise; +inf = case A throughout);                                  */
+/*  - convergence on max |dx| (relative != 0: max |dx| / x) < tol;           */
+/*  - particles are visited from high to low density (ties: lower index      */
+/*    first) in n_blocks consecutive blocks: each block's rates see every    */
+/*    update of the blocks before it in the same sweep.  n_blocks = 1 is the */
+/*    order-independent update, n_blocks = n updates one particle at a time. */
+/* lnG_hist[it][p] holds the most recent rate of p after sweep it; skipped   */
+/* receives 1 for the particles that stopped after their first rate.         */
+/* ------------------------------------------------------------------------- */
+static const float* g_sort_nH;
+static int cmp_density_desc(const void* a, const void* b)
+{
+    const int64_t i = *(const int64_t*)a, j = *(const int64_t*)b;
+    const float ni = g_sort_nH[i], nj = g_sort_nH[j];
+    if (ni > nj) return -1;
+    if (ni < nj) return 1;
+    return (i > j) - (i < j);
+}
+
+int orc_solve_rule(int64_t n, const float* pos, const float* h, const float* mu, const float* nH,
+                   const float* T, int32_t n_ray, const double* dirs, int32_t n_bins,
+                   const double* sigma, const double* w, double L, double box, double tol,
+                   int32_t max_iter, double tau_skip, double tau_case_b, int32_t relative,
+                   int32_t n_blocks, double rtol, int32_t n_threads,
+                   double* x_hist /*[(max_iter+1)][n]*/, double* lnG_hist /*[max_iter][n]*/,
+                   int32_t* skipped /*[n]*/, int32_t* iters_done, double* maxdx_hist)
+{
+    if (n_blocks < 1 || n_blocks > n) return -1;
+    double thin = 0.0;
+    for (int b = 0; b < n_bins; ++b) thin += w[b] * sigma[b];
+    double* x = (double*)malloc(sizeof(double) * n);
+    double* lnG_all = (double*)malloc(sizeof(double) * n);
+    double* al = (double*)malloc(sizeof(double) * n);
+    double* alB = (double*)malloc(sizeof(double) * n);
+    double* ga = (double*)malloc(sizeof(double) * n);
+    int64_t* order = (int64_t*)malloc(sizeof(int64_t) * n);
+    int64_t* src = (int64_t*)malloc(sizeof(int64_t) * n);
+    int32_t* skip = (int32_t*)calloc((size_t)n, sizeof(int32_t));
+    const int64_t bs = (n + n_blocks - 1) / n_blocks;
+    double* Nc = (double*)malloc(sizeof(double) * bs * n_ray);
+    double* lnG = (double*)malloc(sizeof(double) * bs);
+    double* G = (double*)malloc(sizeof(double) * bs);
+    double* tau = (double*)malloc(sizeof(double) * bs);
+    if (!x || !lnG_all || !al || !alB || !ga || !order || !src || !skip || !Nc || !lnG || !G ||
+        !tau)
+        return -2;
+    for (int64_t p = 0; p < n; ++p) {
+        order[p] = p;
+        al[p] = orc_alpha_A((double)T[p]);
+        alB[p] = orc_alpha_B((double)T[p]);
+        ga[p] = orc_gamma_coll((double)T[p]);
+        x[p] = orc_xeq(thin, (double)nH[p], al[p], ga[p], 0.0);
+        lnG_all[p] = log(thin);
+    }
+    g_sort_nH = nH;
+    qsort(order, (size_t)n, sizeof(int64_t), cmp_density_desc);
+    if (x_hist) memcpy(x_hist, x, sizeof(double) * n);
+    int it = 0;
+    for (it = 0; it < max_iter; ++it) {
+        double mdx = 0.0;
+        for (int64_t b0 = 0; b0 < n; b0 += bs) {
+            const int64_t b1 = b0 + bs < n ? b0 + bs : n;
+            int64_t m = 0;
+            for (int64_t q = b0; q < b1; ++q)
+                if (!skip[order[q]]) src[m++] = order[q];
+            if (m == 0) continue;
+            orc_columns(n, pos, h, mu, x, n_ray, dirs, L, box, m, src, rtol, 1, Nc, NULL, NULL,
+                        NULL, NULL, n_threads);
+            orc_gamma(m, n_ray, Nc, n_bins, sigma, w, lnG, G, tau);
+            for (int64_t i = 0; i < m; ++i) {
+                const int64_t p = src[i];
+                lnG_all[p] = lnG[i];
+                if (it == 0 && tau[i] < tau_skip) {
+                    skip[p] = 1;
+                    continue;
+                }
+                const double a = tau[i] >= tau_case_b ? alB[p] : al[p];
+                const double xn = orc_xeq(G[i], (double)nH[p], a, ga[p], 0.0);
+                double dx = fabs(xn - x[p]);
+                if (relative) dx /= x[p];
+                if (dx > mdx) mdx = dx;
+                x[p] = xn;
+            }
+        }
+        if (x_hist) memcpy(x_hist + (size_t)(it + 1) * n, x, sizeof(double) * n);
+        if (lnG_hist) memcpy(lnG_hist + (size_t)it * n, lnG_all, sizeof(double) * n);
+        if (maxdx_hist) maxdx_hist[it] = mdx;
+        if (mdx < tol) { ++it; break; }
+    }
+    if (skipped) memcpy(skipped, skip, sizeof(int32_t) * n);
+    if (iters_done) *iters_done = it;
+    free(x); free(lnG_all); free(al); free(alB); free(ga); free(order); free(src); free(skip);
+    free(Nc); free(lnG); free(G); free(tau);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Reference radix tree.  Keys: 63-bit Morton codes (21 bits per axis, x in   */
 /* the highest position of each triple) of positions quantised over the      */
 /* cube of side max extent anchored at the minimum corner; ties broken by the */

@@ -31,6 +31,12 @@ int orc_solve(int64_t n, const float* pos, const float* h, const float* mu, cons
               int32_t max_iter, const double* x_init, double rtol, int32_t n_threads,
               double* x_hist, double* lnG_hist, double* N_last, int32_t* iters_done,
               double* maxdx_hist);
+int orc_solve_rule(int64_t n, const float* pos, const float* h, const float* mu, const float* nH,
+                   const float* T, int32_t n_ray, const double* dirs, int32_t n_bins,
+                   const double* sigma, const double* w, double L, double box, double tol,
+                   int32_t max_iter, double tau_skip, double tau_case_b, int32_t relative,
+                   int32_t n_blocks, double rtol, int32_t n_threads, double* x_hist,
+                   double* lnG_hist, int32_t* skipped, int32_t* iters_done, double* maxdx_hist);
 void orc_morton(int64_t n, const float* pos, uint64_t* codes);
 int64_t orc_lbvh(int64_t n, const float* pos, const float* h, int32_t leaf_max,
                  int32_t* perm, uint64_t* codes_sorted, float* node_lo, float* node_hi,

@@ -404,6 +404,95 @@ def test_resume_from_state_is_exact():
 
 
 # ---------------------------------------------------------------------------
+# the paper's own update rule (Sec. 4): tau_skip, case B where tau_eff >= 1,
+# relative convergence, density-ordered updates
+# ---------------------------------------------------------------------------
+def _rule_halo():
+    return W.isothermal_halo(n=240, seed=61, n_bins=6, n_peak=30.0)
+
+
+def test_rule_defaults_are_the_order_independent_update():
+    wl = _small_lattice()
+    a = oracle.solve(wl, max_iter=4, tol=0.0)
+    b = oracle.solve_rule(wl, max_iter=4, tol=0.0)
+    np.testing.assert_array_equal(a["x_hist"], b["x_hist"])
+    np.testing.assert_array_equal(a["lnG_hist"], b["lnG_hist"])
+    assert not b["skipped"].any()
+
+
+@pytest.mark.parametrize("n_blocks", [1, 5, 240])
+def test_rule_density_order_against_single_source_steps(n_blocks):
+    """Blocked Gauss-Seidel in density-descending order, redone by hand: each
+    block's particles take one order-independent step (oracle.step restricted
+    to them) from the state that already holds the earlier blocks' updates."""
+    wl = _rule_halo()
+    r = oracle.solve_rule(wl, n_blocks=n_blocks, max_iter=3, tol=0.0)
+    order = sorted(range(wl.n), key=lambda i: (-float(wl.n_H[i]), i))
+    size = -(-wl.n // n_blocks)
+    x = oracle.x_thin(wl)
+    for k in range(3):
+        for b0 in range(0, wl.n, size):
+            blk = np.array(order[b0:b0 + size])
+            x[blk] = oracle.step(wl, x, sources=blk)["x_new"]
+        np.testing.assert_allclose(r["x_hist"][k + 1], x, rtol=1e-13)
+
+
+def test_rule_density_order_converges_to_the_same_fixed_point():
+    """Gauss-Seidel needs fewer sweeps here and reaches the fixed point of the
+    order-independent update; from x_thin its iterates are monotone too."""
+    wl = _rule_halo()
+    j = oracle.solve_rule(wl, max_iter=200, tol=1e-9)
+    g = oracle.solve_rule(wl, n_blocks=wl.n, max_iter=200, tol=1e-9)
+    assert g["iters"] < j["iters"]
+    np.testing.assert_allclose(g["x_hist"][-1], j["x_hist"][-1], rtol=1e-6)
+    assert np.all(np.diff(g["x_hist"], axis=0) >= -1e-15 * g["x_hist"][1:])
+
+
+def test_rule_case_b_in_thick_gas_and_case_a_in_thin_gas():
+    """Deep in the lattice Gamma underflows, so the converged x is the
+    collisional root x_ce = alpha / (alpha + gamma) with case B rates where
+    tau_eff >= 1 (eq. xroots at Gamma = 0); optically thin gas is untouched."""
+    wl = W.make_config(0, n_side_lattice=8, box=50.0, max_iter=30)
+    wl.mu = wl.mu * np.float32(8.0)                  # thicker: tau_eff ~ 1e3
+    rb = oracle.solve_rule(wl, tau_case_b=1.0, max_iter=30, tol=1e-12)
+    aB, g = oracle.alpha_B(1e4)[0], oracle.gamma_coll(1e4)[0]
+    np.testing.assert_allclose(rb["x_hist"][-1], aB / (aB + g), rtol=1e-9)
+    ra = oracle.solve_rule(wl, max_iter=30, tol=1e-12)
+    aA = oracle.alpha_A(1e4)[0]
+    np.testing.assert_allclose(ra["x_hist"][-1], aA / (aA + g), rtol=1e-9)
+    thin = W.make_config(0, n_side_lattice=6, box=37.5, max_iter=4)
+    thin.mu = thin.mu * np.float32(1e-6)             # tau_eff ~ 1e-6
+    t_a = oracle.solve_rule(thin, max_iter=4, tol=0.0)
+    t_b = oracle.solve_rule(thin, tau_case_b=1.0, max_iter=4, tol=0.0)
+    np.testing.assert_array_equal(t_a["x_hist"], t_b["x_hist"])
+
+
+def test_rule_tau_skip_freezes_thin_particles():
+    """The skipped set is the particles whose first rate (an order-independent
+    step from x_thin) gives tau_eff < tau_skip; they keep x_thin exactly."""
+    wl = _rule_halo()
+    x0 = oracle.x_thin(wl)
+    first = oracle.step(wl, x0)
+    tau_skip = float(np.median(first["tau"]))
+    r = oracle.solve_rule(wl, tau_skip=tau_skip, max_iter=6, tol=0.0)
+    np.testing.assert_array_equal(r["skipped"], first["tau"] < tau_skip)
+    np.testing.assert_array_equal(r["x_hist"][-1][r["skipped"]], x0[r["skipped"]])
+    moved = ~r["skipped"]
+    assert np.all(r["x_hist"][-1][moved] > x0[moved])
+
+
+def test_rule_relative_convergence():
+    """The stop test max |dx| / x < tol, recomputed from the iterates."""
+    wl = _rule_halo()
+    tol = 2e-2
+    r = oracle.solve_rule(wl, relative=True, max_iter=100, tol=tol)
+    xh = r["x_hist"]
+    rel = np.max(np.abs(np.diff(xh, axis=0)) / xh[:-1], axis=1)
+    np.testing.assert_allclose(r["maxdx"], rel, rtol=1e-12)
+    assert rel[-1] < tol and np.all(rel[:-1] >= tol)
+
+
+# ---------------------------------------------------------------------------
 # reference tree
 # ---------------------------------------------------------------------------
 def _tree_case(n, seed=0, dup=False):
