@@ -183,6 +183,8 @@ def main():
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--leaf", type=int, default=0)
     ap.add_argument("--traversal", type=int, default=0, help="0 wave-cooperative, 1 per lane")
+    ap.add_argument("--rules", type=int, default=1,
+                    help="also time the solve under the paper's update rules (1 = yes)")
     ap.add_argument("--tiles", type=int, default=0,
                     help="1: columns from row tiles once the recorded paths have been reused")
     ap.add_argument("--paths", type=int, default=-1,
@@ -315,6 +317,29 @@ def main():
     }
     print(f"timed {args.steps} steps in {dt:.3f} s; iterations {iters}", file=sys.stderr,
           flush=True)
+    if args.rules and wl.tol > 0:
+        # time to solution under the paper's update rules (Sec. 4), same geometry
+        # and recorded paths; the order-independent case A solve is the timed step
+        rules = {"density_blocks_16": dict(n_blocks=16),
+                 "paper": dict(tau_skip=1e-4, tau_case_b=1.0, relative=True, n_blocks=16)}
+        # the timed solve without its tree build and path recording (the rule
+        # solves below reuse both)
+        res = {"order_independent": {"sweeps": int(iters[-1]),
+                                     "ms": (dt * 1e3 - tm["build_ms"] - tm["record_ms"])
+                                     / args.steps}}
+        for name, rule in rules.items():
+            print(f"update rule {name}", file=sys.stderr, flush=True)
+            s.set_update_rule(**rule)
+            s.set_state(None)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = s.iterate(wl.max_iter, wl.tol, want_x=False)
+            torch.cuda.synchronize()
+            res[name] = {"rule": rule, "sweeps": r["iters"], "converged": r["converged"],
+                         "ms": (time.perf_counter() - t0) * 1e3}
+        s.set_update_rule()
+        s.set_state(None)
+        out["update_rules"] = res
     if args.adjoint:
         # forward+adjoint against the plain forward, K frozen at the solve's iterations
         K = int(iters[-1])

@@ -154,15 +154,39 @@ int rrt_compute_columns(rrt_ctx* ctx, double* N_out, int64_t* n_hits_out);
 int rrt_compute_gamma(rrt_ctx* ctx, double* lnG_out, double* G_out, float* tau_out);
 
 /* One equilibrium update from the current Gamma (Appendix C.3, physical root
- * x_-): x <- x_-(Gamma, n_H, T).  x_out: device double[n] (nullable);
- * max_dx_out: host max |x_new - x_old| (nullable, syncs). */
+ * x_-): x <- x_-(Gamma, n_H, T) with case A rates, for every particle
+ * (the update rule below applies to rrt_iterate_equilibrium only).
+ * x_out: device double[n] (nullable); max_dx_out: host max |x_new - x_old|
+ * (nullable, syncs). */
 int rrt_update_equilibrium(rrt_ctx* ctx, double* x_out, double* max_dx_out);
 
-/* The fixed point (Sec. 3.3, Sec. 4): repeat columns -> Gamma -> x until
- * max |dx| < tol or max_iter iterations.  x_out: device double[n] (nullable).
- * iters_done, max_dx_out: host (nullable).  Returns RRT_NOT_CONVERGED if
- * max_iter was reached with max|dx| >= tol.  Synchronises once per iteration
- * (8 bytes) for the convergence test. */
+/* The update rule of rrt_iterate_equilibrium, after the paper's own scheme
+ * (Sec. 4, implementation details).  Defaults (0, +inf, 0, 1) give the
+ * order-independent case A update that every other entry point assumes.
+ *   tau_skip    >= 0: particles whose first shielded rate of the solve gives
+ *               tau_eff < tau_skip keep their starting state for good and cast
+ *               no rays afterwards (0 = none are frozen);
+ *   tau_case_b  > 0: case B recombination (Hui & Gnedin 1997) for particles
+ *               with tau_eff >= tau_case_b, case A below (+inf = case A only);
+ *   relative    1: convergence on max |dx| / x instead of max |dx|;
+ *   n_blocks    1..2^20: each sweep visits the particles from high to low
+ *               n_H (ties: lower input index first) in n_blocks blocks of
+ *               ceil(n / n_blocks); a block's rates see every update of the
+ *               blocks before it (1 = every particle from the same state).
+ * tau_eff decisions are taken in FP64 from ln Gamma.  While a rule other than
+ * the default is set, rrt_forward, rrt_backward and rrt_iterate_halos return
+ * RRT_E_STATE.  Intersections are not counted for sweeps that skip rays over
+ * recorded paths (rrt_get_counters reports -1 for the last sweep). */
+int rrt_set_update_rule(rrt_ctx* ctx, double tau_skip, double tau_case_b, int32_t relative,
+                        int32_t n_blocks);
+
+/* The fixed point (Sec. 3.3, Sec. 4): repeat columns -> Gamma -> x until the
+ * largest change of a sweep is below tol or max_iter sweeps, under the update
+ * rule above.  x_out: device double[n] (nullable).  iters_done, max_dx_out:
+ * host (nullable).  Returns RRT_NOT_CONVERGED if max_iter was reached without
+ * convergence.  Synchronises once per sweep (16 bytes) for the convergence
+ * test; the first call of rrt_set_update_rule's density order also copies
+ * n_H to the host once. */
 int rrt_iterate_equilibrium(rrt_ctx* ctx, int32_t max_iter, double tol, double* x_out,
                             int32_t* iters_done, double* max_dx_out);
 

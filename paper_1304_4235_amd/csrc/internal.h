@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -58,6 +59,9 @@ struct TraceGeom {
     const int32_t* seg_root;    // [n_halo]
     const int32_t* seg_end;     // [n_halo]
     const int32_t* seg_active;  // [n_halo] or null
+    // column evaluations only: rays of sources with want[p] == 0 are skipped
+    // (their columns keep their previous values); null = every source
+    const uint8_t* want;
     double L;              // segment length
     double box;            // periodic side, 0 = isolated
     double plo[3], phi[3]; // bounds of particle positions
@@ -154,6 +158,20 @@ struct Ctx {
     bool tiles_valid = false;
     bool tiles_unfit = false;
     int32_t use_tiles = 0;         // 1: build row tiles after kTileAfter evaluations
+    // the paper's update rule for the fixed point (rrt_set_update_rule)
+    double rule_tau_skip = 0.0;    // first-sweep tau_eff below this: frozen
+    double rule_tau_case_b = HUGE_VAL;   // case B recombination from this tau_eff
+    int32_t rule_relative = 0;     // convergence on max |dx| / x
+    int32_t rule_blocks = 1;       // blocks of the density-descending order per sweep
+    double* alphaB_s = nullptr;    // [n] case B coefficient, tree order
+    uint8_t* skip_s = nullptr;     // [n] frozen after the first sweep
+    uint8_t* want_s = nullptr;     // [n] updated in the current block step
+    int32_t* block_s = nullptr;    // [n] block of the density order, tree order
+    int32_t blocks_for = 0;        // rule_blocks that block_s was computed for (0: none)
+    int32_t* block_list = nullptr; // [n] tree positions grouped by block (ascending within)
+    std::vector<int64_t> block_off;  // [rule_blocks + 1] start of each block in block_list
+    const int32_t* row_list = nullptr;   // the recorded-path product's sources, or null (all)
+    int64_t row_list_n = 0;
     int path_evals = 0;            // column evaluations since the paths were recorded
     bool capturing = false;        // a graph capture is in progress (no allocation)
 
@@ -247,6 +265,8 @@ hipError_t launch_record_paths(Ctx& c, const uint64_t* row_off, int2* path, uint
 hipError_t launch_path_columns(Ctx& c, int group);
 void drop_graph(Ctx& c);
 hipError_t build_tiles(Ctx& c);
+hipError_t launch_want(Ctx& c, int block, bool use_skip);
+hipError_t launch_block_ids(Ctx& c, const int32_t* block_in);
 void free_tiles(Ctx& c);
 hipError_t launch_tile_columns(Ctx& c, int group);
 hipError_t launch_count_hits(Ctx& c, uint64_t* row_cnt);
@@ -269,7 +289,7 @@ int64_t adj_waves(const Ctx& c);
 
 // ---- launchers (rate.hip) ----
 hipError_t launch_init_state(Ctx& c, bool use_given);
-hipError_t launch_gamma(Ctx& c, bool update_x);
+hipError_t launch_gamma(Ctx& c, bool update_x, bool first_sweep = false);
 hipError_t launch_update_x(Ctx& c);
 hipError_t launch_to_input_order_d(Ctx& c, const double* src, double* dst, int32_t stride);
 hipError_t launch_to_input_order_f(Ctx& c, const float* src, float* dst);

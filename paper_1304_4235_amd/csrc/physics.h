@@ -12,6 +12,13 @@ __device__ __forceinline__ double alpha_caseA(double T)
     return 1.269e-13 * pow(lam, 1.503) / pow(1.0 + pow(lam / 0.522, 0.470), 1.923);
 }
 
+// Case B recombination coefficient (Hui & Gnedin 1997 fit), cm^3 s^-1.
+__device__ __forceinline__ double alpha_caseB(double T)
+{
+    const double lam = 2.0 * 157807.0 / T;
+    return 2.753e-14 * pow(lam, 1.5) / pow(1.0 + pow(lam / 2.74, 0.407), 2.242);
+}
+
 // Collisional ionisation coefficient (Cen 1992 fit), cm^3 s^-1.
 __device__ __forceinline__ double gamma_collisional(double T)
 {

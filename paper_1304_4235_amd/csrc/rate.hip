@@ -30,8 +30,9 @@ constexpr int kBlock = 256;
 __global__ void k_init_state(const int32_t* __restrict__ perm, const float* __restrict__ T,
                              const double* __restrict__ x_init, const float* __restrict__ nH_s,
                              const double* __restrict__ mu_s, int64_t n, double gthin,
-                             double* __restrict__ alpha, double* __restrict__ gcoll,
-                             double* __restrict__ x_s, float* __restrict__ mux)
+                             double* __restrict__ alpha, double* __restrict__ alphaB,
+                             double* __restrict__ gcoll, double* __restrict__ x_s,
+                             float* __restrict__ mux)
 {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -39,11 +40,24 @@ __global__ void k_init_state(const int32_t* __restrict__ perm, const float* __re
     double Tj = (double)T[j];
     double al = alpha_caseA(Tj), gc = gamma_collisional(Tj);
     alpha[i] = al;
+    alphaB[i] = alpha_caseB(Tj);
     gcoll[i] = gc;
     double x = x_init ? x_init[j] : x_minus(gthin, (double)nH_s[i], al, gc);
     x_s[i] = x;
     mux[i] = (float)(mu_s[i] * x);
 }
+
+// The paper's update rule (Sec. 4): which particles this step updates, the
+// frozen set decided on the first sweep, case B from a tau_eff threshold, and
+// relative changes for the convergence test.
+struct RateRule {
+    const uint8_t* want;      // null = every particle
+    uint8_t* skip;            // first sweep: set for tau_eff < tau_skip (null = none)
+    double tau_skip;
+    double tau_case_b;        // +inf = case A throughout
+    const double* alphaB;
+    int relative;
+};
 
 // One thread per particle: rays, then bins; optionally the equilibrium update.
 __global__ void __launch_bounds__(256)
@@ -54,12 +68,14 @@ k_gamma(const double* __restrict__ N, int64_t n, int n_ray, int n_bins,
         const double* __restrict__ mu_s, const double* __restrict__ alpha,
         const double* __restrict__ gcoll, double* __restrict__ x_s, float* __restrict__ mux,
         unsigned long long* __restrict__ maxdx_bits, const int32_t* __restrict__ seg_of,
-        const int32_t* __restrict__ seg_active, unsigned long long* __restrict__ seg_maxdx)
+        const int32_t* __restrict__ seg_active, unsigned long long* __restrict__ seg_maxdx,
+        RateRule rule)
 {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     double dx = 0.0;
     const int h = (seg_of && i < n) ? seg_of[i] : -1;
-    const bool live = !(seg_active && h >= 0 && seg_active[h] == 0);
+    const bool live = !(seg_active && h >= 0 && seg_active[h] == 0) &&
+                      !(rule.want && i < n && rule.want[i] == 0);
     if (i < n && live) {
         double m = -INFINITY, s = 0.0;
         for (int k = 0; k < n_ray; ++k) {
@@ -89,9 +105,14 @@ k_gamma(const double* __restrict__ N, int64_t n, int n_ray, int n_bins,
         if (lnG) lnG[i] = l;
         if (G) G[i] = g;
         if (tau) tau[i] = (float)(ln_gthin - l);
-        if (update_x) {
-            double xn = x_minus(g, (double)nH_s[i], alpha[i], gcoll[i]);
+        const double te = ln_gthin - l;              // tau_eff in FP64 decides
+        if (update_x && rule.skip && te < rule.tau_skip) {
+            rule.skip[i] = 1;                         // keeps its state for good
+        } else if (update_x) {
+            const double al = te >= rule.tau_case_b ? rule.alphaB[i] : alpha[i];
+            double xn = x_minus(g, (double)nH_s[i], al, gcoll[i]);
             dx = fabs(xn - x_s[i]);
+            if (rule.relative) dx /= x_s[i];
             x_s[i] = xn;
             mux[i] = (float)(mu_s[i] * xn);
         }
@@ -223,17 +244,60 @@ hipError_t launch_init_state(Ctx& c, bool use_given)
 {
     hipLaunchKernelGGL(k_init_state, dim3(nblk(c.n)), dim3(kBlock), 0, c.stream, c.perm, c.T_in,
                        use_given ? c.x_init : nullptr, c.nH_s, c.mu_s, c.n, c.gamma_thin,
-                       c.alpha_s, c.gcoll_s, c.x_s, c.mux_s);
+                       c.alpha_s, c.alphaB_s, c.gcoll_s, c.x_s, c.mux_s);
     return hipGetLastError();
 }
 
-hipError_t launch_gamma(Ctx& c, bool update_x)
+hipError_t launch_gamma(Ctx& c, bool update_x, bool first_sweep)
 {
+    RateRule rule;
+    rule.want = c.geom.want;
+    rule.skip = (first_sweep && c.rule_tau_skip > 0.0) ? c.skip_s : nullptr;
+    rule.tau_skip = c.rule_tau_skip;
+    rule.tau_case_b = c.rule_tau_case_b;
+    rule.alphaB = c.alphaB_s;
+    rule.relative = c.rule_relative;
     hipLaunchKernelGGL(k_gamma, dim3(nblk(c.n)), dim3(kBlock), 0, c.stream, c.N_s, c.n, c.n_ray,
                        c.n_bins, c.ws_rel, c.dsig_l2, c.sigma_min, c.ln_ws_max,
                        std::log(c.gamma_thin), c.lnG_s, c.G_s, c.tau_s, update_x ? 1 : 0, c.nH_s,
                        c.mu_s, c.alpha_s, c.gcoll_s, c.x_s, c.mux_s, c.red, c.geom.seg_of,
-                       c.geom.seg_active, c.geom.seg_active ? c.seg_maxdx : nullptr);
+                       c.geom.seg_active, c.geom.seg_active ? c.seg_maxdx : nullptr, rule);
+    return hipGetLastError();
+}
+
+namespace {
+
+// particles of block `block` of the density order that are not frozen
+__global__ void k_want(const int32_t* __restrict__ block_s, const uint8_t* __restrict__ skip,
+                       int64_t n, int block, uint8_t* __restrict__ want)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const bool in_block = !block_s || block_s[i] == block;
+    want[i] = (in_block && !(skip && skip[i])) ? 1 : 0;
+}
+
+__global__ void k_block_ids(const int32_t* __restrict__ perm, const int32_t* __restrict__ block_in,
+                            int64_t n, int32_t* __restrict__ block_s)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) block_s[i] = block_in[perm[i]];
+}
+
+}  // namespace
+
+hipError_t launch_want(Ctx& c, int block, bool use_skip)
+{
+    hipLaunchKernelGGL(k_want, dim3(nblk(c.n)), dim3(kBlock), 0, c.stream,
+                       c.rule_blocks > 1 ? c.block_s : nullptr, use_skip ? c.skip_s : nullptr,
+                       c.n, block, c.want_s);
+    return hipGetLastError();
+}
+
+hipError_t launch_block_ids(Ctx& c, const int32_t* block_in)
+{
+    hipLaunchKernelGGL(k_block_ids, dim3(nblk(c.n)), dim3(kBlock), 0, c.stream, c.perm, block_in,
+                       c.n, c.block_s);
     return hipGetLastError();
 }
 

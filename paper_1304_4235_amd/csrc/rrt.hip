@@ -64,10 +64,16 @@ void free_particles(Ctx& c)
                     c.alpha_s, c.gcoll_s, c.x_s, c.mux_s, c.lnG_s, c.G_s, c.tau_s, c.N_s,
                     c.perm, c.codes, c.nodes, c.keys_b, c.vals_b, c.k_left, c.k_right,
                     c.k_parent, c.k_first, c.k_last, c.k_lo, c.k_hi, c.k_cnt, c.k_dfs, c.k_flag,
-                    c.seg_of, c.k_seg};
+                    c.seg_of, c.k_seg, c.alphaB_s, c.skip_s, c.want_s, c.block_s,
+                    c.block_list};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     c.seg_of = c.k_seg = nullptr;
+    c.alphaB_s = nullptr;
+    c.skip_s = c.want_s = nullptr;
+    c.block_s = nullptr;
+    c.block_list = nullptr;
+    c.blocks_for = 0;
     void* adj[] = {c.xhist, c.adj_lam, c.adj_lup, c.adj_nu, c.adj_pis, c.adj_gnH, c.adj_y,
                    c.adj_wpart, c.adj_gw, c.adj_tpart};
     for (void* b : adj)
@@ -109,6 +115,7 @@ int alloc_particles(Ctx& c, int64_t n)
     A(c.nodes, 2 * m) A(c.keys_b, m) A(c.vals_b, m) A(c.k_left, mi) A(c.k_right, mi)
     A(c.k_parent, 2 * m) A(c.k_first, mi) A(c.k_last, mi) A(c.k_lo, 3 * mi) A(c.k_hi, 3 * mi)
     A(c.k_cnt, mi) A(c.k_dfs, mi) A(c.k_flag, mi) A(c.seg_of, m) A(c.k_seg, mi)
+    A(c.alphaB_s, m) A(c.skip_s, m) A(c.want_s, m) A(c.block_s, m) A(c.block_list, m)
 #undef A
     if (e != hipSuccess) {
         free_particles(c);
@@ -625,6 +632,8 @@ int rrt_build_tree(rrt_ctx* x)
     g.seg_root = segmented ? c.seg_root : nullptr;
     g.seg_end = segmented ? c.seg_end : nullptr;
     g.seg_active = nullptr;
+    g.want = nullptr;
+    c.blocks_for = 0;            // the density blocks are in tree order
     HIP_OK(launch_init_state(c, c.x_init_given));
     if (c.timing) c.t_build += ev_end(c);
     c.paths_valid = false;       // new geometry: the recorded paths no longer apply
@@ -694,6 +703,82 @@ int rrt_update_equilibrium(rrt_ctx* x, double* x_out, double* max_dx_out)
     return RRT_OK;
 }
 
+namespace {
+
+bool default_rule(const Ctx& c)
+{
+    return c.rule_tau_skip == 0.0 && std::isinf(c.rule_tau_case_b) && c.rule_relative == 0 &&
+           c.rule_blocks == 1;
+}
+
+// Block of every particle in the density-descending order (ties: lower input
+// index first), blocks of ceil(n / n_blocks) consecutive particles.
+int ensure_blocks(Ctx& c)
+{
+    if (c.blocks_for == c.rule_blocks) return RRT_OK;
+    const int64_t n = c.n;
+    std::vector<float> nh((size_t)n);
+    std::vector<int32_t> perm((size_t)n);
+    HIP_OK(hipMemcpyAsync(nh.data(), c.nH_s, sizeof(float) * n, hipMemcpyDeviceToHost, c.stream));
+    HIP_OK(hipMemcpyAsync(perm.data(), c.perm, sizeof(int32_t) * n, hipMemcpyDeviceToHost,
+                          c.stream));
+    HIP_OK(hipStreamSynchronize(c.stream));
+    std::vector<int64_t> ord((size_t)n);
+    for (int64_t i = 0; i < n; ++i) ord[i] = i;
+    std::sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) {
+        if (nh[a] != nh[b]) return nh[a] > nh[b];
+        return perm[a] < perm[b];
+    });
+    const int64_t bs = (n + c.rule_blocks - 1) / c.rule_blocks;
+    std::vector<int32_t> blk((size_t)n);
+    for (int64_t r = 0; r < n; ++r) blk[ord[r]] = (int32_t)(r / bs);
+    // each block's tree positions in ascending order (coherent rays)
+    std::vector<int32_t> lst((size_t)n);
+    c.block_off.assign((size_t)c.rule_blocks + 1, 0);
+    for (int64_t i = 0; i < n; ++i) ++c.block_off[(size_t)blk[i] + 1];
+    for (int b = 0; b < c.rule_blocks; ++b) c.block_off[b + 1] += c.block_off[b];
+    std::vector<int64_t> fill(c.block_off.begin(), c.block_off.end() - 1);
+    for (int64_t i = 0; i < n; ++i) lst[(size_t)fill[blk[i]]++] = (int32_t)i;
+    HIP_OK(hipMemcpyAsync(c.block_s, blk.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice,
+                          c.stream));
+    HIP_OK(hipMemcpyAsync(c.block_list, lst.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice,
+                          c.stream));
+    HIP_OK(hipStreamSynchronize(c.stream));
+    c.blocks_for = c.rule_blocks;
+    return RRT_OK;
+}
+
+// the per-step particle mask lives only inside one sweep of the driver
+struct WantGuard {
+    Ctx& c;
+    explicit WantGuard(Ctx& cc) : c(cc) {}
+    ~WantGuard()
+    {
+        c.geom.want = nullptr;
+        c.row_list = nullptr;
+        c.row_list_n = 0;
+    }
+};
+
+}  // namespace
+
+int rrt_set_update_rule(rrt_ctx* x, double tau_skip, double tau_case_b, int32_t relative,
+                        int32_t n_blocks)
+{
+    if (!x) return RRT_E_ARG;
+    Ctx& c = x->c;
+    if (!(tau_skip >= 0.0) || std::isinf(tau_skip))
+        return fail(c, RRT_E_ARG, "tau_skip must be finite and >= 0");
+    if (!(tau_case_b > 0.0)) return fail(c, RRT_E_ARG, "tau_case_b must be > 0 (inf: case A)");
+    if (relative != 0 && relative != 1) return fail(c, RRT_E_ARG, "relative must be 0 or 1");
+    if (n_blocks < 1 || n_blocks > (1 << 20)) return fail(c, RRT_E_ARG, "n_blocks 1..2^20");
+    c.rule_tau_skip = tau_skip;
+    c.rule_tau_case_b = tau_case_b;
+    c.rule_relative = relative;
+    c.rule_blocks = n_blocks;
+    return RRT_OK;
+}
+
 int rrt_iterate_equilibrium(rrt_ctx* x, int32_t max_iter, double tol, double* x_out,
                             int32_t* iters_done, double* max_dx_out)
 {
@@ -701,22 +786,50 @@ int rrt_iterate_equilibrium(rrt_ctx* x, int32_t max_iter, double tol, double* x_
     Ctx& c = x->c;
     if (int r = need_tree(c)) return r;
     if (max_iter < 0 || !(tol >= 0.0)) return fail(c, RRT_E_ARG, "max_iter >= 0 and tol >= 0");
+    const bool ordered = c.rule_blocks > 1;
+    const bool skipping = c.rule_tau_skip > 0.0;
+    if (ordered && c.rule_blocks > c.n)
+        return fail(c, RRT_E_ARG, "%d blocks for %lld particles", c.rule_blocks, (long long)c.n);
+    if (ordered)
+        if (int r = ensure_blocks(c)) return r;
+    if (skipping) HIP_OK(hipMemsetAsync(c.skip_s, 0, (size_t)c.n, c.stream));
+    const int n_steps = ordered ? c.rule_blocks : 1;
+    const bool masked = ordered || skipping;
+    WantGuard guard(c);
     int it = 0;
     double mdx = INFINITY;
     for (it = 0; it < max_iter;) {
         HIP_OK(hipMemsetAsync(c.red, 0, 2 * sizeof(unsigned long long), c.stream));
         int64_t hits = -1;
-        if (int r = columns_impl(c, &hits)) return r;
-        ev_begin(c);
-        HIP_OK(launch_gamma(c, true));
+        for (int b = 0; b < n_steps; ++b) {
+            // one block of the density order (all particles for the
+            // order-independent update), frozen particles left out
+            if (masked) {
+                HIP_OK(launch_want(c, b, skipping && it > 0));
+                c.geom.want = c.want_s;
+            }
+            if (ordered) {                    // the product walks only this block's rays
+                c.row_list = c.block_list + c.block_off[b];
+                c.row_list_n = c.block_off[b + 1] - c.block_off[b];
+            }
+            if (int r = columns_impl(c, &hits)) return r;
+            ev_begin(c);
+            HIP_OK(launch_gamma(c, true, it == 0));
+            if (c.timing) c.t_rate += ev_end(c);
+        }
+        c.geom.want = nullptr;
+        c.row_list = nullptr;
+        c.row_list_n = 0;
         HIP_OK(hipMemcpyAsync(c.red_host, c.red, 2 * sizeof(unsigned long long),
                               hipMemcpyDeviceToHost, c.stream));
-        if (c.timing) c.t_rate += ev_end(c);
         HIP_OK(hipStreamSynchronize(c.stream));
         ++it;
         std::memcpy(&mdx, &c.red_host[0], sizeof mdx);
-        c.last_hits = hits >= 0 ? hits : (int64_t)c.red_host[1];
-        c.total_hits += c.last_hits;
+        // intersections of the sweep: counted by traversal, or all recorded
+        // ones when every ray was evaluated; not counted for masked sweeps
+        // over recorded paths
+        c.last_hits = hits < 0 ? (int64_t)c.red_host[1] : (masked ? -1 : hits);
+        if (c.last_hits > 0) c.total_hits += c.last_hits;
         if (mdx < tol) break;
     }
     c.have_columns = c.have_gamma = false;
@@ -733,6 +846,7 @@ int rrt_set_density(rrt_ctx* x, const float* n_H)
     Ctx& c = x->c;
     if (!c.have_tree) return fail(c, RRT_E_STATE, "rrt_build_tree has not been called");
     if (!n_H) return fail(c, RRT_E_ARG, "n_H is required");
+    c.blocks_for = 0;                  // the density order may change
     HIP_OK(launch_set_density(c, n_H));
     HIP_OK(launch_mux(c));
     c.have_columns = c.have_gamma = false;
@@ -746,6 +860,9 @@ int rrt_forward(rrt_ctx* x, int32_t K, double* lnG_out, double* x_out)
     Ctx& c = x->c;
     if (int r = need_tree(c)) return r;
     if (K < 1 || K > 100000) return fail(c, RRT_E_ARG, "K must be 1..100000");
+    if (!default_rule(c))
+        return fail(c, RRT_E_STATE, "the reverse mode differentiates the order-independent "
+                                    "case A update: reset the update rule");
     const size_t n = (size_t)c.n;
     if (c.xhist_cap < K + 1 || !c.xhist) {
         HIP_OK(dalloc(&c.xhist, (size_t)(K + 1) * n));
@@ -1050,6 +1167,9 @@ int rrt_iterate_halos(rrt_ctx* x, int32_t max_iter, double tol, int32_t per_laun
     if (int r = need_tree(c)) return r;
     if (max_iter < 1 || !(tol >= 0.0) || per_launch < 1 || per_launch > 256)
         return fail(c, RRT_E_ARG, "max_iter >= 1, tol >= 0, per_launch 1..256");
+    if (!default_rule(c))
+        return fail(c, RRT_E_STATE, "batched halos use the order-independent case A update: "
+                                    "reset the update rule");
     if (int r = ensure_seg_buffers(c)) return r;
     SegGuard guard(c);
     HIP_OK(launch_seg_init(c));

@@ -135,7 +135,8 @@ k_tile_columns(const uint64_t* __restrict__ row_off, const uint16_t* __restrict_
                const float* __restrict__ fac, const uint64_t* __restrict__ set_off,
                const uint32_t* __restrict__ set, const float* __restrict__ mux, int64_t n_rows,
                int tile_rows, int64_t n_tiles, double* __restrict__ N, int64_t n,
-               const int32_t* __restrict__ seg_of, const int32_t* __restrict__ seg_active)
+               const int32_t* __restrict__ seg_of, const int32_t* __restrict__ seg_active,
+               const uint8_t* __restrict__ want)
 {
     extern __shared__ float smux[];
     const int lane = threadIdx.x & (G - 1);
@@ -152,6 +153,7 @@ k_tile_columns(const uint64_t* __restrict__ row_off, const uint16_t* __restrict_
         for (int64_t row = r0 + threadIdx.x / G; row < r1; row += groups) {
             // rows of halos that have stopped iterating keep their last columns
             if (seg_active && seg_active[seg_of[row % n]] == 0) continue;
+            if (want && !want[row % n]) continue;     // not updated in this step
             const uint64_t a = row_off[row], b = row_off[row + 1];
             double acc = 0.0;
             for (uint64_t q = (a >> 2) + lane; 4 * q < b; q += 2 * G) {
@@ -187,7 +189,8 @@ hipError_t launch_tiles_g(Ctx& c, int64_t n_rows, unsigned nb, size_t lds)
 {
     hipLaunchKernelGGL(k_tile_columns<G>, dim3(nb), dim3(512), lds, c.stream, c.row_off,
                        c.tile_idx, c.tile_fac, c.tile_off, c.tile_set, c.mux_s, n_rows,
-                       c.tile_rows, c.n_tiles, c.N_s, c.n, c.geom.seg_of, c.geom.seg_active);
+                       c.tile_rows, c.n_tiles, c.N_s, c.n, c.geom.seg_of, c.geom.seg_active,
+                       c.geom.want);
     return hipGetLastError();
 }
 

@@ -175,6 +175,7 @@ k_trace(const Node* __restrict__ nodes, const float4* __restrict__ p4,
             end = g.seg_end[h];
             live = !g.seg_active || g.seg_active[h] != 0;
         }
+        if (MODE == kModeColumn && g.want && !g.want[ps]) live = false;
         if (!live) lo[0] = 1, hi[0] = 0;            // no image loop at all
         for (int sx = lo[0]; sx <= hi[0]; ++sx)
         for (int sy = lo[1]; sy <= hi[1]; ++sy)
@@ -350,6 +351,7 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
         end = g.seg_end[h];
         live = !g.seg_active || g.seg_active[h] != 0;
     }
+    if (MODE == kModeColumn && g.want && active && !g.want[ps]) live = false;
     uint64_t pending = __ballot(live);
     while (pending) {
     const int leader = __ffsll((unsigned long long)pending) - 1;
@@ -508,16 +510,22 @@ template <int G>
 __global__ void __launch_bounds__(256)
 k_path_columns(const uint64_t* __restrict__ row_off, const int2* __restrict__ path,
                const float* __restrict__ mux, int64_t n_rows, double* __restrict__ N, int64_t n,
-               const int32_t* __restrict__ seg_of, const int32_t* __restrict__ seg_active)
+               const int32_t* __restrict__ seg_of, const int32_t* __restrict__ seg_active,
+               const uint8_t* __restrict__ want, const int32_t* __restrict__ list,
+               int64_t list_n)
 {
     const int lane = threadIdx.x & (G - 1);
     const int64_t stride = (int64_t)gridDim.x * (blockDim.x / G);
     const long long* p = reinterpret_cast<const long long*>(path);
+    // with a source list, the rows are its sources' rays: v -> (k, list[i])
+    const int64_t n_iter = list ? list_n * (n_rows / n) : n_rows;
     // the G lanes of a group share the row, so the loop is uniform per group
-    for (int64_t row = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G; row < n_rows;
-         row += stride) {
+    for (int64_t v = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G; v < n_iter;
+         v += stride) {
+        const int64_t row = list ? (v / list_n) * n + list[v % list_n] : v;
         // rows of halos that have stopped iterating keep their last columns
         if (seg_active && seg_active[seg_of[row % n]] == 0) continue;
+        if (want && !want[row % n]) continue;     // not updated in this step
         const uint64_t a = row_off[row], b = row_off[row + 1];
         double acc = 0.0;
         // Lanes stride through the row one entry at a time, so the particle
@@ -599,19 +607,25 @@ hipError_t launch_path_columns(Ctx& c, int group)
 {
     const int64_t n_rows = c.n * (int64_t)c.n_ray;
     const int bs = 256;
-    const unsigned nb = stride_blocks(n_rows, bs / group);
+    const int64_t n_iter = c.row_list ? c.row_list_n * (int64_t)c.n_ray : n_rows;
+    if (n_iter == 0) return hipSuccess;
+    const unsigned nb = stride_blocks(n_iter, bs / group);
     if (group == 64)
         hipLaunchKernelGGL(k_path_columns<64>, dim3(nb), dim3(bs), 0, c.stream, c.row_off, c.path,
-                           c.mux_s, n_rows, c.N_s, c.n, c.geom.seg_of, c.geom.seg_active);
+                           c.mux_s, n_rows, c.N_s, c.n, c.geom.seg_of, c.geom.seg_active,
+                           c.geom.want, c.row_list, c.row_list_n);
     else if (group == 32)
         hipLaunchKernelGGL(k_path_columns<32>, dim3(nb), dim3(bs), 0, c.stream, c.row_off, c.path,
-                           c.mux_s, n_rows, c.N_s, c.n, c.geom.seg_of, c.geom.seg_active);
+                           c.mux_s, n_rows, c.N_s, c.n, c.geom.seg_of, c.geom.seg_active,
+                           c.geom.want, c.row_list, c.row_list_n);
     else if (group == 16)
         hipLaunchKernelGGL(k_path_columns<16>, dim3(nb), dim3(bs), 0, c.stream, c.row_off, c.path,
-                           c.mux_s, n_rows, c.N_s, c.n, c.geom.seg_of, c.geom.seg_active);
+                           c.mux_s, n_rows, c.N_s, c.n, c.geom.seg_of, c.geom.seg_active,
+                           c.geom.want, c.row_list, c.row_list_n);
     else
         hipLaunchKernelGGL(k_path_columns<8>, dim3(nb), dim3(bs), 0, c.stream, c.row_off, c.path,
-                           c.mux_s, n_rows, c.N_s, c.n, c.geom.seg_of, c.geom.seg_active);
+                           c.mux_s, n_rows, c.N_s, c.n, c.geom.seg_of, c.geom.seg_active,
+                           c.geom.want, c.row_list, c.row_list_n);
     return hipGetLastError();
 }
 

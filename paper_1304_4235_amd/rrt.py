@@ -63,6 +63,7 @@ SIGNATURES = {
     "rrt_set_density": ([_vp, _vp], C.c_int),
     "rrt_set_halos": ([_vp, _i32, _vp], C.c_int),
     "rrt_set_tuning": ([_vp, _i32, _i32], C.c_int),
+    "rrt_set_update_rule": ([_vp, _d, _d, _i32, _i32], C.c_int),
     "rrt_iterate_halos": ([_vp, _i32, _d, _i32, _vp, _vp], C.c_int),
     "rrt_forward": ([_vp, _i32, _vp, _vp], C.c_int),
     "rrt_backward": ([_vp, _vp, _vp, _vp, _vp], C.c_int),
@@ -175,6 +176,15 @@ class Solver:
         tiles (0/1)."""
         for k, v in kw.items():
             self._check(_lib.rrt_set_tuning(self._h, TUNE_KEYS[k], int(v)), f"rrt_set_tuning {k}")
+
+    def set_update_rule(self, tau_skip: float = 0.0, tau_case_b: float = float("inf"),
+                        relative: bool = False, n_blocks: int = 1):
+        """The paper's update rule for iterate(): frozen thin particles, case B
+        above a tau_eff threshold, relative convergence, density-ordered blocks.
+        Defaults restore the order-independent case A update."""
+        self._check(_lib.rrt_set_update_rule(self._h, float(tau_skip), float(tau_case_b),
+                                             int(bool(relative)), int(n_blocks)),
+                    "rrt_set_update_rule")
 
     def set_halos(self, offsets):
         off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
