@@ -17,6 +17,10 @@ constexpr int kTabIntervals = 256;        // cubic pieces per kernel table
 constexpr int kMaxRays = 3072;
 constexpr int kMaxBins = 4096;
 constexpr int kDefaultLeaf = 8;
+// most particles a leaf holds (its count is stored in 3 bits)
+constexpr int kLeafMax = 8;
+// waves per block of the traversal kernels (blocks of at most 256 threads)
+constexpr int kWavesPerBlock = 4;
 // particles x rays: rays are indexed with 32-bit integers on the device
 constexpr int64_t kMaxRows = 2147483647;
 // distinct particles a row tile of the recorded paths may touch (its mu*x is

@@ -110,7 +110,7 @@ int alloc_particles(Ctx& c, int64_t n)
 #define A(p, cnt)                                                    \
     if (e == hipSuccess) e = dalloc(&(p), (cnt));
     A(c.pos_in, 3 * m) A(c.h_in, m) A(c.mu_in, m) A(c.nH_in, m) A(c.T_in, m) A(c.x_init, m)
-    A(c.p4, m) A(c.mu_s, m) A(c.mu0_s, m) A(c.nH0_s, m) A(c.nH_s, m) A(c.alpha_s, m) A(c.gcoll_s, m) A(c.x_s, m)
+    A(c.p4, m + kLeafMax) A(c.mu_s, m) A(c.mu0_s, m) A(c.nH0_s, m) A(c.nH_s, m) A(c.alpha_s, m) A(c.gcoll_s, m) A(c.x_s, m)
     A(c.mux_s, m) A(c.lnG_s, m) A(c.G_s, m) A(c.tau_s, m) A(c.perm, m) A(c.codes, m)
     A(c.nodes, 2 * m) A(c.keys_b, m) A(c.vals_b, m) A(c.k_left, mi) A(c.k_right, mi)
     A(c.k_parent, 2 * m) A(c.k_first, mi) A(c.k_last, mi) A(c.k_lo, 3 * mi) A(c.k_hi, 3 * mi)
@@ -121,6 +121,12 @@ int alloc_particles(Ctx& c, int64_t n)
         free_particles(c);
         return fail(c, RRT_E_NOMEM, "device allocation for %lld particles failed: %s",
                     (long long)n, hipGetErrorString(e));
+    }
+    // the spare particle entries past n are read with whole leaves, never used
+    e = hipMemset(c.p4 + m, 0, sizeof(float4) * kLeafMax);
+    if (e != hipSuccess) {
+        free_particles(c);
+        return fail(c, RRT_E_HIP, "hipMemset: %s", hipGetErrorString(e));
     }
     c.n_cap = n;
     return RRT_OK;

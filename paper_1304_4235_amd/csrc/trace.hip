@@ -207,9 +207,18 @@ k_trace(const Node* __restrict__ nodes, const float4* __restrict__ p4,
                 if (leafw < 0) { node = node + 1; continue; }
                 const int f = leafw >> 3;
                 const int c = (f + (leafw & 7) + 1 <= g.n) ? (leafw & 7) + 1 : 0;
-                for (int q = 0; q < c; ++q) {
+                // the leaf's particles (contiguous in tree order) are loaded
+                // together; p4 holds kLeafMax spare entries past n
+                float4 Qs[kLeafMax];
+                if (c > 0) {
+#pragma unroll
+                    for (int q = 0; q < kLeafMax; ++q) Qs[q] = p4[f + q];
+                }
+#pragma unroll
+                for (int q = 0; q < kLeafMax; ++q) {
+                    if (q >= c) break;
                     const int j = f + q;
-                    const float4 Q = p4[j];
+                    const float4 Q = Qs[q];
                     double d0 = ((double)Q.x - rp[0]) + sh[0];
                     double d1 = ((double)Q.y - rp[1]) + sh[1];
                     double d2 = ((double)Q.z - rp[2]) + sh[2];
@@ -275,6 +284,15 @@ k_trace(const Node* __restrict__ nodes, const float4* __restrict__ p4,
     for (int off = 32; off > 0; off >>= 1) c64 += __shfl_xor(c64, off, 64);
     if ((threadIdx.x & 63) == 0 && c64) atomicAdd(out.hits_total, (unsigned long long)c64);
 }
+// LDS written by some lanes of a wave and read by others: order the accesses
+// within the wave (no block barrier needed, the wave runs in lockstep)
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Wave-cooperative variant: the 64 rays of a wave (same direction, sources
 // adjacent in tree order) walk ONE node sequence, the depth-first union of
 // their individual walks.  Node and leaf-particle loads are wave-uniform
@@ -289,6 +307,10 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
              const KernelTables* __restrict__ tabs, TraceGeom g, RayOut out)
 {
     __shared__ float4 tab[3 * kTabIntervals];
+    // per wave: the hit rays of the current leaf, and its (ray, particle) results
+    __shared__ uint8_t s_lane[kWavesPerBlock][64];
+    __shared__ uint8_t s_in[kWavesPerBlock][64 * kLeafMax];
+    __shared__ float s_gk[kWavesPerBlock][64 * kLeafMax];
     constexpr bool kTerms = MODE != kModeCount;
     if (kTerms) {
         const float4* src = reinterpret_cast<const float4*>(tabs);
@@ -300,6 +322,8 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
     const float4* t_erf = tab + 2 * kTabIntervals;
 
     const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const uint64_t lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
     const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     const int64_t waves_per_dir = (g.n + 63) / 64;
     const int k = (int)(wave / waves_per_dir);
@@ -389,13 +413,33 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
             if (leafw < 0) { node = node + 1; continue; }
             const int f = leafw >> 3;
             const int c = (f + (leafw & 7) + 1 <= g.n) ? (leafw & 7) + 1 : 0;
-            for (int q = 0; q < c; ++q) {
+            // Leaf work compacted over the wave: the (hit ray, leaf particle)
+            // pairs are spread over all 64 lanes, so a leaf that few of the
+            // wave's rays reach costs few wave instructions.  A pair's lane
+            // takes its ray's origin from the ray's lane and evaluates the
+            // canonical predicate and the chord factor; each ray then takes
+            // its particles' results in particle order, exactly as if it had
+            // looped over them itself.
+            const uint64_t hm = __ballot(hit);
+            const int k_hit = __popcll(hm);
+            const int rank = __popcll(hm & lt_mask);
+            if (hit) s_lane[wv][rank] = (uint8_t)lane;
+            wave_sync();
+            const int pairs = k_hit * c;
+            for (int base = 0; base < pairs; base += 64) {
+                const int t = base + lane;
+                const bool act = t < pairs;
+                const int q = act ? t / k_hit : 0;
+                const int owner = act ? (int)s_lane[wv][t - q * k_hit] : lane;
+                const double o0 = __shfl(rp[0], owner, 64);
+                const double o1 = __shfl(rp[1], owner, 64);
+                const double o2 = __shfl(rp[2], owner, 64);
+                if (!act) continue;
                 const int j = f + q;
                 const float4 Q = p4[j];
-                if (!hit) continue;
-                double d0 = ((double)Q.x - rp[0]) + sh[0];
-                double d1 = ((double)Q.y - rp[1]) + sh[1];
-                double d2 = ((double)Q.z - rp[2]) + sh[2];
+                double d0 = ((double)Q.x - o0) + sh[0];
+                double d1 = ((double)Q.y - o1) + sh[1];
+                double d2 = ((double)Q.z - o2) + sh[2];
                 double sp = d0 * u[0] + d1 * u[1] + d2 * u[2];
                 double tt = sp < 0.0 ? 0.0 : (sp > L ? L : sp);
                 double c0 = d0 - tt * u[0];
@@ -404,48 +448,62 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
                 double D2 = c0 * c0 + c1 * c1 + c2 * c2;
                 double hj = (double)Q.w;
                 double h2 = hj * hj;
-                if (!(D2 < h2)) continue;
-                ++cnt;
-                if (MODE == kModeCount) continue;
-                if (MODE == kModeRecord) {
-                    if (w < out.hit_cap) {
-                        out.hit_j[w] = out.perm[j];
-                        out.hit_img[w] = (sx + 8) | ((sy + 8) << 4) | ((sz + 8) << 8);
-                    }
-                    ++w;
-                }
-                double px = d0 - sp * u[0], py = d1 - sp * u[1], pz = d2 - sp * u[2];
-                double b2 = px * px + py * py + pz * pz;
-                double l2 = h2 - b2;
+                const bool in = D2 < h2;
                 float gk = 0.0f;
-                if (l2 > 0.0) {
-                    const float ih2 = 1.0f / (float)h2;
-                    const float wq = fminf((float)l2 * ih2, 1.0f);
-                    const double Lr = L - sp;
-                    float K;
-                    if (sp >= 0.0 && sp * sp >= l2 && Lr >= 0.0 && Lr * Lr >= l2) {
-                        K = sqrtf(wq) * tab_eval(t_full, wq);
-                    } else {
-                        const float ih = 1.0f / Q.w;
-                        const float lh = sqrtf(wq);
-                        const float z1 = fmaxf((float)(-sp) * ih, -lh);
-                        const float z2 = fminf((float)Lr * ih, lh);
-                        const float q2 = fminf((float)b2 * ih2, 1.0f);
-                        K = z2 > z1 ? tab_eval(t_gauss, q2) *
-                                          (erf_t_odd(t_erf, z2) - erf_t_odd(t_erf, z1))
-                                    : 0.0f;
+                if (kTerms && in) {
+                    double px = d0 - sp * u[0], py = d1 - sp * u[1], pz = d2 - sp * u[2];
+                    double b2 = px * px + py * py + pz * pz;
+                    double l2 = h2 - b2;
+                    if (l2 > 0.0) {
+                        const float ih2 = 1.0f / (float)h2;
+                        const float wq = fminf((float)l2 * ih2, 1.0f);
+                        const double Lr = L - sp;
+                        float K;
+                        if (sp >= 0.0 && sp * sp >= l2 && Lr >= 0.0 && Lr * Lr >= l2) {
+                            K = sqrtf(wq) * tab_eval(t_full, wq);
+                        } else {
+                            const float ih = 1.0f / Q.w;
+                            const float lh = sqrtf(wq);
+                            const float z1 = fmaxf((float)(-sp) * ih, -lh);
+                            const float z2 = fminf((float)Lr * ih, lh);
+                            const float q2 = fminf((float)b2 * ih2, 1.0f);
+                            K = z2 > z1 ? tab_eval(t_gauss, q2) *
+                                              (erf_t_odd(t_erf, z2) - erf_t_odd(t_erf, z1))
+                                        : 0.0f;
+                        }
+                        gk = ih2 * K;
                     }
-                    gk = ih2 * K;
                 }
-                if (MODE == kModePath) {
-                    if (w < out.hit_cap) out.path[w] = make_int2(j, __float_as_int(gk));
-                    ++w;
-                } else if (MODE == kModeScatter) {
-                    if (nur != 0.0) unsafeAtomicAdd(out.y + j, (double)gk * nur);
-                } else {
-                    acc += (double)(mux[j] * gk);
+                s_in[wv][t] = in ? 1 : 0;
+                s_gk[wv][t] = gk;
+            }
+            wave_sync();
+            if (hit) {
+                for (int q = 0; q < c; ++q) {
+                    const int t = q * k_hit + rank;
+                    if (!s_in[wv][t]) continue;
+                    const int j = f + q;
+                    const float gk = s_gk[wv][t];
+                    ++cnt;
+                    if (MODE == kModeCount) continue;
+                    if (MODE == kModeRecord) {
+                        if (w < out.hit_cap) {
+                            out.hit_j[w] = out.perm[j];
+                            out.hit_img[w] = (sx + 8) | ((sy + 8) << 4) | ((sz + 8) << 8);
+                        }
+                        ++w;
+                    }
+                    if (MODE == kModePath) {
+                        if (w < out.hit_cap) out.path[w] = make_int2(j, __float_as_int(gk));
+                        ++w;
+                    } else if (MODE == kModeScatter) {
+                        if (nur != 0.0) unsafeAtomicAdd(out.y + j, (double)gk * nur);
+                    } else {
+                        acc += (double)(mux[j] * gk);
+                    }
                 }
             }
+            wave_sync();                  // the pair buffers are reused by the next leaf
             node = max(skip, node + 1);
         }
     }
