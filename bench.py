@@ -59,23 +59,35 @@ def make_workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_isothermal_halo_262144.json")
-KERNEL_COUNTER_NAMES = {"recorded_paths": "rrt::k_path_columns<64>", "traversal": None}
+# the kernel (source file, function) behind each timed phase, for the counters
+KERNEL_SOURCES = {"recorded_paths": ("paper_1304_4235_amd/csrc/trace.hip", "k_path_columns"),
+                  "row_tiles": ("paper_1304_4235_amd/csrc/tiles.hip", "k_tile_columns"),
+                  "traversal": ("paper_1304_4235_amd/csrc/trace.hip", "k_trace_wave")}
+
+
+def kernel_source_sha256(path: str, function: str) -> str:
+    """Hash of one kernel's definition (signature line to its closing brace)."""
+    import hashlib
+    txt = open(os.path.join(ROOT, path)).read()
+    i = txt.index("\n" + function + "(") + 1
+    j = txt.index("\n}\n", i) + 3
+    return hashlib.sha256(txt[i:j].encode()).hexdigest()
 
 
 def measured_traffic(workload: str, kernel_key: str):
-    """HBM bytes per launch from the committed counter summary, only while the
-    kernel source is the one the counters were taken with (else None)."""
-    import hashlib
-    if workload != "isothermal_halo_262144" or not os.path.exists(TRAFFIC_FILE):
+    """HBM bytes per launch from the committed counter summary of this workload,
+    only while the kernel's source is the one the counters were taken with."""
+    f = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if kernel_key not in KERNEL_SOURCES or not os.path.exists(f):
         return None
-    d = json.load(open(TRAFFIC_FILE))
-    src = os.path.join(ROOT, d["source"])
-    if hashlib.sha256(open(src, "rb").read()).hexdigest() != d["source_sha256"]:
-        return None
-    name = KERNEL_COUNTER_NAMES.get(kernel_key)
-    k = d["kernels"].get(name) if name else None
-    return None if k is None else k["fetch_bytes"] + k["write_bytes"]
+    path, function = KERNEL_SOURCES[kernel_key]
+    for name, k in json.load(open(f))["kernels"].items():
+        if k.get("function") != function:
+            continue
+        if k.get("source_sha256") != kernel_source_sha256(path, function):
+            return None
+        return k["fetch_bytes"] + k["write_bytes"]
+    return None
 
 
 def cpu_baseline(wl, x, budget_s: float = 12.0):
