@@ -59,10 +59,13 @@ def make_workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-# the kernel (source file, function) behind each timed phase, for the counters
-KERNEL_SOURCES = {"recorded_paths": ("paper_1304_4235_amd/csrc/trace.hip", "k_path_columns"),
-                  "row_tiles": ("paper_1304_4235_amd/csrc/tiles.hip", "k_tile_columns"),
-                  "traversal": ("paper_1304_4235_amd/csrc/trace.hip", "k_trace_wave")}
+# the kernel behind each timed phase (source file, function, counter-name prefix)
+KERNEL_SOURCES = {"recorded_paths": ("paper_1304_4235_amd/csrc/trace.hip", "k_path_columns",
+                                     "k_path_columns<"),
+                  "row_tiles": ("paper_1304_4235_amd/csrc/tiles.hip", "k_tile_columns",
+                                "k_tile_columns<"),
+                  "traversal": ("paper_1304_4235_amd/csrc/trace.hip", "k_trace_wave",
+                                "k_trace_wave<0>")}
 
 
 def kernel_source_sha256(path: str, function: str) -> str:
@@ -80,9 +83,9 @@ def measured_traffic(workload: str, kernel_key: str):
     f = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if kernel_key not in KERNEL_SOURCES or not os.path.exists(f):
         return None
-    path, function = KERNEL_SOURCES[kernel_key]
+    path, function, prefix = KERNEL_SOURCES[kernel_key]
     for name, k in json.load(open(f))["kernels"].items():
-        if k.get("function") != function:
+        if not name.startswith(prefix):
             continue
         if k.get("source_sha256") != kernel_source_sha256(path, function):
             return None
