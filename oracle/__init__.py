@@ -62,6 +62,12 @@ def lib():
         L.orc_solve_rule.argtypes = [i64, vp, vp, vp, vp, vp, i32, vp, i32, vp, vp, d, d, d,
                                      i32, d, d, i32, i32, d, i32, vp, vp, vp, vp, vp]
         L.orc_solve_rule.restype = C.c_int
+        L.orc_columns_near_far.argtypes = [i64, vp, vp, vp, vp, i32, vp, d, d, i64, vp, d, vp, vp,
+                                           vp, i32]
+        L.orc_columns_near_far.restype = C.c_int
+        L.orc_slab_lnG.argtypes = [d, d, d, d, d, d]
+        L.orc_slab_lnG.restype = d
+        L.orc_gamma_near_far.argtypes = [i64, i32, vp, vp, d, d, vp, vp, vp, vp]
         L.orc_morton.argtypes = [i64, vp, vp]
         L.orc_lbvh.argtypes = [i64, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]
         L.orc_lbvh.restype = i64
@@ -272,6 +278,71 @@ def solve_rule(wl, tau_skip: float = 0.0, tau_case_b: float = float("inf"),
     k = int(it[0])
     return dict(x_hist=xh[: k + 1], lnG_hist=lh[:k], skipped=sk.astype(bool), iters=k,
                 maxdx=md[:k])
+
+
+# ----------------------------------------------------------------------------
+# near/far scheme (Sec. 4.1.2) with the monochromatic slab solution (App. C.4)
+# ----------------------------------------------------------------------------
+def columns_near_far(wl, x: np.ndarray, sources=None, rtol=DEFAULT_RTOL, n_threads: int = None):
+    """Per ray: far HI column, near total-hydrogen column (x = 1) and the number
+    of near particles hit.  Arrays [n_src, n_ray]."""
+    n = wl.n
+    src = _c(np.arange(n) if sources is None else sources, np.int64)
+    ns = src.size
+    Nf = np.zeros((ns, wl.n_ray))
+    Nn = np.zeros((ns, wl.n_ray))
+    cnt = np.zeros((ns, wl.n_ray), np.int64)
+    nt = N_THREADS if n_threads is None else n_threads
+    rc = lib().orc_columns_near_far(n, _p(_c(wl.pos, np.float32)), _p(_c(wl.h, np.float32)),
+                                    _p(_c(wl.mu, np.float32)), _p(_c(x, np.float64)), wl.n_ray,
+                                    _p(_c(wl.dirs, np.float64)), wl.l_ray, wl.box, ns, _p(src),
+                                    rtol, _p(Nf), _p(Nn), _p(cnt), nt)
+    assert rc == 0
+    return Nf, Nn, cnt
+
+
+def slab_lnG(lnG0, nH, alpha, gcoll, sigma, N):
+    """ln of the rate at total hydrogen column N into a uniform slab (App. C.4)."""
+    f = lib().orc_slab_lnG
+    b = np.broadcast_arrays(*map(np.asarray, (lnG0, nH, alpha, gcoll, sigma, N)))
+    out = np.array([f(*map(float, v)) for v in zip(*[a.ravel() for a in b])])
+    return out.reshape(b[0].shape)
+
+
+def step_near_far(wl, x: np.ndarray, sources=None, rtol=DEFAULT_RTOL):
+    """One order-independent update with the near/far rate (one frequency bin)."""
+    assert wl.n_bins == 1, "the slab solution is monochromatic"
+    src = np.arange(wl.n) if sources is None else np.asarray(sources)
+    Nf, Nn, cnt = columns_near_far(wl, x, src, rtol=rtol)
+    T = wl.T[src].astype(np.float64)
+    nH = wl.n_H[src].astype(np.float64)
+    al, ga = alpha_A(T), gamma_coll(T)
+    lnG = np.zeros(src.size)
+    lib().orc_gamma_near_far(src.size, wl.n_ray, _p(_c(Nf, np.float64)), _p(_c(Nn, np.float64)),
+                             float(wl.w[0]), float(wl.sigma[0]), _p(_c(nH, np.float64)),
+                             _p(_c(al, np.float64)), _p(_c(ga, np.float64)), _p(lnG))
+    G = np.exp(lnG)
+    xn = xeq(G, nH, al, ga)
+    return dict(N_far=Nf, N_near=Nn, near_hits=cnt, lnG=lnG, G=G, x_new=xn,
+                tau=math.log(gamma_thin(wl)) - lnG)
+
+
+def solve_near_far(wl, max_iter: int = None, tol: float = None, rtol=DEFAULT_RTOL):
+    """The order-independent fixed point with the near/far rate, from x_thin."""
+    mi = wl.max_iter if max_iter is None else max_iter
+    tl = wl.tol if tol is None else tol
+    x = x_thin(wl)
+    xh, lh, md = [x.copy()], [], []
+    for _ in range(mi):
+        r = step_near_far(wl, x, rtol=rtol)
+        d = float(np.max(np.abs(r["x_new"] - x)))
+        x = r["x_new"]
+        xh.append(x.copy())
+        lh.append(r["lnG"])
+        md.append(d)
+        if d < tl:
+            break
+    return dict(x_hist=np.array(xh), lnG_hist=np.array(lh), iters=len(md), maxdx=np.array(md))
 
 
 # ----------------------------------------------------------------------------

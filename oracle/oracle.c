@@ -293,6 +293,155 @@ int orc_columns(int64_t n, const float* pos, const float* h, const float* mu, co
 }
 
 /* ------------------------------------------------------------------------- */
+/* Near/far split (Sec. 4.1.2).  The near particles of source p are those that */
+/* contribute to p's density in the scatter form of eq. nhi: the particle     */
+/* image whose kernel sphere contains p, |d|^2 < h_j^2 with d as in the hit    */
+/* predicate and |d|^2 summed x, y, z in FP64.  Per ray, N_far is the HI       */
+/* column of the other particles the ray hits, and N_near the total hydrogen   */
+/* column (every x = 1) of the near ones.                                     */
+/* ------------------------------------------------------------------------- */
+int orc_columns_near_far(int64_t n, const float* pos, const float* h, const float* mu,
+                         const double* x, int32_t n_ray, const double* dirs, double L, double box,
+                         int64_t n_src, const int64_t* src, double rtol, double* N_far,
+                         double* N_near, int64_t* near_hits, int32_t n_threads)
+{
+    if (n <= 0 || n_ray <= 0 || n_src < 0) return -1;
+    double plo[3] = {INFINITY, INFINITY, INFINITY}, phi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    double hmax = 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+        for (int a = 0; a < 3; ++a) {
+            double v = pos[3 * j + a];
+            if (v < plo[a]) plo[a] = v;
+            if (v > phi[a]) phi[a] = v;
+        }
+        if (h[j] > hmax) hmax = h[j];
+    }
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#else
+    (void)n_threads;
+#endif
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t si = 0; si < n_src; ++si) {
+        int64_t p = src[si];
+        double rp[3] = {pos[3 * p], pos[3 * p + 1], pos[3 * p + 2]};
+        for (int k = 0; k < n_ray; ++k) {
+            const double* u = dirs + 3 * k;
+            int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+            if (box > 0.0) {
+                for (int a = 0; a < 3; ++a) {
+                    double e = rp[a] + L * u[a];
+                    double smin = rp[a] < e ? rp[a] : e, smax = rp[a] < e ? e : rp[a];
+                    image_range(smin, smax, plo[a], phi[a], hmax, box, &lo[a], &hi[a]);
+                }
+            }
+            double far = 0.0, near = 0.0;
+            int64_t cnt = 0;
+            for (int sx = lo[0]; sx <= hi[0]; ++sx)
+            for (int sy = lo[1]; sy <= hi[1]; ++sy)
+            for (int sz = lo[2]; sz <= hi[2]; ++sz) {
+                double sh[3] = {(double)sx * box, (double)sy * box, (double)sz * box};
+                if (box <= 0.0) sh[0] = sh[1] = sh[2] = 0.0;
+                for (int64_t j = 0; j < n; ++j) {
+                    double d[3];
+                    for (int a = 0; a < 3; ++a)
+                        d[a] = ((double)pos[3 * j + a] - rp[a]) + sh[a];
+                    double sp;
+                    double hj = (double)h[j];
+                    if (!seg_hit(d, u, L, hj, &sp)) continue;
+                    const double D0 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+                    if (D0 < hj * hj) {
+                        near += hit_column(d, u, sp, L, hj, (double)mu[j], rtol);
+                        ++cnt;
+                    } else {
+                        far += hit_column(d, u, sp, L, hj, (double)mu[j] * x[j], rtol);
+                    }
+                }
+            }
+            N_far[si * n_ray + k] = far;
+            N_near[si * n_ray + k] = near;
+            if (near_hits) near_hits[si * n_ray + k] = cnt;
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* The near particles as a uniform slab (Sec. 4.1.2, Appendix C.4): gas of     */
+/* density nH (alpha, gamma at its T), lit by monochromatic radiation of       */
+/* cross-section sigma that gives the rate Gamma0 at the surface.  At total    */
+/* hydrogen column N into the slab the neutral fraction x satisfies            */
+/*   sigma N = (1/x0 - 1/x) + ln[x(1-x0) / (x0(1-x))]                          */
+/*           + (1/xce) ln[x(xce-x0) / (x0(xce-x))]                             */
+/* (eq. analytic_slab_eqn), x0 the equilibrium at the surface, xce =          */
+/* alpha/(alpha+gamma), and the rate there is Gamma = nH Xi(x)/x (eq.          */
+/* slabone) with Xi = alpha(1-x)^2 - gamma(1-x)x = (alpha+gamma)(1-x)(xce-x).  */
+/* Solved by bisection for v = ln(xce - x) in long double, so that thick       */
+/* slabs, where xce - x underflows, stay representable.  Returns ln Gamma.     */
+/* ------------------------------------------------------------------------- */
+double orc_slab_lnG(double lnG0, double nH, double alpha, double gcoll, double sigma, double N)
+{
+    if (lnG0 == -INFINITY) return -INFINITY;
+    const long double a = alpha, g = gcoll, xce = a / (a + g);
+    const long double lg = (long double)lnG0 - logl((long double)nH);     /* ln(Gamma0/nH) */
+    if (lg < -11000.0L) {
+        /* rate too small to represent: x = xce through the slab */
+        return (double)((long double)lnG0 - (long double)sigma * xce * (long double)N);
+    }
+    const long double G = expl(lg);
+    /* surface root and xce - x0 without cancellation */
+    const long double sD = sqrtl((G + g) * (G + g) + 4.0L * G * a);
+    const long double x0 = 2.0L * a / (G + 2.0L * a + g + sD);
+    const long double d0 = a * G * (1.0L + (G + 2.0L * g + 4.0L * a) / (sD + g)) /
+                           ((a + g) * (G + 2.0L * a + g + sD));
+    const long double v0 = logl(d0);
+    const long double target = (long double)sigma * (long double)N;
+    if (!(target > 0.0L)) return (double)((long double)lnG0);
+    #define ORC_F(v, out) do {                                                  \
+        const long double e_ = expl(v), xx_ = xce - e_;                          \
+        out = (1.0L / x0 - 1.0L / xx_) + logl(xx_ * (1.0L - x0) / (x0 * (1.0L - xx_))) + \
+              (logl(xx_ * d0 / x0) - (v)) / xce;                                 \
+    } while (0)
+    long double hi = v0, lo = v0 - xce * target - 64.0L, f;
+    ORC_F(lo, f);
+    while (f < target) { lo -= xce * target + 64.0L; ORC_F(lo, f); }
+    for (int it = 0; it < 400; ++it) {
+        const long double mid = 0.5L * (lo + hi);
+        if (mid == lo || mid == hi) break;
+        ORC_F(mid, f);
+        if (f < target) hi = mid;
+        else lo = mid;
+    }
+    #undef ORC_F
+    const long double v = 0.5L * (lo + hi);
+    const long double xs = xce - expl(v);
+    return (double)(logl((long double)nH) + logl(a + g) + logl(1.0L - xs) + v - logl(xs));
+}
+
+/* Shielded rate of the near/far scheme for a monochromatic spectrum (one bin   */
+/* w, sigma): per ray the far column attenuates the surface rate w sigma        */
+/* exp(-sigma N_far) (eq. gammafar), the slab of the near particles gives        */
+/* Gamma_k (eq. gammashldk), and Gamma = (1/N_ray) sum_k Gamma_k (eq.           */
+/* gammashld, 4 pi inside w).  ln Gamma by log-sum-exp over the rays.           */
+void orc_gamma_near_far(int64_t n_src, int32_t n_ray, const double* N_far, const double* N_near,
+                        double w, double sigma, const double* nH, const double* alpha,
+                        const double* gcoll, double* lnG)
+{
+    for (int64_t i = 0; i < n_src; ++i) {
+        double m = -INFINITY, s = 0.0;
+        double* lk = (double*)malloc(sizeof(double) * n_ray);
+        for (int k = 0; k < n_ray; ++k) {
+            const double l0 = log(w * sigma) - sigma * N_far[i * n_ray + k];
+            lk[k] = orc_slab_lnG(l0, nH[i], alpha[i], gcoll[i], sigma, N_near[i * n_ray + k]);
+            if (lk[k] > m) m = lk[k];
+        }
+        for (int k = 0; k < n_ray; ++k) s += exp(lk[k] - m);
+        lnG[i] = (m == -INFINITY) ? -INFINITY : m + log(s / (double)n_ray);
+        free(lk);
+    }
+}
+
+/* ------------------------------------------------------------------------- */
 /* Shielded photoionisation rate, Sec. 3.3 eq. gamma_shld with the frequency  */
 /* integral done over bins: Gamma = (1/N_ray) sum_k sum_b w_b sigma_b         */
 /* exp(-sigma_b N_k).  ln Gamma by a log-sum-exp over all (k, b) terms.       */

@@ -19,6 +19,14 @@ int orc_columns(int64_t n, const float* pos, const float* h, const float* mu, co
                 int64_t n_src, const int64_t* src, double rtol, int32_t mode,
                 double* N_out, int64_t* row_hits, const int64_t* row_off,
                 int32_t* hit_j, int32_t* hit_img, int32_t n_threads);
+int orc_columns_near_far(int64_t n, const float* pos, const float* h, const float* mu,
+                         const double* x, int32_t n_ray, const double* dirs, double L, double box,
+                         int64_t n_src, const int64_t* src, double rtol, double* N_far,
+                         double* N_near, int64_t* near_hits, int32_t n_threads);
+double orc_slab_lnG(double lnG0, double nH, double alpha, double gcoll, double sigma, double N);
+void orc_gamma_near_far(int64_t n_src, int32_t n_ray, const double* N_far, const double* N_near,
+                        double w, double sigma, const double* nH, const double* alpha,
+                        const double* gcoll, double* lnG);
 void orc_gamma(int64_t n_src, int32_t n_ray, const double* N, int32_t n_bins,
                const double* sigma, const double* w, double* lnG, double* G, double* tau);
 double orc_alpha_A(double T);

@@ -493,6 +493,64 @@ def test_rule_relative_convergence():
 
 
 # ---------------------------------------------------------------------------
+# near/far scheme (Sec. 4.1.2) and the slab solution of Appendix C.4
+# ---------------------------------------------------------------------------
+_A, _G = oracle.alpha_A(1e4)[0], oracle.gamma_coll(1e4)[0]
+
+
+def test_slab_rate_at_the_surface_is_the_incident_rate():
+    for lg0 in (-25.0, -27.6, -35.0):
+        assert abs(oracle.slab_lnG(lg0, 1e-2, _A, _G, W.SIGMA_TH, 0.0) - lg0) < 1e-14
+
+
+@pytest.mark.parametrize("N", [1e16, 3e17, 1e18, 4e18])
+def test_slab_rate_against_the_slice_by_slice_solver(N):
+    """The inverse solution against an independent numerical slab (pinned to
+    the analytic depth above): rate at depth = Gamma0 exp(-HI optical depth)."""
+    nH, G0 = 1e-2, 1e-12
+    _, xs = oracle.slab_numerical(G0, nH, 1e4, W.SIGMA_TH, N / nH, 40000)
+    tau = float(np.sum(xs) * W.SIGMA_TH * N / 40000)
+    got = oracle.slab_lnG(math.log(G0), nH, _A, _G, W.SIGMA_TH, N)
+    assert abs(got - (math.log(G0) - tau)) < 1e-7 * max(1.0, tau)
+
+
+def test_slab_rate_limits():
+    """Highly ionised gas is attenuated by its surface neutral fraction
+    (ln Gamma = ln Gamma0 - sigma x0 N to first order); deep in a thick slab each
+    extra column adds x_ce of neutral gas, so d ln Gamma / dN -> -sigma x_ce."""
+    nH, G0 = 1e-6, 1e-12
+    x0 = oracle.xeq(G0, nH, _A, _G)
+    N = 1e15                                      # sigma x0 N ~ 4e-5
+    got = oracle.slab_lnG(math.log(G0), nH, _A, _G, W.SIGMA_TH, N)
+    assert abs((math.log(G0) - got) / (W.SIGMA_TH * x0 * N) - 1) < 1e-3
+    N1, N2 = 5e20, 6e20
+    l1 = oracle.slab_lnG(math.log(G0), 1e-2, _A, _G, W.SIGMA_TH, N1)
+    l2 = oracle.slab_lnG(math.log(G0), 1e-2, _A, _G, W.SIGMA_TH, N2)
+    slope = (l2 - l1) / (N2 - N1)
+    assert abs(slope / (-W.SIGMA_TH * _A / (_A + _G)) - 1) < 1e-9
+    assert l2 < l1 < math.log(G0)
+
+
+def test_near_far_columns_split_the_plain_column():
+    """With every x = 1 the far and near columns add up to the plain column;
+    each ray from a source hits every near particle, and the near set is the
+    particles whose kernel contains the source (brute force, periodic images)."""
+    wl = W.make_config(0, n_side_lattice=6, box=37.5)
+    src = np.array([0, 7, 100, 215])
+    ones = np.ones(wl.n)
+    Nf, Nn, cnt = oracle.columns_near_far(wl, ones, src)
+    Np = oracle.columns(wl, ones, src)
+    np.testing.assert_allclose(Nf + Nn, Np, rtol=1e-12)
+    pos = wl.pos.astype(np.float64)
+    for i, p in enumerate(src):
+        d = pos - pos[p]
+        d -= wl.box * np.round(d / wl.box)           # minimum image: h < box / 2 here
+        inside = np.sum(np.sum(d * d, axis=1) < wl.h.astype(np.float64) ** 2)
+        assert np.all(cnt[i] == inside), (cnt[i], inside)
+    assert np.all(Nn > 0) and np.all(Nf > 0)
+
+
+# ---------------------------------------------------------------------------
 # reference tree
 # ---------------------------------------------------------------------------
 def _tree_case(n, seed=0, dup=False):
