@@ -200,6 +200,9 @@ def main():
     ap.add_argument("--traversal", type=int, default=0, help="0 wave-cooperative, 1 per lane")
     ap.add_argument("--rules", type=int, default=1,
                     help="also time the solve under the paper's update rules (1 = yes)")
+    ap.add_argument("--near-far", type=int, default=1,
+                    help="also time the near/far scheme on the same geometry with a grey "
+                         "spectrum (1 = yes)")
     ap.add_argument("--tiles", type=int, default=0,
                     help="1: columns from row tiles once the recorded paths have been reused")
     ap.add_argument("--paths", type=int, default=-1,
@@ -355,6 +358,33 @@ def main():
         s.set_update_rule()
         s.set_state(None)
         out["update_rules"] = res
+    if args.near_far and wl.tol > 0:
+        # the paper's near/far scheme (monochromatic slab solution) against the
+        # plain scheme, same geometry, one grey bin carrying the same thin rate
+        import workloads as W
+        sg, wg = W.grey_spectrum(float(np.sum(wl.sigma * wl.w)))
+        res = {"spectrum": "one bin at 13.6 eV, same optically thin rate"}
+        s.enable_timing(True)
+        for name, nf in (("plain", False), ("near_far", True)):
+            print(f"scheme {name} (grey)", file=sys.stderr, flush=True)
+            s.set_spectrum(sg, wg)
+            s.set_scheme(nf)
+            s.set_state(None)
+            s.reset_timing()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = s.iterate(wl.max_iter, wl.tol, want_x=False)
+            torch.cuda.synchronize()
+            t = (time.perf_counter() - t0) * 1e3
+            tmn = s.timing()
+            res[name] = {"sweeps": r["iters"], "converged": r["converged"], "ms": t,
+                         "path_recording_ms": tmn["record_ms"],
+                         "ms_per_sweep_after_recording": (t - tmn["record_ms"]) / max(r["iters"], 1)}
+        s.enable_timing(False)
+        s.set_scheme(False)
+        s.set_spectrum(wl.sigma, wl.w)
+        s.set_state(None)
+        out["near_far_scheme"] = res
     if args.adjoint:
         # forward+adjoint against the plain forward, K frozen at the solve's iterations
         K = int(iters[-1])

@@ -160,6 +160,26 @@ int rrt_compute_gamma(rrt_ctx* ctx, double* lnG_out, double* G_out, float* tau_o
  * (nullable, syncs). */
 int rrt_update_equilibrium(rrt_ctx* ctx, double* x_out, double* max_dx_out);
 
+/* The paper's stable scheme for SPH (Sec. 4.1.2).  near_far = 1: the
+ * particles a ray from source i intersects are split into near ones (their
+ * kernel contains i, so they contribute to i's density in the scatter form of
+ * eq. nhi; |d|^2 < h^2 in FP64 with d as in the hit predicate) and far ones.
+ * Per ray the far HI column attenuates the radiation reaching a uniform slab
+ * that stands for the near particles: density n_H and temperature of i, total
+ * hydrogen column = the near particles' column with every x = 1.  The ray's
+ * rate is the rate at the bottom of that slab (eq. gammashldk), from the
+ * monochromatic slab solution of Appendix C.4, so the spectrum must have one
+ * bin (RRT_E_STATE otherwise); Gamma = (1/n_ray) sum_k Gamma_k (eq.
+ * gammashld).  Recorded paths are dropped when the scheme changes.  While it is
+ * set, rrt_forward, rrt_backward, rrt_iterate_halos and update rules other
+ * than the default return RRT_E_STATE.  0 (default): the plain scheme. */
+int rrt_set_scheme(rrt_ctx* ctx, int32_t near_far);
+
+/* Near total-hydrogen columns of the last rrt_compute_columns under the
+ * near/far scheme (the far columns are what rrt_compute_columns returns):
+ * device double out[n][n_ray], input order, cm^-2.  Synchronises. */
+int rrt_get_near_columns(rrt_ctx* ctx, double* out);
+
 /* The update rule of rrt_iterate_equilibrium, after the paper's own scheme
  * (Sec. 4, implementation details).  Defaults (0, +inf, 0, 1) give the
  * order-independent case A update that every other entry point assumes.

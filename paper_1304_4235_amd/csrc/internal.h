@@ -162,6 +162,9 @@ struct Ctx {
     bool tiles_valid = false;
     bool tiles_unfit = false;
     int32_t use_tiles = 0;         // 1: build row tiles after kTileAfter evaluations
+    // near/far scheme (rrt_set_scheme): near total-hydrogen columns per ray
+    int32_t near_far = 0;
+    double* Nn_s = nullptr;        // [n_ray][n]
     // the paper's update rule for the fixed point (rrt_set_update_rule)
     double rule_tau_skip = 0.0;    // first-sweep tau_eff below this: frozen
     double rule_tau_case_b = HUGE_VAL;   // case B recombination from this tau_eff

@@ -42,4 +42,55 @@ __device__ __forceinline__ double x_minus(double G, double nH, double al, double
     return 2.0 * P / (negQ + sqrt(eq_discriminant(G, nH, al, gc)));
 }
 
+// ln of the photoionisation rate at total hydrogen column N into a uniform
+// slab of density nH (coefficients alpha, gcoll at its temperature) lit by
+// monochromatic radiation of cross-section sigma that gives the rate
+// exp(lnG0) at the surface (Appendix C.4): the depth of neutral fraction x is
+//   sigma N = (1/x0 - 1/x) + ln[x(1-x0)/(x0(1-x))] + (1/xce) ln[x(xce-x0)/(x0(xce-x))]
+// and the rate there nH (alpha+gcoll)(1-x)(xce-x)/x.  Newton's method on
+// v = ln(xce - x), kept inside a shrinking bracket, so thick slabs (where
+// xce - x underflows) stay finite in ln Gamma.
+__device__ inline double slab_ln_rate(double lnG0, double nH, double alpha, double gcoll,
+                                      double sigma, double N)
+{
+    if (lnG0 == -INFINITY) return -INFINITY;
+    const double xce = alpha / (alpha + gcoll);
+    const double target = sigma * N;
+    const double lg = lnG0 - log(nH);
+    // below the double range the surface is already at xce: the slab only
+    // attenuates by its neutral column xce N
+    if (lg < -700.0) return lnG0 - target * xce;
+    if (!(target > 0.0)) return lnG0;
+    const double G = exp(lg);
+    const double sD = sqrt((G + gcoll) * (G + gcoll) + 4.0 * G * alpha);
+    const double den = G + 2.0 * alpha + gcoll + sD;
+    const double x0 = 2.0 * alpha / den;
+    // xce - x0 without cancellation
+    const double e0 = alpha * G * (1.0 + (G + 2.0 * gcoll + 4.0 * alpha) / (sD + gcoll)) /
+                      ((alpha + gcoll) * den);
+    const double v0 = log(e0);
+    const double c0 = 1.0 / x0 + log((1.0 - x0) / x0) + log(e0 / x0) / xce;
+    double lo = v0 - xce * target - 64.0, hi = v0;
+    double v = v0 - xce * target;                     // deep-slab estimate
+    if (v < lo || v > hi) v = 0.5 * (lo + hi);
+    for (int it = 0; it < 100; ++it) {
+        const double e = exp(v), x = xce - e;
+        // F(v) - target, decreasing in v
+        const double F = c0 - 1.0 / x + log(x / (1.0 - x)) + (log(x) - v) / xce - target;
+        if (F > 0.0) lo = v;
+        else hi = v;
+        const double dF = -e * (1.0 / (x * x) + 1.0 / x + 1.0 / (1.0 - x) + 1.0 / (xce * x)) -
+                          1.0 / xce;
+        double vn = v - F / dF;
+        if (!(vn > lo && vn < hi)) vn = 0.5 * (lo + hi);   // keep to the bracket
+        if (fabs(vn - v) <= 1e-14 * fmax(1.0, fabs(v))) {
+            v = vn;
+            break;
+        }
+        v = vn;
+    }
+    const double xs = xce - exp(v);
+    return log(nH) + log(alpha + gcoll) + log1p(-xs) + v - log(xs);
+}
+
 }  // namespace rrt

@@ -57,6 +57,11 @@ struct RateRule {
     double tau_case_b;        // +inf = case A throughout
     const double* alphaB;
     int relative;
+    // near/far scheme (one frequency bin): far columns in N, near total-hydrogen
+    // columns here; each ray's rate is the slab solution of its near column lit
+    // by the far-attenuated radiation (null = plain rate)
+    const double* Nn;
+    double sigma1;
 };
 
 // One thread per particle: rays, then bins; optionally the equilibrium update.
@@ -77,30 +82,48 @@ k_gamma(const double* __restrict__ N, int64_t n, int n_ray, int n_bins,
     const bool live = !(seg_active && h >= 0 && seg_active[h] == 0) &&
                       !(rule.want && i < n && rule.want[i] == 0);
     if (i < n && live) {
-        double m = -INFINITY, s = 0.0;
-        for (int k = 0; k < n_ray; ++k) {
-            double Nk = N[(int64_t)k * n + i];
-            float Nf = (float)Nk;
-            float S0 = 0.f, S1 = 0.f, S2 = 0.f, S3 = 0.f;
-            int b = 0;
-            for (; b + 3 < n_bins; b += 4) {
-                S0 = fmaf(ws_rel[b], exp2f(-dsig_l2[b] * Nf), S0);
-                S1 = fmaf(ws_rel[b + 1], exp2f(-dsig_l2[b + 1] * Nf), S1);
-                S2 = fmaf(ws_rel[b + 2], exp2f(-dsig_l2[b + 2] * Nf), S2);
-                S3 = fmaf(ws_rel[b + 3], exp2f(-dsig_l2[b + 3] * Nf), S3);
+        double m = -INFINITY, s = 0.0, l;
+        if (rule.Nn) {
+            // near/far: per ray the slab of near particles lit by the radiation
+            // the far particles let through (one bin: ln w sigma = ln_ws_max)
+            for (int k = 0; k < n_ray; ++k) {
+                const double l0 = ln_ws_max - rule.sigma1 * N[(int64_t)k * n + i];
+                const double v = slab_ln_rate(l0, (double)nH_s[i], alpha[i], gcoll[i],
+                                              rule.sigma1, rule.Nn[(int64_t)k * n + i]);
+                if (v == -INFINITY) continue;
+                if (v > m) {
+                    s = s * exp(m - v) + 1.0;
+                    m = v;
+                } else {
+                    s += exp(v - m);
+                }
             }
-            for (; b < n_bins; ++b) S0 = fmaf(ws_rel[b], exp2f(-dsig_l2[b] * Nf), S0);
-            float S = (S0 + S1) + (S2 + S3);
-            if (!(S > 0.f)) continue;                     // this ray carries nothing
-            double v = -sigma_min * Nk + log((double)S);
-            if (v > m) {
-                s = s * exp(m - v) + 1.0;
-                m = v;
-            } else {
-                s += exp(v - m);
+            l = (s > 0.0) ? (m + log(s / (double)n_ray)) : -INFINITY;
+        } else {
+            for (int k = 0; k < n_ray; ++k) {
+                double Nk = N[(int64_t)k * n + i];
+                float Nf = (float)Nk;
+                float S0 = 0.f, S1 = 0.f, S2 = 0.f, S3 = 0.f;
+                int b = 0;
+                for (; b + 3 < n_bins; b += 4) {
+                    S0 = fmaf(ws_rel[b], exp2f(-dsig_l2[b] * Nf), S0);
+                    S1 = fmaf(ws_rel[b + 1], exp2f(-dsig_l2[b + 1] * Nf), S1);
+                    S2 = fmaf(ws_rel[b + 2], exp2f(-dsig_l2[b + 2] * Nf), S2);
+                    S3 = fmaf(ws_rel[b + 3], exp2f(-dsig_l2[b + 3] * Nf), S3);
+                }
+                for (; b < n_bins; ++b) S0 = fmaf(ws_rel[b], exp2f(-dsig_l2[b] * Nf), S0);
+                float S = (S0 + S1) + (S2 + S3);
+                if (!(S > 0.f)) continue;                     // this ray carries nothing
+                double v = -sigma_min * Nk + log((double)S);
+                if (v > m) {
+                    s = s * exp(m - v) + 1.0;
+                    m = v;
+                } else {
+                    s += exp(v - m);
+                }
             }
+            l = (s > 0.0) ? (ln_ws_max + m + log(s / (double)n_ray)) : -INFINITY;
         }
-        double l = (s > 0.0) ? (ln_ws_max + m + log(s / (double)n_ray)) : -INFINITY;
         double g = exp(l);
         if (lnG) lnG[i] = l;
         if (G) G[i] = g;
@@ -257,6 +280,8 @@ hipError_t launch_gamma(Ctx& c, bool update_x, bool first_sweep)
     rule.tau_case_b = c.rule_tau_case_b;
     rule.alphaB = c.alphaB_s;
     rule.relative = c.rule_relative;
+    rule.Nn = c.near_far ? c.Nn_s : nullptr;
+    rule.sigma1 = c.sigma_min;
     hipLaunchKernelGGL(k_gamma, dim3(nblk(c.n)), dim3(kBlock), 0, c.stream, c.N_s, c.n, c.n_ray,
                        c.n_bins, c.ws_rel, c.dsig_l2, c.sigma_min, c.ln_ws_max,
                        std::log(c.gamma_thin), c.lnG_s, c.G_s, c.tau_s, update_x ? 1 : 0, c.nH_s,

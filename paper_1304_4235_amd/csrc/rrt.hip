@@ -65,7 +65,7 @@ void free_particles(Ctx& c)
                     c.perm, c.codes, c.nodes, c.keys_b, c.vals_b, c.k_left, c.k_right,
                     c.k_parent, c.k_first, c.k_last, c.k_lo, c.k_hi, c.k_cnt, c.k_dfs, c.k_flag,
                     c.seg_of, c.k_seg, c.alphaB_s, c.skip_s, c.want_s, c.block_s,
-                    c.block_list};
+                    c.block_list, c.Nn_s};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     c.seg_of = c.k_seg = nullptr;
@@ -74,6 +74,7 @@ void free_particles(Ctx& c)
     c.block_s = nullptr;
     c.block_list = nullptr;
     c.blocks_for = 0;
+    c.Nn_s = nullptr;
     void* adj[] = {c.xhist, c.adj_lam, c.adj_lup, c.adj_nu, c.adj_pis, c.adj_gnH, c.adj_y,
                    c.adj_wpart, c.adj_gw, c.adj_tpart};
     for (void* b : adj)
@@ -136,11 +137,14 @@ int alloc_columns(Ctx& c)
 {
     if (c.N_s) (void)hipFree(c.N_s);
     c.N_s = nullptr;
+    if (c.Nn_s) (void)hipFree(c.Nn_s);
+    c.Nn_s = nullptr;
     // rays are indexed with 32-bit integers on the device
     if (c.n * (int64_t)c.n_ray > kMaxRows)
         return fail(c, RRT_E_ARG, "%lld particles x %d rays exceeds 2^31 - 1 rays",
                     (long long)c.n, c.n_ray);
     hipError_t e = dalloc(&c.N_s, (size_t)c.n * (size_t)c.n_ray);
+    if (e == hipSuccess && c.near_far) e = dalloc(&c.Nn_s, (size_t)c.n * (size_t)c.n_ray);
     if (e != hipSuccess)
         return fail(c, RRT_E_NOMEM, "column buffer allocation failed: %s", hipGetErrorString(e));
     return RRT_OK;
@@ -259,13 +263,13 @@ int columns_impl(Ctx& c, int64_t* hits)
         // intersections per ray up to hundreds; short rays want fewer lanes
         const int group = c.path_group ? c.path_group
                           : mean >= 40 ? 32 : mean >= 16 ? 16 : 8;
-        if (c.use_tiles && !c.tiles_valid && !c.tiles_unfit && !c.capturing &&
+        if (c.use_tiles && !c.near_far && !c.tiles_valid && !c.tiles_unfit && !c.capturing &&
             ++c.path_evals > kTileAfter) {
             ev_begin(c);
             HIP_OK(build_tiles(c));
             if (c.timing) c.t_tile_build += ev_end(c);
         }
-        const bool tiles = c.tiles_valid && c.use_tiles;
+        const bool tiles = c.tiles_valid && c.use_tiles && !c.near_far;
         ev_begin(c);
         if (tiles) HIP_OK(launch_tile_columns(c, group));
         else HIP_OK(launch_path_columns(c, group));
@@ -680,6 +684,8 @@ int rrt_compute_gamma(rrt_ctx* x, double* lnG_out, double* G_out, float* tau_out
     Ctx& c = x->c;
     if (int r = need_tree(c)) return r;
     if (!c.have_columns) return fail(c, RRT_E_STATE, "no columns: call rrt_compute_columns");
+    if (c.near_far && c.n_bins != 1)
+        return fail(c, RRT_E_STATE, "the near/far slab solution needs one frequency bin");
     HIP_OK(launch_gamma(c, false));
     c.have_gamma = true;
     if (lnG_out) HIP_OK(launch_to_input_order_d(c, c.lnG_s, lnG_out, 1));
@@ -768,6 +774,31 @@ struct WantGuard {
 
 }  // namespace
 
+int rrt_set_scheme(rrt_ctx* x, int32_t near_far)
+{
+    if (!x) return RRT_E_ARG;
+    Ctx& c = x->c;
+    if (near_far != 0 && near_far != 1) return fail(c, RRT_E_ARG, "near_far must be 0 or 1");
+    if (near_far == c.near_far) return RRT_OK;
+    c.near_far = near_far;
+    free_paths(c);                    // recorded entries carry the near flag
+    c.have_columns = c.have_gamma = false;
+    if (c.n > 0 && c.have_rays) return alloc_columns(c);
+    return RRT_OK;
+}
+
+int rrt_get_near_columns(rrt_ctx* x, double* out)
+{
+    if (!x) return RRT_E_ARG;
+    Ctx& c = x->c;
+    if (!out) return fail(c, RRT_E_ARG, "out is required");
+    if (!c.near_far || !c.have_columns)
+        return fail(c, RRT_E_STATE, "near columns need the near/far scheme and rrt_compute_columns");
+    HIP_OK(launch_to_input_order_d(c, c.Nn_s, out, c.n_ray));
+    HIP_OK(hipStreamSynchronize(c.stream));
+    return RRT_OK;
+}
+
 int rrt_set_update_rule(rrt_ctx* x, double tau_skip, double tau_case_b, int32_t relative,
                         int32_t n_blocks)
 {
@@ -792,6 +823,10 @@ int rrt_iterate_equilibrium(rrt_ctx* x, int32_t max_iter, double tol, double* x_
     Ctx& c = x->c;
     if (int r = need_tree(c)) return r;
     if (max_iter < 0 || !(tol >= 0.0)) return fail(c, RRT_E_ARG, "max_iter >= 0 and tol >= 0");
+    if (c.near_far && c.n_bins != 1)
+        return fail(c, RRT_E_STATE, "the near/far slab solution needs one frequency bin");
+    if (c.near_far && !default_rule(c))
+        return fail(c, RRT_E_STATE, "the near/far scheme runs with the default update rule");
     const bool ordered = c.rule_blocks > 1;
     const bool skipping = c.rule_tau_skip > 0.0;
     if (ordered && c.rule_blocks > c.n)
@@ -866,9 +901,9 @@ int rrt_forward(rrt_ctx* x, int32_t K, double* lnG_out, double* x_out)
     Ctx& c = x->c;
     if (int r = need_tree(c)) return r;
     if (K < 1 || K > 100000) return fail(c, RRT_E_ARG, "K must be 1..100000");
-    if (!default_rule(c))
-        return fail(c, RRT_E_STATE, "the reverse mode differentiates the order-independent "
-                                    "case A update: reset the update rule");
+    if (!default_rule(c) || c.near_far)
+        return fail(c, RRT_E_STATE, "the reverse mode differentiates the plain order-independent "
+                                    "case A update: reset the update rule and the scheme");
     const size_t n = (size_t)c.n;
     if (c.xhist_cap < K + 1 || !c.xhist) {
         HIP_OK(dalloc(&c.xhist, (size_t)(K + 1) * n));
@@ -1173,9 +1208,9 @@ int rrt_iterate_halos(rrt_ctx* x, int32_t max_iter, double tol, int32_t per_laun
     if (int r = need_tree(c)) return r;
     if (max_iter < 1 || !(tol >= 0.0) || per_launch < 1 || per_launch > 256)
         return fail(c, RRT_E_ARG, "max_iter >= 1, tol >= 0, per_launch 1..256");
-    if (!default_rule(c))
-        return fail(c, RRT_E_STATE, "batched halos use the order-independent case A update: "
-                                    "reset the update rule");
+    if (!default_rule(c) || c.near_far)
+        return fail(c, RRT_E_STATE, "batched halos use the plain order-independent case A "
+                                    "update: reset the update rule and the scheme");
     if (int r = ensure_seg_buffers(c)) return r;
     SegGuard guard(c);
     HIP_OK(launch_seg_init(c));

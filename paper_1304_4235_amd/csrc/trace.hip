@@ -112,7 +112,15 @@ struct RayOut {
     uint64_t hit_cap;       // record mode: capacity of hit_j / hit_img
     const int32_t* perm;
     unsigned long long* hits_total;
+    // near/far split (column and path modes): a hit is near when the
+    // particle's kernel contains the source, |d|^2 < h^2 (FP64, x, y, z order)
+    int near_far;
+    double* Nn;             // column mode: [n_ray][n] near total-hydrogen columns
+    const double* mu;       // hydrogen content per tree index (near columns use x = 1)
 };
+
+// sign bit of a recorded factor: the hit is near (factors are >= 0)
+constexpr uint32_t kNearBit = 0x80000000u;
 
 // The canonical predicate (shared operation order with the FP64 reference):
 // d = (r_j - r_p) + s B ; s_par = d.u ; t = clamp(s_par, 0, L) ; c = d - t u ;
@@ -162,7 +170,7 @@ k_trace(const Node* __restrict__ nodes, const float4* __restrict__ p4,
             if (fabsf(ua) < 1e-20f) ua = 1e-20f;
             inv[a] = 1.0f / ua;
         }
-        double acc = 0.0;
+        double acc = 0.0, accn = 0.0;
         uint64_t w = (MODE == kModeRecord || MODE == kModePath) ? out.row_off[gid] : 0;
         const double nur = (MODE == kModeScatter) ? out.nu[gid] : 0.0;
 
@@ -264,11 +272,15 @@ k_trace(const Node* __restrict__ nodes, const float4* __restrict__ p4,
                         }
                         gk = ih2 * K;
                     }
+                    const bool near = out.near_far && (d0 * d0 + d1 * d1 + d2 * d2) < h2;
                     if (MODE == kModePath) {
-                        if (w < out.hit_cap) out.path[w] = make_int2(j, __float_as_int(gk));
+                        const uint32_t bits = (uint32_t)__float_as_int(gk) | (near ? kNearBit : 0u);
+                        if (w < out.hit_cap) out.path[w] = make_int2(j, (int)bits);
                         ++w;
                     } else if (MODE == kModeScatter) {
                         if (nur != 0.0) unsafeAtomicAdd(out.y + j, (double)gk * nur);
+                    } else if (near) {
+                        accn += (double)((float)out.mu[j] * gk);
                     } else {
                         acc += (double)(mux[j] * gk);
                     }
@@ -277,6 +289,7 @@ k_trace(const Node* __restrict__ nodes, const float4* __restrict__ p4,
             }
         }
         if ((MODE == kModeColumn || MODE == kModeRecord) && live) out.N[(int64_t)k * g.n + ps] = acc;
+        if (MODE == kModeColumn && live && out.near_far) out.Nn[(int64_t)k * g.n + ps] = accn;
         if (MODE == kModeCount) out.row_cnt[gid] = cnt;
     }
     // one atomic per wave for the total intersection count
@@ -360,7 +373,7 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
         if (fabsf(ua) < 1e-20f) ua = 1e-20f;
         inv[a] = 1.0f / ua;
     }
-    double acc = 0.0;
+    double acc = 0.0, accn = 0.0;
     uint32_t cnt = 0;
     uint64_t w = ((MODE == kModeRecord || MODE == kModePath) && active) ? out.row_off[gid] : 0;
     const double nur = (MODE == kModeScatter && active) ? out.nu[gid] : 0.0;
@@ -449,6 +462,7 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
                 double hj = (double)Q.w;
                 double h2 = hj * hj;
                 const bool in = D2 < h2;
+                const bool near = out.near_far && (d0 * d0 + d1 * d1 + d2 * d2) < h2;
                 float gk = 0.0f;
                 if (kTerms && in) {
                     double px = d0 - sp * u[0], py = d1 - sp * u[1], pz = d2 - sp * u[2];
@@ -474,7 +488,7 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
                         gk = ih2 * K;
                     }
                 }
-                s_in[wv][t] = in ? 1 : 0;
+                s_in[wv][t] = in ? (near ? 2 : 1) : 0;
                 s_gk[wv][t] = gk;
             }
             wave_sync();
@@ -493,11 +507,15 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
                         }
                         ++w;
                     }
+                    const bool near = s_in[wv][t] == 2;
                     if (MODE == kModePath) {
-                        if (w < out.hit_cap) out.path[w] = make_int2(j, __float_as_int(gk));
+                        const uint32_t bits = (uint32_t)__float_as_int(gk) | (near ? kNearBit : 0u);
+                        if (w < out.hit_cap) out.path[w] = make_int2(j, (int)bits);
                         ++w;
                     } else if (MODE == kModeScatter) {
                         if (nur != 0.0) unsafeAtomicAdd(out.y + j, (double)gk * nur);
+                    } else if (near) {
+                        accn += (double)((float)out.mu[j] * gk);
                     } else {
                         acc += (double)(mux[j] * gk);
                     }
@@ -510,6 +528,7 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
     }   // halos of this wave
     if (active) {
         if ((MODE == kModeColumn || MODE == kModeRecord) && live) out.N[gid] = acc;
+        if (MODE == kModeColumn && live && out.near_far) out.Nn[gid] = accn;
         if (MODE == kModeCount) out.row_cnt[gid] = cnt;
     }
     uint64_t c64 = cnt;
@@ -564,13 +583,13 @@ static hipError_t launch_mode(Ctx& c, int mode, RayOut o)
 // G lanes share a row; they stride through it (coalesced 8-byte loads) and
 // reduce their partial sums in FP64.
 // ---------------------------------------------------------------------------
-template <int G>
+template <int G, bool NF>
 __global__ void __launch_bounds__(256)
 k_path_columns(const uint64_t* __restrict__ row_off, const int2* __restrict__ path,
                const float* __restrict__ mux, int64_t n_rows, double* __restrict__ N, int64_t n,
                const int32_t* __restrict__ seg_of, const int32_t* __restrict__ seg_active,
                const uint8_t* __restrict__ want, const int32_t* __restrict__ list,
-               int64_t list_n)
+               int64_t list_n, double* __restrict__ Nn, const double* __restrict__ mu)
 {
     const int lane = threadIdx.x & (G - 1);
     const int64_t stride = (int64_t)gridDim.x * (blockDim.x / G);
@@ -585,7 +604,7 @@ k_path_columns(const uint64_t* __restrict__ row_off, const int2* __restrict__ pa
         if (seg_active && seg_active[seg_of[row % n]] == 0) continue;
         if (want && !want[row % n]) continue;     // not updated in this step
         const uint64_t a = row_off[row], b = row_off[row + 1];
-        double acc = 0.0;
+        double acc = 0.0, accn = 0.0;
         // Lanes stride through the row one entry at a time, so the particle
         // gathers of one instruction are consecutive intersections along the
         // ray and share cache lines (measured: grouping four consecutive
@@ -598,13 +617,29 @@ k_path_columns(const uint64_t* __restrict__ row_off, const int2* __restrict__ pa
             const long long v3 = e + 3 * G < b ? __builtin_nontemporal_load(p + e + 3 * G) : 0ll;
             const float m0 = mux[(int)v0], m1 = mux[(int)v1];
             const float m2 = mux[(int)v2], m3 = mux[(int)v3];
-            acc += (double)(m0 * __int_as_float((int)(v0 >> 32)));
-            acc += (double)(m1 * __int_as_float((int)(v1 >> 32)));
-            acc += (double)(m2 * __int_as_float((int)(v2 >> 32)));
-            acc += (double)(m3 * __int_as_float((int)(v3 >> 32)));
+            if (!NF) {
+                acc += (double)(m0 * __int_as_float((int)(v0 >> 32)));
+                acc += (double)(m1 * __int_as_float((int)(v1 >> 32)));
+                acc += (double)(m2 * __int_as_float((int)(v2 >> 32)));
+                acc += (double)(m3 * __int_as_float((int)(v3 >> 32)));
+            } else {
+                // near hits (sign bit) add mu * factor to the near column
+                const long long vv[4] = {v0, v1, v2, v3};
+                const float mm[4] = {m0, m1, m2, m3};
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const uint32_t bits = (uint32_t)(vv[q] >> 32);
+                    const float f = __int_as_float((int)(bits & ~kNearBit));
+                    if (bits & kNearBit) accn += (double)((float)mu[(int)vv[q]] * f);
+                    else acc += (double)(mm[q] * f);
+                }
+            }
         }
         for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
+        if (NF)
+            for (int off = G / 2; off > 0; off >>= 1) accn += __shfl_xor(accn, off, G);
         if (lane == 0) N[row] = acc;
+        if (NF && lane == 0) Nn[row] = accn;
     }
 }
 
@@ -614,6 +649,9 @@ hipError_t launch_columns(Ctx& c)
     o.N = c.N_s;
     o.perm = c.perm;
     o.hits_total = c.red + 1;
+    o.near_far = c.near_far;
+    o.Nn = c.Nn_s;
+    o.mu = c.mu_s;
     return launch_mode(c, kModeColumn, o);
 }
 
@@ -648,6 +686,7 @@ hipError_t launch_record_paths(Ctx& c, const uint64_t* row_off, int2* path, uint
     o.path = path;
     o.perm = c.perm;
     o.hits_total = c.red + 3;
+    o.near_far = c.near_far;
     return launch_mode(c, kModePath, o);
 }
 
@@ -661,6 +700,25 @@ hipError_t launch_scatter_traverse(Ctx& c, const double* nu, double* y)
     return launch_mode(c, kModeScatter, o);
 }
 
+namespace {
+
+template <int G>
+hipError_t launch_path_g(Ctx& c, int64_t n_rows, unsigned nb)
+{
+    if (c.near_far)
+        hipLaunchKernelGGL((k_path_columns<G, true>), dim3(nb), dim3(256), 0, c.stream, c.row_off,
+                           c.path, c.mux_s, n_rows, c.N_s, c.n, c.geom.seg_of, c.geom.seg_active,
+                           c.geom.want, c.row_list, c.row_list_n, c.Nn_s, c.mu_s);
+    else
+        hipLaunchKernelGGL((k_path_columns<G, false>), dim3(nb), dim3(256), 0, c.stream,
+                           c.row_off, c.path, c.mux_s, n_rows, c.N_s, c.n, c.geom.seg_of,
+                           c.geom.seg_active, c.geom.want, c.row_list, c.row_list_n, nullptr,
+                           nullptr);
+    return hipGetLastError();
+}
+
+}  // namespace
+
 hipError_t launch_path_columns(Ctx& c, int group)
 {
     const int64_t n_rows = c.n * (int64_t)c.n_ray;
@@ -668,23 +726,10 @@ hipError_t launch_path_columns(Ctx& c, int group)
     const int64_t n_iter = c.row_list ? c.row_list_n * (int64_t)c.n_ray : n_rows;
     if (n_iter == 0) return hipSuccess;
     const unsigned nb = stride_blocks(n_iter, bs / group);
-    if (group == 64)
-        hipLaunchKernelGGL(k_path_columns<64>, dim3(nb), dim3(bs), 0, c.stream, c.row_off, c.path,
-                           c.mux_s, n_rows, c.N_s, c.n, c.geom.seg_of, c.geom.seg_active,
-                           c.geom.want, c.row_list, c.row_list_n);
-    else if (group == 32)
-        hipLaunchKernelGGL(k_path_columns<32>, dim3(nb), dim3(bs), 0, c.stream, c.row_off, c.path,
-                           c.mux_s, n_rows, c.N_s, c.n, c.geom.seg_of, c.geom.seg_active,
-                           c.geom.want, c.row_list, c.row_list_n);
-    else if (group == 16)
-        hipLaunchKernelGGL(k_path_columns<16>, dim3(nb), dim3(bs), 0, c.stream, c.row_off, c.path,
-                           c.mux_s, n_rows, c.N_s, c.n, c.geom.seg_of, c.geom.seg_active,
-                           c.geom.want, c.row_list, c.row_list_n);
-    else
-        hipLaunchKernelGGL(k_path_columns<8>, dim3(nb), dim3(bs), 0, c.stream, c.row_off, c.path,
-                           c.mux_s, n_rows, c.N_s, c.n, c.geom.seg_of, c.geom.seg_active,
-                           c.geom.want, c.row_list, c.row_list_n);
-    return hipGetLastError();
+    if (group == 64) return launch_path_g<64>(c, n_rows, nb);
+    if (group == 32) return launch_path_g<32>(c, n_rows, nb);
+    if (group == 16) return launch_path_g<16>(c, n_rows, nb);
+    return launch_path_g<8>(c, n_rows, nb);
 }
 
 }  // namespace rrt

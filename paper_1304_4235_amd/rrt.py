@@ -64,6 +64,8 @@ SIGNATURES = {
     "rrt_set_halos": ([_vp, _i32, _vp], C.c_int),
     "rrt_set_tuning": ([_vp, _i32, _i32], C.c_int),
     "rrt_set_update_rule": ([_vp, _d, _d, _i32, _i32], C.c_int),
+    "rrt_set_scheme": ([_vp, _i32], C.c_int),
+    "rrt_get_near_columns": ([_vp, _vp], C.c_int),
     "rrt_iterate_halos": ([_vp, _i32, _d, _i32, _vp, _vp], C.c_int),
     "rrt_forward": ([_vp, _i32, _vp, _vp], C.c_int),
     "rrt_backward": ([_vp, _vp, _vp, _vp, _vp], C.c_int),
@@ -185,6 +187,16 @@ class Solver:
         self._check(_lib.rrt_set_update_rule(self._h, float(tau_skip), float(tau_case_b),
                                              int(bool(relative)), int(n_blocks)),
                     "rrt_set_update_rule")
+
+    def set_scheme(self, near_far: bool):
+        """The paper's near/far scheme (True) or the plain scheme (False)."""
+        self._check(_lib.rrt_set_scheme(self._h, int(bool(near_far))), "rrt_set_scheme")
+
+    def near_columns(self):
+        """Near total-hydrogen columns [n, n_ray] of the last compute_columns."""
+        out = torch.empty(self.n, self.n_ray, dtype=torch.float64, device=self.device)
+        self._check(_lib.rrt_get_near_columns(self._h, _ptr(out)), "rrt_get_near_columns")
+        return out
 
     def set_halos(self, offsets):
         off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
