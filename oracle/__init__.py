@@ -65,6 +65,8 @@ def lib():
         L.orc_columns_near_far.argtypes = [i64, vp, vp, vp, vp, i32, vp, d, d, i64, vp, d, vp, vp,
                                            vp, i32]
         L.orc_columns_near_far.restype = C.c_int
+        L.orc_x_evolve.argtypes = [d, d, d, d, d, d]
+        L.orc_x_evolve.restype = d
         L.orc_slab_lnG.argtypes = [d, d, d, d, d, d]
         L.orc_slab_lnG.restype = d
         L.orc_gamma_near_far.argtypes = [i64, i32, vp, vp, d, d, vp, vp, vp, vp]
@@ -278,6 +280,33 @@ def solve_rule(wl, tau_skip: float = 0.0, tau_case_b: float = float("inf"),
     k = int(it[0])
     return dict(x_hist=xh[: k + 1], lnG_hist=lh[:k], skipped=sk.astype(bool), iters=k,
                 maxdx=md[:k])
+
+
+# ----------------------------------------------------------------------------
+# non-equilibrium evolution (Appendix C.3, time-dependent solution)
+# ----------------------------------------------------------------------------
+def x_evolve(x0, Gamma, nH, alpha, gcoll, t):
+    """x after time t at constant rates, from x0."""
+    f = lib().orc_x_evolve
+    b = np.broadcast_arrays(*map(np.asarray, (x0, Gamma, nH, alpha, gcoll, t)))
+    out = np.array([f(*map(float, v)) for v in zip(*[a.ravel() for a in b])])
+    return out.reshape(b[0].shape)
+
+
+def evolve(wl, x0: np.ndarray, dt: float, n_steps: int, rtol=DEFAULT_RTOL):
+    """n_steps of: columns and Gamma at the current state, then every particle
+    advances by dt at that Gamma.  Returns the states after each step."""
+    T = wl.T.astype(np.float64)
+    nH = wl.n_H.astype(np.float64)
+    al, ga = alpha_A(T), gamma_coll(T)
+    x = np.asarray(x0, np.float64).copy()
+    hist = [x.copy()]
+    for _ in range(n_steps):
+        N = columns(wl, x, rtol=rtol)
+        _, G, _ = gamma(N, wl.sigma, wl.w)
+        x = x_evolve(x, G, nH, al, ga, dt)
+        hist.append(x.copy())
+    return np.array(hist)
 
 
 # ----------------------------------------------------------------------------

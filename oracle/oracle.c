@@ -293,6 +293,26 @@ int orc_columns(int64_t n, const float* pos, const float* h, const float* mu, co
 }
 
 /* ------------------------------------------------------------------------- */
+/* Non-equilibrium evolution at constant Gamma, T, nH (Appendix C.3, y = 0):    */
+/* dx/dt = R (x - x_eq)(x - x_+) integrates to                                */
+/*   x(t) = x_eq + (x0 - x_eq) (x_+ - x_eq) F / ((x_+ - x0) + (x0 - x_eq) F),  */
+/*   F = exp(-(x_+ - x_eq) t / t_rc),  t_rc = 1 / ((alpha + gamma) nH),        */
+/* with x_eq = x_- and x_+ the roots of eq. xroots.  In long double.           */
+/* ------------------------------------------------------------------------- */
+double orc_x_evolve(double x0, double Gamma, double nH, double alpha, double gcoll, double t)
+{
+    const long double n = nH, a = alpha, g = gcoll, G = Gamma;
+    const long double R = (g + a) * n, P = a * n, negQ = G + a * n + R;
+    const long double disc = negQ * negQ - 4.0L * P * R;
+    const long double sq = sqrtl(disc > 0.0L ? disc : 0.0L);
+    const long double xm = 2.0L * P / (negQ + sq);       /* x_- (Vieta form)        */
+    const long double xp = (negQ + sq) / (2.0L * R);      /* x_+                      */
+    const long double F = expl(-(xp - xm) * (long double)t * R);
+    const long double d0 = (long double)x0 - xm;
+    return (double)(xm + d0 * (xp - xm) * F / ((xp - (long double)x0) + d0 * F));
+}
+
+/* ------------------------------------------------------------------------- */
 /* Near/far split (Sec. 4.1.2).  The near particles of source p are those that */
 /* contribute to p's density in the scatter form of eq. nhi: the particle     */
 /* image whose kernel sphere contains p, |d|^2 < h_j^2 with d as in the hit    */

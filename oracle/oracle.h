@@ -23,6 +23,7 @@ int orc_columns_near_far(int64_t n, const float* pos, const float* h, const floa
                          const double* x, int32_t n_ray, const double* dirs, double L, double box,
                          int64_t n_src, const int64_t* src, double rtol, double* N_far,
                          double* N_near, int64_t* near_hits, int32_t n_threads);
+double orc_x_evolve(double x0, double Gamma, double nH, double alpha, double gcoll, double t);
 double orc_slab_lnG(double lnG0, double nH, double alpha, double gcoll, double sigma, double N);
 void orc_gamma_near_far(int64_t n_src, int32_t n_ray, const double* N_far, const double* N_near,
                         double w, double sigma, const double* nH, const double* alpha,

@@ -493,6 +493,31 @@ def test_rule_relative_convergence():
 
 
 # ---------------------------------------------------------------------------
+# non-equilibrium evolution (Appendix C.3)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("G,nH,x0", [(1e-12, 1e-3, 1e-5), (1e-13, 1e-1, 0.9), (0.0, 1e-2, 0.3),
+                                     (1e-11, 1e-4, 0.5)])
+def test_x_evolve_against_numerical_integration(G, nH, x0):
+    """The closed form against a high-accuracy integration of eq. dxdt."""
+    from scipy.integrate import solve_ivp
+    a, g = oracle.alpha_A(1e4)[0], oracle.gamma_coll(1e4)[0]
+    trc = 1.0 / ((a + g) * nH)
+    ts = np.array([0.0, 0.01, 0.3, 2.0, 10.0]) * trc
+    rhs = lambda t, x: [-(G + g * (1 - x[0]) * nH) * x[0] + a * (1 - x[0]) * nH * (1 - x[0])]
+    sol = solve_ivp(rhs, (0, ts[-1]), [x0], t_eval=ts, rtol=1e-12, atol=1e-16, method="Radau")
+    got = oracle.x_evolve(x0, G, nH, a, g, ts)
+    np.testing.assert_allclose(got, sol.y[0], rtol=1e-8, atol=1e-14)
+
+
+def test_x_evolve_limits():
+    a, g = oracle.alpha_A(1e4)[0], oracle.gamma_coll(1e4)[0]
+    for G, nH, x0 in [(1e-12, 1e-3, 1e-5), (1e-15, 1.0, 0.2)]:
+        assert oracle.x_evolve(x0, G, nH, a, g, 0.0) == pytest.approx(x0, rel=1e-15)
+        assert oracle.x_evolve(x0, G, nH, a, g, 1e30) == pytest.approx(
+            oracle.xeq(G, nH, a, g), rel=1e-12)
+
+
+# ---------------------------------------------------------------------------
 # near/far scheme (Sec. 4.1.2) and the slab solution of Appendix C.4
 # ---------------------------------------------------------------------------
 _A, _G = oracle.alpha_A(1e4)[0], oracle.gamma_coll(1e4)[0]
