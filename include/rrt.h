@@ -180,6 +180,15 @@ int rrt_set_scheme(rrt_ctx* ctx, int32_t near_far);
  * device double out[n][n_ray], input order, cm^-2.  Synchronises. */
 int rrt_get_near_columns(rrt_ctx* ctx, double* out);
 
+/* Non-equilibrium evolution (Appendix C.3, time-dependent solution of eq.
+ * dxdt with y = 0): n_steps steps of length dt seconds; each step takes the
+ * columns and Gamma of the current state and advances every particle by dt
+ * with the closed-form solution at that constant Gamma (case A rates, the
+ * current scheme).  dt = 0 leaves x unchanged; a very long dt gives the
+ * equilibrium update.  x_out: device double[n] (nullable, syncs).  Needs the
+ * default update rule (RRT_E_STATE otherwise). */
+int rrt_evolve(rrt_ctx* ctx, double dt, int32_t n_steps, double* x_out);
+
 /* The update rule of rrt_iterate_equilibrium, after the paper's own scheme
  * (Sec. 4, implementation details).  Defaults (0, +inf, 0, 1) give the
  * order-independent case A update that every other entry point assumes.

@@ -273,6 +273,7 @@ hipError_t launch_path_columns(Ctx& c, int group);
 void drop_graph(Ctx& c);
 hipError_t build_tiles(Ctx& c);
 hipError_t launch_want(Ctx& c, int block, bool use_skip);
+hipError_t launch_evolve(Ctx& c, double dt);
 hipError_t launch_block_ids(Ctx& c, const int32_t* block_in);
 void free_tiles(Ctx& c);
 hipError_t launch_tile_columns(Ctx& c, int group);

@@ -42,6 +42,22 @@ __device__ __forceinline__ double x_minus(double G, double nH, double al, double
     return 2.0 * P / (negQ + sqrt(eq_discriminant(G, nH, al, gc)));
 }
 
+// x after time t at constant Gamma, nH and coefficients, from x0 (Appendix
+// C.3, y = 0): dx/dt = R (x - x_-)(x - x_+) with R = (alpha + gcoll) nH gives
+// x(t) = x_- + (x0 - x_-) (x_+ - x_-) F / ((x_+ - x0) + (x0 - x_-) F) with
+// F = exp(-R (x_+ - x_-) t); x_+ - x_- = sqrt(D) / R.
+__device__ __forceinline__ double x_after(double x0, double G, double nH, double al, double gc,
+                                          double t)
+{
+    const double R = (gc + al) * nH;
+    const double sD = sqrt(eq_discriminant(G, nH, al, gc));
+    const double xm = x_minus(G, nH, al, gc);
+    const double gap = sD / R;                       // x_+ - x_-
+    const double F = exp(-sD * t);
+    const double d0 = x0 - xm;
+    return xm + d0 * gap * F / ((xm + gap - x0) + d0 * F);
+}
+
 // ln of the photoionisation rate at total hydrogen column N into a uniform
 // slab of density nH (coefficients alpha, gcoll at its temperature) lit by
 // monochromatic radiation of cross-section sigma that gives the rate

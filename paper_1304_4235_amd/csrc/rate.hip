@@ -311,6 +311,30 @@ __global__ void k_block_ids(const int32_t* __restrict__ perm, const int32_t* __r
 
 }  // namespace
 
+namespace {
+
+// every particle advances by dt at its current rate (case A)
+__global__ void k_evolve(const double* __restrict__ G, int64_t n, const float* __restrict__ nH_s,
+                         const double* __restrict__ mu_s, const double* __restrict__ alpha,
+                         const double* __restrict__ gcoll, double dt, double* __restrict__ x_s,
+                         float* __restrict__ mux)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double x = x_after(x_s[i], G[i], (double)nH_s[i], alpha[i], gcoll[i], dt);
+    x_s[i] = x;
+    mux[i] = (float)(mu_s[i] * x);
+}
+
+}  // namespace
+
+hipError_t launch_evolve(Ctx& c, double dt)
+{
+    hipLaunchKernelGGL(k_evolve, dim3(nblk(c.n)), dim3(kBlock), 0, c.stream, c.G_s, c.n, c.nH_s,
+                       c.mu_s, c.alpha_s, c.gcoll_s, dt, c.x_s, c.mux_s);
+    return hipGetLastError();
+}
+
 hipError_t launch_want(Ctx& c, int block, bool use_skip)
 {
     hipLaunchKernelGGL(k_want, dim3(nblk(c.n)), dim3(kBlock), 0, c.stream,

@@ -881,6 +881,33 @@ int rrt_iterate_equilibrium(rrt_ctx* x, int32_t max_iter, double tol, double* x_
     return (max_iter > 0 && !(mdx < tol)) ? RRT_NOT_CONVERGED : RRT_OK;
 }
 
+int rrt_evolve(rrt_ctx* x, double dt, int32_t n_steps, double* x_out)
+{
+    if (!x) return RRT_E_ARG;
+    Ctx& c = x->c;
+    if (int r = need_tree(c)) return r;
+    if (!(dt >= 0.0) || std::isinf(dt) || n_steps < 0)
+        return fail(c, RRT_E_ARG, "dt must be finite and >= 0, n_steps >= 0");
+    if (!default_rule(c))
+        return fail(c, RRT_E_STATE, "the evolution uses case A rates: reset the update rule");
+    if (c.near_far && c.n_bins != 1)
+        return fail(c, RRT_E_STATE, "the near/far slab solution needs one frequency bin");
+    for (int s = 0; s < n_steps && dt > 0.0; ++s) {     // no time, no change
+        int64_t hits = -1;
+        if (int r = columns_impl(c, &hits)) return r;
+        ev_begin(c);
+        HIP_OK(launch_gamma(c, false));
+        HIP_OK(launch_evolve(c, dt));
+        if (c.timing) c.t_rate += ev_end(c);
+    }
+    c.have_columns = c.have_gamma = false;
+    if (x_out) {
+        HIP_OK(launch_to_input_order_d(c, c.x_s, x_out, 1));
+        HIP_OK(hipStreamSynchronize(c.stream));
+    }
+    return RRT_OK;
+}
+
 int rrt_set_density(rrt_ctx* x, const float* n_H)
 {
     if (!x) return RRT_E_ARG;

@@ -65,6 +65,7 @@ SIGNATURES = {
     "rrt_set_tuning": ([_vp, _i32, _i32], C.c_int),
     "rrt_set_update_rule": ([_vp, _d, _d, _i32, _i32], C.c_int),
     "rrt_set_scheme": ([_vp, _i32], C.c_int),
+    "rrt_evolve": ([_vp, _d, _i32, _vp], C.c_int),
     "rrt_get_near_columns": ([_vp, _vp], C.c_int),
     "rrt_iterate_halos": ([_vp, _i32, _d, _i32, _vp, _vp], C.c_int),
     "rrt_forward": ([_vp, _i32, _vp, _vp], C.c_int),
@@ -187,6 +188,13 @@ class Solver:
         self._check(_lib.rrt_set_update_rule(self._h, float(tau_skip), float(tau_case_b),
                                              int(bool(relative)), int(n_blocks)),
                     "rrt_set_update_rule")
+
+    def evolve(self, dt: float, n_steps: int):
+        """Non-equilibrium evolution: n_steps of dt seconds at the rate of each
+        step's current state.  Returns x (input order)."""
+        x = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        self._check(_lib.rrt_evolve(self._h, float(dt), int(n_steps), _ptr(x)), "rrt_evolve")
+        return x
 
     def set_scheme(self, near_far: bool):
         """The paper's near/far scheme (True) or the plain scheme (False)."""
