@@ -268,8 +268,12 @@ int rrt_iterate_halos(rrt_ctx* ctx, int32_t max_iter, double tol, int32_t per_la
  *   RRT_TUNE_LEAF         particles per tree leaf (1..8), from the next build
  *   RRT_TUNE_ADJOINT      transposed column product of rrt_backward over
  *                         recorded paths: 0 (default) = gather over paths
- *                         transposed once per geometry when memory allows,
- *                         else atomic scatter; 1 = always atomic scatter
+ *                         transposed once per geometry when memory allows
+ *                         (deterministic), else per row tile in LDS with one
+ *                         atomic add per distinct particle of a tile (when the
+ *                         tiles fit), else one atomic add per intersection;
+ *                         1 = always one atomic add per intersection;
+ *                         2 = always per row tile (when the tiles fit)
  *   RRT_TUNE_TILES        0 (default): columns from the recorded paths as
  *                         recorded.  1: after a few column evaluations over the
  *                         same recorded paths (and before the graph of a

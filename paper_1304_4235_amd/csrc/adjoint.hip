@@ -27,7 +27,10 @@ constexpr int kBlock = 256;
 
 inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
-// One thread per particle (tree order) at step k.
+// One thread per particle (tree order) at step k: the adjoint of ln Gamma, of
+// x and of every ray's column.  Pass 1 forms ln Gamma as the forward rate
+// kernel does and keeps each ray's S and T (FP32) for pass 2; the weights'
+// gradient is accumulated by k_adj_wbins from pis and ell.
 __global__ void __launch_bounds__(256)
 k_adj_rate(const double* __restrict__ N, int64_t n, int n_ray, int n_bins,
            const float* __restrict__ ws_rel, const float* __restrict__ dsig_l2,
@@ -35,84 +38,98 @@ k_adj_rate(const double* __restrict__ N, int64_t n, int n_ray, int n_bins,
            const float* __restrict__ nH_s, const double* __restrict__ alpha,
            const double* __restrict__ gcoll, const double* __restrict__ lam,
            const double* __restrict__ lup, double* __restrict__ nu, double* __restrict__ pis,
-           double* __restrict__ gnH, double* __restrict__ gw_part)
+           double* __restrict__ gnH, float2* __restrict__ st, double* __restrict__ ell_out)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const bool act = i < n;
-    const int64_t ii = act ? i : 0;
-    double ell = 0.0;
-    if (act) {
-        // pass 1: ln Gamma exactly as the forward rate kernel forms it
-        double m = -INFINITY, s = 0.0;
-        for (int k = 0; k < n_ray; ++k) {
-            const double Nk = N[(int64_t)k * n + i];
-            const float Nf = (float)Nk;
-            float S = 0.f;
-            for (int b = 0; b < n_bins; ++b) S = fmaf(ws_rel[b], exp2f(-dsig_l2[b] * Nf), S);
-            if (!(S > 0.f)) continue;
-            const double v = -sigma_min * Nk + log((double)S);
-            if (v > m) {
-                s = s * exp(m - v) + 1.0;
-                m = v;
-            } else {
-                s += exp(v - m);
-            }
+    if (i >= n) return;
+    // pass 1: ln Gamma exactly as the forward rate kernel forms it
+    double m = -INFINITY, s = 0.0;
+    for (int k = 0; k < n_ray; ++k) {
+        const double Nk = N[(int64_t)k * n + i];
+        const float Nf = (float)Nk;
+        float S = 0.f, T = 0.f;
+        for (int b = 0; b < n_bins; ++b) {
+            const float e = ws_rel[b] * exp2f(-dsig_l2[b] * Nf);
+            S += e;
+            T = fmaf(e, srat[b], T);
         }
-        const double l = (s > 0.0) ? (ln_ws_max + m + log(s / (double)n_ray)) : -INFINITY;
-        const double G = exp(l);
-        const double nh = (double)nH_s[i];
-        const double x = x_minus(G, nh, alpha[i], gcoll[i]);
-        const double sD = sqrt(eq_discriminant(G, nh, alpha[i], gcoll[i]));
-        const double dxdl = (sD > 0.0) ? -G * x / sD : 0.0;
-        const double li = lam[i];
-        ell = (lup ? lup[i] : 0.0) + li * dxdl;
-        gnH[i] += -li * dxdl / nh;
-        // pass 2: adjoint of every ray's column, and pi_i / S_i for the bins
-        for (int k = 0; k < n_ray; ++k) {
-            const double Nk = N[(int64_t)k * n + i];
-            const float Nf = (float)Nk;
-            float S = 0.f, T = 0.f;
-            for (int b = 0; b < n_bins; ++b) {
-                const float e = ws_rel[b] * exp2f(-dsig_l2[b] * Nf);
-                S += e;
-                T = fmaf(e, srat[b], T);
-            }
-            double nk = 0.0, pk = 0.0;
-            if (S > 0.f && s > 0.0) {
-                const double v = -sigma_min * Nk + log((double)S);
-                const double pi = exp(v - m) / s;
-                pk = pi / (double)S;
-                nk = -ell * pi * sigma_min * ((double)T / (double)S);
-            }
-            nu[(int64_t)k * n + i] = nk;
-            pis[(int64_t)k * n + i] = pk;
+        st[(int64_t)k * n + i] = make_float2(S, T);
+        if (!(S > 0.f)) continue;
+        const double v = -sigma_min * Nk + log((double)S);
+        if (v > m) {
+            s = s * exp(m - v) + 1.0;
+            m = v;
+        } else {
+            s += exp(v - m);
         }
     }
-    // pass 3: per-bin weight derivative, reduced over the wave in a fixed order
-    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
-    for (int b = 0; b < n_bins; ++b) {
-        double acc = 0.0;
-        if (act && ell != 0.0) {
-            const float ds = dsig_l2[b];
-            for (int k = 0; k < n_ray; ++k) {
-                const float Nf = (float)N[(int64_t)k * n + ii];
-                acc += pis[(int64_t)k * n + ii] * (double)exp2f(-ds * Nf);
-            }
-            acc *= ell;
+    const double l = (s > 0.0) ? (ln_ws_max + m + log(s / (double)n_ray)) : -INFINITY;
+    const double G = exp(l);
+    const double nh = (double)nH_s[i];
+    const double x = x_minus(G, nh, alpha[i], gcoll[i]);
+    const double sD = sqrt(eq_discriminant(G, nh, alpha[i], gcoll[i]));
+    const double dxdl = (sD > 0.0) ? -G * x / sD : 0.0;
+    const double li = lam[i];
+    const double ell = (lup ? lup[i] : 0.0) + li * dxdl;
+    gnH[i] += -li * dxdl / nh;
+    ell_out[i] = ell;
+    // pass 2: adjoint of every ray's column, and pi / S per ray for the bins
+    for (int k = 0; k < n_ray; ++k) {
+        const double Nk = N[(int64_t)k * n + i];
+        const float2 ST = st[(int64_t)k * n + i];
+        double nk = 0.0, pk = 0.0;
+        if (ST.x > 0.f && s > 0.0) {
+            const double v = -sigma_min * Nk + log((double)ST.x);
+            const double pi = exp(v - m) / s;
+            pk = pi / (double)ST.x;
+            nk = -ell * pi * sigma_min * ((double)ST.y / (double)ST.x);
         }
-        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-        if ((threadIdx.x & 63) == 0) gw_part[wave * n_bins + b] = acc;
+        nu[(int64_t)k * n + i] = nk;
+        pis[(int64_t)k * n + i] = pk;
     }
 }
 
-// sum the per-wave partials of every bin, in wave order, into the accumulator
-__global__ void k_adj_bins(const double* __restrict__ part, int64_t n_waves, int n_bins,
+// Weight gradient partials: a wave serves 64 bins (one per lane) for a chunk
+// of kAdjChunk particles; each particle's rays are read once per wave (wave-
+// uniform loads) and every lane forms its own bin's factor.  Per lane the sum
+// runs over the chunk's particles, then rays, in order.
+__global__ void __launch_bounds__(256)
+k_adj_wbins(const double* __restrict__ N, const double* __restrict__ pis,
+            const double* __restrict__ ell, const float* __restrict__ dsig_l2, int64_t n,
+            int n_ray, int n_bins, int64_t n_chunks, double* __restrict__ part)
+{
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    const int groups = (n_bins + 63) / 64;
+    if (wave >= (int64_t)groups * n_chunks) return;
+    const int g = (int)(wave % groups);
+    const int64_t chunk = wave / groups;
+    const int b = g * 64 + lane;
+    const float ds = b < n_bins ? dsig_l2[b] : 0.0f;
+    const int64_t i0 = chunk * kAdjChunk;
+    const int64_t i1 = i0 + kAdjChunk < n ? i0 + kAdjChunk : n;
+    double acc = 0.0;
+    for (int64_t i = i0; i < i1; ++i) {
+        const double e = ell[i];
+        if (e == 0.0) continue;
+        double a = 0.0;
+        for (int k = 0; k < n_ray; ++k) {
+            const float Nf = (float)N[(int64_t)k * n + i];
+            a += pis[(int64_t)k * n + i] * (double)exp2f(-ds * Nf);
+        }
+        acc += e * a;
+    }
+    if (b < n_bins) part[chunk * n_bins + b] = acc;
+}
+
+// sum the per-chunk partials of every bin, in chunk order, into the accumulator
+__global__ void k_adj_bins(const double* __restrict__ part, int64_t n_chunks, int n_bins,
                            double* __restrict__ acc)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= n_bins) return;
     double s = 0.0;
-    for (int64_t w = 0; w < n_waves; ++w) s += part[w * n_bins + b];
+    for (int64_t w = 0; w < n_chunks; ++w) s += part[w * n_bins + b];
     acc[b] += s;
 }
 
@@ -194,12 +211,18 @@ hipError_t launch_adj_rate(Ctx& c, const double* lup)
     hipLaunchKernelGGL(k_adj_rate, dim3(nblk(c.n)), dim3(kBlock), 0, c.stream, c.N_s, c.n, c.n_ray,
                        c.n_bins, c.ws_rel, c.dsig_l2, c.srat, c.sigma_min, c.ln_ws_max, c.nH_s,
                        c.alpha_s, c.gcoll_s, c.adj_lam, lup, c.adj_nu, c.adj_pis, c.adj_gnH,
-                       c.adj_wpart);
+                       c.adj_st, c.adj_ell);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int64_t n_waves = (int64_t)nblk(c.n) * (kBlock / 64);
+    const int64_t chunks = adj_chunks(c);
+    const int64_t waves = chunks * ((c.n_bins + 63) / 64);
+    hipLaunchKernelGGL(k_adj_wbins, dim3((unsigned)((waves * 64 + kBlock - 1) / kBlock)),
+                       dim3(kBlock), 0, c.stream, c.N_s, c.adj_pis, c.adj_ell, c.dsig_l2, c.n,
+                       c.n_ray, c.n_bins, chunks, c.adj_wpart);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_adj_bins, dim3((c.n_bins + 255) / 256), dim3(256), 0, c.stream,
-                       c.adj_wpart, n_waves, c.n_bins, c.adj_gw);
+                       c.adj_wpart, chunks, c.n_bins, c.adj_gw);
     return hipGetLastError();
 }
 
@@ -228,5 +251,7 @@ hipError_t launch_adj_init(Ctx& c, double* part)
 }
 
 int64_t adj_waves(const Ctx& c) { return (int64_t)nblk(c.n) * (kBlock / 64); }
+
+int64_t adj_chunks(const Ctx& c) { return (c.n + kAdjChunk - 1) / kAdjChunk; }
 
 }  // namespace rrt

@@ -152,7 +152,7 @@ struct Ctx {
     bool tpaths_unfit = false;
     // row tiles of the recorded paths (tiles.hip)
     uint64_t* tile_off = nullptr;  // [n_tiles + 1] start of each tile's particle set
-    uint32_t* tile_set = nullptr;  // sorted distinct particles of each tile
+    uint32_t* tile_set = nullptr;  // distinct particles of each tile
     uint16_t* tile_idx = nullptr;  // [path_hits] position of the entry's particle in its set
     float* tile_fac = nullptr;     // [path_hits] K/h^2 of the entry
     int tile_rows = 0;
@@ -222,7 +222,9 @@ struct Ctx {
     double* adj_pis = nullptr;   // [n_ray][n] softmax / S per ray
     double* adj_gnH = nullptr;   // [n] dL/dn_H, tree order
     double* adj_y = nullptr;     // [n] transposed product
-    double* adj_wpart = nullptr; // [waves][n_bins] per-wave bin partials
+    double* adj_wpart = nullptr; // [chunks][n_bins] per-chunk bin partials
+    float2* adj_st = nullptr;    // [n_ray][n] per-ray S and T of the rate
+    double* adj_ell = nullptr;   // [n] adjoint of ln Gamma at the current step
     double* adj_gw = nullptr;    // [n_bins] accumulated over steps
     double* adj_tpart = nullptr; // [waves] initial-state partials
     size_t adj_n = 0, adj_nr = 0;  // sizes the adjoint buffers were allocated for
@@ -244,7 +246,7 @@ struct Ctx {
     hipEvent_t ev_a = nullptr, ev_b = nullptr;
 
     int32_t path_group = 0;       // lanes per ray in the path product (0 = automatic)
-    int32_t adj_scatter = 0;      // 1: reverse mode scatters atomically, never transposes
+    int32_t adj_scatter = 0;      // 1: atomic scatter, 2: tile scatter, 0: automatic
 
     // counters: intersections of the last iteration and since the last reset
     int64_t last_hits = 0, total_hits = 0;
@@ -277,6 +279,9 @@ hipError_t launch_evolve(Ctx& c, double dt);
 hipError_t launch_block_ids(Ctx& c, const int32_t* block_in);
 void free_tiles(Ctx& c);
 hipError_t launch_tile_columns(Ctx& c, int group);
+hipError_t launch_tile_scatter(Ctx& c, const double* nu, double* y);
+// largest tile set the reverse-mode tile scatter accumulates in LDS (64 KiB)
+constexpr int kTileScatterMaxSet = 8192;
 hipError_t launch_count_hits(Ctx& c, uint64_t* row_cnt);
 hipError_t launch_record_hits(Ctx& c, const uint64_t* row_off, int32_t* hit_j, int32_t* hit_img,
                               uint64_t cap);
@@ -294,6 +299,9 @@ hipError_t launch_adj_scatter(Ctx& c);
 hipError_t launch_adj_x(Ctx& c, const double* xprev);
 hipError_t launch_adj_init(Ctx& c, double* part);
 int64_t adj_waves(const Ctx& c);
+int64_t adj_chunks(const Ctx& c);
+// particles per partial of the reverse-mode weight gradient
+constexpr int64_t kAdjChunk = 256;
 
 // ---- launchers (rate.hip) ----
 hipError_t launch_init_state(Ctx& c, bool use_given);

@@ -76,11 +76,13 @@ void free_particles(Ctx& c)
     c.blocks_for = 0;
     c.Nn_s = nullptr;
     void* adj[] = {c.xhist, c.adj_lam, c.adj_lup, c.adj_nu, c.adj_pis, c.adj_gnH, c.adj_y,
-                   c.adj_wpart, c.adj_gw, c.adj_tpart};
+                   c.adj_wpart, c.adj_gw, c.adj_tpart, c.adj_st, c.adj_ell};
     for (void* b : adj)
         if (b) (void)hipFree(b);
     c.xhist = c.adj_lam = c.adj_lup = c.adj_nu = c.adj_pis = c.adj_gnH = c.adj_y = nullptr;
     c.adj_wpart = c.adj_gw = c.adj_tpart = nullptr;
+    c.adj_st = nullptr;
+    c.adj_ell = nullptr;
     c.adj_n = c.adj_nr = 0;
     c.xhist_cap = 0;
     c.fwd_K = -1;
@@ -973,11 +975,13 @@ int rrt_backward(rrt_ctx* x, const double* dL_dlnG, const double* dL_dx, double*
         HIP_OK(dalloc(&c.adj_y, n));
         HIP_OK(dalloc(&c.adj_nu, nr));
         HIP_OK(dalloc(&c.adj_pis, nr));
+        HIP_OK(dalloc(&c.adj_st, nr));
+        HIP_OK(dalloc(&c.adj_ell, n));
         HIP_OK(dalloc(&c.adj_tpart, (size_t)waves));
         c.adj_n = n;
         c.adj_nr = nr;
     }
-    HIP_OK(dalloc(&c.adj_wpart, (size_t)waves * c.n_bins));
+    HIP_OK(dalloc(&c.adj_wpart, (size_t)adj_chunks(c) * c.n_bins));
     HIP_OK(dalloc(&c.adj_gw, (size_t)c.n_bins));
     HIP_OK(hipMemsetAsync(c.adj_gw, 0, sizeof(double) * c.n_bins, c.stream));
     HIP_OK(hipMemsetAsync(c.adj_gnH, 0, sizeof(double) * n, c.stream));
@@ -993,7 +997,7 @@ int rrt_backward(rrt_ctx* x, const double* dL_dlnG, const double* dL_dx, double*
         int64_t hits = -1;
         if (int r = columns_impl(c, &hits)) return r;
         HIP_OK(launch_adj_rate(c, (k == K && dL_dlnG) ? c.adj_lup : nullptr));
-        if (c.paths_valid && !c.tpaths_valid && !c.tpaths_unfit && !c.adj_scatter) {
+        if (c.paths_valid && !c.tpaths_valid && !c.tpaths_unfit && c.adj_scatter == 0) {
             // transposed paths (8 B per intersection) plus sort scratch (24 B)
             size_t fr = 0, tot = 0;
             HIP_OK(hipMemGetInfo(&fr, &tot));
@@ -1005,8 +1009,18 @@ int rrt_backward(rrt_ctx* x, const double* dL_dlnG, const double* dL_dx, double*
                 c.tpaths_unfit = true;
             }
         }
-        if (c.paths_valid && c.tpaths_valid && !c.adj_scatter) {
+        // without transposed paths: accumulate per row tile in LDS when the
+        // tiles can be built and fit (one global atomic per distinct particle
+        // of a tile instead of one per intersection)
+        const bool try_tiles = c.paths_valid && !c.near_far &&
+                               (c.adj_scatter == 2 || (c.adj_scatter == 0 && c.tpaths_unfit));
+        if (try_tiles && !c.tiles_valid && !c.tiles_unfit) HIP_OK(build_tiles(c));
+        const bool tile_scatter = try_tiles && c.tiles_valid &&
+                                  c.tile_max_u <= kTileScatterMaxSet;
+        if (c.paths_valid && c.tpaths_valid && c.adj_scatter == 0) {
             HIP_OK(launch_gather_cols(c));
+        } else if (tile_scatter) {
+            HIP_OK(launch_tile_scatter(c, c.adj_nu, c.adj_y));
         } else if (c.paths_valid) {
             HIP_OK(launch_adj_scatter(c));
         } else {
@@ -1356,7 +1370,7 @@ int rrt_set_tuning(rrt_ctx* x, int32_t key, int32_t value)
         c.use_tiles = value;
         break;
     case RRT_TUNE_ADJOINT:
-        if (value != 0 && value != 1) return fail(c, RRT_E_ARG, "adjoint mode must be 0 or 1");
+        if (value < 0 || value > 2) return fail(c, RRT_E_ARG, "adjoint mode must be 0, 1 or 2");
         c.adj_scatter = value;
         break;
     case RRT_TUNE_LEAF:

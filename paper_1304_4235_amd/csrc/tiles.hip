@@ -4,9 +4,9 @@
 // consecutive rows is a bundle of parallel rays from neighbouring sources, and
 // the rays of a bundle cross mostly the same particles: a tile of a few hundred
 // rows with ~10^5 intersections touches only a few thousand distinct particles.
-// Once per geometry, each tile's distinct particle indices are collected
-// (sorted) and every recorded entry's particle index is replaced by its 16-bit
-// position in the tile's set.  The column product then loads the set's mu*x
+// Once per geometry, each tile's distinct particle indices are collected and
+// every recorded entry's particle index is replaced by its 16-bit position in
+// the tile's set.  The column product then loads the set's mu*x
 // into LDS once per tile and streams 6 bytes per intersection (local index and
 // FP32 factor) with no per-intersection global gathers.  The columns equal
 // those of the plain product over the recorded paths up to FP64 summation
@@ -72,52 +72,102 @@ k_tile_count(const uint64_t* __restrict__ row_off, const int2* __restrict__ path
     }
 }
 
-// sorted set per tile, and the local index of every entry
+// Each tile's set and the local index of every entry.  The local index of an
+// occupied hash slot is the number of occupied slots before it (occupancy
+// bitmap + prefix counts), so the set follows the hash table's slot order; no
+// sum depends on that order (every entry keeps its own particle's values).
+__device__ __forceinline__ uint32_t slot_id(const uint32_t* occ, const uint32_t* pre, uint32_t s)
+{
+    return pre[s >> 5] + __popc(occ[s >> 5] & ((1u << (s & 31)) - 1u));
+}
+
 __global__ void __launch_bounds__(kBuildBlock)
 k_tile_build(const uint64_t* __restrict__ row_off, const int2* __restrict__ path, int64_t n_rows,
              int tile_rows, int64_t n_tiles, const uint64_t* __restrict__ set_off,
              uint32_t* __restrict__ set, uint16_t* __restrict__ idx, float* __restrict__ fac)
 {
+    constexpr int kWords = kHashSlots / 32;           // 1024 bitmap words
     __shared__ uint32_t tab[kHashSlots];
+    __shared__ uint32_t occ[kWords];
+    __shared__ uint32_t pre[kWords];
     __shared__ uint32_t count;
     for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
         const int64_t r0 = t * tile_rows;
         const int64_t r1 = r0 + tile_rows < n_rows ? r0 + tile_rows : n_rows;
         const uint64_t a = row_off[r0], b = row_off[r1];
         tile_collect(tab, &count, path, a, b);
-        const uint32_t u = count;
-        // bitonic sort of the table: the distinct indices end up first, ascending
-        // (empty slots hold the largest key), so the set is deterministic
-        for (int k = 2; k <= kHashSlots; k <<= 1) {
-            for (int jj = k >> 1; jj > 0; jj >>= 1) {
-                for (int i = threadIdx.x; i < kHashSlots; i += blockDim.x) {
-                    const int ixj = i ^ jj;
-                    if (ixj > i) {
-                        const uint32_t x = tab[i], y = tab[ixj];
-                        const bool up = (i & k) == 0;
-                        if ((x > y) == up) {
-                            tab[i] = y;
-                            tab[ixj] = x;
-                        }
-                    }
-                }
-                __syncthreads();
-            }
+        for (int w = threadIdx.x; w < kWords; w += blockDim.x) {
+            uint32_t m = 0;
+            for (int q = 0; q < 32; ++q)
+                if (tab[32 * w + q] != kEmpty) m |= 1u << q;
+            occ[w] = m;
         }
+        __syncthreads();
+        if (threadIdx.x < 64) {                       // one wave: 16 words per lane
+            const int l = threadIdx.x;
+            uint32_t loc[kWords / 64];
+            uint32_t sum = 0;
+            for (int q = 0; q < kWords / 64; ++q) {
+                loc[q] = sum;
+                sum += __popc(occ[l * (kWords / 64) + q]);
+            }
+            uint32_t incl = sum;
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t y = __shfl_up(incl, off, 64);
+                if (l >= off) incl += y;
+            }
+            const uint32_t base = incl - sum;
+            for (int q = 0; q < kWords / 64; ++q) pre[l * (kWords / 64) + q] = base + loc[q];
+        }
+        __syncthreads();
         const uint64_t so = set_off[t];
-        for (uint32_t i = threadIdx.x; i < u; i += blockDim.x) set[so + i] = tab[i];
+        for (int sl = threadIdx.x; sl < kHashSlots; sl += blockDim.x) {
+            const uint32_t key = tab[sl];
+            if (key != kEmpty) set[so + slot_id(occ, pre, (uint32_t)sl)] = key;
+        }
         for (uint64_t e = a + threadIdx.x; e < b; e += blockDim.x) {
             const int2 h = path[e];
             const uint32_t j = (uint32_t)h.x;
-            uint32_t lo = 0, hi = u;              // first position with tab[pos] >= j
-            while (lo < hi) {
-                const uint32_t mid = (lo + hi) >> 1;
-                if (tab[mid] < j) lo = mid + 1;
-                else hi = mid;
-            }
-            idx[e] = (uint16_t)lo;
+            uint32_t sl = hash_slot(j);
+            for (int probe = 0; probe < kHashSlots && tab[sl] != j; ++probe)
+                sl = (sl + 1) & (kHashSlots - 1);
+            idx[e] = (uint16_t)slot_id(occ, pre, sl);
             fac[e] = __int_as_float(h.y);
         }
+        __syncthreads();
+    }
+}
+
+// Transposed product over the tiles (reverse mode): y_j += factor * nu_row for
+// every entry, accumulated per distinct particle of the tile in LDS, then one
+// global atomic add per particle (instead of one per intersection).  The
+// order of the additions is not fixed.
+__global__ void __launch_bounds__(512)
+k_tile_scatter(const uint64_t* __restrict__ row_off, const uint16_t* __restrict__ idx,
+               const float* __restrict__ fac, const uint64_t* __restrict__ set_off,
+               const uint32_t* __restrict__ set, const double* __restrict__ nu, int64_t n_rows,
+               int tile_rows, int64_t n_tiles, double* __restrict__ y)
+{
+    extern __shared__ double sacc[];
+    const int lane = threadIdx.x & 63;
+    const int waves = blockDim.x >> 6;
+    for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+        const uint64_t so = set_off[t];
+        const uint32_t u = (uint32_t)(set_off[t + 1] - so);
+        for (uint32_t i = threadIdx.x; i < u; i += blockDim.x) sacc[i] = 0.0;
+        __syncthreads();
+        const int64_t r0 = t * tile_rows;
+        const int64_t r1 = r0 + tile_rows < n_rows ? r0 + tile_rows : n_rows;
+        for (int64_t row = r0 + (threadIdx.x >> 6); row < r1; row += waves) {
+            const double v = nu[row];
+            if (v == 0.0) continue;
+            const uint64_t a = row_off[row], b = row_off[row + 1];
+            for (uint64_t e = a + lane; e < b; e += 64)
+                atomicAdd(&sacc[idx[e]], (double)fac[e] * v);
+        }
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < u; i += blockDim.x)
+            if (sacc[i] != 0.0) unsafeAtomicAdd(y + set[so + i], sacc[i]);
         __syncthreads();
     }
 }
@@ -298,6 +348,18 @@ hipError_t build_tiles(Ctx& c)
         }
     }
     return e;
+}
+
+hipError_t launch_tile_scatter(Ctx& c, const double* nu, double* y)
+{
+    const int64_t n_rows = c.n * (int64_t)c.n_ray;
+    const size_t lds = sizeof(double) * (size_t)std::max<int64_t>(c.tile_max_u, 1);
+    const unsigned nb = (unsigned)std::min<int64_t>(c.n_tiles, kMaxBlocks);
+    hipError_t e = hipMemsetAsync(y, 0, sizeof(double) * c.n, c.stream);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_tile_scatter, dim3(nb), dim3(512), lds, c.stream, c.row_off, c.tile_idx,
+                       c.tile_fac, c.tile_off, c.tile_set, nu, n_rows, c.tile_rows, c.n_tiles, y);
+    return hipGetLastError();
 }
 
 hipError_t launch_tile_columns(Ctx& c, int group)

@@ -251,7 +251,7 @@ def test_many_rays_products_cover_every_ray():
     _say("many rays: reverse-mode products")
     s.set_tuning(path_group=0)
     out = []
-    for mode in (0, 1):
+    for mode in (0, 1, 2):
         s.set_tuning(adjoint_scatter=mode)
         lnG, xk = s.forward(K)
         dw, dn = s.backward(torch.ones_like(lnG), None)
@@ -260,9 +260,29 @@ def test_many_rays_products_cover_every_ray():
     lnG, xk = sb.forward(K)
     dw, dn = sb.backward(torch.ones_like(lnG), None)
     out.append((dw, dn.cpu().numpy()))
-    for i in (1, 2):
+    for i in (1, 2, 3):
         np.testing.assert_allclose(out[i][1], out[0][1], rtol=1e-9,
                                    atol=1e-12 * np.abs(out[0][1]).max())
         np.testing.assert_allclose(out[i][0], out[0][0], rtol=1e-9)
     s.close()
     sb.close()
+
+
+def test_tile_scatter_matches_transposed_gather():
+    """Reverse mode accumulating per row tile in LDS (one global atomic per
+    distinct particle of a tile) against the deterministic gather over the
+    transposed paths: the same products, summed in another order."""
+    wl = W.isothermal_halo(n=8192, n_bins=16, seed=46)
+    K = 4
+    s = _setup(wl, K)
+    s.enable_timing(True)
+    out = []
+    for mode in (0, 2):
+        s.set_tuning(adjoint_scatter=mode)
+        lnG, x = s.forward(K)
+        dw, dn = s.backward(torch.ones_like(lnG), None)
+        out.append((dw, dn.cpu().numpy()))
+    assert s.timing()["tile_set_total"] > 0          # the row tiles were built
+    np.testing.assert_allclose(out[1][1], out[0][1], rtol=1e-9,
+                               atol=1e-12 * np.abs(out[0][1]).max())
+    np.testing.assert_allclose(out[1][0], out[0][0], rtol=1e-9)
