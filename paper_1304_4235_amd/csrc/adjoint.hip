@@ -90,18 +90,29 @@ k_adj_rate(const double* __restrict__ N, int64_t n, int n_ray, int n_bins,
 }
 
 // Weight gradient partials: a wave serves 64 bins (one per lane) for a chunk
-// of kAdjChunk particles; each particle's rays are read once per wave (wave-
-// uniform loads) and every lane forms its own bin's factor.  Per lane the sum
-// runs over the chunk's particles, then rays, in order.
+// of kAdjChunk particles.  For each ray, 64 particles' column and ell * pi / S
+// are staged in LDS with coalesced loads, and every lane forms its own bin's
+// factor from the LDS broadcasts.  Per lane the sum runs over rays, then the
+// chunk's particles, in order.
+__device__ __forceinline__ void adj_wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __global__ void __launch_bounds__(256)
 k_adj_wbins(const double* __restrict__ N, const double* __restrict__ pis,
             const double* __restrict__ ell, const float* __restrict__ dsig_l2, int64_t n,
             int n_ray, int n_bins, int64_t n_chunks, double* __restrict__ part)
 {
+    __shared__ float sN[4][64];
+    __shared__ double sW[4][64];
     const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
     const int groups = (n_bins + 63) / 64;
-    if (wave >= (int64_t)groups * n_chunks) return;
+    if (wave >= (int64_t)groups * n_chunks) return;           // whole wave
     const int g = (int)(wave % groups);
     const int64_t chunk = wave / groups;
     const int b = g * 64 + lane;
@@ -109,15 +120,20 @@ k_adj_wbins(const double* __restrict__ N, const double* __restrict__ pis,
     const int64_t i0 = chunk * kAdjChunk;
     const int64_t i1 = i0 + kAdjChunk < n ? i0 + kAdjChunk : n;
     double acc = 0.0;
-    for (int64_t i = i0; i < i1; ++i) {
-        const double e = ell[i];
-        if (e == 0.0) continue;
-        double a = 0.0;
-        for (int k = 0; k < n_ray; ++k) {
-            const float Nf = (float)N[(int64_t)k * n + i];
-            a += pis[(int64_t)k * n + i] * (double)exp2f(-ds * Nf);
+    for (int k = 0; k < n_ray; ++k) {
+        for (int64_t ib = i0; ib < i1; ib += 64) {
+            const int64_t i = ib + lane;
+            const bool in = i < i1;
+            sN[wv][lane] = in ? (float)N[(int64_t)k * n + i] : 0.0f;
+            sW[wv][lane] = in ? ell[i] * pis[(int64_t)k * n + i] : 0.0;
+            adj_wave_sync();
+            const int m = (int)(i1 - ib < 64 ? i1 - ib : 64);
+            for (int q = 0; q < m; ++q) {
+                const double w = sW[wv][q];
+                if (w != 0.0) acc += w * (double)exp2f(-ds * sN[wv][q]);
+            }
+            adj_wave_sync();
         }
-        acc += e * a;
     }
     if (b < n_bins) part[chunk * n_bins + b] = acc;
 }
