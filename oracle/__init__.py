@@ -50,7 +50,7 @@ def lib():
         L.orc_gk15_poly.argtypes = [d, d, d, vp, vp]
         L.orc_kernel_norm.argtypes = [d, i32]; L.orc_kernel_norm.restype = d
         L.orc_columns.argtypes = [i64, vp, vp, vp, vp, i32, vp, d, d, i64, vp, d, i32,
-                                  vp, vp, vp, vp, vp, i32]
+                                  vp, vp, vp, vp, vp, vp, i32]
         L.orc_columns.restype = C.c_int
         L.orc_gamma.argtypes = [i64, i32, vp, i32, vp, vp, vp, vp, vp]
         for f in ("orc_alpha_A", "orc_alpha_B", "orc_gamma_coll"):
@@ -129,12 +129,15 @@ def kernel_norm(h: float, which: str = "Gt") -> float:
 # columns, rates, equilibrium (Sec. 3.3, 4.1.1, Appendix C.3)
 # ----------------------------------------------------------------------------
 def columns(wl, x: np.ndarray, sources=None, hits: bool = False, rtol=DEFAULT_RTOL,
-            n_threads: int = None):
+            n_threads: int = None, factors: bool = False):
     """Columns N[src, k] in cm^-2 for the given source particles (all by default).
 
     With ``hits=True`` also returns (row_off, hit_j, hit_img): the hit list of
     ray (src_i, k) is hit_j[row_off[i*n_ray+k] : row_off[i*n_ray+k+1]] with the
-    periodic image code (sx+8) | (sy+8)<<4 | (sz+8)<<8 in hit_img.
+    periodic image code (sx+8) | (sy+8)<<4 | (sz+8)<<8 in hit_img.  With
+    ``factors=True`` as well, hit_fac: each hit's column per unit neutral
+    fraction (mu_j times its clipped chord integral, cm^-2), so that
+    N[i, k] = sum over the ray's hits of hit_fac * x[hit_j].
     """
     L = lib()
     n = wl.n
@@ -145,21 +148,25 @@ def columns(wl, x: np.ndarray, sources=None, hits: bool = False, rtol=DEFAULT_RT
     N = np.zeros((src.size, wl.n_ray), np.float64)
     if not hits:
         rc = L.orc_columns(n, _p(pos), _p(h), _p(mu), _p(xx), wl.n_ray, _p(dirs), wl.l_ray,
-                           wl.box, src.size, _p(src), rtol, 1, _p(N), None, None, None, None, nt)
+                           wl.box, src.size, _p(src), rtol, 1, _p(N), None, None, None, None, None,
+                           nt)
         assert rc == 0
         return N
     cnt = np.zeros(src.size * wl.n_ray, np.int64)
     rc = L.orc_columns(n, _p(pos), _p(h), _p(mu), _p(xx), wl.n_ray, _p(dirs), wl.l_ray, wl.box,
-                       src.size, _p(src), rtol, 0, None, _p(cnt), None, None, None, nt)
+                       src.size, _p(src), rtol, 0, None, _p(cnt), None, None, None, None, nt)
     assert rc == 0
     off = np.zeros(cnt.size + 1, np.int64)
     off[1:] = np.cumsum(cnt)
     hj = np.zeros(max(1, int(off[-1])), np.int32)
     hi = np.zeros(max(1, int(off[-1])), np.int32)
+    hf = np.zeros(max(1, int(off[-1])), np.float64) if factors else None
     rc = L.orc_columns(n, _p(pos), _p(h), _p(mu), _p(xx), wl.n_ray, _p(dirs), wl.l_ray, wl.box,
                        src.size, _p(src), rtol, 1, _p(N), None, _p(off[:-1].copy()), _p(hj),
-                       _p(hi), nt)
+                       _p(hi), _p(hf), nt)
     assert rc == 0
+    if factors:
+        return N, off, hj[: off[-1]], hi[: off[-1]], hf[: off[-1]]
     return N, off, hj[: off[-1]], hi[: off[-1]]
 
 
@@ -173,7 +180,7 @@ def columns_and_counts(wl, x: np.ndarray, sources, rtol=DEFAULT_RTOL, n_threads:
     rc = L.orc_columns(wl.n, _p(_c(wl.pos, np.float32)), _p(_c(wl.h, np.float32)),
                        _p(_c(wl.mu, np.float32)), _p(_c(x, np.float64)), wl.n_ray,
                        _p(_c(wl.dirs, np.float64)), wl.l_ray, wl.box, src.size, _p(src), rtol, 1,
-                       _p(N), _p(cnt), None, None, None, nt)
+                       _p(N), _p(cnt), None, None, None, None, nt)
     assert rc == 0
     return N, cnt.reshape(src.size, wl.n_ray)
 
@@ -251,6 +258,80 @@ def solve(wl, max_iter: int = None, tol: float = None, x_init=None, rtol=DEFAULT
     assert rc == 0
     k = int(it[0])
     return dict(x_hist=xh[: k + 1], lnG_hist=lh[:k], N_last=Nl, iters=k, maxdx=md[:k])
+
+
+def xeq_partials(x, Gamma, nH, alpha, gcoll):
+    """Partial derivatives of the physical root x_- of R x^2 + Q x + P = 0
+    (Appendix C.3, eq. xroots, y = 0; R = (gamma + alpha) n_H,
+    Q = -(Gamma + alpha n_H + R), P = alpha n_H) with respect to Gamma and n_H,
+    by implicit differentiation of the quadratic:
+        (2 R x + Q) dx = -(x dQ + x^2 dR + dP),   2 R x_- + Q = -sqrt(Q^2 - 4 P R).
+    Returns (dx/dGamma, dx/dn_H) at the given root x."""
+    x, G, n, a, g = (np.asarray(v, np.float64) for v in (x, Gamma, nH, alpha, gcoll))
+    R = (g + a) * n
+    Q = -(G + a * n + R)
+    P = a * n
+    sq = np.sqrt(np.maximum(Q * Q - 4.0 * P * R, 0.0))
+    dx_dG = -x / sq                                       # dQ/dGamma = -1
+    dx_dn = (-(2.0 * a + g) * x + (g + a) * x * x + a) / sq
+    return dx_dG, dx_dn
+
+
+def adjoint(wl, K: int, dL_dlnG=None, dL_dx=None, rtol=DEFAULT_RTOL, n_threads: int = None):
+    """Reverse mode of K order-independent iterations from the optically thin
+    state (Sec. 3.3, Sec. 4): x^0 = x_-(Gamma_thin), then K times columns
+    (eq. colden) -> Gamma (eq. gamma_shld) -> x^k = x_-(Gamma^k).  Parameters:
+    the bin weights w and the densities n_H, a particle's hydrogen content
+    scaling with its density (mu_j proportional to n_H,j at fixed h).
+
+    Given dL/d ln Gamma^K and dL/dx^K (None = zero), returns dict(dw, dnH,
+    lnG, x) with the forward outputs ln Gamma^K and x^K of the oracle's solve.
+    The chain rule is written out step by step, last iteration first:
+      x^k = x_-(Gamma^k):   lbar = xbar dx/dGamma Gamma,  nbar += xbar dx/dn_H
+      ln Gamma^k = ln (1/N_ray) sum_k' sum_b w_b sigma_b exp(-sigma_b N_k'):
+          with pi_{k'b} each term's share of the sum,
+          wbar_b += lbar sum_k' pi_{k'b} / w_b,  Nbar_k' = -lbar sum_b sigma_b pi_{k'b}
+      N_{pk'} = sum over hits of f_h x^{k-1}_j (f_h proportional to mu_j):
+          xbar^{k-1}_j = sum over j's hits of Nbar f_h,
+          nbar_j += sum over j's hits of Nbar f_h x^{k-1}_j / n_H,j
+    and finally x^0's own dependence on Gamma_thin = sum_b w_b sigma_b and n_H.
+    """
+    n, nr = wl.n, wl.n_ray
+    sig = np.asarray(wl.sigma, np.float64)
+    w = np.asarray(wl.w, np.float64)
+    nH = np.asarray(wl.n_H, np.float32).astype(np.float64)
+    T = np.asarray(wl.T, np.float32).astype(np.float64)
+    al, ga = alpha_A(T), gamma_coll(T)
+    fw = solve(wl, max_iter=K, tol=0.0, rtol=rtol, n_threads=n_threads)
+    assert fw["iters"] == K
+    xh, lh = fw["x_hist"], fw["lnG_hist"]
+    _, off, hj, _, hf = columns(wl, xh[0], hits=True, factors=True, rtol=rtol,
+                                n_threads=n_threads)
+    ray = np.repeat(np.arange(n * nr), np.diff(off))      # ray row p * n_ray + k' of each hit
+    xbar = np.zeros(n) if dL_dx is None else np.asarray(dL_dx, np.float64).copy()
+    dw = np.zeros(sig.size)
+    dn = np.zeros(n)
+    lnws = np.log(w * sig)
+    for k in range(K, 0, -1):
+        lnG = lh[k - 1]
+        G = np.exp(lnG)
+        dxdG, dxdn = xeq_partials(xh[k], G, nH, al, ga)
+        lbar = xbar * dxdG * G
+        if k == K and dL_dlnG is not None:
+            lbar = lbar + np.asarray(dL_dlnG, np.float64)
+        dn += xbar * dxdn
+        N = columns(wl, xh[k - 1], rtol=rtol, n_threads=n_threads)
+        pi = np.exp(lnws[None, None, :] - sig[None, None, :] * N[:, :, None]
+                    - lnG[:, None, None] - np.log(nr))
+        dw += np.einsum("p,pkb->b", lbar, pi) / w
+        Nbar = -lbar[:, None] * np.einsum("pkb,b->pk", pi, sig)
+        c = Nbar.ravel()[ray] * hf
+        xbar = np.bincount(hj, weights=c, minlength=n)
+        dn += np.bincount(hj, weights=c * xh[k - 1][hj], minlength=n) / nH
+    dxdG0, dxdn0 = xeq_partials(xh[0], np.sum(w * sig), nH, al, ga)
+    dn += xbar * dxdn0
+    dw += sig * np.sum(xbar * dxdG0)
+    return dict(dw=dw, dnH=dn, lnG=lh[K - 1], x=xh[K])
 
 
 def solve_rule(wl, tau_skip: float = 0.0, tau_case_b: float = float("inf"),

@@ -221,12 +221,14 @@ static double hit_column(const double d[3], const double u[3], double sp, double
 /* Columns N[src][k] for selected source particles.  mu*x gives atoms/kpc_cm^2 and
  * the kernel integral is in kpc^-2, so N is in cm^-2.
  *   mode 0: count hits only (row_hits), no integrals
- *   mode 1: columns (N_out), optional hit lists written at row offsets row_off */
+ *   mode 1: columns (N_out), optional hit lists written at row offsets row_off;
+ *           with hit_fac, each hit's column per unit neutral fraction, mu_j
+ *           times the clipped chord integral (dN/dx_j of that hit) */
 int orc_columns(int64_t n, const float* pos, const float* h, const float* mu, const double* x,
                 int32_t n_ray, const double* dirs, double L, double box,
                 int64_t n_src, const int64_t* src, double rtol, int32_t mode,
                 double* N_out, int64_t* row_hits, const int64_t* row_off,
-                int32_t* hit_j, int32_t* hit_img, int32_t n_threads)
+                int32_t* hit_j, int32_t* hit_img, double* hit_fac, int32_t n_threads)
 {
     if (n <= 0 || n_ray <= 0 || n_src < 0) return -1;
     double plo[3] = {INFINITY, INFINITY, INFINITY}, phi[3] = {-INFINITY, -INFINITY, -INFINITY};
@@ -280,6 +282,8 @@ int orc_columns(int64_t n, const float* pos, const float* h, const float* mu, co
                             hit_j[w] = (int32_t)j;
                             if (hit_img)
                                 hit_img[w] = (sx + 8) | ((sy + 8) << 4) | ((sz + 8) << 8);
+                            if (hit_fac)
+                                hit_fac[w] = hit_column(d, u, sp, L, hj, (double)mu[j], rtol);
                             ++w;
                         }
                     }
@@ -559,7 +563,7 @@ int orc_solve(int64_t n, const float* pos, const float* h, const float* mu, cons
     int it = 0;
     for (it = 0; it < max_iter; ++it) {
         orc_columns(n, pos, h, mu, x, n_ray, dirs, L, box, n, src, rtol, 1, Nc, NULL, NULL,
-                    NULL, NULL, n_threads);
+                    NULL, NULL, NULL, n_threads);
         orc_gamma(n, n_ray, Nc, n_bins, sigma, w, lnG, G, NULL);
         double mdx = 0.0;
         for (int64_t p = 0; p < n; ++p) {
@@ -652,7 +656,7 @@ int orc_solve_rule(int64_t n, const float* pos, const float* h, const float* mu,
                 if (!skip[order[q]]) src[m++] = order[q];
             if (m == 0) continue;
             orc_columns(n, pos, h, mu, x, n_ray, dirs, L, box, m, src, rtol, 1, Nc, NULL, NULL,
-                        NULL, NULL, n_threads);
+                        NULL, NULL, NULL, n_threads);
             orc_gamma(m, n_ray, Nc, n_bins, sigma, w, lnG, G, tau);
             for (int64_t i = 0; i < m; ++i) {
                 const int64_t p = src[i];

@@ -18,7 +18,7 @@ int orc_columns(int64_t n, const float* pos, const float* h, const float* mu, co
                 int32_t n_ray, const double* dirs, double L, double box,
                 int64_t n_src, const int64_t* src, double rtol, int32_t mode,
                 double* N_out, int64_t* row_hits, const int64_t* row_off,
-                int32_t* hit_j, int32_t* hit_img, int32_t n_threads);
+                int32_t* hit_j, int32_t* hit_img, double* hit_fac, int32_t n_threads);
 int orc_columns_near_far(int64_t n, const float* pos, const float* h, const float* mu,
                          const double* x, int32_t n_ray, const double* dirs, double L, double box,
                          int64_t n_src, const int64_t* src, double rtol, double* N_far,

@@ -576,6 +576,95 @@ def test_near_far_columns_split_the_plain_column():
 
 
 # ---------------------------------------------------------------------------
+# reverse mode
+# ---------------------------------------------------------------------------
+def test_hit_factors_rebuild_the_columns():
+    """Per-hit factors (column per unit neutral fraction) summed with any x give
+    the columns at that x: the column is linear in x (eq. colden)."""
+    wl = W.make_config(0, n_side_lattice=6, box=37.5)
+    rng = np.random.default_rng(3)
+    x = rng.uniform(0.01, 1.0, wl.n)
+    src = np.array([0, 5, 77, 215])
+    N, off, hj, _, hf = oracle.columns(wl, np.ones(wl.n), src, hits=True, factors=True)
+    assert np.all(hf > 0)
+    np.testing.assert_allclose(np.add.reduceat(hf, off[:-1]).reshape(N.shape), N, rtol=1e-12)
+    Nx = oracle.columns(wl, x, src)
+    rebuilt = np.add.reduceat(hf * x[hj], off[:-1]).reshape(N.shape)
+    np.testing.assert_allclose(rebuilt, Nx, rtol=1e-12)
+
+
+@pytest.mark.parametrize("G,nH,T", [(1e-12, 1e-3, 1e4), (3e-14, 0.3, 1e4), (1e-12, 2.0, 3e4),
+                                    (1e-15, 1e-5, 8e3)])
+def test_xeq_partials_against_central_differences(G, nH, T):
+    a, g = oracle.alpha_A(T)[0], oracle.gamma_coll(T)[0]
+    x = oracle.xeq(G, nH, a, g)[()]
+    dG, dn = oracle.xeq_partials(x, G, nH, a, g)
+    eG, en = 1e-5 * G, 1e-5 * nH
+    fG = (oracle.xeq(G + eG, nH, a, g) - oracle.xeq(G - eG, nH, a, g))[()] / (2 * eG)
+    fn = (oracle.xeq(G, nH + en, a, g) - oracle.xeq(G, nH - en, a, g))[()] / (2 * en)
+    assert abs(dG / fG - 1) < 1e-7 and abs(dn / fn - 1) < 1e-7
+
+
+def _adjoint_case():
+    wl = W.make_config(0, n_side_lattice=6, box=37.5, max_iter=3)
+    wl.sigma, wl.w = W.power_law_spectrum(6, 1.5, 1e-12)
+    rng = np.random.default_rng(1)
+    wl.n_H = (np.full(wl.n, 5e-3) * rng.uniform(0.5, 2.0, wl.n)).astype(np.float32)
+    return wl
+
+
+def test_adjoint_against_central_differences_of_the_solve():
+    """The oracle's reverse mode against central differences of its own K-step
+    solve (an independent computation): every bin weight, and densities with
+    mu scaled alongside n_H in FP32 (the rounding of mu limits those to ~2e-5).
+    A dropped term (x^0's dependence, mu's scaling, the x_- partials, the chain
+    through the columns) moves some gradient by more than 5 percent here."""
+    wl = _adjoint_case()
+    K = 3
+    rng = np.random.default_rng(5)
+    gl, gx = rng.uniform(-1, 1, wl.n), rng.uniform(-1, 1, wl.n)
+    r = oracle.adjoint(wl, K, gl, gx)
+    ref = oracle.solve(wl, max_iter=K, tol=0.0)
+    np.testing.assert_array_equal(r["x"], ref["x_hist"][-1])
+
+    def loss(w, nH, mu):
+        wl2 = W.Workload(**{**wl.__dict__, "w": w, "n_H": nH, "mu": mu})
+        f = oracle.solve(wl2, max_iter=K, tol=0.0)
+        return np.sum(gl * f["lnG_hist"][-1]) + np.sum(gx * f["x_hist"][-1])
+
+    w0, n0, m0 = wl.w.copy(), wl.n_H.copy(), wl.mu.copy()
+    for b in range(wl.n_bins):
+        e = 1e-4 * w0[b]
+        wp, wm = w0.copy(), w0.copy()
+        wp[b] += e
+        wm[b] -= e
+        fd = (loss(wp, n0, m0) - loss(wm, n0, m0)) / (2 * e)
+        assert abs(r["dw"][b] - fd) <= 1e-6 * abs(fd), (b, r["dw"][b], fd)
+    scale = np.abs(r["dnH"]).max()
+    for j in list(rng.choice(wl.n, 10, replace=False)) + [int(np.argmax(np.abs(r["dnH"])))]:
+        up, lo = np.float32(n0[j] * (1 + 1e-3)), np.float32(n0[j] * (1 - 1e-3))
+        npl, nmi, mpl, mmi = n0.copy(), n0.copy(), m0.copy(), m0.copy()
+        npl[j], nmi[j] = up, lo
+        mpl[j] = np.float32(np.float64(m0[j]) * np.float64(up) / np.float64(n0[j]))
+        mmi[j] = np.float32(np.float64(m0[j]) * np.float64(lo) / np.float64(n0[j]))
+        fd = (loss(w0, npl, mpl) - loss(w0, nmi, mmi)) / (float(up) - float(lo))
+        assert abs(r["dnH"][j] - fd) <= 2e-4 * abs(fd) + 1e-6 * scale, (j, r["dnH"][j], fd)
+
+
+def test_adjoint_is_linear_in_the_output_derivatives():
+    wl = _adjoint_case()
+    rng = np.random.default_rng(9)
+    a, b = rng.uniform(-1, 1, wl.n), rng.uniform(-1, 1, wl.n)
+    ra, rb = oracle.adjoint(wl, 2, a, None), oracle.adjoint(wl, 2, None, b)
+    rab = oracle.adjoint(wl, 2, a, b)
+    np.testing.assert_allclose(rab["dw"], ra["dw"] + rb["dw"], rtol=1e-12)
+    np.testing.assert_allclose(rab["dnH"], ra["dnH"] + rb["dnH"], rtol=1e-10,
+                               atol=1e-13 * np.abs(rab["dnH"]).max())
+    z = oracle.adjoint(wl, 2, None, None)
+    assert not np.any(z["dw"]) and not np.any(z["dnH"])
+
+
+# ---------------------------------------------------------------------------
 # reference tree
 # ---------------------------------------------------------------------------
 def _tree_case(n, seed=0, dup=False):
