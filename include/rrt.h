@@ -283,9 +283,14 @@ int rrt_iterate_halos(rrt_ctx* ctx, int32_t max_iter, double tol, int32_t per_la
  *                         needs no global gather; the columns agree to FP64
  *                         summation order.  The one-time build costs about as
  *                         much as a hundred evaluations save on long rays, so
- *                         it pays for long solves with short rays only. */
+ *                         it pays for long solves with short rays only.
+ *   RRT_TUNE_KEEP_COLUMNS 1 (default): rrt_forward keeps every iteration's
+ *                         columns for rrt_backward when they take at most an
+ *                         eighth of the free device memory (8 n n_ray K
+ *                         bytes); 0: rrt_backward recomputes them from the
+ *                         kept states.  The same columns either way. */
 enum { RRT_TUNE_TRACE_BLOCK = 1, RRT_TUNE_PACKET = 2, RRT_TUNE_PATH_GROUP = 3, RRT_TUNE_LEAF = 4,
-       RRT_TUNE_ADJOINT = 5, RRT_TUNE_TILES = 6 };
+       RRT_TUNE_ADJOINT = 5, RRT_TUNE_TILES = 6, RRT_TUNE_KEEP_COLUMNS = 7 };
 int rrt_set_tuning(rrt_ctx* ctx, int32_t key, int32_t value);
 
 /* Replace the state: x device double[n] in input order (checkpoint / resume,

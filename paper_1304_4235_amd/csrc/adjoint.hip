@@ -222,9 +222,9 @@ hipError_t launch_set_density(Ctx& c, const float* nH)
     return hipGetLastError();
 }
 
-hipError_t launch_adj_rate(Ctx& c, const double* lup)
+hipError_t launch_adj_rate(Ctx& c, const double* N, const double* lup)
 {
-    hipLaunchKernelGGL(k_adj_rate, dim3(nblk(c.n)), dim3(kBlock), 0, c.stream, c.N_s, c.n, c.n_ray,
+    hipLaunchKernelGGL(k_adj_rate, dim3(nblk(c.n)), dim3(kBlock), 0, c.stream, N, c.n, c.n_ray,
                        c.n_bins, c.ws_rel, c.dsig_l2, c.srat, c.sigma_min, c.ln_ws_max, c.nH_s,
                        c.alpha_s, c.gcoll_s, c.adj_lam, lup, c.adj_nu, c.adj_pis, c.adj_gnH,
                        c.adj_st, c.adj_ell);
@@ -233,7 +233,7 @@ hipError_t launch_adj_rate(Ctx& c, const double* lup)
     const int64_t chunks = adj_chunks(c);
     const int64_t waves = chunks * ((c.n_bins + 63) / 64);
     hipLaunchKernelGGL(k_adj_wbins, dim3((unsigned)((waves * 64 + kBlock - 1) / kBlock)),
-                       dim3(kBlock), 0, c.stream, c.N_s, c.adj_pis, c.adj_ell, c.dsig_l2, c.n,
+                       dim3(kBlock), 0, c.stream, N, c.adj_pis, c.adj_ell, c.dsig_l2, c.n,
                        c.n_ray, c.n_bins, chunks, c.adj_wpart);
     e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -215,6 +215,10 @@ struct Ctx {
     // reverse mode: iterates of the last rrt_forward and adjoint work buffers
     double* xhist = nullptr;     // [(K + 1)][n] tree order
     int32_t xhist_cap = 0;       // K + 1 slots allocated
+    double* Nhist = nullptr;     // [K][n_ray * n] columns of each forward iteration
+    int32_t Nhist_cap = 0;       // K slots allocated
+    bool Nhist_on = false;       // the last rrt_forward kept its columns
+    int32_t keep_columns = 1;    // 0: rrt_backward always recomputes the columns
     int32_t fwd_K = -1;          // steps of the last rrt_forward (-1: none)
     double* adj_lam = nullptr;   // [n] adjoint of x^k
     double* adj_lup = nullptr;   // [n] upstream adjoint of lnG^K
@@ -294,7 +298,7 @@ hipError_t launch_gather_cols(Ctx& c);
 
 // ---- launchers (adjoint.hip) ----
 hipError_t launch_set_density(Ctx& c, const float* nH);
-hipError_t launch_adj_rate(Ctx& c, const double* lup);
+hipError_t launch_adj_rate(Ctx& c, const double* N, const double* lup);
 hipError_t launch_adj_scatter(Ctx& c);
 hipError_t launch_adj_x(Ctx& c, const double* xprev);
 hipError_t launch_adj_init(Ctx& c, double* part);

@@ -76,10 +76,13 @@ void free_particles(Ctx& c)
     c.blocks_for = 0;
     c.Nn_s = nullptr;
     void* adj[] = {c.xhist, c.adj_lam, c.adj_lup, c.adj_nu, c.adj_pis, c.adj_gnH, c.adj_y,
-                   c.adj_wpart, c.adj_gw, c.adj_tpart, c.adj_st, c.adj_ell};
+                   c.adj_wpart, c.adj_gw, c.adj_tpart, c.adj_st, c.adj_ell, c.Nhist};
     for (void* b : adj)
         if (b) (void)hipFree(b);
     c.xhist = c.adj_lam = c.adj_lup = c.adj_nu = c.adj_pis = c.adj_gnH = c.adj_y = nullptr;
+    c.Nhist = nullptr;
+    c.Nhist_cap = 0;
+    c.Nhist_on = false;
     c.adj_wpart = c.adj_gw = c.adj_tpart = nullptr;
     c.adj_st = nullptr;
     c.adj_ell = nullptr;
@@ -938,6 +941,28 @@ int rrt_forward(rrt_ctx* x, int32_t K, double* lnG_out, double* x_out)
         HIP_OK(dalloc(&c.xhist, (size_t)(K + 1) * n));
         c.xhist_cap = K + 1;
     }
+    // Every iteration's columns are kept for rrt_backward when they take at
+    // most an eighth of the free memory; otherwise it recomputes them from the
+    // kept states.
+    const size_t nr = n * (size_t)c.n_ray;
+    c.Nhist_on = c.keep_columns && c.Nhist && c.Nhist_cap >= K;
+    if (!c.Nhist_on) {
+        if (c.Nhist) (void)hipFree(c.Nhist);
+        c.Nhist = nullptr;
+        c.Nhist_cap = 0;
+        size_t fr = 0, tot = 0;
+        HIP_OK(hipMemGetInfo(&fr, &tot));
+        const size_t need = (size_t)K * nr * sizeof(double);
+        if (c.keep_columns && need <= fr / 8) {
+            if (hipMalloc((void**)&c.Nhist, need) == hipSuccess) {
+                c.Nhist_cap = K;
+                c.Nhist_on = true;
+            } else {
+                (void)hipGetLastError();
+                c.Nhist = nullptr;
+            }
+        }
+    }
     c.fwd_K = -1;
     HIP_OK(launch_init_state(c, false));
     HIP_OK(hipMemcpyAsync(c.xhist, c.x_s, sizeof(double) * n, hipMemcpyDeviceToDevice,
@@ -946,6 +971,9 @@ int rrt_forward(rrt_ctx* x, int32_t K, double* lnG_out, double* x_out)
         HIP_OK(hipMemsetAsync(c.red, 0, 2 * sizeof(unsigned long long), c.stream));
         int64_t hits = -1;
         if (int r = columns_impl(c, &hits)) return r;
+        if (c.Nhist_on)
+            HIP_OK(hipMemcpyAsync(c.Nhist + (size_t)(k - 1) * nr, c.N_s, sizeof(double) * nr,
+                                  hipMemcpyDeviceToDevice, c.stream));
         HIP_OK(launch_gamma(c, true));
         HIP_OK(hipMemcpyAsync(c.xhist + (size_t)k * n, c.x_s, sizeof(double) * n,
                               hipMemcpyDeviceToDevice, c.stream));
@@ -991,12 +1019,18 @@ int rrt_backward(rrt_ctx* x, const double* dL_dlnG, const double* dL_dx, double*
     const int K = c.fwd_K;
     for (int k = K; k >= 1; --k) {
         double* xprev = c.xhist + (size_t)(k - 1) * n;
-        HIP_OK(hipMemcpyAsync(c.x_s, xprev, sizeof(double) * n, hipMemcpyDeviceToDevice,
-                              c.stream));
-        HIP_OK(launch_mux(c));
-        int64_t hits = -1;
-        if (int r = columns_impl(c, &hits)) return r;
-        HIP_OK(launch_adj_rate(c, (k == K && dL_dlnG) ? c.adj_lup : nullptr));
+        // the columns of iteration k, kept by the forward or recomputed from x^(k-1)
+        const double* Nk = c.N_s;
+        if (c.Nhist_on) {
+            Nk = c.Nhist + (size_t)(k - 1) * nr;
+        } else {
+            HIP_OK(hipMemcpyAsync(c.x_s, xprev, sizeof(double) * n, hipMemcpyDeviceToDevice,
+                                  c.stream));
+            HIP_OK(launch_mux(c));
+            int64_t hits = -1;
+            if (int r = columns_impl(c, &hits)) return r;
+        }
+        HIP_OK(launch_adj_rate(c, Nk, (k == K && dL_dlnG) ? c.adj_lup : nullptr));
         if (c.paths_valid && !c.tpaths_valid && !c.tpaths_unfit && c.adj_scatter == 0) {
             // transposed paths (8 B per intersection) plus sort scratch (24 B)
             size_t fr = 0, tot = 0;
@@ -1364,6 +1398,10 @@ int rrt_set_tuning(rrt_ctx* x, int32_t key, int32_t value)
         if (value != 0 && value != 8 && value != 16 && value != 32 && value != 64)
             return fail(c, RRT_E_ARG, "path group must be 0, 8, 16, 32 or 64");
         c.path_group = value;
+        break;
+    case RRT_TUNE_KEEP_COLUMNS:
+        if (value != 0 && value != 1) return fail(c, RRT_E_ARG, "keep_columns must be 0 or 1");
+        c.keep_columns = value;
         break;
     case RRT_TUNE_TILES:
         if (value != 0 && value != 1) return fail(c, RRT_E_ARG, "tiles must be 0 or 1");

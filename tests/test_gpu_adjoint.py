@@ -331,3 +331,25 @@ def test_adjoint_matches_oracle_adjoint_everywhere(case):
         assert np.all(ew <= GRAD_RTOL * np.abs(ref["dw"]) + GRAD_ATOL * np.abs(ref["dw"]).max())
         assert np.all(en <= GRAD_RTOL * np.abs(ref["dnH"]) + GRAD_ATOL * np.abs(ref["dnH"]).max())
         s.close()
+
+
+def test_kept_and_recomputed_columns_give_the_same_gradients():
+    """The reverse mode reads each iteration's columns as kept by the forward,
+    or recomputes them from the kept states: the same columns, so the same
+    gradients (bit for bit with the deterministic gather)."""
+    wl = W.isothermal_halo(n=4096, n_bins=16, seed=48, n_peak=3.0)
+    K = 5
+    s = _setup(wl, K)
+    rng = np.random.default_rng(12)
+    gl = torch.tensor(rng.uniform(-1, 1, wl.n), device="cuda")
+    gx = torch.tensor(rng.uniform(-1, 1, wl.n), device="cuda")
+    out = []
+    for keep in (1, 0, 1):
+        s.set_tuning(keep_columns=keep)
+        lnG, x = s.forward(K)
+        dw, dn = s.backward(gl, gx)
+        out.append((dw, dn.cpu().numpy()))
+    for dw, dn in out[1:]:
+        np.testing.assert_array_equal(dw, out[0][0])
+        np.testing.assert_array_equal(dn, out[0][1])
+    s.close()
