@@ -284,6 +284,9 @@ hipError_t launch_block_ids(Ctx& c, const int32_t* block_in);
 void free_tiles(Ctx& c);
 hipError_t launch_tile_columns(Ctx& c, int group);
 hipError_t launch_tile_scatter(Ctx& c, const double* nu, double* y);
+// lanes per row of the tile products: the tuned path group, else from the
+// mean intersections per row
+int tile_group(const Ctx& c);
 // largest tile set the reverse-mode tile scatter accumulates in LDS (64 KiB)
 constexpr int kTileScatterMaxSet = 8192;
 hipError_t launch_count_hits(Ctx& c, uint64_t* row_cnt);

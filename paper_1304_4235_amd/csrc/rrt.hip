@@ -274,9 +274,11 @@ int columns_impl(Ctx& c, int64_t* hits)
             HIP_OK(build_tiles(c));
             if (c.timing) c.t_tile_build += ev_end(c);
         }
-        const bool tiles = c.tiles_valid && c.use_tiles && !c.near_far;
+        // a source list (one block of the density order) walks only its own
+        // rows in the plain product; the tiles serve full sweeps
+        const bool tiles = c.tiles_valid && c.use_tiles && !c.near_far && !c.row_list;
         ev_begin(c);
-        if (tiles) HIP_OK(launch_tile_columns(c, group));
+        if (tiles) HIP_OK(launch_tile_columns(c, tile_group(c)));
         else HIP_OK(launch_path_columns(c, group));
         if (c.timing) {
             if (tiles) {

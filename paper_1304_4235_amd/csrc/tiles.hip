@@ -138,10 +138,16 @@ k_tile_build(const uint64_t* __restrict__ row_off, const int2* __restrict__ path
     }
 }
 
+typedef unsigned short v4u16 __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
 // Transposed product over the tiles (reverse mode): y_j += factor * nu_row for
 // every entry, accumulated per distinct particle of the tile in LDS, then one
-// global atomic add per particle (instead of one per intersection).  The
-// order of the additions is not fixed.
+// global atomic add per particle (instead of one per intersection).  G lanes
+// per row take aligned groups of four consecutive entries, and each group
+// loads its next row's offsets and adjoint value before it works on the
+// current row.  The order of the additions is not fixed.
+template <int G>
 __global__ void __launch_bounds__(512)
 k_tile_scatter(const uint64_t* __restrict__ row_off, const uint16_t* __restrict__ idx,
                const float* __restrict__ fac, const uint64_t* __restrict__ set_off,
@@ -149,8 +155,10 @@ k_tile_scatter(const uint64_t* __restrict__ row_off, const uint16_t* __restrict_
                int tile_rows, int64_t n_tiles, double* __restrict__ y)
 {
     extern __shared__ double sacc[];
-    const int lane = threadIdx.x & 63;
-    const int waves = blockDim.x >> 6;
+    const int lane = threadIdx.x & (G - 1);
+    const int groups = blockDim.x / G;
+    const v4u16* iq = reinterpret_cast<const v4u16*>(idx);
+    const v4f* fq = reinterpret_cast<const v4f*>(fac);
     for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
         const uint64_t so = set_off[t];
         const uint32_t u = (uint32_t)(set_off[t + 1] - so);
@@ -158,12 +166,37 @@ k_tile_scatter(const uint64_t* __restrict__ row_off, const uint16_t* __restrict_
         __syncthreads();
         const int64_t r0 = t * tile_rows;
         const int64_t r1 = r0 + tile_rows < n_rows ? r0 + tile_rows : n_rows;
-        for (int64_t row = r0 + (threadIdx.x >> 6); row < r1; row += waves) {
-            const double v = nu[row];
-            if (v == 0.0) continue;
-            const uint64_t a = row_off[row], b = row_off[row + 1];
-            for (uint64_t e = a + lane; e < b; e += 64)
-                atomicAdd(&sacc[idx[e]], (double)fac[e] * v);
+        int64_t row = r0 + threadIdx.x / G;
+        uint64_t a = 0, b = 0;
+        double v = 0.0;
+        if (row < r1) {
+            a = row_off[row];
+            b = row_off[row + 1];
+            v = nu[row];
+        }
+        for (; row < r1; row += groups) {
+            const int64_t next = row + groups;
+            uint64_t an = 0, bn = 0;
+            double vn = 0.0;
+            if (next < r1) {
+                an = row_off[next];
+                bn = row_off[next + 1];
+                vn = nu[next];
+            }
+            if (v != 0.0) {
+                for (uint64_t q = (a >> 2) + lane; 4 * q < b; q += G) {
+                    const v4u16 i4 = __builtin_nontemporal_load(iq + q);
+                    const v4f f4 = __builtin_nontemporal_load(fq + q);
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const uint64_t e = 4 * q + k;
+                        if (e >= a && e < b) atomicAdd(&sacc[i4[k]], (double)f4[k] * v);
+                    }
+                }
+            }
+            a = an;
+            b = bn;
+            v = vn;
         }
         __syncthreads();
         for (uint32_t i = threadIdx.x; i < u; i += blockDim.x)
@@ -171,9 +204,6 @@ k_tile_scatter(const uint64_t* __restrict__ row_off, const uint16_t* __restrict_
         __syncthreads();
     }
 }
-
-typedef unsigned short v4u16 __attribute__((ext_vector_type(4)));
-typedef float v4f __attribute__((ext_vector_type(4)));
 
 // N_row = sum over the row's entries of mux[set[idx]] * factor, with the
 // tile's mux staged in LDS.  G lanes per row; each lane takes aligned groups of
@@ -350,6 +380,27 @@ hipError_t build_tiles(Ctx& c)
     return e;
 }
 
+namespace {
+
+template <int G>
+void launch_scatter_g(Ctx& c, const double* nu, double* y, int64_t n_rows, unsigned nb,
+                      size_t lds)
+{
+    hipLaunchKernelGGL(k_tile_scatter<G>, dim3(nb), dim3(512), lds, c.stream, c.row_off,
+                       c.tile_idx, c.tile_fac, c.tile_off, c.tile_set, nu, n_rows, c.tile_rows,
+                       c.n_tiles, y);
+}
+
+}  // namespace
+
+int tile_group(const Ctx& c)
+{
+    if (c.path_group) return c.path_group;
+    const double mean = (double)c.path_hits / (double)std::max<int64_t>(c.n * (int64_t)c.n_ray, 1);
+    // each lane takes four entries at a time: a quarter of the plain product's lanes
+    return mean >= 160 ? 32 : mean >= 40 ? 16 : 8;
+}
+
 hipError_t launch_tile_scatter(Ctx& c, const double* nu, double* y)
 {
     const int64_t n_rows = c.n * (int64_t)c.n_ray;
@@ -357,8 +408,11 @@ hipError_t launch_tile_scatter(Ctx& c, const double* nu, double* y)
     const unsigned nb = (unsigned)std::min<int64_t>(c.n_tiles, kMaxBlocks);
     hipError_t e = hipMemsetAsync(y, 0, sizeof(double) * c.n, c.stream);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_tile_scatter, dim3(nb), dim3(512), lds, c.stream, c.row_off, c.tile_idx,
-                       c.tile_fac, c.tile_off, c.tile_set, nu, n_rows, c.tile_rows, c.n_tiles, y);
+    const int g = tile_group(c);
+    if (g == 64) launch_scatter_g<64>(c, nu, y, n_rows, nb, lds);
+    else if (g == 32) launch_scatter_g<32>(c, nu, y, n_rows, nb, lds);
+    else if (g == 16) launch_scatter_g<16>(c, nu, y, n_rows, nb, lds);
+    else launch_scatter_g<8>(c, nu, y, n_rows, nb, lds);
     return hipGetLastError();
 }
 

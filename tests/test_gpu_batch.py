@@ -124,3 +124,22 @@ def test_grouped_recording_under_a_small_budget(frac):
     N1, h1 = sb.compute_columns()
     N2, h2 = _solver(wl, record_paths=0).compute_columns()
     assert h1 == h2
+
+
+def test_batched_solve_over_row_tiles_matches_plain():
+    """Row tiles in the batched solve: built before the graph is captured, and
+    the tile product skips the rows of halos that have stopped, as the plain
+    product does.  Same iteration counts, same states to summation order."""
+    wl, parts = _batch(SIZES, PEAKS)
+    out = []
+    for tiles in (0, 1):
+        sb = _solver(wl)
+        sb.set_tuning(tiles=tiles)
+        sb.enable_timing(True)
+        rb = sb.iterate_halos(200, 1e-3, per_launch=8)
+        assert rb["converged"]
+        if tiles:
+            assert sb.timing()["tile_set_total"] > 0, "row tiles were not built"
+        out.append(rb)
+    np.testing.assert_array_equal(out[0]["halo_iters"], out[1]["halo_iters"])
+    np.testing.assert_allclose(out[1]["x"].cpu().numpy(), out[0]["x"].cpu().numpy(), rtol=1e-9)

@@ -141,3 +141,26 @@ def test_rule_is_rejected_where_it_does_not_apply(halo):
     lnG, x = s.forward(2)
     assert torch.isfinite(lnG).all()
     s.close()
+
+
+@pytest.mark.parametrize("blocks", [1, 5])
+def test_rule_over_row_tiles(halo, blocks):
+    """The update rule with row tiles switched on: frozen particles' rows are
+    skipped by the tile product as by the plain one; one block of the density
+    order walks only its own rows (plain product over its source list)."""
+    wl, tau_skip, first_tau = halo
+    from paper_1304_4235_amd import Solver
+    res = []
+    for tiles in (0, 1):
+        s = Solver.from_workload(wl)
+        s.set_tuning(tiles=tiles)
+        s.enable_timing(True)
+        s.set_update_rule(n_blocks=blocks, tau_skip=tau_skip)
+        r = s.iterate(30, 0.0)
+        if tiles:
+            tm = s.timing()
+            assert tm["tile_set_total"] > 0, "row tiles were not built"
+            assert (tm["n_tile"] > 0) == (blocks == 1)
+        res.append(r["x"].cpu().numpy())
+        s.close()
+    np.testing.assert_allclose(res[1], res[0], rtol=1e-9)
