@@ -260,7 +260,15 @@ struct Ctx {
     double t_trace = 0, t_rate = 0, t_build = 0, n_trace = 0;
     double t_record = 0, t_spmv = 0, n_spmv = 0;
     double t_tile = 0, n_tile = 0, t_tile_build = 0;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // timing: event pairs recorded around launches on the context's stream and
+    // resolved later (no host wait per launch); acc receives the milliseconds
+    struct TimedSpan {
+        hipEvent_t a, b;
+        double* acc;
+    };
+    std::vector<TimedSpan> spans;
+    std::vector<hipEvent_t> ev_free;
+    hipEvent_t ev_open = nullptr;
 };
 
 // ---- launchers (tree.hip) ----

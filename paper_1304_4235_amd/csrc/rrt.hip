@@ -155,19 +155,55 @@ int alloc_columns(Ctx& c)
     return RRT_OK;
 }
 
-void ev_begin(Ctx& c)
+hipEvent_t ev_take(Ctx& c)
 {
-    if (c.timing) (void)hipEventRecord(c.ev0, c.stream);
+    if (!c.ev_free.empty()) {
+        hipEvent_t e = c.ev_free.back();
+        c.ev_free.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return e;
 }
 
-double ev_end(Ctx& c)
+// Wait for the recorded spans and add their durations to their accumulators.
+void ev_flush(Ctx& c)
 {
-    if (!c.timing) return 0.0;
-    (void)hipEventRecord(c.ev1, c.stream);
-    (void)hipEventSynchronize(c.ev1);
-    float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, c.ev0, c.ev1);
-    return ms;
+    if (c.spans.empty()) return;
+    (void)hipEventSynchronize(c.spans.back().b);       // every span is on c.stream
+    for (const Ctx::TimedSpan& sp : c.spans) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, sp.a, sp.b) == hipSuccess) *sp.acc += ms;
+        else (void)hipGetLastError();
+        c.ev_free.push_back(sp.a);
+        c.ev_free.push_back(sp.b);
+    }
+    c.spans.clear();
+}
+
+void ev_begin(Ctx& c)
+{
+    if (c.ev_open) c.ev_free.push_back(c.ev_open);
+    c.ev_open = nullptr;
+    if (!c.timing) return;
+    c.ev_open = ev_take(c);
+    if (c.ev_open) (void)hipEventRecord(c.ev_open, c.stream);
+}
+
+// Close the span opened by ev_begin; its duration goes to *acc when resolved.
+void ev_end(Ctx& c, double* acc)
+{
+    if (!c.timing || !c.ev_open) return;
+    hipEvent_t b = ev_take(c);
+    if (!b) return;
+    (void)hipEventRecord(b, c.stream);
+    c.spans.push_back(Ctx::TimedSpan{c.ev_open, b, acc});
+    c.ev_open = nullptr;
+    if (c.spans.size() >= 4096) ev_flush(c);
 }
 
 int need_tree(Ctx& c)
@@ -234,7 +270,7 @@ int record_paths(Ctx& c)
         c.path = nullptr;
         c.path_cap = 0;
         c.paths_unfit = true;
-        if (c.timing) c.t_record += ev_end(c);
+        ev_end(c, &c.t_record);
         return RRT_OK;
     }
     if (total > c.path_cap || !c.path) {
@@ -248,7 +284,7 @@ int record_paths(Ctx& c)
     HIP_OK(launch_record_paths(c, c.row_off, c.path, total));
     c.path_hits = (int64_t)total;
     c.paths_valid = true;
-    if (c.timing) c.t_record += ev_end(c);
+    ev_end(c, &c.t_record);
     return RRT_OK;
 }
 
@@ -272,7 +308,7 @@ int columns_impl(Ctx& c, int64_t* hits)
             ++c.path_evals > kTileAfter) {
             ev_begin(c);
             HIP_OK(build_tiles(c));
-            if (c.timing) c.t_tile_build += ev_end(c);
+            ev_end(c, &c.t_tile_build);
         }
         // a source list (one block of the density order) walks only its own
         // rows in the plain product; the tiles serve full sweeps
@@ -282,10 +318,10 @@ int columns_impl(Ctx& c, int64_t* hits)
         else HIP_OK(launch_path_columns(c, group));
         if (c.timing) {
             if (tiles) {
-                c.t_tile += ev_end(c);
+                ev_end(c, &c.t_tile);
                 c.n_tile += 1;
             } else {
-                c.t_spmv += ev_end(c);
+                ev_end(c, &c.t_spmv);
                 c.n_spmv += 1;
             }
         }
@@ -294,7 +330,7 @@ int columns_impl(Ctx& c, int64_t* hits)
         ev_begin(c);
         HIP_OK(launch_columns(c));
         if (c.timing) {
-            c.t_trace += ev_end(c);
+            ev_end(c, &c.t_trace);
             c.n_trace += 1;
         }
     }
@@ -343,8 +379,6 @@ int rrt_create(rrt_ctx** out, const rrt_params* params, void* stream)
     if (e == hipSuccess) e = hipMalloc((void**)&c.tables, sizeof(KernelTables));
     if (e == hipSuccess) e = hipMalloc((void**)&c.red, 4 * sizeof(unsigned long long));
     if (e == hipSuccess) e = hipHostMalloc((void**)&c.red_host, 4 * sizeof(unsigned long long));
-    if (e == hipSuccess) e = hipEventCreate(&c.ev0);
-    if (e == hipSuccess) e = hipEventCreate(&c.ev1);
     if (e == hipSuccess) {
         KernelTables host;
         fill_kernel_tables(&host);
@@ -378,8 +412,11 @@ void rrt_destroy(rrt_ctx* x)
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (c.red_host) (void)hipHostFree(c.red_host);
-    if (c.ev0) (void)hipEventDestroy(c.ev0);
-    if (c.ev1) (void)hipEventDestroy(c.ev1);
+    ev_flush(c);
+    if (c.ev_open) c.ev_free.push_back(c.ev_open);
+    c.ev_open = nullptr;
+    for (hipEvent_t e : c.ev_free) (void)hipEventDestroy(e);
+    c.ev_free.clear();
     delete x;
 }
 
@@ -652,7 +689,7 @@ int rrt_build_tree(rrt_ctx* x)
     g.want = nullptr;
     c.blocks_for = 0;            // the density blocks are in tree order
     HIP_OK(launch_init_state(c, c.x_init_given));
-    if (c.timing) c.t_build += ev_end(c);
+    ev_end(c, &c.t_build);
     c.paths_valid = false;       // new geometry: the recorded paths no longer apply
     c.paths_unfit = false;
     free_tpaths(c);
@@ -863,7 +900,7 @@ int rrt_iterate_equilibrium(rrt_ctx* x, int32_t max_iter, double tol, double* x_
             if (int r = columns_impl(c, &hits)) return r;
             ev_begin(c);
             HIP_OK(launch_gamma(c, true, it == 0));
-            if (c.timing) c.t_rate += ev_end(c);
+            ev_end(c, &c.t_rate);
         }
         c.geom.want = nullptr;
         c.row_list = nullptr;
@@ -905,7 +942,7 @@ int rrt_evolve(rrt_ctx* x, double dt, int32_t n_steps, double* x_out)
         ev_begin(c);
         HIP_OK(launch_gamma(c, false));
         HIP_OK(launch_evolve(c, dt));
-        if (c.timing) c.t_rate += ev_end(c);
+        ev_end(c, &c.t_rate);
     }
     c.have_columns = c.have_gamma = false;
     if (x_out) {
@@ -1160,7 +1197,7 @@ int run_active_halos(Ctx& c, double tol, int32_t max_iter, int32_t per_launch)
             max_iter > kTileAfter) {
             ev_begin(c);
             HIP_OK(build_tiles(c));
-            if (timing) c.t_tile_build += ev_end(c);
+            ev_end(c, &c.t_tile_build);
         }
         hipStream_t user = c.stream;
         c.stream = c.gstream;
@@ -1560,6 +1597,7 @@ int rrt_get_timing(rrt_ctx* x, double* out12)
 {
     if (!x || !out12) return RRT_E_ARG;
     Ctx& c = x->c;
+    ev_flush(c);
     out12[0] = c.t_trace;
     out12[1] = c.t_rate;
     out12[2] = c.t_build;
@@ -1579,6 +1617,7 @@ int rrt_reset_timing(rrt_ctx* x)
 {
     if (!x) return RRT_E_ARG;
     Ctx& c = x->c;
+    ev_flush(c);                      // spans recorded before the reset are dropped
     c.t_trace = c.t_rate = c.t_build = c.n_trace = 0.0;
     c.t_record = c.t_spmv = c.n_spmv = 0.0;
     c.t_tile = c.n_tile = c.t_tile_build = 0.0;
