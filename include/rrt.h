@@ -238,7 +238,8 @@ int rrt_forward(rrt_ctx* ctx, int32_t K, double* lnG_out, double* x_out);
 
 /* Gradients of a scalar loss through the last rrt_forward, given its
  * derivatives with respect to the outputs (device, input order, nullable =
- * zero): dL_dlnG double[n], dL_dx double[n].  Writes dL_dw (host double
+ * zero): dL_dlnG double[n], dL_dx double[n].  RRT_E_STATE unless rrt_forward
+ * ran after the last change of spectrum, rays, tree or densities.  Writes dL_dw (host double
  * [n_bins], the spectrum as given; every w_b must be > 0) and dL_dnH (device
  * double[n], input order).  The transposed column product uses the recorded
  * paths, or re-traverses the tree when they are not recorded; it accumulates

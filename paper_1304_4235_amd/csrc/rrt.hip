@@ -501,6 +501,7 @@ int rrt_set_rays(rrt_ctx* x, int32_t n_ray, const double* dirs)
     c.geom.n_ray = n_ray;
     c.have_rays = true;
     c.have_columns = c.have_gamma = false;
+    c.fwd_K = -1;
     free_paths(c);
     if (c.have_particles && (changed || !c.N_s)) return alloc_columns(c);
     return RRT_OK;
@@ -596,6 +597,7 @@ int rrt_set_spectrum(rrt_ctx* x, int32_t n_bins, const double* sigma, const doub
     c.all_bins_weighted = (m == n_bins);
     c.have_spectrum = true;
     c.have_gamma = false;
+    c.fwd_K = -1;                      // rrt_backward needs a forward with this spectrum
     return RRT_OK;
 }
 
@@ -605,6 +607,7 @@ int rrt_build_tree(rrt_ctx* x)
     Ctx& c = x->c;
     if (!c.have_particles) return fail(c, RRT_E_STATE, "rrt_set_particles has not been called");
     if (!c.have_spectrum) return fail(c, RRT_E_STATE, "rrt_set_spectrum must precede the build");
+    c.fwd_K = -1;
     ev_begin(c);
     // bounds and validation
     const int nb = (int)std::min<int64_t>(1024, (c.n + 255) / 256);

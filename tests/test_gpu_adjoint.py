@@ -353,3 +353,23 @@ def test_kept_and_recomputed_columns_give_the_same_gradients():
         np.testing.assert_array_equal(dw, out[0][0])
         np.testing.assert_array_equal(dn, out[0][1])
     s.close()
+
+
+def test_backward_needs_a_forward_with_the_current_parameters():
+    from paper_1304_4235_amd import RRTError
+    wl = W.isothermal_halo(n=1024, n_bins=4, seed=49)
+    s = _setup(wl, 2)
+    for change in ("spectrum", "density", "tree"):
+        lnG, x = s.forward(2)
+        if change == "spectrum":
+            s.set_spectrum(s.sigma, 1.1 * wl.w)
+        elif change == "density":
+            s.set_density(torch.tensor(wl.n_H * 1.1, dtype=torch.float32))
+        else:
+            s.build_tree()
+        with pytest.raises(RRTError):
+            s.backward(torch.ones_like(lnG), None)
+    lnG, x = s.forward(2)
+    dw, dn = s.backward(torch.ones_like(lnG), None)
+    assert np.all(np.isfinite(dw))
+    s.close()
