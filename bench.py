@@ -359,15 +359,18 @@ def main():
         s.set_state(None)
         out["update_rules"] = res
     if args.near_far and wl.tol > 0:
-        # the paper's near/far scheme (monochromatic slab solution) against the
-        # plain scheme, same geometry, one grey bin carrying the same thin rate
+        # the paper's near/far scheme against the plain scheme, same geometry:
+        # one grey bin carrying the same thin rate (monochromatic slab
+        # solution), then the workload's own spectrum (polychromatic slab)
         import workloads as W
         sg, wg = W.grey_spectrum(float(np.sum(wl.sigma * wl.w)))
-        res = {"spectrum": "one bin at 13.6 eV, same optically thin rate"}
+        res = {"spectrum": "one bin at 13.6 eV, same optically thin rate; "
+                           f"near_far_polychromatic: the workload's {wl.n_bins} bins"}
         s.enable_timing(True)
-        for name, nf in (("plain", False), ("near_far", True)):
-            print(f"scheme {name} (grey)", file=sys.stderr, flush=True)
-            s.set_spectrum(sg, wg)
+        for name, nf, spec in (("plain", False, (sg, wg)), ("near_far", True, (sg, wg)),
+                               ("near_far_polychromatic", True, (wl.sigma, wl.w))):
+            print(f"scheme {name}", file=sys.stderr, flush=True)
+            s.set_spectrum(*spec)
             s.set_scheme(nf)
             s.set_state(None)
             s.reset_timing()

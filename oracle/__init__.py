@@ -70,6 +70,9 @@ def lib():
         L.orc_slab_lnG.argtypes = [d, d, d, d, d, d]
         L.orc_slab_lnG.restype = d
         L.orc_gamma_near_far.argtypes = [i64, i32, vp, vp, d, d, vp, vp, vp, vp]
+        L.orc_slab_lnG_poly.argtypes = [i32, vp, vp, d, d, d, d, d]
+        L.orc_slab_lnG_poly.restype = d
+        L.orc_gamma_near_far_poly.argtypes = [i64, i32, vp, vp, i32, vp, vp, vp, vp, vp, vp, i32]
         L.orc_morton.argtypes = [i64, vp, vp]
         L.orc_lbvh.argtypes = [i64, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]
         L.orc_lbvh.restype = i64
@@ -419,18 +422,67 @@ def slab_lnG(lnG0, nH, alpha, gcoll, sigma, N):
     return out.reshape(b[0].shape)
 
 
-def step_near_far(wl, x: np.ndarray, sources=None, rtol=DEFAULT_RTOL):
-    """One order-independent update with the near/far rate (one frequency bin)."""
-    assert wl.n_bins == 1, "the slab solution is monochromatic"
+def slab_lnG_poly(sigma, w, N_far, nH, alpha, gcoll, N_near):
+    """ln of the rate at the bottom of a uniform slab of total hydrogen column
+    N_near lit by the binned spectrum (w, sigma) after a far column N_far
+    (Sec. 4.1.2, eq. gammashldk; the polychromatic form of App. C.4's slab)."""
+    sg, ww = _c(sigma, np.float64), _c(w, np.float64)
+    f = lib().orc_slab_lnG_poly
+    b = np.broadcast_arrays(*map(np.asarray, (N_far, nH, alpha, gcoll, N_near)))
+    out = np.array([f(sg.size, _p(sg), _p(ww), *map(float, v))
+                    for v in zip(*[a.ravel() for a in b])])
+    return out.reshape(b[0].shape)
+
+
+def slab_rk4_poly(sigma, w, N_far, nH, alpha, gcoll, N_near, n_steps=4000):
+    """The same slab as an ODE in the total hydrogen column t: the HI column y
+    below the surface grows as dy/dt = x_-(Gamma(N_far + y)), integrated by
+    classical RK4 from t = 0 to N_near.  An independent check of the
+    quadrature-and-bisection form.  Returns ln Gamma at the bottom."""
+    sg = np.asarray(sigma, np.float64)
+    lws = np.log(np.asarray(w, np.float64) * sg)
+    f = lib().orc_xeq
+
+    def lnG(N):
+        v = lws - sg * N
+        m = v.max()
+        return m + math.log(np.exp(v - m).sum())
+
+    def rhs(y):
+        return f(math.exp(lnG(N_far + y)), nH, alpha, gcoll, 0.0)
+
+    h = N_near / n_steps
+    y = 0.0
+    for _ in range(n_steps):
+        k1 = rhs(y)
+        k2 = rhs(y + 0.5 * h * k1)
+        k3 = rhs(y + 0.5 * h * k2)
+        k4 = rhs(y + h * k3)
+        y += h * (k1 + 2 * k2 + 2 * k3 + k4) / 6.0
+    return lnG(N_far + y)
+
+
+def step_near_far(wl, x: np.ndarray, sources=None, rtol=DEFAULT_RTOL, n_threads: int = None):
+    """One order-independent update with the near/far rate: the analytic slab
+    for one frequency bin, the polychromatic slab for several."""
     src = np.arange(wl.n) if sources is None else np.asarray(sources)
     Nf, Nn, cnt = columns_near_far(wl, x, src, rtol=rtol)
     T = wl.T[src].astype(np.float64)
     nH = wl.n_H[src].astype(np.float64)
     al, ga = alpha_A(T), gamma_coll(T)
     lnG = np.zeros(src.size)
-    lib().orc_gamma_near_far(src.size, wl.n_ray, _p(_c(Nf, np.float64)), _p(_c(Nn, np.float64)),
-                             float(wl.w[0]), float(wl.sigma[0]), _p(_c(nH, np.float64)),
-                             _p(_c(al, np.float64)), _p(_c(ga, np.float64)), _p(lnG))
+    if wl.n_bins == 1:
+        lib().orc_gamma_near_far(src.size, wl.n_ray, _p(_c(Nf, np.float64)),
+                                 _p(_c(Nn, np.float64)), float(wl.w[0]), float(wl.sigma[0]),
+                                 _p(_c(nH, np.float64)), _p(_c(al, np.float64)),
+                                 _p(_c(ga, np.float64)), _p(lnG))
+    else:
+        nt = N_THREADS if n_threads is None else n_threads
+        lib().orc_gamma_near_far_poly(src.size, wl.n_ray, _p(_c(Nf, np.float64)),
+                                      _p(_c(Nn, np.float64)), wl.n_bins,
+                                      _p(_c(wl.sigma, np.float64)), _p(_c(wl.w, np.float64)),
+                                      _p(_c(nH, np.float64)), _p(_c(al, np.float64)),
+                                      _p(_c(ga, np.float64)), _p(lnG), nt)
     G = np.exp(lnG)
     xn = xeq(G, nH, al, ga)
     return dict(N_far=Nf, N_near=Nn, near_hits=cnt, lnG=lnG, G=G, x_new=xn,

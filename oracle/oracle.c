@@ -466,6 +466,124 @@ void orc_gamma_near_far(int64_t n_src, int32_t n_ray, const double* N_far, const
 }
 
 /* ------------------------------------------------------------------------- */
+/* Polychromatic slab for the near/far scheme (Sec. 4.1.2, eq. gammashldk with  */
+/* the slab of App. C.4 lit by a binned spectrum).  The slab is uniform (n_H,  */
+/* alpha, gcoll of the source) and in equilibrium at every depth; the spectrum */
+/* reaching HI column u below its surface has been attenuated by N_far + u, so */
+/*   ln Gamma(u) = ln sum_b w_b sigma_b exp(-sigma_b (N_far + u)),             */
+/*   x(u) = x_-(Gamma(u)),  and the total hydrogen column down to u is         */
+/*   H(u) = int_0^u du' / x(u').                                               */
+/* The bottom of the slab is where H(U) = N_near; the ray's rate is Gamma(U).   */
+/* H by adaptive Gauss-Kronrod quadrature over geometric pieces, U by          */
+/* bisection (H(u) >= u, so U lies in [0, N_near]).  One bin reproduces the    */
+/* analytic slab above.                                                        */
+/* prm: [0] n_bins, [1] N_far, [2] nH, [3] alpha, [4] gcoll, then ln(w sigma)   */
+/* and sigma per bin.                                                          */
+/* ------------------------------------------------------------------------- */
+static double slab_poly_lnG_at(double N, const double* prm)
+{
+    const int nb = (int)prm[0];
+    const double* lws = prm + 5;
+    const double* sg = prm + 5 + nb;
+    double m = -INFINITY;
+    for (int b = 0; b < nb; ++b) {
+        const double v = lws[b] - sg[b] * N;
+        if (v > m) m = v;
+    }
+    if (m == -INFINITY) return m;
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += exp(lws[b] - sg[b] * N - m);
+    return m + log(s);
+}
+
+static double slab_poly_inv_x(double u, const double* prm)
+{
+    const double G = exp(slab_poly_lnG_at(prm[1] + u, prm));
+    return 1.0 / orc_xeq(G, prm[2], prm[3], prm[4], 0.0);
+}
+
+double orc_slab_lnG_poly(int32_t n_bins, const double* sigma, const double* w, double N_far,
+                         double nH, double alpha, double gcoll, double N_near)
+{
+    double* prm = (double*)malloc(sizeof(double) * (5 + 2 * (size_t)n_bins));
+    if (!prm) return NAN;
+    prm[0] = n_bins;
+    prm[1] = N_far;
+    prm[2] = nH;
+    prm[3] = alpha;
+    prm[4] = gcoll;
+    double smax = 0.0;
+    for (int b = 0; b < n_bins; ++b) {
+        prm[5 + b] = w[b] > 0.0 ? log(w[b] * sigma[b]) : -INFINITY;
+        prm[5 + n_bins + b] = sigma[b];
+        if (w[b] > 0.0 && sigma[b] > smax) smax = sigma[b];
+    }
+    /* H is summed over pieces [u_{j-1}, u_j] with u_j = expm1(j / 20) / sigma_max, so
+     * that Gamma, and with it 1/x, changes by a bounded factor within a piece;
+     * each piece by adaptive quadrature to 1e-13 of a lower bound of its value
+     * (1/x decreases with depth).  The piece where H reaches N_near is bisected. */
+    double U = 0.0;
+    if (N_near > 0.0) {
+        const double u0 = 1.0 / smax;
+        double lo = 0.0, H_lo = 0.0, hi = N_near;
+        for (int j = 1;; ++j) {
+            const double b = fmin(u0 * expm1(0.05 * j), N_near);
+            const double tol = 1e-13 * (b - lo) * slab_poly_inv_x(b, prm);
+            const double I = orc_integrate(slab_poly_inv_x, prm, lo, b, tol);
+            if (H_lo + I >= N_near || b >= N_near) {
+                hi = b;
+                break;
+            }
+            H_lo += I;
+            lo = b;
+        }
+        for (int it = 0; it < 400; ++it) {
+            const double mid = 0.5 * (lo + hi);
+            if (mid <= lo || mid >= hi) break;
+            const double tol = 1e-13 * (mid - lo) * slab_poly_inv_x(mid, prm);
+            const double Hm = H_lo + orc_integrate(slab_poly_inv_x, prm, lo, mid, tol);
+            if (Hm < N_near) {
+                lo = mid;
+                H_lo = Hm;
+            } else {
+                hi = mid;
+            }
+        }
+        U = 0.5 * (lo + hi);
+    }
+    const double out = slab_poly_lnG_at(N_far + U, prm);
+    free(prm);
+    return out;
+}
+
+/* Near/far shielded rate for a binned spectrum: per ray the polychromatic slab */
+/* above, Gamma = (1/N_ray) sum_k Gamma_k (eq. gammashld), ln by log-sum-exp.   */
+void orc_gamma_near_far_poly(int64_t n_src, int32_t n_ray, const double* N_far,
+                             const double* N_near, int32_t n_bins, const double* sigma,
+                             const double* w, const double* nH, const double* alpha,
+                             const double* gcoll, double* lnG, int32_t n_threads)
+{
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#else
+    (void)n_threads;
+#endif
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t i = 0; i < n_src; ++i) {
+        double m = -INFINITY, s = 0.0;
+        double* lk = (double*)malloc(sizeof(double) * n_ray);
+        for (int k = 0; k < n_ray; ++k) {
+            lk[k] = orc_slab_lnG_poly(n_bins, sigma, w, N_far[i * n_ray + k], nH[i], alpha[i],
+                                      gcoll[i], N_near[i * n_ray + k]);
+            if (lk[k] > m) m = lk[k];
+        }
+        for (int k = 0; k < n_ray; ++k) s += exp(lk[k] - m);
+        lnG[i] = (m == -INFINITY) ? -INFINITY : m + log(s / (double)n_ray);
+        free(lk);
+    }
+}
+
+/* ------------------------------------------------------------------------- */
 /* Shielded photoionisation rate, Sec. 3.3 eq. gamma_shld with the frequency  */
 /* integral done over bins: Gamma = (1/N_ray) sum_k sum_b w_b sigma_b         */
 /* exp(-sigma_b N_k).  ln Gamma by a log-sum-exp over all (k, b) terms.       */

@@ -25,6 +25,12 @@ int orc_columns_near_far(int64_t n, const float* pos, const float* h, const floa
                          double* N_near, int64_t* near_hits, int32_t n_threads);
 double orc_x_evolve(double x0, double Gamma, double nH, double alpha, double gcoll, double t);
 double orc_slab_lnG(double lnG0, double nH, double alpha, double gcoll, double sigma, double N);
+double orc_slab_lnG_poly(int32_t n_bins, const double* sigma, const double* w, double N_far,
+                         double nH, double alpha, double gcoll, double N_near);
+void orc_gamma_near_far_poly(int64_t n_src, int32_t n_ray, const double* N_far,
+                             const double* N_near, int32_t n_bins, const double* sigma,
+                             const double* w, const double* nH, const double* alpha,
+                             const double* gcoll, double* lnG, int32_t n_threads);
 void orc_gamma_near_far(int64_t n_src, int32_t n_ray, const double* N_far, const double* N_near,
                         double w, double sigma, const double* nH, const double* alpha,
                         const double* gcoll, double* lnG);

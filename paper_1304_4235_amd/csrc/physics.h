@@ -109,4 +109,91 @@ __device__ inline double slab_ln_rate(double lnG0, double nH, double alpha, doub
     return log(nH) + log(alpha + gcoll) + log1p(-xs) + v - log(xs);
 }
 
+// A binned spectrum as the rate kernel holds it: the bins with w_b > 0,
+// ws_rel = w_b sigma_b / max_b(w_b sigma_b), dsig_l2 = (sigma_b - sigma_min) log2(e).
+struct SpectrumView {
+    const float* ws_rel;
+    const float* dsig_l2;
+    int n_bins;
+    double sigma_min;
+    double ln_ws_max;
+};
+
+// ln of the rate of the spectrum after a hydrogen column N (cm^-2), from FP32
+// terms shifted by the least-absorbed bin; *sbar (nullable) receives the
+// rate-weighted mean cross-section -d ln Gamma / dN.
+__device__ inline double ln_rate_after(double N, const SpectrumView& sp, double* sbar)
+{
+    const float Nf = (float)N;
+    float S = 0.f, D = 0.f;
+    for (int b = 0; b < sp.n_bins; ++b) {
+        const float e = sp.ws_rel[b] * exp2f(-sp.dsig_l2[b] * Nf);
+        S += e;
+        D = fmaf(sp.dsig_l2[b], e, D);
+    }
+    if (!(S > 0.f)) {
+        if (sbar) *sbar = sp.sigma_min;
+        return -INFINITY;
+    }
+    if (sbar) *sbar = sp.sigma_min + 0.6931471805599453 * (double)(D / S);
+    return sp.ln_ws_max - sp.sigma_min * N + log((double)S);
+}
+
+constexpr int kSlabMaxSteps = 4096;
+
+// ln of the rate at the bottom of a uniform slab (density nH, coefficients
+// alpha, gcoll at its temperature) of total hydrogen column Nn, lit by the
+// binned spectrum after a far column Nf: the polychromatic near slab.  With
+// HI column u below the surface the rate is Gamma(Nf + u), the neutral
+// fraction x(u) = x_-(Gamma), and the hydrogen column down to u is
+// H(u) = int_0^u du' / x(u'); the bottom is where H = Nn.  The march takes
+// steps that lower ln Gamma by about 1/2 (6-point Gauss-Legendre on each,
+// nodes glx and weights glw on [-1, 1]); inside the step where H passes Nn,
+// Newton's method on the depth, kept to a bracket (dH/du = 1/x).  Once x is
+// within 1e-13 of x_ce, 1/x stays constant and the rest of the slab is linear.
+__device__ inline double slab_ln_rate_poly(double Nf, double Nn, double nH, double alpha,
+                                           double gcoll, const SpectrumView& sp,
+                                           const double* glx, const double* glw)
+{
+    double sb = 0.0;
+    double l = ln_rate_after(Nf, sp, &sb);
+    if (!(Nn > 0.0) || l == -INFINITY) return l;
+    const double xce = alpha / (alpha + gcoll);
+    auto x_at = [&](double u) {
+        return x_minus(exp(ln_rate_after(Nf + u, sp, nullptr)), nH, alpha, gcoll);
+    };
+    auto piece = [&](double u0, double u1) {          // int_{u0}^{u1} du / x
+        const double c = 0.5 * (u0 + u1), h = 0.5 * (u1 - u0);
+        double acc = 0.0;
+        for (int q = 0; q < 6; ++q) acc += glw[q] / x_at(c + h * glx[q]);
+        return acc * h;
+    };
+    double u = 0.0, H = 0.0;
+    for (int step = 0; step < kSlabMaxSteps; ++step) {
+        const double x = x_minus(exp(l), nH, alpha, gcoll);
+        if (xce / x - 1.0 < 1e-13) break;             // neutral from here on
+        const double du = 0.5 / sb;
+        const double I = piece(u, u + du);
+        if (H + I >= Nn) {
+            double lo = 0.0, hi = du, t = du * ((Nn - H) / I);
+            for (int it = 0; it < 60; ++it) {
+                const double F = H + piece(u, u + t) - Nn;
+                if (fabs(F) <= 1e-15 * Nn) break;     // t is the bottom
+                if (F > 0.0) hi = t;
+                else lo = t;
+                double tn = t - F * x_at(u + t);
+                if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
+                const bool done = fabs(tn - t) <= 1e-15 * (u + t);
+                t = tn;
+                if (done) break;
+            }
+            return ln_rate_after(Nf + u + t, sp, nullptr);
+        }
+        H += I;
+        u += du;
+        l = ln_rate_after(Nf + u, sp, &sb);
+    }
+    return ln_rate_after(Nf + u + (Nn - H) * xce, sp, nullptr);
+}
+
 }  // namespace rrt

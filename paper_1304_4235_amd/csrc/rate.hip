@@ -57,14 +57,19 @@ struct RateRule {
     double tau_case_b;        // +inf = case A throughout
     const double* alphaB;
     int relative;
-    // near/far scheme (one frequency bin): far columns in N, near total-hydrogen
-    // columns here; each ray's rate is the slab solution of its near column lit
-    // by the far-attenuated radiation (null = plain rate)
+    // near/far scheme: far columns in N, near total-hydrogen columns here; each
+    // ray's rate is the slab solution of its near column lit by the
+    // far-attenuated radiation (null = plain rate): analytic for one bin, the
+    // polychromatic slab (Gauss-Legendre nodes and weights below) for several
     const double* Nn;
     double sigma1;
+    double gl_x[6], gl_w[6];
 };
 
+enum { kSchemePlain = 0, kSchemeNearMono = 1, kSchemeNearPoly = 2 };
+
 // One thread per particle: rays, then bins; optionally the equilibrium update.
+template <int SCHEME>
 __global__ void __launch_bounds__(256)
 k_gamma(const double* __restrict__ N, int64_t n, int n_ray, int n_bins,
         const float* __restrict__ ws_rel, const float* __restrict__ dsig_l2, double sigma_min,
@@ -83,13 +88,22 @@ k_gamma(const double* __restrict__ N, int64_t n, int n_ray, int n_bins,
                       !(rule.want && i < n && rule.want[i] == 0);
     if (i < n && live) {
         double m = -INFINITY, s = 0.0, l;
-        if (rule.Nn) {
+        if (SCHEME != kSchemePlain) {
             // near/far: per ray the slab of near particles lit by the radiation
-            // the far particles let through (one bin: ln w sigma = ln_ws_max)
+            // the far particles let through
+            const SpectrumView sp{ws_rel, dsig_l2, n_bins, sigma_min, ln_ws_max};
             for (int k = 0; k < n_ray; ++k) {
-                const double l0 = ln_ws_max - rule.sigma1 * N[(int64_t)k * n + i];
-                const double v = slab_ln_rate(l0, (double)nH_s[i], alpha[i], gcoll[i],
-                                              rule.sigma1, rule.Nn[(int64_t)k * n + i]);
+                double v;
+                if (SCHEME == kSchemeNearPoly) {
+                    v = slab_ln_rate_poly(N[(int64_t)k * n + i], rule.Nn[(int64_t)k * n + i],
+                                          (double)nH_s[i], alpha[i], gcoll[i], sp, rule.gl_x,
+                                          rule.gl_w);
+                } else {
+                    // one bin: ln w sigma = ln_ws_max
+                    const double l0 = ln_ws_max - rule.sigma1 * N[(int64_t)k * n + i];
+                    v = slab_ln_rate(l0, (double)nH_s[i], alpha[i], gcoll[i], rule.sigma1,
+                                     rule.Nn[(int64_t)k * n + i]);
+                }
                 if (v == -INFINITY) continue;
                 if (v > m) {
                     s = s * exp(m - v) + 1.0;
@@ -263,6 +277,35 @@ inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); 
 
 }  // namespace
 
+namespace {
+
+// Nodes and weights of the 6-point Gauss-Legendre rule on [-1, 1]: the roots
+// of the Legendre polynomial P_6 by Newton's method from the usual cosine
+// estimates, weights 2 / ((1 - x^2) P_6'(x)^2).
+void gauss_legendre6(double* x, double* w)
+{
+    const int m = 6;
+    for (int i = 0; i < m; ++i) {
+        double z = std::cos(M_PI * (i + 0.75) / (m + 0.5)), dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;                         // P_0, P_1
+            for (int k = 2; k <= m; ++k) {
+                const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = m * (z * p1 - p0) / (z * z - 1.0);          // P_m'(z)
+            const double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) break;
+        }
+        x[i] = z;
+        w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+}  // namespace
+
 hipError_t launch_init_state(Ctx& c, bool use_given)
 {
     hipLaunchKernelGGL(k_init_state, dim3(nblk(c.n)), dim3(kBlock), 0, c.stream, c.perm, c.T_in,
@@ -282,11 +325,20 @@ hipError_t launch_gamma(Ctx& c, bool update_x, bool first_sweep)
     rule.relative = c.rule_relative;
     rule.Nn = c.near_far ? c.Nn_s : nullptr;
     rule.sigma1 = c.sigma_min;
-    hipLaunchKernelGGL(k_gamma, dim3(nblk(c.n)), dim3(kBlock), 0, c.stream, c.N_s, c.n, c.n_ray,
-                       c.n_bins, c.ws_rel, c.dsig_l2, c.sigma_min, c.ln_ws_max,
-                       std::log(c.gamma_thin), c.lnG_s, c.G_s, c.tau_s, update_x ? 1 : 0, c.nH_s,
-                       c.mu_s, c.alpha_s, c.gcoll_s, c.x_s, c.mux_s, c.red, c.geom.seg_of,
-                       c.geom.seg_active, c.geom.seg_active ? c.seg_maxdx : nullptr, rule);
+    gauss_legendre6(rule.gl_x, rule.gl_w);
+    const int scheme = !c.near_far ? kSchemePlain : c.n_bins == 1 ? kSchemeNearMono
+                                                                  : kSchemeNearPoly;
+    auto launch = [&](auto kernel) {
+        hipLaunchKernelGGL(kernel, dim3(nblk(c.n)), dim3(kBlock), 0, c.stream, c.N_s, c.n,
+                           c.n_ray, c.n_bins, c.ws_rel, c.dsig_l2, c.sigma_min, c.ln_ws_max,
+                           std::log(c.gamma_thin), c.lnG_s, c.G_s, c.tau_s, update_x ? 1 : 0,
+                           c.nH_s, c.mu_s, c.alpha_s, c.gcoll_s, c.x_s, c.mux_s, c.red,
+                           c.geom.seg_of, c.geom.seg_active,
+                           c.geom.seg_active ? c.seg_maxdx : nullptr, rule);
+    };
+    if (scheme == kSchemePlain) launch(k_gamma<kSchemePlain>);
+    else if (scheme == kSchemeNearMono) launch(k_gamma<kSchemeNearMono>);
+    else launch(k_gamma<kSchemeNearPoly>);
     return hipGetLastError();
 }
 

@@ -731,8 +731,6 @@ int rrt_compute_gamma(rrt_ctx* x, double* lnG_out, double* G_out, float* tau_out
     Ctx& c = x->c;
     if (int r = need_tree(c)) return r;
     if (!c.have_columns) return fail(c, RRT_E_STATE, "no columns: call rrt_compute_columns");
-    if (c.near_far && c.n_bins != 1)
-        return fail(c, RRT_E_STATE, "the near/far slab solution needs one frequency bin");
     HIP_OK(launch_gamma(c, false));
     c.have_gamma = true;
     if (lnG_out) HIP_OK(launch_to_input_order_d(c, c.lnG_s, lnG_out, 1));
@@ -870,8 +868,6 @@ int rrt_iterate_equilibrium(rrt_ctx* x, int32_t max_iter, double tol, double* x_
     Ctx& c = x->c;
     if (int r = need_tree(c)) return r;
     if (max_iter < 0 || !(tol >= 0.0)) return fail(c, RRT_E_ARG, "max_iter >= 0 and tol >= 0");
-    if (c.near_far && c.n_bins != 1)
-        return fail(c, RRT_E_STATE, "the near/far slab solution needs one frequency bin");
     if (c.near_far && !default_rule(c))
         return fail(c, RRT_E_STATE, "the near/far scheme runs with the default update rule");
     const bool ordered = c.rule_blocks > 1;
@@ -937,8 +933,6 @@ int rrt_evolve(rrt_ctx* x, double dt, int32_t n_steps, double* x_out)
         return fail(c, RRT_E_ARG, "dt must be finite and >= 0, n_steps >= 0");
     if (!default_rule(c))
         return fail(c, RRT_E_STATE, "the evolution uses case A rates: reset the update rule");
-    if (c.near_far && c.n_bins != 1)
-        return fail(c, RRT_E_STATE, "the near/far slab solution needs one frequency bin");
     for (int s = 0; s < n_steps && dt > 0.0; ++s) {     // no time, no change
         int64_t hits = -1;
         if (int r = columns_impl(c, &hits)) return r;

@@ -1,6 +1,7 @@
 """The paper's near/far scheme for SPH (Sec. 4.1.2) on the GPU against the FP64
 oracle: near/far columns per ray, the per-ray slab rate of the near particles
-(monochromatic slab solution of Appendix C.4) and the fixed point.
+(the monochromatic slab solution of Appendix C.4 for one bin, the
+polychromatic slab for several) and the fixed point.
 
 Bars as for the plain scheme: columns 1e-6 relative; ln Gamma 1e-4 absolute
 where tau_eff <= 100 (tau_eff 1e-6 relative beyond); x 1e-4 relative.
@@ -52,10 +53,22 @@ def _grey_halo():
     return wl
 
 
+def _poly(wl, n_bins=8):
+    wl.sigma, wl.w = W.power_law_spectrum(n_bins, 1.5, 1e-12)
+    return wl
+
+
+def _case(which):
+    return {"lattice": _lattice, "halo": _grey_halo,
+            "lattice_poly": lambda: _poly(_lattice()),
+            "halo_poly": lambda: _poly(_grey_halo())}[which]()
+
+
 @pytest.mark.parametrize("which,paths", [("lattice", -1), ("lattice", 0), ("halo", -1),
-                                         ("halo", 0)])
+                                         ("halo", 0), ("lattice_poly", -1), ("halo_poly", -1),
+                                         ("halo_poly", 0)])
 def test_near_far_columns_rates_and_step(which, paths):
-    wl = _lattice() if which == "lattice" else _grey_halo()
+    wl = _case(which)
     s = _solver(wl, record_paths=paths)
     rng = np.random.default_rng(4)
     x = np.minimum(oracle.x_thin(wl) * rng.uniform(1, 300, wl.n), 0.99)
@@ -82,9 +95,10 @@ def test_near_far_columns_rates_and_step(which, paths):
     assert not np.allclose(lnG_plain.cpu().numpy(), lnG.cpu().numpy(), rtol=1e-3)
 
 
-def test_near_far_fixed_point():
-    wl = _lattice()
-    _say("oracle near/far solve")
+@pytest.mark.parametrize("which", ["lattice", "lattice_poly"])
+def test_near_far_fixed_point(which):
+    wl = _case(which)
+    _say("oracle near/far solve", which)
     ref = oracle.solve_near_far(wl, max_iter=40, tol=1e-3)
     assert 2 <= ref["iters"] < 40
     s = _solver(wl)
@@ -104,13 +118,6 @@ def test_near_far_fixed_point():
 
 def test_near_far_requirements():
     from paper_1304_4235_amd import RRTError
-    wl = W.isothermal_halo(n=2000, seed=82, n_bins=8)
-    s = _solver(wl)
-    s.compute_columns(want_N=False, count=False)
-    with pytest.raises(RRTError):                     # polychromatic: no slab solution
-        s.compute_gamma()
-    with pytest.raises(RRTError):
-        s.iterate(5, 1e-3)
     wl1 = _grey_halo()
     s1 = _solver(wl1)
     with pytest.raises(RRTError):

@@ -556,6 +556,66 @@ def test_slab_rate_limits():
     assert l2 < l1 < math.log(G0)
 
 
+_SLAB_CASES = [(Nf, Nn, nH) for Nf in (0.0, 3e17, 1e19) for Nn in (1e16, 1e18, 1e20, 3e21)
+               for nH in (1e-3, 0.3)]
+
+
+def test_poly_slab_with_one_bin_is_the_analytic_slab():
+    """The polychromatic slab (quadrature of 1/x over the HI column, bisection
+    for the bottom) with one bin against the closed form of App. C.4, from
+    optically thin to 1e4 e-folds deep."""
+    a, g = oracle.alpha_A(1e4)[0], oracle.gamma_coll(1e4)[0]
+    sig, w = W.grey_spectrum(1e-12)
+    for Nf, Nn, nH in _SLAB_CASES:
+        lp = oracle.slab_lnG_poly(sig, w, Nf, nH, a, g, Nn)[()]
+        la = oracle.slab_lnG(math.log(w[0] * sig[0]) - sig[0] * Nf, nH, a, g, sig[0], Nn)[()]
+        assert abs(lp - la) <= 1e-12 * abs(la) + 1e-10, (Nf, Nn, nH, lp, la)
+
+
+@pytest.mark.parametrize("Nf,Nn,nH", [(0.0, 1e20, 0.3), (3e17, 3e21, 1e-3), (0.0, 3e21, 0.3),
+                                      (1e19, 3e21, 0.3), (3e17, 1e18, 0.3)])
+def test_poly_slab_against_rk4_in_the_hydrogen_column(Nf, Nn, nH):
+    """Eight bins: the same slab as the ODE dy/dt = x_-(Gamma(N_far + y)) in the
+    total hydrogen column t, by RK4 at n and 2n steps; the quadrature form
+    agrees within twice RK4's own change between them."""
+    a, g = oracle.alpha_A(1e4)[0], oracle.gamma_coll(1e4)[0]
+    sig, w = W.power_law_spectrum(8, 1.5, 1e-12)
+    lp = oracle.slab_lnG_poly(sig, w, Nf, nH, a, g, Nn)[()]
+    r1 = oracle.slab_rk4_poly(sig, w, Nf, nH, a, g, Nn, 3000)
+    r2 = oracle.slab_rk4_poly(sig, w, Nf, nH, a, g, Nn, 6000)
+    assert abs(lp - r2) <= 2.0 * abs(r1 - r2) + 1e-10 * abs(lp), (lp, r1, r2)
+
+
+def test_poly_slab_limits():
+    a, g = oracle.alpha_A(1e4)[0], oracle.gamma_coll(1e4)[0]
+    sig, w = W.power_law_spectrum(8, 1.5, 1e-12)
+    lnws = np.log(w * sig)
+    for Nf in (0.0, 1e18):
+        # a slab of zero thickness passes the far-attenuated rate unchanged
+        lf = oracle.slab_lnG_poly(sig, w, Nf, 0.1, a, g, 0.0)[()]
+        v = lnws - sig * Nf
+        assert lf == pytest.approx(v.max() + math.log(np.exp(v - v.max()).sum()), abs=1e-13)
+        # thicker slabs let less through; denser gas too (more recombination)
+        Ns = [1e17, 1e18, 1e19, 1e20, 1e21]
+        ls = [oracle.slab_lnG_poly(sig, w, Nf, 0.1, a, g, Nn)[()] for Nn in Ns]
+        assert all(l2 < l1 for l1, l2 in zip(ls, ls[1:]))
+        assert oracle.slab_lnG_poly(sig, w, Nf, 1.0, a, g, 1e20)[()] < \
+            oracle.slab_lnG_poly(sig, w, Nf, 0.01, a, g, 1e20)[()]
+
+
+def test_near_far_rate_poly_with_one_bin_equals_mono():
+    """The near/far step for one bin through both code paths of the oracle: the
+    analytic slab and the polychromatic one."""
+    wl = W.make_config(0, n_side_lattice=6, box=37.5)
+    rng = np.random.default_rng(6)
+    x = np.minimum(oracle.x_thin(wl) * rng.uniform(1, 300, wl.n), 0.99)
+    src = np.array([0, 9, 100, 215])
+    mono = oracle.step_near_far(wl, x, src)
+    wl2 = W.Workload(**{**wl.__dict__, "sigma": np.repeat(wl.sigma, 2), "w": np.repeat(wl.w, 2) / 2})
+    poly = oracle.step_near_far(wl2, x, src)
+    np.testing.assert_allclose(poly["lnG"], mono["lnG"], rtol=1e-11, atol=1e-11)
+
+
 def test_near_far_columns_split_the_plain_column():
     """With every x = 1 the far and near columns add up to the plain column;
     each ray from a source hits every near particle, and the near set is the
