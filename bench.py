@@ -52,6 +52,8 @@ def make_workload(name: str):
         return W.make_config(2)
     if name == "halo_batch_64":
         return W.make_config(3)
+    if name == "lognormal_field_shard_0of8":
+        return W.field_shard(W.make_config(2), 0, 8)
     if name == "halo_batch_64_small":
         return W.halo_batch(n_lo=2048, n_hi=32768, name="halo_batch_64_small")
     if name.startswith("isothermal_halo_"):
@@ -335,6 +337,12 @@ def main():
     }
     print(f"timed {args.steps} steps in {dt:.3f} s; iterations {iters}", file=sys.stderr,
           flush=True)
+    if "n_owned" in wl.meta:
+        # one GPU's share of the field: owned particles plus ghosts within
+        # l_ray + max(h); every source is traced, ghosts included
+        out["config"]["shard"] = {"rank": wl.meta["shard"], "of": wl.meta["n_ranks"],
+                                  "owned_particles": wl.meta["n_owned"],
+                                  "ghost_particles": wl.n - wl.meta["n_owned"]}
     if args.rules and wl.tol > 0:
         # time to solution under the paper's update rules (Sec. 4), same geometry
         # and recorded paths; the order-independent case A solve is the timed step

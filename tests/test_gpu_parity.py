@@ -474,3 +474,29 @@ def test_wave_and_lane_traversals_agree(which):
     np.testing.assert_array_equal(oa, ob)
     np.testing.assert_array_equal(ja, jb)
     np.testing.assert_array_equal(ia, ib)
+
+
+@pytest.mark.parametrize("rank", [0, 5])
+def test_field_shard_owned_columns_equal_the_whole_field(rank):
+    """One GPU's share of a periodic field: block `rank` of 8 plus every
+    particle within l_ray + max(h) of it, in the same periodic box.  The rays
+    of owned sources reach only particles of the shard, so their columns equal
+    those of the whole field (summation order aside)."""
+    wl = W.lognormal_field(n_grid=40, box=3125.0, n_bins=16)
+    rng = np.random.default_rng(31)
+    x = np.minimum(oracle.x_thin(wl) * rng.uniform(1, 1e3, wl.n), 0.99)
+    full = _solver(wl)
+    full.set_state(torch.tensor(x))
+    N_full, _ = full.compute_columns()
+    N_full = N_full.cpu().numpy()
+    full.close()
+    sh = W.field_shard(wl, rank, 8)
+    idx, n_own = sh.meta["index"], sh.meta["n_owned"]
+    _say("shard", rank, "owned", n_own, "ghosts", sh.n - n_own)
+    assert 0 < n_own < sh.n < wl.n
+    s = _solver(sh)
+    s.set_state(torch.tensor(x[idx]))
+    N_sh, _ = s.compute_columns()
+    np.testing.assert_allclose(N_sh.cpu().numpy()[:n_own], N_full[idx[:n_own]], rtol=1e-12,
+                               atol=0)
+    s.close()

@@ -124,3 +124,25 @@ def test_halo_batch_offsets():
     assert off[0] == 0 and off[-1] == wl.n and np.all(np.diff(off) >= 512)
     sub = wl.subset_halo(1)
     assert sub.n == off[2] - off[1]
+
+
+def test_field_shard_holds_everything_owned_rays_can_reach():
+    """Blocks of a periodic field: owned particles partition the field; every
+    particle within l_ray + h_j (periodic distance) of an owned source is in
+    that source's shard."""
+    wl = W.lognormal_field(n_grid=16, box=1250.0, n_bins=4)
+    owned_total = 0
+    rng = np.random.default_rng(2)
+    for r in range(8):
+        sh = W.field_shard(wl, r, 8)
+        idx, n_own = sh.meta["index"], sh.meta["n_owned"]
+        assert len(np.unique(idx)) == len(idx)
+        owned_total += n_own
+        inside = set(idx.tolist())
+        p = wl.pos.astype(np.float64)
+        for s in rng.choice(idx[:n_own], 20, replace=False):
+            d = p - p[s]
+            d -= wl.box * np.round(d / wl.box)
+            reach = np.sqrt((d * d).sum(1)) <= wl.l_ray + wl.h.astype(np.float64)
+            assert set(np.nonzero(reach)[0].tolist()) <= inside
+    assert owned_total == wl.n

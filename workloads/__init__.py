@@ -321,6 +321,35 @@ def halo_batch(n_halo: int = 64, n_lo: int = 8192, n_hi: int = 524288, peak_lo: 
                               seed=seed))
 
 
+def field_shard(wl: Workload, rank: int, n_ranks: int = 8) -> Workload:
+    """One GPU's share of a periodic field split into n_ranks = m^3 cubic blocks:
+    the particles of block ``rank`` (owned, first) and every other particle whose
+    periodic distance to the block is at most l_ray + max(h) on each axis
+    (ghosts), kept in the same periodic box.  Every particle a ray from an owned
+    source can reach is in the shard, so owned sources see the same
+    intersections as in the whole field.  meta["n_owned"] counts the owned
+    particles and meta["index"] maps shard particles to the field's."""
+    assert wl.box > 0.0, "shards of a periodic field"
+    m = round(n_ranks ** (1.0 / 3.0))
+    assert m ** 3 == n_ranks and 0 <= rank < n_ranks
+    side = wl.box / m
+    cell = np.array([rank // (m * m), (rank // m) % m, rank % m], dtype=np.float64)
+    lo = cell * side
+    p = wl.pos.astype(np.float64)
+    owned = np.all((p >= lo) & (p < lo + side), axis=1)
+    reach = wl.l_ray + float(wl.h.max())
+    # periodic distance of each coordinate to the block's interval
+    c = lo + 0.5 * side
+    d = np.abs(p - c)
+    d = np.minimum(d, wl.box - d) - 0.5 * side
+    near = np.all(d <= reach, axis=1) & ~owned
+    idx = np.concatenate([np.nonzero(owned)[0], np.nonzero(near)[0]])
+    meta = dict(wl.meta, shard=rank, n_ranks=n_ranks, n_owned=int(owned.sum()), index=idx)
+    return dataclasses.replace(wl, name=f"{wl.name}_shard{rank}of{n_ranks}", pos=wl.pos[idx],
+                               h=wl.h[idx], mu=wl.mu[idx], n_H=wl.n_H[idx], T=wl.T[idx],
+                               meta=meta)
+
+
 def make_config(i: int, **kw) -> Workload:
     """The five configurations by index (0-based); keyword overrides shrink them."""
     if i == 0:
