@@ -37,7 +37,7 @@ k_adj_rate(const double* __restrict__ N, int64_t n, int n_ray, int n_bins,
            const float* __restrict__ srat, double sigma_min, double ln_ws_max,
            const float* __restrict__ nH_s, const double* __restrict__ alpha,
            const double* __restrict__ gcoll, const double* __restrict__ lam,
-           const double* __restrict__ lup, double* __restrict__ nu, double* __restrict__ pis,
+           const double* __restrict__ lup, float* __restrict__ nu, double* __restrict__ pis,
            double* __restrict__ gnH, float2* __restrict__ st, double* __restrict__ ell_out)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -84,7 +84,7 @@ k_adj_rate(const double* __restrict__ N, int64_t n, int n_ray, int n_bins,
             pk = pi / (double)ST.x;
             nk = -ell * pi * sigma_min * ((double)ST.y / (double)ST.x);
         }
-        nu[(int64_t)k * n + i] = nk;
+        nu[(int64_t)k * n + i] = (float)nk;
         pis[(int64_t)k * n + i] = pk;
     }
 }
@@ -152,13 +152,13 @@ __global__ void k_adj_bins(const double* __restrict__ part, int64_t n_chunks, in
 // transposed product over recorded paths: y_j += (K/h^2) nu_row for every hit
 __global__ void __launch_bounds__(256)
 k_adj_scatter(const uint64_t* __restrict__ row_off, const int2* __restrict__ path,
-              const double* __restrict__ nu, int64_t n_rows, double* __restrict__ y)
+              const float* __restrict__ nu, int64_t n_rows, double* __restrict__ y)
 {
     const int lane = threadIdx.x & 63;
     const int64_t stride = (int64_t)gridDim.x * (blockDim.x >> 6);
     for (int64_t row = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6; row < n_rows;
          row += stride) {
-        const double v = nu[row];
+        const double v = (double)nu[row];
         if (v == 0.0) continue;
         const uint64_t a = row_off[row], b = row_off[row + 1];
         for (uint64_t e = a + lane; e < b; e += 64) {

@@ -222,7 +222,7 @@ struct Ctx {
     int32_t fwd_K = -1;          // steps of the last rrt_forward (-1: none)
     double* adj_lam = nullptr;   // [n] adjoint of x^k
     double* adj_lup = nullptr;   // [n] upstream adjoint of lnG^K
-    double* adj_nu = nullptr;    // [n_ray][n] adjoint of the columns
+    float* adj_nu = nullptr;     // [n_ray][n] adjoint of the columns (FP32)
     double* adj_pis = nullptr;   // [n_ray][n] softmax / S per ray
     double* adj_gnH = nullptr;   // [n] dL/dn_H, tree order
     double* adj_y = nullptr;     // [n] transposed product
@@ -291,7 +291,7 @@ hipError_t launch_evolve(Ctx& c, double dt);
 hipError_t launch_block_ids(Ctx& c, const int32_t* block_in);
 void free_tiles(Ctx& c);
 hipError_t launch_tile_columns(Ctx& c, int group);
-hipError_t launch_tile_scatter(Ctx& c, const double* nu, double* y);
+hipError_t launch_tile_scatter(Ctx& c, const float* nu, double* y);
 // lanes per row of the tile products: the tuned path group, else from the
 // mean intersections per row
 int tile_group(const Ctx& c);
@@ -301,7 +301,7 @@ hipError_t launch_count_hits(Ctx& c, uint64_t* row_cnt);
 hipError_t launch_record_hits(Ctx& c, const uint64_t* row_off, int32_t* hit_j, int32_t* hit_img,
                               uint64_t cap);
 
-hipError_t launch_scatter_traverse(Ctx& c, const double* nu, double* y);
+hipError_t launch_scatter_traverse(Ctx& c, const float* nu, double* y);
 
 // ---- transpose.hip ----
 hipError_t build_transposed_paths(Ctx& c);

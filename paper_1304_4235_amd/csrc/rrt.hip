@@ -79,7 +79,8 @@ void free_particles(Ctx& c)
                    c.adj_wpart, c.adj_gw, c.adj_tpart, c.adj_st, c.adj_ell, c.Nhist};
     for (void* b : adj)
         if (b) (void)hipFree(b);
-    c.xhist = c.adj_lam = c.adj_lup = c.adj_nu = c.adj_pis = c.adj_gnH = c.adj_y = nullptr;
+    c.xhist = c.adj_lam = c.adj_lup = c.adj_pis = c.adj_gnH = c.adj_y = nullptr;
+    c.adj_nu = nullptr;
     c.Nhist = nullptr;
     c.Nhist_cap = 0;
     c.Nhist_on = false;

@@ -151,7 +151,7 @@ template <int G>
 __global__ void __launch_bounds__(512)
 k_tile_scatter(const uint64_t* __restrict__ row_off, const uint16_t* __restrict__ idx,
                const float* __restrict__ fac, const uint64_t* __restrict__ set_off,
-               const uint32_t* __restrict__ set, const double* __restrict__ nu, int64_t n_rows,
+               const uint32_t* __restrict__ set, const float* __restrict__ nu, int64_t n_rows,
                int tile_rows, int64_t n_tiles, double* __restrict__ y)
 {
     extern __shared__ double sacc[];
@@ -172,7 +172,7 @@ k_tile_scatter(const uint64_t* __restrict__ row_off, const uint16_t* __restrict_
         if (row < r1) {
             a = row_off[row];
             b = row_off[row + 1];
-            v = nu[row];
+            v = (double)nu[row];
         }
         for (; row < r1; row += groups) {
             const int64_t next = row + groups;
@@ -181,7 +181,7 @@ k_tile_scatter(const uint64_t* __restrict__ row_off, const uint16_t* __restrict_
             if (next < r1) {
                 an = row_off[next];
                 bn = row_off[next + 1];
-                vn = nu[next];
+                vn = (double)nu[next];
             }
             if (v != 0.0) {
                 for (uint64_t q = (a >> 2) + lane; 4 * q < b; q += G) {
@@ -383,7 +383,7 @@ hipError_t build_tiles(Ctx& c)
 namespace {
 
 template <int G>
-void launch_scatter_g(Ctx& c, const double* nu, double* y, int64_t n_rows, unsigned nb,
+void launch_scatter_g(Ctx& c, const float* nu, double* y, int64_t n_rows, unsigned nb,
                       size_t lds)
 {
     hipLaunchKernelGGL(k_tile_scatter<G>, dim3(nb), dim3(512), lds, c.stream, c.row_off,
@@ -401,7 +401,7 @@ int tile_group(const Ctx& c)
     return mean >= 160 ? 32 : mean >= 40 ? 16 : 8;
 }
 
-hipError_t launch_tile_scatter(Ctx& c, const double* nu, double* y)
+hipError_t launch_tile_scatter(Ctx& c, const float* nu, double* y)
 {
     const int64_t n_rows = c.n * (int64_t)c.n_ray;
     const size_t lds = sizeof(double) * (size_t)std::max<int64_t>(c.tile_max_u, 1);

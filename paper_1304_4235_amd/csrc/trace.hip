@@ -105,7 +105,7 @@ struct RayOut {
     uint64_t* row_cnt;      // [n_ray * n] hits per ray (count mode)
     const uint64_t* row_off;// [n_ray * n] write offsets (record / path modes)
     int2* path;             // path mode: (tree index, factor bits) per hit
-    const double* nu;       // scatter mode: adjoint of each ray's column
+    const float* nu;        // scatter mode: adjoint of each ray's column
     double* y;              // scatter mode: accumulated per tree index
     int32_t* hit_j;         // record mode: input index of each hit
     int32_t* hit_img;       // record mode: image code of each hit
@@ -172,7 +172,7 @@ k_trace(const Node* __restrict__ nodes, const float4* __restrict__ p4,
         }
         double acc = 0.0, accn = 0.0;
         uint64_t w = (MODE == kModeRecord || MODE == kModePath) ? out.row_off[gid] : 0;
-        const double nur = (MODE == kModeScatter) ? out.nu[gid] : 0.0;
+        const double nur = (MODE == kModeScatter) ? (double)out.nu[gid] : 0.0;
 
         // the subtree this ray's halo owns (the whole tree for one problem)
         int root = 0, end = g.n_nodes;
@@ -376,7 +376,7 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
     double acc = 0.0, accn = 0.0;
     uint32_t cnt = 0;
     uint64_t w = ((MODE == kModeRecord || MODE == kModePath) && active) ? out.row_off[gid] : 0;
-    const double nur = (MODE == kModeScatter && active) ? out.nu[gid] : 0.0;
+    const double nur = (MODE == kModeScatter && active) ? (double)out.nu[gid] : 0.0;
 
     // lanes of one wave can belong to two halos (at a halo boundary in tree
     // order): walk each halo's subtree in turn with that halo's lanes
@@ -690,7 +690,7 @@ hipError_t launch_record_paths(Ctx& c, const uint64_t* row_off, int2* path, uint
     return launch_mode(c, kModePath, o);
 }
 
-hipError_t launch_scatter_traverse(Ctx& c, const double* nu, double* y)
+hipError_t launch_scatter_traverse(Ctx& c, const float* nu, double* y)
 {
     RayOut o{};
     o.nu = nu;

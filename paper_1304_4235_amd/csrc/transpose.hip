@@ -114,7 +114,7 @@ __global__ void k_col_starts(const uint32_t* __restrict__ key, int64_t m, int64_
 // y_j = sum over particle j's entries of factor * nu[row], in row order
 __global__ void __launch_bounds__(256)
 k_gather_cols(const uint64_t* __restrict__ col_off, const uint64_t* __restrict__ ent,
-              const double* __restrict__ nu, int64_t n, double* __restrict__ y)
+              const float* __restrict__ nu, int64_t n, double* __restrict__ y)
 {
     const int lane = threadIdx.x & 63;
     const int64_t stride = (int64_t)gridDim.x * (blockDim.x >> 6);
@@ -128,8 +128,8 @@ k_gather_cols(const uint64_t* __restrict__ col_off, const uint64_t* __restrict__
             const uint64_t v1 = e + 64 < b ? (uint64_t)__builtin_nontemporal_load(p + e + 64) : 0ull;
             const uint64_t v2 = e + 128 < b ? (uint64_t)__builtin_nontemporal_load(p + e + 128) : 0ull;
             const uint64_t v3 = e + 192 < b ? (uint64_t)__builtin_nontemporal_load(p + e + 192) : 0ull;
-            const double n0 = nu[(uint32_t)v0], n1 = nu[(uint32_t)v1];
-            const double n2 = nu[(uint32_t)v2], n3 = nu[(uint32_t)v3];
+            const double n0 = (double)nu[(uint32_t)v0], n1 = (double)nu[(uint32_t)v1];
+            const double n2 = (double)nu[(uint32_t)v2], n3 = (double)nu[(uint32_t)v3];
             acc += (double)__int_as_float((int)(v0 >> 32)) * n0;
             acc += (double)__int_as_float((int)(v1 >> 32)) * n1;
             acc += (double)__int_as_float((int)(v2 >> 32)) * n2;
