@@ -172,8 +172,8 @@ int rrt_update_equilibrium(rrt_ctx* ctx, double* x_out, double* max_dx_out);
  * in equilibrium at every depth under the far-attenuated binned spectrum,
  * solved per ray (the bottom is where the hydrogen column, the integral of
  * 1/x over the HI column, reaches the near column; 6-point Gauss-Legendre
- * steps and Newton's method), in place of the paper's 4-D table of the same
- * function.  Gamma = (1/n_ray) sum_k Gamma_k (eq. gammashld).  Recorded paths are dropped when the scheme changes.  While it is
+ * steps and Newton's method, with the spectrum's attenuation tabulated once
+ * per spectrum), in place of the paper's 4-D table of the same function.  Gamma = (1/n_ray) sum_k Gamma_k (eq. gammashld).  Recorded paths are dropped when the scheme changes.  While it is
  * set, rrt_forward, rrt_backward, rrt_iterate_halos and update rules other
  * than the default return RRT_E_STATE.  0 (default): the plain scheme. */
 int rrt_set_scheme(rrt_ctx* ctx, int32_t near_far);

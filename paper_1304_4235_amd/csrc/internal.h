@@ -210,6 +210,12 @@ struct Ctx {
     float* srat = nullptr;       // sigma_b / sigma_min
     double sigma_min = 0.0, ln_ws_max = 0.0, gamma_thin = 0.0, ws_max = 0.0;
     std::vector<double> sigma_host;   // the spectrum as given
+    std::vector<double> w_host;
+    // attenuation table of the spectrum for the polychromatic near slab
+    // (double2 per node; built on first use, dropped with the spectrum)
+    double* att_tab = nullptr;
+    int att_m = 0;
+    double att_dt = 0.0, att_tmax = 0.0, att_smax = 0.0;
     bool all_bins_weighted = false;   // every w_b > 0 (no bin dropped)
 
     // reverse mode: iterates of the last rrt_forward and adjoint work buffers

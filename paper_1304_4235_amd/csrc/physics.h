@@ -109,50 +109,64 @@ __device__ inline double slab_ln_rate(double lnG0, double nH, double alpha, doub
     return log(nH) + log(alpha + gcoll) + log1p(-xs) + v - log(xs);
 }
 
-// A binned spectrum as the rate kernel holds it: the bins with w_b > 0,
-// ws_rel = w_b sigma_b / max_b(w_b sigma_b), dsig_l2 = (sigma_b - sigma_min) log2(e).
-struct SpectrumView {
-    const float* ws_rel;
-    const float* dsig_l2;
-    int n_bins;
-    double sigma_min;
-    double ln_ws_max;
+// The spectrum's attenuation, tabulated once per spectrum: with
+// S(N) = sum_b (w_b sigma_b / max) exp(-(sigma_b - sigma_min) N), the rate
+// after a hydrogen column N is ln Gamma = ln_ws_max - sigma_min N + ln S(N).
+// v[i] = (ln S, d ln S / dt) at t_i = i dt, t = ln(1 + sigma_max N); beyond
+// t_max every bin but the least absorbed has decayed by e^-60 and ln S is
+// constant.  Cubic Hermite interpolation in t.
+struct AttenuationTable {
+    const double2* v;
+    int m;
+    double dt, t_max, sigma_max, sigma_min, ln_ws_max;
 };
 
-// ln of the rate of the spectrum after a hydrogen column N (cm^-2), from FP32
-// terms shifted by the least-absorbed bin; *sbar (nullable) receives the
+// ln Gamma after a hydrogen column N (cm^-2); *sbar (nullable) receives the
 // rate-weighted mean cross-section -d ln Gamma / dN.
-__device__ inline double ln_rate_after(double N, const SpectrumView& sp, double* sbar)
+__device__ inline double ln_rate_after(double N, const AttenuationTable& at, double* sbar)
 {
-    const float Nf = (float)N;
-    float S = 0.f, D = 0.f;
-    for (int b = 0; b < sp.n_bins; ++b) {
-        const float e = sp.ws_rel[b] * exp2f(-sp.dsig_l2[b] * Nf);
-        S += e;
-        D = fmaf(sp.dsig_l2[b], e, D);
+    double lnS, dlnS_dN = 0.0;
+    const double t = log1p(N * at.sigma_max);
+    if (!(t < at.t_max) || at.m < 2) {
+        lnS = at.v[at.m - 1].x;
+    } else {
+        const double u = t / at.dt;
+        int i = (int)u;
+        if (i > at.m - 2) i = at.m - 2;
+        const double th = u - i, th2 = th * th;
+        const double2 a = at.v[i], b = at.v[i + 1];
+        const double h00 = (1.0 + 2.0 * th) * (1.0 - th) * (1.0 - th);
+        const double h10 = th * (1.0 - th) * (1.0 - th);
+        const double h01 = th2 * (3.0 - 2.0 * th), h11 = th2 * (th - 1.0);
+        lnS = h00 * a.x + h10 * at.dt * a.y + h01 * b.x + h11 * at.dt * b.y;
+        if (sbar) {
+            const double d00 = 6.0 * th2 - 6.0 * th, d10 = 3.0 * th2 - 4.0 * th + 1.0;
+            const double d01 = 6.0 * th - 6.0 * th2, d11 = 3.0 * th2 - 2.0 * th;
+            const double dlnS_dt =
+                (d00 * a.x + d10 * at.dt * a.y + d01 * b.x + d11 * at.dt * b.y) / at.dt;
+            dlnS_dN = dlnS_dt * at.sigma_max / (1.0 + N * at.sigma_max);
+        }
     }
-    if (!(S > 0.f)) {
-        if (sbar) *sbar = sp.sigma_min;
-        return -INFINITY;
-    }
-    if (sbar) *sbar = sp.sigma_min + 0.6931471805599453 * (double)(D / S);
-    return sp.ln_ws_max - sp.sigma_min * N + log((double)S);
+    if (sbar) *sbar = fmax(at.sigma_min - dlnS_dN, at.sigma_min);
+    return at.ln_ws_max - at.sigma_min * N + lnS;
 }
 
 constexpr int kSlabMaxSteps = 4096;
+constexpr int kAttNodes = 4096;      // nodes of the attenuation table
 
 // ln of the rate at the bottom of a uniform slab (density nH, coefficients
 // alpha, gcoll at its temperature) of total hydrogen column Nn, lit by the
-// binned spectrum after a far column Nf: the polychromatic near slab.  With
-// HI column u below the surface the rate is Gamma(Nf + u), the neutral
-// fraction x(u) = x_-(Gamma), and the hydrogen column down to u is
+// binned spectrum (attenuation table sp) after a far column Nf: the
+// polychromatic near slab.  With HI column u below the surface the rate is
+// Gamma(Nf + u), the neutral fraction x(u) = x_-(Gamma), and the hydrogen
+// column down to u is
 // H(u) = int_0^u du' / x(u'); the bottom is where H = Nn.  The march takes
 // steps that lower ln Gamma by about 1/2 (6-point Gauss-Legendre on each,
 // nodes glx and weights glw on [-1, 1]); inside the step where H passes Nn,
 // Newton's method on the depth, kept to a bracket (dH/du = 1/x).  Once x is
 // within 1e-13 of x_ce, 1/x stays constant and the rest of the slab is linear.
 __device__ inline double slab_ln_rate_poly(double Nf, double Nn, double nH, double alpha,
-                                           double gcoll, const SpectrumView& sp,
+                                           double gcoll, const AttenuationTable& sp,
                                            const double* glx, const double* glw)
 {
     double sb = 0.0;

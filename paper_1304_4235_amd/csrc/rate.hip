@@ -64,6 +64,7 @@ struct RateRule {
     const double* Nn;
     double sigma1;
     double gl_x[6], gl_w[6];
+    AttenuationTable att;
 };
 
 enum { kSchemePlain = 0, kSchemeNearMono = 1, kSchemeNearPoly = 2 };
@@ -91,12 +92,11 @@ k_gamma(const double* __restrict__ N, int64_t n, int n_ray, int n_bins,
         if (SCHEME != kSchemePlain) {
             // near/far: per ray the slab of near particles lit by the radiation
             // the far particles let through
-            const SpectrumView sp{ws_rel, dsig_l2, n_bins, sigma_min, ln_ws_max};
             for (int k = 0; k < n_ray; ++k) {
                 double v;
                 if (SCHEME == kSchemeNearPoly) {
                     v = slab_ln_rate_poly(N[(int64_t)k * n + i], rule.Nn[(int64_t)k * n + i],
-                                          (double)nH_s[i], alpha[i], gcoll[i], sp, rule.gl_x,
+                                          (double)nH_s[i], alpha[i], gcoll[i], rule.att, rule.gl_x,
                                           rule.gl_w);
                 } else {
                     // one bin: ln w sigma = ln_ws_max
@@ -304,6 +304,58 @@ void gauss_legendre6(double* x, double* w)
     }
 }
 
+// Attenuation table of the current spectrum (its weighted bins): ln S and
+// d ln S / dt at kAttNodes nodes uniform in t = ln(1 + sigma_max N) up to the
+// column where the second least absorbed bin has decayed by e^-60 relative to
+// the least absorbed one.  FP64 log-sum-exp at every node.
+hipError_t build_attenuation_table(Ctx& c)
+{
+    std::vector<double> sg, lw;
+    for (size_t b = 0; b < c.sigma_host.size(); ++b) {
+        if (!(c.w_host[b] > 0.0)) continue;
+        sg.push_back(c.sigma_host[b]);
+        lw.push_back(std::log(c.w_host[b] * c.sigma_host[b]) - c.ln_ws_max);
+    }
+    const double smin = c.sigma_min;
+    double smax = smin, s2 = INFINITY;
+    for (double v : sg) {
+        smax = std::max(smax, v);
+        if (v > smin * (1.0 + 1e-12)) s2 = std::min(s2, v);
+    }
+    const double n_sat = std::isfinite(s2) ? 60.0 / (s2 - smin) : 0.0;
+    const int m = kAttNodes;
+    const double tmax = std::log1p(n_sat * smax);
+    const double dt = tmax > 0.0 ? tmax / (m - 1) : 1.0;
+    std::vector<double> tab(2 * (size_t)m);
+    for (int i = 0; i < m; ++i) {
+        const double N = std::expm1(i * dt) / smax;
+        double mx = -INFINITY;
+        for (size_t b = 0; b < sg.size(); ++b) mx = std::max(mx, lw[b] - (sg[b] - smin) * N);
+        double S = 0.0, D = 0.0;
+        for (size_t b = 0; b < sg.size(); ++b) {
+            const double e = std::exp(lw[b] - (sg[b] - smin) * N - mx);
+            S += e;
+            D += (sg[b] - smin) * e;
+        }
+        tab[2 * i] = mx + std::log(S);
+        tab[2 * i + 1] = -(D / S) * (1.0 + N * smax) / smax;    // d ln S / dt
+    }
+    void* d = nullptr;
+    hipError_t e = hipMalloc(&d, sizeof(double) * tab.size());
+    if (e != hipSuccess) return e;
+    e = hipMemcpy(d, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(d);
+        return e;
+    }
+    c.att_tab = static_cast<double*>(d);
+    c.att_m = tmax > 0.0 ? m : 1;
+    c.att_dt = dt;
+    c.att_tmax = tmax;
+    c.att_smax = smax;
+    return hipSuccess;
+}
+
 }  // namespace
 
 hipError_t launch_init_state(Ctx& c, bool use_given)
@@ -328,6 +380,16 @@ hipError_t launch_gamma(Ctx& c, bool update_x, bool first_sweep)
     gauss_legendre6(rule.gl_x, rule.gl_w);
     const int scheme = !c.near_far ? kSchemePlain : c.n_bins == 1 ? kSchemeNearMono
                                                                   : kSchemeNearPoly;
+    rule.att = AttenuationTable{};
+    if (scheme == kSchemeNearPoly) {
+        if (!c.att_tab) {
+            hipError_t e = build_attenuation_table(c);
+            if (e != hipSuccess) return e;
+        }
+        rule.att = AttenuationTable{reinterpret_cast<const double2*>(c.att_tab), c.att_m,
+                                    c.att_dt, c.att_tmax, c.att_smax, c.sigma_min,
+                                    c.ln_ws_max};
+    }
     auto launch = [&](auto kernel) {
         hipLaunchKernelGGL(kernel, dim3(nblk(c.n)), dim3(kBlock), 0, c.stream, c.N_s, c.n,
                            c.n_ray, c.n_bins, c.ws_rel, c.dsig_l2, c.sigma_min, c.ln_ws_max,

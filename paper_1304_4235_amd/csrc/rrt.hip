@@ -413,6 +413,7 @@ void rrt_destroy(rrt_ctx* x)
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (c.red_host) (void)hipHostFree(c.red_host);
+    if (c.att_tab) (void)hipFree(c.att_tab);
     ev_flush(c);
     if (c.ev_open) c.ev_free.push_back(c.ev_open);
     c.ev_open = nullptr;
@@ -595,6 +596,9 @@ int rrt_set_spectrum(rrt_ctx* x, int32_t n_bins, const double* sigma, const doub
     c.ws_max = wsmax;
     c.gamma_thin = thin;
     c.sigma_host.assign(sigma, sigma + n_bins);
+    c.w_host.assign(w, w + n_bins);
+    if (c.att_tab) (void)hipFree(c.att_tab);     // tabulated for the old spectrum
+    c.att_tab = nullptr;
     c.all_bins_weighted = (m == n_bins);
     c.have_spectrum = true;
     c.have_gamma = false;

@@ -313,8 +313,11 @@ __device__ __forceinline__ void wave_sync()
 // wave descends or skips.  A lane only tests the particles of leaves its own
 // ray's box test accepted, and sees them in depth-first order, so every lane's
 // hits, counts and recorded paths equal those of its own walk.
+// Six waves per SIMD (measured: the count and record passes run 4.5% faster on
+// the 2.1M-particle field than at the four that ~100 VGPRs would allow, with
+// a few registers spilled to scratch).
 template <int MODE>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, 6)
 k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
              const float* __restrict__ mux, const double* __restrict__ dirs,
              const KernelTables* __restrict__ tabs, TraceGeom g, RayOut out)
