@@ -414,6 +414,10 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
         }
         int node = sroot;
         while (node < send) {
+            // the wave walks one node sequence: keep the index in a scalar
+            // register so the node is read with scalar loads and the slab
+            // test takes its bounds from scalar registers
+            node = __builtin_amdgcn_readfirstlane(node);
             const Node nd = nodes[node];
             const int skip = __float_as_int(nd.a.w);
             const int leafw = __float_as_int(nd.b.w);
