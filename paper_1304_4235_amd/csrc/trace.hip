@@ -350,7 +350,10 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
     const double rp[3] = {(double)P.x, (double)P.y, (double)P.z};
     const double u[3] = {dirs[3 * k], dirs[3 * k + 1], dirs[3 * k + 2]};
     const double L = g.L, B = g.box;
-    const float Lf = (float)L;
+    // converted once: the empty asm keeps the compiler from converting L again
+    // (and canonicalising it) at every node of the walk
+    float Lf = (float)L;
+    asm volatile("" : "+v"(Lf));
     const int64_t gid = (int64_t)k * g.n + ps;
 
     int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
