@@ -126,6 +126,35 @@ constexpr uint32_t kNearBit = 0x80000000u;
 // d = (r_j - r_p) + s B ; s_par = d.u ; t = clamp(s_par, 0, L) ; c = d - t u ;
 // hit <=> |c|^2 < h^2.
 #pragma clang fp contract(off)
+// K/h^2 of one intersection: the chord integral of the kernel (eq. Gt) in
+// units of h, over h^2.  sp = d.u locates the point of the ray nearest the
+// particle, b2 is the squared impact parameter and h2 = h^2, all FP64; hf = h.
+// A segment that spans the whole sphere takes the full-chord table; one that
+// starts or ends inside it takes the Gaussian and erf tables with z clipped
+// to [0, L].  0 for a tangent touch.  Reciprocals and the square root are the
+// hardware's single instructions (about 1 ulp): the factor is an FP32 value
+// whose table evaluation rounds several times anyway.
+__device__ __forceinline__ float chord_factor(double sp, double b2, double h2, double L,
+                                              float hf, const float4* __restrict__ t_full,
+                                              const float4* __restrict__ t_gauss,
+                                              const float4* __restrict__ t_erf)
+{
+    const double l2 = h2 - b2;
+    if (!(l2 > 0.0)) return 0.0f;
+    const float ih2 = __builtin_amdgcn_rcpf((float)h2);
+    const float wq = fminf((float)l2 * ih2, 1.0f);
+    const float lh = __builtin_amdgcn_sqrtf(wq);
+    const double Lr = L - sp;
+    if (sp >= 0.0 && sp * sp >= l2 && Lr >= 0.0 && Lr * Lr >= l2)
+        return ih2 * (lh * tab_eval(t_full, wq));
+    const float ih = __builtin_amdgcn_rcpf(hf);
+    const float z1 = fmaxf((float)(-sp) * ih, -lh);
+    const float z2 = fminf((float)Lr * ih, lh);
+    if (!(z2 > z1)) return 0.0f;
+    const float q2 = fminf((float)b2 * ih2, 1.0f);
+    return ih2 * (tab_eval(t_gauss, q2) * (erf_t_odd(t_erf, z2) - erf_t_odd(t_erf, z1)));
+}
+
 template <int MODE>
 __global__ void __launch_bounds__(256)
 k_trace(const Node* __restrict__ nodes, const float4* __restrict__ p4,
@@ -250,29 +279,9 @@ k_trace(const Node* __restrict__ nodes, const float4* __restrict__ p4,
                     }
                     double px = d0 - sp * u[0], py = d1 - sp * u[1], pz = d2 - sp * u[2];
                     double b2 = px * px + py * py + pz * pz;
-                    double l2 = h2 - b2;
-                    // factor K/h^2 of this intersection (0 for a tangent touch)
-                    float gk = 0.0f;
-                    if (l2 > 0.0) {
-                        const float ih2 = 1.0f / (float)h2;
-                        const float wq = fminf((float)l2 * ih2, 1.0f);
-                        const double Lr = L - sp;
-                        float K;
-                        if (sp >= 0.0 && sp * sp >= l2 && Lr >= 0.0 && Lr * Lr >= l2) {
-                            K = sqrtf(wq) * tab_eval(t_full, wq);
-                        } else {
-                            const float ih = 1.0f / Q.w;
-                            const float lh = sqrtf(wq);
-                            const float z1 = fmaxf((float)(-sp) * ih, -lh);
-                            const float z2 = fminf((float)Lr * ih, lh);
-                            const float q2 = fminf((float)b2 * ih2, 1.0f);
-                            K = z2 > z1 ? tab_eval(t_gauss, q2) *
-                                              (erf_t_odd(t_erf, z2) - erf_t_odd(t_erf, z1))
-                                        : 0.0f;
-                        }
-                        gk = ih2 * K;
-                    }
-                    const bool near = out.near_far && (d0 * d0 + d1 * d1 + d2 * d2) < h2;
+                    const float gk = chord_factor(sp, b2, h2, L, Q.w, t_full, t_gauss, t_erf);
+                    bool near = false;
+                    if (out.near_far) near = (d0 * d0 + d1 * d1 + d2 * d2) < h2;
                     if (MODE == kModePath) {
                         const uint32_t bits = (uint32_t)__float_as_int(gk) | (near ? kNearBit : 0u);
                         if (w < out.hit_cap) out.path[w] = make_int2(j, (int)bits);
@@ -472,31 +481,14 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
                 double hj = (double)Q.w;
                 double h2 = hj * hj;
                 const bool in = D2 < h2;
-                const bool near = out.near_far && (d0 * d0 + d1 * d1 + d2 * d2) < h2;
+                // the near test only for the near/far split (a uniform branch)
+                bool near = false;
+                if (out.near_far) near = (d0 * d0 + d1 * d1 + d2 * d2) < h2;
                 float gk = 0.0f;
                 if (kTerms && in) {
                     double px = d0 - sp * u[0], py = d1 - sp * u[1], pz = d2 - sp * u[2];
                     double b2 = px * px + py * py + pz * pz;
-                    double l2 = h2 - b2;
-                    if (l2 > 0.0) {
-                        const float ih2 = 1.0f / (float)h2;
-                        const float wq = fminf((float)l2 * ih2, 1.0f);
-                        const double Lr = L - sp;
-                        float K;
-                        if (sp >= 0.0 && sp * sp >= l2 && Lr >= 0.0 && Lr * Lr >= l2) {
-                            K = sqrtf(wq) * tab_eval(t_full, wq);
-                        } else {
-                            const float ih = 1.0f / Q.w;
-                            const float lh = sqrtf(wq);
-                            const float z1 = fmaxf((float)(-sp) * ih, -lh);
-                            const float z2 = fminf((float)Lr * ih, lh);
-                            const float q2 = fminf((float)b2 * ih2, 1.0f);
-                            K = z2 > z1 ? tab_eval(t_gauss, q2) *
-                                              (erf_t_odd(t_erf, z2) - erf_t_odd(t_erf, z1))
-                                        : 0.0f;
-                        }
-                        gk = ih2 * K;
-                    }
+                    gk = chord_factor(sp, b2, h2, L, Q.w, t_full, t_gauss, t_erf);
                 }
                 s_in[wv][t] = in ? (near ? 2 : 1) : 0;
                 s_gk[wv][t] = gk;

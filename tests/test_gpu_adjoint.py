@@ -68,12 +68,17 @@ def test_adjoint_vs_gpu_central_differences(paths):
         fd = (_gpu_loss(s, wp, nH0, K, lnG_t, c_x) - _gpu_loss(s, wm, nH0, K, lnG_t, c_x)) / (2 * h)
         _say("w", b, dw[b], fd)
         assert abs(dw[b] - fd) <= 2e-3 * abs(fd) + 1e-4 * np.max(np.abs(dw)) 
-    # densities: step of the FP32 representation near 1e-3 relative
+    # densities: relative step 1e-2 (in FP32).  The forward rounds mu x and
+    # the chord factors to FP32, so the loss moves by a few of its ulps whenever
+    # any rounding flips; for a low-density particle a 1e-3 step leaves that
+    # noise at several percent of the difference (measured: 948 / 967 / 977.6
+    # at steps 1e-3 / 3e-3 / 1e-2 against an adjoint of 976.3), while the
+    # central difference's own error at 1e-2 is far below the tolerance.
     scale = np.max(np.abs(dn))
     big = np.argsort(-np.abs(dn))[:4]
     for j in list(rng.choice(wl.n, 6, replace=False)) + list(big):
-        up = np.float32(nH0[j] * (1 + 1e-3))
-        dn_ = np.float32(nH0[j] * (1 - 1e-3))
+        up = np.float32(nH0[j] * (1 + 1e-2))
+        dn_ = np.float32(nH0[j] * (1 - 1e-2))
         npl, nmi = nH0.copy(), nH0.copy()
         npl[j], nmi[j] = up, dn_
         fd = (_gpu_loss(s, w0, npl, K, lnG_t, c_x) - _gpu_loss(s, w0, nmi, K, lnG_t, c_x)) / \
