@@ -334,7 +334,9 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
     __shared__ float4 tab[3 * kTabIntervals];
     // per wave: the hit rays of the current leaf, and its (ray, particle) results
     __shared__ uint8_t s_lane[kWavesPerBlock][64];
-    __shared__ uint8_t s_in[kWavesPerBlock][64 * kLeafMax];
+    // per hit ray of the current leaf: bit q set when the ray hits the leaf's
+    // particle q, bit 8 + q when that hit is near
+    __shared__ unsigned int s_mask[kWavesPerBlock][64];
     __shared__ float s_gk[kWavesPerBlock][64 * kLeafMax];
     constexpr bool kTerms = MODE != kModeCount;
     if (kTerms) {
@@ -449,13 +451,16 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
             // pairs are spread over all 64 lanes, so a leaf that few of the
             // wave's rays reach costs few wave instructions.  A pair's lane
             // takes its ray's origin from the ray's lane and evaluates the
-            // canonical predicate and the chord factor; each ray then takes
-            // its particles' results in particle order, exactly as if it had
-            // looped over them itself.
+            // canonical predicate and the chord factor, and sets the pair's
+            // bit in its ray's hit mask; each ray then takes its hits in
+            // particle order, exactly as if it had looped over them itself.
             const uint64_t hm = __ballot(hit);
             const int k_hit = __popcll(hm);
             const int rank = __popcll(hm & lt_mask);
-            if (hit) s_lane[wv][rank] = (uint8_t)lane;
+            if (hit) {
+                s_lane[wv][rank] = (uint8_t)lane;
+                s_mask[wv][rank] = 0u;
+            }
             wave_sync();
             const int pairs = k_hit * c;
             for (int base = 0; base < pairs; base += 64) {
@@ -490,18 +495,18 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
                     double b2 = px * px + py * py + pz * pz;
                     gk = chord_factor(sp, b2, h2, L, Q.w, t_full, t_gauss, t_erf);
                 }
-                s_in[wv][t] = in ? (near ? 2 : 1) : 0;
-                s_gk[wv][t] = gk;
+                if (in) atomicOr(&s_mask[wv][t - q * k_hit], (near ? 0x101u : 1u) << q);
+                if (kTerms) s_gk[wv][t] = gk;
             }
             wave_sync();
             if (hit) {
-                for (int q = 0; q < c; ++q) {
-                    const int t = q * k_hit + rank;
-                    if (!s_in[wv][t]) continue;
+                const unsigned int m = s_mask[wv][rank];
+                if (MODE == kModeCount) cnt += __popc(m & 0xffu);
+                for (unsigned int hb = MODE == kModeCount ? 0u : m & 0xffu; hb; hb &= hb - 1) {
+                    const int q = __ffs(hb) - 1;
                     const int j = f + q;
-                    const float gk = s_gk[wv][t];
+                    const float gk = s_gk[wv][q * k_hit + rank];
                     ++cnt;
-                    if (MODE == kModeCount) continue;
                     if (MODE == kModeRecord) {
                         if (w < out.hit_cap) {
                             out.hit_j[w] = out.perm[j];
@@ -509,7 +514,7 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
                         }
                         ++w;
                     }
-                    const bool near = s_in[wv][t] == 2;
+                    const bool near = (m >> (8 + q)) & 1u;
                     if (MODE == kModePath) {
                         const uint32_t bits = (uint32_t)__float_as_int(gk) | (near ? kNearBit : 0u);
                         if (w < out.hit_cap) out.path[w] = make_int2(j, (int)bits);
