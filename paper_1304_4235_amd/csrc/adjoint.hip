@@ -28,9 +28,11 @@ constexpr int kBlock = 256;
 inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 // One thread per particle (tree order) at step k: the adjoint of ln Gamma, of
-// x and of every ray's column.  Pass 1 forms ln Gamma as the forward rate
-// kernel does and keeps each ray's S and T (FP32) for pass 2; the weights'
-// gradient is accumulated by k_adj_wbins from pis and ell.
+// x and of every ray's column.  Pass 1 forms ln Gamma from the same terms as
+// the forward rate kernel (hardware 2^x), summed in one FP32 accumulator
+// instead of four, so the two agree to FP32 rounding; it keeps each ray's S
+// and T for pass 2.  The weights' gradient is accumulated by k_adj_wbins from
+// pis and ell.
 __global__ void __launch_bounds__(256)
 k_adj_rate(const double* __restrict__ N, int64_t n, int n_ray, int n_bins,
            const float* __restrict__ ws_rel, const float* __restrict__ dsig_l2,
@@ -42,14 +44,14 @@ k_adj_rate(const double* __restrict__ N, int64_t n, int n_ray, int n_bins,
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
-    // pass 1: ln Gamma exactly as the forward rate kernel forms it
+    // pass 1: ln Gamma
     double m = -INFINITY, s = 0.0;
     for (int k = 0; k < n_ray; ++k) {
         const double Nk = N[(int64_t)k * n + i];
         const float Nf = (float)Nk;
         float S = 0.f, T = 0.f;
         for (int b = 0; b < n_bins; ++b) {
-            const float e = ws_rel[b] * exp2f(-dsig_l2[b] * Nf);
+            const float e = ws_rel[b] * __builtin_amdgcn_exp2f(-dsig_l2[b] * Nf);
             S += e;
             T = fmaf(e, srat[b], T);
         }
@@ -130,7 +132,7 @@ k_adj_wbins(const double* __restrict__ N, const double* __restrict__ pis,
             const int m = (int)(i1 - ib < 64 ? i1 - ib : 64);
             for (int q = 0; q < m; ++q) {
                 const double w = sW[wv][q];
-                if (w != 0.0) acc += w * (double)exp2f(-ds * sN[wv][q]);
+                if (w != 0.0) acc += w * (double)__builtin_amdgcn_exp2f(-ds * sN[wv][q]);
             }
             adj_wave_sync();
         }
