@@ -368,6 +368,31 @@ def test_bad_input_is_rejected():
         s.compute_columns()
 
 
+def test_empty_and_degenerate_arguments_are_rejected():
+    """Empty inputs are errors at the boundary, not silent no-ops: no particles,
+    no rays, no bins; so are a non-unit direction, a non-positive cross-section,
+    a negative weight and a spectrum whose optically thin rate is zero."""
+    from paper_1304_4235_amd import RRTError, Solver
+    s = Solver(10.0)
+    e = np.zeros(0, np.float32)
+    with pytest.raises(RRTError, match="RRT_E_ARG"):
+        s.set_particles(np.zeros((0, 3), np.float32), e, e, e, e)
+    for dirs in (np.zeros((0, 3)), np.array([[1.0, 1.0, 0.0]])):
+        with pytest.raises(RRTError, match="RRT_E_ARG"):
+            s.set_rays(dirs)
+    for sigma, w in [([], []), ([-6e-18], [1.0]), ([6e-18], [-1.0]), ([6e-18, 1e-18], [0.0, 0.0]),
+                     ([6e-18], [np.nan])]:
+        with pytest.raises(RRTError, match="RRT_E_ARG"):
+            s.set_spectrum(np.array(sigma, float), np.array(w, float))
+    # the context still works after the rejected calls
+    wl = _tiny([(1.0, 2.0, 3.0), (1.5, 2.0, 3.0)], [2.0, 2.0])
+    t = Solver.from_workload(wl)
+    N, hits = t.compute_columns()
+    assert hits > 0 and np.all(np.isfinite(N.cpu().numpy()))
+    t.close()
+    s.close()
+
+
 # ---------------------------------------------------------------------------
 # recorded paths vs traversal
 # ---------------------------------------------------------------------------
