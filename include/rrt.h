@@ -173,9 +173,11 @@ int rrt_update_equilibrium(rrt_ctx* ctx, double* x_out, double* max_dx_out);
  * solved per ray (the bottom is where the hydrogen column, the integral of
  * 1/x over the HI column, reaches the near column; 6-point Gauss-Legendre
  * steps and Newton's method, with the spectrum's attenuation tabulated once
- * per spectrum), in place of the paper's 4-D table of the same function.  Gamma = (1/n_ray) sum_k Gamma_k (eq. gammashld).  Recorded paths are dropped when the scheme changes.  While it is
- * set, rrt_forward, rrt_backward, rrt_iterate_halos and update rules other
- * than the default return RRT_E_STATE.  0 (default): the plain scheme. */
+ * per spectrum), in place of the paper's 4-D table of the same function.
+ * Gamma = (1/n_ray) sum_k Gamma_k (eq. gammashld).  Recorded paths are
+ * dropped when the scheme changes.  While it is set, rrt_forward,
+ * rrt_backward, rrt_iterate_halos and update rules other than the default
+ * return RRT_E_STATE.  0 (default): the plain scheme. */
 int rrt_set_scheme(rrt_ctx* ctx, int32_t near_far);
 
 /* Near total-hydrogen columns of the last rrt_compute_columns under the
@@ -242,9 +244,9 @@ int rrt_forward(rrt_ctx* ctx, int32_t K, double* lnG_out, double* x_out);
 /* Gradients of a scalar loss through the last rrt_forward, given its
  * derivatives with respect to the outputs (device, input order, nullable =
  * zero): dL_dlnG double[n], dL_dx double[n].  RRT_E_STATE unless rrt_forward
- * ran after the last change of spectrum, rays, tree or densities.  Writes dL_dw (host double
- * [n_bins], the spectrum as given; every w_b must be > 0) and dL_dnH (device
- * double[n], input order).  The transposed column product uses the recorded
+ * ran after the last change of spectrum, rays, tree or densities.  Writes
+ * dL_dw (host double[n_bins], the spectrum as given; every w_b must be > 0)
+ * and dL_dnH (device double[n], input order).  The transposed column product uses the recorded
  * paths, or re-traverses the tree when they are not recorded; it accumulates
  * with FP64 atomics, so dL_dnH can differ between runs in the last bits. */
 int rrt_backward(rrt_ctx* ctx, const double* dL_dlnG, const double* dL_dx, double* dL_dw,
@@ -335,9 +337,10 @@ int rrt_get_hits(rrt_ctx* ctx, int64_t cap, int64_t* row_off, int32_t* hit_j,
  *   [8] columns from row tiles           [9] number of those launches
  *   [10] row-tile builds                 [11] distinct particles summed over
  *                                             the row tiles (-1 when none)
- * Timing is recorded only after rrt_enable_timing(ctx, 1); each timed phase
- * synchronises the stream.  Phases of a batched solve replayed from a graph
- * are not timed. */
+ * Timing is recorded only after rrt_enable_timing(ctx, 1): a pair of events
+ * on the context's stream around each timed phase, resolved (and the stream
+ * synchronised) by rrt_get_timing, so timing adds no synchronisation between
+ * launches.  Phases of a batched solve replayed from a graph are not timed. */
 int rrt_enable_timing(rrt_ctx* ctx, int32_t on);
 int rrt_get_timing(rrt_ctx* ctx, double* out12);
 int rrt_reset_timing(rrt_ctx* ctx);
