@@ -76,12 +76,13 @@ struct TraceGeom {
     int32_t n_nodes;
 };
 
-// Table of cubic pieces on [0, 1]: piece i covers [i/256, (i+1)/256], value
-// c.x + c.y u + c.z u^2 + c.w u^3 in the local coordinate u.
+// The kernel chord integral's pieces: erf as a table of cubic pieces on
+// [0, 1] (piece i covers [i/256, (i+1)/256], value c.x + c.y u + c.z u^2 +
+// c.w u^3 in the local coordinate u), and the Gaussian's two constants.
 struct KernelTables {
-    float4 chord_full[kTabIntervals];   // G(w) = F(q)/sqrt(w), w = 1 - q^2
-    float4 gauss[kTabIntervals];        // E(q^2) = C exp(-t^2 q^2)
     float4 erf_t[kTabIntervals];        // erf(t zeta), zeta in [0, 1]
+    double gauss_c;                     // C = N h^3 sqrt(pi) / (2 t)
+    double gauss_a;                     // t^2 log2(e): exp(-t^2 q^2) = 2^(-a q^2)
 };
 
 struct Ctx {

@@ -15,7 +15,8 @@
 // z2/h) in units of h: for the truncated Gaussian (eq. Gt) the closed form
 // I(h,b,z1,z2) = (N h^3 sqrt(pi) / (2t)) e^{-t^2 q^2} [erf(t z2/h) - erf(t z1/h)] / h^2
 // with t = A h = 2 pi^(1/6), q = b/h, z clipped to the sphere and to [0, L].
-// The three one-dimensional factors come from cubic tables staged in LDS.
+// erf comes from a table of cubic pieces staged in LDS; the Gaussian from the
+// hardware 2^x with its exponent formed in FP64.
 #include "internal.h"
 
 #include <climits>
@@ -38,21 +39,6 @@ KConst kconst()
     double t = 2.0 * std::pow(pi, 1.0 / 6.0);
     double nh3 = (8.0 / pi) / (std::erf(t) - 2.0 * t * std::exp(-t * t) / std::sqrt(pi));
     return {t, nh3 * std::sqrt(pi) / (2.0 * t)};
-}
-
-// erf(t sqrt(w)) / sqrt(w): a power series in w near 0 (no 0/0), direct above.
-double erf_over_sqrt(double t, double w)
-{
-    const double pi = 3.14159265358979323846;
-    if (w < 0.01) {
-        double s = 0.0, term = t;   // t^(2n+1) w^n (-1)^n / n!
-        for (int k = 0; k < 30; ++k) {
-            s += term / (2 * k + 1);
-            term *= -t * t * w / (k + 1);
-        }
-        return 2.0 / std::sqrt(pi) * s;
-    }
-    return std::erf(t * std::sqrt(w)) / std::sqrt(w);
 }
 
 template <typename F>
@@ -127,32 +113,38 @@ constexpr uint32_t kNearBit = 0x80000000u;
 // hit <=> |c|^2 < h^2.
 #pragma clang fp contract(off)
 // K/h^2 of one intersection: the chord integral of the kernel (eq. Gt) in
-// units of h, over h^2.  sp = d.u locates the point of the ray nearest the
-// particle, b2 is the squared impact parameter and h2 = h^2, all FP64; hf = h.
-// A segment that spans the whole sphere takes the full-chord table; one that
-// starts or ends inside it takes the Gaussian and erf tables with z clipped
-// to [0, L].  0 for a tangent touch.  Reciprocals and the square root are the
-// hardware's single instructions (about 1 ulp): the factor is an FP32 value
-// whose table evaluation rounds several times anyway.
+// units of h, over h^2, C e^{-t^2 q^2} [erf(t z2) - erf(t z1)] / h^2.  sp = d.u
+// locates the point of the ray nearest the particle, b2 is the squared impact
+// parameter and h2 = h^2, all FP64; hf = h.  z1, z2 are the chord's ends in
+// units of h, clipped to the sphere and to the segment [0, L].  0 for a
+// tangent touch.
+//  * The Gaussian: the exponent -a q^2 (a = t^2 log2 e, q^2 = b2 / h2) is
+//    formed in FP64; its integer part is applied exactly and its fraction by
+//    the hardware 2^x (about 1 ulp).
+//  * erf from the LDS table; a chord that spans the whole sphere (z1 = -z2)
+//    needs one lookup, erf being odd.
+//  * Reciprocals and the square root are the hardware's single instructions
+//    (about 1 ulp).
 __device__ __forceinline__ float chord_factor(double sp, double b2, double h2, double L,
-                                              float hf, const float4* __restrict__ t_full,
-                                              const float4* __restrict__ t_gauss,
-                                              const float4* __restrict__ t_erf)
+                                              float hf, const float4* __restrict__ t_erf,
+                                              double gc, double ga)
 {
     const double l2 = h2 - b2;
     if (!(l2 > 0.0)) return 0.0f;
     const float ih2 = __builtin_amdgcn_rcpf((float)h2);
-    const float wq = fminf((float)l2 * ih2, 1.0f);
-    const float lh = __builtin_amdgcn_sqrtf(wq);
-    const double Lr = L - sp;
-    if (sp >= 0.0 && sp * sp >= l2 && Lr >= 0.0 && Lr * Lr >= l2)
-        return ih2 * (lh * tab_eval(t_full, wq));
+    const float lh = __builtin_amdgcn_sqrtf(fminf((float)l2 * ih2, 1.0f));
     const float ih = __builtin_amdgcn_rcpf(hf);
     const float z1 = fmaxf((float)(-sp) * ih, -lh);
-    const float z2 = fminf((float)Lr * ih, lh);
+    const float z2 = fminf((float)(L - sp) * ih, lh);
     if (!(z2 > z1)) return 0.0f;
-    const float q2 = fminf((float)b2 * ih2, 1.0f);
-    return ih2 * (tab_eval(t_gauss, q2) * (erf_t_odd(t_erf, z2) - erf_t_odd(t_erf, z1)));
+    const double e = -ga * (b2 / h2);
+    const double en = floor(e);
+    const float g = (float)gc * ldexpf(__builtin_amdgcn_exp2f((float)(e - en)), (int)en);
+    const float e2 = erf_t_odd(t_erf, z2);
+    float e1;
+    if (z1 == -z2) e1 = -e2;
+    else e1 = erf_t_odd(t_erf, z1);
+    return ih2 * (g * (e2 - e1));
 }
 
 template <int MODE>
@@ -161,16 +153,13 @@ k_trace(const Node* __restrict__ nodes, const float4* __restrict__ p4,
         const float* __restrict__ mux, const double* __restrict__ dirs,
         const KernelTables* __restrict__ tabs, TraceGeom g, RayOut out)
 {
-    __shared__ float4 tab[3 * kTabIntervals];
+    __shared__ float4 t_erf[kTabIntervals];
     constexpr bool kTerms = MODE != kModeCount;
     if (kTerms) {
-        const float4* src = reinterpret_cast<const float4*>(tabs);
-        for (int i = threadIdx.x; i < 3 * kTabIntervals; i += blockDim.x) tab[i] = src[i];
+        for (int i = threadIdx.x; i < kTabIntervals; i += blockDim.x) t_erf[i] = tabs->erf_t[i];
         __syncthreads();
     }
-    const float4* t_full = tab;
-    const float4* t_gauss = tab + kTabIntervals;
-    const float4* t_erf = tab + 2 * kTabIntervals;
+    const double gc = tabs->gauss_c, ga = tabs->gauss_a;
 
     const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t n_rays = (int64_t)g.n * g.n_ray;
@@ -279,7 +268,7 @@ k_trace(const Node* __restrict__ nodes, const float4* __restrict__ p4,
                     }
                     double px = d0 - sp * u[0], py = d1 - sp * u[1], pz = d2 - sp * u[2];
                     double b2 = px * px + py * py + pz * pz;
-                    const float gk = chord_factor(sp, b2, h2, L, Q.w, t_full, t_gauss, t_erf);
+                    const float gk = chord_factor(sp, b2, h2, L, Q.w, t_erf, gc, ga);
                     bool near = false;
                     if (out.near_far) near = (d0 * d0 + d1 * d1 + d2 * d2) < h2;
                     if (MODE == kModePath) {
@@ -331,7 +320,7 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
              const float* __restrict__ mux, const double* __restrict__ dirs,
              const KernelTables* __restrict__ tabs, TraceGeom g, RayOut out)
 {
-    __shared__ float4 tab[3 * kTabIntervals];
+    __shared__ float4 t_erf[kTabIntervals];
     // per wave: the hit rays of the current leaf, and its (ray, particle) results
     __shared__ uint8_t s_lane[kWavesPerBlock][64];
     // per hit ray of the current leaf: bit q set when the ray hits the leaf's
@@ -340,13 +329,10 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
     __shared__ float s_gk[kWavesPerBlock][64 * kLeafMax];
     constexpr bool kTerms = MODE != kModeCount;
     if (kTerms) {
-        const float4* src = reinterpret_cast<const float4*>(tabs);
-        for (int i = threadIdx.x; i < 3 * kTabIntervals; i += blockDim.x) tab[i] = src[i];
+        for (int i = threadIdx.x; i < kTabIntervals; i += blockDim.x) t_erf[i] = tabs->erf_t[i];
         __syncthreads();
     }
-    const float4* t_full = tab;
-    const float4* t_gauss = tab + kTabIntervals;
-    const float4* t_erf = tab + 2 * kTabIntervals;
+    const double gc = tabs->gauss_c, ga = tabs->gauss_a;
 
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
@@ -493,7 +479,7 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
                 if (kTerms && in) {
                     double px = d0 - sp * u[0], py = d1 - sp * u[1], pz = d2 - sp * u[2];
                     double b2 = px * px + py * py + pz * pz;
-                    gk = chord_factor(sp, b2, h2, L, Q.w, t_full, t_gauss, t_erf);
+                    gk = chord_factor(sp, b2, h2, L, Q.w, t_erf, gc, ga);
                 }
                 if (in) atomicOr(&s_mask[wv][t - q * k_hit], (near ? 0x101u : 1u) << q);
                 if (kTerms) s_gk[wv][t] = gk;
@@ -550,11 +536,9 @@ void fill_kernel_tables(KernelTables* host)
 {
     const KConst kc = kconst();
     const double t = kc.t, C = kc.C;
-    fit_cubics(host->chord_full, [&](double w) {
-        return 2.0 * C * std::exp(-t * t * (1.0 - w)) * erf_over_sqrt(t, w);
-    });
-    fit_cubics(host->gauss, [&](double q2) { return C * std::exp(-t * t * q2); });
     fit_cubics(host->erf_t, [&](double z) { return std::erf(t * z); });
+    host->gauss_c = C;
+    host->gauss_a = t * t / std::log(2.0);
 }
 
 template <int MODE>
