@@ -339,12 +339,14 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
     const uint64_t lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
     const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     const int64_t waves_per_dir = (g.n + 63) / 64;
-    const int k = (int)(wave / waves_per_dir);
+    // the wave's direction and image range are uniform: scalar registers
+    const int k = __builtin_amdgcn_readfirstlane((int)(wave / waves_per_dir));
     if (k >= g.n_ray) return;                                // whole wave
     const int ps = (int)((wave - (int64_t)k * waves_per_dir) * 64 + lane);
     const bool active = ps < g.n;
     const float4 P = p4[active ? ps : g.n - 1];
-    const double rp[3] = {(double)P.x, (double)P.y, (double)P.z};
+    // the ray's origin: FP32 inputs, widened exactly where FP64 needs them
+    const float rpf[3] = {P.x, P.y, P.z};
     const double u[3] = {dirs[3 * k], dirs[3 * k + 1], dirs[3 * k + 2]};
     const double L = g.L, B = g.box;
     // converted once: the empty asm keeps the compiler from converting L again
@@ -357,8 +359,9 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
     int ulo[3] = {0, 0, 0}, uhi[3] = {0, 0, 0};
     if (B > 0.0) {
         for (int a = 0; a < 3; ++a) {
-            double e = rp[a] + L * u[a];
-            double smin = rp[a] < e ? rp[a] : e, smax = rp[a] < e ? e : rp[a];
+            const double r = (double)rpf[a];
+            double e = r + L * u[a];
+            double smin = r < e ? r : e, smax = r < e ? e : r;
             lo[a] = (int)ceil((smin - g.hmax - g.phi[a]) / B - 1e-6);
             hi[a] = (int)floor((smax + g.hmax - g.plo[a]) / B + 1e-6);
             int l = active ? lo[a] : INT_MAX, h = active ? hi[a] : INT_MIN;
@@ -366,8 +369,8 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
                 l = min(l, __shfl_xor(l, off, 64));
                 h = max(h, __shfl_xor(h, off, 64));
             }
-            ulo[a] = l;
-            uhi[a] = h;
+            ulo[a] = __builtin_amdgcn_readfirstlane(l);
+            uhi[a] = __builtin_amdgcn_readfirstlane(h);
         }
     }
     float inv[3];
@@ -408,7 +411,7 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
         if (!(B > 0.0)) sh[0] = sh[1] = sh[2] = 0.0;
         float oai[3], obi[3];
         for (int a = 0; a < 3; ++a) {
-            double o = rp[a] - sh[a];
+            double o = (double)rpf[a] - sh[a];
             oai[a] = (float)(o + (double)g.pad) * inv[a];
             obi[a] = (float)(o - (double)g.pad) * inv[a];
         }
@@ -454,9 +457,9 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
                 const bool act = t < pairs;
                 const int q = act ? t / k_hit : 0;
                 const int owner = act ? (int)s_lane[wv][t - q * k_hit] : lane;
-                const double o0 = __shfl(rp[0], owner, 64);
-                const double o1 = __shfl(rp[1], owner, 64);
-                const double o2 = __shfl(rp[2], owner, 64);
+                const double o0 = (double)__shfl(rpf[0], owner, 64);
+                const double o1 = (double)__shfl(rpf[1], owner, 64);
+                const double o2 = (double)__shfl(rpf[2], owner, 64);
                 if (!act) continue;
                 const int j = f + q;
                 const float4 Q = p4[j];
