@@ -223,6 +223,42 @@ def test_full_halo_sampled_sources():
         x = xn.cpu().numpy()
 
 
+def _halo_of(wl, h):
+    a, b = int(wl.halo_offsets[h]), int(wl.halo_offsets[h + 1])
+    part = W.Workload(name=f"{wl.name}_halo{h}", pos=wl.pos[a:b], h=wl.h[a:b], mu=wl.mu[a:b],
+                      n_H=wl.n_H[a:b], T=wl.T[a:b], dirs=wl.dirs, sigma=wl.sigma, w=wl.w,
+                      l_ray=wl.l_ray, box=wl.box, tol=wl.tol, max_iter=wl.max_iter)
+    return part, a
+
+
+def test_full_batch_sampled_sources():
+    """The 64-halo batch at full size (7.1M particles), solved in one context
+    with the launch knobs the autotuner picks for it: the final state's
+    columns, rates and next update, on sampled sources of the smallest, the
+    largest and two other halos, against the oracle fed that halo's state."""
+    wl = W.make_config(3)
+    s = _solver(wl)
+    s.set_tuning(trace_block=256, packet=64, path_group=32)
+    r = s.iterate_halos(wl.max_iter, wl.tol, per_launch=16)
+    assert r["converged"]
+    _say("full batch: iterations per halo", r["halo_iters"].min(), "to", r["halo_iters"].max())
+    x = r["x"].cpu().numpy()
+    N, _ = s.compute_columns()
+    lnG, _, _ = s.compute_gamma()
+    xn, _ = s.update_equilibrium()
+    N, lnG, xn = N.cpu().numpy(), lnG.cpu().numpy(), xn.cpu().numpy()
+    sizes = np.diff(wl.halo_offsets)
+    rng = np.random.default_rng(4)
+    for h in sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), 7, 40}):
+        part, a = _halo_of(wl, h)
+        src = np.sort(rng.choice(part.n, 4, replace=False))
+        _say("full batch: halo", h, "of", part.n, "particles, sources", src)
+        ref = oracle.step(part, x[a:a + part.n], sources=src)
+        _check_columns(N[a + src], ref["N"])
+        _check_rates(lnG[a + src], ref["lnG"], ref["tau"])
+        _check_x(xn[a + src], ref["x_new"])
+
+
 # ---------------------------------------------------------------------------
 # periodic lognormal field: 48 rays, many bins, fixed iteration count
 # ---------------------------------------------------------------------------
