@@ -21,6 +21,7 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 GCC_FLAGS = ["-O2", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
              "-Wall"]
+KPC_CM = 3.0856775814913673e21          # 1 kpc in cm (IAU 2012 au, parsec by definition)
 
 
 def build(force: bool = True) -> str:
@@ -545,6 +546,26 @@ def slab_depth_analytic(x, x0, x_ce, nH, sigma):
     t = (1.0 / x0 - 1.0 / x) + np.log(x * (1.0 - x0) / (x0 * (1.0 - x))) + \
         (1.0 / x_ce) * np.log(x * (x_ce - x0) / (x0 * (x_ce - x)))
     return t / (nH * sigma)
+
+
+def plane_slab_profile(sigma, w, nH, T, depth, n_points=4000):
+    """Neutral fraction and HI column against depth in a uniform plane slab lit
+    on one face by the binned spectrum (w, sigma): at every depth the gas is
+    in equilibrium with the radiation the HI above it lets through (the
+    reference of the paper's slab tests, Sec. 5.1, for any spectrum).  The rate
+    at total hydrogen column t below the surface is the bottom rate of
+    slab_lnG_poly with no far column; for one bin that is the analytic slab of
+    Appendix C.4.  depth in kpc.  Returns (z in kpc at n_points + 1 even steps,
+    x, N_HI from the surface in cm^-2 by the trapezoid rule in t)."""
+    T = float(T)
+    a = float(alpha_A(np.array([T]))[0])
+    g = float(gamma_coll(np.array([T]))[0])
+    z = np.linspace(0.0, float(depth), n_points + 1)
+    t = z * nH * KPC_CM
+    lnG = np.array([slab_lnG_poly(sigma, w, 0.0, nH, a, g, tt) for tt in t]).ravel()
+    x = xeq(np.exp(lnG), np.full_like(t, nH), np.full_like(t, a), np.full_like(t, g))
+    NHI = np.concatenate([[0.0], np.cumsum(0.5 * (x[1:] + x[:-1]) * np.diff(t))])
+    return z, x, NHI
 
 
 def slab_numerical(Gamma0, nH, T, sigma, depth, n_slices):

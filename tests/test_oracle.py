@@ -815,3 +815,45 @@ def test_reference_tree_query_finds_brute_force_hits():
                 node = node + 1 if (ok and t["count"][node] == 0) else t["skip"][node]
             want = set(inv[hj[off[i * 12 + k]: off[i * 12 + k + 1]]].tolist())
             assert want <= reached
+
+
+# ---------------------------------------------------------------------------
+# plane-slab reference profile (the reference of the slab tests, Sec. 5.1)
+# ---------------------------------------------------------------------------
+def test_plane_slab_profile_one_bin_is_the_analytic_slab():
+    """For one bin the profile's x(z) is Appendix C.4's analytic slab: the
+    analytic depth of each profile x equals its z; the surface takes the thin
+    rate's root and the far side is neutral."""
+    nH, T = 1.5e-3, 1e4
+    sig, w = W.grey_spectrum(1e-12)
+    depth = 200.0
+    z, x, NHI = oracle.plane_slab_profile(sig, w, nH, T, depth, n_points=600)
+    a, g = oracle.alpha_A(np.array([T]))[0], oracle.gamma_coll(np.array([T]))[0]
+    x_ce = a / (a + g)
+    x0 = oracle.xeq(1e-12, nH, a, g)
+    assert abs(x[0] - x0) <= 1e-12 * x0
+    sel = (x > 2 * x0) & (x < 0.99 * x_ce)
+    assert sel.sum() > 20
+    za = oracle.slab_depth_analytic(x[sel], x0, x_ce, nH, sig[0]) / oracle.KPC_CM
+    assert np.max(np.abs(za - z[sel])) < 1e-6 * depth
+    assert x[-1] > 0.99 * x_ce
+    # the HI column is the integral of x over the hydrogen column
+    assert np.all(np.diff(NHI) > 0)
+    t = z * nH * oracle.KPC_CM
+    assert abs(NHI[-1] - np.trapezoid(x, t)) <= 1e-12 * NHI[-1]
+
+
+def test_plane_slab_profile_power_law_is_monotone_and_harder():
+    """Eight power-law bins: x rises monotonically with depth from the thin
+    rate's root, and the front lies deeper than for one bin at 13.6 eV with the
+    same thin rate (harder photons penetrate further)."""
+    nH, T, depth = 1.5e-3, 1e4, 200.0
+    sig, w = W.power_law_spectrum(8, 1.5, 1e-12)
+    z, x, _ = oracle.plane_slab_profile(sig, w, nH, T, depth, n_points=400)
+    a, g = oracle.alpha_A(np.array([T]))[0], oracle.gamma_coll(np.array([T]))[0]
+    assert abs(x[0] - oracle.xeq(1e-12, nH, a, g)) <= 1e-12 * x[0]
+    assert np.all(np.diff(x) > 0)
+    sg, wg = W.grey_spectrum(1e-12)
+    zg, xg, _ = oracle.plane_slab_profile(sg, wg, nH, T, depth, n_points=400)
+    half = 0.5 * a / (a + g)
+    assert np.interp(half, x, z) > np.interp(half, xg, zg) + 20.0
