@@ -568,6 +568,67 @@ def plane_slab_profile(sigma, w, nH, T, depth, n_points=4000):
     return z, x, NHI
 
 
+# ---------------------------------------------------------------------------
+# spherically symmetric reference (the spherical solver of the halo test, Sec. 5.3)
+# ---------------------------------------------------------------------------
+def _lse(v, axis, wts=None):
+    m = np.max(v, axis=axis, keepdims=True)
+    e = np.exp(v - m)
+    if wts is not None:
+        e = e * wts
+    return (m + np.log(np.sum(e, axis=axis, keepdims=True))).squeeze(axis)
+
+
+def sphere_columns(r, mu, nH_of_r, x_of_r, r_max, l_ray, n_s=1200):
+    """HI columns N[i, j] (cm^-2) of rays of length l_ray (kpc) from radius r[i]
+    in the direction at cos(angle) mu[j] to the outward radial direction,
+    through gas of density nH_of_r(R) and neutral fraction x_of_r(R) out to
+    r_max (midpoint rule with n_s steps along the ray)."""
+    ds = l_ray / n_s
+    s = (np.arange(n_s) + 0.5) * ds
+    r3, m3, s3 = r[:, None, None], mu[None, :, None], s[None, None, :]
+    R = np.sqrt(np.maximum(r3 ** 2 + s3 ** 2 + 2.0 * r3 * s3 * m3, 0.0))
+    f = np.where(R <= r_max, nH_of_r(R) * x_of_r(R), 0.0)
+    return np.sum(f, axis=-1) * ds * KPC_CM
+
+
+def spherical_profile(n_peak, r_core, r_max, T, sigma, w, l_ray, n_sh=120, n_mu=32,
+                      n_s=1200, tol=1e-6, max_iter=1000):
+    """Equilibrium neutral fraction of the cored isothermal sphere n_H = n_peak
+    / (1 + (r/r_core)^2), r <= r_max, in an isotropic binned background (w,
+    sigma): shells log-spaced in r from 0.01 kpc, rays of length l_ray from
+    each shell over n_mu Gauss-Legendre directions in cos(angle) (the axial
+    symmetry does the azimuth), the rate of a shell the direction-weighted
+    mean of sum_b w_b sigma_b e^{-sigma_b N} in the log domain, and x = x_- of
+    that rate, iterated from the thin state until max |dx| < tol (Jacobi).
+    Returns (r in kpc, x, iterations)."""
+    r = np.geomspace(0.01, r_max, n_sh)
+    mu, wmu = np.polynomial.legendre.leggauss(n_mu)
+    wmu = wmu / 2.0
+    Tv = np.array([float(T)])
+    a, g = float(alpha_A(Tv)[0]), float(gamma_coll(Tv)[0])
+    nH_of_r = lambda R: n_peak / (1.0 + (R / r_core) ** 2)
+    nH_r = nH_of_r(r)
+    sg, ww = np.asarray(sigma, np.float64), np.asarray(w, np.float64)
+    lws = np.log(ww * sg)
+    lr = np.log(r)
+    one = np.ones(n_sh)
+    x = xeq(np.full(n_sh, np.sum(ww * sg)), nH_r, a * one, g * one)
+    for it in range(max_iter):
+        xr = x
+        N = sphere_columns(r, mu, nH_of_r,
+                           lambda R: np.interp(np.log(np.maximum(R, r[0])), lr, xr),
+                           r_max, l_ray, n_s)
+        lnS = _lse(lws[None, None, :] - sg[None, None, :] * N[:, :, None], axis=2)
+        lnG = _lse(lnS, axis=1, wts=wmu[None, :])
+        xn = xeq(np.exp(lnG), nH_r, a * one, g * one)
+        d = np.max(np.abs(xn - x))
+        x = xn
+        if d < tol:
+            break
+    return r, x, it + 1
+
+
 def slab_numerical(Gamma0, nH, T, sigma, depth, n_slices):
     """Monochromatic plane-parallel radiation on a uniform slab, solved slice by
     slice from the surface inwards (the slab solver of Sec. 5.1): the HI optical

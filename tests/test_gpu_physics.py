@@ -81,3 +81,50 @@ def test_one_sided_slab_plain_scheme_is_over_neutral():
     ratio = np.median(x[m]) / np.median(np.interp(depth[m], z, xr))
     _say("plain scheme: lit face", np.median(x[m]), "against", np.median(np.interp(depth[m], z, xr)))
     assert ratio > 100.0
+
+
+def _halo_errors(wl, near_far, r_ref, x_ref):
+    from paper_1304_4235_amd import Solver
+    s = Solver.from_workload(wl)
+    s.set_scheme(near_far)
+    r = s.iterate(300, 1e-4)
+    assert r["iters"] < 300
+    x = r["x"].cpu().numpy()
+    s.close()
+    rp = np.linalg.norm(wl.pos.astype(np.float64), axis=1)
+    xr = np.exp(np.interp(np.log(rp), np.log(r_ref), np.log(x_ref)))
+    return rp, np.log10(x) - np.log10(xr)
+
+
+def test_isothermal_halo_matches_spherical_profile():
+    """The 262144-particle halo with its 12 rays and 128 bins against the
+    spherically symmetric solution of the same cored sphere (the halo test's
+    spherical solver, Sec. 5.3: 120 shells, 32 directions, the same ray
+    length).  The near/far scheme's median error per radial bin stays within
+    0.03 dex away from the ionisation front and 0.2 dex across it; the plain
+    scheme is more neutral than the near/far scheme at the front (Sec. 4.1.2)."""
+    wl = W.make_config(1)
+    m = wl.meta
+    r_ref, x_ref, its = oracle.spherical_profile(m["n_peak"], m["r_core"], m["r_max"],
+                                                 float(wl.T[0]), wl.sigma, wl.w, wl.l_ray)
+    T = np.array([float(wl.T[0])])
+    a, g = oracle.alpha_A(T)[0], oracle.gamma_coll(T)[0]
+    r_front = np.exp(np.interp(-0.5 * a / (a + g), -x_ref, np.log(r_ref)))
+    _say("spherical reference:", its, "iterations, front at", r_front, "kpc")
+    edges = np.geomspace(0.2, m["r_max"], 13)
+    med = {}
+    for near_far in (True, False):
+        rp, e = _halo_errors(wl, near_far, r_ref, x_ref)
+        front = np.abs(np.log10(rp / r_front)) < 0.2
+        med[near_far] = np.median(e[front])
+        _say("near/far" if near_far else "plain", "front region:", f"{med[near_far]:+.3f} dex")
+        if not near_far:
+            continue
+        for lo, hi in zip(edges[:-1], edges[1:]):
+            sel = (rp >= lo) & (rp < hi) & ~front
+            if sel.sum() < 30:
+                continue
+            _say(f"  r {lo:7.2f}-{hi:7.2f}: {np.median(e[sel]):+.4f} dex")
+            assert abs(np.median(e[sel])) <= 0.03
+        assert abs(med[True]) <= 0.2
+    assert med[False] > med[True] + 0.1

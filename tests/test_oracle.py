@@ -857,3 +857,39 @@ def test_plane_slab_profile_power_law_is_monotone_and_harder():
     zg, xg, _ = oracle.plane_slab_profile(sg, wg, nH, T, depth, n_points=400)
     half = 0.5 * a / (a + g)
     assert np.interp(half, x, z) > np.interp(half, xg, zg) + 20.0
+
+
+# ---------------------------------------------------------------------------
+# spherical reference (the halo test, Sec. 5.3)
+# ---------------------------------------------------------------------------
+def test_sphere_columns_uniform_sphere_chords():
+    """Columns through a uniform sphere with x = 1 are n_H times the chord from
+    the start point to the surface, -r mu + sqrt(R^2 - r^2 (1 - mu^2)), capped by
+    the ray length (midpoint rule: within one step of the edge)."""
+    R, L, nH, n_s = 50.0, 80.0, 2e-3, 4000
+    r = np.array([0.0, 10.0, 30.0, 49.0])
+    mu = np.array([-1.0, -0.6, -0.1, 0.0, 0.4, 1.0])
+    N = oracle.sphere_columns(r, mu, lambda q: np.full_like(q, nH), lambda q: np.ones_like(q),
+                              R, L, n_s)
+    chord = -r[:, None] * mu[None, :] + np.sqrt(R ** 2 - r[:, None] ** 2 * (1 - mu[None, :] ** 2))
+    want = nH * np.minimum(chord, L) * oracle.KPC_CM
+    assert np.all(np.abs(N - want) <= nH * (L / n_s) * oracle.KPC_CM * 1.0001)
+
+
+def test_spherical_profile_thin_limit_and_neutral_core():
+    """A near-empty sphere takes the thin rate's root at every radius; the
+    workload's halo is neutral in its core, ionised at its edge, and x falls
+    monotonically with radius."""
+    sig, w = W.power_law_spectrum(8, 1.5, 1e-12)
+    T = 1e4
+    a, g = oracle.alpha_A(np.array([T]))[0], oracle.gamma_coll(np.array([T]))[0]
+    r, x, _ = oracle.spherical_profile(1e-9, 1.0, 150.0, T, sig, w, 100.0, n_sh=24, n_mu=8,
+                                       n_s=200)
+    nH = 1e-9 / (1 + r ** 2)
+    want = oracle.xeq(np.full_like(r, 1e-12), nH, np.full_like(r, a), np.full_like(r, g))
+    assert np.max(np.abs(x - want) / want) < 1e-8
+    r, x, its = oracle.spherical_profile(1.0, 1.0, 150.0, T, sig, w, 100.0, n_sh=60, n_mu=16,
+                                         n_s=600)
+    assert its < 1000
+    assert x[0] > 0.99 * a / (a + g) and x[-1] < 1e-3
+    assert np.all(np.diff(x) <= 1e-12)
