@@ -174,10 +174,15 @@ int rrt_update_equilibrium(rrt_ctx* ctx, double* x_out, double* max_dx_out);
  * 1/x over the HI column, reaches the near column; 6-point Gauss-Legendre
  * steps and Newton's method, with the spectrum's attenuation tabulated once
  * per spectrum), in place of the paper's 4-D table of the same function.
- * Gamma = (1/n_ray) sum_k Gamma_k (eq. gammashld).  Recorded paths are
- * dropped when the scheme changes.  While it is set, rrt_forward,
- * rrt_backward, rrt_iterate_halos and update rules other than the default
- * return RRT_E_STATE.  0 (default): the plain scheme. */
+ * Weighting (eq. gammashld, 4 pi inside w): with near_far = 1 each ray's slab
+ * is lit by the ray's share, 1/n_ray of the far-attenuated spectrum, and
+ * Gamma = sum_k Gamma_k (exact for a plane-parallel beam, Sec. 5.1-5.2);
+ * near_far = 2 is a variant that lights each slab with the whole
+ * far-attenuated spectrum and takes Gamma = (1/n_ray) sum_k Gamma_k (exact
+ * when light arrives alike from every direction).  Recorded paths are dropped
+ * when the split is switched on or off, not between 1 and 2.  While a near/far
+ * scheme is set, rrt_forward, rrt_backward, rrt_iterate_halos and update rules
+ * other than the default return RRT_E_STATE.  0 (default): the plain scheme. */
 int rrt_set_scheme(rrt_ctx* ctx, int32_t near_far);
 
 /* Near total-hydrogen columns of the last rrt_compute_columns under the

@@ -70,10 +70,10 @@ def lib():
         L.orc_x_evolve.restype = d
         L.orc_slab_lnG.argtypes = [d, d, d, d, d, d]
         L.orc_slab_lnG.restype = d
-        L.orc_gamma_near_far.argtypes = [i64, i32, vp, vp, d, d, vp, vp, vp, vp]
+        L.orc_gamma_near_far.argtypes = [i64, i32, vp, vp, d, d, vp, vp, vp, vp, i32]
         L.orc_slab_lnG_poly.argtypes = [i32, vp, vp, d, d, d, d, d]
         L.orc_slab_lnG_poly.restype = d
-        L.orc_gamma_near_far_poly.argtypes = [i64, i32, vp, vp, i32, vp, vp, vp, vp, vp, vp, i32]
+        L.orc_gamma_near_far_poly.argtypes = [i64, i32, vp, vp, i32, vp, vp, vp, vp, vp, vp, i32, i32]
         L.orc_morton.argtypes = [i64, vp, vp]
         L.orc_lbvh.argtypes = [i64, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]
         L.orc_lbvh.restype = i64
@@ -463,9 +463,12 @@ def slab_rk4_poly(sigma, w, N_far, nH, alpha, gcoll, N_near, n_steps=4000):
     return lnG(N_far + y)
 
 
-def step_near_far(wl, x: np.ndarray, sources=None, rtol=DEFAULT_RTOL, n_threads: int = None):
+def step_near_far(wl, x: np.ndarray, sources=None, rtol=DEFAULT_RTOL, n_threads: int = None,
+                  share: bool = True):
     """One order-independent update with the near/far rate: the analytic slab
-    for one frequency bin, the polychromatic slab for several."""
+    for one frequency bin, the polychromatic slab for several.  share: each
+    ray's slab lit by the ray's share of the radiation, rates summed (the
+    paper's weighting), else lit by all of it, rates averaged (variant)."""
     src = np.arange(wl.n) if sources is None else np.asarray(sources)
     Nf, Nn, cnt = columns_near_far(wl, x, src, rtol=rtol)
     T = wl.T[src].astype(np.float64)
@@ -476,28 +479,29 @@ def step_near_far(wl, x: np.ndarray, sources=None, rtol=DEFAULT_RTOL, n_threads:
         lib().orc_gamma_near_far(src.size, wl.n_ray, _p(_c(Nf, np.float64)),
                                  _p(_c(Nn, np.float64)), float(wl.w[0]), float(wl.sigma[0]),
                                  _p(_c(nH, np.float64)), _p(_c(al, np.float64)),
-                                 _p(_c(ga, np.float64)), _p(lnG))
+                                 _p(_c(ga, np.float64)), _p(lnG), int(bool(share)))
     else:
         nt = N_THREADS if n_threads is None else n_threads
         lib().orc_gamma_near_far_poly(src.size, wl.n_ray, _p(_c(Nf, np.float64)),
                                       _p(_c(Nn, np.float64)), wl.n_bins,
                                       _p(_c(wl.sigma, np.float64)), _p(_c(wl.w, np.float64)),
                                       _p(_c(nH, np.float64)), _p(_c(al, np.float64)),
-                                      _p(_c(ga, np.float64)), _p(lnG), nt)
+                                      _p(_c(ga, np.float64)), _p(lnG), nt, int(bool(share)))
     G = np.exp(lnG)
     xn = xeq(G, nH, al, ga)
     return dict(N_far=Nf, N_near=Nn, near_hits=cnt, lnG=lnG, G=G, x_new=xn,
                 tau=math.log(gamma_thin(wl)) - lnG)
 
 
-def solve_near_far(wl, max_iter: int = None, tol: float = None, rtol=DEFAULT_RTOL):
+def solve_near_far(wl, max_iter: int = None, tol: float = None, rtol=DEFAULT_RTOL,
+                   share: bool = True):
     """The order-independent fixed point with the near/far rate, from x_thin."""
     mi = wl.max_iter if max_iter is None else max_iter
     tl = wl.tol if tol is None else tol
     x = x_thin(wl)
     xh, lh, md = [x.copy()], [], []
     for _ in range(mi):
-        r = step_near_far(wl, x, rtol=rtol)
+        r = step_near_far(wl, x, rtol=rtol, share=share)
         d = float(np.max(np.abs(r["x_new"] - x)))
         x = r["x_new"]
         xh.append(x.copy())
@@ -566,6 +570,41 @@ def plane_slab_profile(sigma, w, nH, T, depth, n_points=4000):
     x = xeq(np.exp(lnG), np.full_like(t, nH), np.full_like(t, a), np.full_like(t, g))
     NHI = np.concatenate([[0.0], np.cumsum(0.5 * (x[1:] + x[:-1]) * np.diff(t))])
     return z, x, NHI
+
+
+def two_sided_slab_profile(sigma, w, nH, T, depth, n_points=4000, tol=1e-12,
+                           max_iter=10000):
+    """Neutral fraction against height z (kpc) in a uniform plane slab lit
+    equally on both faces (the two-sided slab of Sec. 5.2): each height takes
+    half the rate the spectrum gives through the HI column below it and half
+    through the column above, sum_b w_b sigma_b e^{-sigma_b N}, and x = x_- of
+    that rate; iterated from the thin state (Jacobi, columns by the trapezoid
+    rule on n_points + 1 heights) until max |dx| < tol.  Returns (z, x,
+    N_HI below, N_HI above, iterations)."""
+    T = float(T)
+    a = float(alpha_A(np.array([T]))[0])
+    g = float(gamma_coll(np.array([T]))[0])
+    z = np.linspace(0.0, float(depth), n_points + 1)
+    dt = np.diff(z) * nH * KPC_CM
+    sg, ww = np.asarray(sigma, np.float64), np.asarray(w, np.float64)
+    lws = np.log(ww * sg)
+    one = np.ones_like(z)
+    x = xeq(np.full_like(z, np.sum(ww * sg)), nH * one, a * one, g * one)
+    for it in range(max_iter):
+        seg = 0.5 * (x[1:] + x[:-1]) * dt
+        below = np.concatenate([[0.0], np.cumsum(seg)])
+        above = below[-1] - below
+        ln_dn = _lse(lws[None, :] - sg[None, :] * below[:, None], axis=1)
+        ln_up = _lse(lws[None, :] - sg[None, :] * above[:, None], axis=1)
+        lnG = _lse(np.stack([ln_dn, ln_up], 1), axis=1) - math.log(2.0)
+        xn = xeq(np.exp(lnG), nH * one, a * one, g * one)
+        d = np.max(np.abs(xn - x))
+        x = xn
+        if d < tol:
+            break
+    seg = 0.5 * (x[1:] + x[:-1]) * dt
+    below = np.concatenate([[0.0], np.cumsum(seg)])
+    return z, x, below, below[-1] - below, it + 1
 
 
 # ---------------------------------------------------------------------------

@@ -443,24 +443,29 @@ double orc_slab_lnG(double lnG0, double nH, double alpha, double gcoll, double s
 }
 
 /* Shielded rate of the near/far scheme for a monochromatic spectrum (one bin   */
-/* w, sigma): per ray the far column attenuates the surface rate w sigma        */
-/* exp(-sigma N_far) (eq. gammafar), the slab of the near particles gives        */
-/* Gamma_k (eq. gammashldk), and Gamma = (1/N_ray) sum_k Gamma_k (eq.           */
-/* gammashld, 4 pi inside w).  ln Gamma by log-sum-exp over the rays.           */
+/* w, sigma): per ray the far column attenuates the surface rate (eq.           */
+/* gammafar) and the slab of the near particles lit by it gives Gamma_k (eq.    */
+/* gammashldk).  share = 1 (the paper's weighting, eq. gammashld's 4 pi / N_ray  */
+/* with 4 pi inside w): each slab is lit by the ray's share, (w sigma / N_ray)   */
+/* exp(-sigma N_far), and Gamma = sum_k Gamma_k.  share = 0 (variant): each slab */
+/* is lit by w sigma exp(-sigma N_far), as if the ray's radiation came from all  */
+/* directions, and Gamma = (1/N_ray) sum_k Gamma_k.  ln Gamma by log-sum-exp.    */
 void orc_gamma_near_far(int64_t n_src, int32_t n_ray, const double* N_far, const double* N_near,
                         double w, double sigma, const double* nH, const double* alpha,
-                        const double* gcoll, double* lnG)
+                        const double* gcoll, double* lnG, int32_t share)
 {
+    const double lit = share ? w * sigma / (double)n_ray : w * sigma;
+    const double mean = share ? 1.0 : 1.0 / (double)n_ray;
     for (int64_t i = 0; i < n_src; ++i) {
         double m = -INFINITY, s = 0.0;
         double* lk = (double*)malloc(sizeof(double) * n_ray);
         for (int k = 0; k < n_ray; ++k) {
-            const double l0 = log(w * sigma) - sigma * N_far[i * n_ray + k];
+            const double l0 = log(lit) - sigma * N_far[i * n_ray + k];
             lk[k] = orc_slab_lnG(l0, nH[i], alpha[i], gcoll[i], sigma, N_near[i * n_ray + k]);
             if (lk[k] > m) m = lk[k];
         }
         for (int k = 0; k < n_ray; ++k) s += exp(lk[k] - m);
-        lnG[i] = (m == -INFINITY) ? -INFINITY : m + log(s / (double)n_ray);
+        lnG[i] = (m == -INFINITY) ? -INFINITY : m + log(s * mean);
         free(lk);
     }
 }
@@ -557,30 +562,36 @@ double orc_slab_lnG_poly(int32_t n_bins, const double* sigma, const double* w, d
 }
 
 /* Near/far shielded rate for a binned spectrum: per ray the polychromatic slab */
-/* above, Gamma = (1/N_ray) sum_k Gamma_k (eq. gammashld), ln by log-sum-exp.   */
+/* above, lit by the ray's share w / N_ray of the spectrum with Gamma = sum_k    */
+/* Gamma_k (share = 1, eq. gammashld with 4 pi inside w), or by w with Gamma =   */
+/* (1/N_ray) sum_k Gamma_k (share = 0, variant); ln by log-sum-exp.             */
 void orc_gamma_near_far_poly(int64_t n_src, int32_t n_ray, const double* N_far,
                              const double* N_near, int32_t n_bins, const double* sigma,
                              const double* w, const double* nH, const double* alpha,
-                             const double* gcoll, double* lnG, int32_t n_threads)
+                             const double* gcoll, double* lnG, int32_t n_threads, int32_t share)
 {
+    const double mean = share ? 1.0 : 1.0 / (double)n_ray;
 #ifdef _OPENMP
     if (n_threads > 0) omp_set_num_threads(n_threads);
 #else
     (void)n_threads;
 #endif
+    double* lit = (double*)malloc(sizeof(double) * (size_t)n_bins);
+    for (int b = 0; b < n_bins; ++b) lit[b] = share ? w[b] / (double)n_ray : w[b];
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t i = 0; i < n_src; ++i) {
         double m = -INFINITY, s = 0.0;
         double* lk = (double*)malloc(sizeof(double) * n_ray);
         for (int k = 0; k < n_ray; ++k) {
-            lk[k] = orc_slab_lnG_poly(n_bins, sigma, w, N_far[i * n_ray + k], nH[i], alpha[i],
-                                      gcoll[i], N_near[i * n_ray + k]);
+            lk[k] = orc_slab_lnG_poly(n_bins, sigma, lit, N_far[i * n_ray + k], nH[i],
+                                      alpha[i], gcoll[i], N_near[i * n_ray + k]);
             if (lk[k] > m) m = lk[k];
         }
         for (int k = 0; k < n_ray; ++k) s += exp(lk[k] - m);
-        lnG[i] = (m == -INFINITY) ? -INFINITY : m + log(s / (double)n_ray);
+        lnG[i] = (m == -INFINITY) ? -INFINITY : m + log(s * mean);
         free(lk);
     }
+    free(lit);
 }
 
 /* ------------------------------------------------------------------------- */

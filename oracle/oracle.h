@@ -30,10 +30,10 @@ double orc_slab_lnG_poly(int32_t n_bins, const double* sigma, const double* w, d
 void orc_gamma_near_far_poly(int64_t n_src, int32_t n_ray, const double* N_far,
                              const double* N_near, int32_t n_bins, const double* sigma,
                              const double* w, const double* nH, const double* alpha,
-                             const double* gcoll, double* lnG, int32_t n_threads);
+                             const double* gcoll, double* lnG, int32_t n_threads, int32_t share);
 void orc_gamma_near_far(int64_t n_src, int32_t n_ray, const double* N_far, const double* N_near,
                         double w, double sigma, const double* nH, const double* alpha,
-                        const double* gcoll, double* lnG);
+                        const double* gcoll, double* lnG, int32_t share);
 void orc_gamma(int64_t n_src, int32_t n_ray, const double* N, int32_t n_bins,
                const double* sigma, const double* w, double* lnG, double* G, double* tau);
 double orc_alpha_A(double T);

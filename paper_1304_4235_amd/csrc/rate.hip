@@ -65,6 +65,9 @@ struct RateRule {
     double sigma1;
     double gl_x[6], gl_w[6];
     AttenuationTable att;
+    // 1: each slab lit by its ray's share, rates summed (the paper's weighting);
+    // 0: lit by the whole far-attenuated spectrum, rates averaged (variant)
+    int nf_share;
 };
 
 enum { kSchemePlain = 0, kSchemeNearMono = 1, kSchemeNearPoly = 2 };
@@ -91,7 +94,12 @@ k_gamma(const double* __restrict__ N, int64_t n, int n_ray, int n_bins,
         double m = -INFINITY, s = 0.0, l;
         if (SCHEME != kSchemePlain) {
             // near/far: per ray the slab of near particles lit by the radiation
-            // the far particles let through
+            // the far particles let through.  The paper's weighting lights each
+            // slab with the ray's share, 1/n_ray of the spectrum (eq.
+            // gammashld's 4 pi / N_ray, with 4 pi inside w), and sums the
+            // slabs' bottom rates; the variant lights it with all of it and
+            // averages them.  (The table of binned spectra carries the shift.)
+            const double ln_share = rule.nf_share ? -log((double)n_ray) : 0.0;
             for (int k = 0; k < n_ray; ++k) {
                 double v;
                 if (SCHEME == kSchemeNearPoly) {
@@ -100,7 +108,7 @@ k_gamma(const double* __restrict__ N, int64_t n, int n_ray, int n_bins,
                                           rule.gl_w);
                 } else {
                     // one bin: ln w sigma = ln_ws_max
-                    const double l0 = ln_ws_max - rule.sigma1 * N[(int64_t)k * n + i];
+                    const double l0 = ln_ws_max + ln_share - rule.sigma1 * N[(int64_t)k * n + i];
                     v = slab_ln_rate(l0, (double)nH_s[i], alpha[i], gcoll[i], rule.sigma1,
                                      rule.Nn[(int64_t)k * n + i]);
                 }
@@ -112,7 +120,8 @@ k_gamma(const double* __restrict__ N, int64_t n, int n_ray, int n_bins,
                     s += exp(v - m);
                 }
             }
-            l = (s > 0.0) ? (m + log(s / (double)n_ray)) : -INFINITY;
+            if (!rule.nf_share) s /= (double)n_ray;
+            l = (s > 0.0) ? (m + log(s)) : -INFINITY;
         } else {
             // 2^x is the hardware instruction (about 1 ulp), which flushes
             // results below 2^-126 to zero: the bin of smallest cross-section
@@ -382,6 +391,7 @@ hipError_t launch_gamma(Ctx& c, bool update_x, bool first_sweep)
     rule.relative = c.rule_relative;
     rule.Nn = c.near_far ? c.Nn_s : nullptr;
     rule.sigma1 = c.sigma_min;
+    rule.nf_share = c.near_far == 1;
     gauss_legendre6(rule.gl_x, rule.gl_w);
     const int scheme = !c.near_far ? kSchemePlain : c.n_bins == 1 ? kSchemeNearMono
                                                                   : kSchemeNearPoly;
@@ -391,9 +401,12 @@ hipError_t launch_gamma(Ctx& c, bool update_x, bool first_sweep)
             hipError_t e = build_attenuation_table(c);
             if (e != hipSuccess) return e;
         }
+        // with the paper's weighting each ray's slab is lit by its share,
+        // 1/n_ray, of the spectrum
+        const double shift = c.near_far == 1 ? std::log((double)c.n_ray) : 0.0;
         rule.att = AttenuationTable{reinterpret_cast<const double2*>(c.att_tab), c.att_m,
                                     c.att_dt, c.att_tmax, c.att_smax, c.sigma_min,
-                                    c.ln_ws_max};
+                                    c.ln_ws_max - shift};
     }
     auto launch = [&](auto kernel) {
         hipLaunchKernelGGL(kernel, dim3(nblk(c.n)), dim3(kBlock), 0, c.stream, c.N_s, c.n,

@@ -828,11 +828,14 @@ int rrt_set_scheme(rrt_ctx* x, int32_t near_far)
 {
     if (!x) return RRT_E_ARG;
     Ctx& c = x->c;
-    if (near_far != 0 && near_far != 1) return fail(c, RRT_E_ARG, "near_far must be 0 or 1");
+    if (near_far < 0 || near_far > 2) return fail(c, RRT_E_ARG, "near_far must be 0, 1 or 2");
     if (near_far == c.near_far) return RRT_OK;
+    const bool split_changes = (near_far != 0) != (c.near_far != 0);
     c.near_far = near_far;
+    c.have_gamma = false;             // the rates change; the columns only with the split
+    if (!split_changes) return RRT_OK;
     free_paths(c);                    // recorded entries carry the near flag
-    c.have_columns = c.have_gamma = false;
+    c.have_columns = false;
     if (c.n > 0 && c.have_rays) return alloc_columns(c);
     return RRT_OK;
 }

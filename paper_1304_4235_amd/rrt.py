@@ -196,9 +196,11 @@ class Solver:
         self._check(_lib.rrt_evolve(self._h, float(dt), int(n_steps), _ptr(x)), "rrt_evolve")
         return x
 
-    def set_scheme(self, near_far: bool):
-        """The paper's near/far scheme (True) or the plain scheme (False)."""
-        self._check(_lib.rrt_set_scheme(self._h, int(bool(near_far))), "rrt_set_scheme")
+    def set_scheme(self, near_far):
+        """The paper's near/far scheme (True or 1), its variant that lights each
+        ray's near slab with the whole far-attenuated spectrum (2), or the plain
+        scheme (False or 0)."""
+        self._check(_lib.rrt_set_scheme(self._h, int(near_far)), "rrt_set_scheme")
 
     def near_columns(self):
         """Near total-hydrogen columns [n, n_ray] of the last compute_columns."""

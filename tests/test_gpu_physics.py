@@ -83,10 +83,10 @@ def test_one_sided_slab_plain_scheme_is_over_neutral():
     assert ratio > 100.0
 
 
-def _halo_errors(wl, near_far, r_ref, x_ref):
+def _halo_errors(wl, scheme, r_ref, x_ref):
     from paper_1304_4235_amd import Solver
     s = Solver.from_workload(wl)
-    s.set_scheme(near_far)
+    s.set_scheme(scheme)
     r = s.iterate(300, 1e-4)
     assert r["iters"] < 300
     x = r["x"].cpu().numpy()
@@ -100,9 +100,16 @@ def test_isothermal_halo_matches_spherical_profile():
     """The 262144-particle halo with its 12 rays and 128 bins against the
     spherically symmetric solution of the same cored sphere (the halo test's
     spherical solver, Sec. 5.3: 120 shells, 32 directions, the same ray
-    length).  The near/far scheme's median error per radial bin stays within
-    0.03 dex away from the ionisation front and 0.2 dex across it; the plain
-    scheme is more neutral than the near/far scheme at the front (Sec. 4.1.2)."""
+    length), per radial bin of the median error of x:
+      * the variant weighting (each near slab lit by its ray's whole
+        far-attenuated spectrum), exact for isotropic light: within 0.03 dex
+        away from the ionisation front and 0.2 dex across it;
+      * the paper's weighting (each near slab lit by its ray's share), exact
+        for beams: within 0.03 dex in the neutral core and the thin outskirts,
+        more neutral than the sphere across the front, where each of the 12
+        slabs misses the other rays' light (the error the paper describes for
+        its halo test, Sec. 5.3);
+      * the plain scheme: more neutral at the front than the variant."""
     wl = W.make_config(1)
     m = wl.meta
     r_ref, x_ref, its = oracle.spherical_profile(m["n_peak"], m["r_core"], m["r_max"],
@@ -112,19 +119,58 @@ def test_isothermal_halo_matches_spherical_profile():
     r_front = np.exp(np.interp(-0.5 * a / (a + g), -x_ref, np.log(r_ref)))
     _say("spherical reference:", its, "iterations, front at", r_front, "kpc")
     edges = np.geomspace(0.2, m["r_max"], 13)
-    med = {}
-    for near_far in (True, False):
-        rp, e = _halo_errors(wl, near_far, r_ref, x_ref)
+    front_med = {}
+    for scheme in (2, 1, 0):
+        rp, e = _halo_errors(wl, scheme, r_ref, x_ref)
         front = np.abs(np.log10(rp / r_front)) < 0.2
-        med[near_far] = np.median(e[front])
-        _say("near/far" if near_far else "plain", "front region:", f"{med[near_far]:+.3f} dex")
-        if not near_far:
-            continue
+        front_med[scheme] = np.median(e[front])
+        _say("scheme", scheme, "front region:", f"{front_med[scheme]:+.3f} dex")
         for lo, hi in zip(edges[:-1], edges[1:]):
             sel = (rp >= lo) & (rp < hi) & ~front
             if sel.sum() < 30:
                 continue
-            _say(f"  r {lo:7.2f}-{hi:7.2f}: {np.median(e[sel]):+.4f} dex")
-            assert abs(np.median(e[sel])) <= 0.03
-        assert abs(med[True]) <= 0.2
-    assert med[False] > med[True] + 0.1
+            med = np.median(e[sel])
+            _say(f"  r {lo:7.2f}-{hi:7.2f}: {med:+.4f} dex")
+            if scheme == 2 or (scheme == 1 and (hi < 0.6 * r_front or lo > 3.5 * r_front)):
+                assert abs(med) <= 0.03
+    assert abs(front_med[2]) <= 0.2
+    assert front_med[1] > 0.1
+    assert front_med[0] > front_med[2] + 0.1
+
+
+@pytest.mark.parametrize("n_bins", [1, 8])
+def test_two_sided_slab_near_far_matches_plane_slab(n_bins):
+    """The slab lit on both faces (two rays per particle, +z and -z) against the
+    two-sided plane-slab solution: the median error of x and of both HI
+    columns to the faces, per tenth of the height and away from the lateral
+    edges and the fronts, within 0.03 and 0.1 dex."""
+    wl = W.one_sided_slab(n_bins=n_bins, faces=2)
+    D, nH, T = wl.meta["depth"], float(wl.n_H[0]), float(wl.T[0])
+    r, x, _ = _slab_state(wl, True)
+    from paper_1304_4235_amd import Solver
+    s = Solver.from_workload(wl)
+    s.set_state(torch.tensor(x))
+    N, _ = s.compute_columns()
+    N = N.cpu().numpy()
+    s.close()
+    z, xr, below, above, _ = oracle.two_sided_slab_profile(wl.sigma, wl.w, nH, T, D)
+    zp = wl.pos[:, 2].astype(np.float64)
+    ex = np.log10(x) - np.log10(np.interp(zp, z, xr))
+    e_up = np.log10(N[:, 0]) - np.log10(np.interp(zp, z, above))
+    e_dn = np.log10(N[:, 1]) - np.log10(np.interp(zp, z, below))
+    a, g = oracle.alpha_A(np.array([T]))[0], oracle.gamma_coll(np.array([T]))[0]
+    half = 0.5 * a / (a + g)
+    fronts = z[np.nonzero(np.diff(np.sign(xr - half)))[0]]
+    near_front = np.zeros(wl.n, bool)
+    for zf in fronts:
+        near_front |= np.abs(zp - zf) < np.median(wl.h)
+    use = _central(wl) & ~near_front
+    edges = np.linspace(0.0, D, 11)
+    for lo, hi in zip(edges[:-1], edges[1:]):
+        m = use & (zp >= lo) & (zp < hi)
+        if m.sum() < 20:
+            continue
+        _say(f"bins {n_bins} z {lo:5.0f}-{hi:5.0f}: x {np.median(ex[m]):+.3f} dex, "
+             f"N_HI up {np.median(e_up[m]):+.3f}, down {np.median(e_dn[m]):+.3f} dex")
+        assert abs(np.median(ex[m])) <= 0.03
+        assert abs(np.median(e_up[m])) <= 0.1 and abs(np.median(e_dn[m])) <= 0.1

@@ -893,3 +893,83 @@ def test_spherical_profile_thin_limit_and_neutral_core():
     assert its < 1000
     assert x[0] > 0.99 * a / (a + g) and x[-1] < 1e-3
     assert np.all(np.diff(x) <= 1e-12)
+
+
+def test_two_sided_slab_profile_thick_faces_are_one_sided_at_half_intensity():
+    """A slab lit on both faces and thick enough that neither face's radiation
+    crosses it: near each face the profile is the one-sided analytic slab
+    (App. C.4) lit by half the spectrum, and it is symmetric about the midplane."""
+    sig, w = W.grey_spectrum(1e-12)
+    D = 400.0
+    z, x, below, above, its = oracle.two_sided_slab_profile(sig, w, 1.5e-3, 1e4, D,
+                                                            n_points=8000)
+    assert its < 10000
+    assert np.max(np.abs(x - x[::-1]) / x) < 1e-8
+    assert np.allclose(below + above, below[-1], rtol=1e-12)
+    zs, xs, _ = oracle.plane_slab_profile(sig, 0.5 * w, 1.5e-3, 1e4, 150.0, n_points=300)
+    for xf in (np.interp(D - zs, z, x), np.interp(zs, z, x)):
+        assert np.max(np.abs(np.log10(xf) - np.log10(xs))) < 0.01
+
+
+def _near_far_lnG(n_ray, N_far, N_near, nH=1.5e-3, T=1e4, bins=1, share=1):
+    a, g = oracle.alpha_A(np.array([T]))[0], oracle.gamma_coll(np.array([T]))[0]
+    Nf = np.ascontiguousarray(N_far, np.float64)
+    Nn = np.ascontiguousarray(N_near, np.float64)
+    one = lambda v: np.array([v], np.float64)
+    out = np.zeros(1)
+    if bins == 1:
+        sig, w = W.grey_spectrum(1e-12)
+        oracle.lib().orc_gamma_near_far(1, n_ray, oracle._p(Nf), oracle._p(Nn), float(w[0]),
+                                        float(sig[0]), oracle._p(one(nH)), oracle._p(one(a)),
+                                        oracle._p(one(g)), oracle._p(out), share)
+    else:
+        sig, w = W.power_law_spectrum(bins, 1.5, 1e-12)
+        oracle.lib().orc_gamma_near_far_poly(1, n_ray, oracle._p(Nf), oracle._p(Nn), bins,
+                                             oracle._p(sig), oracle._p(w), oracle._p(one(nH)),
+                                             oracle._p(one(a)), oracle._p(one(g)),
+                                             oracle._p(out), 1, share)
+    return out[0], sig, w, a, g
+
+
+@pytest.mark.parametrize("bins", [1, 8])
+def test_near_far_rays_light_their_slabs_with_their_share(bins):
+    """eq. gammashld sums 4 pi / N_ray times each ray's slab rate: with 4 pi
+    inside w, each near slab is lit by 1/N_ray of the far-attenuated spectrum
+    and the rays' bottom rates add up.  So: the thin limit returns Gamma_thin
+    exactly; a ray that is blocked contributes nothing, and the other ray's
+    slab is the one-sided slab lit by half the spectrum (the error the paper
+    reads off its two-sided slab vanishes once one ray meets a high optical
+    depth, Sec. 5.2)."""
+    N = 3e20
+    thin, *_ = _near_far_lnG(4, [0.0] * 4, [0.0] * 4, bins=bins)
+    assert abs(thin - math.log(1e-12)) < 1e-12
+    two, sig, w, a, g = _near_far_lnG(2, [0.0, 1e30], [N, N], bins=bins)
+    if bins == 1:
+        want = oracle.slab_lnG(math.log(0.5 * w[0] * sig[0]), 1.5e-3, a, g, sig[0], N)
+    else:
+        want = oracle.slab_lnG_poly(sig, 0.5 * w, 0.0, 1.5e-3, a, g, N)
+    assert abs(two - float(want)) < 1e-9
+
+
+@pytest.mark.parametrize("bins", [1, 8])
+def test_near_far_variant_lights_each_slab_with_the_whole_spectrum(bins):
+    """The variant weighting lights every ray's near slab with the whole
+    far-attenuated spectrum and averages the rays: when every ray sees the same
+    columns (light from all directions alike) it is the one-sided slab lit by
+    the whole spectrum, where the paper's weighting gives N_ray slabs lit by
+    1/N_ray each; the thin limit is Gamma_thin in both."""
+    N = 3e20
+    thin, *_ = _near_far_lnG(4, [0.0] * 4, [0.0] * 4, bins=bins, share=0)
+    assert abs(thin - math.log(1e-12)) < 1e-12
+    iso, sig, w, a, g = _near_far_lnG(4, [1e17] * 4, [N] * 4, bins=bins, share=0)
+    paper, *_ = _near_far_lnG(4, [1e17] * 4, [N] * 4, bins=bins, share=1)
+    if bins == 1:
+        want = oracle.slab_lnG(math.log(w[0] * sig[0]) - sig[0] * 1e17, 1.5e-3, a, g, sig[0], N)
+        quarter = oracle.slab_lnG(math.log(0.25 * w[0] * sig[0]) - sig[0] * 1e17, 1.5e-3, a, g,
+                                  sig[0], N)
+    else:
+        want = oracle.slab_lnG_poly(sig, w, 1e17, 1.5e-3, a, g, N)
+        quarter = oracle.slab_lnG_poly(sig, 0.25 * w, 1e17, 1.5e-3, a, g, N)
+    assert abs(iso - float(want)) < 1e-9
+    assert abs(paper - (float(quarter) + math.log(4.0))) < 1e-9
+    assert paper < iso

@@ -261,16 +261,18 @@ def isothermal_halo(n: int = 262144, n_peak: float = 1.0, r_core: float = 1.0,
 def one_sided_slab(n_xy: int = 24, n_z: int = 32, depth: float = 200.0, n_H: float = 1.5e-3,
                    T: float = 1e4, gamma_thin: float = 1e-12, n_bins: int = 1,
                    jitter: float = 0.1, seed: int = BASE_SEED + 5, tol: float = 1e-5,
-                   max_iter: int = 400, name: str = "one_sided_slab") -> Workload:
+                   max_iter: int = 400, name: str = "one_sided_slab",
+                   faces: int = 1) -> Workload:
     """A slab of uniform n_H and T lit on one face: the setting of the paper's
     slab tests (Sec. 5.1, 5.2), with a jittered lattice standing in for its
     glass and a grey or power-law spectrum for its UV background.
 
     n_xy x n_xy x n_z particles with spacing depth / n_z fill 0 <= z <= depth
     (isolated: no periodic images).  Every particle casts one ray, along +z
-    towards the lit face at z = depth, of length 2 depth.  One bin at 13.6 eV
-    (n_bins = 1), else n_bins power-law bins (J ~ nu^-1.5), each spectrum
-    carrying the optically thin rate gamma_thin.
+    towards the lit face at z = depth, of length 2 depth; with faces = 2 a
+    second one along -z, so that both faces are lit (Sec. 5.2's two-sided
+    slab).  One bin at 13.6 eV (n_bins = 1), else n_bins power-law bins
+    (J ~ nu^-1.5), each spectrum carrying the optically thin rate gamma_thin.
     """
     rng = np.random.default_rng(seed)
     a = depth / n_z
@@ -286,10 +288,10 @@ def one_sided_slab(n_xy: int = 24, n_z: int = 32, depth: float = 200.0, n_H: flo
         sigma, w = power_law_spectrum(n_bins, 1.5, gamma_thin)
     return Workload(name=name, pos=pos, h=h, mu=mu,
                     n_H=np.full(n, n_H, dtype=np.float32), T=np.full(n, T, dtype=np.float32),
-                    dirs=np.array([[0.0, 0.0, 1.0]]), sigma=sigma, w=w,
-                    l_ray=float(2 * depth), box=0.0, tol=tol, max_iter=max_iter,
+                    dirs=np.array([[0.0, 0.0, 1.0], [0.0, 0.0, -1.0]][:faces]), sigma=sigma,
+                    w=w, l_ray=float(2 * depth), box=0.0, tol=tol, max_iter=max_iter,
                     meta=dict(recipe="one_sided_slab", spacing=a, depth=depth, n_xy=n_xy,
-                              seed=seed))
+                              seed=seed, faces=faces))
 
 
 def lognormal_field(n_grid: int = 128, box: float = 10000.0, sigma_ln: float = 1.5,
