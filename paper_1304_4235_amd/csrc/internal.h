@@ -29,6 +29,10 @@ constexpr int kTileMaxSet = 16384;
 // The column products read recorded entries in aligned groups of four, so the
 // arrays holding them are allocated with this many entries to spare.
 constexpr int kPathPad = 4;
+constexpr int kChunkLen = 32;              // entries per chunk of one-pass recording
+constexpr uint32_t kNoChunk = 0xffffffffu;
+constexpr int kPoolSlices = 1024;          // independent allocation counters
+constexpr int kCtrStride = 16;             // counters 128 bytes apart
 // column evaluations over one set of recorded paths before its row tiles are
 // built (the build costs about as much as a few evaluations)
 constexpr int kTileAfter = 8;
@@ -147,6 +151,19 @@ struct Ctx {
     int64_t path_hits = 0;        // entries in use
     bool paths_valid = false;
     bool paths_unfit = false;     // recording was tried and exceeded the budget
+    // one-pass recording: each ray's hits appended to chunks of kChunkLen
+    // entries from a pool of kPoolSlices slices, linked per row, then
+    // compacted into path
+    bool one_pass = true;
+    uint64_t pool_cap = 0;            // > 0: at most this many chunks (tests the fallback)
+    uint64_t last_total = 0;          // entries of the last recording (sizes the pool)
+    int2* pool = nullptr;             // [pool_chunks * kChunkLen]
+    uint32_t* chunk_next = nullptr;   // [pool_chunks] next chunk of the same row
+    uint32_t* row_first = nullptr;    // [pool_rows] first chunk of each row
+    unsigned long long* pool_ctr = nullptr;   // per slice (kCtrStride apart), then overflow
+    uint64_t pool_chunks = 0;         // kPoolSlices * slice_chunks
+    uint64_t slice_chunks = 0;
+    int64_t pool_rows = 0;
     uint64_t* tpath = nullptr;    // transposed paths: (factor bits << 32 | row) by particle
     uint64_t* tcol_off = nullptr; // [n + 1] start of each particle's entries
     bool tpaths_valid = false;
@@ -290,6 +307,8 @@ hipError_t scan_exclusive_u64(Ctx& c, const uint64_t* in, uint64_t* out, int64_t
 void fill_kernel_tables(KernelTables* host);
 hipError_t launch_columns(Ctx& c);
 hipError_t launch_record_paths(Ctx& c, const uint64_t* row_off, int2* path, uint64_t cap);
+hipError_t launch_record_chunks(Ctx& c, uint64_t* row_cnt);
+hipError_t launch_compact_chunks(Ctx& c);
 hipError_t launch_path_columns(Ctx& c, int group);
 void drop_graph(Ctx& c);
 hipError_t build_tiles(Ctx& c);

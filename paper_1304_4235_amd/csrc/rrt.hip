@@ -57,8 +57,11 @@ hipError_t dalloc(T** p, size_t count)
     return hipMalloc((void**)p, count * sizeof(T));
 }
 
+void free_pool(Ctx& c);
+
 void free_particles(Ctx& c)
 {
+    free_pool(c);
     void* bufs[] = {c.pos_in, c.h_in, c.mu_in, c.nH_in, c.T_in, c.x_init, c.p4, c.mu_s, c.nH_s,
                     c.mu0_s, c.nH0_s,
                     c.alpha_s, c.gcoll_s, c.x_s, c.mux_s, c.lnG_s, c.G_s, c.tau_s, c.N_s,
@@ -225,6 +228,68 @@ void free_tpaths(Ctx& c)
     c.tpaths_unfit = false;
 }
 
+// the one-pass recording's pool: kept between recordings (re-allocating tens
+// of gigabytes was measured to cost up to seconds), released with the particle
+// buffers, at rrt_destroy, when one-pass recording is switched, or when the
+// paths would not fit beside it
+void free_pool(Ctx& c)
+{
+    if (c.pool) (void)hipFree(c.pool);
+    if (c.chunk_next) (void)hipFree(c.chunk_next);
+    if (c.row_first) (void)hipFree(c.row_first);
+    c.pool = nullptr;
+    c.chunk_next = nullptr;
+    c.row_first = nullptr;
+    c.pool_chunks = c.slice_chunks = 0;
+    c.pool_rows = 0;
+}
+
+// The pool for a recording: room for 5/4 of the last recording's entries plus
+// half a chunk per row, over kPoolSlices slices.  Leaves no pool, with no
+// error, before a context's first recording, when the last one averaged 128
+// or more intersections per ray (measured on MI355X: one pass saves 17% on the
+// field's 73 per ray and costs 39% on the halo's 500, whose count pass is
+// cheap beside the chunk bookkeeping), or when it would take more than 45% of
+// the free memory; the walk then counts and records apart.
+void ensure_pool(Ctx& c, int64_t n_rows)
+{
+    uint64_t chunks;
+    if (c.pool_cap) {
+        chunks = c.pool_cap;
+    } else {
+        if (c.last_total == 0 || c.last_total >= (uint64_t)n_rows * 128) return;
+        const uint64_t entries = c.last_total / 4 * 5 + (uint64_t)n_rows * (kChunkLen / 2);
+        chunks = (entries + kChunkLen - 1) / kChunkLen;
+    }
+    const uint64_t per_slice =
+        std::min<uint64_t>((chunks + kPoolSlices - 1) / kPoolSlices, 0xfffffff0ull / kPoolSlices);
+    if (c.pool && c.slice_chunks >= per_slice && c.pool_rows >= n_rows) return;
+    free_pool(c);
+    const uint64_t total_chunks = per_slice * kPoolSlices;
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+        (void)hipGetLastError();
+        return;
+    }
+    const size_t bytes = total_chunks * (sizeof(int2) * kChunkLen + sizeof(uint32_t)) +
+                         sizeof(uint32_t) * (size_t)n_rows;
+    if (bytes > fr / 20 * 9) return;
+    hipError_t e = hipMalloc((void**)&c.pool, total_chunks * sizeof(int2) * kChunkLen);
+    if (e == hipSuccess) e = hipMalloc((void**)&c.chunk_next, total_chunks * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc((void**)&c.row_first, sizeof(uint32_t) * (size_t)n_rows);
+    if (e == hipSuccess && !c.pool_ctr)
+        e = hipMalloc((void**)&c.pool_ctr,
+                      ((size_t)kPoolSlices * kCtrStride + 1) * sizeof(unsigned long long));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        free_pool(c);
+        return;
+    }
+    c.pool_chunks = total_chunks;
+    c.slice_chunks = per_slice;
+    c.pool_rows = n_rows;
+}
+
 void free_paths(Ctx& c)
 {
     drop_graph(c);
@@ -242,28 +307,56 @@ void free_paths(Ctx& c)
 }
 
 
-// Count every ray's intersections, scan to row offsets, then record (tree index,
-// K/h^2) per intersection.  Leaves the paths invalid (and traversal in charge)
-// when they would exceed the budget.
+// Record (tree index, K/h^2) per intersection, rows in order, with row offsets.
+// One pass when the pool is there: the walk appends each ray's entries to
+// chunks of the pool and counts them, a scan gives the offsets, and the chunks
+// are compacted into the path array.  Otherwise, or when a slice of the pool
+// runs out, two passes: a count, the scan, then a record into the offsets.
+// Leaves the paths invalid (and traversal in charge) when they would exceed
+// the budget.
 int record_paths(Ctx& c)
 {
     const int64_t n_rows = c.n * (int64_t)c.n_ray;
     ev_begin(c);
     HIP_OK(dalloc(&c.row_off, (size_t)n_rows + 1));
     HIP_OK(hipMemsetAsync(c.row_off + n_rows, 0, sizeof(uint64_t), c.stream));
-    HIP_OK(launch_count_hits(c, c.row_off));
+    bool chunked = false;
+    if (c.one_pass && c.prm.traversal == 0 && c.prm.path_budget == 0) {
+        ensure_pool(c, n_rows);
+        chunked = c.pool != nullptr;
+    }
+    const size_t n_ctr = (size_t)kPoolSlices * kCtrStride + 1;
+    if (chunked) {
+        HIP_OK(hipMemsetAsync(c.pool_ctr, 0, n_ctr * sizeof(unsigned long long), c.stream));
+        HIP_OK(launch_record_chunks(c, c.row_off));
+    } else {
+        HIP_OK(launch_count_hits(c, c.row_off));
+    }
     HIP_OK(scan_exclusive_u64(c, c.row_off, c.row_off, n_rows + 1));
     uint64_t total = 0;
+    unsigned long long overflow = 0;
     HIP_OK(hipMemcpyAsync(&total, c.row_off + n_rows, sizeof total, hipMemcpyDeviceToHost,
                           c.stream));
+    if (chunked)
+        HIP_OK(hipMemcpyAsync(&overflow, c.pool_ctr + n_ctr - 1, sizeof overflow,
+                              hipMemcpyDeviceToHost, c.stream));
     HIP_OK(hipStreamSynchronize(c.stream));
+    if (overflow) chunked = false;    // a slice ran out: the counts stand, record again
     size_t budget = (size_t)c.prm.path_budget;
     if (budget == 0) {
         size_t fr = 0, tot = 0;
         HIP_OK(hipMemGetInfo(&fr, &tot));
         budget = fr / 2 + (c.path ? (size_t)c.path_cap * sizeof(int2) / 2 : 0);
+        if (c.pool && (size_t)total * sizeof(int2) > budget) {
+            // the pool itself may be what is in the way: decide without it
+            chunked = false;
+            free_pool(c);
+            HIP_OK(hipMemGetInfo(&fr, &tot));
+            budget = fr / 2 + (c.path ? (size_t)c.path_cap * sizeof(int2) / 2 : 0);
+        }
     }
     if ((size_t)total * sizeof(int2) > budget) {
+        free_pool(c);
         if (c.prm.record_paths == 1)
             return fail(c, RRT_E_NOMEM, "recorded paths need %llu bytes, budget %zu",
                         (unsigned long long)total * sizeof(int2), budget);
@@ -282,8 +375,10 @@ int record_paths(Ctx& c)
     free_tpaths(c);                  // both are derived from the previous paths
     free_tiles(c);
     c.path_evals = 0;
-    HIP_OK(launch_record_paths(c, c.row_off, c.path, total));
+    if (chunked) HIP_OK(launch_compact_chunks(c));
+    else HIP_OK(launch_record_paths(c, c.row_off, c.path, total));
     c.path_hits = (int64_t)total;
+    c.last_total = total;
     c.paths_valid = true;
     ev_end(c, &c.t_record);
     return RRT_OK;
@@ -406,6 +501,8 @@ void rrt_destroy(rrt_ctx* x)
     if (c.gstream) (void)hipStreamDestroy(c.gstream);
     if (c.ev_a) (void)hipEventDestroy(c.ev_a);
     if (c.ev_b) (void)hipEventDestroy(c.ev_b);
+    if (c.pool_ctr) (void)hipFree(c.pool_ctr);
+    c.pool_ctr = nullptr;
     void* bufs[] = {c.tables, c.red, c.dirs, c.ws, c.dsig_l2, c.ws_rel, c.srat, c.hist,
                     c.scan_tmp, c.halo_off, c.seg_root, c.seg_end, c.seg_active, c.seg_maxdx,
                     c.seg_iters, c.seg_state};
@@ -1443,6 +1540,12 @@ int rrt_set_tuning(rrt_ctx* x, int32_t key, int32_t value)
             return fail(c, RRT_E_ARG, "path group must be 0, 8, 16, 32 or 64");
         c.path_group = value;
         break;
+    case RRT_TUNE_ONE_PASS:
+        if (value < 0) return fail(c, RRT_E_ARG, "one_pass must be >= 0");
+        c.one_pass = value != 0;
+        c.pool_cap = value > 1 ? (uint64_t)value : 0;
+        free_pool(c);
+        return RRT_OK;
     case RRT_TUNE_KEEP_COLUMNS:
         if (value != 0 && value != 1) return fail(c, RRT_E_ARG, "keep_columns must be 0 or 1");
         c.keep_columns = value;

@@ -84,7 +84,10 @@ __device__ __forceinline__ float erf_t_odd(const float4* __restrict__ tb, float 
 // column: accumulate N; count: hits per ray; record: hit lists for inspection;
 // path: per hit (tree index, K/h^2) for the streaming product
 // scatter: y_j += (K/h^2) nu_ray for every hit (transposed column product)
-enum { kModeColumn = 0, kModeCount = 1, kModeRecord = 2, kModePath = 3, kModeScatter = 4 };
+// chunk: the path entries of each ray appended to pool chunks, with the counts
+// (one-pass recording; wave-cooperative walk only)
+enum { kModeColumn = 0, kModeCount = 1, kModeRecord = 2, kModePath = 3, kModeScatter = 4,
+       kModeChunk = 5 };
 
 struct RayOut {
     double* N;              // [n_ray][n] columns (column / record modes)
@@ -103,6 +106,13 @@ struct RayOut {
     int near_far;
     double* Nn;             // column mode: [n_ray][n] near total-hydrogen columns
     const double* mu;       // hydrogen content per tree index (near columns use x = 1)
+    // chunk mode: pool of chunks, their links, each row's first chunk, the
+    // per-slice allocation counters and the overflow flag after them
+    int2* pool;
+    uint32_t* chunk_next;
+    uint32_t* row_first;
+    unsigned long long* pool_ctr;
+    uint64_t slice_chunks;
 };
 
 // sign bit of a recorded factor: the hit is near (factors are >= 0)
@@ -382,6 +392,12 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
     double acc = 0.0, accn = 0.0;
     uint32_t cnt = 0;
     uint64_t w = ((MODE == kModeRecord || MODE == kModePath) && active) ? out.row_off[gid] : 0;
+    // chunk mode: the ray's current chunk, entries in it, its first chunk, and
+    // whether its slice of the pool ran out (then the ray only counts).  Waves
+    // take chunks from slice (wave mod kPoolSlices), each with its own counter.
+    uint32_t cur = kNoChunk, fill = kChunkLen, first = kNoChunk;
+    bool dropped = false;
+    const uint32_t slice = (uint32_t)(wave % kPoolSlices);
     const double nur = (MODE == kModeScatter && active) ? (double)out.nu[gid] : 0.0;
 
     // lanes of one wave can belong to two halos (at a halo boundary in tree
@@ -508,6 +524,35 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
                         const uint32_t bits = (uint32_t)__float_as_int(gk) | (near ? kNearBit : 0u);
                         if (w < out.hit_cap) out.path[w] = make_int2(j, (int)bits);
                         ++w;
+                    } else if (MODE == kModeChunk) {
+                        if (fill == kChunkLen && !dropped) {
+                            // one allocation for every lane that needs a chunk now
+                            const uint64_t need = __ballot(1);
+                            const int leader = __ffsll((unsigned long long)need) - 1;
+                            unsigned long long base = 0;
+                            if (lane == leader)
+                                base = atomicAdd(out.pool_ctr + (size_t)slice * kCtrStride,
+                                                 (unsigned long long)__popcll(need));
+                            base = __shfl(base, leader, 64);
+                            const unsigned long long local = base + __popcll(need & lt_mask);
+                            if (local < out.slice_chunks) {
+                                const uint32_t nc =
+                                    (uint32_t)(slice * out.slice_chunks + local);
+                                if (cur == kNoChunk) first = nc;
+                                else out.chunk_next[cur] = nc;
+                                cur = nc;
+                                fill = 0;
+                            } else {
+                                dropped = true;           // counted, not stored
+                                out.pool_ctr[(size_t)kPoolSlices * kCtrStride] = 1ull;
+                            }
+                        }
+                        if (!dropped) {
+                            const uint32_t bits =
+                                (uint32_t)__float_as_int(gk) | (near ? kNearBit : 0u);
+                            out.pool[(uint64_t)cur * kChunkLen + fill] = make_int2(j, (int)bits);
+                            ++fill;
+                        }
                     } else if (MODE == kModeScatter) {
                         if (nur != 0.0) unsafeAtomicAdd(out.y + j, (double)gk * nur);
                     } else if (near) {
@@ -525,13 +570,35 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
     if (active) {
         if ((MODE == kModeColumn || MODE == kModeRecord) && live) out.N[gid] = acc;
         if (MODE == kModeColumn && live && out.near_far) out.Nn[gid] = accn;
-        if (MODE == kModeCount) out.row_cnt[gid] = cnt;
+        if (MODE == kModeCount || MODE == kModeChunk) out.row_cnt[gid] = cnt;
+        if (MODE == kModeChunk) out.row_first[gid] = first;
     }
     uint64_t c64 = cnt;
     for (int off = 32; off > 0; off >>= 1) c64 += __shfl_xor(c64, off, 64);
     if (lane == 0 && c64) atomicAdd(out.hits_total, (unsigned long long)c64);
 }
 #pragma clang fp contract(on)
+
+// One-pass recording, second step: each row's entries from its chain of
+// chunks into the row-ordered path array (kChunkLen lanes per row, one chunk
+// per step).  Every row's chain holds exactly ceil(count / kChunkLen) chunks.
+__global__ void __launch_bounds__(256)
+k_compact_chunks(const uint64_t* __restrict__ row_off, const uint32_t* __restrict__ row_first,
+                 const uint32_t* __restrict__ chunk_next, const int2* __restrict__ pool,
+                 int64_t n_rows, int2* __restrict__ path)
+{
+    const int lane = threadIdx.x & (kChunkLen - 1);
+    const int64_t stride = (int64_t)gridDim.x * (blockDim.x / kChunkLen);
+    for (int64_t row = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kChunkLen;
+         row < n_rows; row += stride) {
+        const uint64_t a = row_off[row], b = row_off[row + 1];
+        uint32_t ch = row_first[row];
+        for (uint64_t e = a; e < b; e += kChunkLen) {
+            if (e + lane < b) path[e + lane] = pool[(uint64_t)ch * kChunkLen + lane];
+            if (e + kChunkLen < b) ch = chunk_next[ch];
+        }
+    }
+}
 
 }  // namespace
 
@@ -670,6 +737,36 @@ hipError_t launch_record_hits(Ctx& c, const uint64_t* row_off, int32_t* hit_j, i
     o.perm = c.perm;
     o.hits_total = c.red + 1;
     return launch_mode(c, kModeRecord, o);
+}
+
+hipError_t launch_record_chunks(Ctx& c, uint64_t* row_cnt)
+{
+    RayOut o{};
+    o.row_cnt = row_cnt;
+    o.perm = c.perm;
+    o.hits_total = c.red + 3;
+    o.near_far = c.near_far;
+    o.pool = c.pool;
+    o.chunk_next = c.chunk_next;
+    o.row_first = c.row_first;
+    o.pool_ctr = c.pool_ctr;
+    o.slice_chunks = c.slice_chunks;
+    const int bs = c.prm.block_size > 0 ? c.prm.block_size : 128;
+    const int64_t waves = ((c.n + 63) / 64) * (int64_t)c.n_ray;
+    const unsigned nb = (unsigned)((waves * 64 + bs - 1) / bs);
+    hipLaunchKernelGGL(k_trace_wave<kModeChunk>, dim3(nb), dim3(bs), 0, c.stream, c.nodes, c.p4,
+                       c.mux_s, c.dirs, c.tables, c.geom, o);
+    return hipGetLastError();
+}
+
+hipError_t launch_compact_chunks(Ctx& c)
+{
+    const int64_t n_rows = c.n * (int64_t)c.n_ray;
+    if (n_rows == 0) return hipSuccess;
+    const unsigned nb = stride_blocks(n_rows, 256 / kChunkLen);
+    hipLaunchKernelGGL(k_compact_chunks, dim3(nb), dim3(256), 0, c.stream, c.row_off,
+                       c.row_first, c.chunk_next, c.pool, n_rows, c.path);
+    return hipGetLastError();
 }
 
 hipError_t launch_record_paths(Ctx& c, const uint64_t* row_off, int2* path, uint64_t cap)

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "librrt.so")
 
 RRT_OK, RRT_NOT_CONVERGED = 0, 1
 TUNE_KEYS = {"trace_block": 1, "packet": 2, "path_group": 3, "leaf": 4, "adjoint_scatter": 5,
-             "tiles": 6, "keep_columns": 7}
+             "tiles": 6, "keep_columns": 7, "one_pass": 8}
 ERRORS = {-1: "RRT_E_ARG", -2: "RRT_E_HIP", -3: "RRT_E_INPUT", -4: "RRT_E_STATE",
           -5: "RRT_E_NOMEM", -6: "RRT_E_CAPACITY"}
 

@@ -561,3 +561,30 @@ def test_field_shard_owned_columns_equal_the_whole_field(rank):
     np.testing.assert_allclose(N_sh.cpu().numpy()[:n_own], N_full[idx[:n_own]], rtol=1e-12,
                                atol=0)
     s.close()
+
+
+@pytest.mark.parametrize("room", ["ample", "short"])
+def test_one_pass_recording_equals_two_passes(room):
+    """One-pass recording (hits appended to pool chunks, then compacted) gives
+    the same recorded paths as a counting walk followed by a recording walk:
+    bit-identical columns over them and the same counts.  The pool is capped
+    from the first recording's count so that the second recording takes one
+    pass whatever the intersections per ray; a pool of about 2000 chunks runs
+    short at once, and the recording falls back to the second walk with the
+    counts it has."""
+    wl = W.isothermal_halo(n=16384, seed=21)
+    x = np.minimum(oracle.x_thin(wl) * np.geomspace(1, 1e4, wl.n), 0.999)
+    out = []
+    for one_pass in (False, True):
+        s = _solver(wl, record_paths=1)
+        s.set_tuning(one_pass=0)
+        _, first = s.compute_columns(want_N=False)       # two walks
+        if one_pass:
+            cap = first * 3 // 64 + 4096 if room == "ample" else 2000
+            s.set_tuning(one_pass=int(cap))
+        s.build_tree()                                     # drops the paths
+        s.set_state(torch.tensor(x))
+        N, hits = s.compute_columns()
+        assert s.timing()["path_hits"] == hits == first
+        out.append(N.cpu().numpy())
+    np.testing.assert_array_equal(out[0], out[1])
