@@ -146,3 +146,21 @@ def test_field_shard_holds_everything_owned_rays_can_reach():
             reach = np.sqrt((d * d).sum(1)) <= wl.l_ray + wl.h.astype(np.float64)
             assert set(np.nonzero(reach)[0].tolist()) <= inside
     assert owned_total == wl.n
+
+
+def test_one_sided_slab_recipe():
+    """The slab of the physics checks: a jittered lattice filling 0..depth in z
+    with the stated spacing and density, one ray to the lit face (two for
+    faces = 2), rays long enough to cross the slab, and the stated thin rate."""
+    wl = W.one_sided_slab(n_xy=6, n_z=8, depth=50.0)
+    a = wl.meta["spacing"]
+    assert wl.n == 6 * 6 * 8 and a == 50.0 / 8
+    assert wl.pos[:, 2].min() > 0 and wl.pos[:, 2].max() < 50.0
+    assert np.all(np.abs(wl.pos / a - np.round(wl.pos / a - 0.5) - 0.5) <= 0.1 + 1e-5)
+    np.testing.assert_allclose(wl.mu, 1.5e-3 * a ** 3 * W.KPC_CM, rtol=1e-6)
+    np.testing.assert_array_equal(wl.dirs, [[0.0, 0.0, 1.0]])
+    assert wl.l_ray >= 50.0 and wl.box == 0.0
+    assert abs(np.sum(wl.w * wl.sigma) - 1e-12) < 1e-24
+    two = W.one_sided_slab(n_xy=6, n_z=8, depth=50.0, faces=2, n_bins=8)
+    np.testing.assert_array_equal(two.dirs, [[0.0, 0.0, 1.0], [0.0, 0.0, -1.0]])
+    assert two.n_bins == 8 and abs(np.sum(two.w * two.sigma) - 1e-12) < 1e-24
