@@ -580,22 +580,32 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
 #pragma clang fp contract(on)
 
 // One-pass recording, second step: each row's entries from its chain of
-// chunks into the row-ordered path array (kChunkLen lanes per row, one chunk
-// per step).  Every row's chain holds exactly ceil(count / kChunkLen) chunks.
+// chunks into the row-ordered path array.  Every row's chain holds exactly
+// ceil(count / kChunkLen) chunks.  The chain is a sequence of dependent loads,
+// so a row takes only kCompactLanes lanes (each copies kChunkLen /
+// kCompactLanes entries of a chunk) and a wave follows 64 / kCompactLanes
+// chains at once; the next link is loaded before the chunk is copied.
+constexpr int kCompactLanes = 8;
 __global__ void __launch_bounds__(256)
 k_compact_chunks(const uint64_t* __restrict__ row_off, const uint32_t* __restrict__ row_first,
                  const uint32_t* __restrict__ chunk_next, const int2* __restrict__ pool,
                  int64_t n_rows, int2* __restrict__ path)
 {
-    const int lane = threadIdx.x & (kChunkLen - 1);
-    const int64_t stride = (int64_t)gridDim.x * (blockDim.x / kChunkLen);
-    for (int64_t row = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kChunkLen;
+    const int lane = threadIdx.x & (kCompactLanes - 1);
+    const int64_t stride = (int64_t)gridDim.x * (blockDim.x / kCompactLanes);
+    for (int64_t row = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kCompactLanes;
          row < n_rows; row += stride) {
         const uint64_t a = row_off[row], b = row_off[row + 1];
         uint32_t ch = row_first[row];
         for (uint64_t e = a; e < b; e += kChunkLen) {
-            if (e + lane < b) path[e + lane] = pool[(uint64_t)ch * kChunkLen + lane];
-            if (e + kChunkLen < b) ch = chunk_next[ch];
+            const uint32_t nxt = e + kChunkLen < b ? chunk_next[ch] : 0u;
+            const int2* src = pool + (uint64_t)ch * kChunkLen;
+#pragma unroll
+            for (int q = 0; q < kChunkLen / kCompactLanes; ++q) {
+                const int i = q * kCompactLanes + lane;
+                if (e + i < b) path[e + i] = src[i];
+            }
+            ch = nxt;
         }
     }
 }
@@ -763,7 +773,7 @@ hipError_t launch_compact_chunks(Ctx& c)
 {
     const int64_t n_rows = c.n * (int64_t)c.n_ray;
     if (n_rows == 0) return hipSuccess;
-    const unsigned nb = stride_blocks(n_rows, 256 / kChunkLen);
+    const unsigned nb = stride_blocks(n_rows, 256 / kCompactLanes);
     hipLaunchKernelGGL(k_compact_chunks, dim3(nb), dim3(256), 0, c.stream, c.row_off,
                        c.row_first, c.chunk_next, c.pool, n_rows, c.path);
     return hipGetLastError();
