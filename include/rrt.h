@@ -305,20 +305,17 @@ int rrt_iterate_halos(rrt_ctx* ctx, int32_t max_iter, double tol, int32_t per_la
  *                         that appends each ray's entries to 32-entry chunks
  *                         of a pool and counts them, then compact the chunks
  *                         into rows; when the pool runs short, record in a
- *                         second walk as with 0.  Used when the context's
- *                         previous recording averaged fewer than 128
- *                         intersections per ray (so a context's first
- *                         recording takes two walks); the pool, sized from it
- *                         (5/4 of its entries plus half a chunk per ray), in
- *                         1024 slices with a counter each, at most 45% of the
- *                         free memory, is kept between recordings (released
- *                         with the particle buffers, at rrt_destroy, when this
- *                         knob is set, or when the paths would not fit beside
- *                         it).  0: a
+ *                         second walk as with 0.  The pool is sized from the
+ *                         context's previous recording (so its first
+ *                         recording takes two walks): 5/4 of its entries plus
+ *                         half a chunk per ray, in 1024 slices with a counter
+ *                         each, at most 45% of the free memory.  It is kept
+ *                         between recordings, and released with the particle
+ *                         buffers, at rrt_destroy, when this knob is set, or
+ *                         when the paths would not fit beside it.  0: a
  *                         counting walk, then a recording walk.  n > 1: one
- *                         pass with the pool capped near n chunks, whatever
- *                         the intersections per ray.  The same paths either
- *                         way. */
+ *                         pass with a pool of about n chunks, also on a first
+ *                         recording.  The same paths either way. */
 enum { RRT_TUNE_TRACE_BLOCK = 1, RRT_TUNE_PACKET = 2, RRT_TUNE_PATH_GROUP = 3, RRT_TUNE_LEAF = 4,
        RRT_TUNE_ADJOINT = 5, RRT_TUNE_TILES = 6, RRT_TUNE_KEEP_COLUMNS = 7,
        RRT_TUNE_ONE_PASS = 8 };

@@ -246,18 +246,15 @@ void free_pool(Ctx& c)
 
 // The pool for a recording: room for 5/4 of the last recording's entries plus
 // half a chunk per row, over kPoolSlices slices.  Leaves no pool, with no
-// error, before a context's first recording, when the last one averaged 128
-// or more intersections per ray (measured on MI355X: one pass saves 17% on the
-// field's 73 per ray and costs 39% on the halo's 500, whose count pass is
-// cheap beside the chunk bookkeeping), or when it would take more than 45% of
-// the free memory; the walk then counts and records apart.
+// error, before a context's first recording or when it would take more than
+// 45% of the free memory; the walk then counts and records apart.
 void ensure_pool(Ctx& c, int64_t n_rows)
 {
     uint64_t chunks;
     if (c.pool_cap) {
         chunks = c.pool_cap;
     } else {
-        if (c.last_total == 0 || c.last_total >= (uint64_t)n_rows * 128) return;
+        if (c.last_total == 0) return;
         const uint64_t entries = c.last_total / 4 * 5 + (uint64_t)n_rows * (kChunkLen / 2);
         chunks = (entries + kChunkLen - 1) / kChunkLen;
     }

@@ -392,12 +392,13 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
     double acc = 0.0, accn = 0.0;
     uint32_t cnt = 0;
     uint64_t w = ((MODE == kModeRecord || MODE == kModePath) && active) ? out.row_off[gid] : 0;
-    // chunk mode: the ray's current chunk, entries in it, its first chunk, and
-    // whether its slice of the pool ran out (then the ray only counts).  Waves
-    // take chunks from slice (wave mod kPoolSlices), each with its own counter.
-    uint32_t cur = kNoChunk, fill = kChunkLen, first = kNoChunk;
-    bool dropped = false;
-    const uint32_t slice = (uint32_t)(wave % kPoolSlices);
+    // chunk mode: the ray's current chunk (kNoChunk before the first, kDropped
+    // once its slice of the pool ran out: then the ray only counts) and the
+    // entries in it.  Waves take chunks from slice (wave mod kPoolSlices), each
+    // with its own counter.
+    constexpr uint32_t kDropped = kNoChunk - 1;
+    uint32_t cur = kNoChunk, fill = kChunkLen;
+    const uint32_t slice = __builtin_amdgcn_readfirstlane((uint32_t)(wave % kPoolSlices));
     const double nur = (MODE == kModeScatter && active) ? (double)out.nu[gid] : 0.0;
 
     // lanes of one wave can belong to two halos (at a halo boundary in tree
@@ -525,7 +526,7 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
                         if (w < out.hit_cap) out.path[w] = make_int2(j, (int)bits);
                         ++w;
                     } else if (MODE == kModeChunk) {
-                        if (fill == kChunkLen && !dropped) {
+                        if (fill == kChunkLen && cur != kDropped) {
                             // one allocation for every lane that needs a chunk now
                             const uint64_t need = __ballot(1);
                             const int leader = __ffsll((unsigned long long)need) - 1;
@@ -538,16 +539,16 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
                             if (local < out.slice_chunks) {
                                 const uint32_t nc =
                                     (uint32_t)(slice * out.slice_chunks + local);
-                                if (cur == kNoChunk) first = nc;
+                                if (cur == kNoChunk) out.row_first[gid] = nc;
                                 else out.chunk_next[cur] = nc;
                                 cur = nc;
                                 fill = 0;
                             } else {
-                                dropped = true;           // counted, not stored
+                                cur = kDropped;           // counted, not stored
                                 out.pool_ctr[(size_t)kPoolSlices * kCtrStride] = 1ull;
                             }
                         }
-                        if (!dropped) {
+                        if (cur != kDropped) {
                             const uint32_t bits =
                                 (uint32_t)__float_as_int(gk) | (near ? kNearBit : 0u);
                             out.pool[(uint64_t)cur * kChunkLen + fill] = make_int2(j, (int)bits);
@@ -571,7 +572,6 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
         if ((MODE == kModeColumn || MODE == kModeRecord) && live) out.N[gid] = acc;
         if (MODE == kModeColumn && live && out.near_far) out.Nn[gid] = accn;
         if (MODE == kModeCount || MODE == kModeChunk) out.row_cnt[gid] = cnt;
-        if (MODE == kModeChunk) out.row_first[gid] = first;
     }
     uint64_t c64 = cnt;
     for (int off = 32; off > 0; off >>= 1) c64 += __shfl_xor(c64, off, 64);
