@@ -33,6 +33,7 @@ constexpr int kChunkLen = 32;              // entries per chunk of one-pass reco
 constexpr uint32_t kNoChunk = 0xffffffffu;
 constexpr int kPoolSlices = 1024;          // independent allocation counters
 constexpr int kCtrStride = 16;             // counters 128 bytes apart
+constexpr int kSliceTries = 16;            // slices a chunk request tries
 // column evaluations over one set of recorded paths before its row tiles are
 // built (the build costs about as much as a few evaluations)
 constexpr int kTileAfter = 8;

@@ -393,9 +393,9 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
     uint32_t cnt = 0;
     uint64_t w = ((MODE == kModeRecord || MODE == kModePath) && active) ? out.row_off[gid] : 0;
     // chunk mode: the ray's current chunk (kNoChunk before the first, kDropped
-    // once its slice of the pool ran out: then the ray only counts) and the
-    // entries in it.  Waves take chunks from slice (wave mod kPoolSlices), each
-    // with its own counter.
+    // once the pool ran out for it: then the ray only counts) and the entries
+    // in it.  Waves take chunks from slice (wave mod kPoolSlices) first, each
+    // slice with its own counter.
     constexpr uint32_t kDropped = kNoChunk - 1;
     uint32_t cur = kNoChunk, fill = kChunkLen;
     const uint32_t slice = __builtin_amdgcn_readfirstlane((uint32_t)(wave % kPoolSlices));
@@ -527,18 +527,32 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
                         ++w;
                     } else if (MODE == kModeChunk) {
                         if (fill == kChunkLen && cur != kDropped) {
-                            // one allocation for every lane that needs a chunk now
-                            const uint64_t need = __ballot(1);
-                            const int leader = __ffsll((unsigned long long)need) - 1;
-                            unsigned long long base = 0;
-                            if (lane == leader)
-                                base = atomicAdd(out.pool_ctr + (size_t)slice * kCtrStride,
-                                                 (unsigned long long)__popcll(need));
-                            base = __shfl(base, leader, 64);
-                            const unsigned long long local = base + __popcll(need & lt_mask);
-                            if (local < out.slice_chunks) {
-                                const uint32_t nc =
-                                    (uint32_t)(slice * out.slice_chunks + local);
+                            // a chunk for every lane that needs one now: one
+                            // allocation in the wave's slice, then, for lanes it
+                            // could not serve, in further slices (stride 97,
+                            // odd, so kSliceTries distinct ones) while any has room
+                            uint64_t need = __ballot(1);
+                            bool got = false;
+                            uint32_t nc = 0;
+                            for (int t = 0; t < kSliceTries && need; ++t) {
+                                const uint32_t sl = (slice + 97u * (uint32_t)t) % kPoolSlices;
+                                const int leader = __ffsll((unsigned long long)need) - 1;
+                                unsigned long long base = 0;
+                                if (lane == leader)
+                                    base = atomicAdd(out.pool_ctr + (size_t)sl * kCtrStride,
+                                                     (unsigned long long)__popcll(need));
+                                base = __shfl(base, leader, 64);
+                                if (!got) {
+                                    const unsigned long long local =
+                                        base + __popcll(need & lt_mask);
+                                    if (local < out.slice_chunks) {
+                                        got = true;
+                                        nc = (uint32_t)(sl * out.slice_chunks + local);
+                                    }
+                                }
+                                need = __ballot(!got);
+                            }
+                            if (got) {
                                 if (cur == kNoChunk) out.row_first[gid] = nc;
                                 else out.chunk_next[cur] = nc;
                                 cur = nc;
