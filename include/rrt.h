@@ -80,8 +80,9 @@ typedef struct {
  * kernel chord factor K/h^2 of each) does not depend on x, because the column
  * is linear in the neutral fractions (Sec. 4.1.1, eq. colden).  With path
  * recording the first column evaluation after a tree build traverses the tree
- * twice (count, then record 8 bytes per intersection: particle index and
- * factor); every evaluation then forms N = sum (mu x)_j * factor_j by a
+ * and records 8 bytes per intersection (particle index and factor), in one
+ * walk or in a counting walk and a recording walk (RRT_TUNE_ONE_PASS); every
+ * evaluation then forms N = sum (mu x)_j * factor_j by a
  * streaming product over the recorded paths.  Without it, every evaluation
  * traverses the tree.  Both give the same intersections and terms; the two
  * sums differ only in summation order. */
