@@ -290,7 +290,7 @@ def main():
                                     achieved=b / (avg * 1e-3) / 1e9,
                                     build_ms_per_step=tm["tile_build_ms"] / args.steps)
     if tm["record_ms"]:
-        kernels["path_recording"] = dict(kernel="k_trace<1> + k_trace<3> (count, record)",
+        kernels["path_recording"] = dict(kernel="k_trace_wave<5> + k_compact_chunks (one walk into pool chunks, then rows; a context's first recording: k_trace_wave<1> + k_trace_wave<3>, count then record)",
                                          total_ms=tm["record_ms"],
                                          per_step_ms=tm["record_ms"] / args.steps)
     dom = max((k for k in kernels if "achieved" in kernels[k]),
