@@ -8,10 +8,12 @@ equilibrium) until max|dx| < tol.  Reported:
           (every iteration's columns sum over all intersections, periodic
           images counted separately);
   particles_per_s_per_iteration  N_p * iterations / time;
-  roofline  for the dominant kernel (traversal + column): algorithmic bytes
-          per launch (20 B per intersection: x, y, z, h, mu*x in FP32; plus
-          the 8-byte column per ray) over the average launch duration, timed
-          with HIP events on the library's stream, against 8 TB/s HBM;
+  roofline  for the dominant kernel: algorithmic bytes per launch over the
+          average launch duration, timed with HIP events on the library's
+          stream, against 8 TB/s HBM.  The product over recorded paths counts
+          8 B per intersection (particle index, K/h^2) and 16 B per ray (row
+          offset, FP64 column); the traversal without recording counts 20 B
+          per intersection (x, y, z, h, mu*x in FP32) and 8 B per ray;
   cpu_baseline  the FP64 oracle on a bounded sample of source particles of
           the same workload (the update is order-independent, so a sample of
           sources at the same state is an exact sub-problem).
