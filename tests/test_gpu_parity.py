@@ -588,3 +588,29 @@ def test_one_pass_recording_equals_two_passes(room):
         assert s.timing()["path_hits"] == hits == first
         out.append(N.cpu().numpy())
     np.testing.assert_array_equal(out[0], out[1])
+
+
+def test_full_halo_one_walk_recording():
+    """The 262144-particle halo with the default knobs, as the solve of a
+    whole step runs it: a context's second recording (one walk into the pool
+    sized from the first, chunks taken from 1024 slices) records the same
+    paths as its first (a counting walk, then a recording walk): the same
+    count, bit-identical columns, and sampled sources equal to the oracle."""
+    wl = W.make_config(1)
+    s = _solver(wl)
+    x = oracle.x_thin(wl)
+    cols = []
+    for k in range(2):
+        _say("full halo recording", k)
+        if k:
+            s.build_tree()                                 # drops the paths
+        s.set_state(torch.tensor(x))
+        N, hits = s.compute_columns()
+        assert hits == s.timing()["path_hits"]
+        cols.append((N.cpu().numpy(), hits))
+    assert cols[1][1] == cols[0][1]
+    np.testing.assert_array_equal(cols[1][0], cols[0][0])
+    src = np.sort(np.random.default_rng(5).choice(wl.n, 16, replace=False))
+    ref = oracle.step(wl, x, sources=src)
+    _check_columns(cols[1][0][src], ref["N"])
+    s.close()
