@@ -77,6 +77,9 @@ def lib():
         L.orc_morton.argtypes = [i64, vp, vp]
         L.orc_lbvh.argtypes = [i64, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]
         L.orc_lbvh.restype = i64
+        L.orc_morton_seg.argtypes = [i64, vp, i32, vp, vp]
+        L.orc_lbvh_seg.argtypes = [i64, vp, vp, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.orc_lbvh_seg.restype = i64
         _lib = L
     return _lib
 
@@ -515,14 +518,24 @@ def solve_near_far(wl, max_iter: int = None, tol: float = None, rtol=DEFAULT_RTO
 # ----------------------------------------------------------------------------
 # reference tree
 # ----------------------------------------------------------------------------
-def morton(pos: np.ndarray) -> np.ndarray:
+def morton(pos: np.ndarray, halo_offsets=None) -> np.ndarray:
+    """Tree keys in input order: Morton codes, with the halo index above them
+    when halo_offsets (H + 1 input offsets, H > 1) splits the particles into
+    independent halos."""
     pos = _c(pos, np.float32)
     out = np.zeros(pos.shape[0], np.uint64)
-    lib().orc_morton(pos.shape[0], _p(pos), _p(out))
+    if halo_offsets is None:
+        lib().orc_morton(pos.shape[0], _p(pos), _p(out))
+    else:
+        off = _c(halo_offsets, np.int64)
+        lib().orc_morton_seg(pos.shape[0], _p(pos), off.size - 1, _p(off), _p(out))
     return out
 
 
-def lbvh(pos: np.ndarray, h: np.ndarray, leaf_max: int) -> dict:
+def lbvh(pos: np.ndarray, h: np.ndarray, leaf_max: int, halo_offsets=None) -> dict:
+    """The reference tree (see oracle.c); with halo_offsets, the tree of
+    independent halos, each in a subtree of its own: seg_root / seg_end give
+    the node range [root, end) of each halo."""
     pos, h = _c(pos, np.float32), _c(h, np.float32)
     n = pos.shape[0]
     m = 2 * n
@@ -533,11 +546,18 @@ def lbvh(pos: np.ndarray, h: np.ndarray, leaf_max: int) -> dict:
     skip = np.zeros(m, np.int32)
     first = np.zeros(m, np.int32)
     count = np.zeros(m, np.int32)
-    nn = lib().orc_lbvh(n, _p(pos), _p(h), leaf_max, _p(perm), _p(codes), _p(lo), _p(hi),
-                        _p(skip), _p(first), _p(count))
+    off = None if halo_offsets is None else _c(halo_offsets, np.int64)
+    nh = 1 if off is None else off.size - 1
+    root = np.zeros(nh, np.int32)
+    end = np.zeros(nh, np.int32)
+    nn = lib().orc_lbvh_seg(n, _p(pos), _p(h), leaf_max, nh, _p(off), _p(perm), _p(codes),
+                            _p(lo), _p(hi), _p(skip), _p(first), _p(count), _p(root), _p(end))
     assert nn > 0
-    return dict(perm=perm, codes=codes, lo=lo[:nn], hi=hi[:nn], skip=skip[:nn],
-                first=first[:nn], count=count[:nn], n_nodes=int(nn))
+    out = dict(perm=perm, codes=codes, lo=lo[:nn], hi=hi[:nn], skip=skip[:nn],
+               first=first[:nn], count=count[:nn], n_nodes=int(nn))
+    if nh > 1:
+        out.update(seg_root=root, seg_end=end)
+    return out
 
 
 # ----------------------------------------------------------------------------

@@ -823,15 +823,31 @@ int orc_solve_rule(int64_t n, const float* pos, const float* h, const float* mu,
 /* Ranges of at most leaf_max particles become leaves.  Nodes are emitted in  */
 /* depth-first pre-order; skip = index of the first node after the subtree.   */
 /* Boxes are exact FP32 min/max of (r - h, r + h).                            */
+/*                                                                           */
+/* Independent halos in one tree: with H > 1 halos (particles               */
+/* [off[g], off[g+1]) of the input form halo g) the key of a particle of     */
+/* halo g is g in the bits above the Morton code, which takes               */
+/* b = floor((63 - ceil(log2 H)) / 3) bits per axis, quantised over the same */
+/* cube; and a range becomes a leaf only when it also lies in one halo.  So  */
+/* every halo owns one subtree, whose root is the topmost node whose range   */
+/* is exactly that halo's particles.                                         */
 /* ------------------------------------------------------------------------- */
-static uint64_t spread21(uint64_t v)
+static uint64_t spread_bits(uint64_t v, int bits)
 {
     uint64_t r = 0;
-    for (int i = 0; i < 21; ++i) r |= ((v >> i) & 1ull) << (3 * i);
+    for (int i = 0; i < bits; ++i) r |= ((v >> i) & 1ull) << (3 * i);
     return r;
 }
 
-void orc_morton(int64_t n, const float* pos, uint64_t* codes)
+static int halo_key_bits(int32_t n_halo)
+{
+    int hb = 0;
+    while (((int64_t)1 << hb) < (int64_t)n_halo) ++hb;     /* ceil(log2 H) */
+    return n_halo > 1 ? (63 - hb) / 3 : 21;
+}
+
+void orc_morton_seg(int64_t n, const float* pos, int32_t n_halo, const int64_t* halo_off,
+                    uint64_t* codes)
 {
     float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (int64_t j = 0; j < n; ++j)
@@ -845,17 +861,31 @@ void orc_morton(int64_t n, const float* pos, uint64_t* codes)
         double e = (double)hi[a] - (double)lo[a];
         if (e > ext) ext = e;
     }
-    double scale = ext > 0.0 ? 2097152.0 / ext : 0.0;
+    const int bits = halo_key_bits(n_halo);
+    const double cells = (double)((uint64_t)1 << bits);
+    double scale = ext > 0.0 ? cells / ext : 0.0;
+    int32_t g = 0;
     for (int64_t j = 0; j < n; ++j) {
         uint64_t q[3];
         for (int a = 0; a < 3; ++a) {
             double v = floor(((double)pos[3 * j + a] - (double)lo[a]) * scale);
             if (v < 0.0) v = 0.0;
-            if (v > 2097151.0) v = 2097151.0;
+            if (v > cells - 1.0) v = cells - 1.0;
             q[a] = (uint64_t)v;
         }
-        codes[j] = (spread21(q[0]) << 2) | (spread21(q[1]) << 1) | spread21(q[2]);
+        uint64_t key = (spread_bits(q[0], bits) << 2) | (spread_bits(q[1], bits) << 1) |
+                       spread_bits(q[2], bits);
+        if (n_halo > 1) {
+            while (g + 1 < n_halo && j >= halo_off[g + 1]) ++g;
+            key |= (uint64_t)g << (3 * bits);
+        }
+        codes[j] = key;
     }
+}
+
+void orc_morton(int64_t n, const float* pos, uint64_t* codes)
+{
+    orc_morton_seg(n, pos, 1, NULL, codes);
 }
 
 typedef struct { uint64_t code; int64_t idx; } keyidx;
@@ -872,10 +902,13 @@ typedef struct {
     const uint64_t* code;  /* sorted codes */
     const float* pos;      /* sorted positions [n][3] */
     const float* h;        /* sorted h */
+    int64_t n;
     int32_t leaf_max;
+    int halo_shift;        /* the halo field starts at this bit; 64 = one problem */
     int64_t cnt;
     float* lo; float* hi;
     int32_t* skip; int32_t* first; int32_t* count;
+    int32_t* seg_root; int32_t* seg_end;   /* per halo, or NULL */
 } tree_ctx;
 
 static int64_t split_of(const tree_ctx* c, int64_t f, int64_t l)
@@ -893,6 +926,11 @@ static int64_t split_of(const tree_ctx* c, int64_t f, int64_t l)
     return ((l >> bit) << bit) - 1;
 }
 
+static uint64_t halo_of_code(const tree_ctx* c, uint64_t code)
+{
+    return c->halo_shift >= 64 ? 0 : code >> c->halo_shift;
+}
+
 static void build_rec(tree_ctx* c, int64_t f, int64_t l)
 {
     int64_t me = c->cnt++;
@@ -906,7 +944,12 @@ static void build_rec(tree_ctx* c, int64_t f, int64_t l)
         }
     for (int a = 0; a < 3; ++a) { c->lo[3 * me + a] = lo[a]; c->hi[3 * me + a] = hi[a]; }
     int64_t n = l - f + 1;
-    if (n <= c->leaf_max) {
+    const uint64_t gf = halo_of_code(c, c->code[f]), gl = halo_of_code(c, c->code[l]);
+    /* the topmost range that is exactly one halo roots that halo's subtree */
+    const int whole_halo = gf == gl && (f == 0 || halo_of_code(c, c->code[f - 1]) != gf) &&
+                           (l == c->n - 1 || halo_of_code(c, c->code[l + 1]) != gl);
+    if (c->seg_root && whole_halo && c->seg_root[gf] < 0) c->seg_root[gf] = (int32_t)me;
+    if (n <= c->leaf_max && gf == gl) {
         c->first[me] = (int32_t)f;
         c->count[me] = (int32_t)n;
     } else {
@@ -917,20 +960,31 @@ static void build_rec(tree_ctx* c, int64_t f, int64_t l)
         build_rec(c, s + 1, l);
     }
     c->skip[me] = (int32_t)c->cnt;
+    if (c->seg_root && whole_halo && c->seg_root[gf] == (int32_t)me)
+        c->seg_end[gf] = (int32_t)c->cnt;
 }
 
 /* Outputs: perm[n] (sorted position -> original index), codes_sorted[n],
- * node arrays sized for 2n - 1 nodes.  Returns the node count. */
-int64_t orc_lbvh(int64_t n, const float* pos, const float* h, int32_t leaf_max,
-                 int32_t* perm, uint64_t* codes_sorted, float* node_lo, float* node_hi,
-                 int32_t* node_skip, int32_t* node_first, int32_t* node_count)
+ * node arrays sized for 2n - 1 nodes, and with H > 1 halos seg_root[H] and
+ * seg_end[H] (each halo's subtree is nodes [root, end)).  Returns the node
+ * count, or -1 on bad arguments. */
+int64_t orc_lbvh_seg(int64_t n, const float* pos, const float* h, int32_t leaf_max,
+                     int32_t n_halo, const int64_t* halo_off, int32_t* perm,
+                     uint64_t* codes_sorted, float* node_lo, float* node_hi, int32_t* node_skip,
+                     int32_t* node_first, int32_t* node_count, int32_t* seg_root,
+                     int32_t* seg_end)
 {
-    if (n <= 0 || leaf_max < 1) return -1;
+    if (n <= 0 || leaf_max < 1 || n_halo < 1) return -1;
+    if (n_halo > 1) {
+        if (!halo_off || halo_off[0] != 0 || halo_off[n_halo] != n) return -1;
+        for (int32_t g = 0; g < n_halo; ++g)
+            if (halo_off[g + 1] <= halo_off[g]) return -1;
+    }
     uint64_t* codes = (uint64_t*)malloc(sizeof(uint64_t) * n);
     keyidx* ki = (keyidx*)malloc(sizeof(keyidx) * n);
     float* sp = (float*)malloc(sizeof(float) * 3 * n);
     float* sh = (float*)malloc(sizeof(float) * n);
-    orc_morton(n, pos, codes);
+    orc_morton_seg(n, pos, n_halo, halo_off, codes);
     for (int64_t j = 0; j < n; ++j) { ki[j].code = codes[j]; ki[j].idx = j; }
     qsort(ki, (size_t)n, sizeof(keyidx), cmp_keyidx);
     for (int64_t i = 0; i < n; ++i) {
@@ -940,9 +994,21 @@ int64_t orc_lbvh(int64_t n, const float* pos, const float* h, int32_t leaf_max,
         sp[3 * i] = pos[3 * j]; sp[3 * i + 1] = pos[3 * j + 1]; sp[3 * i + 2] = pos[3 * j + 2];
         sh[i] = h[j];
     }
-    tree_ctx c = {codes_sorted, sp, sh, leaf_max, 0, node_lo, node_hi, node_skip, node_first,
-                  node_count};
+    const int segmented = n_halo > 1 && seg_root && seg_end;
+    if (segmented)
+        for (int32_t g = 0; g < n_halo; ++g) seg_root[g] = seg_end[g] = -1;
+    tree_ctx c = {codes_sorted, sp, sh, n, leaf_max, n_halo > 1 ? 3 * halo_key_bits(n_halo) : 64,
+                  0, node_lo, node_hi, node_skip, node_first, node_count,
+                  segmented ? seg_root : NULL, segmented ? seg_end : NULL};
     build_rec(&c, 0, n - 1);
     free(codes); free(ki); free(sp); free(sh);
     return c.cnt;
+}
+
+int64_t orc_lbvh(int64_t n, const float* pos, const float* h, int32_t leaf_max,
+                 int32_t* perm, uint64_t* codes_sorted, float* node_lo, float* node_hi,
+                 int32_t* node_skip, int32_t* node_first, int32_t* node_count)
+{
+    return orc_lbvh_seg(n, pos, h, leaf_max, 1, NULL, perm, codes_sorted, node_lo, node_hi,
+                        node_skip, node_first, node_count, NULL, NULL);
 }

@@ -53,6 +53,13 @@ int orc_solve_rule(int64_t n, const float* pos, const float* h, const float* mu,
                    int32_t n_blocks, double rtol, int32_t n_threads, double* x_hist,
                    double* lnG_hist, int32_t* skipped, int32_t* iters_done, double* maxdx_hist);
 void orc_morton(int64_t n, const float* pos, uint64_t* codes);
+void orc_morton_seg(int64_t n, const float* pos, int32_t n_halo, const int64_t* halo_off,
+                    uint64_t* codes);
+int64_t orc_lbvh_seg(int64_t n, const float* pos, const float* h, int32_t leaf_max,
+                     int32_t n_halo, const int64_t* halo_off, int32_t* perm,
+                     uint64_t* codes_sorted, float* node_lo, float* node_hi, int32_t* node_skip,
+                     int32_t* node_first, int32_t* node_count, int32_t* seg_root,
+                     int32_t* seg_end);
 int64_t orc_lbvh(int64_t n, const float* pos, const float* h, int32_t leaf_max,
                  int32_t* perm, uint64_t* codes_sorted, float* node_lo, float* node_hi,
                  int32_t* node_skip, int32_t* node_first, int32_t* node_count);

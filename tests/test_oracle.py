@@ -817,6 +817,135 @@ def test_reference_tree_query_finds_brute_force_hits():
             assert want <= reached
 
 
+def _halo_case(sizes, seed=0):
+    """Halos of the given sizes at different places, overlapping in space."""
+    rng = np.random.default_rng(seed)
+    pos, h = [], []
+    for g, m in enumerate(sizes):
+        c = rng.uniform(-20, 20, 3)
+        pos.append(c + rng.normal(0, 4 + g, (m, 3)))
+        h.append(rng.uniform(0.3, 2.5, m))
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    return np.concatenate(pos).astype(np.float32), np.concatenate(h).astype(np.float32), off
+
+
+def test_halo_keys_definition():
+    """With H halos the key is the halo index above a Morton code of
+    floor((63 - ceil(log2 H)) / 3) bits per axis over the common scene cube."""
+    pos = np.array([[0, 0, 0], [1, 1, 1], [1, 0, 0], [0, 0, 1], [0.5, 0.25, 0.75]], np.float32)
+    for H, bits in [(2, 20), (3, 20), (4, 20), (5, 20), (8, 20), (9, 19), (64, 19), (65, 18),
+                    (513, 17)]:
+        # the last particles one per halo; halos past the fifth are empty
+        off = np.array([0] + list(range(max(1, 6 - H), 5)) + [5] * max(1, H - 4), np.int64)
+        assert off.size == H + 1
+        c = oracle.morton(pos, halo_offsets=off)
+        top = (1 << bits) - 1
+
+        def spread(v):
+            return sum(((v >> i) & 1) << (3 * i) for i in range(bits))
+
+        q = np.minimum(np.floor(pos.astype(np.float64) * (1 << bits)), top).astype(np.int64)
+        for j in range(5):
+            g = int(np.searchsorted(off, j, side="right") - 1)
+            want = (g << (3 * bits)) | (spread(int(q[j, 0])) << 2) | \
+                (spread(int(q[j, 1])) << 1) | spread(int(q[j, 2]))
+            assert int(c[j]) == want, (H, j)
+    # one halo: the plain 21-bit code
+    np.testing.assert_array_equal(oracle.morton(pos, halo_offsets=[0, 5]), oracle.morton(pos))
+
+
+def test_halo_tree_with_one_halo_is_the_plain_tree():
+    pos, h = _tree_case(1000, seed=7)
+    a = oracle.lbvh(pos, h, 4)
+    b = oracle.lbvh(pos, h, 4, halo_offsets=[0, 1000])
+    for k in ("perm", "codes", "lo", "hi", "skip", "first", "count"):
+        np.testing.assert_array_equal(a[k], b[k])
+
+
+@pytest.mark.parametrize("sizes,leaf", [((300, 1, 2, 57, 640), 8), ((5, 5, 5, 5), 4),
+                                        ((1, 1), 8), ((2000, 33), 1)])
+def test_halo_tree_structure(sizes, leaf):
+    """Every halo's particles are one contiguous run of the sorted order, and
+    one subtree [seg_root, seg_end) holds exactly them; no leaf mixes halos;
+    boxes, skip links and leaf ranges as in the plain tree."""
+    pos, h, off = _halo_case(sizes)
+    t = oracle.lbvh(pos, h, leaf, halo_offsets=off)
+    n, m = pos.shape[0], t["n_nodes"]
+    perm = t["perm"]
+    assert sorted(perm.tolist()) == list(range(n))
+    halo = np.searchsorted(off, np.arange(n), side="right") - 1     # input index -> halo
+    hs = halo[perm]
+    np.testing.assert_array_equal(hs, np.sort(hs))                  # contiguous runs
+    np.testing.assert_array_equal(np.searchsorted(hs, np.arange(len(sizes))), off[:-1])
+    sp, sh = pos[perm], h[perm]
+    covered = np.zeros(n, bool)
+    for i in range(m):
+        f, c, s = t["first"][i], t["count"][i], t["skip"][i]
+        assert i < s <= m
+        if c > 0:
+            assert c <= leaf and s == i + 1
+            assert np.all(hs[f:f + c] == hs[f]), "a leaf mixes halos"
+            assert not covered[f:f + c].any()
+            covered[f:f + c] = True
+            np.testing.assert_array_equal(t["lo"][i], (sp[f:f + c] - sh[f:f + c, None]).min(0))
+            np.testing.assert_array_equal(t["hi"][i], (sp[f:f + c] + sh[f:f + c, None]).max(0))
+        else:
+            l, r = i + 1, t["skip"][i + 1]
+            assert t["skip"][r] == s
+    assert covered.all()
+    for g in range(len(sizes)):
+        a, b = t["seg_root"][g], t["seg_end"][g]
+        assert 0 <= a < b <= m and t["skip"][a] == b
+        got = []
+        for i in range(a, b):
+            if t["count"][i] > 0:
+                got.extend(range(t["first"][i], t["first"][i] + t["count"][i]))
+        assert got == list(range(off[g], off[g + 1])), f"halo {g} subtree"
+        # the root is the topmost such node: its parent's range is wider
+        if a > 0:
+            parents = [i for i in range(a) if t["count"][i] == 0 and i < a < t["skip"][i]]
+            p = max(parents)
+            assert t["skip"][p] - p > b - a
+
+
+def test_halo_tree_query_finds_each_halos_brute_force_hits():
+    """Walking halo g's subtree reaches every particle of halo g that the
+    brute-force predicate hits on a ray from a particle of halo g."""
+    sizes = (120, 7, 260)
+    pos, h, off = _halo_case(sizes, seed=5)
+    t = oracle.lbvh(pos, h, 4, halo_offsets=off)
+    dirs = W.healpix_dirs(1)
+    inv = np.empty(pos.shape[0], np.int64)
+    inv[t["perm"]] = np.arange(pos.shape[0])
+    for g in range(len(sizes)):
+        a, b = int(off[g]), int(off[g + 1])
+        wl, x = _one(pos[a:b], h[a:b], dirs=dirs, L=9.0)
+        src = np.arange(0, b - a, max(1, (b - a) // 6))
+        _, o, hj, _ = oracle.columns(wl, x, sources=src, hits=True)
+        for i, s in enumerate(src):
+            for k in range(12):
+                org = pos[a + s].astype(np.float64)
+                e = org + 9.0 * dirs[k]
+                reached, node = set(), int(t["seg_root"][g])
+                while node < t["seg_end"][g]:
+                    lo, hi = t["lo"][node], t["hi"][node]
+                    t0, t1, ok = 0.0, 1.0, True
+                    for ax in range(3):
+                        dd = e[ax] - org[ax]
+                        if abs(dd) < 1e-300:
+                            ok = ok and lo[ax] <= org[ax] <= hi[ax]
+                        else:
+                            u0, u1 = (lo[ax] - org[ax]) / dd, (hi[ax] - org[ax]) / dd
+                            t0, t1 = max(t0, min(u0, u1)), min(t1, max(u0, u1))
+                    ok = ok and t0 <= t1
+                    if ok and t["count"][node] > 0:
+                        f = t["first"][node]
+                        reached.update(range(f, f + t["count"][node]))
+                    node = node + 1 if (ok and t["count"][node] == 0) else t["skip"][node]
+                want = set(inv[a + hj[o[i * 12 + k]: o[i * 12 + k + 1]]].tolist())
+                assert want <= reached
+
+
 # ---------------------------------------------------------------------------
 # plane-slab reference profile (the reference of the slab tests, Sec. 5.1)
 # ---------------------------------------------------------------------------
