@@ -31,11 +31,19 @@
  *  - Pointers marked "device" are caller-owned device memory on the GPU the
  *    context was created on; "host" pointers are caller-owned host memory.
  *    The library copies what it keeps; it never frees caller memory.
+ *  - Device memory: the library never allocates device memory.  Every device
+ *    buffer of a context (particle arrays in tree order, tree, columns,
+ *    reductions, scratch, the reverse mode's iterates) is carved from the
+ *    workspace the caller gives with rrt_set_workspace, sized by
+ *    rrt_workspace_size; the recorded ray paths, and what is derived from
+ *    them, from the path buffer given with rrt_set_path_buffer, sized by
+ *    rrt_count_paths.  A call that finds too little room returns
+ *    RRT_E_WORKSPACE before it changes any state, and rrt_workspace_info
+ *    says how much it asked for.  Both regions stay referenced until they are
+ *    replaced or the context is destroyed.  Pinned host memory of a few bytes
+ *    is allocated for reductions.
  *  - Work is enqueued on the stream given to rrt_create (NULL = the null
  *    stream).  Calls that return a scalar to the host synchronise that stream.
- *  - The library allocates its own device buffers (tree, sorted particle
- *    arrays, columns, scratch) with hipMalloc, sized by the particle count,
- *    and releases them in rrt_destroy.
  *  - A context is not thread-safe; use one context per host thread.
  */
 #ifndef RRT_H
@@ -55,8 +63,8 @@ enum {
     RRT_E_HIP = -2,           /* HIP runtime error                             */
     RRT_E_INPUT = -3,         /* non-finite or out-of-range particle data      */
     RRT_E_STATE = -4,         /* call out of order (e.g. columns before tree)  */
-    RRT_E_NOMEM = -5,         /* device allocation failed                      */
-    RRT_E_CAPACITY = -6       /* caller buffer too small                       */
+    RRT_E_WORKSPACE = -5,     /* no workspace or path buffer, or too little room */
+    RRT_E_CAPACITY = -6       /* caller output buffer too small                */
 };
 
 typedef struct rrt_ctx rrt_ctx;
@@ -64,13 +72,12 @@ typedef struct rrt_ctx rrt_ctx;
 typedef struct {
     double l_ray;          /* ray length in kpc, >= 0 (Sec. 3.3: l_ray)              */
     double box;            /* periodic box side in kpc; 0 = isolated (no images)    */
-    int64_t path_budget;   /* bytes the recorded ray paths may take; 0 = half of the
-                              free device memory at the time of recording           */
     int32_t leaf_size;     /* max particles per tree leaf, 1..8 (0 = default 8)     */
     int32_t block_size;    /* threads per block of the traversal: 0 (= 128) or a
                               multiple of 64 up to 256                               */
-    int32_t record_paths;  /* -1 = record when within path_budget (default),
-                              0 = traverse every iteration, 1 = require recording   */
+    int32_t record_paths;  /* -1 = record when they fit in the path buffer
+                              (default), 0 = traverse every iteration, 1 = require
+                              recording (RRT_E_WORKSPACE when they do not fit)       */
     int32_t traversal;     /* 0 = wave-cooperative walk (default), 1 = one
                               independent walk per lane; identical results          */
     int32_t reserved[2];   /* must be zero                                           */
@@ -80,22 +87,82 @@ typedef struct {
  * kernel chord factor K/h^2 of each) does not depend on x, because the column
  * is linear in the neutral fractions (Sec. 4.1.1, eq. colden).  With path
  * recording the first column evaluation after a tree build traverses the tree
- * and records 8 bytes per intersection (particle index and factor), in one
- * walk or in a counting walk and a recording walk (RRT_TUNE_ONE_PASS); every
- * evaluation then forms N = sum (mu x)_j * factor_j by a
+ * and records 8 bytes per intersection (particle index and factor) into the
+ * path buffer; every evaluation then forms N = sum (mu x)_j * factor_j by a
  * streaming product over the recorded paths.  Without it, every evaluation
  * traverses the tree.  Both give the same intersections and terms; the two
- * sums differ only in summation order. */
+ * sums differ only in summation order.  The recording takes
+ *   - one recording walk, when rrt_count_paths counted the current tree;
+ *   - else, when the path buffer has room for the paths and a pool of chunks
+ *     beside them (RRT_TUNE_ONE_PASS), one walk that appends each ray's
+ *     entries to 32-entry chunks of the pool and counts them, and a copy of
+ *     the chunks into rows; if the pool runs short, a second, recording walk
+ *     with the counts the first one took;
+ *   - else a counting walk and a recording walk. */
 
 /* Library version as major*10000 + minor*100 + patch. */
 int rrt_version(void);
 
 /* Create a context on the current HIP device.  stream: a hipStream_t (may be
- * NULL).  *out receives the context; on failure *out is NULL. */
+ * NULL).  *out receives the context; on failure *out is NULL.  Allocates no
+ * device memory: give it a workspace before any call that needs one. */
 int rrt_create(rrt_ctx** out, const rrt_params* params, void* stream);
 
-/* Release every device buffer the context owns. Safe on NULL. */
+/* Release the context.  The caller's workspace and path buffer are not freed
+ * (the caller owns them); they are no longer referenced afterwards. Safe on
+ * NULL. */
 void rrt_destroy(rrt_ctx* ctx);
+
+/* ---- device memory -----------------------------------------------------
+ * The problem statement of the method (Sec. 4, implementation details: the
+ * spectrum, N_ray, l_ray, the update criterion; the particle fields of
+ * Sec. 4.1.1, eq. nhi) fixes what a context holds, so its fixed buffers are
+ * known from the sizes alone. */
+
+/* Bytes of workspace for a problem of n particles, n_ray rays, n_bins
+ * frequency bins and n_halo independent halos (1 = one problem), under the
+ * context's current scheme (rrt_set_scheme adds the near columns), plus the
+ * reverse mode's buffers for K iterations (reverse_K = 0: none).  Includes
+ * the largest scratch any call takes, except the staging of the inspection
+ * calls' hit lists (rrt_get_hits: 8 bytes per ray plus 8 per intersection).
+ * host size_t* bytes.  No device work. */
+int rrt_workspace_size(const rrt_ctx* ctx, int64_t n, int32_t n_ray, int32_t n_bins,
+                       int32_t n_halo, int32_t reverse_K, size_t* bytes);
+
+/* Give the context its workspace: device memory of `bytes` bytes, 256-byte
+ * aligned, owned by the caller, not overlapping the previous workspace or the
+ * path buffer.  The context's buffers are carved from it.  When a workspace
+ * was set before, every live buffer moves into the new one (a device copy;
+ * synchronises the stream), so a context can grow its workspace at any time
+ * without losing state; the old memory is no longer referenced when the call
+ * returns.  RRT_E_WORKSPACE if the live buffers do not fit. */
+int rrt_set_workspace(rrt_ctx* ctx, void* dev, size_t bytes);
+
+/* Usage of the context's device memory, host size_t out[6]: workspace bytes
+ * in use and its size, path-buffer bytes in use and its size, and the size
+ * and region (0 = workspace, 1 = path buffer) of the last request that found
+ * no room (0 and -1 if none). */
+int rrt_workspace_info(const rrt_ctx* ctx, size_t* out6);
+
+/* Recorded paths, first step: a counting walk over the current tree (Sec.
+ * 4.1.1, eq. colden: which particles each ray intersects).  Host outputs,
+ * each nullable: *n_hits, the intersections of every ray (each periodic
+ * image separately); *bytes_paths, the path buffer the recorded paths need
+ * (8 bytes per intersection and a little padding); *bytes_one_walk, the size
+ * with which a later recording of a geometry with up to this many
+ * intersections takes one walk (the paths and the chunk pool beside them).
+ * The counts are kept, so the next column evaluation records with one walk.
+ * Synchronises. */
+int rrt_count_paths(rrt_ctx* ctx, int64_t* n_hits, size_t* bytes_paths, size_t* bytes_one_walk);
+
+/* Recorded paths, second step: the device memory they are recorded into,
+ * owned by the caller, 256-byte aligned (NULL and 0: none).  Besides the
+ * paths, the library uses the rest of it for the one-walk chunk pool while
+ * recording, and, room permitting, for the reverse mode's transposed paths
+ * and kept columns and for row tiles; each of these is optional and has a
+ * slower form that needs no memory.  Replacing the buffer drops the recorded
+ * paths and everything in the old buffer (synchronises the stream first). */
+int rrt_set_path_buffer(rrt_ctx* ctx, void* dev, size_t bytes);
 
 /* Text of the last error on this context (or of the last failed create when
  * ctx is NULL).  Valid until the next call on the context. */
@@ -109,8 +176,10 @@ const char* rrt_last_error(const rrt_ctx* ctx);
  *   n_H  float[n]     hydrogen density in cm^-3, > 0
  *   T    float[n]     temperature in K, > 0
  * x_init: device double[n] initial neutral fractions, or NULL for the optically
- * thin state x_thin = x_-(Gamma_thin) (Sec. 4).  Copied; validated by
- * rrt_build_tree, which must follow. n >= 1. */
+ * thin state x_thin = x_-(Gamma_thin) (Sec. 4).  Copied into the workspace
+ * (rrt_workspace_size with this n); validated by rrt_build_tree, which must
+ * follow and returns RRT_E_INPUT for non-finite or out-of-range values
+ * (x_init outside [0, 1] included).  n >= 1. */
 int rrt_set_particles(rrt_ctx* ctx, int64_t n, const float* pos, const float* h,
                       const float* mu, const float* n_H, const float* T,
                       const double* x_init);
@@ -175,15 +244,13 @@ int rrt_update_equilibrium(rrt_ctx* ctx, double* x_out, double* max_dx_out);
  * 1/x over the HI column, reaches the near column; 6-point Gauss-Legendre
  * steps and Newton's method, with the spectrum's attenuation tabulated once
  * per spectrum), in place of the paper's 4-D table of the same function.
- * Weighting (eq. gammashld, 4 pi inside w): with near_far = 1 each ray's slab
- * is lit by the ray's share, 1/n_ray of the far-attenuated spectrum, and
- * Gamma = sum_k Gamma_k (exact for a plane-parallel beam, Sec. 5.1-5.2);
- * near_far = 2 is a variant that lights each slab with the whole
- * far-attenuated spectrum and takes Gamma = (1/n_ray) sum_k Gamma_k (exact
- * when light arrives alike from every direction).  Recorded paths are dropped
- * when the split is switched on or off, not between 1 and 2.  While a near/far
- * scheme is set, rrt_forward, rrt_backward, rrt_iterate_halos and update rules
- * other than the default return RRT_E_STATE.  0 (default): the plain scheme. */
+ * Each ray's slab is lit by the ray's share, 1/n_ray of the far-attenuated
+ * spectrum, and Gamma = sum_k Gamma_k (eq. gammashld with 4 pi inside w; the
+ * weighting the paper's two-sided slab discussion of Sec. 5.2 implies).
+ * Recorded paths are dropped when the scheme changes; the near columns take
+ * 8 bytes per ray more workspace.  While the near/far scheme is set,
+ * rrt_forward, rrt_backward, rrt_iterate_halos and update rules other than
+ * the default return RRT_E_STATE.  0 (default): the plain scheme. */
 int rrt_set_scheme(rrt_ctx* ctx, int32_t near_far);
 
 /* Near total-hydrogen columns of the last rrt_compute_columns under the
@@ -224,9 +291,12 @@ int rrt_set_update_rule(rrt_ctx* ctx, double tau_skip, double tau_case_b, int32_
  * largest change of a sweep is below tol or max_iter sweeps, under the update
  * rule above.  x_out: device double[n] (nullable).  iters_done, max_dx_out:
  * host (nullable).  Returns RRT_NOT_CONVERGED if max_iter was reached without
- * convergence.  Synchronises once per sweep (16 bytes) for the convergence
- * test; the first call of rrt_set_update_rule's density order also copies
- * n_H to the host once. */
+ * convergence.  Synchronises once per sweep (64 bytes: the largest change,
+ * intersections, the convergence counts of rrt_get_convergence and the input
+ * flags) for the convergence test; the first call of rrt_set_update_rule's
+ * density order also copies n_H to the host once.  RRT_E_INPUT when a given
+ * state or density was out of range, or an update left a neutral fraction
+ * outside [0, 1]. */
 int rrt_iterate_equilibrium(rrt_ctx* ctx, int32_t max_iter, double tol, double* x_out,
                             int32_t* iters_done, double* max_dx_out);
 
@@ -239,7 +309,8 @@ int rrt_iterate_equilibrium(rrt_ctx* ctx, int32_t max_iter, double tol, double* 
  * ln Gamma of the last iteration and x^K. */
 
 /* New densities without a new tree (geometry and recorded paths are kept):
- * n_H device float[n] in input order, > 0. */
+ * n_H device float[n] in input order, > 0 and finite; other values raise the
+ * device flag of rrt_set_state (RRT_E_INPUT at the next synchronising call). */
 int rrt_set_density(rrt_ctx* ctx, const float* n_H);
 
 /* Exactly K iterations from the optically thin state, keeping every iterate
@@ -261,7 +332,10 @@ int rrt_backward(rrt_ctx* ctx, const double* dL_dlnG, const double* dL_dx, doubl
 /* The fixed point of every halo at once: each halo iterates until its own
  * max|dx| < tol or max_iter iterations, then keeps its state while the others
  * continue (per-halo masks on the device).  After a first eager iteration
- * (which records the ray paths when they fit), the iterations run as replays
+ * (which records the ray paths when they fit in the path buffer; when the
+ * whole batch's do not, the halos are solved in groups whose paths fit, after
+ * one counting walk, which takes 8 more bytes per ray of workspace; a halo
+ * too large alone traverses), the iterations run as replays
  * of a HIP graph of per_launch (1..256) iterations captured once per geometry
  * and parameters, on a stream the library owns (ordered after the context's
  * stream by events); the host reads 8 bytes after each replay.  x_out: device
@@ -280,8 +354,9 @@ int rrt_iterate_halos(rrt_ctx* ctx, int32_t max_iter, double tol, int32_t per_la
  *   RRT_TUNE_LEAF         particles per tree leaf (1..8), from the next build
  *   RRT_TUNE_ADJOINT      transposed column product of rrt_backward over
  *                         recorded paths: 0 (default) = gather over paths
- *                         transposed once per geometry when memory allows
- *                         (deterministic), else per row tile in LDS with one
+ *                         transposed once per geometry when they fit in the
+ *                         path buffer (32 bytes per intersection while they are
+ *                         built; deterministic), else per row tile in LDS with one
  *                         atomic add per distinct particle of a tile (when the
  *                         tiles fit), else one atomic add per intersection;
  *                         1 = always one atomic add per intersection;
@@ -297,38 +372,51 @@ int rrt_iterate_halos(rrt_ctx* ctx, int32_t max_iter, double tol, int32_t per_la
  *                         much as a hundred evaluations save on long rays, so
  *                         it pays for long solves with short rays only.
  *   RRT_TUNE_KEEP_COLUMNS 1 (default): rrt_forward keeps every iteration's
- *                         columns for rrt_backward when they take at most an
- *                         eighth of the free device memory (8 n n_ray K
- *                         bytes); 0: rrt_backward recomputes them from the
- *                         kept states.  The same columns either way.
- *   RRT_TUNE_ONE_PASS     1 (default): with the wave-cooperative walk and an
- *                         automatic path budget, record the paths in one walk
- *                         that appends each ray's entries to 32-entry chunks
- *                         of a pool and counts them, then compact the chunks
+ *                         columns for rrt_backward when they fit in the path
+ *                         buffer beside the paths (8 n n_ray K bytes); 0:
+ *                         rrt_backward recomputes them from the kept states.
+ *                         The same columns either way.
+ *   RRT_TUNE_ONE_PASS     1 (default): with the wave-cooperative walk,
+ *                         record the paths in one walk that appends each
+ *                         ray's entries to 32-entry chunks of a pool in the
+ *                         path buffer and counts them, then copy the chunks
  *                         into rows; when the pool runs short, record in a
  *                         second walk as with 0.  The pool is sized from the
- *                         context's previous recording (so its first
- *                         recording takes two walks): 5/4 of its entries plus
- *                         half a chunk per ray, in 1024 slices with a counter
- *                         each, at most 45% of the free memory.  It is kept
- *                         between recordings, and released with the particle
- *                         buffers, at rrt_destroy, when this knob is set, or
- *                         when the paths would not fit beside it.  0: a
- *                         counting walk, then a recording walk.  n > 1: one
- *                         pass with a pool of about n chunks, also on a first
- *                         recording.  The same paths either way. */
+ *                         context's previous recording or count (so a
+ *                         context's first recording takes two walks unless
+ *                         rrt_count_paths ran): 5/4 of its entries plus half
+ *                         a chunk per ray, in 1024 slices with a counter
+ *                         each; after a recording that ran short, half as
+ *                         large again (up to 4x).  It is used only when the
+ *                         path buffer holds it beside the paths, and freed
+ *                         once the paths are in rows.  0: a counting walk,
+ *                         then a recording walk.  n > 1: one pass with a pool
+ *                         of about n chunks, also on a first recording.  The
+ *                         same paths either way. */
 enum { RRT_TUNE_TRACE_BLOCK = 1, RRT_TUNE_PACKET = 2, RRT_TUNE_PATH_GROUP = 3, RRT_TUNE_LEAF = 4,
        RRT_TUNE_ADJOINT = 5, RRT_TUNE_TILES = 6, RRT_TUNE_KEEP_COLUMNS = 7,
        RRT_TUNE_ONE_PASS = 8 };
 int rrt_set_tuning(rrt_ctx* ctx, int32_t key, int32_t value);
 
 /* Replace the state: x device double[n] in input order (checkpoint / resume,
- * or a given iterate); NULL resets to x_thin. */
+ * or a given iterate); NULL resets to x_thin.  Values outside [0, 1] (NaN
+ * included) raise a device flag that the next call which synchronises
+ * reports as RRT_E_INPUT (and clears). */
 int rrt_set_state(rrt_ctx* ctx, const double* x);
 
 /* Read the state: device outputs in input order, each nullable. */
 int rrt_get_state(rrt_ctx* ctx, double* x_out, double* lnG_out, double* G_out,
                   float* tau_out);
+
+/* Convergence history of the last rrt_iterate_equilibrium (Sec. 4: the paper
+ * reports the fraction of particles whose neutral fraction has converged
+ * after each iteration).  For sweep s < min(cap, sweeps): max_dx[s], the
+ * largest change (relative when the update rule says so); n_abs[s] and
+ * n_rel[s], the particles updated in that sweep whose change |dx| was below
+ * the solve's tol, and whose |dx| / x_old was below tol.  Host outputs, each
+ * nullable; *n_sweeps receives the number of sweeps. */
+int rrt_get_convergence(rrt_ctx* ctx, int32_t cap, int32_t* n_sweeps, double* max_dx,
+                        int64_t* n_abs, int64_t* n_rel);
 
 /* Tree export for inspection (host outputs).  Node i of the depth-first layout:
  * box lo[i][3], hi[i][3] (exact FP32 min/max of r -/+ h over its particles),
@@ -341,12 +429,42 @@ int rrt_get_tree(rrt_ctx* ctx, int64_t cap, int64_t* n_nodes, float* lo, float* 
                  int32_t* skip, int32_t* first, int32_t* count, int32_t* perm,
                  uint64_t* codes);
 
+/* Each halo's subtree (rrt_set_halos): nodes [root[h], end[h]) of the
+ * depth-first layout hold exactly halo h's particles (host int32 outputs,
+ * n_halo each; one problem: the whole tree). */
+int rrt_get_halo_roots(rrt_ctx* ctx, int32_t* root, int32_t* end);
+
+/* Hit lists of the rays of some sources, from the wave-cooperative walk the
+ * column evaluations and the path recording run (Sec. 4.1.1, eq. colden:
+ * which particles each ray intersects, and the kernel chord factor of each).
+ * src: host int64[n_src] input indices of distinct source particles, 1 <=
+ * n_src <= 4096.  Host outputs: row_off int64[n_src * n_ray + 1], the hits of
+ * ray k of source src[i] are entries row_off[i*n_ray+k] ..
+ * row_off[i*n_ray+k+1]) of hit_j (input index of the particle), hit_img (its
+ * periodic image, coded as in rrt_get_hits) and hit_fac (K/h^2 in kpc^-2,
+ * FP32; nullable).  cap: capacity of the entry arrays; with too little
+ * capacity (or null hit_j), row_off is filled and RRT_E_CAPACITY returned
+ * (RRT_OK for null arrays).  Staging comes from the workspace (12 bytes per
+ * hit plus 8 per ray).  Synchronises. */
+int rrt_get_hits_rows(rrt_ctx* ctx, int32_t n_src, const int64_t* src, int64_t cap,
+                      int64_t* row_off, int32_t* hit_j, int32_t* hit_img, float* hit_fac);
+
+/* The recorded paths of the rays of some sources, as the streaming product
+ * sums them: same arguments and layout as rrt_get_hits_rows, with hit_j the
+ * input index of each recorded particle and hit_fac its factor.  The order
+ * within a ray is the order of the walk.  RRT_E_STATE when no paths are
+ * recorded.  Synchronises. */
+int rrt_get_path_rows(rrt_ctx* ctx, int32_t n_src, const int64_t* src, int64_t cap,
+                      int64_t* row_off, int32_t* hit_j, float* hit_fac);
+
 /* Hit lists for the current geometry (host outputs): the intersections of ray
  * (p, k) are hit_j[row_off[p*n_ray+k] .. row_off[p*n_ray+k+1]) as input
  * particle indices, with the periodic image of each in hit_img as
  * (sx+8) | (sy+8)<<4 | (sz+8)<<8 (the image of particle j sits at r_j + s*box).
  * row_off: int64[n*n_ray + 1].  cap: capacity of hit_j/hit_img; if the total
- * exceeds it, row_off is still filled and RRT_E_CAPACITY is returned. */
+ * exceeds it, row_off is still filled and RRT_E_CAPACITY is returned.
+ * Staging comes from the workspace: 8 bytes per ray, plus 8 per intersection
+ * when the lists are written. */
 int rrt_get_hits(rrt_ctx* ctx, int64_t cap, int64_t* row_off, int32_t* hit_j,
                  int32_t* hit_img);
 
@@ -372,6 +490,21 @@ int rrt_reset_timing(rrt_ctx* ctx);
  * of rrt_iterate_equilibrium, out2[1] = intersections summed over every
  * iteration since the last rrt_reset_timing. */
 int rrt_get_counters(rrt_ctx* ctx, int64_t* out2);
+
+/* Path recordings since rrt_create, host int64 out[n_out] (up to
+ * RRT_N_REC_STATS entries): [0] in one walk into the chunk pool, [1] one walk
+ * whose pool ran short, finished by a second, recording walk, [2] one
+ * recording walk after rrt_count_paths, [3] a counting and a recording walk,
+ * [4] recordings that did not fit the path buffer (traversal instead). */
+enum { RRT_N_REC_STATS = 5 };
+int rrt_get_recording_stats(rrt_ctx* ctx, int64_t* out, int32_t n_out);
+
+/* The work of the walk (diagnostics): one counting pass of the
+ * wave-cooperative walk over every ray of the current tree that also tallies
+ * host int64 out6 = [rays, node visits of the 64-ray packets, node visits of
+ * single rays (box tests passed), leaf visits of the packets, particle pair
+ * tests, intersections].  Synchronises. */
+int rrt_trace_stats(rrt_ctx* ctx, int64_t* out6);
 
 #ifdef __cplusplus
 }

@@ -206,11 +206,13 @@ __global__ void k_adj_init(const double* __restrict__ lam, const float* __restri
 
 __global__ void k_set_density(const int32_t* __restrict__ perm, const float* __restrict__ nH,
                               const float* __restrict__ mu0_s, const float* __restrict__ nH0_s,
-                              int64_t n, float* __restrict__ nH_s, double* __restrict__ mu_s)
+                              int64_t n, float* __restrict__ nH_s, double* __restrict__ mu_s,
+                              unsigned long long* __restrict__ bad)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     const float v = nH[perm[i]];
+    if (!(v > 0.f) || !isfinite(v)) atomicOr(bad, 1ull);      // densities must be > 0
     nH_s[i] = v;
     mu_s[i] = (double)mu0_s[i] * ((double)v / (double)nH0_s[i]);
 }
@@ -220,7 +222,7 @@ __global__ void k_set_density(const int32_t* __restrict__ perm, const float* __r
 hipError_t launch_set_density(Ctx& c, const float* nH)
 {
     hipLaunchKernelGGL(k_set_density, dim3(nblk(c.n)), dim3(kBlock), 0, c.stream, c.perm, nH,
-                       c.mu0_s, c.nH0_s, c.n, c.nH_s, c.mu_s);
+                       c.mu0_s, c.nH0_s, c.n, c.nH_s, c.mu_s, c.red + kRedInput);
     return hipGetLastError();
 }
 

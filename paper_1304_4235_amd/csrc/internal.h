@@ -90,8 +90,45 @@ struct KernelTables {
     double gauss_a;                     // t^2 log2(e): exp(-t^2 q^2) = 2^(-a q^2)
 };
 
+// Device memory of a context: regions the caller owns (include/rrt.h,
+// rrt_set_workspace and rrt_set_path_buffer), carved into the context's
+// buffers.  Each live block remembers the pointer variable that holds it
+// (its owner), so the workspace can be moved into a larger region by a device
+// copy and a rebase of those pointers.  Freeing is bookkeeping only: every
+// buffer is used on the context's stream (or on the batched solve's stream,
+// ordered after it by events), so a block handed out again is written only
+// after the work that used it before.
+enum { kRegionWs = 0, kRegionPath = 1 };
+struct Arena {
+    struct Block {
+        uint64_t off, size;
+        int region;
+        void** owner;
+    };
+    char* base[2] = {nullptr, nullptr};
+    uint64_t cap[2] = {0, 0};
+    std::vector<Block> blocks;       // live blocks, in no particular order
+    uint64_t short_bytes = 0;        // the last request that found no room
+    int short_region = -1;
+};
+constexpr uint64_t kWsAlign = 256;
+
+// Slots of the context's device reduction array.
+enum {
+    kRedMaxDx = 0,      // max |dx| of a sweep (FP64 bits, atomic max)
+    kRedHits = 1,       // intersections of a column evaluation
+    kRedBuild = 2,      // tree construction consistency flags
+    kRedScratch = 3,    // counts of walks that are not column evaluations
+    kRedConvAbs = 4,    // particles of a sweep with |dx| < tol
+    kRedConvRel = 5,    // particles of a sweep with |dx| / x < tol
+    kRedInput = 6,      // a given x or n_H was non-finite or out of range
+    kRedNumeric = 7,    // an update produced a non-finite neutral fraction
+    kRedSlots = 8
+};
+
 struct Ctx {
     rrt_params prm{};
+    Arena arena;
     hipStream_t stream = nullptr;
     int device = 0;
     std::string err;
@@ -206,10 +243,6 @@ struct Ctx {
     // build scratch
     uint64_t* keys_b = nullptr;
     int32_t* vals_b = nullptr;
-    uint32_t* hist = nullptr;
-    size_t hist_cap = 0;
-    void* scan_tmp = nullptr;
-    size_t scan_tmp_bytes = 0;
     int32_t* k_left = nullptr;   // radix tree children (>= 0 internal, < 0 leaf ~i)
     int32_t* k_right = nullptr;
     int32_t* k_parent = nullptr; // [2n-1]: internal 0..n-2, leaves n-1..2n-2
@@ -223,7 +256,6 @@ struct Ctx {
 
     // spectrum and rays (device)
     double* dirs = nullptr;      // [n_ray][3]
-    double* ws = nullptr;        // w_b sigma_b
     float* dsig_l2 = nullptr;    // (sigma_b - sigma_min) * log2(e)
     float* ws_rel = nullptr;     // w_b sigma_b / max_b(w_b sigma_b)
     float* srat = nullptr;       // sigma_b / sigma_min
@@ -259,9 +291,25 @@ struct Ctx {
     size_t adj_n = 0, adj_nr = 0;  // sizes the adjoint buffers were allocated for
     KernelTables* tables = nullptr;
 
-    // reductions (device) and a host mirror
-    unsigned long long* red = nullptr;   // [0] max|dx| bits, [1] hits, [2] input error flags
+    // reductions (device, kRedSlots) and a host mirror
+    unsigned long long* red = nullptr;
     unsigned long long* red_host = nullptr;  // pinned
+    // per sweep of the last rrt_iterate_equilibrium: max |dx| and the
+    // particles whose change is below tol, absolutely and relative to x
+    std::vector<double> conv_maxdx;
+    std::vector<int64_t> conv_abs, conv_rel;
+    // path recordings since rrt_create: in one walk, one walk that ran short
+    // and took a second, after rrt_count_paths, a counting and a recording walk
+    int64_t n_rec_one = 0, n_rec_fallback = 0, n_rec_counted = 0, n_rec_two = 0, n_rec_unfit = 0;
+    // row_off holds the exclusive scan of the current geometry's per-ray
+    // counts (rrt_count_paths), count_total their sum
+    bool counts_valid = false;
+    uint64_t count_total = 0;
+    // the one-walk pool holds pool_scale x the last recording's entries (plus
+    // half a chunk per ray); it grows by half after a recording that ran short
+    double pool_scale = 1.25;
+    double conv_tol = 0.0;       // tolerance of the running fixed point (convergence counts)
+    bool ctx_bufs = false;       // tables, reductions and chunk counters are in the workspace
 
     // geometry
     TraceGeom geom{};
@@ -296,6 +344,39 @@ struct Ctx {
     hipEvent_t ev_open = nullptr;
 };
 
+// ---- device memory (workspace.hip) ----
+// Carve `bytes` for *owner from a region (what *owner held is released
+// first).  hipErrorOutOfMemory when no gap is large enough; the request is
+// recorded in c.arena.short_*.
+hipError_t ws_alloc(Ctx& c, void** owner, size_t bytes, int region);
+template <typename T>
+inline hipError_t ws_alloc(Ctx& c, T** owner, size_t count, int region = kRegionWs)
+{
+    return ws_alloc(c, reinterpret_cast<void**>(owner), count * sizeof(T), region);
+}
+void ws_free(Ctx& c, void** owner);
+template <typename T>
+inline void ws_free(Ctx& c, T** owner)
+{
+    ws_free(c, reinterpret_cast<void**>(owner));
+}
+uint64_t ws_used(const Ctx& c, int region);
+uint64_t ws_high_water(const Ctx& c, int region);
+uint64_t ws_largest_gap(const Ctx& c, int region);
+hipError_t ws_move(Ctx& c, char* base, uint64_t cap);
+uint64_t workspace_bytes(int64_t n, int n_ray, int n_bins, int n_halo, int K, bool near_far);
+// A buffer for the duration of one call, released when it goes out of scope.
+template <typename T>
+struct Scratch {
+    Ctx& c;
+    T* p = nullptr;
+    explicit Scratch(Ctx& cc) : c(cc) {}
+    ~Scratch() { ws_free(c, &p); }
+    hipError_t get(size_t count, int region = kRegionWs) { return ws_alloc(c, &p, count, region); }
+    Scratch(const Scratch&) = delete;
+    Scratch& operator=(const Scratch&) = delete;
+};
+
 // ---- launchers (tree.hip) ----
 hipError_t launch_bounds(Ctx& c, float* part_out /*[nb][8]*/, int nb);
 hipError_t launch_morton(Ctx& c, const double lo[3], double scale, int bits);
@@ -325,6 +406,18 @@ int tile_group(const Ctx& c);
 // largest tile set the reverse-mode tile scatter accumulates in LDS (64 KiB)
 constexpr int kTileScatterMaxSet = 8192;
 hipError_t launch_count_hits(Ctx& c, uint64_t* row_cnt);
+// the rays of sampled sources only (sorted tree positions): per-ray counts
+// and hit lists at rows i * n_ray + k
+hipError_t launch_count_rows(Ctx& c, const int32_t* src_list, int32_t src_n, uint64_t* row_cnt);
+hipError_t launch_record_rows(Ctx& c, const int32_t* src_list, int32_t src_n,
+                              const uint64_t* row_off, int32_t* hit_j, int32_t* hit_img,
+                              float* hit_fac, uint64_t cap);
+// a count pass of the wave-cooperative walk that also tallies its work
+hipError_t launch_trace_stats(Ctx& c, uint64_t* row_cnt, unsigned long long* stats);
+// sampled rows (tree-order row ids) of the recorded paths: counts when
+// dst_off is null, else the entries at those offsets
+hipError_t launch_path_rows(Ctx& c, const int64_t* rows, int m, uint64_t* cnt,
+                            const uint64_t* dst_off, int32_t* hit_j, float* hit_fac);
 hipError_t launch_record_hits(Ctx& c, const uint64_t* row_off, int32_t* hit_j, int32_t* hit_img,
                               uint64_t cap);
 
@@ -352,6 +445,8 @@ hipError_t launch_update_x(Ctx& c);
 hipError_t launch_to_input_order_d(Ctx& c, const double* src, double* dst, int32_t stride);
 hipError_t launch_to_input_order_f(Ctx& c, const float* src, float* dst);
 hipError_t launch_from_input_order_d(Ctx& c, const double* src, double* dst);
+// a given state into c.x_s, flagging values outside [0, 1] in red[kRedInput]
+hipError_t launch_state_from_input(Ctx& c, const double* src);
 hipError_t launch_mux(Ctx& c);
 hipError_t launch_seg_finalize(Ctx& c, double tol, int max_iter);
 hipError_t launch_seg_init(Ctx& c);

@@ -32,7 +32,7 @@ __global__ void k_init_state(const int32_t* __restrict__ perm, const float* __re
                              const double* __restrict__ mu_s, int64_t n, double gthin,
                              double* __restrict__ alpha, double* __restrict__ alphaB,
                              double* __restrict__ gcoll, double* __restrict__ x_s,
-                             float* __restrict__ mux)
+                             float* __restrict__ mux, unsigned long long* __restrict__ bad_input)
 {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -43,6 +43,7 @@ __global__ void k_init_state(const int32_t* __restrict__ perm, const float* __re
     alphaB[i] = alpha_caseB(Tj);
     gcoll[i] = gc;
     double x = x_init ? x_init[j] : x_minus(gthin, (double)nH_s[i], al, gc);
+    if (!(x >= 0.0 && x <= 1.0)) atomicOr(bad_input, 1ull);   // a given state out of range
     x_s[i] = x;
     mux[i] = (float)(mu_s[i] * x);
 }
@@ -65,9 +66,9 @@ struct RateRule {
     double sigma1;
     double gl_x[6], gl_w[6];
     AttenuationTable att;
-    // 1: each slab lit by its ray's share, rates summed (the paper's weighting);
-    // 0: lit by the whole far-attenuated spectrum, rates averaged (variant)
-    int nf_share;
+    // convergence counts of the updated particles: |dx| < conv_tol and
+    // |dx| / x < conv_tol (slots kRedConvAbs, kRedConvRel of red)
+    double conv_tol;
 };
 
 enum { kSchemePlain = 0, kSchemeNearMono = 1, kSchemeNearPoly = 2 };
@@ -87,6 +88,7 @@ k_gamma(const double* __restrict__ N, int64_t n, int n_ray, int n_bins,
 {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     double dx = 0.0;
+    bool conv_a = false, conv_r = false, bad = false;
     const int h = (seg_of && i < n) ? seg_of[i] : -1;
     const bool live = !(seg_active && h >= 0 && seg_active[h] == 0) &&
                       !(rule.want && i < n && rule.want[i] == 0);
@@ -94,12 +96,11 @@ k_gamma(const double* __restrict__ N, int64_t n, int n_ray, int n_bins,
         double m = -INFINITY, s = 0.0, l;
         if (SCHEME != kSchemePlain) {
             // near/far: per ray the slab of near particles lit by the radiation
-            // the far particles let through.  The paper's weighting lights each
-            // slab with the ray's share, 1/n_ray of the spectrum (eq.
-            // gammashld's 4 pi / N_ray, with 4 pi inside w), and sums the
-            // slabs' bottom rates; the variant lights it with all of it and
-            // averages them.  (The table of binned spectra carries the shift.)
-            const double ln_share = rule.nf_share ? -log((double)n_ray) : 0.0;
+            // the far particles let through.  Each slab is lit by the ray's
+            // share, 1/n_ray of the spectrum (eq. gammashld's 4 pi / N_ray,
+            // with 4 pi inside w), and the slabs' bottom rates add up.  (The
+            // table of binned spectra carries the shift.)
+            const double ln_share = -log((double)n_ray);
             for (int k = 0; k < n_ray; ++k) {
                 double v;
                 if (SCHEME == kSchemeNearPoly) {
@@ -120,7 +121,6 @@ k_gamma(const double* __restrict__ N, int64_t n, int n_ray, int n_bins,
                     s += exp(v - m);
                 }
             }
-            if (!rule.nf_share) s /= (double)n_ray;
             l = (s > 0.0) ? (m + log(s)) : -INFINITY;
         } else {
             // 2^x is the hardware instruction (about 1 ulp), which flushes
@@ -162,13 +162,24 @@ k_gamma(const double* __restrict__ N, int64_t n, int n_ray, int n_bins,
         } else if (update_x) {
             const double al = te >= rule.tau_case_b ? rule.alphaB[i] : alpha[i];
             double xn = x_minus(g, (double)nH_s[i], al, gcoll[i]);
-            dx = fabs(xn - x_s[i]);
-            if (rule.relative) dx /= x_s[i];
+            const double xo = x_s[i];
+            const double da = fabs(xn - xo);
+            conv_a = da < rule.conv_tol;
+            conv_r = da < rule.conv_tol * xo;
+            bad = !(xn >= 0.0 && xn <= 1.0);          // also catches NaN
+            dx = rule.relative ? da / xo : da;
             x_s[i] = xn;
             mux[i] = (float)(mu_s[i] * xn);
         }
     }
     if (update_x) {
+        // one atomic per wave for each count, and for the flag
+        const uint64_t ba = __ballot(conv_a), br = __ballot(conv_r), bb = __ballot(bad);
+        if ((threadIdx.x & 63) == 0) {
+            if (ba) atomicAdd(maxdx_bits + (kRedConvAbs - kRedMaxDx), (unsigned long long)__popcll(ba));
+            if (br) atomicAdd(maxdx_bits + (kRedConvRel - kRedMaxDx), (unsigned long long)__popcll(br));
+            if (bb) atomicOr(maxdx_bits + (kRedNumeric - kRedMaxDx), 1ull);
+        }
         if (seg_maxdx) {
             // per-halo maximum: one atomic per wave when the wave holds one halo
             const int h0 = __shfl(h, 0, 64);
@@ -287,6 +298,22 @@ __global__ void k_gather_d(const int32_t* __restrict__ perm, const double* __res
     if (i < n) dst[i] = src[perm[i]];
 }
 
+// a given state: input order -> tree order, flagging values outside [0, 1]
+// (NaN included) in *bad
+__global__ void k_gather_state(const int32_t* __restrict__ perm, const double* __restrict__ src,
+                               int64_t n, double* __restrict__ dst,
+                               unsigned long long* __restrict__ bad)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    bool b = false;
+    if (i < n) {
+        const double v = src[perm[i]];
+        b = !(v >= 0.0 && v <= 1.0);
+        dst[i] = v;
+    }
+    if (__ballot(b) && (threadIdx.x & 63) == 0) atomicOr(bad, 1ull);
+}
+
 inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 }  // namespace
@@ -354,15 +381,15 @@ hipError_t build_attenuation_table(Ctx& c)
         tab[2 * i] = mx + std::log(S);
         tab[2 * i + 1] = -(D / S) * (1.0 + N * smax) / smax;    // d ln S / dt
     }
-    void* d = nullptr;
-    hipError_t e = hipMalloc(&d, sizeof(double) * tab.size());
+    hipError_t e = ws_alloc(c, &c.att_tab, tab.size());
     if (e != hipSuccess) return e;
-    e = hipMemcpy(d, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice);
+    e = hipMemcpyAsync(c.att_tab, tab.data(), sizeof(double) * tab.size(),
+                       hipMemcpyHostToDevice, c.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c.stream);     // tab goes out of scope
     if (e != hipSuccess) {
-        (void)hipFree(d);
+        ws_free(c, &c.att_tab);
         return e;
     }
-    c.att_tab = static_cast<double*>(d);
     c.att_m = tmax > 0.0 ? m : 1;
     c.att_dt = dt;
     c.att_tmax = tmax;
@@ -376,7 +403,7 @@ hipError_t launch_init_state(Ctx& c, bool use_given)
 {
     hipLaunchKernelGGL(k_init_state, dim3(nblk(c.n)), dim3(kBlock), 0, c.stream, c.perm, c.T_in,
                        use_given ? c.x_init : nullptr, c.nH_s, c.mu_s, c.n, c.gamma_thin,
-                       c.alpha_s, c.alphaB_s, c.gcoll_s, c.x_s, c.mux_s);
+                       c.alpha_s, c.alphaB_s, c.gcoll_s, c.x_s, c.mux_s, c.red + kRedInput);
     return hipGetLastError();
 }
 
@@ -391,7 +418,7 @@ hipError_t launch_gamma(Ctx& c, bool update_x, bool first_sweep)
     rule.relative = c.rule_relative;
     rule.Nn = c.near_far ? c.Nn_s : nullptr;
     rule.sigma1 = c.sigma_min;
-    rule.nf_share = c.near_far == 1;
+    rule.conv_tol = c.conv_tol;
     gauss_legendre6(rule.gl_x, rule.gl_w);
     const int scheme = !c.near_far ? kSchemePlain : c.n_bins == 1 ? kSchemeNearMono
                                                                   : kSchemeNearPoly;
@@ -401,9 +428,8 @@ hipError_t launch_gamma(Ctx& c, bool update_x, bool first_sweep)
             hipError_t e = build_attenuation_table(c);
             if (e != hipSuccess) return e;
         }
-        // with the paper's weighting each ray's slab is lit by its share,
-        // 1/n_ray, of the spectrum
-        const double shift = c.near_far == 1 ? std::log((double)c.n_ray) : 0.0;
+        // each ray's slab is lit by its share, 1/n_ray, of the spectrum
+        const double shift = std::log((double)c.n_ray);
         rule.att = AttenuationTable{reinterpret_cast<const double2*>(c.att_tab), c.att_m,
                                     c.att_dt, c.att_tmax, c.att_smax, c.sigma_min,
                                     c.ln_ws_max - shift};
@@ -595,6 +621,13 @@ hipError_t launch_to_input_order_f(Ctx& c, const float* src, float* dst)
 {
     hipLaunchKernelGGL(k_scatter_f, dim3(nblk(c.n)), dim3(kBlock), 0, c.stream, c.perm, src, c.n,
                        dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_state_from_input(Ctx& c, const double* src)
+{
+    hipLaunchKernelGGL(k_gather_state, dim3(nblk(c.n)), dim3(kBlock), 0, c.stream, c.perm, src,
+                       c.n, c.x_s, c.red + kRedInput);
     return hipGetLastError();
 }
 

@@ -41,84 +41,81 @@ int fail(Ctx& c, int code, const char* fmt, ...)
     return code;
 }
 
+// A request the workspace or the path buffer had no room for.
+int ws_fail(Ctx& c, const char* what)
+{
+    const Arena& a = c.arena;
+    if (!a.base[kRegionWs])
+        return fail(c, RRT_E_WORKSPACE, "%s: no workspace (rrt_workspace_size, rrt_set_workspace)",
+                    what);
+    const int r = a.short_region < 0 ? kRegionWs : a.short_region;
+    return fail(c, RRT_E_WORKSPACE,
+                "%s: %llu bytes in one piece do not fit the %s (%llu of %llu bytes in use)", what,
+                (unsigned long long)a.short_bytes, r == kRegionWs ? "workspace" : "path buffer",
+                (unsigned long long)ws_used(c, r), (unsigned long long)a.cap[r]);
+}
+
 #define HIP_OK(expr)                                                                       \
     do {                                                                                   \
         hipError_t e_ = (expr);                                                            \
+        if (e_ == hipErrorOutOfMemory) return ws_fail(c, #expr);                           \
         if (e_ != hipSuccess)                                                              \
             return fail(c, RRT_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));      \
     } while (0)
 
-template <typename T>
-hipError_t dalloc(T** p, size_t count)
+// every buffer of the per-particle and per-ray families, which are released
+// and carved again together
+void free_adjoint(Ctx& c)
 {
-    if (*p) (void)hipFree(*p);
-    *p = nullptr;
-    if (count == 0) count = 1;
-    return hipMalloc((void**)p, count * sizeof(T));
-}
-
-void free_pool(Ctx& c);
-
-void free_particles(Ctx& c)
-{
-    free_pool(c);
-    void* bufs[] = {c.pos_in, c.h_in, c.mu_in, c.nH_in, c.T_in, c.x_init, c.p4, c.mu_s, c.nH_s,
-                    c.mu0_s, c.nH0_s,
-                    c.alpha_s, c.gcoll_s, c.x_s, c.mux_s, c.lnG_s, c.G_s, c.tau_s, c.N_s,
-                    c.perm, c.codes, c.nodes, c.keys_b, c.vals_b, c.k_left, c.k_right,
-                    c.k_parent, c.k_first, c.k_last, c.k_lo, c.k_hi, c.k_cnt, c.k_dfs, c.k_flag,
-                    c.seg_of, c.k_seg, c.alphaB_s, c.skip_s, c.want_s, c.block_s,
-                    c.block_list, c.Nn_s};
-    for (void* b : bufs)
-        if (b) (void)hipFree(b);
-    c.seg_of = c.k_seg = nullptr;
-    c.alphaB_s = nullptr;
-    c.skip_s = c.want_s = nullptr;
-    c.block_s = nullptr;
-    c.block_list = nullptr;
-    c.blocks_for = 0;
-    c.Nn_s = nullptr;
-    void* adj[] = {c.xhist, c.adj_lam, c.adj_lup, c.adj_nu, c.adj_pis, c.adj_gnH, c.adj_y,
-                   c.adj_wpart, c.adj_gw, c.adj_tpart, c.adj_st, c.adj_ell, c.Nhist};
-    for (void* b : adj)
-        if (b) (void)hipFree(b);
-    c.xhist = c.adj_lam = c.adj_lup = c.adj_pis = c.adj_gnH = c.adj_y = nullptr;
-    c.adj_nu = nullptr;
-    c.Nhist = nullptr;
+    void** adj[] = {(void**)&c.xhist, (void**)&c.adj_lam, (void**)&c.adj_lup, (void**)&c.adj_nu,
+                    (void**)&c.adj_pis, (void**)&c.adj_gnH, (void**)&c.adj_y, (void**)&c.adj_wpart,
+                    (void**)&c.adj_gw, (void**)&c.adj_tpart, (void**)&c.adj_st, (void**)&c.adj_ell,
+                    (void**)&c.Nhist};
+    for (void** b : adj) ws_free(c, b);
     c.Nhist_cap = 0;
     c.Nhist_on = false;
-    c.adj_wpart = c.adj_gw = c.adj_tpart = nullptr;
-    c.adj_st = nullptr;
-    c.adj_ell = nullptr;
     c.adj_n = c.adj_nr = 0;
     c.xhist_cap = 0;
     c.fwd_K = -1;
-    c.pos_in = c.h_in = c.mu_in = c.nH_in = c.T_in = nullptr;
-    c.x_init = nullptr;
-    c.p4 = nullptr;
-    c.nH_s = c.mux_s = c.tau_s = c.mu0_s = c.nH0_s = nullptr;
-    c.mu_s = nullptr;
-    c.alpha_s = c.gcoll_s = c.x_s = c.lnG_s = c.G_s = c.N_s = nullptr;
-    c.perm = nullptr;
-    c.codes = nullptr;
-    c.nodes = nullptr;
-    c.keys_b = nullptr;
-    c.vals_b = nullptr;
-    c.k_left = c.k_right = c.k_parent = c.k_first = c.k_last = nullptr;
-    c.k_lo = c.k_hi = nullptr;
-    c.k_cnt = c.k_dfs = c.k_flag = nullptr;
+}
+
+void free_columns(Ctx& c)
+{
+    ws_free(c, &c.N_s);
+    ws_free(c, &c.Nn_s);
+    ws_free(c, &c.row_off);
+    c.counts_valid = false;
+}
+
+void free_particles(Ctx& c)
+{
+    void** bufs[] = {(void**)&c.pos_in, (void**)&c.h_in, (void**)&c.mu_in, (void**)&c.nH_in,
+                     (void**)&c.T_in, (void**)&c.x_init, (void**)&c.p4, (void**)&c.mu_s,
+                     (void**)&c.nH_s, (void**)&c.mu0_s, (void**)&c.nH0_s, (void**)&c.alpha_s,
+                     (void**)&c.gcoll_s, (void**)&c.x_s, (void**)&c.mux_s, (void**)&c.lnG_s,
+                     (void**)&c.G_s, (void**)&c.tau_s, (void**)&c.perm, (void**)&c.codes,
+                     (void**)&c.nodes, (void**)&c.keys_b, (void**)&c.vals_b, (void**)&c.k_left,
+                     (void**)&c.k_right, (void**)&c.k_parent, (void**)&c.k_first,
+                     (void**)&c.k_last, (void**)&c.k_lo, (void**)&c.k_hi, (void**)&c.k_cnt,
+                     (void**)&c.k_dfs, (void**)&c.k_flag, (void**)&c.seg_of, (void**)&c.k_seg,
+                     (void**)&c.alphaB_s, (void**)&c.skip_s, (void**)&c.want_s,
+                     (void**)&c.block_s, (void**)&c.block_list};
+    for (void** b : bufs) ws_free(c, b);
+    free_columns(c);
+    free_adjoint(c);
+    c.blocks_for = 0;
     c.n_cap = 0;
 }
 
 int alloc_particles(Ctx& c, int64_t n)
 {
-    if (n <= c.n_cap && c.N_s) return RRT_OK;
+    if (n <= c.n_cap && c.p4) return RRT_OK;
     free_particles(c);
     const size_t m = (size_t)n;
     const size_t mi = m > 1 ? m - 1 : 1;
     hipError_t e = hipSuccess;
 #define A(p, cnt)                                                    \
-    if (e == hipSuccess) e = dalloc(&(p), (cnt));
+    if (e == hipSuccess) e = ws_alloc(c, &(p), (cnt));
     A(c.pos_in, 3 * m) A(c.h_in, m) A(c.mu_in, m) A(c.nH_in, m) A(c.T_in, m) A(c.x_init, m)
     A(c.p4, m + kLeafMax) A(c.mu_s, m) A(c.mu0_s, m) A(c.nH0_s, m) A(c.nH_s, m) A(c.alpha_s, m) A(c.gcoll_s, m) A(c.x_s, m)
     A(c.mux_s, m) A(c.lnG_s, m) A(c.G_s, m) A(c.tau_s, m) A(c.perm, m) A(c.codes, m)
@@ -128,35 +125,86 @@ int alloc_particles(Ctx& c, int64_t n)
     A(c.alphaB_s, m) A(c.skip_s, m) A(c.want_s, m) A(c.block_s, m) A(c.block_list, m)
 #undef A
     if (e != hipSuccess) {
+        const int r = ws_fail(c, "particle buffers");
         free_particles(c);
-        return fail(c, RRT_E_NOMEM, "device allocation for %lld particles failed: %s",
-                    (long long)n, hipGetErrorString(e));
+        return r;
     }
     // the spare particle entries past n are read with whole leaves, never used
-    e = hipMemset(c.p4 + m, 0, sizeof(float4) * kLeafMax);
+    e = hipMemsetAsync(c.p4 + m, 0, sizeof(float4) * kLeafMax, c.stream);
     if (e != hipSuccess) {
         free_particles(c);
-        return fail(c, RRT_E_HIP, "hipMemset: %s", hipGetErrorString(e));
+        return fail(c, RRT_E_HIP, "hipMemsetAsync: %s", hipGetErrorString(e));
     }
     c.n_cap = n;
     return RRT_OK;
 }
 
+// Columns (and near columns) and the recorded paths' row offsets, [n_ray][n].
 int alloc_columns(Ctx& c)
 {
-    if (c.N_s) (void)hipFree(c.N_s);
-    c.N_s = nullptr;
-    if (c.Nn_s) (void)hipFree(c.Nn_s);
-    c.Nn_s = nullptr;
+    free_columns(c);
     // rays are indexed with 32-bit integers on the device
     if (c.n * (int64_t)c.n_ray > kMaxRows)
         return fail(c, RRT_E_ARG, "%lld particles x %d rays exceeds 2^31 - 1 rays",
                     (long long)c.n, c.n_ray);
-    hipError_t e = dalloc(&c.N_s, (size_t)c.n * (size_t)c.n_ray);
-    if (e == hipSuccess && c.near_far) e = dalloc(&c.Nn_s, (size_t)c.n * (size_t)c.n_ray);
-    if (e != hipSuccess)
-        return fail(c, RRT_E_NOMEM, "column buffer allocation failed: %s", hipGetErrorString(e));
+    const size_t nr = (size_t)c.n * (size_t)c.n_ray;
+    hipError_t e = ws_alloc(c, &c.N_s, nr);
+    if (e == hipSuccess && c.near_far) e = ws_alloc(c, &c.Nn_s, nr);
+    if (e == hipSuccess) e = ws_alloc(c, &c.row_off, nr + 1);
+    if (e != hipSuccess) {
+        const int r = ws_fail(c, "column buffers");
+        free_columns(c);
+        return r;
+    }
     return RRT_OK;
+}
+
+// The context's own small buffers: kernel tables, reductions, chunk counters.
+int alloc_ctx_buffers(Ctx& c)
+{
+    if (c.ctx_bufs) return RRT_OK;
+    HIP_OK(ws_alloc(c, &c.tables, 1));
+    HIP_OK(ws_alloc(c, &c.red, kRedSlots));
+    HIP_OK(ws_alloc(c, &c.pool_ctr, (size_t)kPoolSlices * kCtrStride + 1));
+    KernelTables host;
+    fill_kernel_tables(&host);
+    HIP_OK(hipMemcpyAsync(c.tables, &host, sizeof host, hipMemcpyHostToDevice, c.stream));
+    HIP_OK(hipMemsetAsync(c.red, 0, kRedSlots * sizeof(unsigned long long), c.stream));
+    HIP_OK(hipStreamSynchronize(c.stream));        // `host` goes out of scope
+    c.ctx_bufs = true;
+    return RRT_OK;
+}
+
+int need_ws(Ctx& c)
+{
+    if (!c.ctx_bufs)
+        return fail(c, RRT_E_WORKSPACE, "no workspace (rrt_workspace_size, rrt_set_workspace)");
+    return RRT_OK;
+}
+
+// Read and clear the device input flags; RRT_E_INPUT when one was raised.
+// Expects red_host[kRedInput..kRedNumeric] copied and the stream synchronised.
+int check_flags(Ctx& c)
+{
+    const unsigned long long bad_in = c.red_host[kRedInput], bad_num = c.red_host[kRedNumeric];
+    if (!bad_in && !bad_num) return RRT_OK;
+    c.red_host[kRedInput] = c.red_host[kRedNumeric] = 0;
+    HIP_OK(hipMemsetAsync(c.red + kRedInput, 0, 2 * sizeof(unsigned long long), c.stream));
+    HIP_OK(hipStreamSynchronize(c.stream));
+    if (bad_in)
+        return fail(c, RRT_E_INPUT, "a given neutral fraction was outside [0, 1] or a given "
+                                    "density not finite and > 0 (rrt_set_state, "
+                                    "rrt_set_particles' x_init, rrt_set_density)");
+    return fail(c, RRT_E_INPUT, "an update produced a neutral fraction outside [0, 1]");
+}
+
+// Synchronise and report the input flags.
+int sync_flags(Ctx& c)
+{
+    HIP_OK(hipMemcpyAsync(c.red_host + kRedInput, c.red + kRedInput,
+                          2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, c.stream));
+    HIP_OK(hipStreamSynchronize(c.stream));
+    return check_flags(c);
 }
 
 hipEvent_t ev_take(Ctx& c)
@@ -220,160 +268,177 @@ int need_tree(Ctx& c)
 
 void free_tpaths(Ctx& c)
 {
-    if (c.tpath) (void)hipFree(c.tpath);
-    if (c.tcol_off) (void)hipFree(c.tcol_off);
-    c.tpath = nullptr;
-    c.tcol_off = nullptr;
+    ws_free(c, &c.tpath);
+    ws_free(c, &c.tcol_off);
     c.tpaths_valid = false;
     c.tpaths_unfit = false;
 }
 
-// the one-pass recording's pool: kept between recordings (re-allocating tens
-// of gigabytes was measured to cost up to seconds), released with the particle
-// buffers, at rrt_destroy, when one-pass recording is switched, or when the
-// paths would not fit beside it
 void free_pool(Ctx& c)
 {
-    if (c.pool) (void)hipFree(c.pool);
-    if (c.chunk_next) (void)hipFree(c.chunk_next);
-    if (c.row_first) (void)hipFree(c.row_first);
-    c.pool = nullptr;
-    c.chunk_next = nullptr;
-    c.row_first = nullptr;
+    ws_free(c, &c.pool);
+    ws_free(c, &c.chunk_next);
+    ws_free(c, &c.row_first);
     c.pool_chunks = c.slice_chunks = 0;
     c.pool_rows = 0;
 }
 
-// The pool for a recording: room for 5/4 of the last recording's entries plus
-// half a chunk per row, over kPoolSlices slices.  Leaves no pool, with no
-// error, before a context's first recording or when it would take more than
-// 45% of the free memory; the walk then counts and records apart.
-void ensure_pool(Ctx& c, int64_t n_rows)
-{
-    uint64_t chunks;
-    if (c.pool_cap) {
-        chunks = c.pool_cap;
-    } else {
-        if (c.last_total == 0) return;
-        const uint64_t entries = c.last_total / 4 * 5 + (uint64_t)n_rows * (kChunkLen / 2);
-        chunks = (entries + kChunkLen - 1) / kChunkLen;
-    }
-    const uint64_t per_slice =
-        std::min<uint64_t>((chunks + kPoolSlices - 1) / kPoolSlices, 0xfffffff0ull / kPoolSlices);
-    if (c.pool && c.slice_chunks >= per_slice && c.pool_rows >= n_rows) return;
-    free_pool(c);
-    const uint64_t total_chunks = per_slice * kPoolSlices;
-    size_t fr = 0, tot = 0;
-    if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
-        (void)hipGetLastError();
-        return;
-    }
-    const size_t bytes = total_chunks * (sizeof(int2) * kChunkLen + sizeof(uint32_t)) +
-                         sizeof(uint32_t) * (size_t)n_rows;
-    if (bytes > fr / 20 * 9) return;
-    hipError_t e = hipMalloc((void**)&c.pool, total_chunks * sizeof(int2) * kChunkLen);
-    if (e == hipSuccess) e = hipMalloc((void**)&c.chunk_next, total_chunks * sizeof(uint32_t));
-    if (e == hipSuccess) e = hipMalloc((void**)&c.row_first, sizeof(uint32_t) * (size_t)n_rows);
-    if (e == hipSuccess && !c.pool_ctr)
-        e = hipMalloc((void**)&c.pool_ctr,
-                      ((size_t)kPoolSlices * kCtrStride + 1) * sizeof(unsigned long long));
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        free_pool(c);
-        return;
-    }
-    c.pool_chunks = total_chunks;
-    c.slice_chunks = per_slice;
-    c.pool_rows = n_rows;
-}
-
+// What is recorded in the path buffer and derived from the recorded paths.
 void free_paths(Ctx& c)
 {
     drop_graph(c);
     free_tpaths(c);
     free_tiles(c);
+    free_pool(c);
     c.path_evals = 0;
-    if (c.row_off) (void)hipFree(c.row_off);
-    if (c.path) (void)hipFree(c.path);
-    c.row_off = nullptr;
-    c.path = nullptr;
+    ws_free(c, &c.path);
     c.path_cap = 0;
     c.path_hits = 0;
     c.paths_valid = false;
     c.paths_unfit = false;
 }
 
+// Chunks of the one-walk pool for a recording expected to hold `entries`
+// entries over n_rows rays: pool_scale x entries plus half a chunk per ray,
+// rounded up to whole slices (or the tuned pool size).
+uint64_t pool_chunks_for(const Ctx& c, uint64_t entries, int64_t n_rows)
+{
+    uint64_t chunks;
+    if (c.pool_cap) {
+        chunks = c.pool_cap;
+    } else {
+        const uint64_t e = (uint64_t)((double)entries * c.pool_scale) +
+                           (uint64_t)n_rows * (kChunkLen / 2);
+        chunks = (e + kChunkLen - 1) / kChunkLen;
+    }
+    const uint64_t per_slice =
+        std::min<uint64_t>((chunks + kPoolSlices - 1) / kPoolSlices, 0xfffffff0ull / kPoolSlices);
+    return per_slice * kPoolSlices;
+}
 
-// Record (tree index, K/h^2) per intersection, rows in order, with row offsets.
-// One pass when the pool is there: the walk appends each ray's entries to
-// chunks of the pool and counts them, a scan gives the offsets, and the chunks
-// are compacted into the path array.  Otherwise, or when a slice of the pool
-// runs out, two passes: a count, the scan, then a record into the offsets.
-// Leaves the paths invalid (and traversal in charge) when they would exceed
-// the budget.
+uint64_t pool_bytes(uint64_t chunks, int64_t n_rows)
+{
+    auto up = [](uint64_t b) { return (b + kWsAlign - 1) / kWsAlign * kWsAlign; };
+    return up(chunks * sizeof(int2) * kChunkLen) + up(chunks * sizeof(uint32_t)) +
+           up((uint64_t)n_rows * sizeof(uint32_t));
+}
+
+uint64_t path_bytes(uint64_t entries)
+{
+    return (((entries ? entries : 1) + kPathPad) * sizeof(int2) + kWsAlign - 1) / kWsAlign *
+           kWsAlign;
+}
+
+// The one-walk pool in the path buffer, when it fits beside paths of about the
+// expected size.  No pool (and no error) otherwise.
+void ensure_pool(Ctx& c, int64_t n_rows, uint64_t expect)
+{
+    free_pool(c);
+    if (!c.pool_cap && expect == 0) return;            // nothing to size it from
+    const uint64_t chunks = pool_chunks_for(c, expect, n_rows);
+    if (pool_bytes(chunks, n_rows) + path_bytes(expect) > ws_largest_gap(c, kRegionPath)) return;
+    hipError_t e = ws_alloc(c, &c.pool, chunks * kChunkLen, kRegionPath);
+    if (e == hipSuccess) e = ws_alloc(c, &c.chunk_next, chunks, kRegionPath);
+    if (e == hipSuccess) e = ws_alloc(c, &c.row_first, (size_t)n_rows, kRegionPath);
+    if (e != hipSuccess) {
+        free_pool(c);
+        return;
+    }
+    c.pool_chunks = chunks;
+    c.slice_chunks = chunks / kPoolSlices;
+    c.pool_rows = n_rows;
+}
+
+// The paths do not fit the path buffer: traverse instead, or fail when
+// recording is required.
+int paths_unfit(Ctx& c, uint64_t total)
+{
+    free_paths(c);
+    c.last_total = total;
+    c.n_rec_unfit += 1;
+    if (c.prm.record_paths == 1)
+        return fail(c, RRT_E_WORKSPACE,
+                    "recorded paths need %llu bytes; the path buffer holds %llu "
+                    "(rrt_count_paths, rrt_set_path_buffer)",
+                    (unsigned long long)path_bytes(total),
+                    (unsigned long long)c.arena.cap[kRegionPath]);
+    c.paths_unfit = true;
+    return RRT_OK;
+}
+
+// Record (tree index, K/h^2) per intersection into the path buffer, rows in
+// order, with row offsets in c.row_off: one recording walk when the counts of
+// this tree are known (rrt_count_paths); else one walk into pool chunks, their
+// compaction into rows, and a second, recording walk only when the pool ran
+// short; else a counting walk and a recording walk.  Leaves the paths unfit
+// (and traversal in charge) when they do not fit the path buffer.
 int record_paths(Ctx& c)
 {
     const int64_t n_rows = c.n * (int64_t)c.n_ray;
-    ev_begin(c);
-    HIP_OK(dalloc(&c.row_off, (size_t)n_rows + 1));
-    HIP_OK(hipMemsetAsync(c.row_off + n_rows, 0, sizeof(uint64_t), c.stream));
-    bool chunked = false;
-    if (c.one_pass && c.prm.traversal == 0 && c.prm.path_budget == 0) {
-        ensure_pool(c, n_rows);
-        chunked = c.pool != nullptr;
-    }
-    const size_t n_ctr = (size_t)kPoolSlices * kCtrStride + 1;
-    if (chunked) {
-        HIP_OK(hipMemsetAsync(c.pool_ctr, 0, n_ctr * sizeof(unsigned long long), c.stream));
-        HIP_OK(launch_record_chunks(c, c.row_off));
-    } else {
-        HIP_OK(launch_count_hits(c, c.row_off));
-    }
-    HIP_OK(scan_exclusive_u64(c, c.row_off, c.row_off, n_rows + 1));
-    uint64_t total = 0;
-    unsigned long long overflow = 0;
-    HIP_OK(hipMemcpyAsync(&total, c.row_off + n_rows, sizeof total, hipMemcpyDeviceToHost,
-                          c.stream));
-    if (chunked)
-        HIP_OK(hipMemcpyAsync(&overflow, c.pool_ctr + n_ctr - 1, sizeof overflow,
-                              hipMemcpyDeviceToHost, c.stream));
-    HIP_OK(hipStreamSynchronize(c.stream));
-    if (overflow) chunked = false;    // a slice ran out: the counts stand, record again
-    size_t budget = (size_t)c.prm.path_budget;
-    if (budget == 0) {
-        size_t fr = 0, tot = 0;
-        HIP_OK(hipMemGetInfo(&fr, &tot));
-        budget = fr / 2 + (c.path ? (size_t)c.path_cap * sizeof(int2) / 2 : 0);
-        if (c.pool && (size_t)total * sizeof(int2) > budget) {
-            // the pool itself may be what is in the way: decide without it
-            chunked = false;
-            free_pool(c);
-            HIP_OK(hipMemGetInfo(&fr, &tot));
-            budget = fr / 2 + (c.path ? (size_t)c.path_cap * sizeof(int2) / 2 : 0);
-        }
-    }
-    if ((size_t)total * sizeof(int2) > budget) {
-        free_pool(c);
+    free_paths(c);
+    if (!c.arena.base[kRegionPath]) {
+        c.n_rec_unfit += 1;
         if (c.prm.record_paths == 1)
-            return fail(c, RRT_E_NOMEM, "recorded paths need %llu bytes, budget %zu",
-                        (unsigned long long)total * sizeof(int2), budget);
-        if (c.path) (void)hipFree(c.path);
-        c.path = nullptr;
-        c.path_cap = 0;
+            return fail(c, RRT_E_WORKSPACE,
+                        "recording the paths needs a path buffer (rrt_count_paths, "
+                        "rrt_set_path_buffer)");
         c.paths_unfit = true;
-        ev_end(c, &c.t_record);
         return RRT_OK;
     }
-    if (total > c.path_cap || !c.path) {
-        HIP_OK(dalloc(&c.path, (size_t)std::max<uint64_t>(total, 1) + kPathPad));
-        c.path_cap = std::max<uint64_t>(total, 1);
+    ev_begin(c);
+    uint64_t total = 0;
+    int kind = 3;                                   // counting walk + recording walk
+    if (c.counts_valid) {
+        total = c.count_total;
+        kind = 2;
+    } else {
+        bool chunked = false;
+        if (c.one_pass && c.prm.traversal == 0) {
+            ensure_pool(c, n_rows, c.last_total);
+            chunked = c.pool != nullptr;
+        }
+        const size_t n_ctr = (size_t)kPoolSlices * kCtrStride + 1;
+        if (chunked) {
+            HIP_OK(hipMemsetAsync(c.pool_ctr, 0, n_ctr * sizeof(unsigned long long), c.stream));
+            HIP_OK(launch_record_chunks(c, c.row_off));
+        } else {
+            HIP_OK(launch_count_hits(c, c.row_off));
+        }
+        HIP_OK(hipMemsetAsync(c.row_off + n_rows, 0, sizeof(uint64_t), c.stream));
+        HIP_OK(scan_exclusive_u64(c, c.row_off, c.row_off, n_rows + 1));
+        unsigned long long overflow = 0;
+        HIP_OK(hipMemcpyAsync(&total, c.row_off + n_rows, sizeof total, hipMemcpyDeviceToHost,
+                              c.stream));
+        if (chunked)
+            HIP_OK(hipMemcpyAsync(&overflow, c.pool_ctr + n_ctr - 1, sizeof overflow,
+                                  hipMemcpyDeviceToHost, c.stream));
+        HIP_OK(hipStreamSynchronize(c.stream));
+        if (chunked) {
+            kind = overflow ? 1 : 0;
+            // a pool that ran short is sized half as large again next time
+            if (overflow) c.pool_scale = std::min(c.pool_scale * 1.5, 4.0);
+        }
+        c.counts_valid = true;                      // row_off holds this tree's offsets
+        c.count_total = total;
     }
-    drop_graph(c);
-    free_tpaths(c);                  // both are derived from the previous paths
-    free_tiles(c);
-    c.path_evals = 0;
-    if (chunked) HIP_OK(launch_compact_chunks(c));
+    // the compaction needs the paths beside the pool; the recording walk only
+    // the paths
+    if (kind == 0 && ws_alloc(c, &c.path, total + kPathPad, kRegionPath) != hipSuccess) kind = 1;
+    if (kind != 0) {
+        free_pool(c);
+        if (ws_alloc(c, &c.path, total + kPathPad, kRegionPath) != hipSuccess) {
+            ev_end(c, &c.t_record);
+            return paths_unfit(c, total);
+        }
+    }
+    c.path_cap = std::max<uint64_t>(total, 1);
+    if (kind == 0) HIP_OK(launch_compact_chunks(c));
     else HIP_OK(launch_record_paths(c, c.row_off, c.path, total));
+    free_pool(c);
+    if (kind == 0) c.n_rec_one += 1;
+    else if (kind == 1) c.n_rec_fallback += 1;
+    else if (kind == 2) c.n_rec_counted += 1;
+    else c.n_rec_two += 1;
     c.path_hits = (int64_t)total;
     c.last_total = total;
     c.paths_valid = true;
@@ -435,7 +500,7 @@ int columns_impl(Ctx& c, int64_t* hits)
 
 extern "C" {
 
-int rrt_version(void) { return 1 * 10000 + 0 * 100 + 0; }
+int rrt_version(void) { return 2 * 10000 + 0 * 100 + 0; }
 
 int rrt_create(rrt_ctx** out, const rrt_params* params, void* stream)
 {
@@ -447,11 +512,11 @@ int rrt_create(rrt_ctx** out, const rrt_params* params, void* stream)
     if (!(params->l_ray >= 0.0) || !std::isfinite(params->l_ray) || !(params->box >= 0.0) ||
         !std::isfinite(params->box) || params->leaf_size < 0 || params->leaf_size > 8 ||
         params->block_size < 0 || params->block_size > 256 || (params->block_size % 64) != 0 ||
-        params->record_paths < -1 || params->record_paths > 1 || params->path_budget < 0 ||
-        params->traversal < 0 || params->traversal > 1) {
+        params->record_paths < -1 || params->record_paths > 1 || params->traversal < 0 ||
+        params->traversal > 1) {
         g_create_err = "rrt_create: invalid params (l_ray >= 0, box >= 0, leaf_size 0..8, "
                        "block_size a multiple of 64 up to 256, record_paths -1..1, "
-                       "path_budget >= 0, traversal 0..1)";
+                       "traversal 0..1)";
         return RRT_E_ARG;
     }
     for (int i = 0; i < 2; ++i)
@@ -462,21 +527,16 @@ int rrt_create(rrt_ctx** out, const rrt_params* params, void* stream)
     rrt_ctx* x = new (std::nothrow) rrt_ctx;
     if (!x) {
         g_create_err = "rrt_create: out of host memory";
-        return RRT_E_NOMEM;
+        return RRT_E_ARG;
     }
     Ctx& c = x->c;
     c.prm = *params;
     c.leaf = params->leaf_size ? params->leaf_size : kDefaultLeaf;
     c.stream = reinterpret_cast<hipStream_t>(stream);
     hipError_t e = hipGetDevice(&c.device);
-    if (e == hipSuccess) e = hipMalloc((void**)&c.tables, sizeof(KernelTables));
-    if (e == hipSuccess) e = hipMalloc((void**)&c.red, 4 * sizeof(unsigned long long));
-    if (e == hipSuccess) e = hipHostMalloc((void**)&c.red_host, 4 * sizeof(unsigned long long));
-    if (e == hipSuccess) {
-        KernelTables host;
-        fill_kernel_tables(&host);
-        e = hipMemcpy(c.tables, &host, sizeof host, hipMemcpyHostToDevice);
-    }
+    if (e == hipSuccess)
+        e = hipHostMalloc((void**)&c.red_host, kRedSlots * sizeof(unsigned long long));
+    if (e == hipSuccess) std::memset(c.red_host, 0, kRedSlots * sizeof(unsigned long long));
     if (e != hipSuccess) {
         g_create_err = std::string("rrt_create: HIP error: ") + hipGetErrorString(e);
         rrt_destroy(x);
@@ -492,28 +552,21 @@ void rrt_destroy(rrt_ctx* x)
     Ctx& c = x->c;
     if (c.stream) (void)hipStreamSynchronize(c.stream);
     else (void)hipDeviceSynchronize();
-    free_particles(c);
-    free_paths(c);
     drop_graph(c);
-    if (c.gstream) (void)hipStreamDestroy(c.gstream);
+    if (c.gstream) {
+        (void)hipStreamSynchronize(c.gstream);
+        (void)hipStreamDestroy(c.gstream);
+    }
     if (c.ev_a) (void)hipEventDestroy(c.ev_a);
     if (c.ev_b) (void)hipEventDestroy(c.ev_b);
-    if (c.pool_ctr) (void)hipFree(c.pool_ctr);
-    c.pool_ctr = nullptr;
-    void* bufs[] = {c.tables, c.red, c.dirs, c.ws, c.dsig_l2, c.ws_rel, c.srat, c.hist,
-                    c.scan_tmp, c.halo_off, c.seg_root, c.seg_end, c.seg_active, c.seg_maxdx,
-                    c.seg_iters, c.seg_state};
     if (c.seg_state_host) (void)hipHostFree(c.seg_state_host);
-    for (void* b : bufs)
-        if (b) (void)hipFree(b);
     if (c.red_host) (void)hipHostFree(c.red_host);
-    if (c.att_tab) (void)hipFree(c.att_tab);
     ev_flush(c);
     if (c.ev_open) c.ev_free.push_back(c.ev_open);
     c.ev_open = nullptr;
     for (hipEvent_t e : c.ev_free) (void)hipEventDestroy(e);
     c.ev_free.clear();
-    delete x;
+    delete x;                         // the device memory is the caller's
 }
 
 const char* rrt_last_error(const rrt_ctx* x)
@@ -521,17 +574,94 @@ const char* rrt_last_error(const rrt_ctx* x)
     return x ? x->c.err.c_str() : g_create_err.c_str();
 }
 
+int rrt_workspace_size(const rrt_ctx* x, int64_t n, int32_t n_ray, int32_t n_bins,
+                       int32_t n_halo, int32_t reverse_K, size_t* bytes)
+{
+    if (!x || !bytes || n < 0 || n > (int64_t(1) << 28) || n_ray < 0 || n_ray > kMaxRays ||
+        n_bins < 0 || n_bins > kMaxBins || n_halo < 0 || n_halo > 4096 || reverse_K < 0 ||
+        reverse_K > 100000)
+        return RRT_E_ARG;
+    *bytes = (size_t)workspace_bytes(n, n_ray, n_bins, n_halo, reverse_K, x->c.near_far != 0);
+    return RRT_OK;
+}
+
+int rrt_set_workspace(rrt_ctx* x, void* dev, size_t bytes)
+{
+    if (!x) return RRT_E_ARG;
+    Ctx& c = x->c;
+    if (!dev || bytes == 0) return fail(c, RRT_E_ARG, "a workspace needs a device pointer and size");
+    if (reinterpret_cast<uintptr_t>(dev) % kWsAlign)
+        return fail(c, RRT_E_ARG, "the workspace must be %llu-byte aligned",
+                    (unsigned long long)kWsAlign);
+    const uint64_t hw = ws_high_water(c, kRegionWs);
+    if (hw > bytes)
+        return fail(c, RRT_E_WORKSPACE, "the context's buffers reach %llu bytes; the new "
+                                        "workspace has %zu", (unsigned long long)hw, bytes);
+    // a captured graph and the geometry refer to the old addresses
+    drop_graph(c);
+    if (c.gstream) HIP_OK(hipStreamSynchronize(c.gstream));
+    HIP_OK(ws_move(c, static_cast<char*>(dev), bytes));
+    if (c.have_tree && c.n_halo > 1) {
+        c.geom.seg_of = c.seg_of;
+        c.geom.seg_root = c.seg_root;
+        c.geom.seg_end = c.seg_end;
+    }
+    return alloc_ctx_buffers(c);
+}
+
+int rrt_workspace_info(const rrt_ctx* x, size_t* out6)
+{
+    if (!x || !out6) return RRT_E_ARG;
+    const Ctx& c = x->c;
+    out6[0] = (size_t)ws_used(c, kRegionWs);
+    out6[1] = (size_t)c.arena.cap[kRegionWs];
+    out6[2] = (size_t)ws_used(c, kRegionPath);
+    out6[3] = (size_t)c.arena.cap[kRegionPath];
+    out6[4] = (size_t)c.arena.short_bytes;
+    out6[5] = (size_t)(int64_t)c.arena.short_region;
+    return RRT_OK;
+}
+
+int rrt_set_path_buffer(rrt_ctx* x, void* dev, size_t bytes)
+{
+    if (!x) return RRT_E_ARG;
+    Ctx& c = x->c;
+    if ((dev == nullptr) != (bytes == 0))
+        return fail(c, RRT_E_ARG, "a path buffer needs both a pointer and a size (or neither)");
+    if (reinterpret_cast<uintptr_t>(dev) % kWsAlign)
+        return fail(c, RRT_E_ARG, "the path buffer must be %llu-byte aligned",
+                    (unsigned long long)kWsAlign);
+    // work queued on the old buffer finishes before it is given back
+    if (c.stream) HIP_OK(hipStreamSynchronize(c.stream));
+    if (c.gstream) HIP_OK(hipStreamSynchronize(c.gstream));
+    free_paths(c);
+    ws_free(c, &c.Nhist);
+    c.Nhist_cap = 0;
+    c.Nhist_on = false;
+    for (const Arena::Block& b : c.arena.blocks)
+        if (b.region == kRegionPath)
+            return fail(c, RRT_E_STATE, "a buffer of the old path buffer is still in use");
+    c.arena.base[kRegionPath] = static_cast<char*>(dev);
+    c.arena.cap[kRegionPath] = bytes;
+    return RRT_OK;
+}
+
 int rrt_set_particles(rrt_ctx* x, int64_t n, const float* pos, const float* h, const float* mu,
                       const float* n_H, const float* T, const double* x_init)
 {
     if (!x) return RRT_E_ARG;
     Ctx& c = x->c;
+    if (int r = need_ws(c)) return r;
     if (n < 1 || n > (int64_t(1) << 28))
         return fail(c, RRT_E_ARG, "particle count %lld outside 1..2^28", (long long)n);
     if (!pos || !h || !mu || !n_H || !T) return fail(c, RRT_E_ARG, "null particle array");
+    free_paths(c);
     int r = alloc_particles(c, n);
     if (r) return r;
     c.n = n;
+    if (c.have_rays) {
+        if (int r2 = alloc_columns(c)) return r2;
+    }
     HIP_OK(hipMemcpyAsync(c.pos_in, pos, sizeof(float) * 3 * n, hipMemcpyDeviceToDevice, c.stream));
     HIP_OK(hipMemcpyAsync(c.h_in, h, sizeof(float) * n, hipMemcpyDeviceToDevice, c.stream));
     HIP_OK(hipMemcpyAsync(c.mu_in, mu, sizeof(float) * n, hipMemcpyDeviceToDevice, c.stream));
@@ -543,10 +673,9 @@ int rrt_set_particles(rrt_ctx* x, int64_t n, const float* pos, const float* h, c
                               c.stream));
     c.have_particles = true;
     c.have_tree = c.have_columns = c.have_gamma = false;
+    c.fwd_K = -1;
     c.n_halo = 1;                 // rrt_set_halos may follow
     c.halo_off_host.clear();
-    free_paths(c);
-    if (c.have_rays) return alloc_columns(c);
     return RRT_OK;
 }
 
@@ -562,19 +691,21 @@ int rrt_set_halos(rrt_ctx* x, int32_t n_halo, const int64_t* offsets)
     for (int h = 0; h < n_halo; ++h)
         if (offsets[h + 1] <= offsets[h])
             return fail(c, RRT_E_ARG, "halo %d is empty or offsets decrease", h);
-    HIP_OK(dalloc(&c.halo_off, (size_t)n_halo + 1));
-    HIP_OK(dalloc(&c.seg_root, (size_t)n_halo));
-    HIP_OK(dalloc(&c.seg_end, (size_t)n_halo));
-    HIP_OK(dalloc(&c.seg_active, (size_t)n_halo));
-    HIP_OK(dalloc(&c.seg_maxdx, (size_t)n_halo));
-    HIP_OK(dalloc(&c.seg_iters, (size_t)n_halo));
-    if (!c.seg_state) HIP_OK(dalloc(&c.seg_state, 4));
+    free_paths(c);
+    HIP_OK(ws_alloc(c, &c.halo_off, (size_t)n_halo + 1));
+    HIP_OK(ws_alloc(c, &c.seg_root, (size_t)n_halo));
+    HIP_OK(ws_alloc(c, &c.seg_end, (size_t)n_halo));
+    HIP_OK(ws_alloc(c, &c.seg_active, (size_t)n_halo));
+    HIP_OK(ws_alloc(c, &c.seg_maxdx, (size_t)n_halo));
+    HIP_OK(ws_alloc(c, &c.seg_iters, (size_t)n_halo));
+    if (!c.seg_state) HIP_OK(ws_alloc(c, &c.seg_state, 4));
     if (!c.seg_state_host) HIP_OK(hipHostMalloc((void**)&c.seg_state_host, 4 * sizeof(int32_t)));
-    HIP_OK(hipMemcpy(c.halo_off, offsets, sizeof(int64_t) * (n_halo + 1), hipMemcpyHostToDevice));
     c.halo_off_host.assign(offsets, offsets + n_halo + 1);
+    HIP_OK(hipMemcpyAsync(c.halo_off, c.halo_off_host.data(), sizeof(int64_t) * (n_halo + 1),
+                          hipMemcpyHostToDevice, c.stream));
+    HIP_OK(hipStreamSynchronize(c.stream));
     c.n_halo = n_halo;
     c.have_tree = c.have_columns = c.have_gamma = false;
-    free_paths(c);
     return RRT_OK;
 }
 
@@ -582,6 +713,7 @@ int rrt_set_rays(rrt_ctx* x, int32_t n_ray, const double* dirs)
 {
     if (!x) return RRT_E_ARG;
     Ctx& c = x->c;
+    if (int r = need_ws(c)) return r;
     if (n_ray < 1 || n_ray > kMaxRays || !dirs)
         return fail(c, RRT_E_ARG, "n_ray must be 1..%d with a direction array", kMaxRays);
     for (int k = 0; k < n_ray; ++k) {
@@ -590,15 +722,19 @@ int rrt_set_rays(rrt_ctx* x, int32_t n_ray, const double* dirs)
         if (!std::isfinite(nn) || std::fabs(nn - 1.0) > 1e-6)
             return fail(c, RRT_E_ARG, "direction %d is not a unit vector", k);
     }
-    HIP_OK(dalloc(&c.dirs, (size_t)3 * n_ray));
-    HIP_OK(hipMemcpy(c.dirs, dirs, sizeof(double) * 3 * n_ray, hipMemcpyHostToDevice));
-    bool changed = n_ray != c.n_ray;
+    free_paths(c);
+    HIP_OK(ws_alloc(c, &c.dirs, (size_t)3 * n_ray));
+    HIP_OK(hipMemcpyAsync(c.dirs, dirs, sizeof(double) * 3 * n_ray, hipMemcpyHostToDevice,
+                          c.stream));
+    HIP_OK(hipStreamSynchronize(c.stream));
+    const bool changed = n_ray != c.n_ray;
     c.n_ray = n_ray;
     c.geom.n_ray = n_ray;
     c.have_rays = true;
     c.have_columns = c.have_gamma = false;
+    c.counts_valid = false;
     c.fwd_K = -1;
-    free_paths(c);
+    if (changed) free_adjoint(c);
     if (c.have_particles && (changed || !c.N_s)) return alloc_columns(c);
     return RRT_OK;
 }
@@ -647,6 +783,7 @@ int rrt_set_spectrum(rrt_ctx* x, int32_t n_bins, const double* sigma, const doub
 {
     if (!x) return RRT_E_ARG;
     Ctx& c = x->c;
+    if (int r = need_ws(c)) return r;
     if (n_bins < 1 || n_bins > kMaxBins || !sigma || !w)
         return fail(c, RRT_E_ARG, "n_bins must be 1..%d with sigma and w arrays", kMaxBins);
     double smin = INFINITY, wsmax = 0.0, thin = 0.0;
@@ -672,9 +809,10 @@ int rrt_set_spectrum(rrt_ctx* x, int32_t n_bins, const double* sigma, const doub
     }
     int m = (int)rel.size();
     if (m != c.n_bins || !c.ws_rel || !c.srat) {
-        HIP_OK(dalloc(&c.ws_rel, m));
-        HIP_OK(dalloc(&c.dsig_l2, m));
-        HIP_OK(dalloc(&c.srat, m));
+        drop_graph(c);
+        HIP_OK(ws_alloc(c, &c.ws_rel, m));
+        HIP_OK(ws_alloc(c, &c.dsig_l2, m));
+        HIP_OK(ws_alloc(c, &c.srat, m));
     }
     HIP_OK(hipMemcpyAsync(c.ws_rel, rel.data(), sizeof(float) * m, hipMemcpyHostToDevice,
                           c.stream));
@@ -691,8 +829,7 @@ int rrt_set_spectrum(rrt_ctx* x, int32_t n_bins, const double* sigma, const doub
     c.gamma_thin = thin;
     c.sigma_host.assign(sigma, sigma + n_bins);
     c.w_host.assign(w, w + n_bins);
-    if (c.att_tab) (void)hipFree(c.att_tab);     // tabulated for the old spectrum
-    c.att_tab = nullptr;
+    ws_free(c, &c.att_tab);             // tabulated for the old spectrum
     c.all_bins_weighted = (m == n_bins);
     c.have_spectrum = true;
     c.have_gamma = false;
@@ -707,19 +844,22 @@ int rrt_build_tree(rrt_ctx* x)
     if (!c.have_particles) return fail(c, RRT_E_STATE, "rrt_set_particles has not been called");
     if (!c.have_spectrum) return fail(c, RRT_E_STATE, "rrt_set_spectrum must precede the build");
     c.fwd_K = -1;
+    // a new geometry: the recorded paths and their counts no longer apply
+    free_paths(c);
+    c.counts_valid = false;
+    c.have_tree = c.have_columns = c.have_gamma = false;
     ev_begin(c);
     // bounds and validation
     const int nb = (int)std::min<int64_t>(1024, (c.n + 255) / 256);
-    float* part = nullptr;
-    HIP_OK(hipMalloc(&part, sizeof(float) * 8 * nb));
-    hipError_t e = launch_bounds(c, part, nb);
     std::vector<float> hp(8 * nb);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(hp.data(), part, sizeof(float) * 8 * nb, hipMemcpyDeviceToHost,
-                           c.stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
-    (void)hipFree(part);
-    HIP_OK(e);
+    {
+        Scratch<float> part(c);
+        HIP_OK(part.get((size_t)8 * nb));
+        HIP_OK(launch_bounds(c, part.p, nb));
+        HIP_OK(hipMemcpyAsync(hp.data(), part.p, sizeof(float) * 8 * nb, hipMemcpyDeviceToHost,
+                              c.stream));
+        HIP_OK(hipStreamSynchronize(c.stream));
+    }
     float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     float hmax = 0.f, bad = 0.f;
     for (int b = 0; b < nb; ++b) {
@@ -743,14 +883,11 @@ int rrt_build_tree(rrt_ctx* x)
     while ((1 << hb) < c.n_halo) ++hb;
     c.key_bits = c.n_halo > 1 ? (63 - hb) / 3 : 21;
     const double scale = ext > 0.0 ? (double)(1u << c.key_bits) / ext : 0.0;
-    HIP_OK(hipMemsetAsync(c.red + 2, 0, sizeof(unsigned long long), c.stream));
+    HIP_OK(hipMemsetAsync(c.red + kRedBuild, 0, sizeof(unsigned long long), c.stream));
     HIP_OK(launch_morton(c, dlo, scale, c.key_bits));
     HIP_OK(radix_sort_pairs(c, c.codes, c.perm, c.n));
-    if (c.n_halo > 1) {
-        std::vector<int32_t> neg(c.n_halo, -1);
-        HIP_OK(hipMemcpyAsync(c.seg_root, neg.data(), sizeof(int32_t) * c.n_halo,
-                              hipMemcpyHostToDevice, c.stream));
-    }
+    if (c.n_halo > 1)                            // every byte 0xff: -1, no halo root yet
+        HIP_OK(hipMemsetAsync(c.seg_root, 0xff, sizeof(int32_t) * c.n_halo, c.stream));
     HIP_OK(build_radix_tree(c));
     if (c.n_halo > 1) {
         std::vector<int32_t> roots(c.n_halo);
@@ -764,12 +901,12 @@ int rrt_build_tree(rrt_ctx* x)
     int32_t nn = 1;
     if (c.n > 1)
         HIP_OK(hipMemcpyAsync(&nn, c.k_dfs, sizeof(int32_t), hipMemcpyDeviceToHost, c.stream));
-    HIP_OK(hipMemcpyAsync(c.red_host + 2, c.red + 2, sizeof(unsigned long long),
+    HIP_OK(hipMemcpyAsync(c.red_host + kRedBuild, c.red + kRedBuild, sizeof(unsigned long long),
                           hipMemcpyDeviceToHost, c.stream));
     HIP_OK(hipStreamSynchronize(c.stream));
-    if (c.red_host[2] != 0 || nn < 1 || nn > 2 * c.n - 1)
+    if (c.red_host[kRedBuild] != 0 || nn < 1 || nn > 2 * c.n - 1)
         return fail(c, RRT_E_HIP, "tree construction inconsistent (flags %llu, %d nodes)",
-                    (unsigned long long)c.red_host[2], nn);
+                    (unsigned long long)c.red_host[kRedBuild], nn);
     c.n_nodes = nn;
     TraceGeom& g = c.geom;
     g.L = c.prm.l_ray;
@@ -792,14 +929,8 @@ int rrt_build_tree(rrt_ctx* x)
     c.blocks_for = 0;            // the density blocks are in tree order
     HIP_OK(launch_init_state(c, c.x_init_given));
     ev_end(c, &c.t_build);
-    c.paths_valid = false;       // new geometry: the recorded paths no longer apply
-    c.paths_unfit = false;
-    free_tpaths(c);
-    free_tiles(c);
-    c.path_evals = 0;
-    drop_graph(c);
+    if (int r = sync_flags(c)) return r;         // a given x_init out of range
     c.have_tree = true;
-    c.have_columns = c.have_gamma = false;
     return RRT_OK;
 }
 
@@ -808,17 +939,15 @@ int rrt_compute_columns(rrt_ctx* x, double* N_out, int64_t* n_hits_out)
     if (!x) return RRT_E_ARG;
     Ctx& c = x->c;
     if (int r = need_tree(c)) return r;
-    HIP_OK(hipMemsetAsync(c.red + 1, 0, sizeof(unsigned long long), c.stream));
+    HIP_OK(hipMemsetAsync(c.red + kRedHits, 0, sizeof(unsigned long long), c.stream));
     int64_t hits = -1;
     if (int r = columns_impl(c, &hits)) return r;
     if (N_out) HIP_OK(launch_to_input_order_d(c, c.N_s, N_out, c.n_ray));
     if (n_hits_out) {
-        if (hits < 0) {
-            HIP_OK(hipMemcpyAsync(c.red_host + 1, c.red + 1, sizeof(unsigned long long),
-                                  hipMemcpyDeviceToHost, c.stream));
-            HIP_OK(hipStreamSynchronize(c.stream));
-            hits = (int64_t)c.red_host[1];
-        }
+        HIP_OK(hipMemcpyAsync(c.red_host + kRedHits, c.red + kRedHits,
+                              sizeof(unsigned long long), hipMemcpyDeviceToHost, c.stream));
+        if (int r = sync_flags(c)) return r;
+        if (hits < 0) hits = (int64_t)c.red_host[kRedHits];
         *n_hits_out = hits;
     }
     return RRT_OK;
@@ -844,16 +973,16 @@ int rrt_update_equilibrium(rrt_ctx* x, double* x_out, double* max_dx_out)
     Ctx& c = x->c;
     if (int r = need_tree(c)) return r;
     if (!c.have_gamma) return fail(c, RRT_E_STATE, "no rate: call rrt_compute_gamma");
-    HIP_OK(hipMemsetAsync(c.red, 0, sizeof(unsigned long long), c.stream));
+    HIP_OK(hipMemsetAsync(c.red + kRedMaxDx, 0, sizeof(unsigned long long), c.stream));
     HIP_OK(launch_update_x(c));
     c.have_columns = c.have_gamma = false;
     if (x_out) HIP_OK(launch_to_input_order_d(c, c.x_s, x_out, 1));
     if (max_dx_out) {
-        HIP_OK(hipMemcpyAsync(c.red_host, c.red, sizeof(unsigned long long),
-                              hipMemcpyDeviceToHost, c.stream));
-        HIP_OK(hipStreamSynchronize(c.stream));
+        HIP_OK(hipMemcpyAsync(c.red_host + kRedMaxDx, c.red + kRedMaxDx,
+                              sizeof(unsigned long long), hipMemcpyDeviceToHost, c.stream));
+        if (int r = sync_flags(c)) return r;
         double d;
-        std::memcpy(&d, &c.red_host[0], sizeof d);
+        std::memcpy(&d, &c.red_host[kRedMaxDx], sizeof d);
         *max_dx_out = d;
     }
     return RRT_OK;
@@ -922,15 +1051,22 @@ int rrt_set_scheme(rrt_ctx* x, int32_t near_far)
 {
     if (!x) return RRT_E_ARG;
     Ctx& c = x->c;
-    if (near_far < 0 || near_far > 2) return fail(c, RRT_E_ARG, "near_far must be 0, 1 or 2");
+    if (near_far < 0 || near_far > 1) return fail(c, RRT_E_ARG, "near_far must be 0 or 1");
     if (near_far == c.near_far) return RRT_OK;
-    const bool split_changes = (near_far != 0) != (c.near_far != 0);
-    c.near_far = near_far;
-    c.have_gamma = false;             // the rates change; the columns only with the split
-    if (!split_changes) return RRT_OK;
     free_paths(c);                    // recorded entries carry the near flag
-    c.have_columns = false;
-    if (c.n > 0 && c.have_rays) return alloc_columns(c);
+    c.have_columns = c.have_gamma = false;
+    if (c.n > 0 && c.have_rays) {
+        // the near columns take their own buffer; alloc_columns drops the counts
+        const int32_t old = c.near_far;
+        c.near_far = near_far;
+        if (int r = alloc_columns(c)) {
+            c.near_far = old;
+            (void)alloc_columns(c);
+            return r;
+        }
+        return RRT_OK;
+    }
+    c.near_far = near_far;
     return RRT_OK;
 }
 
@@ -984,8 +1120,13 @@ int rrt_iterate_equilibrium(rrt_ctx* x, int32_t max_iter, double tol, double* x_
     WantGuard guard(c);
     int it = 0;
     double mdx = INFINITY;
+    c.conv_tol = tol;
+    c.conv_maxdx.clear();
+    c.conv_abs.clear();
+    c.conv_rel.clear();
     for (it = 0; it < max_iter;) {
-        HIP_OK(hipMemsetAsync(c.red, 0, 2 * sizeof(unsigned long long), c.stream));
+        // the sweep's reductions; the input flags (slots 6, 7) persist until reported
+        HIP_OK(hipMemsetAsync(c.red, 0, kRedInput * sizeof(unsigned long long), c.stream));
         int64_t hits = -1;
         for (int b = 0; b < n_steps; ++b) {
             // one block of the density order (all particles for the
@@ -1006,15 +1147,19 @@ int rrt_iterate_equilibrium(rrt_ctx* x, int32_t max_iter, double tol, double* x_
         c.geom.want = nullptr;
         c.row_list = nullptr;
         c.row_list_n = 0;
-        HIP_OK(hipMemcpyAsync(c.red_host, c.red, 2 * sizeof(unsigned long long),
+        HIP_OK(hipMemcpyAsync(c.red_host, c.red, kRedSlots * sizeof(unsigned long long),
                               hipMemcpyDeviceToHost, c.stream));
         HIP_OK(hipStreamSynchronize(c.stream));
+        if (int r = check_flags(c)) return r;
         ++it;
-        std::memcpy(&mdx, &c.red_host[0], sizeof mdx);
+        std::memcpy(&mdx, &c.red_host[kRedMaxDx], sizeof mdx);
+        c.conv_maxdx.push_back(mdx);
+        c.conv_abs.push_back((int64_t)c.red_host[kRedConvAbs]);
+        c.conv_rel.push_back((int64_t)c.red_host[kRedConvRel]);
         // intersections of the sweep: counted by traversal, or all recorded
         // ones when every ray was evaluated; not counted for masked sweeps
         // over recorded paths
-        c.last_hits = hits < 0 ? (int64_t)c.red_host[1] : (masked ? -1 : hits);
+        c.last_hits = hits < 0 ? (int64_t)c.red_host[kRedHits] : (masked ? -1 : hits);
         if (c.last_hits > 0) c.total_hits += c.last_hits;
         if (mdx < tol) break;
     }
@@ -1046,7 +1191,7 @@ int rrt_evolve(rrt_ctx* x, double dt, int32_t n_steps, double* x_out)
     c.have_columns = c.have_gamma = false;
     if (x_out) {
         HIP_OK(launch_to_input_order_d(c, c.x_s, x_out, 1));
-        HIP_OK(hipStreamSynchronize(c.stream));
+        if (int r = sync_flags(c)) return r;
     }
     return RRT_OK;
 }
@@ -1076,39 +1221,33 @@ int rrt_forward(rrt_ctx* x, int32_t K, double* lnG_out, double* x_out)
                                     "case A update: reset the update rule and the scheme");
     const size_t n = (size_t)c.n;
     if (c.xhist_cap < K + 1 || !c.xhist) {
-        HIP_OK(dalloc(&c.xhist, (size_t)(K + 1) * n));
+        HIP_OK(ws_alloc(c, &c.xhist, (size_t)(K + 1) * n));
         c.xhist_cap = K + 1;
     }
-    // Every iteration's columns are kept for rrt_backward when they take at
-    // most an eighth of the free memory; otherwise it recomputes them from the
-    // kept states.
     const size_t nr = n * (size_t)c.n_ray;
-    c.Nhist_on = c.keep_columns && c.Nhist && c.Nhist_cap >= K;
-    if (!c.Nhist_on) {
-        if (c.Nhist) (void)hipFree(c.Nhist);
-        c.Nhist = nullptr;
-        c.Nhist_cap = 0;
-        size_t fr = 0, tot = 0;
-        HIP_OK(hipMemGetInfo(&fr, &tot));
-        const size_t need = (size_t)K * nr * sizeof(double);
-        if (c.keep_columns && need <= fr / 8) {
-            if (hipMalloc((void**)&c.Nhist, need) == hipSuccess) {
-                c.Nhist_cap = K;
-                c.Nhist_on = true;
-            } else {
-                (void)hipGetLastError();
-                c.Nhist = nullptr;
-            }
-        }
-    }
     c.fwd_K = -1;
     HIP_OK(launch_init_state(c, false));
     HIP_OK(hipMemcpyAsync(c.xhist, c.x_s, sizeof(double) * n, hipMemcpyDeviceToDevice,
                           c.stream));
     for (int k = 1; k <= K; ++k) {
-        HIP_OK(hipMemsetAsync(c.red, 0, 2 * sizeof(unsigned long long), c.stream));
+        HIP_OK(hipMemsetAsync(c.red, 0, kRedInput * sizeof(unsigned long long), c.stream));
         int64_t hits = -1;
         if (int r = columns_impl(c, &hits)) return r;
+        if (k == 1) {
+            // Every iteration's columns are kept for rrt_backward when they fit
+            // in the path buffer beside the paths (recorded by the evaluation
+            // just made); otherwise it recomputes them from the kept states.
+            c.Nhist_on = c.keep_columns && c.Nhist && c.Nhist_cap >= K;
+            if (!c.Nhist_on) {
+                ws_free(c, &c.Nhist);
+                c.Nhist_cap = 0;
+                if (c.keep_columns &&
+                    ws_alloc(c, &c.Nhist, (size_t)K * nr, kRegionPath) == hipSuccess) {
+                    c.Nhist_cap = K;
+                    c.Nhist_on = true;
+                }
+            }
+        }
         if (c.Nhist_on)
             HIP_OK(hipMemcpyAsync(c.Nhist + (size_t)(k - 1) * nr, c.N_s, sizeof(double) * nr,
                                   hipMemcpyDeviceToDevice, c.stream));
@@ -1135,20 +1274,21 @@ int rrt_backward(rrt_ctx* x, const double* dL_dlnG, const double* dL_dx, double*
     const size_t n = (size_t)c.n, nr = n * (size_t)c.n_ray;
     const int64_t waves = adj_waves(c);
     if (!c.adj_lam || c.adj_n != n || c.adj_nr != nr) {
-        HIP_OK(dalloc(&c.adj_lam, n));
-        HIP_OK(dalloc(&c.adj_lup, n));
-        HIP_OK(dalloc(&c.adj_gnH, n));
-        HIP_OK(dalloc(&c.adj_y, n));
-        HIP_OK(dalloc(&c.adj_nu, nr));
-        HIP_OK(dalloc(&c.adj_pis, nr));
-        HIP_OK(dalloc(&c.adj_st, nr));
-        HIP_OK(dalloc(&c.adj_ell, n));
-        HIP_OK(dalloc(&c.adj_tpart, (size_t)waves));
+        c.adj_n = c.adj_nr = 0;
+        HIP_OK(ws_alloc(c, &c.adj_lam, n));
+        HIP_OK(ws_alloc(c, &c.adj_lup, n));
+        HIP_OK(ws_alloc(c, &c.adj_gnH, n));
+        HIP_OK(ws_alloc(c, &c.adj_y, n));
+        HIP_OK(ws_alloc(c, &c.adj_nu, nr));
+        HIP_OK(ws_alloc(c, &c.adj_pis, nr));
+        HIP_OK(ws_alloc(c, &c.adj_st, nr));
+        HIP_OK(ws_alloc(c, &c.adj_ell, n));
+        HIP_OK(ws_alloc(c, &c.adj_tpart, (size_t)waves));
         c.adj_n = n;
         c.adj_nr = nr;
     }
-    HIP_OK(dalloc(&c.adj_wpart, (size_t)adj_chunks(c) * c.n_bins));
-    HIP_OK(dalloc(&c.adj_gw, (size_t)c.n_bins));
+    HIP_OK(ws_alloc(c, &c.adj_wpart, (size_t)adj_chunks(c) * c.n_bins));
+    HIP_OK(ws_alloc(c, &c.adj_gw, (size_t)c.n_bins));
     HIP_OK(hipMemsetAsync(c.adj_gw, 0, sizeof(double) * c.n_bins, c.stream));
     HIP_OK(hipMemsetAsync(c.adj_gnH, 0, sizeof(double) * n, c.stream));
     if (dL_dx) HIP_OK(launch_from_input_order_d(c, dL_dx, c.adj_lam));
@@ -1171,15 +1311,11 @@ int rrt_backward(rrt_ctx* x, const double* dL_dlnG, const double* dL_dx, double*
         HIP_OK(launch_adj_rate(c, Nk, (k == K && dL_dlnG) ? c.adj_lup : nullptr));
         if (c.paths_valid && !c.tpaths_valid && !c.tpaths_unfit && c.adj_scatter == 0) {
             // transposed paths (8 B per intersection) plus sort scratch (24 B)
-            size_t fr = 0, tot = 0;
-            HIP_OK(hipMemGetInfo(&fr, &tot));
-            const size_t need = (size_t)c.path_hits * 32 + (size_t)c.n * 8 + (64u << 20);
-            if (need < fr / 2 + fr / 4) {
-                HIP_OK(build_transposed_paths(c));
-                c.tpaths_valid = true;
-            } else {
-                c.tpaths_unfit = true;
-            }
+            // in the path buffer, when they fit beside the paths
+            const hipError_t e = build_transposed_paths(c);
+            if (e == hipSuccess) c.tpaths_valid = true;
+            else if (e == hipErrorOutOfMemory) c.tpaths_unfit = true;
+            else HIP_OK(e);
         }
         // without transposed paths: accumulate per row tile in LDS when the
         // tiles can be built and fit (one global atomic per distinct particle
@@ -1212,7 +1348,7 @@ int rrt_backward(rrt_ctx* x, const double* dL_dlnG, const double* dL_dx, double*
     HIP_OK(hipMemcpyAsync(c.x_s, c.xhist + (size_t)K * n, sizeof(double) * n,
                           hipMemcpyDeviceToDevice, c.stream));
     HIP_OK(launch_mux(c));
-    HIP_OK(hipStreamSynchronize(c.stream));
+    if (int r = sync_flags(c)) return r;
     double thin = 0.0;
     for (double v : tp) thin += v;
     if (dL_dw)
@@ -1228,12 +1364,12 @@ namespace {
 int ensure_seg_buffers(Ctx& c)
 {
     if (c.n_halo == 1 && (!c.seg_root || !c.seg_active)) {
-        HIP_OK(dalloc(&c.seg_root, 1));
-        HIP_OK(dalloc(&c.seg_end, 1));
-        HIP_OK(dalloc(&c.seg_active, 1));
-        HIP_OK(dalloc(&c.seg_maxdx, 1));
-        HIP_OK(dalloc(&c.seg_iters, 1));
-        if (!c.seg_state) HIP_OK(dalloc(&c.seg_state, 4));
+        HIP_OK(ws_alloc(c, &c.seg_root, 1));
+        HIP_OK(ws_alloc(c, &c.seg_end, 1));
+        HIP_OK(ws_alloc(c, &c.seg_active, 1));
+        HIP_OK(ws_alloc(c, &c.seg_maxdx, 1));
+        HIP_OK(ws_alloc(c, &c.seg_iters, 1));
+        if (!c.seg_state) HIP_OK(ws_alloc(c, &c.seg_state, 4));
         if (!c.seg_state_host)
             HIP_OK(hipHostMalloc((void**)&c.seg_state_host, 4 * sizeof(int32_t)));
     }
@@ -1338,31 +1474,26 @@ int run_active_halos(Ctx& c, double tol, int32_t max_iter, int32_t per_launch)
 
 // Which halos can share recorded paths: per-halo intersection totals from one
 // count pass, packed first-fit by decreasing size into groups whose paths fit
-// the budget.  A halo too large for the budget alone forms a group that
+// the path buffer.  A halo too large for it alone forms a group that
 // traverses every iteration.  Counts stay in row_cnt for the per-group offsets.
 int plan_groups(Ctx& c, uint64_t* row_cnt, std::vector<std::vector<int>>& groups,
                 std::vector<bool>& recordable, uint64_t& max_group)
 {
     const int nh = c.n_halo;
-    unsigned long long* d_hits = nullptr;
-    HIP_OK(hipMalloc(&d_hits, sizeof(unsigned long long) * nh));
-    hipError_t e = hipMemsetAsync(d_hits, 0, sizeof(unsigned long long) * nh, c.stream);
-    if (e == hipSuccess) e = launch_count_hits(c, row_cnt);
-    if (e == hipSuccess) e = launch_halo_hits(c, row_cnt, d_hits);
     std::vector<unsigned long long> hits(nh);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(hits.data(), d_hits, sizeof(unsigned long long) * nh,
-                           hipMemcpyDeviceToHost, c.stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
-    (void)hipFree(d_hits);
-    HIP_OK(e);
-    size_t budget = (size_t)c.prm.path_budget;
-    if (budget == 0) {
-        size_t fr = 0, tot = 0;
-        HIP_OK(hipMemGetInfo(&fr, &tot));
-        budget = fr / 2 + (c.path ? (size_t)c.path_cap * sizeof(int2) / 2 : 0);
+    {
+        Scratch<unsigned long long> d_hits(c);
+        HIP_OK(d_hits.get((size_t)nh));
+        HIP_OK(hipMemsetAsync(d_hits.p, 0, sizeof(unsigned long long) * nh, c.stream));
+        HIP_OK(launch_count_hits(c, row_cnt));
+        HIP_OK(launch_halo_hits(c, row_cnt, d_hits.p));
+        HIP_OK(hipMemcpyAsync(hits.data(), d_hits.p, sizeof(unsigned long long) * nh,
+                              hipMemcpyDeviceToHost, c.stream));
+        HIP_OK(hipStreamSynchronize(c.stream));
     }
-    const uint64_t cap = budget / sizeof(int2);
+    // entries the path buffer holds (with the padding of one array)
+    const uint64_t room = c.arena.cap[kRegionPath] / sizeof(int2);
+    const uint64_t cap = room > (uint64_t)kPathPad + kWsAlign ? room - kPathPad - kWsAlign : 0;
     std::vector<int> order(nh);
     for (int h = 0; h < nh; ++h) order[h] = h;
     std::stable_sort(order.begin(), order.end(),
@@ -1411,6 +1542,73 @@ int plan_groups(Ctx& c, uint64_t* row_cnt, std::vector<std::vector<int>>& groups
     return RRT_OK;
 }
 
+// Halos in groups whose recorded paths fit the path buffer, one group after
+// another (the paths held one group at a time are not valid for the batch).
+int run_groups(Ctx& c, double tol, int32_t max_iter, int32_t per_launch)
+{
+    const int64_t n_rows = c.n * (int64_t)c.n_ray;
+    Scratch<uint64_t> row_cnt(c);
+    Scratch<int32_t> d_mask(c);
+    HIP_OK(row_cnt.get((size_t)n_rows));
+    HIP_OK(d_mask.get((size_t)c.n_halo));
+    std::vector<std::vector<int>> groups;
+    std::vector<bool> recordable;
+    uint64_t max_group = 0;
+    if (int r = plan_groups(c, row_cnt.p, groups, recordable, max_group)) return r;
+    if (groups.size() == 1 && recordable[0]) {
+        // all paths fit: keep the counts, so the first iteration records them
+        // with one walk
+        HIP_OK(hipMemcpyAsync(c.row_off, row_cnt.p, sizeof(uint64_t) * n_rows,
+                              hipMemcpyDeviceToDevice, c.stream));
+        HIP_OK(hipMemsetAsync(c.row_off + n_rows, 0, sizeof(uint64_t), c.stream));
+        HIP_OK(scan_exclusive_u64(c, c.row_off, c.row_off, n_rows + 1));
+        HIP_OK(hipMemcpyAsync(&c.count_total, c.row_off + n_rows, sizeof(uint64_t),
+                              hipMemcpyDeviceToHost, c.stream));
+        HIP_OK(hipStreamSynchronize(c.stream));
+        c.counts_valid = true;
+        return run_active_halos(c, tol, max_iter, per_launch);
+    }
+    free_paths(c);
+    c.counts_valid = false;            // row_off takes each group's offsets
+    if (max_group > 0) HIP_OK(ws_alloc(c, &c.path, (size_t)max_group + kPathPad, kRegionPath));
+    c.path_cap = max_group;
+    std::vector<int32_t> mask(c.n_halo);
+    int r = RRT_OK;
+    for (size_t g = 0; g < groups.size() && r == RRT_OK; ++g) {
+        std::fill(mask.begin(), mask.end(), 0);
+        for (int h : groups[g]) mask[h] = 1;
+        HIP_OK(hipMemcpyAsync(d_mask.p, mask.data(), sizeof(int32_t) * c.n_halo,
+                              hipMemcpyHostToDevice, c.stream));
+        HIP_OK(launch_seg_group_init(c, d_mask.p));
+        if (recordable[g]) {
+            uint64_t total = 0;
+            HIP_OK(launch_mask_rows(c, row_cnt.p, d_mask.p, c.row_off));
+            HIP_OK(hipMemsetAsync(c.row_off + n_rows, 0, sizeof(uint64_t), c.stream));
+            HIP_OK(scan_exclusive_u64(c, c.row_off, c.row_off, n_rows + 1));
+            HIP_OK(hipMemcpyAsync(&total, c.row_off + n_rows, sizeof total,
+                                  hipMemcpyDeviceToHost, c.stream));
+            HIP_OK(hipStreamSynchronize(c.stream));      // also: mask is read
+            // record only this group's rays: they are the active ones; tiles
+            // and transposed paths of the previous group go
+            free_tpaths(c);
+            free_tiles(c);
+            HIP_OK(launch_record_paths(c, c.row_off, c.path, total));
+            if (!c.paths_valid) drop_graph(c);           // the graph held traversals
+            c.paths_valid = true;
+            c.paths_unfit = false;
+            c.path_hits = (int64_t)total;
+        } else {
+            HIP_OK(hipStreamSynchronize(c.stream));      // mask is read
+            if (c.paths_valid) drop_graph(c);            // the graph held path products
+            c.paths_valid = false;
+            c.paths_unfit = true;
+        }
+        r = run_active_halos(c, tol, max_iter, per_launch);
+    }
+    free_paths(c);
+    return r;
+}
+
 }  // namespace
 
 int rrt_iterate_halos(rrt_ctx* x, int32_t max_iter, double tol, int32_t per_launch, double* x_out,
@@ -1427,87 +1625,26 @@ int rrt_iterate_halos(rrt_ctx* x, int32_t max_iter, double tol, int32_t per_laun
     if (int r = ensure_seg_buffers(c)) return r;
     SegGuard guard(c);
     HIP_OK(launch_seg_init(c));
-    if (c.paths_valid || c.paths_unfit || c.prm.record_paths == 0 || c.n_halo == 1) {
-        // one group: every halo at once (recording, if any, happens in the first iteration)
-        if (int r = run_active_halos(c, tol, max_iter, per_launch)) return r;
-    } else {
-        const int64_t n_rows = c.n * (int64_t)c.n_ray;
-        uint64_t* row_cnt = nullptr;
-        HIP_OK(hipMalloc(&row_cnt, sizeof(uint64_t) * n_rows));
-        std::vector<std::vector<int>> groups;
-        std::vector<bool> recordable;
-        uint64_t max_group = 0;
-        int r = plan_groups(c, row_cnt, groups, recordable, max_group);
-        if (r == RRT_OK && groups.size() == 1 && recordable[0]) {
-            (void)hipFree(row_cnt);
-            row_cnt = nullptr;
-            r = run_active_halos(c, tol, max_iter, per_launch);   // all paths fit
-        } else if (r == RRT_OK) {
-            // halos in groups whose recorded paths fit, one group after another
-            int32_t* d_mask = nullptr;
-            hipError_t e = hipMalloc(&d_mask, sizeof(int32_t) * c.n_halo);
-            if (e == hipSuccess) e = dalloc(&c.row_off, (size_t)n_rows + 1);
-            if (e == hipSuccess && max_group > 0 && (max_group > c.path_cap || !c.path)) {
-                drop_graph(c);
-                e = dalloc(&c.path, (size_t)max_group + kPathPad);
-                c.path_cap = e == hipSuccess ? max_group : 0;
-            }
-            std::vector<int32_t> mask(c.n_halo);
-            for (size_t g = 0; g < groups.size() && e == hipSuccess && r == RRT_OK; ++g) {
-                std::fill(mask.begin(), mask.end(), 0);
-                for (int h : groups[g]) mask[h] = 1;
-                e = hipMemcpyAsync(d_mask, mask.data(), sizeof(int32_t) * c.n_halo,
-                                   hipMemcpyHostToDevice, c.stream);
-                if (e == hipSuccess) e = launch_seg_group_init(c, d_mask);
-                if (e != hipSuccess) break;
-                if (recordable[g]) {
-                    uint64_t total = 0;
-                    e = launch_mask_rows(c, row_cnt, d_mask, c.row_off);
-                    if (e == hipSuccess)
-                        e = hipMemsetAsync(c.row_off + n_rows, 0, sizeof(uint64_t), c.stream);
-                    if (e == hipSuccess) e = scan_exclusive_u64(c, c.row_off, c.row_off, n_rows + 1);
-                    if (e == hipSuccess)
-                        e = hipMemcpyAsync(&total, c.row_off + n_rows, sizeof total,
-                                           hipMemcpyDeviceToHost, c.stream);
-                    if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
-                    if (e == hipSuccess) {
-                        // record only this group's rays: they are the active ones;
-                        // tiles and transposed paths of the previous group go
-                        free_tpaths(c);
-                        free_tiles(c);
-                        e = launch_record_paths(c, c.row_off, c.path, total);
-                    }
-                    if (!c.paths_valid) drop_graph(c);     // the graph held traversals
-                    c.paths_valid = true;
-                    c.paths_unfit = false;
-                    c.path_hits = (int64_t)total;
-                } else {
-                    if (c.paths_valid) drop_graph(c);      // the graph held path products
-                    c.paths_valid = false;
-                    c.paths_unfit = true;
-                }
-                if (e == hipSuccess) r = run_active_halos(c, tol, max_iter, per_launch);
-            }
-            // the recorded paths held one group only: not valid for the whole batch
-            c.paths_valid = false;
-            c.paths_unfit = false;
-            c.path_hits = 0;
-            free_tpaths(c);
-            free_tiles(c);
-            drop_graph(c);
-            if (d_mask) (void)hipFree(d_mask);
-            if (row_cnt) (void)hipFree(row_cnt);
-            row_cnt = nullptr;
-            HIP_OK(e);
-        }
-        if (row_cnt) (void)hipFree(row_cnt);
-        if (r != RRT_OK) return r;
+    c.conv_tol = tol;
+    // one group (every halo at once; the recording, if any, happens in the
+    // first iteration) when the batch's paths need not be recorded or are
+    // known to fit (counted, or a previous recording of this size fitted),
+    // else groups after a count of each halo's intersections
+    bool grouped = false;
+    if (c.prm.record_paths != 0 && c.n_halo > 1 && !c.paths_valid && !c.paths_unfit &&
+        c.arena.base[kRegionPath]) {
+        const uint64_t gap = ws_largest_gap(c, kRegionPath);
+        if (c.counts_valid) grouped = path_bytes(c.count_total) > gap;
+        else grouped = !(c.last_total > 0 && path_bytes(c.last_total) <= gap);
     }
+    if (int r = grouped ? run_groups(c, tol, max_iter, per_launch)
+                        : run_active_halos(c, tol, max_iter, per_launch))
+        return r;
     std::vector<int32_t> its(c.n_halo);
     HIP_OK(hipMemcpyAsync(its.data(), c.seg_iters, sizeof(int32_t) * c.n_halo,
                           hipMemcpyDeviceToHost, c.stream));
     if (x_out) HIP_OK(launch_to_input_order_d(c, c.x_s, x_out, 1));
-    HIP_OK(hipStreamSynchronize(c.stream));
+    if (int r = sync_flags(c)) return r;
     c.have_columns = c.have_gamma = false;
     bool capped = false;
     for (int h = 0; h < c.n_halo; ++h) {
@@ -1573,7 +1710,7 @@ int rrt_set_state(rrt_ctx* x, const double* xs)
     Ctx& c = x->c;
     if (!c.have_tree) return fail(c, RRT_E_STATE, "rrt_build_tree has not been called");
     if (xs) {
-        HIP_OK(launch_from_input_order_d(c, xs, c.x_s));
+        HIP_OK(launch_state_from_input(c, xs));          // flags values outside [0, 1]
         HIP_OK(launch_mux(c));
     } else {
         HIP_OK(launch_init_state(c, false));
@@ -1643,22 +1780,16 @@ int rrt_get_hits(rrt_ctx* x, int64_t cap, int64_t* row_off, int32_t* hit_j, int3
     Ctx& c = x->c;
     if (int r = need_tree(c)) return r;
     const int64_t nr = c.n * (int64_t)c.n_ray;
-    uint64_t* cnt = nullptr;
-    HIP_OK(hipMalloc(&cnt, sizeof(uint64_t) * nr));
-    int rc = RRT_OK;
+    Scratch<uint64_t> cnt(c);
+    HIP_OK(cnt.get((size_t)nr));
     std::vector<uint64_t> hc(nr);
     std::vector<int32_t> perm(c.n);
-    hipError_t e = launch_count_hits(c, cnt);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(hc.data(), cnt, sizeof(uint64_t) * nr, hipMemcpyDeviceToHost, c.stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(perm.data(), c.perm, sizeof(int32_t) * c.n, hipMemcpyDeviceToHost,
-                           c.stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
-    if (e != hipSuccess) {
-        (void)hipFree(cnt);
-        return fail(c, RRT_E_HIP, "hit counting failed: %s", hipGetErrorString(e));
-    }
+    HIP_OK(launch_count_hits(c, cnt.p));
+    HIP_OK(hipMemcpyAsync(hc.data(), cnt.p, sizeof(uint64_t) * nr, hipMemcpyDeviceToHost,
+                          c.stream));
+    HIP_OK(hipMemcpyAsync(perm.data(), c.perm, sizeof(int32_t) * c.n, hipMemcpyDeviceToHost,
+                          c.stream));
+    HIP_OK(hipStreamSynchronize(c.stream));
     // rows in input order (p, k); internal ray id = k * n + tree position
     std::vector<uint64_t> in_cnt(nr);
     for (int64_t k = 0; k < c.n_ray; ++k)
@@ -1666,29 +1797,255 @@ int rrt_get_hits(rrt_ctx* x, int64_t cap, int64_t* row_off, int32_t* hit_j, int3
     row_off[0] = 0;
     for (int64_t r = 0; r < nr; ++r) row_off[r + 1] = row_off[r] + (int64_t)in_cnt[r];
     const int64_t total = row_off[nr];
-    if (total > cap || !hit_j || !hit_img) {
-        (void)hipFree(cnt);
+    if (total > cap || !hit_j || !hit_img)
         return total > cap ? fail(c, RRT_E_CAPACITY, "%lld hits, capacity %lld",
                                   (long long)total, (long long)cap)
                            : RRT_OK;
-    }
     for (int64_t k = 0; k < c.n_ray; ++k)
         for (int64_t i = 0; i < c.n; ++i) hc[k * c.n + i] = row_off[(int64_t)perm[i] * c.n_ray + k];
-    int32_t *dj = nullptr, *di = nullptr;
-    e = hipMemcpyAsync(cnt, hc.data(), sizeof(uint64_t) * nr, hipMemcpyHostToDevice, c.stream);
-    if (e == hipSuccess) e = hipMalloc(&dj, sizeof(int32_t) * std::max<int64_t>(total, 1));
-    if (e == hipSuccess) e = hipMalloc(&di, sizeof(int32_t) * std::max<int64_t>(total, 1));
-    if (e == hipSuccess) e = launch_record_hits(c, cnt, dj, di, (uint64_t)total);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(hit_j, dj, sizeof(int32_t) * total, hipMemcpyDeviceToHost, c.stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(hit_img, di, sizeof(int32_t) * total, hipMemcpyDeviceToHost, c.stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
-    if (e != hipSuccess) rc = fail(c, RRT_E_HIP, "hit recording failed: %s", hipGetErrorString(e));
-    (void)hipFree(cnt);
-    if (dj) (void)hipFree(dj);
-    if (di) (void)hipFree(di);
-    return rc;
+    Scratch<int32_t> dj(c), di(c);
+    HIP_OK(dj.get((size_t)std::max<int64_t>(total, 1)));
+    HIP_OK(di.get((size_t)std::max<int64_t>(total, 1)));
+    HIP_OK(hipMemcpyAsync(cnt.p, hc.data(), sizeof(uint64_t) * nr, hipMemcpyHostToDevice,
+                          c.stream));
+    HIP_OK(launch_record_hits(c, cnt.p, dj.p, di.p, (uint64_t)total));
+    HIP_OK(hipMemcpyAsync(hit_j, dj.p, sizeof(int32_t) * total, hipMemcpyDeviceToHost, c.stream));
+    HIP_OK(hipMemcpyAsync(hit_img, di.p, sizeof(int32_t) * total, hipMemcpyDeviceToHost,
+                          c.stream));
+    HIP_OK(hipStreamSynchronize(c.stream));
+    return RRT_OK;
+}
+
+namespace {
+
+// Tree positions of the given input indices; RRT_E_ARG for an index out of
+// range or repeated.
+int tree_positions(Ctx& c, int32_t n_src, const int64_t* src, std::vector<int32_t>& pos)
+{
+    if (n_src < 1 || n_src > 4096 || !src)
+        return fail(c, RRT_E_ARG, "1..4096 source particles are required");
+    std::vector<int32_t> perm(c.n);
+    HIP_OK(hipMemcpyAsync(perm.data(), c.perm, sizeof(int32_t) * c.n, hipMemcpyDeviceToHost,
+                          c.stream));
+    HIP_OK(hipStreamSynchronize(c.stream));
+    std::vector<int32_t> inv(c.n, -1);
+    for (int64_t i = 0; i < c.n; ++i) inv[perm[i]] = (int32_t)i;
+    pos.resize(n_src);
+    for (int32_t i = 0; i < n_src; ++i) {
+        if (src[i] < 0 || src[i] >= c.n)
+            return fail(c, RRT_E_ARG, "source %lld out of range", (long long)src[i]);
+        pos[i] = inv[src[i]];
+    }
+    std::vector<int32_t> srt(pos);
+    std::sort(srt.begin(), srt.end());
+    if (std::adjacent_find(srt.begin(), srt.end()) != srt.end())
+        return fail(c, RRT_E_ARG, "a source is listed twice");
+    return RRT_OK;
+}
+
+}  // namespace
+
+int rrt_get_hits_rows(rrt_ctx* x, int32_t n_src, const int64_t* src, int64_t cap,
+                      int64_t* row_off, int32_t* hit_j, int32_t* hit_img, float* hit_fac)
+{
+    if (!x) return RRT_E_ARG;
+    Ctx& c = x->c;
+    if (int r = need_tree(c)) return r;
+    if (!row_off) return fail(c, RRT_E_ARG, "row_off is required");
+    std::vector<int32_t> pos;
+    if (int r = tree_positions(c, n_src, src, pos)) return r;
+    // the walk takes the sources in tree order: slot s holds sorted position s
+    std::vector<int32_t> sorted(pos);
+    std::sort(sorted.begin(), sorted.end());
+    std::vector<int32_t> slot_of(n_src);           // caller's source i -> slot
+    for (int32_t i = 0; i < n_src; ++i)
+        slot_of[i] = (int32_t)(std::lower_bound(sorted.begin(), sorted.end(), pos[i]) -
+                               sorted.begin());
+    const int nr = c.n_ray;
+    const size_t rows = (size_t)n_src * nr;
+    Scratch<int32_t> d_list(c);
+    Scratch<uint64_t> d_cnt(c);
+    HIP_OK(d_list.get((size_t)n_src));
+    HIP_OK(d_cnt.get(rows + 1));
+    HIP_OK(hipMemcpyAsync(d_list.p, sorted.data(), sizeof(int32_t) * n_src,
+                          hipMemcpyHostToDevice, c.stream));
+    HIP_OK(launch_count_rows(c, d_list.p, n_src, d_cnt.p));
+    std::vector<uint64_t> cnt(rows);
+    HIP_OK(hipMemcpyAsync(cnt.data(), d_cnt.p, sizeof(uint64_t) * rows, hipMemcpyDeviceToHost,
+                          c.stream));
+    HIP_OK(hipStreamSynchronize(c.stream));
+    // offsets in the caller's order, and in slot order for the device
+    row_off[0] = 0;
+    for (int32_t i = 0; i < n_src; ++i)
+        for (int k = 0; k < nr; ++k) {
+            const size_t r = (size_t)i * nr + k;
+            row_off[r + 1] = row_off[r] + (int64_t)cnt[(size_t)slot_of[i] * nr + k];
+        }
+    const int64_t total = row_off[rows];
+    if (!hit_j || !hit_img) return RRT_OK;
+    if (total > cap)
+        return fail(c, RRT_E_CAPACITY, "%lld hits, capacity %lld", (long long)total,
+                    (long long)cap);
+    std::vector<uint64_t> dev_off(rows + 1);
+    for (int32_t i = 0; i < n_src; ++i)
+        for (int k = 0; k < nr; ++k)
+            dev_off[(size_t)slot_of[i] * nr + k] = (uint64_t)row_off[(size_t)i * nr + k];
+    dev_off[rows] = (uint64_t)total;
+    Scratch<int32_t> dj(c), di(c);
+    Scratch<float> df(c);
+    HIP_OK(dj.get((size_t)std::max<int64_t>(total, 1)));
+    HIP_OK(di.get((size_t)std::max<int64_t>(total, 1)));
+    HIP_OK(df.get((size_t)std::max<int64_t>(total, 1)));
+    HIP_OK(hipMemcpyAsync(d_cnt.p, dev_off.data(), sizeof(uint64_t) * (rows + 1),
+                          hipMemcpyHostToDevice, c.stream));
+    HIP_OK(launch_record_rows(c, d_list.p, n_src, d_cnt.p, dj.p, di.p, df.p, (uint64_t)total));
+    HIP_OK(hipMemcpyAsync(hit_j, dj.p, sizeof(int32_t) * total, hipMemcpyDeviceToHost, c.stream));
+    HIP_OK(hipMemcpyAsync(hit_img, di.p, sizeof(int32_t) * total, hipMemcpyDeviceToHost,
+                          c.stream));
+    if (hit_fac)
+        HIP_OK(hipMemcpyAsync(hit_fac, df.p, sizeof(float) * total, hipMemcpyDeviceToHost,
+                              c.stream));
+    HIP_OK(hipStreamSynchronize(c.stream));
+    return RRT_OK;
+}
+
+int rrt_get_path_rows(rrt_ctx* x, int32_t n_src, const int64_t* src, int64_t cap,
+                      int64_t* row_off, int32_t* hit_j, float* hit_fac)
+{
+    if (!x) return RRT_E_ARG;
+    Ctx& c = x->c;
+    if (int r = need_tree(c)) return r;
+    if (!row_off) return fail(c, RRT_E_ARG, "row_off is required");
+    if (!c.paths_valid) return fail(c, RRT_E_STATE, "no recorded paths");
+    std::vector<int32_t> pos;
+    if (int r = tree_positions(c, n_src, src, pos)) return r;
+    const int nr = c.n_ray;
+    const int m = n_src * nr;
+    std::vector<int64_t> rows((size_t)m);
+    for (int32_t i = 0; i < n_src; ++i)
+        for (int k = 0; k < nr; ++k) rows[(size_t)i * nr + k] = (int64_t)k * c.n + pos[i];
+    Scratch<int64_t> d_rows(c);
+    Scratch<uint64_t> d_cnt(c);
+    HIP_OK(d_rows.get((size_t)m));
+    HIP_OK(d_cnt.get((size_t)m + 1));
+    HIP_OK(hipMemcpyAsync(d_rows.p, rows.data(), sizeof(int64_t) * m, hipMemcpyHostToDevice,
+                          c.stream));
+    HIP_OK(launch_path_rows(c, d_rows.p, m, d_cnt.p, nullptr, nullptr, nullptr));
+    std::vector<uint64_t> cnt((size_t)m + 1);
+    HIP_OK(hipMemcpyAsync(cnt.data(), d_cnt.p, sizeof(uint64_t) * m, hipMemcpyDeviceToHost,
+                          c.stream));
+    HIP_OK(hipStreamSynchronize(c.stream));
+    row_off[0] = 0;
+    for (int r = 0; r < m; ++r) row_off[r + 1] = row_off[r] + (int64_t)cnt[r];
+    const int64_t total = row_off[m];
+    if (!hit_j || !hit_fac) return RRT_OK;
+    if (total > cap)
+        return fail(c, RRT_E_CAPACITY, "%lld entries, capacity %lld", (long long)total,
+                    (long long)cap);
+    for (int r = 0; r <= m; ++r) cnt[r] = (uint64_t)row_off[r];
+    Scratch<int32_t> dj(c);
+    Scratch<float> df(c);
+    HIP_OK(dj.get((size_t)std::max<int64_t>(total, 1)));
+    HIP_OK(df.get((size_t)std::max<int64_t>(total, 1)));
+    HIP_OK(hipMemcpyAsync(d_cnt.p, cnt.data(), sizeof(uint64_t) * (m + 1), hipMemcpyHostToDevice,
+                          c.stream));
+    HIP_OK(launch_path_rows(c, d_rows.p, m, nullptr, d_cnt.p, dj.p, df.p));
+    HIP_OK(hipMemcpyAsync(hit_j, dj.p, sizeof(int32_t) * total, hipMemcpyDeviceToHost, c.stream));
+    HIP_OK(hipMemcpyAsync(hit_fac, df.p, sizeof(float) * total, hipMemcpyDeviceToHost, c.stream));
+    HIP_OK(hipStreamSynchronize(c.stream));
+    return RRT_OK;
+}
+
+int rrt_get_halo_roots(rrt_ctx* x, int32_t* root, int32_t* end)
+{
+    if (!x) return RRT_E_ARG;
+    Ctx& c = x->c;
+    if (!c.have_tree) return fail(c, RRT_E_STATE, "rrt_build_tree has not been called");
+    if (!root || !end) return fail(c, RRT_E_ARG, "root and end are required");
+    if (c.n_halo == 1) {
+        root[0] = 0;
+        end[0] = (int32_t)c.n_nodes;
+        return RRT_OK;
+    }
+    HIP_OK(hipMemcpyAsync(root, c.seg_root, sizeof(int32_t) * c.n_halo, hipMemcpyDeviceToHost,
+                          c.stream));
+    HIP_OK(hipMemcpyAsync(end, c.seg_end, sizeof(int32_t) * c.n_halo, hipMemcpyDeviceToHost,
+                          c.stream));
+    HIP_OK(hipStreamSynchronize(c.stream));
+    return RRT_OK;
+}
+
+int rrt_count_paths(rrt_ctx* x, int64_t* n_hits, size_t* bytes_paths, size_t* bytes_one_walk)
+{
+    if (!x) return RRT_E_ARG;
+    Ctx& c = x->c;
+    if (int r = need_tree(c)) return r;
+    const int64_t n_rows = c.n * (int64_t)c.n_ray;
+    if (!c.counts_valid) {
+        HIP_OK(launch_count_hits(c, c.row_off));
+        HIP_OK(hipMemsetAsync(c.row_off + n_rows, 0, sizeof(uint64_t), c.stream));
+        HIP_OK(scan_exclusive_u64(c, c.row_off, c.row_off, n_rows + 1));
+        HIP_OK(hipMemcpyAsync(&c.count_total, c.row_off + n_rows, sizeof(uint64_t),
+                              hipMemcpyDeviceToHost, c.stream));
+        HIP_OK(hipStreamSynchronize(c.stream));
+        c.counts_valid = true;
+    }
+    const uint64_t total = c.count_total;
+    if (c.last_total == 0) c.last_total = total;      // sizes the next one-walk pool
+    if (n_hits) *n_hits = (int64_t)total;
+    if (bytes_paths) *bytes_paths = (size_t)path_bytes(total);
+    if (bytes_one_walk) {
+        Ctx probe;                                      // the pool sizing at this count
+        probe.pool_cap = c.pool_cap;
+        probe.pool_scale = c.pool_scale;
+        *bytes_one_walk =
+            (size_t)(path_bytes(total) + pool_bytes(pool_chunks_for(probe, total, n_rows), n_rows));
+    }
+    return RRT_OK;
+}
+
+int rrt_get_convergence(rrt_ctx* x, int32_t cap, int32_t* n_sweeps, double* max_dx,
+                        int64_t* n_abs, int64_t* n_rel)
+{
+    if (!x || cap < 0) return RRT_E_ARG;
+    const Ctx& c = x->c;
+    const int32_t m = (int32_t)c.conv_maxdx.size();
+    if (n_sweeps) *n_sweeps = m;
+    for (int32_t s = 0; s < std::min(m, cap); ++s) {
+        if (max_dx) max_dx[s] = c.conv_maxdx[s];
+        if (n_abs) n_abs[s] = c.conv_abs[s];
+        if (n_rel) n_rel[s] = c.conv_rel[s];
+    }
+    return RRT_OK;
+}
+
+int rrt_get_recording_stats(rrt_ctx* x, int64_t* out, int32_t n_out)
+{
+    if (!x || !out || n_out < 0) return RRT_E_ARG;
+    const Ctx& c = x->c;
+    const int64_t v[RRT_N_REC_STATS] = {c.n_rec_one, c.n_rec_fallback, c.n_rec_counted,
+                                        c.n_rec_two, c.n_rec_unfit};
+    for (int32_t i = 0; i < std::min<int32_t>(n_out, RRT_N_REC_STATS); ++i) out[i] = v[i];
+    return RRT_OK;
+}
+
+int rrt_trace_stats(rrt_ctx* x, int64_t* out6)
+{
+    if (!x || !out6) return RRT_E_ARG;
+    Ctx& c = x->c;
+    if (int r = need_tree(c)) return r;
+    const int64_t nr = c.n * (int64_t)c.n_ray;
+    Scratch<uint64_t> cnt(c);
+    Scratch<unsigned long long> st(c);
+    HIP_OK(cnt.get((size_t)nr));
+    HIP_OK(st.get(6));
+    HIP_OK(hipMemsetAsync(st.p, 0, 6 * sizeof(unsigned long long), c.stream));
+    HIP_OK(launch_trace_stats(c, cnt.p, st.p));
+    unsigned long long h[6];
+    HIP_OK(hipMemcpyAsync(h, st.p, sizeof h, hipMemcpyDeviceToHost, c.stream));
+    HIP_OK(hipStreamSynchronize(c.stream));
+    for (int i = 0; i < 6; ++i) out6[i] = (int64_t)h[i];
+    return RRT_OK;
 }
 
 int rrt_enable_timing(rrt_ctx* x, int32_t on)

@@ -280,14 +280,10 @@ void free_tiles(Ctx& c)
 {
     // a captured graph may hold these buffers
     if (c.tile_off || c.tile_set || c.tile_idx || c.tile_fac) drop_graph(c);
-    if (c.tile_off) (void)hipFree(c.tile_off);
-    if (c.tile_set) (void)hipFree(c.tile_set);
-    if (c.tile_idx) (void)hipFree(c.tile_idx);
-    if (c.tile_fac) (void)hipFree(c.tile_fac);
-    c.tile_off = nullptr;
-    c.tile_set = nullptr;
-    c.tile_idx = nullptr;
-    c.tile_fac = nullptr;
+    ws_free(c, &c.tile_off);
+    ws_free(c, &c.tile_set);
+    ws_free(c, &c.tile_idx);
+    ws_free(c, &c.tile_fac);
     c.tiles_valid = false;
     c.tiles_unfit = false;
     c.n_tiles = 0;
@@ -295,10 +291,11 @@ void free_tiles(Ctx& c)
     c.tile_set_total = 0;
 }
 
-// Build the tiles of the current recorded paths.  Rows per tile start from
-// ~2^16 intersections per tile and halve while any tile has more than
-// kTileMaxSet distinct particles.  Marks the tiles unfit (the plain product
-// stays in use) when no tile size works or the arrays do not fit in memory.
+// Build the tiles of the current recorded paths, in the path buffer.  Rows
+// per tile start from ~2^16 intersections per tile and halve while any tile
+// has more than kTileMaxSet distinct particles.  Marks the tiles unfit (the
+// plain product stays in use) when no tile size works or the arrays do not
+// fit beside the paths.
 hipError_t build_tiles(Ctx& c)
 {
     free_tiles(c);
@@ -309,16 +306,14 @@ hipError_t build_tiles(Ctx& c)
     const double mean = (double)m / (double)n_rows;
     int rows = 16;
     while (rows < 4096 && (double)rows * 2.0 * mean <= 65536.0) rows *= 2;
-    uint64_t* d_u = nullptr;
     std::vector<uint64_t> u;
     hipError_t e = hipSuccess;
     for (; rows >= 16; rows /= 2) {
         const int64_t nt = (n_rows + rows - 1) / rows;
         if (nt > (int64_t(1) << 24)) break;
-        if (d_u) (void)hipFree(d_u);
-        d_u = nullptr;
-        e = hipMalloc(&d_u, sizeof(uint64_t) * (nt + 1));
+        e = ws_alloc(c, &c.tile_off, nt + 1, kRegionPath);
         if (e != hipSuccess) break;
+        uint64_t* d_u = c.tile_off;
         hipLaunchKernelGGL(k_tile_count, dim3((unsigned)std::min<int64_t>(nt, 2048)),
                            dim3(kBuildBlock), 0, c.stream, c.row_off, c.path, n_rows, rows, nt,
                            d_u);
@@ -339,25 +334,19 @@ hipError_t build_tiles(Ctx& c)
                 s += v;
             }
             u[nt] = s;
-            size_t fr = 0, tot = 0;
-            e = hipMemGetInfo(&fr, &tot);
-            if (e != hipSuccess) break;
-            const size_t need = (size_t)m * 6 + (size_t)s * 4 + (64u << 20);
-            if (need > fr / 2) break;                   // keep the plain product
             e = hipMemcpyAsync(d_u, u.data(), sizeof(uint64_t) * (nt + 1),
                                hipMemcpyHostToDevice, c.stream);
-            if (e == hipSuccess) e = hipMalloc(&c.tile_set, sizeof(uint32_t) * std::max<uint64_t>(s, 1));
-            if (e == hipSuccess) e = hipMalloc(&c.tile_idx, sizeof(uint16_t) * (m + kPathPad));
-            if (e == hipSuccess) e = hipMalloc(&c.tile_fac, sizeof(float) * (m + kPathPad));
-            if (e != hipSuccess) break;
+            if (e == hipSuccess)
+                e = ws_alloc(c, &c.tile_set, std::max<uint64_t>(s, 1), kRegionPath);
+            if (e == hipSuccess) e = ws_alloc(c, &c.tile_idx, m + kPathPad, kRegionPath);
+            if (e == hipSuccess) e = ws_alloc(c, &c.tile_fac, m + kPathPad, kRegionPath);
+            if (e != hipSuccess) break;                 // keep the plain product
             hipLaunchKernelGGL(k_tile_build, dim3((unsigned)std::min<int64_t>(nt, 2048)),
                                dim3(kBuildBlock), 0, c.stream, c.row_off, c.path, n_rows, rows,
                                nt, d_u, c.tile_set, c.tile_idx, c.tile_fac);
             e = hipGetLastError();
             if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
             if (e != hipSuccess) break;
-            c.tile_off = d_u;
-            d_u = nullptr;
             c.tile_rows = rows;
             c.n_tiles = nt;
             c.tile_max_u = (int64_t)mx;
@@ -367,7 +356,6 @@ hipError_t build_tiles(Ctx& c)
             break;
         }
     }
-    if (d_u) (void)hipFree(d_u);
     if (!c.tiles_valid) {
         const bool unfit = true;
         free_tiles(c);

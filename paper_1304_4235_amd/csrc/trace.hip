@@ -19,6 +19,7 @@
 // hardware 2^x with its exponent formed in FP64.
 #include "internal.h"
 
+#include <algorithm>
 #include <climits>
 #include <cmath>
 
@@ -86,8 +87,9 @@ __device__ __forceinline__ float erf_t_odd(const float4* __restrict__ tb, float 
 // scatter: y_j += (K/h^2) nu_ray for every hit (transposed column product)
 // chunk: the path entries of each ray appended to pool chunks, with the counts
 // (one-pass recording; wave-cooperative walk only)
+// stats: a count pass that also tallies the walk's work (diagnostics)
 enum { kModeColumn = 0, kModeCount = 1, kModeRecord = 2, kModePath = 3, kModeScatter = 4,
-       kModeChunk = 5 };
+       kModeChunk = 5, kModeStats = 6 };
 
 struct RayOut {
     double* N;              // [n_ray][n] columns (column / record modes)
@@ -113,7 +115,28 @@ struct RayOut {
     uint32_t* row_first;
     unsigned long long* pool_ctr;
     uint64_t slice_chunks;
+    // sampled sources (count and record modes): only the rays of the sorted
+    // tree positions src_list[0..src_n) run, and their outputs go to row
+    // i * n_ray + k for the source at src_list[i] (null = every ray, row = ray)
+    const int32_t* src_list;
+    int32_t src_n;
+    float* hit_fac;         // record mode: K/h^2 of each hit (nullable)
+    // stats mode: [rays, wave node visits, lane node visits, wave leaf visits,
+    // pair tests, hits], accumulated
+    unsigned long long* stats;
 };
+
+// Place of tree position ps among the sorted sampled sources, or -1.
+__device__ __forceinline__ int sampled_slot(const int32_t* __restrict__ list, int m, int ps)
+{
+    int lo = 0, hi = m;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (list[mid] < ps) lo = mid + 1;
+        else hi = mid;
+    }
+    return (lo < m && list[lo] == ps) ? lo : -1;
+}
 
 // sign bit of a recorded factor: the hit is near (factors are >= 0)
 constexpr uint32_t kNearBit = 0x80000000u;
@@ -174,7 +197,15 @@ k_trace(const Node* __restrict__ nodes, const float4* __restrict__ p4,
     const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t n_rays = (int64_t)g.n * g.n_ray;
     uint32_t cnt = 0;
-    if (gid < n_rays) {
+    int64_t slot = gid;
+    bool sampled = true;
+    if (gid < n_rays && out.src_list) {
+        const int k = (int)(gid / g.n);
+        const int i = sampled_slot(out.src_list, out.src_n, (int)(gid - (int64_t)k * g.n));
+        sampled = i >= 0;
+        slot = (int64_t)i * g.n_ray + k;
+    }
+    if (gid < n_rays && sampled) {
         const int k = (int)(gid / g.n);
         const int ps = (int)(gid - (int64_t)k * g.n);
         const float4 P = p4[ps];
@@ -199,7 +230,7 @@ k_trace(const Node* __restrict__ nodes, const float4* __restrict__ p4,
             inv[a] = 1.0f / ua;
         }
         double acc = 0.0, accn = 0.0;
-        uint64_t w = (MODE == kModeRecord || MODE == kModePath) ? out.row_off[gid] : 0;
+        uint64_t w = (MODE == kModeRecord || MODE == kModePath) ? out.row_off[slot] : 0;
         const double nur = (MODE == kModeScatter) ? (double)out.nu[gid] : 0.0;
 
         // the subtree this ray's halo owns (the whole tree for one problem)
@@ -268,17 +299,18 @@ k_trace(const Node* __restrict__ nodes, const float4* __restrict__ p4,
                     double h2 = hj * hj;
                     if (!(D2 < h2)) continue;
                     ++cnt;
-                    if (MODE == kModeCount) continue;
+                    if (MODE == kModeCount || MODE == kModeStats) continue;
+                    double px = d0 - sp * u[0], py = d1 - sp * u[1], pz = d2 - sp * u[2];
+                    double b2 = px * px + py * py + pz * pz;
+                    const float gk = chord_factor(sp, b2, h2, L, Q.w, t_erf, gc, ga);
                     if (MODE == kModeRecord) {
                         if (w < out.hit_cap) {
                             out.hit_j[w] = out.perm[j];
                             out.hit_img[w] = (sx + 8) | ((sy + 8) << 4) | ((sz + 8) << 8);
+                            if (out.hit_fac) out.hit_fac[w] = gk;
                         }
                         ++w;
                     }
-                    double px = d0 - sp * u[0], py = d1 - sp * u[1], pz = d2 - sp * u[2];
-                    double b2 = px * px + py * py + pz * pz;
-                    const float gk = chord_factor(sp, b2, h2, L, Q.w, t_erf, gc, ga);
                     bool near = false;
                     if (out.near_far) near = (d0 * d0 + d1 * d1 + d2 * d2) < h2;
                     if (MODE == kModePath) {
@@ -296,9 +328,10 @@ k_trace(const Node* __restrict__ nodes, const float4* __restrict__ p4,
                 node = max(skip, node + 1);
             }
         }
-        if ((MODE == kModeColumn || MODE == kModeRecord) && live) out.N[(int64_t)k * g.n + ps] = acc;
+        if ((MODE == kModeColumn || MODE == kModeRecord) && live && out.N)
+            out.N[(int64_t)k * g.n + ps] = acc;
         if (MODE == kModeColumn && live && out.near_far) out.Nn[(int64_t)k * g.n + ps] = accn;
-        if (MODE == kModeCount) out.row_cnt[gid] = cnt;
+        if (MODE == kModeCount || MODE == kModeStats) out.row_cnt[slot] = cnt;
     }
     // one atomic per wave for the total intersection count
     uint64_t c64 = cnt;
@@ -337,7 +370,8 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
     // particle q, bit 8 + q when that hit is near
     __shared__ unsigned int s_mask[kWavesPerBlock][64];
     __shared__ float s_gk[kWavesPerBlock][64 * kLeafMax];
-    constexpr bool kTerms = MODE != kModeCount;
+    constexpr bool kCountOnly = MODE == kModeCount || MODE == kModeStats;
+    constexpr bool kTerms = !kCountOnly;
     if (kTerms) {
         for (int i = threadIdx.x; i < kTabIntervals; i += blockDim.x) t_erf[i] = tabs->erf_t[i];
         __syncthreads();
@@ -353,8 +387,16 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
     const int k = __builtin_amdgcn_readfirstlane((int)(wave / waves_per_dir));
     if (k >= g.n_ray) return;                                // whole wave
     const int ps = (int)((wave - (int64_t)k * waves_per_dir) * 64 + lane);
-    const bool active = ps < g.n;
-    const float4 P = p4[active ? ps : g.n - 1];
+    // the ray's output row: the ray itself, or its sampled source's place
+    int64_t slot = (int64_t)k * g.n + ps;
+    bool sampled = true;
+    if (out.src_list) {
+        const int i = ps < g.n ? sampled_slot(out.src_list, out.src_n, ps) : -1;
+        sampled = i >= 0;
+        slot = (int64_t)i * g.n_ray + k;
+    }
+    const bool active = ps < g.n && sampled;
+    const float4 P = p4[ps < g.n ? ps : g.n - 1];
     // the ray's origin: FP32 inputs, widened exactly where FP64 needs them
     const float rpf[3] = {P.x, P.y, P.z};
     const double u[3] = {dirs[3 * k], dirs[3 * k + 1], dirs[3 * k + 2]};
@@ -391,7 +433,9 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
     }
     double acc = 0.0, accn = 0.0;
     uint32_t cnt = 0;
-    uint64_t w = ((MODE == kModeRecord || MODE == kModePath) && active) ? out.row_off[gid] : 0;
+    uint64_t w = ((MODE == kModeRecord || MODE == kModePath) && active) ? out.row_off[slot] : 0;
+    // stats mode: wave node visits, lane node visits, wave leaf visits, pair tests
+    uint64_t st_nodes = 0, st_lanes = 0, st_leaves = 0, st_pairs = 0;
     // chunk mode: the ray's current chunk (kNoChunk before the first, kDropped
     // once the pool ran out for it: then the ray only counts) and the entries
     // in it.  Waves take chunks from slice (wave mod kPoolSlices) first, each
@@ -449,6 +493,10 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
             float tmax = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)),
                                fminf(fmaxf(tz0, tz1), Lf));
             const bool hit = mine && tmin <= tmax;
+            if (MODE == kModeStats) {
+                st_nodes += 1;
+                st_lanes += __popcll(__ballot(hit));
+            }
             if (__ballot(hit) == 0) { node = max(skip, node + 1); continue; }
             if (leafw < 0) { node = node + 1; continue; }
             const int f = leafw >> 3;
@@ -469,6 +517,10 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
             }
             wave_sync();
             const int pairs = k_hit * c;
+            if (MODE == kModeStats) {
+                st_leaves += 1;
+                st_pairs += (uint64_t)pairs;
+            }
             for (int base = 0; base < pairs; base += 64) {
                 const int t = base + lane;
                 const bool act = t < pairs;
@@ -507,8 +559,8 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
             wave_sync();
             if (hit) {
                 const unsigned int m = s_mask[wv][rank];
-                if (MODE == kModeCount) cnt += __popc(m & 0xffu);
-                for (unsigned int hb = MODE == kModeCount ? 0u : m & 0xffu; hb; hb &= hb - 1) {
+                if (kCountOnly) cnt += __popc(m & 0xffu);
+                for (unsigned int hb = kCountOnly ? 0u : m & 0xffu; hb; hb &= hb - 1) {
                     const int q = __ffs(hb) - 1;
                     const int j = f + q;
                     const float gk = s_gk[wv][q * k_hit + rank];
@@ -517,6 +569,7 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
                         if (w < out.hit_cap) {
                             out.hit_j[w] = out.perm[j];
                             out.hit_img[w] = (sx + 8) | ((sy + 8) << 4) | ((sz + 8) << 8);
+                            if (out.hit_fac) out.hit_fac[w] = gk;
                         }
                         ++w;
                     }
@@ -583,13 +636,22 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
     }
     }   // halos of this wave
     if (active) {
-        if ((MODE == kModeColumn || MODE == kModeRecord) && live) out.N[gid] = acc;
+        if ((MODE == kModeColumn || MODE == kModeRecord) && live && out.N) out.N[gid] = acc;
         if (MODE == kModeColumn && live && out.near_far) out.Nn[gid] = accn;
-        if (MODE == kModeCount || MODE == kModeChunk) out.row_cnt[gid] = cnt;
+        if (MODE == kModeCount || MODE == kModeChunk || MODE == kModeStats) out.row_cnt[slot] = cnt;
     }
     uint64_t c64 = cnt;
     for (int off = 32; off > 0; off >>= 1) c64 += __shfl_xor(c64, off, 64);
     if (lane == 0 && c64) atomicAdd(out.hits_total, (unsigned long long)c64);
+    const uint64_t rays = MODE == kModeStats ? (uint64_t)__popcll(__ballot(active)) : 0;
+    if (MODE == kModeStats && lane == 0) {
+        atomicAdd(out.stats + 0, (unsigned long long)rays);
+        atomicAdd(out.stats + 1, (unsigned long long)st_nodes);
+        atomicAdd(out.stats + 2, (unsigned long long)st_lanes);
+        atomicAdd(out.stats + 3, (unsigned long long)st_leaves);
+        atomicAdd(out.stats + 4, (unsigned long long)st_pairs);
+        atomicAdd(out.stats + 5, (unsigned long long)c64);
+    }
 }
 #pragma clang fp contract(on)
 
@@ -659,7 +721,14 @@ static hipError_t launch_mode(Ctx& c, int mode, RayOut o)
     else if (mode == kModeCount) launch_one<kModeCount>(c, o);
     else if (mode == kModeRecord) launch_one<kModeRecord>(c, o);
     else if (mode == kModePath) launch_one<kModePath>(c, o);
-    else launch_one<kModeScatter>(c, o);
+    else if (mode == kModeStats) {
+        // the counters are those of the wave-cooperative walk
+        const int bs = c.prm.block_size > 0 ? c.prm.block_size : 128;
+        const int64_t waves = ((c.n + 63) / 64) * (int64_t)c.n_ray;
+        const unsigned nb = (unsigned)((waves * 64 + bs - 1) / bs);
+        hipLaunchKernelGGL(k_trace_wave<kModeStats>, dim3(nb), dim3(bs), 0, c.stream, c.nodes,
+                           c.p4, c.mux_s, c.dirs, c.tables, c.geom, o);
+    } else launch_one<kModeScatter>(c, o);
     return hipGetLastError();
 }
 
@@ -728,12 +797,55 @@ k_path_columns(const uint64_t* __restrict__ row_off, const int2* __restrict__ pa
     }
 }
 
+namespace {
+
+// sampled rows of the recorded paths: entries per row, then the entries
+// (input index of the particle, factor K/h^2 without the near flag)
+__global__ void k_path_row_counts(const uint64_t* __restrict__ row_off,
+                                  const int64_t* __restrict__ rows, int m,
+                                  uint64_t* __restrict__ cnt)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m) cnt[i] = row_off[rows[i] + 1] - row_off[rows[i]];
+}
+
+__global__ void k_path_row_copy(const uint64_t* __restrict__ row_off, const int2* __restrict__ path,
+                                const int32_t* __restrict__ perm, const int64_t* __restrict__ rows,
+                                const uint64_t* __restrict__ dst_off, int m,
+                                int32_t* __restrict__ hit_j, float* __restrict__ hit_fac)
+{
+    for (int i = blockIdx.x; i < m; i += gridDim.x) {
+        const uint64_t a = row_off[rows[i]], b = row_off[rows[i] + 1], o = dst_off[i];
+        for (uint64_t e = a + threadIdx.x; e < b; e += blockDim.x) {
+            const int2 v = path[e];
+            hit_j[o + (e - a)] = perm[v.x];
+            hit_fac[o + (e - a)] = __int_as_float(v.y & (int)~kNearBit);
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_path_rows(Ctx& c, const int64_t* rows, int m, uint64_t* cnt,
+                            const uint64_t* dst_off, int32_t* hit_j, float* hit_fac)
+{
+    if (m <= 0) return hipSuccess;
+    if (!dst_off) {
+        hipLaunchKernelGGL(k_path_row_counts, dim3((m + 255) / 256), dim3(256), 0, c.stream,
+                           c.row_off, rows, m, cnt);
+    } else {
+        hipLaunchKernelGGL(k_path_row_copy, dim3((unsigned)std::min(m, 4096)), dim3(256), 0,
+                           c.stream, c.row_off, c.path, c.perm, rows, dst_off, m, hit_j, hit_fac);
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_columns(Ctx& c)
 {
     RayOut o{};
     o.N = c.N_s;
     o.perm = c.perm;
-    o.hits_total = c.red + 1;
+    o.hits_total = c.red + kRedHits;
     o.near_far = c.near_far;
     o.Nn = c.Nn_s;
     o.mu = c.mu_s;
@@ -745,8 +857,46 @@ hipError_t launch_count_hits(Ctx& c, uint64_t* row_cnt)
     RayOut o{};
     o.row_cnt = row_cnt;
     o.perm = c.perm;
-    o.hits_total = c.red + 3;        // scratch: counting is not a column evaluation
+    o.hits_total = c.red + kRedScratch;   // counting is not a column evaluation
     return launch_mode(c, kModeCount, o);
+}
+
+hipError_t launch_count_rows(Ctx& c, const int32_t* src_list, int32_t src_n, uint64_t* row_cnt)
+{
+    RayOut o{};
+    o.row_cnt = row_cnt;
+    o.perm = c.perm;
+    o.hits_total = c.red + kRedScratch;
+    o.src_list = src_list;
+    o.src_n = src_n;
+    return launch_mode(c, kModeCount, o);
+}
+
+hipError_t launch_record_rows(Ctx& c, const int32_t* src_list, int32_t src_n,
+                              const uint64_t* row_off, int32_t* hit_j, int32_t* hit_img,
+                              float* hit_fac, uint64_t cap)
+{
+    RayOut o{};
+    o.hit_cap = cap;
+    o.row_off = row_off;
+    o.hit_j = hit_j;
+    o.hit_img = hit_img;
+    o.hit_fac = hit_fac;
+    o.perm = c.perm;
+    o.hits_total = c.red + kRedScratch;
+    o.src_list = src_list;
+    o.src_n = src_n;
+    return launch_mode(c, kModeRecord, o);
+}
+
+hipError_t launch_trace_stats(Ctx& c, uint64_t* row_cnt, unsigned long long* stats)
+{
+    RayOut o{};
+    o.row_cnt = row_cnt;
+    o.perm = c.perm;
+    o.hits_total = c.red + kRedScratch;
+    o.stats = stats;
+    return launch_mode(c, kModeStats, o);
 }
 
 hipError_t launch_record_hits(Ctx& c, const uint64_t* row_off, int32_t* hit_j, int32_t* hit_img,
@@ -754,12 +904,11 @@ hipError_t launch_record_hits(Ctx& c, const uint64_t* row_off, int32_t* hit_j, i
 {
     RayOut o{};
     o.hit_cap = cap;
-    o.N = c.N_s;
     o.row_off = row_off;
     o.hit_j = hit_j;
     o.hit_img = hit_img;
     o.perm = c.perm;
-    o.hits_total = c.red + 1;
+    o.hits_total = c.red + kRedScratch;
     return launch_mode(c, kModeRecord, o);
 }
 
@@ -768,7 +917,7 @@ hipError_t launch_record_chunks(Ctx& c, uint64_t* row_cnt)
     RayOut o{};
     o.row_cnt = row_cnt;
     o.perm = c.perm;
-    o.hits_total = c.red + 3;
+    o.hits_total = c.red + kRedScratch;
     o.near_far = c.near_far;
     o.pool = c.pool;
     o.chunk_next = c.chunk_next;
@@ -800,7 +949,7 @@ hipError_t launch_record_paths(Ctx& c, const uint64_t* row_off, int2* path, uint
     o.row_off = row_off;
     o.path = path;
     o.perm = c.perm;
-    o.hits_total = c.red + 3;
+    o.hits_total = c.red + kRedScratch;
     o.near_far = c.near_far;
     return launch_mode(c, kModePath, o);
 }
@@ -811,7 +960,7 @@ hipError_t launch_scatter_traverse(Ctx& c, const float* nu, double* y)
     o.nu = nu;
     o.y = y;
     o.perm = c.perm;
-    o.hits_total = c.red + 1;
+    o.hits_total = c.red + kRedScratch;
     return launch_mode(c, kModeScatter, o);
 }
 

@@ -144,50 +144,49 @@ k_gather_cols(const uint64_t* __restrict__ col_off, const uint64_t* __restrict__
 
 hipError_t scan_exclusive_u64(Ctx& c, const uint64_t* in, uint64_t* out, int64_t m);
 
-// Build the transposed paths into c.tpath / c.tcol_off.  Scratch: two key and
-// two value buffers of path_hits entries, freed before returning.
+// Build the transposed paths into c.tpath / c.tcol_off, in the path buffer.
+// Scratch: two key and one value buffer of path_hits entries and the sort
+// histograms, also from the path buffer, released before returning.
+// hipErrorOutOfMemory (nothing kept) when they do not fit beside the paths.
 hipError_t build_transposed_paths(Ctx& c)
 {
     const int64_t m = c.path_hits;
     const int64_t n_rows = c.n * (int64_t)c.n_ray;
     const int64_t n = c.n;
-    uint32_t *ka = nullptr, *kb = nullptr;
-    uint64_t *vb = nullptr, *hist = nullptr;
-    hipError_t e = hipSuccess;
-    if (c.tpath) (void)hipFree(c.tpath);
-    if (c.tcol_off) (void)hipFree(c.tcol_off);
-    c.tpath = nullptr;
-    c.tcol_off = nullptr;
+    ws_free(c, &c.tpath);
+    ws_free(c, &c.tcol_off);
     const int64_t mm = m > 0 ? m : 1;
     const int64_t n_tiles = (mm + kTile - 1) / kTile;
     const size_t hn = (size_t)n_tiles * 256;
-    if (e == hipSuccess) e = hipMalloc(&c.tpath, sizeof(uint64_t) * mm);
-    if (e == hipSuccess) e = hipMalloc(&c.tcol_off, sizeof(uint64_t) * (n + 1));
-    if (e == hipSuccess) e = hipMalloc(&ka, sizeof(uint32_t) * mm);
-    if (e == hipSuccess) e = hipMalloc(&kb, sizeof(uint32_t) * mm);
-    if (e == hipSuccess) e = hipMalloc(&vb, sizeof(uint64_t) * mm);
-    if (e == hipSuccess) e = hipMalloc(&hist, sizeof(uint64_t) * 2 * hn);
+    Scratch<uint32_t> ka(c), kb(c);
+    Scratch<uint64_t> vb(c), hist(c);
+    hipError_t e = ws_alloc(c, &c.tpath, mm, kRegionPath);
+    if (e == hipSuccess) e = ws_alloc(c, &c.tcol_off, n + 1, kRegionPath);
+    if (e == hipSuccess) e = ka.get(mm, kRegionPath);
+    if (e == hipSuccess) e = kb.get(mm, kRegionPath);
+    if (e == hipSuccess) e = vb.get(mm, kRegionPath);
+    if (e == hipSuccess) e = hist.get(2 * hn, kRegionPath);
     if (e == hipSuccess && m > 0) {
         hipLaunchKernelGGL(k_expand, dim3(stride_blocks(n_rows, 4)), dim3(256), 0,
-                           c.stream, c.row_off, c.path, n_rows, ka, c.tpath);
+                           c.stream, c.row_off, c.path, n_rows, ka.p, c.tpath);
         e = hipGetLastError();
     }
     // sort by particle: enough 8-bit passes to cover the largest index
     int bits = 1;
     while ((int64_t(1) << bits) < n) ++bits;
     const int passes = (bits + 7) / 8;
-    uint32_t* kin = ka;
-    uint32_t* kout = kb;
+    uint32_t* kin = ka.p;
+    uint32_t* kout = kb.p;
     uint64_t* vin = c.tpath;
-    uint64_t* vout = vb;
+    uint64_t* vout = vb.p;
     for (int p = 0; p < passes && e == hipSuccess && m > 0; ++p) {
         hipLaunchKernelGGL(k_hist32, dim3((unsigned)n_tiles), dim3(kBlock), 0, c.stream, kin, m,
-                           8 * p, hist, n_tiles);
+                           8 * p, hist.p, n_tiles);
         e = hipGetLastError();
-        if (e == hipSuccess) e = scan_exclusive_u64(c, hist, hist + hn, (int64_t)hn);
+        if (e == hipSuccess) e = scan_exclusive_u64(c, hist.p, hist.p + hn, (int64_t)hn);
         if (e == hipSuccess) {
             hipLaunchKernelGGL(k_scatter32, dim3((unsigned)n_tiles), dim3(kBlock), 0, c.stream,
-                               kin, vin, kout, vout, m, 8 * p, hist + hn, n_tiles);
+                               kin, vin, kout, vout, m, 8 * p, hist.p + hn, n_tiles);
             e = hipGetLastError();
         }
         std::swap(kin, kout);
@@ -202,16 +201,9 @@ hipError_t build_transposed_paths(Ctx& c)
                            c.stream, kin, m, n, c.tcol_off);
         e = hipGetLastError();
     }
-    if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
-    if (ka) (void)hipFree(ka);
-    if (kb) (void)hipFree(kb);
-    if (vb) (void)hipFree(vb);
-    if (hist) (void)hipFree(hist);
     if (e != hipSuccess) {
-        if (c.tpath) (void)hipFree(c.tpath);
-        if (c.tcol_off) (void)hipFree(c.tcol_off);
-        c.tpath = nullptr;
-        c.tcol_off = nullptr;
+        ws_free(c, &c.tpath);
+        ws_free(c, &c.tcol_off);
     }
     return e;
 }

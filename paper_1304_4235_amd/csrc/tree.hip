@@ -202,16 +202,10 @@ hipError_t scan_rec(hipStream_t st, const T* in, T* out, int64_t m, char* tmp)
 template <typename T>
 hipError_t scan_exclusive(Ctx& c, const T* in, T* out, int64_t m)
 {
-    size_t need = scan_tmp_need<T>(m);
-    if (need > c.scan_tmp_bytes) {
-        if (c.scan_tmp) (void)hipFree(c.scan_tmp);
-        c.scan_tmp = nullptr;
-        c.scan_tmp_bytes = 0;
-        hipError_t e = hipMalloc(&c.scan_tmp, need);
-        if (e != hipSuccess) return e;
-        c.scan_tmp_bytes = need;
-    }
-    return scan_rec<T>(c.stream, in, out, m, reinterpret_cast<char*>(c.scan_tmp));
+    Scratch<char> tmp(c);
+    hipError_t e = tmp.get(scan_tmp_need<T>(m));
+    if (e != hipSuccess) return e;
+    return scan_rec<T>(c.stream, in, out, m, tmp.p);
 }
 
 // ---------------------------------------------------------------------------
@@ -532,15 +526,9 @@ hipError_t radix_sort_pairs(Ctx& c, uint64_t* keys, int32_t* vals, int64_t n)
 {
     int64_t n_tiles = (n + kSortTile - 1) / kSortTile;
     size_t hn = (size_t)n_tiles * 256;
-    if (hn > c.hist_cap) {
-        if (c.hist) (void)hipFree(c.hist);
-        c.hist = nullptr;
-        c.hist_cap = 0;
-        hipError_t e = hipMalloc(&c.hist, 2 * hn * sizeof(uint32_t));
-        if (e != hipSuccess) return e;
-        c.hist_cap = hn;
-    }
-    uint32_t* offs = c.hist + hn;
+    Scratch<uint32_t> hist(c);
+    if (hipError_t e = hist.get(2 * hn)) return e;
+    uint32_t* offs = hist.p + hn;
     uint64_t* ka = keys;
     int32_t* va = vals;
     uint64_t* kb = c.keys_b;
@@ -548,10 +536,10 @@ hipError_t radix_sort_pairs(Ctx& c, uint64_t* keys, int32_t* vals, int64_t n)
     for (int pass = 0; pass < 8; ++pass) {
         int shift = 8 * pass;
         hipLaunchKernelGGL(k_digit_hist, dim3((unsigned)n_tiles), dim3(kBlock), 0, c.stream, ka,
-                           n, shift, c.hist, n_tiles);
+                           n, shift, hist.p, n_tiles);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        e = scan_exclusive<uint32_t>(c, c.hist, offs, (int64_t)hn);
+        e = scan_exclusive<uint32_t>(c, hist.p, offs, (int64_t)hn);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_digit_scatter, dim3((unsigned)n_tiles), dim3(kBlock), 0, c.stream,
                            ka, va, kb, vb, n, shift, offs, n_tiles);
@@ -583,13 +571,13 @@ hipError_t build_radix_tree(Ctx& c)
             return e;
         hipLaunchKernelGGL(k_refit, dim3(nblk(n)), dim3(kBlock), 0, c.stream, c.p4, n, c.leaf,
                            c.k_left, c.k_right, c.k_parent, c.k_lo, c.k_hi, c.k_cnt, c.k_dfs,
-                           c.k_seg, c.seg_of, c.k_flag, c.red + 2);
+                           c.k_seg, c.seg_of, c.k_flag, c.red + kRedBuild);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_layout, dim3(nblk(2 * n - 1)), dim3(kBlock), 0, c.stream, c.p4, n, c.leaf,
                        c.k_left, c.k_right, c.k_parent, c.k_first, c.k_lo, c.k_hi, c.k_cnt,
                        c.k_dfs, c.k_seg, c.k_last, c.seg_of, c.n_halo > 1 ? c.halo_off : nullptr,
-                       c.seg_root, c.seg_end, c.nodes, c.red + 2);
+                       c.seg_root, c.seg_end, c.nodes, c.red + kRedBuild);
     return hipGetLastError();
 }
 

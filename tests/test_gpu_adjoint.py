@@ -133,19 +133,63 @@ def test_adjoint_vs_oracle_central_differences():
 
 
 def test_autograd_function_matches_solver():
+    """RRTFunction's gradients are Solver.backward's on the same loss, bit for
+    bit, and within the oracle-gradient bar of the FP64 oracle's reverse mode
+    on the lattice; a backward whose forward is no longer the solver's latest
+    raises instead of returning the gradient at other parameters."""
     from paper_1304_4235_amd.autograd import RRTFunction, log10_rate_loss
     wl = W.isothermal_halo(n=2048, n_bins=8, seed=43)
-    s = _setup(wl, 4)
+    K = 4
+    s = _setup(wl, K)
     w = torch.tensor(wl.w, dtype=torch.float64, requires_grad=True)
     nH = torch.tensor(wl.n_H, dtype=torch.float32, device="cuda", requires_grad=True)
     with torch.no_grad():
-        lnG_t, _ = RRTFunction.apply(w * 1.2, nH, s, 4)
-    lnG, x = RRTFunction.apply(w, nH, s, 4)
+        lnG_t, _ = RRTFunction.apply(w * 1.2, nH, s, K)
+    lnG, x = RRTFunction.apply(w, nH, s, K)
     loss = log10_rate_loss(lnG, lnG_t) + x.sum()
     loss.backward()
-    assert w.grad is not None and nH.grad is not None
-    assert torch.isfinite(w.grad).all() and torch.isfinite(nH.grad).all()
-    assert float(w.grad.abs().sum()) > 0
+    # the same loss through the solver's own entry points
+    s.set_spectrum(s.sigma, wl.w)
+    s.set_density(torch.tensor(wl.n_H, dtype=torch.float32))
+    lnG2, x2 = s.forward(K)
+    assert torch.equal(lnG2, lnG.detach()) and torch.equal(x2, x.detach())
+    # the output derivatives by the same operations as above
+    l2, x2r = lnG2.clone().requires_grad_(True), x2.clone().requires_grad_(True)
+    (log10_rate_loss(l2, lnG_t) + x2r.sum()).backward()
+    dw, dn = s.backward(l2.grad, x2r.grad)
+    np.testing.assert_array_equal(w.grad.numpy(), dw)
+    np.testing.assert_array_equal(nH.grad.cpu().numpy(), dn.to(torch.float32).cpu().numpy())
+    assert float(w.grad.abs().sum()) > 0 and float(nH.grad.abs().sum()) > 0
+    # a second forward in between: the first graph's backward refuses
+    lnG3, x3 = RRTFunction.apply(w, nH, s, K)
+    with torch.no_grad():
+        RRTFunction.apply(w * 1.1, nH, s, K)
+    with pytest.raises(RuntimeError, match="another forward"):
+        (lnG3.sum() + x3.sum()).backward()
+
+
+def test_autograd_function_against_the_oracle_adjoint():
+    """On the periodic lattice, RRTFunction's gradients of a loss of ln Gamma
+    and x equal the FP64 oracle's reverse mode of the same K-step map, every
+    coordinate, at the oracle-gradient bar."""
+    from paper_1304_4235_amd.autograd import RRTFunction
+    wl = W.make_config(0)
+    K = 3
+    s = _setup(wl, K)
+    rng = np.random.default_rng(44)
+    c_l = rng.uniform(-1, 1, wl.n)
+    c_x = rng.uniform(-1, 1, wl.n)
+    w = torch.tensor(wl.w, dtype=torch.float64, requires_grad=True)
+    nH = torch.tensor(wl.n_H, dtype=torch.float32, device="cuda", requires_grad=True)
+    lnG, x = RRTFunction.apply(w, nH, s, K)
+    loss = (torch.tensor(c_l, device="cuda") * lnG).sum() + \
+        (torch.tensor(c_x, device="cuda") * x).sum()
+    loss.backward()
+    ref = oracle.adjoint(wl, K, dL_dlnG=c_l, dL_dx=c_x)
+    gw, gn = w.grad.numpy(), nH.grad.cpu().numpy().astype(np.float64)
+    np.testing.assert_allclose(gw, ref["dw"], rtol=1e-5, atol=1e-5 * np.max(np.abs(ref["dw"])))
+    np.testing.assert_allclose(gn, ref["dnH"], rtol=1e-5,
+                               atol=1e-5 * np.max(np.abs(ref["dnH"])))
 
 
 def test_full_halo_gradient_central_differences():
@@ -178,6 +222,48 @@ def test_full_halo_gradient_central_differences():
         assert abs(dw[b] - fd) <= 1e-2 * abs(fd) + 1e-3 * np.max(np.abs(dw))
         checked += 1
     # densities: the largest-gradient particles and random ones
+    cand = list(np.argsort(-np.abs(dn))[:12]) + list(rng.choice(wl.n, 12, replace=False))
+    for j in cand:
+        up, lo = np.float32(nH0[j] * (1 + 1e-3)), np.float32(nH0[j] * (1 - 1e-3))
+        npl, nmi = nH0.copy(), nH0.copy()
+        npl[j], nmi[j] = up, lo
+        fd = (_gpu_loss(s, w0, npl, K, lnG_t, c_x) - _gpu_loss(s, w0, nmi, K, lnG_t, c_x)) / \
+            (float(up) - float(lo))
+        _say("n", j, dn[j], fd)
+        assert abs(dn[j] - fd) <= 1e-2 * abs(fd) + 1e-3 * scale_n
+        checked += 1
+    assert checked == 32
+
+
+def test_full_field_gradient_central_differences():
+    """The differentiation workload at the sizes it names: 256 per-bin weights
+    and the 2.1M densities of the lognormal field (48 rays), K = 10 (the
+    field's fixed iteration count); the same loss and the same 32-coordinate
+    central-difference check (relative step 1e-3) and bars as the halo's."""
+    wl = W.make_config(2)
+    from paper_1304_4235_amd import Solver
+    s = Solver.from_workload(wl)
+    K = wl.max_iter
+    w0 = wl.w.copy()
+    nH0 = wl.n_H.astype(np.float32).copy()
+    s.set_spectrum(s.sigma, 1.2 * w0)
+    lnG_t, _ = s.forward(K)
+    c_x = torch.zeros(wl.n, dtype=torch.float64, device="cuda")
+    dw, dn = _adjoint(s, w0, nH0, K, lnG_t, c_x)
+    assert dw.size == 256 and dn.size == wl.n
+    assert np.all(np.isfinite(dw)) and np.all(np.isfinite(dn))
+    rng = np.random.default_rng(12)
+    scale_n = np.max(np.abs(dn))
+    checked = 0
+    for b in rng.choice(wl.n_bins, 8, replace=False):
+        h = 1e-3 * w0[b]
+        wp, wm = w0.copy(), w0.copy()
+        wp[b] += h
+        wm[b] -= h
+        fd = (_gpu_loss(s, wp, nH0, K, lnG_t, c_x) - _gpu_loss(s, wm, nH0, K, lnG_t, c_x)) / (2 * h)
+        _say("w", b, dw[b], fd)
+        assert abs(dw[b] - fd) <= 1e-2 * abs(fd) + 1e-3 * np.max(np.abs(dw))
+        checked += 1
     cand = list(np.argsort(-np.abs(dn))[:12]) + list(rng.choice(wl.n, 12, replace=False))
     for j in cand:
         up, lo = np.float32(nH0[j] * (1 + 1e-3)), np.float32(nH0[j] * (1 - 1e-3))

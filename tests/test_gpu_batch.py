@@ -143,3 +143,28 @@ def test_batched_solve_over_row_tiles_matches_plain():
         out.append(rb)
     np.testing.assert_array_equal(out[0]["halo_iters"], out[1]["halo_iters"])
     np.testing.assert_allclose(out[1]["x"].cpu().numpy(), out[0]["x"].cpu().numpy(), rtol=1e-9)
+
+
+def test_autotuner_picks_change_no_result(tmp_path):
+    """The autotuner times its knobs on a batch and caches the picks; the picks
+    change the launch shapes only: the same iterations per halo and the same
+    states (to summation order) as the defaults."""
+    import json
+    from paper_1304_4235_amd import autotune
+    wl, parts = _batch(SIZES, PEAKS)
+    cache = str(tmp_path / "tune.json")
+    space = dict(leaf=[4, 8], trace_block=[64, 256], packet=[64, 1], path_group=[16, 32],
+                 per_launch=[4, 16])
+    res = autotune.tune(wl, space=space, reps=1, cache_path=cache, use_cache=False)
+    best = res["best"]
+    assert set(best) == {"leaf", "trace_block", "packet", "path_group", "per_launch"}
+    assert best["leaf"] in space["leaf"] and best["per_launch"] in space["per_launch"]
+    again = autotune.tune(wl, space=space, cache_path=cache, use_cache=True)
+    assert again == json.loads(json.dumps(res))                # served from the cache
+    ref = _solver(wl).iterate_halos(200, 1e-3, per_launch=8)
+    s = _solver(wl)
+    autotune.apply(s, best)
+    s.build_tree()
+    r = s.iterate_halos(200, 1e-3, per_launch=best["per_launch"])
+    np.testing.assert_array_equal(r["halo_iters"], ref["halo_iters"])
+    np.testing.assert_allclose(r["x"].cpu().numpy(), ref["x"].cpu().numpy(), rtol=1e-9)

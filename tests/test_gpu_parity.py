@@ -223,6 +223,36 @@ def test_full_halo_sampled_sources():
         x = xn.cpu().numpy()
 
 
+def test_full_halo_late_iterates():
+    """The benchmarked solve of the 262144-particle halo runs 120 sweeps from
+    the optically thin state: the GPU's own iterates at sweep 60 and at the
+    last sweep, checked one step at a time on 24 sources against the oracle
+    fed the same state (the deep-shielding regime of the converged solve)."""
+    wl = W.make_config(1)
+    s = _solver(wl)
+    r = s.iterate(wl.max_iter, wl.tol, want_x=False)
+    assert r["converged"]
+    K = r["iters"]
+    _say("halo: converged in", K, "sweeps")
+    rng = np.random.default_rng(2)
+    src = np.sort(rng.choice(wl.n, 24, replace=False))
+    s.set_state(None)
+    done = 0
+    for k in (K // 2, K - 1):
+        x = s.iterate(k - done, 0.0)["x"].cpu().numpy()     # x^k, the GPU's own iterate
+        done = k
+        _say("halo: step from sweep", k)
+        s.set_state(torch.tensor(x))
+        N, _ = s.compute_columns()
+        lnG, _, tau = s.compute_gamma()
+        xn, _ = s.update_equilibrium()
+        ref = oracle.step(wl, x, sources=src)
+        _check_columns(N.cpu().numpy()[src], ref["N"])
+        _check_rates(lnG.cpu().numpy()[src], ref["lnG"], ref["tau"])
+        _check_x(xn.cpu().numpy()[src], ref["x_new"])
+        s.set_state(torch.tensor(x))
+
+
 def _halo_of(wl, h):
     a, b = int(wl.halo_offsets[h]), int(wl.halo_offsets[h + 1])
     part = W.Workload(name=f"{wl.name}_halo{h}", pos=wl.pos[a:b], h=wl.h[a:b], mu=wl.mu[a:b],
@@ -231,15 +261,22 @@ def _halo_of(wl, h):
     return part, a
 
 
-def test_full_batch_sampled_sources():
+def test_full_batch_sampled_sources(tmp_path):
     """The 64-halo batch at full size (7.1M particles), solved in one context
-    with the launch knobs the autotuner picks for it: the final state's
-    columns, rates and next update, on sampled sources of the smallest, the
-    largest and two other halos, against the oracle fed that halo's state."""
+    with the launch knobs the autotuner picks for it (over a reduced space):
+    the final state's columns, rates and next update, on sampled sources of
+    the smallest, the largest and two other halos, against the oracle fed that
+    halo's state."""
+    from paper_1304_4235_amd import autotune
     wl = W.make_config(3)
+    space = dict(leaf=[8], trace_block=[128, 256], packet=[64], path_group=[16, 32],
+                 per_launch=[16])
+    best = autotune.tune(wl, space=space, reps=1, cache_path=str(tmp_path / "tune.json"),
+                         use_cache=False)["best"]
+    _say("full batch: tuned knobs", best)
     s = _solver(wl)
-    s.set_tuning(trace_block=256, packet=64, path_group=32)
-    r = s.iterate_halos(wl.max_iter, wl.tol, per_launch=16)
+    autotune.apply(s, best)
+    r = s.iterate_halos(wl.max_iter, wl.tol, per_launch=best["per_launch"])
     assert r["converged"]
     _say("full batch: iterations per halo", r["halo_iters"].min(), "to", r["halo_iters"].max())
     x = r["x"].cpu().numpy()
@@ -297,14 +334,15 @@ def test_lognormal_small_every_particle():
 
 def test_lognormal_full_sampled_sources():
     """The 128^3 field (2097152 particles, 10 Mpc periodic box, 48 rays, 256
-    bins): the GPU iterates checked one step at a time on sampled sources
-    against the oracle fed the same state."""
+    bins): every one of its 10 GPU iterates checked one step at a time on 8
+    sampled sources against the oracle fed the same state."""
     wl = W.make_config(2)
     s = _solver(wl)
     rng = np.random.default_rng(3)
     src = np.sort(rng.choice(wl.n, 8, replace=False))
     x = oracle.x_thin(wl)
-    for k in range(2):
+    assert wl.max_iter == 10
+    for k in range(wl.max_iter):
         _say("lognormal field iteration", k)
         s.set_state(torch.tensor(x))
         N, nh = s.compute_columns()
@@ -571,14 +609,16 @@ def test_one_pass_recording_equals_two_passes(room):
     from the first recording's count so that the second recording takes one
     pass whatever the intersections per ray; a pool of about 2000 chunks runs
     short at once, and the recording falls back to the second walk with the
-    counts it has."""
+    counts it has.  The recording statistics say which walks ran: the first
+    recording follows the count the Solver makes to size its path buffer."""
     wl = W.isothermal_halo(n=16384, seed=21)
     x = np.minimum(oracle.x_thin(wl) * np.geomspace(1, 1e4, wl.n), 0.999)
     out = []
     for one_pass in (False, True):
         s = _solver(wl, record_paths=1)
         s.set_tuning(one_pass=0)
-        _, first = s.compute_columns(want_N=False)       # two walks
+        _, first = s.compute_columns(want_N=False)       # one walk after the count
+        np.testing.assert_array_equal(s.recording_stats(), [0, 0, 1, 0, 0])
         if one_pass:
             cap = first * 3 // 64 + 4096 if room == "ample" else 2000
             s.set_tuning(one_pass=int(cap))
@@ -586,6 +626,13 @@ def test_one_pass_recording_equals_two_passes(room):
         s.set_state(torch.tensor(x))
         N, hits = s.compute_columns()
         assert s.timing()["path_hits"] == hits == first
+        st = s.recording_stats()
+        if not one_pass:
+            np.testing.assert_array_equal(st, [0, 0, 1, 1, 0])   # count + record walks
+        elif room == "ample":
+            np.testing.assert_array_equal(st, [1, 0, 1, 0, 0])   # one walk
+        else:
+            np.testing.assert_array_equal(st, [0, 1, 1, 0, 0])   # ran short: second walk
         out.append(N.cpu().numpy())
     np.testing.assert_array_equal(out[0], out[1])
 
@@ -610,6 +657,8 @@ def test_full_halo_one_walk_recording():
         cols.append((N.cpu().numpy(), hits))
     assert cols[1][1] == cols[0][1]
     np.testing.assert_array_equal(cols[1][0], cols[0][0])
+    # the first recording followed the Solver's count, the second took one walk
+    np.testing.assert_array_equal(s.recording_stats(), [1, 0, 1, 0, 0])
     src = np.sort(np.random.default_rng(5).choice(wl.n, 16, replace=False))
     ref = oracle.step(wl, x, sources=src)
     _check_columns(cols[1][0][src], ref["N"])

@@ -101,15 +101,13 @@ def test_isothermal_halo_matches_spherical_profile():
     spherically symmetric solution of the same cored sphere (the halo test's
     spherical solver, Sec. 5.3: 120 shells, 32 directions, the same ray
     length), per radial bin of the median error of x:
-      * the variant weighting (each near slab lit by its ray's whole
-        far-attenuated spectrum), exact for isotropic light: within 0.03 dex
-        away from the ionisation front and 0.2 dex across it;
-      * the paper's weighting (each near slab lit by its ray's share), exact
-        for beams: within 0.03 dex in the neutral core and the thin outskirts,
-        more neutral than the sphere across the front, where each of the 12
-        slabs misses the other rays' light (the error the paper describes for
-        its halo test, Sec. 5.3);
-      * the plain scheme: more neutral at the front than the variant."""
+      * the near/far scheme (each near slab lit by its ray's share of the
+        spectrum, exact for beams): within 0.03 dex in the neutral core and
+        the thin outskirts, more neutral than the sphere across the front,
+        where each of the 12 slabs misses the other rays' light (the error the
+        paper describes for its halo test, Sec. 5.3);
+      * the plain scheme: more neutral than the sphere at the front too, by
+        less (measured +0.08 against +0.97 dex)."""
     wl = W.make_config(1)
     m = wl.meta
     r_ref, x_ref, its = oracle.spherical_profile(m["n_peak"], m["r_core"], m["r_max"],
@@ -120,7 +118,7 @@ def test_isothermal_halo_matches_spherical_profile():
     _say("spherical reference:", its, "iterations, front at", r_front, "kpc")
     edges = np.geomspace(0.2, m["r_max"], 13)
     front_med = {}
-    for scheme in (2, 1, 0):
+    for scheme in (1, 0):
         rp, e = _halo_errors(wl, scheme, r_ref, x_ref)
         front = np.abs(np.log10(rp / r_front)) < 0.2
         front_med[scheme] = np.median(e[front])
@@ -131,11 +129,10 @@ def test_isothermal_halo_matches_spherical_profile():
                 continue
             med = np.median(e[sel])
             _say(f"  r {lo:7.2f}-{hi:7.2f}: {med:+.4f} dex")
-            if scheme == 2 or (scheme == 1 and (hi < 0.6 * r_front or lo > 3.5 * r_front)):
+            if scheme == 1 and (hi < 0.6 * r_front or lo > 3.5 * r_front):
                 assert abs(med) <= 0.03
-    assert abs(front_med[2]) <= 0.2
-    assert front_med[1] > 0.1
-    assert front_med[0] > front_med[2] + 0.1
+    assert front_med[1] > 0.5
+    assert 0.03 < front_med[0] < front_med[1] - 0.5
 
 
 @pytest.mark.parametrize("n_bins", [1, 8])
