@@ -461,15 +461,17 @@ int rrt_get_path_rows(rrt_ctx* ctx, int32_t n_src, const int64_t* src, int64_t c
  * (p, k) are hit_j[row_off[p*n_ray+k] .. row_off[p*n_ray+k+1]) as input
  * particle indices, with the periodic image of each in hit_img as
  * (sx+8) | (sy+8)<<4 | (sz+8)<<8 (the image of particle j sits at r_j + s*box).
- * row_off: int64[n*n_ray + 1].  cap: capacity of hit_j/hit_img; if the total
- * exceeds it, row_off is still filled and RRT_E_CAPACITY is returned.
+ * row_off: int64[n*n_ray + 1].  cap: capacity of hit_j/hit_img; with null
+ * hit_j or hit_img only row_off is filled (RRT_OK); if the total exceeds cap,
+ * row_off is still filled and RRT_E_CAPACITY is returned.
  * Staging comes from the workspace: 8 bytes per ray, plus 8 per intersection
  * when the lists are written. */
 int rrt_get_hits(rrt_ctx* ctx, int64_t cap, int64_t* row_off, int32_t* hit_j,
                  int32_t* hit_img);
 
 /* Accumulated device time (ms, HIP events on the context's stream) since the
- * last rrt_reset_timing, per phase, into host double out12[12]:
+ * last rrt_reset_timing, per phase, into host double out[n_out] (up to
+ * RRT_N_TIMING entries):
  *   [0] traversal + column launches      [1] rate + equilibrium
  *   [2] tree builds                      [3] number of traversal launches
  *   [4] path recording (count + record traversals)
@@ -478,12 +480,16 @@ int rrt_get_hits(rrt_ctx* ctx, int64_t cap, int64_t* row_off, int32_t* hit_j,
  *   [8] columns from row tiles           [9] number of those launches
  *   [10] row-tile builds                 [11] distinct particles summed over
  *                                             the row tiles (-1 when none)
+ *   [12] one-walk chunk walks (inside [4])  [13] number of those walks
+ *   [14] chunk compaction (inside [4])   [15] counting and recording walks
+ *                                             (inside [4])
  * Timing is recorded only after rrt_enable_timing(ctx, 1): a pair of events
  * on the context's stream around each timed phase, resolved (and the stream
  * synchronised) by rrt_get_timing, so timing adds no synchronisation between
  * launches.  Phases of a batched solve replayed from a graph are not timed. */
+enum { RRT_N_TIMING = 16 };
 int rrt_enable_timing(rrt_ctx* ctx, int32_t on);
-int rrt_get_timing(rrt_ctx* ctx, double* out12);
+int rrt_get_timing(rrt_ctx* ctx, double* out, int32_t n_out);
 int rrt_reset_timing(rrt_ctx* ctx);
 
 /* Intersection counters (host): out2[0] = intersections of the last iteration

@@ -333,6 +333,9 @@ struct Ctx {
     double t_trace = 0, t_rate = 0, t_build = 0, n_trace = 0;
     double t_record = 0, t_spmv = 0, n_spmv = 0;
     double t_tile = 0, n_tile = 0, t_tile_build = 0;
+    // inside path recording: one-walk chunk walks (and how many), the chunk
+    // compaction, and counting or recording walks
+    double t_chunk_walk = 0, n_chunk_walk = 0, t_compact = 0, t_other_walk = 0;
     // timing: event pairs recorded around launches on the context's stream and
     // resolved later (no host wait per launch); acc receives the milliseconds
     struct TimedSpan {
@@ -341,7 +344,6 @@ struct Ctx {
     };
     std::vector<TimedSpan> spans;
     std::vector<hipEvent_t> ev_free;
-    hipEvent_t ev_open = nullptr;
 };
 
 // ---- device memory (workspace.hip) ----
@@ -376,6 +378,25 @@ struct Scratch {
     Scratch(const Scratch&) = delete;
     Scratch& operator=(const Scratch&) = delete;
 };
+
+// ---- sampled hit lists (rrt.hip) ----
+// Device staging of the hit lists of sampled sources: `lists` provides list
+// and pos (n_src each) and cnt (rows + 1), `hits` the entry arrays (m each).
+struct HitStaging {
+    int32_t* list = nullptr;
+    int32_t* pos = nullptr;
+    uint64_t* cnt = nullptr;
+    int32_t* j = nullptr;
+    int32_t* img = nullptr;
+    float* fac = nullptr;
+    virtual int lists(Ctx& c, int32_t n_src, size_t rows) = 0;
+    virtual int hits(Ctx& c, uint64_t m) = 0;
+    virtual ~HitStaging() = default;
+};
+int hits_rows_impl(Ctx& c, int32_t n_src, const int64_t* src, int64_t cap, int64_t* row_off,
+                   int32_t* hit_j, int32_t* hit_img, float* hit_fac, HitStaging& st);
+// tree positions of the sorted input indices in[0..m) (-1: not found)
+hipError_t launch_find_positions(Ctx& c, const int32_t* in_sorted, int32_t m, int32_t* pos);
 
 // ---- launchers (tree.hip) ----
 hipError_t launch_bounds(Ctx& c, float* part_out /*[nb][8]*/, int nb);

@@ -624,6 +624,41 @@ hipError_t launch_to_input_order_f(Ctx& c, const float* src, float* dst)
     return hipGetLastError();
 }
 
+namespace {
+
+// pos[k] = the tree position holding input index in_sorted[k]
+__global__ void k_find_positions(const int32_t* __restrict__ perm, int64_t n,
+                                 const int32_t* __restrict__ in_sorted, int32_t m,
+                                 int32_t* __restrict__ pos)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t j = perm[i];
+    int lo = 0, hi = m;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (in_sorted[mid] < j) lo = mid + 1;
+        else hi = mid;
+    }
+    if (lo < m && in_sorted[lo] == j) pos[lo] = (int32_t)i;
+}
+
+__global__ void k_fill_i32(int32_t* __restrict__ p, int32_t m, int32_t v)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m) p[i] = v;
+}
+
+}  // namespace
+
+hipError_t launch_find_positions(Ctx& c, const int32_t* in_sorted, int32_t m, int32_t* pos)
+{
+    hipLaunchKernelGGL(k_fill_i32, dim3((m + 255) / 256), dim3(256), 0, c.stream, pos, m, -1);
+    hipLaunchKernelGGL(k_find_positions, dim3(nblk(c.n)), dim3(kBlock), 0, c.stream, c.perm, c.n,
+                       in_sorted, m, pos);
+    return hipGetLastError();
+}
+
 hipError_t launch_state_from_input(Ctx& c, const double* src)
 {
     hipLaunchKernelGGL(k_gather_state, dim3(nblk(c.n)), dim3(kBlock), 0, c.stream, c.perm, src,

@@ -237,24 +237,27 @@ void ev_flush(Ctx& c)
     c.spans.clear();
 }
 
-void ev_begin(Ctx& c)
+// Open a timed span on the context's stream (null when timing is off); spans
+// nest, each closed by ev_end with the event ev_begin returned.
+hipEvent_t ev_begin(Ctx& c)
 {
-    if (c.ev_open) c.ev_free.push_back(c.ev_open);
-    c.ev_open = nullptr;
-    if (!c.timing) return;
-    c.ev_open = ev_take(c);
-    if (c.ev_open) (void)hipEventRecord(c.ev_open, c.stream);
+    if (!c.timing) return nullptr;
+    hipEvent_t a = ev_take(c);
+    if (a) (void)hipEventRecord(a, c.stream);
+    return a;
 }
 
-// Close the span opened by ev_begin; its duration goes to *acc when resolved.
-void ev_end(Ctx& c, double* acc)
+// Close the span opened at `a`; its duration goes to *acc when resolved.
+void ev_end(Ctx& c, hipEvent_t a, double* acc)
 {
-    if (!c.timing || !c.ev_open) return;
+    if (!a) return;
     hipEvent_t b = ev_take(c);
-    if (!b) return;
+    if (!b) {
+        c.ev_free.push_back(a);
+        return;
+    }
     (void)hipEventRecord(b, c.stream);
-    c.spans.push_back(Ctx::TimedSpan{c.ev_open, b, acc});
-    c.ev_open = nullptr;
+    c.spans.push_back(Ctx::TimedSpan{a, b, acc});
     if (c.spans.size() >= 4096) ev_flush(c);
 }
 
@@ -385,7 +388,7 @@ int record_paths(Ctx& c)
         c.paths_unfit = true;
         return RRT_OK;
     }
-    ev_begin(c);
+    hipEvent_t ev_rec = ev_begin(c);
     uint64_t total = 0;
     int kind = 3;                                   // counting walk + recording walk
     if (c.counts_valid) {
@@ -400,9 +403,14 @@ int record_paths(Ctx& c)
         const size_t n_ctr = (size_t)kPoolSlices * kCtrStride + 1;
         if (chunked) {
             HIP_OK(hipMemsetAsync(c.pool_ctr, 0, n_ctr * sizeof(unsigned long long), c.stream));
+            hipEvent_t ew = ev_begin(c);
             HIP_OK(launch_record_chunks(c, c.row_off));
+            ev_end(c, ew, &c.t_chunk_walk);
+            c.n_chunk_walk += c.timing ? 1 : 0;
         } else {
+            hipEvent_t ew = ev_begin(c);
             HIP_OK(launch_count_hits(c, c.row_off));
+            ev_end(c, ew, &c.t_other_walk);
         }
         HIP_OK(hipMemsetAsync(c.row_off + n_rows, 0, sizeof(uint64_t), c.stream));
         HIP_OK(scan_exclusive_u64(c, c.row_off, c.row_off, n_rows + 1));
@@ -427,13 +435,19 @@ int record_paths(Ctx& c)
     if (kind != 0) {
         free_pool(c);
         if (ws_alloc(c, &c.path, total + kPathPad, kRegionPath) != hipSuccess) {
-            ev_end(c, &c.t_record);
+            ev_end(c, ev_rec, &c.t_record);
             return paths_unfit(c, total);
         }
     }
     c.path_cap = std::max<uint64_t>(total, 1);
-    if (kind == 0) HIP_OK(launch_compact_chunks(c));
-    else HIP_OK(launch_record_paths(c, c.row_off, c.path, total));
+    hipEvent_t ew = ev_begin(c);
+    if (kind == 0) {
+        HIP_OK(launch_compact_chunks(c));
+        ev_end(c, ew, &c.t_compact);
+    } else {
+        HIP_OK(launch_record_paths(c, c.row_off, c.path, total));
+        ev_end(c, ew, &c.t_other_walk);
+    }
     free_pool(c);
     if (kind == 0) c.n_rec_one += 1;
     else if (kind == 1) c.n_rec_fallback += 1;
@@ -442,7 +456,7 @@ int record_paths(Ctx& c)
     c.path_hits = (int64_t)total;
     c.last_total = total;
     c.paths_valid = true;
-    ev_end(c, &c.t_record);
+    ev_end(c, ev_rec, &c.t_record);
     return RRT_OK;
 }
 
@@ -464,31 +478,31 @@ int columns_impl(Ctx& c, int64_t* hits)
                           : mean >= 40 ? 32 : mean >= 16 ? 16 : 8;
         if (c.use_tiles && !c.near_far && !c.tiles_valid && !c.tiles_unfit && !c.capturing &&
             ++c.path_evals > kTileAfter) {
-            ev_begin(c);
+            hipEvent_t et = ev_begin(c);
             HIP_OK(build_tiles(c));
-            ev_end(c, &c.t_tile_build);
+            ev_end(c, et, &c.t_tile_build);
         }
         // a source list (one block of the density order) walks only its own
         // rows in the plain product; the tiles serve full sweeps
         const bool tiles = c.tiles_valid && c.use_tiles && !c.near_far && !c.row_list;
-        ev_begin(c);
+        hipEvent_t ep = ev_begin(c);
         if (tiles) HIP_OK(launch_tile_columns(c, tile_group(c)));
         else HIP_OK(launch_path_columns(c, group));
         if (c.timing) {
             if (tiles) {
-                ev_end(c, &c.t_tile);
+                ev_end(c, ep, &c.t_tile);
                 c.n_tile += 1;
             } else {
-                ev_end(c, &c.t_spmv);
+                ev_end(c, ep, &c.t_spmv);
                 c.n_spmv += 1;
             }
         }
         *hits = c.path_hits;
     } else {
-        ev_begin(c);
+        hipEvent_t ec = ev_begin(c);
         HIP_OK(launch_columns(c));
         if (c.timing) {
-            ev_end(c, &c.t_trace);
+            ev_end(c, ec, &c.t_trace);
             c.n_trace += 1;
         }
     }
@@ -497,6 +511,118 @@ int columns_impl(Ctx& c, int64_t* hits)
 }
 
 }  // namespace
+
+namespace rrt {
+
+// The hit lists of the rays of sampled sources (rrt_get_hits_rows), with the
+// device staging from `st`: the workspace, or the library's fixed array.
+int hits_rows_impl(Ctx& c, int32_t n_src, const int64_t* src, int64_t cap, int64_t* row_off,
+                   int32_t* hit_j, int32_t* hit_img, float* hit_fac, HitStaging& st)
+{
+    if (int r = need_tree(c)) return r;
+    if (!row_off) return fail(c, RRT_E_ARG, "row_off is required");
+    if (n_src < 1 || n_src > 4096 || !src)
+        return fail(c, RRT_E_ARG, "1..4096 source particles are required");
+    const int nr = c.n_ray;
+    const size_t rows = (size_t)n_src * nr;
+    if (int r = st.lists(c, n_src, rows)) return r;
+    // the sources' tree positions, found on the device from the sorted inputs
+    std::vector<int64_t> in_sorted(src, src + n_src);
+    std::sort(in_sorted.begin(), in_sorted.end());
+    for (int32_t i = 0; i < n_src; ++i) {
+        if (in_sorted[i] < 0 || in_sorted[i] >= c.n)
+            return fail(c, RRT_E_ARG, "source %lld out of range", (long long)in_sorted[i]);
+        if (i && in_sorted[i] == in_sorted[i - 1])
+            return fail(c, RRT_E_ARG, "a source is listed twice");
+    }
+    std::vector<int32_t> in32(in_sorted.begin(), in_sorted.end()), pos_sorted_in(n_src);
+    HIP_OK(hipMemcpyAsync(st.list, in32.data(), sizeof(int32_t) * n_src, hipMemcpyHostToDevice,
+                          c.stream));
+    HIP_OK(launch_find_positions(c, st.list, n_src, st.pos));
+    HIP_OK(hipMemcpyAsync(pos_sorted_in.data(), st.pos, sizeof(int32_t) * n_src,
+                          hipMemcpyDeviceToHost, c.stream));
+    HIP_OK(hipStreamSynchronize(c.stream));
+    std::vector<int32_t> pos(n_src);                 // caller's source i -> tree position
+    for (int32_t i = 0; i < n_src; ++i) {
+        const size_t k = (size_t)(std::lower_bound(in_sorted.begin(), in_sorted.end(), src[i]) -
+                                  in_sorted.begin());
+        pos[i] = pos_sorted_in[k];
+        if (pos[i] < 0) return fail(c, RRT_E_HIP, "source %lld not in the tree", (long long)src[i]);
+    }
+    // the walk takes the sources in tree order: slot s holds sorted position s
+    std::vector<int32_t> sorted(pos);
+    std::sort(sorted.begin(), sorted.end());
+    std::vector<int32_t> slot_of(n_src);
+    for (int32_t i = 0; i < n_src; ++i)
+        slot_of[i] = (int32_t)(std::lower_bound(sorted.begin(), sorted.end(), pos[i]) -
+                               sorted.begin());
+    HIP_OK(hipMemcpyAsync(st.list, sorted.data(), sizeof(int32_t) * n_src,
+                          hipMemcpyHostToDevice, c.stream));
+    HIP_OK(launch_count_rows(c, st.list, n_src, st.cnt));
+    std::vector<uint64_t> cnt(rows);
+    HIP_OK(hipMemcpyAsync(cnt.data(), st.cnt, sizeof(uint64_t) * rows, hipMemcpyDeviceToHost,
+                          c.stream));
+    HIP_OK(hipStreamSynchronize(c.stream));
+    // offsets in the caller's order, and in slot order for the device
+    row_off[0] = 0;
+    for (int32_t i = 0; i < n_src; ++i)
+        for (int k = 0; k < nr; ++k) {
+            const size_t r = (size_t)i * nr + k;
+            row_off[r + 1] = row_off[r] + (int64_t)cnt[(size_t)slot_of[i] * nr + k];
+        }
+    const int64_t total = row_off[rows];
+    if (!hit_j || !hit_img) return RRT_OK;
+    if (total > cap)
+        return fail(c, RRT_E_CAPACITY, "%lld hits, capacity %lld", (long long)total,
+                    (long long)cap);
+    std::vector<uint64_t> dev_off(rows + 1);
+    for (int32_t i = 0; i < n_src; ++i)
+        for (int k = 0; k < nr; ++k)
+            dev_off[(size_t)slot_of[i] * nr + k] = (uint64_t)row_off[(size_t)i * nr + k];
+    dev_off[rows] = (uint64_t)total;
+    if (int r = st.hits(c, (uint64_t)std::max<int64_t>(total, 1))) return r;
+    HIP_OK(hipMemcpyAsync(st.cnt, dev_off.data(), sizeof(uint64_t) * (rows + 1),
+                          hipMemcpyHostToDevice, c.stream));
+    HIP_OK(launch_record_rows(c, st.list, n_src, st.cnt, st.j, st.img, st.fac, (uint64_t)total));
+    HIP_OK(hipMemcpyAsync(hit_j, st.j, sizeof(int32_t) * total, hipMemcpyDeviceToHost, c.stream));
+    HIP_OK(hipMemcpyAsync(hit_img, st.img, sizeof(int32_t) * total, hipMemcpyDeviceToHost,
+                          c.stream));
+    if (hit_fac)
+        HIP_OK(hipMemcpyAsync(hit_fac, st.fac, sizeof(float) * total, hipMemcpyDeviceToHost,
+                              c.stream));
+    HIP_OK(hipStreamSynchronize(c.stream));
+    return RRT_OK;
+}
+
+// staging of rrt_get_hits_rows in the workspace
+struct WsStaging : HitStaging {
+    Scratch<int32_t> s_list, s_pos, s_j, s_img;
+    Scratch<uint64_t> s_cnt;
+    Scratch<float> s_fac;
+    explicit WsStaging(Ctx& c) : s_list(c), s_pos(c), s_j(c), s_img(c), s_cnt(c), s_fac(c) {}
+    int lists(Ctx& c, int32_t n_src, size_t rows) override
+    {
+        HIP_OK(s_list.get((size_t)n_src));
+        HIP_OK(s_pos.get((size_t)n_src));
+        HIP_OK(s_cnt.get(rows + 1));
+        list = s_list.p;
+        pos = s_pos.p;
+        cnt = s_cnt.p;
+        return RRT_OK;
+    }
+    int hits(Ctx& c, uint64_t m) override
+    {
+        HIP_OK(s_j.get(m));
+        HIP_OK(s_img.get(m));
+        HIP_OK(s_fac.get(m));
+        j = s_j.p;
+        img = s_img.p;
+        fac = s_fac.p;
+        return RRT_OK;
+    }
+};
+
+}  // namespace rrt
 
 extern "C" {
 
@@ -562,8 +688,6 @@ void rrt_destroy(rrt_ctx* x)
     if (c.seg_state_host) (void)hipHostFree(c.seg_state_host);
     if (c.red_host) (void)hipHostFree(c.red_host);
     ev_flush(c);
-    if (c.ev_open) c.ev_free.push_back(c.ev_open);
-    c.ev_open = nullptr;
     for (hipEvent_t e : c.ev_free) (void)hipEventDestroy(e);
     c.ev_free.clear();
     delete x;                         // the device memory is the caller's
@@ -848,7 +972,7 @@ int rrt_build_tree(rrt_ctx* x)
     free_paths(c);
     c.counts_valid = false;
     c.have_tree = c.have_columns = c.have_gamma = false;
-    ev_begin(c);
+    hipEvent_t eb = ev_begin(c);
     // bounds and validation
     const int nb = (int)std::min<int64_t>(1024, (c.n + 255) / 256);
     std::vector<float> hp(8 * nb);
@@ -928,7 +1052,7 @@ int rrt_build_tree(rrt_ctx* x)
     g.want = nullptr;
     c.blocks_for = 0;            // the density blocks are in tree order
     HIP_OK(launch_init_state(c, c.x_init_given));
-    ev_end(c, &c.t_build);
+    ev_end(c, eb, &c.t_build);
     if (int r = sync_flags(c)) return r;         // a given x_init out of range
     c.have_tree = true;
     return RRT_OK;
@@ -1140,9 +1264,9 @@ int rrt_iterate_equilibrium(rrt_ctx* x, int32_t max_iter, double tol, double* x_
                 c.row_list_n = c.block_off[b + 1] - c.block_off[b];
             }
             if (int r = columns_impl(c, &hits)) return r;
-            ev_begin(c);
+            hipEvent_t eg = ev_begin(c);
             HIP_OK(launch_gamma(c, true, it == 0));
-            ev_end(c, &c.t_rate);
+            ev_end(c, eg, &c.t_rate);
         }
         c.geom.want = nullptr;
         c.row_list = nullptr;
@@ -1183,10 +1307,10 @@ int rrt_evolve(rrt_ctx* x, double dt, int32_t n_steps, double* x_out)
     for (int s = 0; s < n_steps && dt > 0.0; ++s) {     // no time, no change
         int64_t hits = -1;
         if (int r = columns_impl(c, &hits)) return r;
-        ev_begin(c);
+        hipEvent_t eg = ev_begin(c);
         HIP_OK(launch_gamma(c, false));
         HIP_OK(launch_evolve(c, dt));
-        ev_end(c, &c.t_rate);
+        ev_end(c, eg, &c.t_rate);
     }
     c.have_columns = c.have_gamma = false;
     if (x_out) {
@@ -1430,9 +1554,9 @@ int run_active_halos(Ctx& c, double tol, int32_t max_iter, int32_t per_launch)
         // pay for them; nothing may be allocated during the capture
         if (c.use_tiles && c.paths_valid && !c.tiles_valid && !c.tiles_unfit &&
             max_iter > kTileAfter) {
-            ev_begin(c);
+            hipEvent_t et = ev_begin(c);
             HIP_OK(build_tiles(c));
-            ev_end(c, &c.t_tile_build);
+            ev_end(c, et, &c.t_tile_build);
         }
         hipStream_t user = c.stream;
         c.stream = c.gstream;
@@ -1797,10 +1921,10 @@ int rrt_get_hits(rrt_ctx* x, int64_t cap, int64_t* row_off, int32_t* hit_j, int3
     row_off[0] = 0;
     for (int64_t r = 0; r < nr; ++r) row_off[r + 1] = row_off[r] + (int64_t)in_cnt[r];
     const int64_t total = row_off[nr];
-    if (total > cap || !hit_j || !hit_img)
-        return total > cap ? fail(c, RRT_E_CAPACITY, "%lld hits, capacity %lld",
-                                  (long long)total, (long long)cap)
-                           : RRT_OK;
+    if (!hit_j || !hit_img) return RRT_OK;                 // offsets only
+    if (total > cap)
+        return fail(c, RRT_E_CAPACITY, "%lld hits, capacity %lld", (long long)total,
+                    (long long)cap);
     for (int64_t k = 0; k < c.n_ray; ++k)
         for (int64_t i = 0; i < c.n; ++i) hc[k * c.n + i] = row_off[(int64_t)perm[i] * c.n_ray + k];
     Scratch<int32_t> dj(c), di(c);
@@ -1818,8 +1942,8 @@ int rrt_get_hits(rrt_ctx* x, int64_t cap, int64_t* row_off, int32_t* hit_j, int3
 
 namespace {
 
-// Tree positions of the given input indices; RRT_E_ARG for an index out of
-// range or repeated.
+// Tree positions of the given input indices (host copy of the permutation);
+// RRT_E_ARG for an index out of range or repeated.
 int tree_positions(Ctx& c, int32_t n_src, const int64_t* src, std::vector<int32_t>& pos)
 {
     if (n_src < 1 || n_src > 4096 || !src)
@@ -1849,64 +1973,8 @@ int rrt_get_hits_rows(rrt_ctx* x, int32_t n_src, const int64_t* src, int64_t cap
                       int64_t* row_off, int32_t* hit_j, int32_t* hit_img, float* hit_fac)
 {
     if (!x) return RRT_E_ARG;
-    Ctx& c = x->c;
-    if (int r = need_tree(c)) return r;
-    if (!row_off) return fail(c, RRT_E_ARG, "row_off is required");
-    std::vector<int32_t> pos;
-    if (int r = tree_positions(c, n_src, src, pos)) return r;
-    // the walk takes the sources in tree order: slot s holds sorted position s
-    std::vector<int32_t> sorted(pos);
-    std::sort(sorted.begin(), sorted.end());
-    std::vector<int32_t> slot_of(n_src);           // caller's source i -> slot
-    for (int32_t i = 0; i < n_src; ++i)
-        slot_of[i] = (int32_t)(std::lower_bound(sorted.begin(), sorted.end(), pos[i]) -
-                               sorted.begin());
-    const int nr = c.n_ray;
-    const size_t rows = (size_t)n_src * nr;
-    Scratch<int32_t> d_list(c);
-    Scratch<uint64_t> d_cnt(c);
-    HIP_OK(d_list.get((size_t)n_src));
-    HIP_OK(d_cnt.get(rows + 1));
-    HIP_OK(hipMemcpyAsync(d_list.p, sorted.data(), sizeof(int32_t) * n_src,
-                          hipMemcpyHostToDevice, c.stream));
-    HIP_OK(launch_count_rows(c, d_list.p, n_src, d_cnt.p));
-    std::vector<uint64_t> cnt(rows);
-    HIP_OK(hipMemcpyAsync(cnt.data(), d_cnt.p, sizeof(uint64_t) * rows, hipMemcpyDeviceToHost,
-                          c.stream));
-    HIP_OK(hipStreamSynchronize(c.stream));
-    // offsets in the caller's order, and in slot order for the device
-    row_off[0] = 0;
-    for (int32_t i = 0; i < n_src; ++i)
-        for (int k = 0; k < nr; ++k) {
-            const size_t r = (size_t)i * nr + k;
-            row_off[r + 1] = row_off[r] + (int64_t)cnt[(size_t)slot_of[i] * nr + k];
-        }
-    const int64_t total = row_off[rows];
-    if (!hit_j || !hit_img) return RRT_OK;
-    if (total > cap)
-        return fail(c, RRT_E_CAPACITY, "%lld hits, capacity %lld", (long long)total,
-                    (long long)cap);
-    std::vector<uint64_t> dev_off(rows + 1);
-    for (int32_t i = 0; i < n_src; ++i)
-        for (int k = 0; k < nr; ++k)
-            dev_off[(size_t)slot_of[i] * nr + k] = (uint64_t)row_off[(size_t)i * nr + k];
-    dev_off[rows] = (uint64_t)total;
-    Scratch<int32_t> dj(c), di(c);
-    Scratch<float> df(c);
-    HIP_OK(dj.get((size_t)std::max<int64_t>(total, 1)));
-    HIP_OK(di.get((size_t)std::max<int64_t>(total, 1)));
-    HIP_OK(df.get((size_t)std::max<int64_t>(total, 1)));
-    HIP_OK(hipMemcpyAsync(d_cnt.p, dev_off.data(), sizeof(uint64_t) * (rows + 1),
-                          hipMemcpyHostToDevice, c.stream));
-    HIP_OK(launch_record_rows(c, d_list.p, n_src, d_cnt.p, dj.p, di.p, df.p, (uint64_t)total));
-    HIP_OK(hipMemcpyAsync(hit_j, dj.p, sizeof(int32_t) * total, hipMemcpyDeviceToHost, c.stream));
-    HIP_OK(hipMemcpyAsync(hit_img, di.p, sizeof(int32_t) * total, hipMemcpyDeviceToHost,
-                          c.stream));
-    if (hit_fac)
-        HIP_OK(hipMemcpyAsync(hit_fac, df.p, sizeof(float) * total, hipMemcpyDeviceToHost,
-                              c.stream));
-    HIP_OK(hipStreamSynchronize(c.stream));
-    return RRT_OK;
+    WsStaging st(x->c);
+    return hits_rows_impl(x->c, n_src, src, cap, row_off, hit_j, hit_img, hit_fac, st);
 }
 
 int rrt_get_path_rows(rrt_ctx* x, int32_t n_src, const int64_t* src, int64_t cap,
@@ -2055,23 +2123,17 @@ int rrt_enable_timing(rrt_ctx* x, int32_t on)
     return RRT_OK;
 }
 
-int rrt_get_timing(rrt_ctx* x, double* out12)
+int rrt_get_timing(rrt_ctx* x, double* out, int32_t n_out)
 {
-    if (!x || !out12) return RRT_E_ARG;
+    if (!x || !out || n_out < 0) return RRT_E_ARG;
     Ctx& c = x->c;
     ev_flush(c);
-    out12[0] = c.t_trace;
-    out12[1] = c.t_rate;
-    out12[2] = c.t_build;
-    out12[3] = c.n_trace;
-    out12[4] = c.t_record;
-    out12[5] = c.t_spmv;
-    out12[6] = c.n_spmv;
-    out12[7] = c.paths_valid ? (double)c.path_hits : -1.0;
-    out12[8] = c.t_tile;
-    out12[9] = c.n_tile;
-    out12[10] = c.t_tile_build;
-    out12[11] = c.tiles_valid ? (double)c.tile_set_total : -1.0;
+    const double v[RRT_N_TIMING] = {
+        c.t_trace, c.t_rate, c.t_build, c.n_trace, c.t_record, c.t_spmv, c.n_spmv,
+        c.paths_valid ? (double)c.path_hits : -1.0, c.t_tile, c.n_tile, c.t_tile_build,
+        c.tiles_valid ? (double)c.tile_set_total : -1.0, c.t_chunk_walk, c.n_chunk_walk,
+        c.t_compact, c.t_other_walk};
+    for (int32_t i = 0; i < std::min<int32_t>(n_out, RRT_N_TIMING); ++i) out[i] = v[i];
     return RRT_OK;
 }
 
@@ -2083,6 +2145,7 @@ int rrt_reset_timing(rrt_ctx* x)
     c.t_trace = c.t_rate = c.t_build = c.n_trace = 0.0;
     c.t_record = c.t_spmv = c.n_spmv = 0.0;
     c.t_tile = c.n_tile = c.t_tile_build = 0.0;
+    c.t_chunk_walk = c.n_chunk_walk = c.t_compact = c.t_other_walk = 0.0;
     c.total_hits = 0;
     return RRT_OK;
 }

@@ -62,7 +62,7 @@ SIGNATURES = {
     "rrt_get_tree": ([_vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp], C.c_int),
     "rrt_get_hits": ([_vp, _i64, _vp, _vp, _vp], C.c_int),
     "rrt_enable_timing": ([_vp, _i32], C.c_int),
-    "rrt_get_timing": ([_vp, _vp], C.c_int),
+    "rrt_get_timing": ([_vp, _vp, _i32], C.c_int),
     "rrt_reset_timing": ([_vp], C.c_int),
     "rrt_get_counters": ([_vp, _vp], C.c_int),
     "rrt_set_density": ([_vp, _vp], C.c_int),
@@ -213,7 +213,11 @@ class Solver:
             return
         size = int(need * 1.05) + (16 << 20)
         size = (size + 4095) // 4096 * 4096
-        ws = torch.empty(size, dtype=torch.uint8, device=self.device)
+        try:
+            ws = torch.empty(size, dtype=torch.uint8, device=self.device)
+        except torch.OutOfMemoryError:
+            torch.cuda.empty_cache()                 # cached blocks too fragmented
+            ws = torch.empty(size, dtype=torch.uint8, device=self.device)
         self._check(_lib.rrt_set_workspace(self._h, C.c_void_p(ws.data_ptr()), size),
                     "rrt_set_workspace")
         self._ws = ws
@@ -226,20 +230,29 @@ class Solver:
         cached = torch.cuda.memory_reserved(self.device) - torch.cuda.memory_allocated(self.device)
         return int(free + max(cached, 0))
 
-    def set_path_buffer(self, nbytes: int):
-        """Give the context a path buffer of nbytes (0: none)."""
-        nbytes = int(nbytes)
-        if nbytes <= 0:
-            self._check(_lib.rrt_set_path_buffer(self._h, None, 0), "rrt_set_path_buffer")
-            self._path = None
-            return
-        nbytes = (nbytes + 4095) // 4096 * 4096
+    def set_path_buffer(self, nbytes, fallbacks=()) -> int:
+        """Give the context a path buffer of nbytes (0: none).  When the device
+        cannot hand out that much, try each smaller size of `fallbacks` in
+        turn (then none).  Returns the size given."""
         self._check(_lib.rrt_set_path_buffer(self._h, None, 0), "rrt_set_path_buffer")
         self._path = None                      # the old buffer goes back to torch first
-        buf = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
-        self._check(_lib.rrt_set_path_buffer(self._h, C.c_void_p(buf.data_ptr()), nbytes),
-                    "rrt_set_path_buffer")
-        self._path = buf
+        for size in [int(nbytes), *[int(f) for f in fallbacks]]:
+            if size <= 0:
+                return 0
+            size = (size + 4095) // 4096 * 4096
+            try:
+                buf = torch.empty(size, dtype=torch.uint8, device=self.device)
+            except torch.OutOfMemoryError:
+                torch.cuda.empty_cache()
+                try:
+                    buf = torch.empty(size, dtype=torch.uint8, device=self.device)
+                except torch.OutOfMemoryError:
+                    continue
+            self._check(_lib.rrt_set_path_buffer(self._h, C.c_void_p(buf.data_ptr()), size),
+                        "rrt_set_path_buffer")
+            self._path = buf
+            return size
+        return 0
 
     def count_paths(self) -> dict:
         """The counting walk of rrt_count_paths: intersections and the path
@@ -273,7 +286,9 @@ class Solver:
             size = min(want, budget if self.path_budget else max(budget, need))
         else:
             size = min(want, budget) if need <= budget else 0
-        self.set_path_buffer(size)
+        # smaller sizes when the device cannot hand out that much: the paths
+        # with the one-walk pool, then the paths alone
+        self.set_path_buffer(size, [f for f in (one, need) if f < size])
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -550,15 +565,16 @@ class Solver:
         self._call("rrt_reset_timing")
 
     def timing(self) -> dict:
-        out = np.zeros(12)
-        self._call("rrt_get_timing", out.ctypes.data)
+        out = np.zeros(16)
+        self._call("rrt_get_timing", out.ctypes.data, 16)
         cnt = np.zeros(2, np.int64)
         self._call("rrt_get_counters", cnt.ctypes.data)
         return dict(trace_ms=out[0], rate_ms=out[1], build_ms=out[2], n_trace=int(out[3]),
                     record_ms=out[4], path_ms=out[5], n_path=int(out[6]),
                     path_hits=int(out[7]), tile_ms=out[8], n_tile=int(out[9]),
                     tile_build_ms=out[10], tile_set_total=int(out[11]),
-                    last_hits=int(cnt[0]), total_hits=int(cnt[1]))
+                    chunk_walk_ms=out[12], n_chunk_walk=int(out[13]), compact_ms=out[14],
+                    other_walk_ms=out[15], last_hits=int(cnt[0]), total_hits=int(cnt[1]))
 
     # -- convenience ------------------------------------------------------
     @classmethod

@@ -238,8 +238,13 @@ def test_full_halo_gradient_central_differences():
 def test_full_field_gradient_central_differences():
     """The differentiation workload at the sizes it names: 256 per-bin weights
     and the 2.1M densities of the lognormal field (48 rays), K = 10 (the
-    field's fixed iteration count); the same loss and the same 32-coordinate
-    central-difference check (relative step 1e-3) and bars as the halo's."""
+    field's fixed iteration count); the same loss, the same 32-coordinate
+    central-difference check and bars as the halo's, at relative step 1e-2:
+    a bin carries about 1/256 of each rate and the field's densities are
+    near 1e-5 cm^-3, so a 1e-3 step moves the loss by about as much as the
+    FP32 rounding of the forward does (measured at 1e-3: a hard bin -0.0189
+    against -0.0208, a low-density particle 0.446 against 0.512, while the
+    largest components agreed to 2e-4)."""
     wl = W.make_config(2)
     from paper_1304_4235_amd import Solver
     s = Solver.from_workload(wl)
@@ -256,7 +261,7 @@ def test_full_field_gradient_central_differences():
     scale_n = np.max(np.abs(dn))
     checked = 0
     for b in rng.choice(wl.n_bins, 8, replace=False):
-        h = 1e-3 * w0[b]
+        h = 1e-2 * w0[b]
         wp, wm = w0.copy(), w0.copy()
         wp[b] += h
         wm[b] -= h
@@ -266,7 +271,7 @@ def test_full_field_gradient_central_differences():
         checked += 1
     cand = list(np.argsort(-np.abs(dn))[:12]) + list(rng.choice(wl.n, 12, replace=False))
     for j in cand:
-        up, lo = np.float32(nH0[j] * (1 + 1e-3)), np.float32(nH0[j] * (1 - 1e-3))
+        up, lo = np.float32(nH0[j] * (1 + 1e-2)), np.float32(nH0[j] * (1 - 1e-2))
         npl, nmi = nH0.copy(), nH0.copy()
         npl[j], nmi[j] = up, lo
         fd = (_gpu_loss(s, w0, npl, K, lnG_t, c_x) - _gpu_loss(s, w0, nmi, K, lnG_t, c_x)) / \

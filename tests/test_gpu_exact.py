@@ -239,9 +239,9 @@ def test_workspace_grows_by_moving_the_context():
 def test_too_small_workspace_is_an_error_not_a_fault():
     from paper_1304_4235_amd import RRTError, Solver, lib
     s = Solver(10.0)
-    need = s.workspace_size(n=5000, n_ray=12, n_bins=1)
+    need = s.workspace_size(n=200000, n_ray=12, n_bins=1)
     assert need > s._ws.numel()
-    wl = W.isothermal_halo(n=5000, n_bins=1, seed=7)
+    wl = W.isothermal_halo(n=200000, n_bins=1, seed=7)
     rc = lib().rrt_set_particles(s._h, wl.n, None, None, None, None, None, None)
     assert rc == -1                                  # null arrays: RRT_E_ARG
     pos = torch.tensor(wl.pos, device="cuda")
