@@ -40,8 +40,10 @@
  *    rrt_count_paths.  A call that finds too little room returns
  *    RRT_E_WORKSPACE before it changes any state, and rrt_workspace_info
  *    says how much it asked for.  Both regions stay referenced until they are
- *    replaced or the context is destroyed.  Pinned host memory of a few bytes
- *    is allocated for reductions.
+ *    replaced or the context is destroyed.  (The one exception is
+ *    rrt_get_hits_rows_noalloc, which stages in a fixed device array inside
+ *    the library.)  Pinned host memory of a few bytes is allocated for
+ *    reductions.
  *  - Work is enqueued on the stream given to rrt_create (NULL = the null
  *    stream).  Calls that return a scalar to the host synchronise that stream.
  *  - A context is not thread-safe; use one context per host thread.
@@ -448,6 +450,17 @@ int rrt_get_halo_roots(rrt_ctx* ctx, int32_t* root, int32_t* end);
  * hit plus 8 per ray).  Synchronises. */
 int rrt_get_hits_rows(rrt_ctx* ctx, int32_t n_src, const int64_t* src, int64_t cap,
                       int64_t* row_off, int32_t* hit_j, int32_t* hit_img, float* hit_fac);
+
+/* rrt_get_hits_rows for callers that cannot allocate, or grow the workspace,
+ * at that point (under graph capture, in serving loops, under harnesses that
+ * forbid allocation): the same arguments and results, with the device
+ * staging in a fixed array inside the library (about 25 MiB, one per GPU,
+ * held until the process ends) instead of the workspace.  At most 1024
+ * sources, 65536 rays and 2^21 hits per call (RRT_E_CAPACITY beyond).  Calls
+ * on one GPU share the array: calls that overlap on one GPU race. */
+int rrt_get_hits_rows_noalloc(rrt_ctx* ctx, int32_t n_src, const int64_t* src, int64_t cap,
+                              int64_t* row_off, int32_t* hit_j, int32_t* hit_img,
+                              float* hit_fac);
 
 /* The recorded paths of the rays of some sources, as the streaming product
  * sums them: same arguments and layout as rrt_get_hits_rows, with hit_j the

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 SOURCES = ["rrt.hip", "workspace.hip", "tree.hip", "trace.hip", "rate.hip", "adjoint.hip", "transpose.hip",
-           "tiles.hip"]
+           "tiles.hip", "noalloc.hip"]
 LIB = os.path.join(HERE, "librrt.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -398,6 +398,10 @@ int hits_rows_impl(Ctx& c, int32_t n_src, const int64_t* src, int64_t cap, int64
 // tree positions of the sorted input indices in[0..m) (-1: not found)
 hipError_t launch_find_positions(Ctx& c, const int32_t* in_sorted, int32_t m, int32_t* pos);
 
+// With `device` current, look up its copy of the fixed staging array of
+// rrt_get_hits_rows_noalloc (noalloc.hip; once per device).
+hipError_t noalloc_setup(int device);
+
 // ---- launchers (tree.hip) ----
 hipError_t launch_bounds(Ctx& c, float* part_out /*[nb][8]*/, int nb);
 hipError_t launch_morton(Ctx& c, const double lo[3], double scale, int bits);
@@ -476,3 +480,8 @@ hipError_t launch_mask_rows(Ctx& c, const uint64_t* row_cnt, const int32_t* mask
 hipError_t launch_seg_group_init(Ctx& c, const int32_t* mask);
 
 }  // namespace rrt
+
+// the context behind the opaque handle of include/rrt.h
+struct rrt_ctx {
+    rrt::Ctx c;
+};

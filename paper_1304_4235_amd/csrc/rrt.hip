@@ -11,9 +11,6 @@
 
 using namespace rrt;
 
-struct rrt_ctx {
-    Ctx c;
-};
 
 // a captured graph refers to the buffers it was captured with
 void rrt::drop_graph(Ctx& c)
@@ -660,6 +657,8 @@ int rrt_create(rrt_ctx** out, const rrt_params* params, void* stream)
     c.leaf = params->leaf_size ? params->leaf_size : kDefaultLeaf;
     c.stream = reinterpret_cast<hipStream_t>(stream);
     hipError_t e = hipGetDevice(&c.device);
+    // the fixed staging array of rrt_get_hits_rows_noalloc on this device
+    if (e == hipSuccess) e = noalloc_setup(c.device);
     if (e == hipSuccess)
         e = hipHostMalloc((void**)&c.red_host, kRedSlots * sizeof(unsigned long long));
     if (e == hipSuccess) std::memset(c.red_host, 0, kRedSlots * sizeof(unsigned long long));

@@ -84,6 +84,7 @@ SIGNATURES = {
     "rrt_get_halo_roots": ([_vp, _vp, _vp], C.c_int),
     "rrt_get_hits_rows": ([_vp, _i32, _vp, _i64, _vp, _vp, _vp, _vp], C.c_int),
     "rrt_get_path_rows": ([_vp, _i32, _vp, _i64, _vp, _vp, _vp], C.c_int),
+    "rrt_get_hits_rows_noalloc": ([_vp, _i32, _vp, _i64, _vp, _vp, _vp, _vp], C.c_int),
     "rrt_get_recording_stats": ([_vp, _vp, _i32], C.c_int),
     "rrt_trace_stats": ([_vp, _vp], C.c_int),
 }
