@@ -360,7 +360,7 @@ def run_single(name, steps, warmup, args, rules=False, near_far=False, adjoint=T
                        "after_count": rec[2], "count_and_record_walks": rec[3],
                        "did_not_fit": rec[4]},
         "convergence_last_step": {
-            "tol": wl.tol,
+            "tol": wl.tol if wl.tol > 0 else 1e-3,
             "fraction_converged_abs": (conv["n_abs"] / wl.n).round(6).tolist(),
             "fraction_converged_rel": (conv["n_rel"] / wl.n).round(6).tolist()},
     }

@@ -415,7 +415,8 @@ int rrt_get_state(rrt_ctx* ctx, double* x_out, double* lnG_out, double* G_out,
  * after each iteration).  For sweep s < min(cap, sweeps): max_dx[s], the
  * largest change (relative when the update rule says so); n_abs[s] and
  * n_rel[s], the particles updated in that sweep whose change |dx| was below
- * the solve's tol, and whose |dx| / x_old was below tol.  Host outputs, each
+ * the solve's tol, and whose |dx| / x_old was below tol (with tol = 0, a
+ * fixed number of sweeps, below the paper's 1e-3).  Host outputs, each
  * nullable; *n_sweeps receives the number of sweeps. */
 int rrt_get_convergence(rrt_ctx* ctx, int32_t cap, int32_t* n_sweeps, double* max_dx,
                         int64_t* n_abs, int64_t* n_rel);

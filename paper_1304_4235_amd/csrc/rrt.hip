@@ -1243,7 +1243,8 @@ int rrt_iterate_equilibrium(rrt_ctx* x, int32_t max_iter, double tol, double* x_
     WantGuard guard(c);
     int it = 0;
     double mdx = INFINITY;
-    c.conv_tol = tol;
+    // a fixed number of sweeps (tol = 0) counts against the paper's 1e-3
+    c.conv_tol = tol > 0.0 ? tol : 1e-3;
     c.conv_maxdx.clear();
     c.conv_abs.clear();
     c.conv_rel.clear();
@@ -1748,7 +1749,7 @@ int rrt_iterate_halos(rrt_ctx* x, int32_t max_iter, double tol, int32_t per_laun
     if (int r = ensure_seg_buffers(c)) return r;
     SegGuard guard(c);
     HIP_OK(launch_seg_init(c));
-    c.conv_tol = tol;
+    c.conv_tol = tol > 0.0 ? tol : 1e-3;
     // one group (every halo at once; the recording, if any, happens in the
     // first iteration) when the batch's paths need not be recorded or are
     // known to fit (counted, or a previous recording of this size fitted),

@@ -285,11 +285,16 @@ class Solver:
             # required: at least the paths, unless an explicit budget says no
             # (then the library reports RRT_E_WORKSPACE)
             size = min(want, budget if self.path_budget else max(budget, need))
+        elif self.n_halo > 1:
+            # a batch whose paths do not fit at once is solved in groups of
+            # halos whose paths fit the buffer
+            size = min(want, budget)
         else:
             size = min(want, budget) if need <= budget else 0
         # smaller sizes when the device cannot hand out that much: the paths
-        # with the one-walk pool, then the paths alone
-        self.set_path_buffer(size, [f for f in (one, need) if f < size])
+        # with the one-walk pool, then the paths alone (a batch: half as much)
+        smaller = [f for f in (one, need) if f < size] or ([size // 2] if self.n_halo > 1 else [])
+        self.set_path_buffer(size, smaller)
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
