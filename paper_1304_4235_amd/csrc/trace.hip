@@ -340,6 +340,12 @@ k_trace(const Node* __restrict__ nodes, const float4* __restrict__ p4,
 }
 // LDS written by some lanes of a wave and read by others: order the accesses
 // within the wave (no block barrier needed, the wave runs in lockstep)
+// lanes where b holds (the HIP __ballot takes an int and re-tests it)
+__device__ __forceinline__ uint64_t wave_ballot(bool b)
+{
+    return __builtin_amdgcn_ballot_w64(b);
+}
+
 __device__ __forceinline__ void wave_sync()
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -354,32 +360,70 @@ __device__ __forceinline__ void wave_sync()
 // wave descends or skips.  A lane only tests the particles of leaves its own
 // ray's box test accepted, and sees them in depth-first order, so every lane's
 // hits, counts and recorded paths equal those of its own walk.
+//
+// The walk is bound by vector instruction issue (the chip's VALU issue rate is
+// reached with the scalar node loads hidden behind it), so the loops are
+// written for instruction count:
+//  * the rays share one direction, so on each axis the face a ray enters
+//    through (low or high) is the same for all lanes: it is chosen once with
+//    scalar selects, and the slab test needs no per-lane min/max of the pair;
+//  * the node index and the walk's bounds are scalar, so the loop is too;
+//  * a leaf's (ray, particle) pairs are indexed with an FP32 reciprocal (exact
+//    for the at most 64 x 8 pairs) and the rays' origins are read, already in
+//    FP64, from LDS;
+//  * the near test only exists in the near/far variant (NF).
+// LDS per wave: origins 3 x 64 FP64, hit masks 64 x 4 B, factors 64 x 8 x 4 B
+// (the latter not in count modes); plus the erf table per block.  Sized per
+// launch (dynamic LDS), so a 128-thread block holds two waves' buffers.
 // Six waves per SIMD (measured: the count and record passes run 4.5% faster on
 // the 2.1M-particle field than at the four that ~100 VGPRs would allow, with
 // a few registers spilled to scratch).
-template <int MODE>
+constexpr int kWaveOrgBytes = 3 * 64 * (int)sizeof(double);
+constexpr int kWaveMaskBytes = 64 * (int)sizeof(unsigned int);
+constexpr int kWaveGkBytes = 64 * kLeafMax * (int)sizeof(float);
+
+__host__ __device__ constexpr bool mode_terms(int mode)
+{
+    return mode != kModeCount && mode != kModeStats;
+}
+
+// dynamic LDS bytes of one k_trace_wave block
+inline size_t wave_lds_bytes(int mode, int block)
+{
+    const int waves = block / 64;
+    return mode_terms(mode) ? (size_t)kTabIntervals * sizeof(float4) +
+                                  (size_t)waves * (kWaveOrgBytes + kWaveMaskBytes + kWaveGkBytes)
+                            : (size_t)waves * (kWaveOrgBytes + kWaveMaskBytes);
+}
+
+template <int MODE, bool NF>
 __global__ void __launch_bounds__(256, 6)
 k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
              const float* __restrict__ mux, const double* __restrict__ dirs,
              const KernelTables* __restrict__ tabs, TraceGeom g, RayOut out)
 {
-    __shared__ float4 t_erf[kTabIntervals];
-    // per wave: the hit rays of the current leaf, and its (ray, particle) results
-    __shared__ uint8_t s_lane[kWavesPerBlock][64];
-    // per hit ray of the current leaf: bit q set when the ray hits the leaf's
-    // particle q, bit 8 + q when that hit is near
-    __shared__ unsigned int s_mask[kWavesPerBlock][64];
-    __shared__ float s_gk[kWavesPerBlock][64 * kLeafMax];
-    constexpr bool kCountOnly = MODE == kModeCount || MODE == kModeStats;
+    constexpr bool kCountOnly = !mode_terms(MODE);
     constexpr bool kTerms = !kCountOnly;
+    extern __shared__ __align__(16) unsigned char s_dyn[];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int n_wv = blockDim.x >> 6;
+    float4* t_erf = reinterpret_cast<float4*>(s_dyn);
+    unsigned char* s_wave = s_dyn + (kTerms ? kTabIntervals * sizeof(float4) : 0);
+    // per wave: the hit rays' origins (FP64, by rank among the leaf's hit rays),
+    // per hit ray of the current leaf bit q set when the ray hits the leaf's
+    // particle q (bit 8 + q when that hit is near), and the pairs' factors
+    double* s_o = reinterpret_cast<double*>(s_wave) + wv * 3 * 64;
+    unsigned int* s_mask =
+        reinterpret_cast<unsigned int*>(s_wave + n_wv * kWaveOrgBytes) + wv * 64;
+    float* s_gk = reinterpret_cast<float*>(s_wave + n_wv * (kWaveOrgBytes + kWaveMaskBytes)) +
+                  wv * 64 * kLeafMax;
     if (kTerms) {
         for (int i = threadIdx.x; i < kTabIntervals; i += blockDim.x) t_erf[i] = tabs->erf_t[i];
         __syncthreads();
     }
     const double gc = tabs->gauss_c, ga = tabs->gauss_a;
 
-    const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
     const uint64_t lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
     const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     const int64_t waves_per_dir = (g.n + 63) / 64;
@@ -400,11 +444,10 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
     // the ray's origin: FP32 inputs, widened exactly where FP64 needs them
     const float rpf[3] = {P.x, P.y, P.z};
     const double u[3] = {dirs[3 * k], dirs[3 * k + 1], dirs[3 * k + 2]};
-    const double L = g.L, B = g.box;
-    // converted once: the empty asm keeps the compiler from converting L again
-    // (and canonicalising it) at every node of the walk
-    float Lf = (float)L;
-    asm volatile("" : "+v"(Lf));
+    const double B = g.box;
+    // canonical once (the clamps below need canonical operands)
+    const double L = __builtin_canonicalize(g.L);
+    const float Lf = (float)L;
     const int64_t gid = (int64_t)k * g.n + ps;
 
     int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
@@ -425,11 +468,16 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
             uhi[a] = __builtin_amdgcn_readfirstlane(h);
         }
     }
+    // slab parameters in units of the segment length, so the segment is
+    // [0, 1] and both clamps are inline constants
     float inv[3];
+    int flip[3];
     for (int a = 0; a < 3; ++a) {
         float ua = (float)u[a];
         if (fabsf(ua) < 1e-20f) ua = 1e-20f;
-        inv[a] = 1.0f / ua;
+        inv[a] = 1.0f / (ua * Lf);
+        // all ones when the ray enters boxes through the high face on axis a
+        flip[a] = __builtin_amdgcn_readfirstlane(inv[a] < 0.0f ? -1 : 0);
     }
     double acc = 0.0, accn = 0.0;
     uint32_t cnt = 0;
@@ -456,64 +504,91 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
         live = !g.seg_active || g.seg_active[h] != 0;
     }
     if (MODE == kModeColumn && g.want && active && !g.want[ps]) live = false;
-    uint64_t pending = __ballot(live);
+    uint64_t pending = wave_ballot(live);
     while (pending) {
     const int leader = __ffsll((unsigned long long)pending) - 1;
-    const int sroot = __shfl(root, leader, 64), send = __shfl(end, leader, 64);
+    const int sroot = __builtin_amdgcn_readfirstlane(__shfl(root, leader, 64));
+    const int send = __builtin_amdgcn_readfirstlane(__shfl(end, leader, 64));
     const bool in_seg = live && root == sroot;
-    pending &= ~__ballot(in_seg);
+    pending &= ~wave_ballot(in_seg);
     for (int sx = ulo[0]; sx <= uhi[0]; ++sx)
     for (int sy = ulo[1]; sy <= uhi[1]; ++sy)
     for (int sz = ulo[2]; sz <= uhi[2]; ++sz) {
         const bool mine = in_seg && sx >= lo[0] && sx <= hi[0] && sy >= lo[1] && sy <= hi[1] &&
                           sz >= lo[2] && sz <= hi[2];
-        if (__ballot(mine) == 0) continue;
+        if (wave_ballot(mine) == 0) continue;
+        // the segment's end in the slab test; below the start for lanes that
+        // do not walk this image, so their test always fails
+        const float t_end = mine ? 1.0f : -1.0f;
         double sh[3] = {(double)sx * B, (double)sy * B, (double)sz * B};
         if (!(B > 0.0)) sh[0] = sh[1] = sh[2] = 0.0;
-        float oai[3], obi[3];
+        // slab offsets of the entry and exit faces: the low face is padded
+        // by -pad, the high face by +pad
+        float oin[3], oout[3];
         for (int a = 0; a < 3; ++a) {
-            double o = (double)rpf[a] - sh[a];
-            oai[a] = (float)(o + (double)g.pad) * inv[a];
-            obi[a] = (float)(o - (double)g.pad) * inv[a];
+            const double o = (double)rpf[a] - sh[a];
+            const float oa = (float)(o + (double)g.pad) * inv[a];
+            const float ob = (float)(o - (double)g.pad) * inv[a];
+            oin[a] = flip[a] ? ob : oa;
+            oout[a] = flip[a] ? oa : ob;
         }
+        // the wave walks one node sequence: the index is scalar, nodes are
+        // read with scalar loads and the slab test takes its bounds from
+        // scalar registers
         int node = sroot;
         while (node < send) {
-            // the wave walks one node sequence: keep the index in a scalar
-            // register so the node is read with scalar loads and the slab
-            // test takes its bounds from scalar registers
-            node = __builtin_amdgcn_readfirstlane(node);
             const Node nd = nodes[node];
-            const int skip = __float_as_int(nd.a.w);
-            const int leafw = __float_as_int(nd.b.w);
-            float tx0 = fmaf(nd.a.x, inv[0], -oai[0]), tx1 = fmaf(nd.b.x, inv[0], -obi[0]);
-            float ty0 = fmaf(nd.a.y, inv[1], -oai[1]), ty1 = fmaf(nd.b.y, inv[1], -obi[1]);
-            float tz0 = fmaf(nd.a.z, inv[2], -oai[2]), tz1 = fmaf(nd.b.z, inv[2], -obi[2]);
-            float tmin = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)),
-                               fmaxf(fminf(tz0, tz1), 0.0f));
-            float tmax = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)),
-                               fminf(fmaxf(tz0, tz1), Lf));
-            const bool hit = mine && tmin <= tmax;
+            // entry and exit faces: a ^ ((a ^ b) & flip) swaps the pair in
+            // scalar registers (a select on the uniform flag would be a
+            // vector instruction per face)
+            const int dx = (__float_as_int(nd.a.x) ^ __float_as_int(nd.b.x)) & flip[0];
+            const int dy = (__float_as_int(nd.a.y) ^ __float_as_int(nd.b.y)) & flip[1];
+            const int dz = (__float_as_int(nd.a.z) ^ __float_as_int(nd.b.z)) & flip[2];
+            const float ex = __int_as_float(__float_as_int(nd.a.x) ^ dx);
+            const float fx = __int_as_float(__float_as_int(nd.b.x) ^ dx);
+            const float ey = __int_as_float(__float_as_int(nd.a.y) ^ dy);
+            const float fy = __int_as_float(__float_as_int(nd.b.y) ^ dy);
+            const float ez = __int_as_float(__float_as_int(nd.a.z) ^ dz);
+            const float fz = __int_as_float(__float_as_int(nd.b.z) ^ dz);
+            const float tmin = fmaxf(fmaxf(fmaxf(fmaf(ex, inv[0], -oin[0]),
+                                                 fmaf(ey, inv[1], -oin[1])),
+                                           fmaf(ez, inv[2], -oin[2])), 0.0f);
+            const float tmax = fminf(fminf(fminf(fmaf(fx, inv[0], -oout[0]),
+                                                 fmaf(fy, inv[1], -oout[1])),
+                                           fmaf(fz, inv[2], -oout[2])), t_end);
+            const uint64_t hm = wave_ballot(tmin <= tmax);
             if (MODE == kModeStats) {
                 st_nodes += 1;
-                st_lanes += __popcll(__ballot(hit));
+                st_lanes += __popcll(hm);
             }
-            if (__ballot(hit) == 0) { node = max(skip, node + 1); continue; }
-            if (leafw < 0) { node = node + 1; continue; }
+            const int skip = __float_as_int(nd.a.w);
+            const int leafw = __float_as_int(nd.b.w);
+            if (hm == 0) {
+                node = max(skip, node + 1);
+                continue;
+            }
+            if (leafw < 0) {
+                ++node;
+                continue;
+            }
+            node = max(skip, node + 1);
             const int f = leafw >> 3;
             const int c = (f + (leafw & 7) + 1 <= g.n) ? (leafw & 7) + 1 : 0;
             // Leaf work compacted over the wave: the (hit ray, leaf particle)
             // pairs are spread over all 64 lanes, so a leaf that few of the
-            // wave's rays reach costs few wave instructions.  A pair's lane
-            // takes its ray's origin from the ray's lane and evaluates the
-            // canonical predicate and the chord factor, and sets the pair's
-            // bit in its ray's hit mask; each ray then takes its hits in
-            // particle order, exactly as if it had looped over them itself.
-            const uint64_t hm = __ballot(hit);
+            // wave's rays reach costs few wave instructions.  Pair t is hit
+            // ray t mod k_hit (by rank) and leaf particle t / k_hit; its lane
+            // evaluates the canonical predicate and the chord factor and sets
+            // the pair's bit in its ray's hit mask; each ray then takes its
+            // hits in particle order, exactly as if it had looped over them.
+            const bool hit = (hm >> lane) & 1ull;
             const int k_hit = __popcll(hm);
             const int rank = __popcll(hm & lt_mask);
             if (hit) {
-                s_lane[wv][rank] = (uint8_t)lane;
-                s_mask[wv][rank] = 0u;
+                s_o[rank] = (double)rpf[0];
+                s_o[64 + rank] = (double)rpf[1];
+                s_o[128 + rank] = (double)rpf[2];
+                s_mask[rank] = 0u;
             }
             wave_sync();
             const int pairs = k_hit * c;
@@ -521,22 +596,21 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
                 st_leaves += 1;
                 st_pairs += (uint64_t)pairs;
             }
-            for (int base = 0; base < pairs; base += 64) {
-                const int t = base + lane;
-                const bool act = t < pairs;
-                const int q = act ? t / k_hit : 0;
-                const int owner = act ? (int)s_lane[wv][t - q * k_hit] : lane;
-                const double o0 = (double)__shfl(rpf[0], owner, 64);
-                const double o1 = (double)__shfl(rpf[1], owner, 64);
-                const double o2 = (double)__shfl(rpf[2], owner, 64);
-                if (!act) continue;
+            // t / k_hit as (t + 1/2) / k_hit rounded down in FP32: the
+            // quotient is at least 1/(2 k_hit) >= 1/128 away from an integer,
+            // far beyond the error of the reciprocal and product (< 2^-12)
+            const float rk = __builtin_amdgcn_rcpf((float)k_hit);
+            for (int t = lane; t < pairs; t += 64) {
+                const int q = (int)(((float)t + 0.5f) * rk);
+                const int r = t - q * k_hit;
                 const int j = f + q;
                 const float4 Q = p4[j];
-                double d0 = ((double)Q.x - o0) + sh[0];
-                double d1 = ((double)Q.y - o1) + sh[1];
-                double d2 = ((double)Q.z - o2) + sh[2];
+                double d0 = ((double)Q.x - s_o[r]) + sh[0];
+                double d1 = ((double)Q.y - s_o[64 + r]) + sh[1];
+                double d2 = ((double)Q.z - s_o[128 + r]) + sh[2];
                 double sp = d0 * u[0] + d1 * u[1] + d2 * u[2];
-                double tt = sp < 0.0 ? 0.0 : (sp > L ? L : sp);
+                // clamp to [0, L]; a zero's sign cannot change |c|^2
+                double tt = fmin(fmax(sp, 0.0), L);
                 double c0 = d0 - tt * u[0];
                 double c1 = d1 - tt * u[1];
                 double c2 = d2 - tt * u[2];
@@ -544,26 +618,25 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
                 double hj = (double)Q.w;
                 double h2 = hj * hj;
                 const bool in = D2 < h2;
-                // the near test only for the near/far split (a uniform branch)
                 bool near = false;
-                if (out.near_far) near = (d0 * d0 + d1 * d1 + d2 * d2) < h2;
+                if (NF) near = (d0 * d0 + d1 * d1 + d2 * d2) < h2;
                 float gk = 0.0f;
                 if (kTerms && in) {
                     double px = d0 - sp * u[0], py = d1 - sp * u[1], pz = d2 - sp * u[2];
                     double b2 = px * px + py * py + pz * pz;
                     gk = chord_factor(sp, b2, h2, L, Q.w, t_erf, gc, ga);
                 }
-                if (in) atomicOr(&s_mask[wv][t - q * k_hit], (near ? 0x101u : 1u) << q);
-                if (kTerms) s_gk[wv][t] = gk;
+                if (in) atomicOr(&s_mask[r], (near ? 0x101u : 1u) << q);
+                if (kTerms) s_gk[t] = gk;
             }
             wave_sync();
             if (hit) {
-                const unsigned int m = s_mask[wv][rank];
+                const unsigned int m = s_mask[rank];
                 if (kCountOnly) cnt += __popc(m & 0xffu);
                 for (unsigned int hb = kCountOnly ? 0u : m & 0xffu; hb; hb &= hb - 1) {
                     const int q = __ffs(hb) - 1;
                     const int j = f + q;
-                    const float gk = s_gk[wv][q * k_hit + rank];
+                    const float gk = s_gk[q * k_hit + rank];
                     ++cnt;
                     if (MODE == kModeRecord) {
                         if (w < out.hit_cap) {
@@ -573,7 +646,7 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
                         }
                         ++w;
                     }
-                    const bool near = (m >> (8 + q)) & 1u;
+                    const bool near = NF && ((m >> (8 + q)) & 1u);
                     if (MODE == kModePath) {
                         const uint32_t bits = (uint32_t)__float_as_int(gk) | (near ? kNearBit : 0u);
                         if (w < out.hit_cap) out.path[w] = make_int2(j, (int)bits);
@@ -584,7 +657,7 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
                             // allocation in the wave's slice, then, for lanes it
                             // could not serve, in further slices (stride 97,
                             // odd, so kSliceTries distinct ones) while any has room
-                            uint64_t need = __ballot(1);
+                            uint64_t need = wave_ballot(1);
                             bool got = false;
                             uint32_t nc = 0;
                             for (int t = 0; t < kSliceTries && need; ++t) {
@@ -603,7 +676,7 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
                                         nc = (uint32_t)(sl * out.slice_chunks + local);
                                     }
                                 }
-                                need = __ballot(!got);
+                                need = wave_ballot(!got);
                             }
                             if (got) {
                                 if (cur == kNoChunk) out.row_first[gid] = nc;
@@ -631,19 +704,18 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
                 }
             }
             wave_sync();                  // the pair buffers are reused by the next leaf
-            node = max(skip, node + 1);
         }
     }
     }   // halos of this wave
     if (active) {
         if ((MODE == kModeColumn || MODE == kModeRecord) && live && out.N) out.N[gid] = acc;
-        if (MODE == kModeColumn && live && out.near_far) out.Nn[gid] = accn;
+        if (MODE == kModeColumn && live && NF) out.Nn[gid] = accn;
         if (MODE == kModeCount || MODE == kModeChunk || MODE == kModeStats) out.row_cnt[slot] = cnt;
     }
     uint64_t c64 = cnt;
     for (int off = 32; off > 0; off >>= 1) c64 += __shfl_xor(c64, off, 64);
     if (lane == 0 && c64) atomicAdd(out.hits_total, (unsigned long long)c64);
-    const uint64_t rays = MODE == kModeStats ? (uint64_t)__popcll(__ballot(active)) : 0;
+    const uint64_t rays = MODE == kModeStats ? (uint64_t)__popcll(wave_ballot(active)) : 0;
     if (MODE == kModeStats && lane == 0) {
         atomicAdd(out.stats + 0, (unsigned long long)rays);
         atomicAdd(out.stats + 1, (unsigned long long)st_nodes);
@@ -697,21 +769,35 @@ void fill_kernel_tables(KernelTables* host)
     host->gauss_a = t * t / std::log(2.0);
 }
 
+// The wave-cooperative walk: one wave per 64 sources of one direction.  The
+// near/far variant only for the modes that split near hits.
+template <int MODE>
+static void launch_wave(Ctx& c, RayOut o)
+{
+    const int bs = c.prm.block_size > 0 ? c.prm.block_size : 128;
+    const int64_t waves = ((c.n + 63) / 64) * (int64_t)c.n_ray;
+    const unsigned nb = (unsigned)((waves * 64 + bs - 1) / bs);
+    const size_t lds = wave_lds_bytes(MODE, bs);
+    constexpr bool kSplit = MODE == kModeColumn || MODE == kModePath || MODE == kModeChunk;
+    if (kSplit && o.near_far)
+        hipLaunchKernelGGL((k_trace_wave<MODE, kSplit>), dim3(nb), dim3(bs), lds, c.stream,
+                           c.nodes, c.p4, c.mux_s, c.dirs, c.tables, c.geom, o);
+    else
+        hipLaunchKernelGGL((k_trace_wave<MODE, false>), dim3(nb), dim3(bs), lds, c.stream,
+                           c.nodes, c.p4, c.mux_s, c.dirs, c.tables, c.geom, o);
+}
+
 template <int MODE>
 static void launch_one(Ctx& c, RayOut o)
 {
-    int bs = c.prm.block_size > 0 ? c.prm.block_size : 128;
     if (c.prm.traversal == 1) {
+        const int bs = c.prm.block_size > 0 ? c.prm.block_size : 128;
         const int64_t n_rays = c.n * (int64_t)c.n_ray;
         const unsigned nb = (unsigned)((n_rays + bs - 1) / bs);
         hipLaunchKernelGGL(k_trace<MODE>, dim3(nb), dim3(bs), 0, c.stream, c.nodes, c.p4, c.mux_s,
                            c.dirs, c.tables, c.geom, o);
     } else {
-        // one wave per 64 sources of one direction
-        const int64_t waves = ((c.n + 63) / 64) * (int64_t)c.n_ray;
-        const unsigned nb = (unsigned)((waves * 64 + bs - 1) / bs);
-        hipLaunchKernelGGL(k_trace_wave<MODE>, dim3(nb), dim3(bs), 0, c.stream, c.nodes, c.p4,
-                           c.mux_s, c.dirs, c.tables, c.geom, o);
+        launch_wave<MODE>(c, o);
     }
 }
 
@@ -723,11 +809,7 @@ static hipError_t launch_mode(Ctx& c, int mode, RayOut o)
     else if (mode == kModePath) launch_one<kModePath>(c, o);
     else if (mode == kModeStats) {
         // the counters are those of the wave-cooperative walk
-        const int bs = c.prm.block_size > 0 ? c.prm.block_size : 128;
-        const int64_t waves = ((c.n + 63) / 64) * (int64_t)c.n_ray;
-        const unsigned nb = (unsigned)((waves * 64 + bs - 1) / bs);
-        hipLaunchKernelGGL(k_trace_wave<kModeStats>, dim3(nb), dim3(bs), 0, c.stream, c.nodes,
-                           c.p4, c.mux_s, c.dirs, c.tables, c.geom, o);
+        launch_wave<kModeStats>(c, o);
     } else launch_one<kModeScatter>(c, o);
     return hipGetLastError();
 }
@@ -924,11 +1006,7 @@ hipError_t launch_record_chunks(Ctx& c, uint64_t* row_cnt)
     o.row_first = c.row_first;
     o.pool_ctr = c.pool_ctr;
     o.slice_chunks = c.slice_chunks;
-    const int bs = c.prm.block_size > 0 ? c.prm.block_size : 128;
-    const int64_t waves = ((c.n + 63) / 64) * (int64_t)c.n_ray;
-    const unsigned nb = (unsigned)((waves * 64 + bs - 1) / bs);
-    hipLaunchKernelGGL(k_trace_wave<kModeChunk>, dim3(nb), dim3(bs), 0, c.stream, c.nodes, c.p4,
-                       c.mux_s, c.dirs, c.tables, c.geom, o);
+    launch_wave<kModeChunk>(c, o);
     return hipGetLastError();
 }
 
