@@ -87,14 +87,14 @@ def make_workload(name: str):
 
 
 # the kernel behind each timed phase (source file, function, counter-name prefix)
-KERNEL_SOURCES = {"recorded_paths": ("paper_1304_4235_amd/csrc/trace.hip", "k_path_columns",
-                                     "k_path_columns<"),
+KERNEL_SOURCES = {"recorded_paths": ("paper_1304_4235_amd/csrc/trace.hip", "k_path_stream",
+                                     "k_path_stream<"),
                   "row_tiles": ("paper_1304_4235_amd/csrc/tiles.hip", "k_tile_columns",
                                 "k_tile_columns<"),
                   "traversal": ("paper_1304_4235_amd/csrc/trace.hip", "k_trace_wave",
-                                "k_trace_wave<0>"),
+                                "k_trace_wave<0,"),
                   "path_recording_walk": ("paper_1304_4235_amd/csrc/trace.hip", "k_trace_wave",
-                                          "k_trace_wave<5>"),
+                                          "k_trace_wave<5,"),
                   "chunk_compaction": ("paper_1304_4235_amd/csrc/trace.hip", "k_compact_chunks",
                                        "k_compact_chunks")}
 
@@ -225,7 +225,8 @@ def kernel_table(tm, steps, hits_per_iter, rays, wl):
 
     add("traversal", "k_trace_wave<0> (traversal + column, no recorded paths)", tm["trace_ms"],
         tm["n_trace"], BYTES_PER_HIT * hits_per_iter + BYTES_PER_RAY * rays)
-    add("recorded_paths", "k_path_columns (columns from recorded paths)", tm["path_ms"],
+    add("recorded_paths", "k_path_stream (columns from recorded paths, streamed by row blocks)",
+        tm["path_ms"],
         tm["n_path"], BYTES_PER_PATH_HIT * hits_per_iter + BYTES_PER_ROW * rays)
     add("row_tiles", "k_tile_columns (columns from row tiles)", tm["tile_ms"], tm["n_tile"],
         BYTES_PER_TILE_HIT * hits_per_iter + BYTES_PER_ROW * rays

@@ -352,7 +352,11 @@ int rrt_iterate_halos(rrt_ctx* ctx, int32_t max_iter, double tol, int32_t per_la
  *   RRT_TUNE_PACKET       rays walking one node sequence: 64 (a wave-cooperative
  *                         packet, default) or 1 (independent lanes)
  *   RRT_TUNE_PATH_GROUP   lanes per ray in the recorded-path product: 8, 16, 32,
- *                         64, or 0 = chosen from the mean intersections per ray
+ *                         64, or 0 (default): a full sweep of the plain product
+ *                         streams the path array by blocks of rows, and the
+ *                         other products (near/far split, halos that stopped,
+ *                         per-block source lists) take lanes per ray from the
+ *                         mean intersections per ray
  *   RRT_TUNE_LEAF         particles per tree leaf (1..8), from the next build
  *   RRT_TUNE_ADJOINT      transposed column product of rrt_backward over
  *                         recorded paths: 0 (default) = gather over paths

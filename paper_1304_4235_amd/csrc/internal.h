@@ -193,6 +193,7 @@ struct Ctx {
     // entries from a pool of kPoolSlices slices, linked per row, then
     // compacted into path
     bool one_pass = true;
+    bool images_fit = true;      // every reachable periodic image codes in 10 bits per axis
     uint64_t pool_cap = 0;            // > 0: at most this many chunks (tests the fallback)
     uint64_t last_total = 0;          // entries of the last recording (sizes the pool)
     int2* pool = nullptr;             // [pool_chunks * kChunkLen]
@@ -417,6 +418,7 @@ hipError_t launch_record_paths(Ctx& c, const uint64_t* row_off, int2* path, uint
 hipError_t launch_record_chunks(Ctx& c, uint64_t* row_cnt);
 hipError_t launch_compact_chunks(Ctx& c);
 hipError_t launch_path_columns(Ctx& c, int group);
+hipError_t launch_path_stream(Ctx& c);
 void drop_graph(Ctx& c);
 hipError_t build_tiles(Ctx& c);
 hipError_t launch_want(Ctx& c, int block, bool use_skip);

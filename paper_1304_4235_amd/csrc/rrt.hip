@@ -393,7 +393,7 @@ int record_paths(Ctx& c)
         kind = 2;
     } else {
         bool chunked = false;
-        if (c.one_pass && c.prm.traversal == 0) {
+        if (c.one_pass && c.prm.traversal == 0 && c.images_fit) {
             ensure_pool(c, n_rows, c.last_total);
             chunked = c.pool != nullptr;
         }
@@ -473,6 +473,10 @@ int columns_impl(Ctx& c, int64_t* hits)
         // intersections per ray up to hundreds; short rays want fewer lanes
         const int group = c.path_group ? c.path_group
                           : mean >= 40 ? 32 : mean >= 16 ? 16 : 8;
+        // a full sweep of the plain product streams the path array by blocks
+        // of rows unless a lane group per ray is asked for
+        const bool stream = c.path_group == 0 && !c.near_far && !c.row_list &&
+                            !c.geom.seg_active && !c.geom.want;
         if (c.use_tiles && !c.near_far && !c.tiles_valid && !c.tiles_unfit && !c.capturing &&
             ++c.path_evals > kTileAfter) {
             hipEvent_t et = ev_begin(c);
@@ -484,6 +488,7 @@ int columns_impl(Ctx& c, int64_t* hits)
         const bool tiles = c.tiles_valid && c.use_tiles && !c.near_far && !c.row_list;
         hipEvent_t ep = ev_begin(c);
         if (tiles) HIP_OK(launch_tile_columns(c, tile_group(c)));
+        else if (stream) HIP_OK(launch_path_stream(c));
         else HIP_OK(launch_path_columns(c, group));
         if (c.timing) {
             if (tiles) {
@@ -1040,6 +1045,8 @@ int rrt_build_tree(rrt_ctx* x)
     }
     g.hmax = hmax;
     g.pad = (float)(4e-6 * 2.0 * (maxabs + g.L + (double)hmax + g.box));
+    // the one-walk recording codes a hit's periodic image in 10 bits per axis
+    c.images_fit = !(g.box > 0.0) || (g.L + (double)hmax + ext) / g.box + 2.0 <= 511.0;
     g.n = (int32_t)c.n;
     g.n_ray = c.n_ray;
     g.n_nodes = nn;

@@ -141,6 +141,17 @@ __device__ __forceinline__ int sampled_slot(const int32_t* __restrict__ list, in
 // sign bit of a recorded factor: the hit is near (factors are >= 0)
 constexpr uint32_t kNearBit = 0x80000000u;
 
+// A pool entry of the one-walk recording holds, in place of the factor, the
+// periodic image of the hit: 10 bits per axis, s + 512 (images with |s| up to
+// 511; the recording only takes this route when every reachable image fits).
+constexpr int kImgBias = 512;
+
+__host__ __device__ __forceinline__ uint32_t chunk_image_code(int sx, int sy, int sz)
+{
+    return (uint32_t)(sx + kImgBias) | ((uint32_t)(sy + kImgBias) << 10) |
+           ((uint32_t)(sz + kImgBias) << 20);
+}
+
 // The canonical predicate (shared operation order with the FP64 reference):
 // d = (r_j - r_p) + s B ; s_par = d.u ; t = clamp(s_par, 0, L) ; c = d - t u ;
 // hit <=> |c|^2 < h^2.
@@ -178,6 +189,35 @@ __device__ __forceinline__ float chord_factor(double sp, double b2, double h2, d
     if (z1 == -z2) e1 = -e2;
     else e1 = erf_t_odd(t_erf, z1);
     return ih2 * (g * (e2 - e1));
+}
+
+// The pair's geometry in the canonical operation order: d = (r_j - r_p) + s B
+// and sp = d.u (the same arithmetic wherever a pair is evaluated).
+struct PairGeom {
+    double d0, d1, d2, sp;
+};
+
+__device__ __forceinline__ PairGeom pair_geom(const float4 Q, double o0, double o1, double o2,
+                                              const double sh[3], const double u[3])
+{
+    PairGeom pg;
+    pg.d0 = ((double)Q.x - o0) + sh[0];
+    pg.d1 = ((double)Q.y - o1) + sh[1];
+    pg.d2 = ((double)Q.z - o2) + sh[2];
+    pg.sp = pg.d0 * u[0] + pg.d1 * u[1] + pg.d2 * u[2];
+    return pg;
+}
+
+// K/h^2 of a hit: the squared impact parameter from d - sp u, then the chord.
+__device__ __forceinline__ float hit_factor(const PairGeom& pg, const double u[3], float hf,
+                                            double L, const float4* __restrict__ t_erf,
+                                            double gc, double ga)
+{
+    const double px = pg.d0 - pg.sp * u[0], py = pg.d1 - pg.sp * u[1],
+                 pz = pg.d2 - pg.sp * u[2];
+    const double b2 = px * px + py * py + pz * pz;
+    const double hj = (double)hf;
+    return chord_factor(pg.sp, b2, hj * hj, L, hf, t_erf, gc, ga);
 }
 
 template <int MODE>
@@ -373,7 +413,8 @@ __device__ __forceinline__ void wave_sync()
 //    FP64, from LDS;
 //  * the near test only exists in the near/far variant (NF).
 // LDS per wave: origins 3 x 64 FP64, hit masks 64 x 4 B, factors 64 x 8 x 4 B
-// (the latter not in count modes); plus the erf table per block.  Sized per
+// (only in modes that evaluate factors, which also stage the erf table once
+// per block).  Sized per
 // launch (dynamic LDS), so a 128-thread block holds two waves' buffers.
 // Six waves per SIMD (measured: the count and record passes run 4.5% faster on
 // the 2.1M-particle field than at the four that ~100 VGPRs would allow, with
@@ -382,16 +423,19 @@ constexpr int kWaveOrgBytes = 3 * 64 * (int)sizeof(double);
 constexpr int kWaveMaskBytes = 64 * (int)sizeof(unsigned int);
 constexpr int kWaveGkBytes = 64 * kLeafMax * (int)sizeof(float);
 
-__host__ __device__ constexpr bool mode_terms(int mode)
+// modes whose walk evaluates the chord factor of its hits (the one-walk
+// recording leaves it to the compaction)
+__host__ __device__ constexpr bool mode_factors(int mode)
 {
-    return mode != kModeCount && mode != kModeStats;
+    return mode == kModeColumn || mode == kModeRecord || mode == kModePath ||
+           mode == kModeScatter;
 }
 
 // dynamic LDS bytes of one k_trace_wave block
 inline size_t wave_lds_bytes(int mode, int block)
 {
     const int waves = block / 64;
-    return mode_terms(mode) ? (size_t)kTabIntervals * sizeof(float4) +
+    return mode_factors(mode) ? (size_t)kTabIntervals * sizeof(float4) +
                                   (size_t)waves * (kWaveOrgBytes + kWaveMaskBytes + kWaveGkBytes)
                             : (size_t)waves * (kWaveOrgBytes + kWaveMaskBytes);
 }
@@ -402,8 +446,8 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
              const float* __restrict__ mux, const double* __restrict__ dirs,
              const KernelTables* __restrict__ tabs, TraceGeom g, RayOut out)
 {
-    constexpr bool kCountOnly = !mode_terms(MODE);
-    constexpr bool kTerms = !kCountOnly;
+    constexpr bool kCountOnly = MODE == kModeCount || MODE == kModeStats;
+    constexpr bool kTerms = mode_factors(MODE);
     extern __shared__ __align__(16) unsigned char s_dyn[];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
@@ -425,8 +469,8 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
     const double gc = tabs->gauss_c, ga = tabs->gauss_a;
 
     const uint64_t lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
-    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     const int64_t waves_per_dir = (g.n + 63) / 64;
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     // the wave's direction and image range are uniform: scalar registers
     const int k = __builtin_amdgcn_readfirstlane((int)(wave / waves_per_dir));
     if (k >= g.n_ray) return;                                // whole wave
@@ -522,6 +566,7 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
         const float t_end = mine ? 1.0f : -1.0f;
         double sh[3] = {(double)sx * B, (double)sy * B, (double)sz * B};
         if (!(B > 0.0)) sh[0] = sh[1] = sh[2] = 0.0;
+        const uint32_t img_code = chunk_image_code(sx, sy, sz);
         // slab offsets of the entry and exit faces: the low face is padded
         // by -pad, the high face by +pad
         float oin[3], oout[3];
@@ -605,27 +650,20 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
                 const int r = t - q * k_hit;
                 const int j = f + q;
                 const float4 Q = p4[j];
-                double d0 = ((double)Q.x - s_o[r]) + sh[0];
-                double d1 = ((double)Q.y - s_o[64 + r]) + sh[1];
-                double d2 = ((double)Q.z - s_o[128 + r]) + sh[2];
-                double sp = d0 * u[0] + d1 * u[1] + d2 * u[2];
+                const PairGeom pg = pair_geom(Q, s_o[r], s_o[64 + r], s_o[128 + r], sh, u);
                 // clamp to [0, L]; a zero's sign cannot change |c|^2
-                double tt = fmin(fmax(sp, 0.0), L);
-                double c0 = d0 - tt * u[0];
-                double c1 = d1 - tt * u[1];
-                double c2 = d2 - tt * u[2];
+                double tt = fmin(fmax(pg.sp, 0.0), L);
+                double c0 = pg.d0 - tt * u[0];
+                double c1 = pg.d1 - tt * u[1];
+                double c2 = pg.d2 - tt * u[2];
                 double D2 = c0 * c0 + c1 * c1 + c2 * c2;
                 double hj = (double)Q.w;
                 double h2 = hj * hj;
                 const bool in = D2 < h2;
                 bool near = false;
-                if (NF) near = (d0 * d0 + d1 * d1 + d2 * d2) < h2;
+                if (NF) near = (pg.d0 * pg.d0 + pg.d1 * pg.d1 + pg.d2 * pg.d2) < h2;
                 float gk = 0.0f;
-                if (kTerms && in) {
-                    double px = d0 - sp * u[0], py = d1 - sp * u[1], pz = d2 - sp * u[2];
-                    double b2 = px * px + py * py + pz * pz;
-                    gk = chord_factor(sp, b2, h2, L, Q.w, t_erf, gc, ga);
-                }
+                if (kTerms && in) gk = hit_factor(pg, u, Q.w, L, t_erf, gc, ga);
                 if (in) atomicOr(&s_mask[r], (near ? 0x101u : 1u) << q);
                 if (kTerms) s_gk[t] = gk;
             }
@@ -636,7 +674,7 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
                 for (unsigned int hb = kCountOnly ? 0u : m & 0xffu; hb; hb &= hb - 1) {
                     const int q = __ffs(hb) - 1;
                     const int j = f + q;
-                    const float gk = s_gk[q * k_hit + rank];
+                    const float gk = kTerms ? s_gk[q * k_hit + rank] : 0.0f;
                     ++cnt;
                     if (MODE == kModeRecord) {
                         if (w < out.hit_cap) {
@@ -689,8 +727,9 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
                             }
                         }
                         if (cur != kDropped) {
-                            const uint32_t bits =
-                                (uint32_t)__float_as_int(gk) | (near ? kNearBit : 0u);
+                            // the factor is the compaction's: the entry holds
+                            // the image in its place
+                            const uint32_t bits = img_code | (near ? kNearBit : 0u);
                             out.pool[(uint64_t)cur * kChunkLen + fill] = make_int2(j, (int)bits);
                             ++fill;
                         }
@@ -725,25 +764,45 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
         atomicAdd(out.stats + 5, (unsigned long long)c64);
     }
 }
-#pragma clang fp contract(on)
 
 // One-pass recording, second step: each row's entries from its chain of
-// chunks into the row-ordered path array.  Every row's chain holds exactly
-// ceil(count / kChunkLen) chunks.  The chain is a sequence of dependent loads,
-// so a row takes only kCompactLanes lanes (each copies kChunkLen /
-// kCompactLanes entries of a chunk) and a wave follows 64 / kCompactLanes
-// chains at once; the next link is loaded before the chunk is copied.
+// chunks into the row-ordered path array, with the chord factor of each.
+// Every row's chain holds exactly ceil(count / kChunkLen) chunks.  The chain
+// is a sequence of dependent loads, so a row takes only kCompactLanes lanes
+// (each copies kChunkLen / kCompactLanes entries of a chunk) and a wave
+// follows 64 / kCompactLanes chains at once; the next link is loaded before
+// the chunk is copied.
+// The factor is evaluated here rather than in the walk: in the walk's pair
+// loop most lanes hold pairs that miss, and every lane of a wave pays for the
+// instructions; here every lane holds a hit.  The arithmetic is the walk's
+// (same pair geometry and chord factor, FP64 without contraction), so the
+// factors are those every other recording produces.
 constexpr int kCompactLanes = 8;
+
 __global__ void __launch_bounds__(256)
 k_compact_chunks(const uint64_t* __restrict__ row_off, const uint32_t* __restrict__ row_first,
                  const uint32_t* __restrict__ chunk_next, const int2* __restrict__ pool,
-                 int64_t n_rows, int2* __restrict__ path)
+                 int64_t n_rows, int2* __restrict__ path, const float4* __restrict__ p4,
+                 const double* __restrict__ dirs, const KernelTables* __restrict__ tabs,
+                 TraceGeom g)
 {
+    __shared__ float4 t_erf[kTabIntervals];
+    for (int i = threadIdx.x; i < kTabIntervals; i += blockDim.x) t_erf[i] = tabs->erf_t[i];
+    __syncthreads();
+    const double gc = tabs->gauss_c, ga = tabs->gauss_a;
+    const double L = __builtin_canonicalize(g.L), B = g.box;
     const int lane = threadIdx.x & (kCompactLanes - 1);
     const int64_t stride = (int64_t)gridDim.x * (blockDim.x / kCompactLanes);
     for (int64_t row = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kCompactLanes;
          row < n_rows; row += stride) {
         const uint64_t a = row_off[row], b = row_off[row + 1];
+        if (a == b) continue;
+        // the ray: source ps (tree order) along direction k
+        const int k = (int)(row / g.n);
+        const int ps = (int)(row - (int64_t)k * g.n);
+        const float4 P = p4[ps];
+        const double o0 = (double)P.x, o1 = (double)P.y, o2 = (double)P.z;
+        const double u[3] = {dirs[3 * k], dirs[3 * k + 1], dirs[3 * k + 2]};
         uint32_t ch = row_first[row];
         for (uint64_t e = a; e < b; e += kChunkLen) {
             const uint32_t nxt = e + kChunkLen < b ? chunk_next[ch] : 0u;
@@ -751,12 +810,27 @@ k_compact_chunks(const uint64_t* __restrict__ row_off, const uint32_t* __restric
 #pragma unroll
             for (int q = 0; q < kChunkLen / kCompactLanes; ++q) {
                 const int i = q * kCompactLanes + lane;
-                if (e + i < b) path[e + i] = src[i];
+                if (e + i < b) {
+                    const int2 en = src[i];
+                    const uint32_t code = (uint32_t)en.y;
+                    double sh[3] = {0.0, 0.0, 0.0};
+                    if (B > 0.0) {
+                        sh[0] = (double)((int)(code & 1023u) - kImgBias) * B;
+                        sh[1] = (double)((int)((code >> 10) & 1023u) - kImgBias) * B;
+                        sh[2] = (double)((int)((code >> 20) & 1023u) - kImgBias) * B;
+                    }
+                    const float4 Q = p4[en.x];
+                    const PairGeom pg = pair_geom(Q, o0, o1, o2, sh, u);
+                    const float gk = hit_factor(pg, u, Q.w, L, t_erf, gc, ga);
+                    path[e + i] =
+                        make_int2(en.x, (int)((uint32_t)__float_as_int(gk) | (code & kNearBit)));
+                }
             }
             ch = nxt;
         }
     }
 }
+#pragma clang fp contract(on)
 
 }  // namespace
 
@@ -771,20 +845,23 @@ void fill_kernel_tables(KernelTables* host)
 
 // The wave-cooperative walk: one wave per 64 sources of one direction.  The
 // near/far variant only for the modes that split near hits.
+template <int MODE, bool NF>
+static void launch_wave_nf(Ctx& c, RayOut o, int bs, size_t lds, int64_t waves)
+{
+    const unsigned nb = (unsigned)((waves * 64 + bs - 1) / bs);
+    hipLaunchKernelGGL((k_trace_wave<MODE, NF>), dim3(nb), dim3(bs), lds, c.stream, c.nodes, c.p4,
+                       c.mux_s, c.dirs, c.tables, c.geom, o);
+}
+
 template <int MODE>
 static void launch_wave(Ctx& c, RayOut o)
 {
     const int bs = c.prm.block_size > 0 ? c.prm.block_size : 128;
     const int64_t waves = ((c.n + 63) / 64) * (int64_t)c.n_ray;
-    const unsigned nb = (unsigned)((waves * 64 + bs - 1) / bs);
     const size_t lds = wave_lds_bytes(MODE, bs);
     constexpr bool kSplit = MODE == kModeColumn || MODE == kModePath || MODE == kModeChunk;
-    if (kSplit && o.near_far)
-        hipLaunchKernelGGL((k_trace_wave<MODE, kSplit>), dim3(nb), dim3(bs), lds, c.stream,
-                           c.nodes, c.p4, c.mux_s, c.dirs, c.tables, c.geom, o);
-    else
-        hipLaunchKernelGGL((k_trace_wave<MODE, false>), dim3(nb), dim3(bs), lds, c.stream,
-                           c.nodes, c.p4, c.mux_s, c.dirs, c.tables, c.geom, o);
+    if (kSplit && o.near_far) launch_wave_nf<MODE, kSplit>(c, o, bs, lds, waves);
+    else launch_wave_nf<MODE, false>(c, o, bs, lds, waves);
 }
 
 template <int MODE>
@@ -876,6 +953,72 @@ k_path_columns(const uint64_t* __restrict__ row_off, const int2* __restrict__ pa
             for (int off = G / 2; off > 0; off >>= 1) accn += __shfl_xor(accn, off, G);
         if (lane == 0) N[row] = acc;
         if (NF && lane == 0) Nn[row] = accn;
+    }
+}
+
+// Columns from recorded paths, streamed (the full sweep of a plain product):
+// a block takes R consecutive rows, whose entries are one contiguous range of
+// the path array.  It reads that range in windows of kStreamWin entries,
+// eight independent coalesced 8-byte loads per thread (16 KB in flight per
+// block instead of a few hundred bytes per row), gathers mux and stages the
+// products in LDS; then 256 / R lanes per row sum the row's products in FP64
+// and reduce them with shuffles.  Rows that straddle windows carry their
+// partial sums across.  A product mux_j * factor is an FP32 value (widened
+// exactly), so LDS holds it in 4 bytes.  The next block's row offsets are
+// loaded while the current block streams.  The products are those of the
+// row-group kernel; only the FP64 summation order differs.
+// Measured on MI355X over the recorded paths of the 2.1M-particle field
+// (7.35e9 intersections): 12.3 ms per product against 15.5 ms for 32 lanes
+// per row; 4096-entry windows 13.8 ms, 1024-entry windows 14.9 ms.  On the
+// 262144-particle halo both kernels take 2.70 ms.
+constexpr int kStreamWin = 2048;
+
+template <int R>
+__global__ void __launch_bounds__(256)
+k_path_stream(const uint64_t* __restrict__ row_off, const int2* __restrict__ path,
+              const float* __restrict__ mux, int64_t n_rows, double* __restrict__ N)
+{
+    constexpr int G = 256 / R;                 // lanes per row in the reduction
+    constexpr int kPer = kStreamWin / 256;     // entries per thread per window
+    __shared__ float s_prod[kStreamWin];
+    __shared__ uint64_t s_off[R + 1];
+    const int t = threadIdx.x;
+    const int r = t / G, g = t % G;
+    const long long* p = reinterpret_cast<const long long*>(path);
+    const int64_t n_blk = (n_rows + R - 1) / R;
+    int64_t blk = blockIdx.x;
+    // row offsets of the block (threads 0..R), loaded one block ahead
+    uint64_t off = 0;
+    if (blk < n_blk && t <= R && blk * R + t <= n_rows) off = row_off[blk * R + t];
+    for (; blk < n_blk; blk += gridDim.x) {
+        const int64_t r0 = blk * R;
+        const int rn = (int)(n_rows - r0 < R ? n_rows - r0 : R);
+        __syncthreads();                        // the previous block's reads are done
+        if (t <= rn) s_off[t] = off;
+        const int64_t nr0 = r0 + (int64_t)gridDim.x * R;
+        if (nr0 < n_rows && t <= R && nr0 + t <= n_rows) off = row_off[nr0 + t];
+        __syncthreads();
+        const uint64_t e0 = s_off[0], e1 = s_off[rn];
+        const uint64_t lo = r < rn ? s_off[r] : e1, hi = r < rn ? s_off[r + 1] : e1;
+        double acc = 0.0;
+        for (uint64_t w0 = e0; w0 < e1; w0 += kStreamWin) {
+            long long v[kPer];
+#pragma unroll
+            for (int i = 0; i < kPer; ++i) {
+                const uint64_t e = w0 + t + 256 * i;
+                v[i] = e < e1 ? __builtin_nontemporal_load(p + e) : 0ll;
+            }
+#pragma unroll
+            for (int i = 0; i < kPer; ++i)
+                s_prod[t + 256 * i] = mux[(int)v[i]] * __int_as_float((int)(v[i] >> 32));
+            __syncthreads();
+            const uint64_t a = lo > w0 ? lo : w0;
+            const uint64_t b = hi < w0 + kStreamWin ? hi : w0 + kStreamWin;
+            for (uint64_t e = a + g; e < b; e += G) acc += (double)s_prod[e - w0];
+            __syncthreads();                    // the window is consumed
+        }
+        for (int off2 = G / 2; off2 > 0; off2 >>= 1) acc += __shfl_xor(acc, off2, G);
+        if (g == 0 && r < rn) N[r0 + r] = acc;
     }
 }
 
@@ -1016,7 +1159,8 @@ hipError_t launch_compact_chunks(Ctx& c)
     if (n_rows == 0) return hipSuccess;
     const unsigned nb = stride_blocks(n_rows, 256 / kCompactLanes);
     hipLaunchKernelGGL(k_compact_chunks, dim3(nb), dim3(256), 0, c.stream, c.row_off,
-                       c.row_first, c.chunk_next, c.pool, n_rows, c.path);
+                       c.row_first, c.chunk_next, c.pool, n_rows, c.path, c.p4, c.dirs, c.tables,
+                       c.geom);
     return hipGetLastError();
 }
 
@@ -1060,6 +1204,40 @@ hipError_t launch_path_g(Ctx& c, int64_t n_rows, unsigned nb)
 }
 
 }  // namespace
+
+// rows per block of the streamed product: on average at most one window of
+// entries per block, between 4 rows (64 lanes each) and 64 rows (4 lanes each)
+static int stream_rows(double mean)
+{
+    int R = 64;
+    while (R > 4 && R * mean > kStreamWin) R /= 2;
+    return R;
+}
+
+hipError_t launch_path_stream(Ctx& c)
+{
+    const int64_t n_rows = c.n * (int64_t)c.n_ray;
+    if (n_rows == 0) return hipSuccess;
+    const double mean = (double)c.path_hits / (double)n_rows;
+    const int R = stream_rows(mean);
+    const unsigned nb = stride_blocks(n_rows, R);
+    if (R == 64)
+        hipLaunchKernelGGL(k_path_stream<64>, dim3(nb), dim3(256), 0, c.stream, c.row_off,
+                           c.path, c.mux_s, n_rows, c.N_s);
+    else if (R == 32)
+        hipLaunchKernelGGL(k_path_stream<32>, dim3(nb), dim3(256), 0, c.stream, c.row_off,
+                           c.path, c.mux_s, n_rows, c.N_s);
+    else if (R == 16)
+        hipLaunchKernelGGL(k_path_stream<16>, dim3(nb), dim3(256), 0, c.stream, c.row_off,
+                           c.path, c.mux_s, n_rows, c.N_s);
+    else if (R == 8)
+        hipLaunchKernelGGL(k_path_stream<8>, dim3(nb), dim3(256), 0, c.stream, c.row_off,
+                           c.path, c.mux_s, n_rows, c.N_s);
+    else
+        hipLaunchKernelGGL(k_path_stream<4>, dim3(nb), dim3(256), 0, c.stream, c.row_off,
+                           c.path, c.mux_s, n_rows, c.N_s);
+    return hipGetLastError();
+}
 
 hipError_t launch_path_columns(Ctx& c, int group)
 {

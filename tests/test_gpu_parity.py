@@ -665,3 +665,50 @@ def test_full_halo_one_walk_recording():
     ref = oracle.step(wl, x, sources=src)
     _check_columns(cols[1][0][src], ref["N"])
     s.close()
+
+
+@pytest.mark.parametrize("which", ["lattice", "field_small", "halo_full"])
+def test_streamed_product_equals_its_definition(which):
+    """The streamed product (blocks of consecutive rows read through LDS
+    windows of 2048 entries) against the product with 32 lanes per row, and on
+    sampled rays against its definition written out on the host: N = the FP64
+    sum over the ray's recorded hits of fl32(mux_j * factor), mux_j =
+    fl32(mu_j x_j).  The full halo has blocks of more than one window, so rows
+    that straddle windows are covered."""
+    wl = _tile_workload(which)
+    s = _solver(wl)
+    rng = np.random.default_rng(17)
+    x = np.minimum(oracle.x_thin(wl) * rng.uniform(1, 1e3, wl.n), 0.99)
+    s.set_state(torch.tensor(x))
+    s.set_tuning(path_group=32)
+    Ng, hg = s.compute_columns()
+    s.set_tuning(path_group=0)
+    Ns, hs = s.compute_columns()
+    assert hg == hs
+    Ng, Ns = Ng.cpu().numpy(), Ns.cpu().numpy()
+    np.testing.assert_allclose(Ns, Ng, rtol=1e-13, atol=0)
+    # blocks of the stream in tree order: R rows, R from the mean row length
+    cnt = np.zeros(s.n * s.n_ray + 1, np.int64)
+    s._call("rrt_get_hits", 0, cnt.ctypes.data, None, None)
+    per_ray = np.diff(cnt).reshape(s.n, s.n_ray)
+    perm = s.tree()["perm"]
+    rows = per_ray[perm].T.reshape(-1)                # row k * n + ps
+    mean = rows.sum() / rows.size
+    R = 64
+    while R > 4 and R * mean > 2048:
+        R //= 2
+    pad = (-rows.size) % R
+    blocks = np.concatenate([rows, np.zeros(pad, np.int64)]).reshape(-1, R).sum(axis=1)
+    _say(which, "rows per block", R, "largest block", int(blocks.max()), "entries")
+    if which == "halo_full":
+        assert blocks.max() > 2048, "no block spans two windows"
+    src = rng.choice(wl.n, 48, replace=False)
+    ro, hj, fac = s.path_rows(src)
+    mux = (np.asarray(wl.mu, np.float64) * x).astype(np.float32)
+    for i, p in enumerate(src):
+        for k in range(s.n_ray):
+            a, b = ro[i * s.n_ray + k], ro[i * s.n_ray + k + 1]
+            terms = (mux[hj[a:b]] * fac[a:b]).astype(np.float32).astype(np.float64)
+            exact = math.fsum(terms)
+            bound = 1e-15 * max(b - a, 1) * np.abs(terms).sum()
+            assert abs(Ns[p, k] - exact) <= bound, (p, k, Ns[p, k], exact)
