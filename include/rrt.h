@@ -398,10 +398,19 @@ int rrt_iterate_halos(rrt_ctx* ctx, int32_t max_iter, double tol, int32_t per_la
  *                         once the paths are in rows.  0: a counting walk,
  *                         then a recording walk.  n > 1: one pass with a pool
  *                         of about n chunks, also on a first recording.  The
- *                         same paths either way. */
+ *                         same paths either way.
+ *   RRT_TUNE_PACKET_QUEUE 1 (default): the wave-cooperative walk runs as a
+ *                         persistent grid of the blocks the device holds at
+ *                         once, whose waves take packets (64 sources of one
+ *                         direction, over every halo) from one global counter
+ *                         until none is left; 0: one wave per packet, the
+ *                         hardware scheduling them.  The same results either
+ *                         way (measured on MI355X: the queue is 5% faster on
+ *                         the 64-halo batch's column walk, 2-3% on the
+ *                         recording walks of the field and the halo). */
 enum { RRT_TUNE_TRACE_BLOCK = 1, RRT_TUNE_PACKET = 2, RRT_TUNE_PATH_GROUP = 3, RRT_TUNE_LEAF = 4,
        RRT_TUNE_ADJOINT = 5, RRT_TUNE_TILES = 6, RRT_TUNE_KEEP_COLUMNS = 7,
-       RRT_TUNE_ONE_PASS = 8 };
+       RRT_TUNE_ONE_PASS = 8, RRT_TUNE_PACKET_QUEUE = 9 };
 int rrt_set_tuning(rrt_ctx* ctx, int32_t key, int32_t value);
 
 /* Replace the state: x device double[n] in input order (checkpoint / resume,

@@ -123,7 +123,8 @@ enum {
     kRedConvRel = 5,    // particles of a sweep with |dx| / x < tol
     kRedInput = 6,      // a given x or n_H was non-finite or out of range
     kRedNumeric = 7,    // an update produced a non-finite neutral fraction
-    kRedSlots = 8
+    kRedQueue = 8,      // the persistent walk's next packet
+    kRedSlots = 9
 };
 
 struct Ctx {
@@ -193,6 +194,7 @@ struct Ctx {
     // entries from a pool of kPoolSlices slices, linked per row, then
     // compacted into path
     bool one_pass = true;
+    bool packet_queue = true;    // persistent walk with a global packet queue
     bool images_fit = true;      // every reachable periodic image codes in 10 bits per axis
     uint64_t pool_cap = 0;            // > 0: at most this many chunks (tests the fallback)
     uint64_t last_total = 0;          // entries of the last recording (sizes the pool)

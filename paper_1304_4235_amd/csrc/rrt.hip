@@ -1811,6 +1811,10 @@ int rrt_set_tuning(rrt_ctx* x, int32_t key, int32_t value)
         c.pool_cap = value > 1 ? (uint64_t)value : 0;
         free_pool(c);
         return RRT_OK;
+    case RRT_TUNE_PACKET_QUEUE:
+        if (value != 0 && value != 1) return fail(c, RRT_E_ARG, "packet_queue must be 0 or 1");
+        c.packet_queue = value != 0;
+        break;
     case RRT_TUNE_KEEP_COLUMNS:
         if (value != 0 && value != 1) return fail(c, RRT_E_ARG, "keep_columns must be 0 or 1");
         c.keep_columns = value;

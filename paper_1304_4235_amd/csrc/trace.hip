@@ -124,6 +124,10 @@ struct RayOut {
     // stats mode: [rays, wave node visits, lane node visits, wave leaf visits,
     // pair tests, hits], accumulated
     unsigned long long* stats;
+    // wave-cooperative walk, persistent form: a resident grid whose waves take
+    // packets (64 sources of one direction, over every halo) from this counter
+    // until none is left; null = one wave per packet
+    unsigned long long* queue;
 };
 
 // Place of tree position ps among the sorted sampled sources, or -1.
@@ -440,7 +444,7 @@ inline size_t wave_lds_bytes(int mode, int block)
                             : (size_t)waves * (kWaveOrgBytes + kWaveMaskBytes);
 }
 
-template <int MODE, bool NF>
+template <int MODE, bool NF, bool PQ>
 __global__ void __launch_bounds__(256, 6)
 k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
              const float* __restrict__ mux, const double* __restrict__ dirs,
@@ -470,7 +474,13 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
 
     const uint64_t lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
     const int64_t waves_per_dir = (g.n + 63) / 64;
-    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    for (;;) {                                               // packets of this wave
+    if (PQ) {
+        unsigned long long w = 0;
+        if (lane == 0) w = atomicAdd(out.queue, 1ull);
+        wave = (int64_t)__shfl(w, 0, 64);
+    }
     // the wave's direction and image range are uniform: scalar registers
     const int k = __builtin_amdgcn_readfirstlane((int)(wave / waves_per_dir));
     if (k >= g.n_ray) return;                                // whole wave
@@ -763,6 +773,8 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
         atomicAdd(out.stats + 4, (unsigned long long)st_pairs);
         atomicAdd(out.stats + 5, (unsigned long long)c64);
     }
+    if (!PQ) return;
+    }   // packets of this wave
 }
 
 // One-pass recording, second step: each row's entries from its chain of
@@ -832,6 +844,11 @@ k_compact_chunks(const uint64_t* __restrict__ row_off, const uint32_t* __restric
 }
 #pragma clang fp contract(on)
 
+__global__ void k_zero_u64(unsigned long long* p)
+{
+    if (threadIdx.x == 0) *p = 0ull;
+}
+
 }  // namespace
 
 void fill_kernel_tables(KernelTables* host)
@@ -843,14 +860,35 @@ void fill_kernel_tables(KernelTables* host)
     host->gauss_a = t * t / std::log(2.0);
 }
 
-// The wave-cooperative walk: one wave per 64 sources of one direction.  The
-// near/far variant only for the modes that split near hits.
+// The wave-cooperative walk: one wave per 64 sources of one direction, or
+// (packet queue) a resident grid taking packets from a counter.  The near/far
+// variant only for the modes that split near hits.
 template <int MODE, bool NF>
 static void launch_wave_nf(Ctx& c, RayOut o, int bs, size_t lds, int64_t waves)
 {
     const unsigned nb = (unsigned)((waves * 64 + bs - 1) / bs);
-    hipLaunchKernelGGL((k_trace_wave<MODE, NF>), dim3(nb), dim3(bs), lds, c.stream, c.nodes, c.p4,
-                       c.mux_s, c.dirs, c.tables, c.geom, o);
+    // the persistent form for the walks that record, count or evaluate
+    constexpr bool kQueued = MODE == kModeColumn || MODE == kModeCount || MODE == kModePath ||
+                             MODE == kModeChunk;
+    if (kQueued && c.packet_queue) {
+        // a kernel, not a memset, clears the counter (the launch may be captured)
+        hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, c.stream, c.red + kRedQueue);
+        o.queue = c.red + kRedQueue;
+        int per_cu = 0, cus = 0, dev = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_trace_wave<MODE, NF, kQueued>,
+                                                         bs, lds) != hipSuccess || per_cu < 1)
+            per_cu = 1;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                hipSuccess || cus < 1)
+            cus = 1;
+        const unsigned resident = (unsigned)std::min<int64_t>(nb, (int64_t)per_cu * cus);
+        hipLaunchKernelGGL((k_trace_wave<MODE, NF, kQueued>), dim3(resident), dim3(bs), lds,
+                           c.stream, c.nodes, c.p4, c.mux_s, c.dirs, c.tables, c.geom, o);
+        return;
+    }
+    hipLaunchKernelGGL((k_trace_wave<MODE, NF, false>), dim3(nb), dim3(bs), lds, c.stream,
+                       c.nodes, c.p4, c.mux_s, c.dirs, c.tables, c.geom, o);
 }
 
 template <int MODE>

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "librrt.so")
 
 RRT_OK, RRT_NOT_CONVERGED = 0, 1
 TUNE_KEYS = {"trace_block": 1, "packet": 2, "path_group": 3, "leaf": 4, "adjoint_scatter": 5,
-             "tiles": 6, "keep_columns": 7, "one_pass": 8}
+             "tiles": 6, "keep_columns": 7, "one_pass": 8, "packet_queue": 9}
 RRT_E_WORKSPACE, RRT_E_CAPACITY = -5, -6
 ERRORS = {-1: "RRT_E_ARG", -2: "RRT_E_HIP", -3: "RRT_E_INPUT", -4: "RRT_E_STATE",
           -5: "RRT_E_WORKSPACE", -6: "RRT_E_CAPACITY"}
@@ -336,7 +336,8 @@ class Solver:
 
     def set_tuning(self, **kw):
         """Launch knobs: trace_block, packet (1 or 64), path_group, leaf, adjoint_scatter (0/1),
-        tiles (0/1), keep_columns (0/1), one_pass (0, 1 or a pool size in chunks)."""
+        tiles (0/1), keep_columns (0/1), one_pass (0, 1 or a pool size in chunks),
+        packet_queue (0/1)."""
         for k, v in kw.items():
             self._call("rrt_set_tuning", TUNE_KEYS[k], int(v))
 

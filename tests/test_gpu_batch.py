@@ -168,3 +168,30 @@ def test_autotuner_picks_change_no_result(tmp_path):
     r = s.iterate_halos(200, 1e-3, per_launch=best["per_launch"])
     np.testing.assert_array_equal(r["halo_iters"], ref["halo_iters"])
     np.testing.assert_allclose(r["x"].cpu().numpy(), ref["x"].cpu().numpy(), rtol=1e-9)
+
+
+@pytest.mark.parametrize("paths", [-1, 0])
+def test_packet_queue_gives_the_grid_results(paths):
+    """The persistent walk (a resident grid whose waves take 64-ray packets of
+    every halo from one counter) against one wave per packet: the same hit
+    lists, recorded paths, columns and iterates bit for bit, on the batch with
+    a one-particle halo and halos smaller than a packet."""
+    wl, _ = _batch(SIZES, PEAKS)
+    out = []
+    for q in (0, 1):
+        s = _solver(wl, record_paths=paths)
+        s.set_tuning(packet_queue=q)
+        off, hj, hi = s.hits()
+        N, h = s.compute_columns()
+        r = s.iterate_halos(200, 1e-3, per_launch=8)
+        src = np.arange(0, wl.n, 37)
+        ro, pj, pf = s.path_rows(src) if paths != 0 else (None, None, None)
+        out.append((off, hj, hi, N.cpu().numpy(), h, r["x"].cpu().numpy(), r["halo_iters"],
+                    ro, pj, pf))
+    for a, b in zip(out[0], out[1]):
+        if a is None:
+            continue
+        if isinstance(a, np.ndarray):
+            np.testing.assert_array_equal(a, b)
+        else:
+            assert a == b
