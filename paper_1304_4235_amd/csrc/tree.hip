@@ -378,6 +378,19 @@ __device__ __forceinline__ bool collapses(int cnt, int seg, int leaf_max)
 }
 
 // Bottom-up: the second thread to reach a node combines both children.
+// Everything threads share here (the nodes' bounds, counts, layout sizes and
+// halos, and the arrival flags) is read and written with agent-scope atomics,
+// which are coherent across the device's L2 caches without a fence.  What
+// the protocol needs besides is order: a node's results are complete before
+// its parent's flag counts the arrival (wait for the stores), and a child's
+// results are read only after the flag showed both arrived (a compiler
+// barrier; the loads are issued after the atomic returns).  A full fence
+// would write back and invalidate the L2 at every level of every thread.
+__device__ __forceinline__ void stores_done()
+{
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+}
+
 __global__ void k_refit(const float4* __restrict__ p4, int n, int leaf_max,
                         const int32_t* __restrict__ left, const int32_t* __restrict__ right,
                         const int32_t* __restrict__ parent, float* klo, float* khi,
@@ -394,10 +407,10 @@ __global__ void k_refit(const float4* __restrict__ p4, int n, int leaf_max,
             atomicOr(err, 1ull);
             return;
         }
-        __threadfence();
+        stores_done();
         int old = atomicAdd(&flag[node], 1);
         if (old == 0) return;
-        __threadfence();
+        asm volatile("" ::: "memory");
         ChildInfo L = child_info(left[node], p4, klo, khi, kcnt, kdfs, kseg, seg_of);
         ChildInfo R = child_info(right[node], p4, klo, khi, kcnt, kdfs, kseg, seg_of);
         for (int a = 0; a < 3; ++a) {
