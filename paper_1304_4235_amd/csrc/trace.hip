@@ -384,6 +384,35 @@ k_trace(const Node* __restrict__ nodes, const float4* __restrict__ p4,
 }
 // LDS written by some lanes of a wave and read by others: order the accesses
 // within the wave (no block barrier needed, the wave runs in lockstep)
+// One pool chunk for every lane with want: one allocation in the wave's slice,
+// then, for lanes it could not serve, in further slices (stride 97, odd, so
+// kSliceTries distinct ones) while any has room.  Returns whether this lane
+// got one (its index in nc).
+__device__ __forceinline__ bool take_chunk(bool want, uint32_t slice, int lane,
+                                           uint64_t lt_mask, unsigned long long* pool_ctr,
+                                           uint64_t slice_chunks, uint32_t& nc)
+{
+    uint64_t need = __builtin_amdgcn_ballot_w64(want);
+    bool got = false;
+    for (int t = 0; t < kSliceTries && need; ++t) {
+        const uint32_t sl = (slice + 97u * (uint32_t)t) % kPoolSlices;
+        const int leader = __ffsll((unsigned long long)need) - 1;
+        unsigned long long base = 0;
+        if (lane == leader)
+            base = atomicAdd(pool_ctr + (size_t)sl * kCtrStride, (unsigned long long)__popcll(need));
+        base = __shfl(base, leader, 64);
+        if (want && !got) {
+            const unsigned long long local = base + __popcll(need & lt_mask);
+            if (local < slice_chunks) {
+                got = true;
+                nc = (uint32_t)(sl * slice_chunks + local);
+            }
+        }
+        need = __builtin_amdgcn_ballot_w64(want && !got);
+    }
+    return got;
+}
+
 // lanes where b holds (the HIP __ballot takes an int and re-tests it)
 __device__ __forceinline__ uint64_t wave_ballot(bool b)
 {
@@ -426,6 +455,7 @@ __device__ __forceinline__ void wave_sync()
 constexpr int kWaveOrgBytes = 3 * 64 * (int)sizeof(double);
 constexpr int kWaveMaskBytes = 64 * (int)sizeof(unsigned int);
 constexpr int kWaveGkBytes = 64 * kLeafMax * (int)sizeof(float);
+constexpr int kWaveDstBytes = 64 * 16;     // per hit ray: where its entries go
 
 // modes whose walk evaluates the chord factor of its hits (the one-walk
 // recording leaves it to the compaction)
@@ -435,13 +465,21 @@ __host__ __device__ constexpr bool mode_factors(int mode)
            mode == kModeScatter;
 }
 
+// modes whose pair lanes write the entries themselves (no per-ray hit loop)
+__host__ __device__ constexpr bool mode_direct(int mode)
+{
+    return mode == kModePath || mode == kModeChunk;
+}
+
 // dynamic LDS bytes of one k_trace_wave block
 inline size_t wave_lds_bytes(int mode, int block)
 {
-    const int waves = block / 64;
-    return mode_factors(mode) ? (size_t)kTabIntervals * sizeof(float4) +
-                                  (size_t)waves * (kWaveOrgBytes + kWaveMaskBytes + kWaveGkBytes)
-                            : (size_t)waves * (kWaveOrgBytes + kWaveMaskBytes);
+    const size_t waves = (size_t)(block / 64);
+    size_t b = waves * (kWaveOrgBytes + kWaveMaskBytes);
+    if (mode_factors(mode)) b += (size_t)kTabIntervals * sizeof(float4);
+    if (mode_direct(mode)) b += waves * kWaveDstBytes;
+    else if (mode_factors(mode)) b += waves * kWaveGkBytes;
+    return b;
 }
 
 template <int MODE, bool NF, bool PQ>
@@ -452,6 +490,7 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
 {
     constexpr bool kCountOnly = MODE == kModeCount || MODE == kModeStats;
     constexpr bool kTerms = mode_factors(MODE);
+    constexpr bool kDirect = mode_direct(MODE);
     extern __shared__ __align__(16) unsigned char s_dyn[];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
@@ -466,6 +505,11 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
         reinterpret_cast<unsigned int*>(s_wave + n_wv * kWaveOrgBytes) + wv * 64;
     float* s_gk = reinterpret_cast<float*>(s_wave + n_wv * (kWaveOrgBytes + kWaveMaskBytes)) +
                   wv * 64 * kLeafMax;
+    // direct modes, per hit ray: path mode its next write offset; chunk mode
+    // its chunk, the entries in it and its reserved next chunk
+    uint64_t* s_w = reinterpret_cast<uint64_t*>(s_wave + n_wv * (kWaveOrgBytes + kWaveMaskBytes)) +
+                    wv * 64 * 2;
+    uint32_t* s_ch = reinterpret_cast<uint32_t*>(s_w);       // [cur, fill, next, -] per ray
     if (kTerms) {
         for (int i = threadIdx.x; i < kTabIntervals; i += blockDim.x) t_erf[i] = tabs->erf_t[i];
         __syncthreads();
@@ -539,11 +583,11 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
     // stats mode: wave node visits, lane node visits, wave leaf visits, pair tests
     uint64_t st_nodes = 0, st_lanes = 0, st_leaves = 0, st_pairs = 0;
     // chunk mode: the ray's current chunk (kNoChunk before the first, kDropped
-    // once the pool ran out for it: then the ray only counts) and the entries
-    // in it.  Waves take chunks from slice (wave mod kPoolSlices) first, each
-    // slice with its own counter.
+    // once the pool ran out for it: then the ray only counts), the entries in
+    // it, and the next chunk once reserved.  Waves take chunks from slice
+    // (wave mod kPoolSlices) first, each slice with its own counter.
     constexpr uint32_t kDropped = kNoChunk - 1;
-    uint32_t cur = kNoChunk, fill = kChunkLen;
+    uint32_t cur = kNoChunk, fill = 0, nxt = kNoChunk;
     const uint32_t slice = __builtin_amdgcn_readfirstlane((uint32_t)(wave % kPoolSlices));
     const double nur = (MODE == kModeScatter && active) ? (double)out.nu[gid] : 0.0;
 
@@ -639,11 +683,42 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
             const bool hit = (hm >> lane) & 1ull;
             const int k_hit = __popcll(hm);
             const int rank = __popcll(hm & lt_mask);
+            if (MODE == kModeChunk) {
+                // room for every entry this leaf can add (at most c): a first
+                // chunk, or the next one when the current could overflow
+                const bool want = hit && cur != kDropped &&
+                                  (cur == kNoChunk ||
+                                   (fill + (uint32_t)c > kChunkLen && nxt == kNoChunk));
+                if (wave_ballot(want)) {
+                    uint32_t nc = 0;
+                    const bool got = take_chunk(want, slice, lane, lt_mask, out.pool_ctr,
+                                                out.slice_chunks, nc);
+                    if (want && got) {
+                        if (cur == kNoChunk) {
+                            out.row_first[gid] = nc;
+                            cur = nc;
+                            fill = 0;
+                        } else {
+                            out.chunk_next[cur] = nc;
+                            nxt = nc;
+                        }
+                    } else if (want) {
+                        cur = kDropped;                   // counted, not stored
+                        out.pool_ctr[(size_t)kPoolSlices * kCtrStride] = 1ull;
+                    }
+                }
+            }
             if (hit) {
                 s_o[rank] = (double)rpf[0];
                 s_o[64 + rank] = (double)rpf[1];
                 s_o[128 + rank] = (double)rpf[2];
                 s_mask[rank] = 0u;
+                if (MODE == kModePath) s_w[2 * rank] = w;
+                if (MODE == kModeChunk) {
+                    s_ch[4 * rank] = cur;
+                    s_ch[4 * rank + 1] = fill;
+                    s_ch[4 * rank + 2] = nxt;
+                }
             }
             wave_sync();
             const int pairs = k_hit * c;
@@ -675,10 +750,47 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
                 float gk = 0.0f;
                 if (kTerms && in) gk = hit_factor(pg, u, Q.w, L, t_erf, gc, ga);
                 if (in) atomicOr(&s_mask[r], (near ? 0x101u : 1u) << q);
-                if (kTerms) s_gk[t] = gk;
+                if (kTerms && !kDirect) s_gk[t] = gk;
+                if (kDirect) {
+                    // The entry's place: its ray's hits in this leaf are in
+                    // particle order, and every pair of a lower particle of
+                    // the same ray has a lower t (this iteration or earlier),
+                    // so its bit is in the mask now.
+                    wave_sync();
+                    if (in) {
+                        const uint32_t e = __popc(s_mask[r] & ((1u << q) - 1u));
+                        const uint32_t bits = (kTerms ? (uint32_t)__float_as_int(gk) : img_code) |
+                                              (near ? kNearBit : 0u);
+                        if (MODE == kModePath) {
+                            const uint64_t pos = s_w[2 * r] + e;
+                            if (pos < out.hit_cap) out.path[pos] = make_int2(j, (int)bits);
+                        } else {
+                            const uint32_t c0 = s_ch[4 * r], slot = s_ch[4 * r + 1] + e;
+                            const uint32_t ch = slot < kChunkLen ? c0 : s_ch[4 * r + 2];
+                            if (c0 < kDropped && ch < kDropped)
+                                out.pool[(uint64_t)ch * kChunkLen + (slot & (kChunkLen - 1))] =
+                                    make_int2(j, (int)bits);
+                        }
+                    }
+                }
             }
             wave_sync();
-            if (hit) {
+            if (kDirect && hit) {
+                const uint32_t n_new = __popc(s_mask[rank] & 0xffu);
+                cnt += n_new;
+                if (MODE == kModePath) w += n_new;
+                if (MODE == kModeChunk && cur < kDropped) {
+                    fill += n_new;
+                    // a full chunk moves on to the reserved one (reserved
+                    // whenever this leaf could overflow the current one)
+                    if (fill >= kChunkLen && nxt != kNoChunk) {
+                        cur = nxt;
+                        fill -= kChunkLen;
+                        nxt = kNoChunk;
+                    }
+                }
+            }
+            if (!kDirect && hit) {
                 const unsigned int m = s_mask[rank];
                 if (kCountOnly) cnt += __popc(m & 0xffu);
                 for (unsigned int hb = kCountOnly ? 0u : m & 0xffu; hb; hb &= hb - 1) {
@@ -695,55 +807,7 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
                         ++w;
                     }
                     const bool near = NF && ((m >> (8 + q)) & 1u);
-                    if (MODE == kModePath) {
-                        const uint32_t bits = (uint32_t)__float_as_int(gk) | (near ? kNearBit : 0u);
-                        if (w < out.hit_cap) out.path[w] = make_int2(j, (int)bits);
-                        ++w;
-                    } else if (MODE == kModeChunk) {
-                        if (fill == kChunkLen && cur != kDropped) {
-                            // a chunk for every lane that needs one now: one
-                            // allocation in the wave's slice, then, for lanes it
-                            // could not serve, in further slices (stride 97,
-                            // odd, so kSliceTries distinct ones) while any has room
-                            uint64_t need = wave_ballot(1);
-                            bool got = false;
-                            uint32_t nc = 0;
-                            for (int t = 0; t < kSliceTries && need; ++t) {
-                                const uint32_t sl = (slice + 97u * (uint32_t)t) % kPoolSlices;
-                                const int leader = __ffsll((unsigned long long)need) - 1;
-                                unsigned long long base = 0;
-                                if (lane == leader)
-                                    base = atomicAdd(out.pool_ctr + (size_t)sl * kCtrStride,
-                                                     (unsigned long long)__popcll(need));
-                                base = __shfl(base, leader, 64);
-                                if (!got) {
-                                    const unsigned long long local =
-                                        base + __popcll(need & lt_mask);
-                                    if (local < out.slice_chunks) {
-                                        got = true;
-                                        nc = (uint32_t)(sl * out.slice_chunks + local);
-                                    }
-                                }
-                                need = wave_ballot(!got);
-                            }
-                            if (got) {
-                                if (cur == kNoChunk) out.row_first[gid] = nc;
-                                else out.chunk_next[cur] = nc;
-                                cur = nc;
-                                fill = 0;
-                            } else {
-                                cur = kDropped;           // counted, not stored
-                                out.pool_ctr[(size_t)kPoolSlices * kCtrStride] = 1ull;
-                            }
-                        }
-                        if (cur != kDropped) {
-                            // the factor is the compaction's: the entry holds
-                            // the image in its place
-                            const uint32_t bits = img_code | (near ? kNearBit : 0u);
-                            out.pool[(uint64_t)cur * kChunkLen + fill] = make_int2(j, (int)bits);
-                            ++fill;
-                        }
-                    } else if (MODE == kModeScatter) {
+                    if (MODE == kModeScatter) {
                         if (nur != 0.0) unsafeAtomicAdd(out.y + j, (double)gk * nur);
                     } else if (near) {
                         accn += (double)((float)out.mu[j] * gk);
