@@ -74,7 +74,7 @@ typedef struct rrt_ctx rrt_ctx;
 typedef struct {
     double l_ray;          /* ray length in kpc, >= 0 (Sec. 3.3: l_ray)              */
     double box;            /* periodic box side in kpc; 0 = isolated (no images)    */
-    int32_t leaf_size;     /* max particles per tree leaf, 1..8 (0 = default 8)     */
+    int32_t leaf_size;     /* max particles per tree leaf, 1..16 (0 = default 16)   */
     int32_t block_size;    /* threads per block of the traversal: 0 (= 128) or a
                               multiple of 64 up to 256                               */
     int32_t record_paths;  /* -1 = record when they fit in the path buffer
@@ -181,7 +181,7 @@ const char* rrt_last_error(const rrt_ctx* ctx);
  * thin state x_thin = x_-(Gamma_thin) (Sec. 4).  Copied into the workspace
  * (rrt_workspace_size with this n); validated by rrt_build_tree, which must
  * follow and returns RRT_E_INPUT for non-finite or out-of-range values
- * (x_init outside [0, 1] included).  n >= 1. */
+ * (x_init outside [0, 1] included).  1 <= n <= 2^27 (RRT_E_ARG otherwise). */
 int rrt_set_particles(rrt_ctx* ctx, int64_t n, const float* pos, const float* h,
                       const float* mu, const float* n_H, const float* T,
                       const double* x_init);
@@ -357,7 +357,7 @@ int rrt_iterate_halos(rrt_ctx* ctx, int32_t max_iter, double tol, int32_t per_la
  *                         other products (near/far split, halos that stopped,
  *                         per-block source lists) take lanes per ray from the
  *                         mean intersections per ray
- *   RRT_TUNE_LEAF         particles per tree leaf (1..8), from the next build
+ *   RRT_TUNE_LEAF         particles per tree leaf (1..16), from the next build
  *   RRT_TUNE_ADJOINT      transposed column product of rrt_backward over
  *                         recorded paths: 0 (default) = gather over paths
  *                         transposed once per geometry when they fit in the

@@ -24,7 +24,7 @@ from typing import Optional
 import numpy as np
 import torch
 
-DEFAULT_SPACE = dict(leaf=[4, 8], trace_block=[64, 128, 256], packet=[64, 1],
+DEFAULT_SPACE = dict(leaf=[8, 16], trace_block=[64, 128, 256], packet=[64, 1],
                      path_group=[16, 32, 64], per_launch=[4, 16, 64])
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "rrt_autotune.json")
 

@@ -16,9 +16,10 @@ namespace rrt {
 constexpr int kTabIntervals = 256;        // cubic pieces per kernel table
 constexpr int kMaxRays = 3072;
 constexpr int kMaxBins = 4096;
-constexpr int kDefaultLeaf = 8;
-// most particles a leaf holds (its count is stored in 3 bits)
-constexpr int kLeafMax = 8;
+constexpr int kDefaultLeaf = 16;
+// most particles a leaf holds (its count minus one is stored in 4 bits)
+constexpr int kLeafMax = 16;
+constexpr int kLeafShift = 4;
 // waves per block of the traversal kernels (blocks of at most 256 threads)
 constexpr int kWavesPerBlock = 4;
 // particles x rays: rays are indexed with 32-bit integers on the device
@@ -53,7 +54,8 @@ inline unsigned stride_blocks(int64_t items, int items_per_block)
 //   a = (lo.x, lo.y, lo.z, skip as int bits)
 //   b = (hi.x, hi.y, hi.z, leaf word as int bits)
 // leaf word: -1 for an internal node (its first child is the next node);
-// (first << 3) | (count - 1) for a leaf holding particles first..first+count-1.
+// (first << kLeafShift) | (count - 1) for a leaf holding particles
+// first..first+count-1 (so n < 2^27).
 struct Node {
     float4 a;
     float4 b;

@@ -638,11 +638,11 @@ int rrt_create(rrt_ctx** out, const rrt_params* params, void* stream)
     }
     *out = nullptr;
     if (!(params->l_ray >= 0.0) || !std::isfinite(params->l_ray) || !(params->box >= 0.0) ||
-        !std::isfinite(params->box) || params->leaf_size < 0 || params->leaf_size > 8 ||
+        !std::isfinite(params->box) || params->leaf_size < 0 || params->leaf_size > kLeafMax ||
         params->block_size < 0 || params->block_size > 256 || (params->block_size % 64) != 0 ||
         params->record_paths < -1 || params->record_paths > 1 || params->traversal < 0 ||
         params->traversal > 1) {
-        g_create_err = "rrt_create: invalid params (l_ray >= 0, box >= 0, leaf_size 0..8, "
+        g_create_err = "rrt_create: invalid params (l_ray >= 0, box >= 0, leaf_size 0..16, "
                        "block_size a multiple of 64 up to 256, record_paths -1..1, "
                        "traversal 0..1)";
         return RRT_E_ARG;
@@ -705,7 +705,7 @@ const char* rrt_last_error(const rrt_ctx* x)
 int rrt_workspace_size(const rrt_ctx* x, int64_t n, int32_t n_ray, int32_t n_bins,
                        int32_t n_halo, int32_t reverse_K, size_t* bytes)
 {
-    if (!x || !bytes || n < 0 || n > (int64_t(1) << 28) || n_ray < 0 || n_ray > kMaxRays ||
+    if (!x || !bytes || n < 0 || n > (int64_t(1) << 27) || n_ray < 0 || n_ray > kMaxRays ||
         n_bins < 0 || n_bins > kMaxBins || n_halo < 0 || n_halo > 4096 || reverse_K < 0 ||
         reverse_K > 100000)
         return RRT_E_ARG;
@@ -780,8 +780,8 @@ int rrt_set_particles(rrt_ctx* x, int64_t n, const float* pos, const float* h, c
     if (!x) return RRT_E_ARG;
     Ctx& c = x->c;
     if (int r = need_ws(c)) return r;
-    if (n < 1 || n > (int64_t(1) << 28))
-        return fail(c, RRT_E_ARG, "particle count %lld outside 1..2^28", (long long)n);
+    if (n < 1 || n > (int64_t(1) << 27))
+        return fail(c, RRT_E_ARG, "particle count %lld outside 1..2^27", (long long)n);
     if (!pos || !h || !mu || !n_H || !T) return fail(c, RRT_E_ARG, "null particle array");
     free_paths(c);
     int r = alloc_particles(c, n);
@@ -1828,7 +1828,7 @@ int rrt_set_tuning(rrt_ctx* x, int32_t key, int32_t value)
         c.adj_scatter = value;
         break;
     case RRT_TUNE_LEAF:
-        if (value < 1 || value > 8) return fail(c, RRT_E_ARG, "leaf size must be 1..8");
+        if (value < 1 || value > kLeafMax) return fail(c, RRT_E_ARG, "leaf size must be 1..16");
         c.leaf = value;
         c.have_tree = false;          // takes effect with the next rrt_build_tree
         break;
@@ -1900,8 +1900,8 @@ int rrt_get_tree(rrt_ctx* x, int64_t cap, int64_t* n_nodes, float* lo, float* hi
                 if (first) first[i] = -1;
                 if (count) count[i] = 0;
             } else {
-                if (first) first[i] = lw >> 3;
-                if (count) count[i] = (lw & 7) + 1;
+                if (first) first[i] = lw >> kLeafShift;
+                if (count) count[i] = (lw & (kLeafMax - 1)) + 1;
             }
         }
     }

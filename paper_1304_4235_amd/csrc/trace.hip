@@ -316,19 +316,18 @@ k_trace(const Node* __restrict__ nodes, const float4* __restrict__ p4,
                 // skip links always point past the node; max() keeps every walk finite
                 if (!(tmin <= tmax)) { node = max(skip, node + 1); continue; }
                 if (leafw < 0) { node = node + 1; continue; }
-                const int f = leafw >> 3;
-                const int c = (f + (leafw & 7) + 1 <= g.n) ? (leafw & 7) + 1 : 0;
+                const int f = leafw >> kLeafShift;
+                const int c = (f + (leafw & (kLeafMax - 1)) + 1 <= g.n) ? (leafw & (kLeafMax - 1)) + 1 : 0;
                 // the leaf's particles (contiguous in tree order) are loaded
-                // together; p4 holds kLeafMax spare entries past n
-                float4 Qs[kLeafMax];
-                if (c > 0) {
+                // eight at a time; p4 holds kLeafMax spare entries past n
+                for (int q0 = 0; q0 < c; q0 += 8) {
+                float4 Qs[8];
 #pragma unroll
-                    for (int q = 0; q < kLeafMax; ++q) Qs[q] = p4[f + q];
-                }
+                for (int q = 0; q < 8; ++q) Qs[q] = p4[f + q0 + q];
 #pragma unroll
-                for (int q = 0; q < kLeafMax; ++q) {
-                    if (q >= c) break;
-                    const int j = f + q;
+                for (int q = 0; q < 8; ++q) {
+                    if (q0 + q >= c) break;
+                    const int j = f + q0 + q;
                     const float4 Q = Qs[q];
                     double d0 = ((double)Q.x - rp[0]) + sh[0];
                     double d1 = ((double)Q.y - rp[1]) + sh[1];
@@ -369,6 +368,7 @@ k_trace(const Node* __restrict__ nodes, const float4* __restrict__ p4,
                         acc += (double)(mux[j] * gk);
                     }
                 }
+                }   // groups of eight particles
                 node = max(skip, node + 1);
             }
         }
@@ -499,7 +499,7 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
     unsigned char* s_wave = s_dyn + (kTerms ? kTabIntervals * sizeof(float4) : 0);
     // per wave: the hit rays' origins (FP64, by rank among the leaf's hit rays),
     // per hit ray of the current leaf bit q set when the ray hits the leaf's
-    // particle q (bit 8 + q when that hit is near), and the pairs' factors
+    // particle q (bit 16 + q when that hit is near), and the pairs' factors
     double* s_o = reinterpret_cast<double*>(s_wave) + wv * 3 * 64;
     unsigned int* s_mask =
         reinterpret_cast<unsigned int*>(s_wave + n_wv * kWaveOrgBytes) + wv * 64;
@@ -671,8 +671,8 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
                 continue;
             }
             node = max(skip, node + 1);
-            const int f = leafw >> 3;
-            const int c = (f + (leafw & 7) + 1 <= g.n) ? (leafw & 7) + 1 : 0;
+            const int f = leafw >> kLeafShift;
+            const int c = (f + (leafw & (kLeafMax - 1)) + 1 <= g.n) ? (leafw & (kLeafMax - 1)) + 1 : 0;
             // Leaf work compacted over the wave: the (hit ray, leaf particle)
             // pairs are spread over all 64 lanes, so a leaf that few of the
             // wave's rays reach costs few wave instructions.  Pair t is hit
@@ -749,7 +749,7 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
                 if (NF) near = (pg.d0 * pg.d0 + pg.d1 * pg.d1 + pg.d2 * pg.d2) < h2;
                 float gk = 0.0f;
                 if (kTerms && in) gk = hit_factor(pg, u, Q.w, L, t_erf, gc, ga);
-                if (in) atomicOr(&s_mask[r], (near ? 0x101u : 1u) << q);
+                if (in) atomicOr(&s_mask[r], (near ? 0x10001u : 1u) << q);
                 if (kTerms && !kDirect) s_gk[t] = gk;
                 if (kDirect) {
                     // The entry's place: its ray's hits in this leaf are in
@@ -776,7 +776,7 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
             }
             wave_sync();
             if (kDirect && hit) {
-                const uint32_t n_new = __popc(s_mask[rank] & 0xffu);
+                const uint32_t n_new = __popc(s_mask[rank] & 0xffffu);
                 cnt += n_new;
                 if (MODE == kModePath) w += n_new;
                 if (MODE == kModeChunk && cur < kDropped) {
@@ -792,8 +792,8 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
             }
             if (!kDirect && hit) {
                 const unsigned int m = s_mask[rank];
-                if (kCountOnly) cnt += __popc(m & 0xffu);
-                for (unsigned int hb = kCountOnly ? 0u : m & 0xffu; hb; hb &= hb - 1) {
+                if (kCountOnly) cnt += __popc(m & 0xffffu);
+                for (unsigned int hb = kCountOnly ? 0u : m & 0xffffu; hb; hb &= hb - 1) {
                     const int q = __ffs(hb) - 1;
                     const int j = f + q;
                     const float gk = kTerms ? s_gk[q * k_hit + rank] : 0.0f;
@@ -806,7 +806,7 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
                         }
                         ++w;
                     }
-                    const bool near = NF && ((m >> (8 + q)) & 1u);
+                    const bool near = NF && ((m >> (16 + q)) & 1u);
                     if (MODE == kModeScatter) {
                         if (nur != 0.0) unsafeAtomicAdd(out.y + j, (double)gk * nur);
                     } else if (near) {

@@ -489,7 +489,7 @@ __global__ void k_layout(const float4* __restrict__ p4, int n, int leaf_max,
         seg_root[seg] = idx;
         seg_end[seg] = idx + dfs;
     }
-    int leafw = leafy ? ((f << 3) | (cnt - 1)) : -1;
+    int leafw = leafy ? ((f << kLeafShift) | (cnt - 1)) : -1;
     nd.a = make_float4(lo[0], lo[1], lo[2], __int_as_float(idx + dfs));
     nd.b = make_float4(hi[0], hi[1], hi[2], __int_as_float(leafw));
     nodes[idx] = nd;

@@ -18,6 +18,8 @@ import workloads as W
 
 pytestmark = pytest.mark.gpu
 
+LEAF = 16              # the library's default leaf size
+
 
 def _say(*a):
     print(*a, flush=True)
@@ -45,7 +47,7 @@ def test_full_halo_tree_bit_exact():
     wl = W.make_config(1)
     s = _solver(wl)
     _say("halo tree: oracle")
-    _tree_equal(s.tree(), oracle.lbvh(wl.pos, wl.h, 8))
+    _tree_equal(s.tree(), oracle.lbvh(wl.pos, wl.h, LEAF))
 
 
 def _batch6():
@@ -69,7 +71,7 @@ def test_batch_tree_bit_exact(which):
     s = _solver(wl)
     g = s.tree()
     _say("batch tree", which, wl.n, "particles,", g["n_nodes"], "nodes: oracle")
-    _tree_equal(g, oracle.lbvh(wl.pos, wl.h, 8, halo_offsets=wl.halo_offsets))
+    _tree_equal(g, oracle.lbvh(wl.pos, wl.h, LEAF, halo_offsets=wl.halo_offsets))
 
 
 @pytest.mark.parametrize("which", ["halo", "field", "batch"])
@@ -85,7 +87,7 @@ def test_repeated_builds_give_the_same_tree(which):
         _tree_equal(s.tree(), first)
     _say(which, "tree: 5 builds agree,", first["n_nodes"], "nodes: oracle")
     if which == "field":
-        _tree_equal(first, oracle.lbvh(wl.pos, wl.h, 8))
+        _tree_equal(first, oracle.lbvh(wl.pos, wl.h, LEAF))
 
 
 def _rows(off, a, b, r):

@@ -67,7 +67,8 @@ def _hitsets(off, hj, hi, rows):
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("n,leaf,dup", [(1, 4, False), (2, 1, False), (3, 4, False),
                                         (5, 4, False), (1000, 1, False), (4099, 4, False),
-                                        (10007, 8, False), (3000, 4, True)])
+                                        (10007, 8, False), (3000, 4, True), (17, 16, False),
+                                        (10007, 16, False), (4099, 12, False), (3000, 16, True)])
 def test_tree_bit_exact(n, leaf, dup):
     rng = np.random.default_rng(n + leaf)
     pos = rng.uniform(-30, 30, (n, 3)).astype(np.float32)
