@@ -12,6 +12,7 @@ SOURCES = ["rrt.hip", "workspace.hip", "tree.hip", "trace.hip", "rate.hip", "adj
            "tiles.hip", "noalloc.hip"]
 LIB = os.path.join(HERE, "librrt.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ROCM_LIB = "/opt/rocm/lib"
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # the leaf predicate must round operation by operation: honour the
@@ -26,7 +27,9 @@ FLAGS = [
 def build(verbose: bool = False) -> str:
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-o", tmp, *srcs]
+    # roctx ranges around the library's calls (the rocprofiler-sdk marker library)
+    libs = ["-L", ROCM_LIB, "-lrocprofiler-sdk-roctx", f"-Wl,-rpath,{ROCM_LIB}"]
+    cmd = [HIPCC, *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-o", tmp, *srcs, *libs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

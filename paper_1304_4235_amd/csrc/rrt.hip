@@ -1,6 +1,8 @@
 // Host side of librrt: the C ABI declared in include/rrt.h.
 #include "internal.h"
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
@@ -10,6 +12,15 @@
 #include <vector>
 
 using namespace rrt;
+
+// A named range on the profiler's marker track (rocprofv3 --marker-trace)
+// for the duration of one library call or phase; no cost without a profiler.
+struct Range {
+    explicit Range(const char* name) { roctxRangePushA(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range&) = delete;
+    Range& operator=(const Range&) = delete;
+};
 
 
 // a captured graph refers to the buffers it was captured with
@@ -374,6 +385,7 @@ int paths_unfit(Ctx& c, uint64_t total)
 // (and traversal in charge) when they do not fit the path buffer.
 int record_paths(Ctx& c)
 {
+    Range range("rrt: record paths");
     const int64_t n_rows = c.n * (int64_t)c.n_ray;
     free_paths(c);
     if (!c.arena.base[kRegionPath]) {
@@ -967,6 +979,7 @@ int rrt_set_spectrum(rrt_ctx* x, int32_t n_bins, const double* sigma, const doub
 
 int rrt_build_tree(rrt_ctx* x)
 {
+    Range range("rrt_build_tree");
     if (!x) return RRT_E_ARG;
     Ctx& c = x->c;
     if (!c.have_particles) return fail(c, RRT_E_STATE, "rrt_set_particles has not been called");
@@ -1066,6 +1079,7 @@ int rrt_build_tree(rrt_ctx* x)
 
 int rrt_compute_columns(rrt_ctx* x, double* N_out, int64_t* n_hits_out)
 {
+    Range range("rrt_compute_columns");
     if (!x) return RRT_E_ARG;
     Ctx& c = x->c;
     if (int r = need_tree(c)) return r;
@@ -1232,6 +1246,7 @@ int rrt_set_update_rule(rrt_ctx* x, double tau_skip, double tau_case_b, int32_t 
 int rrt_iterate_equilibrium(rrt_ctx* x, int32_t max_iter, double tol, double* x_out,
                             int32_t* iters_done, double* max_dx_out)
 {
+    Range range("rrt_iterate_equilibrium");
     if (!x) return RRT_E_ARG;
     Ctx& c = x->c;
     if (int r = need_tree(c)) return r;
@@ -1304,6 +1319,7 @@ int rrt_iterate_equilibrium(rrt_ctx* x, int32_t max_iter, double tol, double* x_
 
 int rrt_evolve(rrt_ctx* x, double dt, int32_t n_steps, double* x_out)
 {
+    Range range("rrt_evolve");
     if (!x) return RRT_E_ARG;
     Ctx& c = x->c;
     if (int r = need_tree(c)) return r;
@@ -1343,6 +1359,7 @@ int rrt_set_density(rrt_ctx* x, const float* n_H)
 
 int rrt_forward(rrt_ctx* x, int32_t K, double* lnG_out, double* x_out)
 {
+    Range range("rrt_forward");
     if (!x) return RRT_E_ARG;
     Ctx& c = x->c;
     if (int r = need_tree(c)) return r;
@@ -1396,6 +1413,7 @@ int rrt_forward(rrt_ctx* x, int32_t K, double* lnG_out, double* x_out)
 int rrt_backward(rrt_ctx* x, const double* dL_dlnG, const double* dL_dx, double* dL_dw,
                  double* dL_dnH)
 {
+    Range range("rrt_backward");
     if (!x) return RRT_E_ARG;
     Ctx& c = x->c;
     if (int r = need_tree(c)) return r;
@@ -1745,6 +1763,7 @@ int run_groups(Ctx& c, double tol, int32_t max_iter, int32_t per_launch)
 int rrt_iterate_halos(rrt_ctx* x, int32_t max_iter, double tol, int32_t per_launch, double* x_out,
                       int32_t* halo_iters_out)
 {
+    Range range("rrt_iterate_halos");
     if (!x) return RRT_E_ARG;
     Ctx& c = x->c;
     if (int r = need_tree(c)) return r;
