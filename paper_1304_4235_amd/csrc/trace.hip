@@ -879,27 +879,41 @@ k_compact_chunks(const uint64_t* __restrict__ row_off, const uint32_t* __restric
         const float4 P = p4[ps];
         const double o0 = (double)P.x, o1 = (double)P.y, o2 = (double)P.z;
         const double u[3] = {dirs[3 * k], dirs[3 * k + 1], dirs[3 * k + 2]};
+        constexpr int kPer = kChunkLen / kCompactLanes;     // entries per lane per chunk
+        constexpr uint32_t kNoShift = kImgBias | (kImgBias << 10) | (kImgBias << 20);
         uint32_t ch = row_first[row];
         for (uint64_t e = a; e < b; e += kChunkLen) {
             const uint32_t nxt = e + kChunkLen < b ? chunk_next[ch] : 0u;
             const int2* src = pool + (uint64_t)ch * kChunkLen;
+            // the lane's entries of the chunk, then their particles, all in
+            // flight together.  A chunk is whole in the pool, so its slots
+            // past the row end are read too; their (stale) indices are
+            // replaced by particle 0 before the particle loads.
+            int2 en[kPer];
+            float4 Q[kPer];
 #pragma unroll
-            for (int q = 0; q < kChunkLen / kCompactLanes; ++q) {
+            for (int q = 0; q < kPer; ++q) en[q] = src[q * kCompactLanes + lane];
+#pragma unroll
+            for (int q = 0; q < kPer; ++q) {
+                if (e + (uint64_t)(q * kCompactLanes + lane) >= b) en[q].x = 0;
+                Q[q] = p4[en[q].x];
+            }
+#pragma unroll
+            for (int q = 0; q < kPer; ++q) {
                 const int i = q * kCompactLanes + lane;
                 if (e + i < b) {
-                    const int2 en = src[i];
-                    const uint32_t code = (uint32_t)en.y;
+                    const uint32_t code = (uint32_t)en[q].y;
+                    // the image shift, 0 for the source's own image as in the walk
                     double sh[3] = {0.0, 0.0, 0.0};
-                    if (B > 0.0) {
+                    if (B > 0.0 && (code & ~kNearBit) != kNoShift) {
                         sh[0] = (double)((int)(code & 1023u) - kImgBias) * B;
                         sh[1] = (double)((int)((code >> 10) & 1023u) - kImgBias) * B;
                         sh[2] = (double)((int)((code >> 20) & 1023u) - kImgBias) * B;
                     }
-                    const float4 Q = p4[en.x];
-                    const PairGeom pg = pair_geom(Q, o0, o1, o2, sh, u);
-                    const float gk = hit_factor(pg, u, Q.w, L, t_erf, gc, ga);
-                    path[e + i] =
-                        make_int2(en.x, (int)((uint32_t)__float_as_int(gk) | (code & kNearBit)));
+                    const PairGeom pg = pair_geom(Q[q], o0, o1, o2, sh, u);
+                    const float gk = hit_factor(pg, u, Q[q].w, L, t_erf, gc, ga);
+                    path[e + i] = make_int2(
+                        en[q].x, (int)((uint32_t)__float_as_int(gk) | (code & kNearBit)));
                 }
             }
             ch = nxt;
