@@ -14,6 +14,7 @@
 namespace rrt {
 
 constexpr int kTabIntervals = 256;        // cubic pieces per kernel table
+constexpr int kTaylorTerms = 6;           // terms of the thin rays' frequency sum
 constexpr int kMaxRays = 3072;
 constexpr int kMaxBins = 4096;
 constexpr int kDefaultLeaf = 16;
@@ -264,6 +265,10 @@ struct Ctx {
     float* dsig_l2 = nullptr;    // (sigma_b - sigma_min) * log2(e)
     float* ws_rel = nullptr;     // w_b sigma_b / max_b(w_b sigma_b)
     float* srat = nullptr;       // sigma_b / sigma_min
+    // the plain rate's Taylor form for rays thin in every bin: S(N) =
+    // sum_j tay[j] N^j for N <= tay_nmax (-1: never)
+    double tay[kTaylorTerms] = {};
+    double tay_nmax = -1.0;
     double sigma_min = 0.0, ln_ws_max = 0.0, gamma_thin = 0.0, ws_max = 0.0;
     std::vector<double> sigma_host;   // the spectrum as given
     std::vector<double> w_host;

@@ -963,6 +963,26 @@ int rrt_set_spectrum(rrt_ctx* x, int32_t n_bins, const double* sigma, const doub
     HIP_OK(hipStreamSynchronize(c.stream));     // host vectors go out of scope
     if (m != c.n_bins) drop_graph(c);
     c.n_bins = m;
+    // Taylor moments of the bins as the rate kernel sums them (the FP32
+    // tables r_b, d_b with exponent d_b N in base 2): S(N) = sum_b r_b
+    // 2^{-d_b N} = sum_j tay[j] N^j + tail, tay[j] = (-ln 2)^j / j! sum_b r_b
+    // d_b^j, used while every y_b = d_b N ln 2 <= 0.15
+    {
+        const double ln2 = 0.6931471805599453;
+        double dmax = 0.0, fact = 1.0, sgn = 1.0, p = 1.0;
+        for (int b = 0; b < m; ++b) dmax = std::max(dmax, (double)dsl[b]);
+        for (int j = 0; j < kTaylorTerms; ++j) {
+            if (j > 0) {
+                fact *= j;
+                sgn = -sgn;
+                p *= ln2;
+            }
+            double acc = 0.0;
+            for (int b = 0; b < m; ++b) acc += (double)rel[b] * std::pow((double)dsl[b], j);
+            c.tay[j] = sgn * p / fact * acc;
+        }
+        c.tay_nmax = dmax > 0.0 ? 0.15 / (dmax * ln2) : INFINITY;
+    }
     c.sigma_min = smin;
     c.ln_ws_max = std::log(wsmax);
     c.ws_max = wsmax;

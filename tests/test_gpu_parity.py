@@ -713,3 +713,27 @@ def test_streamed_product_equals_its_definition(which):
             exact = math.fsum(terms)
             bound = 1e-15 * max(b - a, 1) * np.abs(terms).sum()
             assert abs(Ns[p, k] - exact) <= bound, (p, k, Ns[p, k], exact)
+
+
+def test_rates_of_thin_and_thick_rays_on_the_same_columns():
+    """The rate of a particle from its rays' columns (Sec. 3.3, eq. gamma_shld):
+    the kernel sums a ray's bins with hardware exponentials, or, for a ray
+    thin in every bin ((sigma_b - sigma_min) N <= 0.15), as the degree-5
+    Taylor form of the same sum.  Both against the FP64 rate of the oracle on
+    the GPU's own columns, on a state with rays on both sides of the switch."""
+    wl = W.isothermal_halo(n=20000, seed=29)
+    s = _solver(wl)
+    x = np.minimum(oracle.x_thin(wl) * np.geomspace(1.0, 100.0, wl.n), 0.99)
+    s.set_state(torch.tensor(x))
+    N, _ = s.compute_columns()
+    lnG, _, _ = s.compute_gamma()
+    N = N.cpu().numpy()
+    sig = np.asarray(wl.sigma, np.float64)
+    y = (sig.max() - sig.min()) * N
+    thin = float(np.mean(y <= 0.15))
+    _say("rays thin in every bin:", thin)
+    assert 0.1 < thin < 0.9, "the state should put rays on both sides of the switch"
+    ref, _, _ = oracle.gamma(N, sig, np.asarray(wl.w, np.float64))
+    err = np.abs(lnG.cpu().numpy() - ref)
+    _say("max |ln Gamma - oracle| on the same columns:", float(err.max()))
+    assert err.max() < 5e-6
