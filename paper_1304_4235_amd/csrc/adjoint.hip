@@ -27,11 +27,28 @@ constexpr int kBlock = 256;
 
 inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
+// Rays thin in every bin ((sigma_b - sigma_min) N <= 0.15): S and T as their
+// degree-5 Taylor forms in N (the forward rate kernel's switch), and, for the
+// weights' gradient, sum over such (particle, ray) pairs of W 2^{-d_b N} as
+// sum_j (-ln 2 d_b)^j / j! sum W N^j.  The tail is below 1.9e-8 of each sum.
+struct ThinSums {
+    double s[kTaylorTerms];
+    double t[kTaylorTerms];
+    double nmax;
+};
+
+__device__ __forceinline__ double horner(const double* c, double x)
+{
+    double r = c[kTaylorTerms - 1];
+    for (int j = kTaylorTerms - 2; j >= 0; --j) r = fma(r, x, c[j]);
+    return r;
+}
+
 // One thread per particle (tree order) at step k: the adjoint of ln Gamma, of
 // x and of every ray's column.  Pass 1 forms ln Gamma from the same terms as
-// the forward rate kernel (hardware 2^x), summed in one FP32 accumulator
-// instead of four, so the two agree to FP32 rounding; it keeps each ray's S
-// and T for pass 2.  The weights' gradient is accumulated by k_adj_wbins from
+// the forward rate kernel (hardware 2^x, or the thin rays' Taylor form),
+// summed in one FP32 accumulator instead of four, so the two agree to FP32
+// rounding; it keeps each ray's S and T for pass 2.  The weights' gradient is accumulated by k_adj_wbins from
 // pis and ell.
 __global__ void __launch_bounds__(256)
 k_adj_rate(const double* __restrict__ N, int64_t n, int n_ray, int n_bins,
@@ -40,7 +57,8 @@ k_adj_rate(const double* __restrict__ N, int64_t n, int n_ray, int n_bins,
            const float* __restrict__ nH_s, const double* __restrict__ alpha,
            const double* __restrict__ gcoll, const double* __restrict__ lam,
            const double* __restrict__ lup, float* __restrict__ nu, double* __restrict__ pis,
-           double* __restrict__ gnH, float2* __restrict__ st, double* __restrict__ ell_out)
+           double* __restrict__ gnH, float2* __restrict__ st, double* __restrict__ ell_out,
+           ThinSums ts)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -50,10 +68,15 @@ k_adj_rate(const double* __restrict__ N, int64_t n, int n_ray, int n_bins,
         const double Nk = N[(int64_t)k * n + i];
         const float Nf = (float)Nk;
         float S = 0.f, T = 0.f;
-        for (int b = 0; b < n_bins; ++b) {
-            const float e = ws_rel[b] * __builtin_amdgcn_exp2f(-dsig_l2[b] * Nf);
-            S += e;
-            T = fmaf(e, srat[b], T);
+        if ((double)Nf <= ts.nmax) {
+            S = (float)horner(ts.s, (double)Nf);
+            T = (float)horner(ts.t, (double)Nf);
+        } else {
+            for (int b = 0; b < n_bins; ++b) {
+                const float e = ws_rel[b] * __builtin_amdgcn_exp2f(-dsig_l2[b] * Nf);
+                S += e;
+                T = fmaf(e, srat[b], T);
+            }
         }
         st[(int64_t)k * n + i] = make_float2(S, T);
         if (!(S > 0.f)) continue;
@@ -106,7 +129,7 @@ __device__ __forceinline__ void adj_wave_sync()
 __global__ void __launch_bounds__(256)
 k_adj_wbins(const double* __restrict__ N, const double* __restrict__ pis,
             const double* __restrict__ ell, const float* __restrict__ dsig_l2, int64_t n,
-            int n_ray, int n_bins, int64_t n_chunks, double* __restrict__ part)
+            int n_ray, int n_bins, int64_t n_chunks, double* __restrict__ part, double nmax)
 {
     __shared__ float sN[4][64];
     __shared__ double sW[4][64];
@@ -121,22 +144,47 @@ k_adj_wbins(const double* __restrict__ N, const double* __restrict__ pis,
     const float ds = b < n_bins ? dsig_l2[b] : 0.0f;
     const int64_t i0 = chunk * kAdjChunk;
     const int64_t i1 = i0 + kAdjChunk < n ? i0 + kAdjChunk : n;
+    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
     double acc = 0.0;
+    // moments sum W N^j of the thin pairs this lane stages
+    double mom[kTaylorTerms] = {};
     for (int k = 0; k < n_ray; ++k) {
         for (int64_t ib = i0; ib < i1; ib += 64) {
             const int64_t i = ib + lane;
             const bool in = i < i1;
-            sN[wv][lane] = in ? (float)N[(int64_t)k * n + i] : 0.0f;
-            sW[wv][lane] = in ? ell[i] * pis[(int64_t)k * n + i] : 0.0;
-            adj_wave_sync();
-            const int m = (int)(i1 - ib < 64 ? i1 - ib : 64);
-            for (int q = 0; q < m; ++q) {
-                const double w = sW[wv][q];
-                if (w != 0.0) acc += w * (double)__builtin_amdgcn_exp2f(-ds * sN[wv][q]);
+            const float Nf = in ? (float)N[(int64_t)k * n + i] : 0.0f;
+            const double w = in ? ell[i] * pis[(int64_t)k * n + i] : 0.0;
+            const bool thin = (double)Nf <= nmax;
+            if (thin && w != 0.0) {
+                double p = w;
+                for (int j = 0; j < kTaylorTerms; ++j) {
+                    mom[j] += p;
+                    p *= (double)Nf;
+                }
             }
+            // the thick pairs, packed to the front, go through every bin
+            const uint64_t thick = __builtin_amdgcn_ballot_w64(!thin && w != 0.0);
+            if (!thin && w != 0.0) {
+                const int q = __popcll(thick & lt);
+                sN[wv][q] = Nf;
+                sW[wv][q] = w;
+            }
+            adj_wave_sync();
+            const int m = __popcll(thick);
+            for (int q = 0; q < m; ++q)
+                acc += sW[wv][q] * (double)__builtin_amdgcn_exp2f(-ds * sN[wv][q]);
             adj_wave_sync();
         }
     }
+    // every bin takes the thin pairs' sum from the wave's moments
+    double c = 1.0, tot = 0.0;
+    for (int j = 0; j < kTaylorTerms; ++j) {
+        double mj = mom[j];
+        for (int off = 32; off > 0; off >>= 1) mj += __shfl_xor(mj, off, 64);
+        tot += c * mj;
+        c *= -0.6931471805599453 * (double)ds / (double)(j + 1);
+    }
+    acc += tot;
     if (b < n_bins) part[chunk * n_bins + b] = acc;
 }
 
@@ -217,6 +265,17 @@ __global__ void k_set_density(const int32_t* __restrict__ perm, const float* __r
     mu_s[i] = (double)mu0_s[i] * ((double)v / (double)nH0_s[i]);
 }
 
+ThinSums thin_sums(const Ctx& c)
+{
+    ThinSums t;
+    for (int j = 0; j < kTaylorTerms; ++j) {
+        t.s[j] = c.tay[j];
+        t.t[j] = c.tay_t[j];
+    }
+    t.nmax = c.tay_nmax;
+    return t;
+}
+
 }  // namespace
 
 hipError_t launch_set_density(Ctx& c, const float* nH)
@@ -231,14 +290,14 @@ hipError_t launch_adj_rate(Ctx& c, const double* N, const double* lup)
     hipLaunchKernelGGL(k_adj_rate, dim3(nblk(c.n)), dim3(kBlock), 0, c.stream, N, c.n, c.n_ray,
                        c.n_bins, c.ws_rel, c.dsig_l2, c.srat, c.sigma_min, c.ln_ws_max, c.nH_s,
                        c.alpha_s, c.gcoll_s, c.adj_lam, lup, c.adj_nu, c.adj_pis, c.adj_gnH,
-                       c.adj_st, c.adj_ell);
+                       c.adj_st, c.adj_ell, thin_sums(c));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t chunks = adj_chunks(c);
     const int64_t waves = chunks * ((c.n_bins + 63) / 64);
     hipLaunchKernelGGL(k_adj_wbins, dim3((unsigned)((waves * 64 + kBlock - 1) / kBlock)),
                        dim3(kBlock), 0, c.stream, N, c.adj_pis, c.adj_ell, c.dsig_l2, c.n,
-                       c.n_ray, c.n_bins, chunks, c.adj_wpart);
+                       c.n_ray, c.n_bins, chunks, c.adj_wpart, c.tay_nmax);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_adj_bins, dim3((c.n_bins + 255) / 256), dim3(256), 0, c.stream,

@@ -268,6 +268,7 @@ struct Ctx {
     // the plain rate's Taylor form for rays thin in every bin: S(N) =
     // sum_j tay[j] N^j for N <= tay_nmax (-1: never)
     double tay[kTaylorTerms] = {};
+    double tay_t[kTaylorTerms] = {};   // the same for T(N) = sum_b r_b s_b 2^{-d_b N}
     double tay_nmax = -1.0;
     double sigma_min = 0.0, ln_ws_max = 0.0, gamma_thin = 0.0, ws_max = 0.0;
     std::vector<double> sigma_host;   // the spectrum as given

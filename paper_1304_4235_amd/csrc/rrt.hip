@@ -977,9 +977,14 @@ int rrt_set_spectrum(rrt_ctx* x, int32_t n_bins, const double* sigma, const doub
                 sgn = -sgn;
                 p *= ln2;
             }
-            double acc = 0.0;
-            for (int b = 0; b < m; ++b) acc += (double)rel[b] * std::pow((double)dsl[b], j);
+            double acc = 0.0, acc_t = 0.0;
+            for (int b = 0; b < m; ++b) {
+                const double t = (double)rel[b] * std::pow((double)dsl[b], j);
+                acc += t;
+                acc_t += t * (double)srt[b];
+            }
             c.tay[j] = sgn * p / fact * acc;
+            c.tay_t[j] = sgn * p / fact * acc_t;
         }
         c.tay_nmax = dmax > 0.0 ? 0.15 / (dmax * ln2) : INFINITY;
     }
