@@ -195,8 +195,17 @@ def test_autograd_function_against_the_oracle_adjoint():
 def test_full_halo_gradient_central_differences():
     """The 262144-particle halo, 128 bins: K frozen from a converged base run,
     loss sum (log10 Gamma - log10 Gamma_target)^2 with the target from 1.2x the
-    weights; 32 random coordinates (weights and densities) by central
-    differences with relative step 1e-3."""
+    weights; 32 coordinates by central differences of the GPU forward.
+
+    Weights and the 12 largest density gradients at relative step 1e-3
+    (measured: 4.2e-5 and 1.3e-4 relative; bars 5e-4 and 1e-3).  12 random
+    densities at relative step 1e-2: most sit in the outskirts with gradients
+    near 5e-5 of the largest, where the difference quotient of the FP32
+    forward through 120 iterations carries an absolute floor (measured 4e-5 of
+    the largest gradient at step 1e-2, 1.9e-4 at 1e-3; up to 10% of such a
+    coordinate), so they take an absolute bar of 2e-4 of the largest.  The
+    small coordinates' relative accuracy is checked against the oracle's
+    reverse mode instead, where no difference quotient is involved."""
     wl = W.make_config(4)
     from paper_1304_4235_amd import Solver
     s = Solver.from_workload(wl)
@@ -219,18 +228,22 @@ def test_full_halo_gradient_central_differences():
         wm[b] -= h
         fd = (_gpu_loss(s, wp, nH0, K, lnG_t, c_x) - _gpu_loss(s, wm, nH0, K, lnG_t, c_x)) / (2 * h)
         _say("w", b, dw[b], fd)
-        assert abs(dw[b] - fd) <= 1e-2 * abs(fd) + 1e-3 * np.max(np.abs(dw))
+        assert abs(dw[b] - fd) <= 5e-4 * abs(fd)
         checked += 1
     # densities: the largest-gradient particles and random ones
-    cand = list(np.argsort(-np.abs(dn))[:12]) + list(rng.choice(wl.n, 12, replace=False))
-    for j in cand:
-        up, lo = np.float32(nH0[j] * (1 + 1e-3)), np.float32(nH0[j] * (1 - 1e-3))
+    top = list(np.argsort(-np.abs(dn))[:12])
+    for j in top + list(rng.choice(wl.n, 12, replace=False)):
+        rel = 1e-3 if j in top else 1e-2
+        up, lo = np.float32(nH0[j] * (1 + rel)), np.float32(nH0[j] * (1 - rel))
         npl, nmi = nH0.copy(), nH0.copy()
         npl[j], nmi[j] = up, lo
         fd = (_gpu_loss(s, w0, npl, K, lnG_t, c_x) - _gpu_loss(s, w0, nmi, K, lnG_t, c_x)) / \
             (float(up) - float(lo))
         _say("n", j, dn[j], fd)
-        assert abs(dn[j] - fd) <= 1e-2 * abs(fd) + 1e-3 * scale_n
+        if j in top:
+            assert abs(dn[j] - fd) <= 1e-3 * abs(fd)
+        else:
+            assert abs(dn[j] - fd) <= 1e-3 * abs(fd) + 2e-4 * scale_n
         checked += 1
     assert checked == 32
 
@@ -238,13 +251,14 @@ def test_full_halo_gradient_central_differences():
 def test_full_field_gradient_central_differences():
     """The differentiation workload at the sizes it names: 256 per-bin weights
     and the 2.1M densities of the lognormal field (48 rays), K = 10 (the
-    field's fixed iteration count); the same loss, the same 32-coordinate
-    central-difference check and bars as the halo's, at relative step 1e-2:
-    a bin carries about 1/256 of each rate and the field's densities are
-    near 1e-5 cm^-3, so a 1e-3 step moves the loss by about as much as the
-    FP32 rounding of the forward does (measured at 1e-3: a hard bin -0.0189
+    field's fixed iteration count); the same loss and 32-coordinate
+    central-difference check as the halo's, at relative step 1e-2: a bin
+    carries about 1/256 of each rate and the field's densities are near
+    1e-5 cm^-3, so a 1e-3 step moves the loss by about as much as the FP32
+    rounding of the forward does (measured at 1e-3: a hard bin -0.0189
     against -0.0208, a low-density particle 0.446 against 0.512, while the
-    largest components agreed to 2e-4)."""
+    largest components agreed to 2e-4).  Measured at 1e-2: weights 3.7e-6
+    relative, densities 1.9e-4 relative at most (bars 1e-4 and 1e-3)."""
     wl = W.make_config(2)
     from paper_1304_4235_amd import Solver
     s = Solver.from_workload(wl)
@@ -267,7 +281,7 @@ def test_full_field_gradient_central_differences():
         wm[b] -= h
         fd = (_gpu_loss(s, wp, nH0, K, lnG_t, c_x) - _gpu_loss(s, wm, nH0, K, lnG_t, c_x)) / (2 * h)
         _say("w", b, dw[b], fd)
-        assert abs(dw[b] - fd) <= 1e-2 * abs(fd) + 1e-3 * np.max(np.abs(dw))
+        assert abs(dw[b] - fd) <= 1e-4 * abs(fd)
         checked += 1
     cand = list(np.argsort(-np.abs(dn))[:12]) + list(rng.choice(wl.n, 12, replace=False))
     for j in cand:
@@ -277,7 +291,7 @@ def test_full_field_gradient_central_differences():
         fd = (_gpu_loss(s, w0, npl, K, lnG_t, c_x) - _gpu_loss(s, w0, nmi, K, lnG_t, c_x)) / \
             (float(up) - float(lo))
         _say("n", j, dn[j], fd)
-        assert abs(dn[j] - fd) <= 1e-2 * abs(fd) + 1e-3 * scale_n
+        assert abs(dn[j] - fd) <= 1e-3 * abs(fd)
         checked += 1
     assert checked == 32
 
@@ -398,6 +412,13 @@ def _adjoint_cases():
 # the largest density gradient.
 GRAD_RTOL = 1e-5     # per coordinate, relative
 GRAD_ATOL = 1e-5     # times the largest gradient of the vector
+# Every density gradient at or above 1e-4 of the largest, on its own scale:
+# measured at most 1.3e-4 relative (median 1e-7, no signed bias) on this halo
+# and on a 20000-particle, 64-bin halo at K = 6.  Below 1e-4 of the largest a
+# coordinate is a cancellation of terms of the largest's size and FP32
+# products limit it to the absolute bar above.
+SMALL_FROM = 1e-4
+SMALL_RTOL = 1e-3
 
 
 @pytest.mark.parametrize("case", ["lattice", "halo"])
@@ -426,6 +447,10 @@ def test_adjoint_matches_oracle_adjoint_everywhere(case):
              f"{en.max() / np.abs(ref['dnH']).max():.2e}")
         assert np.all(ew <= GRAD_RTOL * np.abs(ref["dw"]) + GRAD_ATOL * np.abs(ref["dw"]).max())
         assert np.all(en <= GRAD_RTOL * np.abs(ref["dnH"]) + GRAD_ATOL * np.abs(ref["dnH"]).max())
+        big = np.abs(ref["dnH"]) >= SMALL_FROM * np.abs(ref["dnH"]).max()
+        _say(f"  dn max rel over |g| >= {SMALL_FROM:g} max: "
+             f"{np.max(en[big] / np.abs(ref['dnH'][big])):.2e} ({big.sum()} of {wl.n})")
+        assert np.all(en[big] <= SMALL_RTOL * np.abs(ref["dnH"][big]))
         s.close()
 
 
