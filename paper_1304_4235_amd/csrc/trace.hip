@@ -22,6 +22,7 @@
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <type_traits>
 
 namespace rrt {
 
@@ -208,6 +209,26 @@ __device__ __forceinline__ PairGeom pair_geom(const float4 Q, double o0, double 
     pg.d0 = ((double)Q.x - o0) + sh[0];
     pg.d1 = ((double)Q.y - o1) + sh[1];
     pg.d2 = ((double)Q.z - o2) + sh[2];
+    pg.sp = pg.d0 * u[0] + pg.d1 * u[1] + pg.d2 * u[2];
+    return pg;
+}
+
+// The same from coordinates already in FP64; for an unshifted image
+// (kShifted false, s = 0) the adds of zero are left out, which changes no bit.
+template <bool kShifted>
+__device__ __forceinline__ PairGeom pair_geom_d(double qx, double qy, double qz, double o0,
+                                                double o1, double o2, const double sh[3],
+                                                const double u[3])
+{
+    PairGeom pg;
+    pg.d0 = qx - o0;
+    pg.d1 = qy - o1;
+    pg.d2 = qz - o2;
+    if (kShifted) {
+        pg.d0 = pg.d0 + sh[0];
+        pg.d1 = pg.d1 + sh[1];
+        pg.d2 = pg.d2 + sh[2];
+    }
     pg.sp = pg.d0 * u[0] + pg.d1 * u[1] + pg.d2 * u[2];
     return pg;
 }
@@ -442,13 +463,17 @@ __device__ __forceinline__ void wave_sync()
 //    scalar selects, and the slab test needs no per-lane min/max of the pair;
 //  * the node index and the walk's bounds are scalar, so the loop is too;
 //  * a leaf's (ray, particle) pairs are indexed with an FP32 reciprocal (exact
-//    for the at most 64 x 8 pairs) and the rays' origins are read, already in
-//    FP64, from LDS;
+//    for the at most 64 x 16 pairs); the rays' origins and the leaf's
+//    particles are read, already in FP64, from LDS (each particle is loaded
+//    and widened once per leaf, not once per pair);
+//  * the image shift's three adds only run for a shifted image: for the
+//    unshifted one they add zero, which changes no bit of the predicate;
 //  * the near test only exists in the near/far variant (NF).
-// LDS per wave: origins 3 x 64 FP64, hit masks 64 x 4 B, factors 64 x 8 x 4 B
-// (only in modes that evaluate factors, which also stage the erf table once
-// per block).  Sized per
-// launch (dynamic LDS), so a 128-thread block holds two waves' buffers.
+// LDS per wave: origins 3 x 64 FP64, hit masks 64 x 4 B, factors 64 x 16 x
+// 4 B (modes that evaluate factors in the walk, which also stage the erf
+// table once per block) or the hit rays' write places (modes whose pair lanes
+// write entries), the leaf's particles 16 x 4 FP64.  Sized per launch
+// (dynamic LDS), so a 128-thread block holds two waves' buffers.
 // Six waves per SIMD (measured: the count and record passes run 4.5% faster on
 // the 2.1M-particle field than at the four that ~100 VGPRs would allow, with
 // a few registers spilled to scratch).
@@ -456,6 +481,7 @@ constexpr int kWaveOrgBytes = 3 * 64 * (int)sizeof(double);
 constexpr int kWaveMaskBytes = 64 * (int)sizeof(unsigned int);
 constexpr int kWaveGkBytes = 64 * kLeafMax * (int)sizeof(float);
 constexpr int kWaveDstBytes = 64 * 16;     // per hit ray: where its entries go
+constexpr int kWaveLeafBytes = kLeafMax * 4 * (int)sizeof(double);
 
 // modes whose walk evaluates the chord factor of its hits (the one-walk
 // recording leaves it to the compaction)
@@ -471,14 +497,18 @@ __host__ __device__ constexpr bool mode_direct(int mode)
     return mode == kModePath || mode == kModeChunk;
 }
 
+// per wave: the factor or write-place buffer of a mode
+__host__ __device__ constexpr int wave_pair_bytes(int mode)
+{
+    return mode_direct(mode) ? kWaveDstBytes : mode_factors(mode) ? kWaveGkBytes : 0;
+}
+
 // dynamic LDS bytes of one k_trace_wave block
 inline size_t wave_lds_bytes(int mode, int block)
 {
     const size_t waves = (size_t)(block / 64);
-    size_t b = waves * (kWaveOrgBytes + kWaveMaskBytes);
+    size_t b = waves * (kWaveOrgBytes + kWaveMaskBytes + wave_pair_bytes(mode) + kWaveLeafBytes);
     if (mode_factors(mode)) b += (size_t)kTabIntervals * sizeof(float4);
-    if (mode_direct(mode)) b += waves * kWaveDstBytes;
-    else if (mode_factors(mode)) b += waves * kWaveGkBytes;
     return b;
 }
 
@@ -510,6 +540,10 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
     uint64_t* s_w = reinterpret_cast<uint64_t*>(s_wave + n_wv * (kWaveOrgBytes + kWaveMaskBytes)) +
                     wv * 64 * 2;
     uint32_t* s_ch = reinterpret_cast<uint32_t*>(s_w);       // [cur, fill, next, -] per ray
+    // the current leaf's particles: x, y, z, h in FP64
+    double* s_pd = reinterpret_cast<double*>(
+                       s_wave + n_wv * (kWaveOrgBytes + kWaveMaskBytes + wave_pair_bytes(MODE))) +
+                   wv * kLeafMax * 4;
     if (kTerms) {
         for (int i = threadIdx.x; i < kTabIntervals; i += blockDim.x) t_erf[i] = tabs->erf_t[i];
         __syncthreads();
@@ -621,6 +655,7 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
         double sh[3] = {(double)sx * B, (double)sy * B, (double)sz * B};
         if (!(B > 0.0)) sh[0] = sh[1] = sh[2] = 0.0;
         const uint32_t img_code = chunk_image_code(sx, sy, sz);
+        const bool shifted = (sx | sy | sz) != 0;            // wave-uniform
         // slab offsets of the entry and exit faces: the low face is padded
         // by -pad, the high face by +pad
         float oin[3], oout[3];
@@ -708,6 +743,13 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
                     }
                 }
             }
+            if (lane < c) {
+                const float4 Q = p4[f + lane];
+                s_pd[4 * lane] = (double)Q.x;
+                s_pd[4 * lane + 1] = (double)Q.y;
+                s_pd[4 * lane + 2] = (double)Q.z;
+                s_pd[4 * lane + 3] = (double)Q.w;
+            }
             if (hit) {
                 s_o[rank] = (double)rpf[0];
                 s_o[64 + rank] = (double)rpf[1];
@@ -730,25 +772,30 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
             // quotient is at least 1/(2 k_hit) >= 1/128 away from an integer,
             // far beyond the error of the reciprocal and product (< 2^-12)
             const float rk = __builtin_amdgcn_rcpf((float)k_hit);
+            // two copies of the pair loop: with and without the image shift
+            // (a select per component would cost more than the adds it saves)
+            auto pair_loop = [&](auto shifted_tag) {
+            constexpr bool kShifted = decltype(shifted_tag)::value;
             for (int t = lane; t < pairs; t += 64) {
                 const int q = (int)(((float)t + 0.5f) * rk);
                 const int r = t - q * k_hit;
                 const int j = f + q;
-                const float4 Q = p4[j];
-                const PairGeom pg = pair_geom(Q, s_o[r], s_o[64 + r], s_o[128 + r], sh, u);
+                const double* pq = s_pd + 4 * q;
+                const PairGeom pg = pair_geom_d<kShifted>(pq[0], pq[1], pq[2], s_o[r],
+                                                          s_o[64 + r], s_o[128 + r], sh, u);
                 // clamp to [0, L]; a zero's sign cannot change |c|^2
                 double tt = fmin(fmax(pg.sp, 0.0), L);
                 double c0 = pg.d0 - tt * u[0];
                 double c1 = pg.d1 - tt * u[1];
                 double c2 = pg.d2 - tt * u[2];
                 double D2 = c0 * c0 + c1 * c1 + c2 * c2;
-                double hj = (double)Q.w;
+                double hj = pq[3];
                 double h2 = hj * hj;
                 const bool in = D2 < h2;
                 bool near = false;
                 if (NF) near = (pg.d0 * pg.d0 + pg.d1 * pg.d1 + pg.d2 * pg.d2) < h2;
                 float gk = 0.0f;
-                if (kTerms && in) gk = hit_factor(pg, u, Q.w, L, t_erf, gc, ga);
+                if (kTerms && in) gk = hit_factor(pg, u, (float)hj, L, t_erf, gc, ga);
                 if (in) atomicOr(&s_mask[r], (near ? 0x10001u : 1u) << q);
                 if (kTerms && !kDirect) s_gk[t] = gk;
                 if (kDirect) {
@@ -774,6 +821,9 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
                     }
                 }
             }
+            };
+            if (shifted) pair_loop(std::true_type{});
+            else pair_loop(std::false_type{});
             wave_sync();
             if (kDirect && hit) {
                 const uint32_t n_new = __popc(s_mask[rank] & 0xffffu);
