@@ -32,6 +32,7 @@ constexpr int kTileMaxSet = 16384;
 // arrays holding them are allocated with this many entries to spare.
 constexpr int kPathPad = 4;
 constexpr int kChunkLen = 32;              // entries per chunk of one-pass recording
+constexpr int kChunkShift = 5;             // log2 kChunkLen
 constexpr uint32_t kNoChunk = 0xffffffffu;
 constexpr int kPoolSlices = 1024;          // independent allocation counters
 constexpr int kCtrStride = 16;             // counters 128 bytes apart

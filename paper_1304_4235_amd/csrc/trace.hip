@@ -776,6 +776,8 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
             // (a select per component would cost more than the adds it saves)
             auto pair_loop = [&](auto shifted_tag) {
             constexpr bool kShifted = decltype(shifted_tag)::value;
+            // canonical here, so the clamp below needs no canonicalisation per pair
+            const double Lc = __builtin_canonicalize(L);
             for (int t = lane; t < pairs; t += 64) {
                 const int q = (int)(((float)t + 0.5f) * rk);
                 const int r = t - q * k_hit;
@@ -784,7 +786,7 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
                 const PairGeom pg = pair_geom_d<kShifted>(pq[0], pq[1], pq[2], s_o[r],
                                                           s_o[64 + r], s_o[128 + r], sh, u);
                 // clamp to [0, L]; a zero's sign cannot change |c|^2
-                double tt = fmin(fmax(pg.sp, 0.0), L);
+                double tt = fmin(fmax(pg.sp, 0.0), Lc);
                 double c0 = pg.d0 - tt * u[0];
                 double c1 = pg.d1 - tt * u[1];
                 double c2 = pg.d2 - tt * u[2];
@@ -812,11 +814,13 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
                             const uint64_t pos = s_w[2 * r] + e;
                             if (pos < out.hit_cap) out.path[pos] = make_int2(j, (int)bits);
                         } else {
+                            // a ray that holds a chunk also holds the next one
+                            // whenever this leaf can reach it (reserved above)
                             const uint32_t c0 = s_ch[4 * r], slot = s_ch[4 * r + 1] + e;
                             const uint32_t ch = slot < kChunkLen ? c0 : s_ch[4 * r + 2];
-                            if (c0 < kDropped && ch < kDropped)
-                                out.pool[(uint64_t)ch * kChunkLen + (slot & (kChunkLen - 1))] =
-                                    make_int2(j, (int)bits);
+                            if (c0 < kDropped)
+                                out.pool[((uint64_t)ch << kChunkShift) |
+                                         (slot & (kChunkLen - 1))] = make_int2(j, (int)bits);
                         }
                     }
                 }

@@ -176,7 +176,9 @@ class Solver:
     def _call(self, name: str, *args) -> int:
         """Call an entry point; when it finds too little room in the workspace
         (RRT_E_WORKSPACE, before it changed any state), grow the workspace by
-        what it asked for and call it once more."""
+        what it asked for and call it once more.  The growth is past the
+        current end, so the request fits in one piece however the used blocks
+        are spread."""
         fn = getattr(_lib, name)
         rc = fn(self._h, *args)
         for _ in range(2):
@@ -185,7 +187,7 @@ class Solver:
             info = self.workspace_info()
             if info["short_region"] != 0 or info["short_bytes"] == 0:
                 break
-            self._grow_ws(info["ws_used"] + info["short_bytes"])
+            self._grow_ws(max(info["ws_used"], info["ws_size"]) + info["short_bytes"])
             rc = fn(self._h, *args)
         return self._check(rc, name)
 
