@@ -188,14 +188,37 @@ k_adj_wbins(const double* __restrict__ N, const double* __restrict__ pis,
     if (b < n_bins) part[chunk * n_bins + b] = acc;
 }
 
-// sum the per-chunk partials of every bin, in chunk order, into the accumulator
-__global__ void k_adj_bins(const double* __restrict__ part, int64_t n_chunks, int n_bins,
-                           double* __restrict__ acc)
+// The per-chunk partials of every bin summed into the accumulator in two
+// passes of fixed order (so the gradient is the same on every run).  First,
+// block (g, s) takes the 64 bins of group g (one per lane, coalesced) over the
+// chunks of slice s: its 4 waves take every 4th chunk, added in wave order.
+__global__ void __launch_bounds__(256)
+k_adj_bin_slices(const double* __restrict__ part, int64_t n_chunks, int n_bins,
+                 double* __restrict__ part2)
+{
+    __shared__ double s_w[4][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int b = blockIdx.x * 64 + lane;
+    const int64_t per = (n_chunks + kAdjSlices - 1) / kAdjSlices;
+    const int64_t w0 = (int64_t)blockIdx.y * per;
+    const int64_t w1 = w0 + per < n_chunks ? w0 + per : n_chunks;
+    double acc = 0.0;
+    if (b < n_bins)
+        for (int64_t w = w0 + wv; w < w1; w += 4) acc += part[w * n_bins + b];
+    s_w[wv][lane] = acc;
+    __syncthreads();
+    if (wv == 0 && b < n_bins)
+        part2[(int64_t)blockIdx.y * n_bins + b] =
+            ((s_w[0][lane] + s_w[1][lane]) + s_w[2][lane]) + s_w[3][lane];
+}
+
+// then every bin's slices, in slice order
+__global__ void k_adj_bins(const double* __restrict__ part2, int n_bins, double* __restrict__ acc)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= n_bins) return;
     double s = 0.0;
-    for (int64_t w = 0; w < n_chunks; ++w) s += part[w * n_bins + b];
+    for (int q = 0; q < kAdjSlices; ++q) s += part2[(int64_t)q * n_bins + b];
     acc[b] += s;
 }
 
@@ -300,8 +323,14 @@ hipError_t launch_adj_rate(Ctx& c, const double* N, const double* lup)
                        c.n_ray, c.n_bins, chunks, c.adj_wpart, c.tay_nmax);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_adj_bins, dim3((c.n_bins + 255) / 256), dim3(256), 0, c.stream,
-                       c.adj_wpart, chunks, c.n_bins, c.adj_gw);
+    // the second level sits behind the per-chunk partials
+    double* part2 = c.adj_wpart + (size_t)chunks * c.n_bins;
+    hipLaunchKernelGGL(k_adj_bin_slices, dim3((c.n_bins + 63) / 64, kAdjSlices), dim3(256), 0,
+                       c.stream, c.adj_wpart, chunks, c.n_bins, part2);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_adj_bins, dim3((c.n_bins + 255) / 256), dim3(256), 0, c.stream, part2,
+                       c.n_bins, c.adj_gw);
     return hipGetLastError();
 }
 

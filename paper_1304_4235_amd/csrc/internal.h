@@ -295,7 +295,7 @@ struct Ctx {
     double* adj_pis = nullptr;   // [n_ray][n] softmax / S per ray
     double* adj_gnH = nullptr;   // [n] dL/dn_H, tree order
     double* adj_y = nullptr;     // [n] transposed product
-    double* adj_wpart = nullptr; // [chunks][n_bins] per-chunk bin partials
+    double* adj_wpart = nullptr; // [chunks + kAdjSlices][n_bins] per-chunk bin partials, then per-slice sums
     float2* adj_st = nullptr;    // [n_ray][n] per-ray S and T of the rate
     double* adj_ell = nullptr;   // [n] adjoint of ln Gamma at the current step
     double* adj_gw = nullptr;    // [n_bins] accumulated over steps
@@ -475,6 +475,7 @@ int64_t adj_waves(const Ctx& c);
 int64_t adj_chunks(const Ctx& c);
 // particles per partial of the reverse-mode weight gradient
 constexpr int64_t kAdjChunk = 256;
+constexpr int kAdjSlices = 64;           // second level of the weight-gradient sum
 
 // ---- launchers (rate.hip) ----
 hipError_t launch_init_state(Ctx& c, bool use_given);

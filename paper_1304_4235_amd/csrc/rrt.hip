@@ -1461,7 +1461,7 @@ int rrt_backward(rrt_ctx* x, const double* dL_dlnG, const double* dL_dx, double*
         c.adj_n = n;
         c.adj_nr = nr;
     }
-    HIP_OK(ws_alloc(c, &c.adj_wpart, (size_t)adj_chunks(c) * c.n_bins));
+    HIP_OK(ws_alloc(c, &c.adj_wpart, (size_t)(adj_chunks(c) + kAdjSlices) * c.n_bins));
     HIP_OK(ws_alloc(c, &c.adj_gw, (size_t)c.n_bins));
     HIP_OK(hipMemsetAsync(c.adj_gw, 0, sizeof(double) * c.n_bins, c.stream));
     HIP_OK(hipMemsetAsync(c.adj_gnH, 0, sizeof(double) * n, c.stream));

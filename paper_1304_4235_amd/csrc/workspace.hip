@@ -167,7 +167,7 @@ uint64_t workspace_bytes(int64_t n, int n_ray, int n_bins, int n_halo, int K, bo
             add(8 * nr);
             add(8 * nr);
             add(8 * (((m + 255) / 256) * 4));
-            add(8 * ((m + 255) / 256) * bins);
+            add(8 * ((m + 255) / 256 + kAdjSlices) * bins);
             add(8 * bins);
         }
     }
