@@ -124,6 +124,25 @@ def measured_traffic(workload: str, kernel_key: str):
     return None
 
 
+def measured_cache(workload: str, kernel_key: str):
+    """L1 and L2 hit rates and TA busy fraction of the kernel from the committed
+    cache-counter summary of this workload, only while the kernel's source is
+    the one the counters were taken with (else None)."""
+    f = os.path.join(ROOT, "profiles", f"cache_{workload}.json")
+    if kernel_key not in KERNEL_SOURCES or not os.path.exists(f):
+        return None
+    path, function, prefix = KERNEL_SOURCES[kernel_key]
+    for name, k in json.load(open(f))["kernels"].items():
+        if not name.startswith(prefix):
+            continue
+        if k.get("source_sha256") != kernel_source_sha256(path, function):
+            return None
+        return {"l2_hit_rate": k["l2_hit_rate"], "l2_miss_bytes": k["l2_miss_bytes_128"],
+                "l1_hit_rate": k["l1_hit_rate"], "ta_busy_frac": k["ta_busy_frac"],
+                "source": f"profiles/cache_{workload}.md"}
+    return None
+
+
 def cpu_model() -> str:
     cpu = platform.processor() or platform.machine()
     try:
@@ -260,6 +279,7 @@ def roofline_of(kernels, workload):
             "traffic": measured_traffic(workload, dom),
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
                             "copy-calibrated)",
+            "cache": measured_cache(workload, dom),
             "avg_launch_ms": k["avg_launch_ms"],
             "algorithmic_bytes_per_launch": k["algorithmic_bytes_per_launch"]}
 
