@@ -8,9 +8,10 @@
  * definitions, serially per source particle (OpenMP only spreads independent
  * source particles over threads; the arithmetic of each is unchanged).
  *
- * Build: gcc -O2 -fPIC -shared -ffp-contract=off -fno-fast-math -fopenmp
- * (no FMA contraction: the segment-sphere predicate below must round exactly
- * like the device predicate, operation for operation).
+ * Build: gcc -O2 -fPIC -shared -ffp-contract=off -fno-fast-math -mfma -fopenmp
+ * (no implicit contraction: the segment-sphere predicate below must round
+ * exactly like the device predicate, operation for operation; its fused
+ * multiply-adds are written out as fma(), which IEEE 754 defines exactly).
  *
  * What is computed, by section of the paper:
  *  - G_t, the truncated Gaussian kernel and its constants (Sec. 4.1.1, eq. Gt)
@@ -179,17 +180,20 @@ double orc_kernel_norm(double h, int32_t which)
 /* ------------------------------------------------------------------------- */
 /* Segment / kernel-sphere predicate.                                        */
 /* d = (r_j - r_p) + s B, s_par = d.u, t = clamp(s_par, 0, L),               */
-/* c = d - t u, hit <=> |c|^2 < h_j^2.  Fixed operation order, no FMA.       */
+/* c = d - t u, hit <=> |c|^2 < h_j^2.  Fixed operation order: each dot     */
+/* product starts with a product and adds the next terms by fused           */
+/* multiply-add (x, then y, then z); each c component is one fused          */
+/* multiply-add.                                                             */
 /* ------------------------------------------------------------------------- */
 static inline int seg_hit(const double d[3], const double u[3], double L, double h,
                           double* s_par)
 {
-    double sp = d[0] * u[0] + d[1] * u[1] + d[2] * u[2];
+    double sp = fma(d[2], u[2], fma(d[1], u[1], d[0] * u[0]));
     double t = sp < 0.0 ? 0.0 : (sp > L ? L : sp);
-    double cx = d[0] - t * u[0];
-    double cy = d[1] - t * u[1];
-    double cz = d[2] - t * u[2];
-    double D2 = cx * cx + cy * cy + cz * cz;
+    double cx = fma(-t, u[0], d[0]);
+    double cy = fma(-t, u[1], d[1]);
+    double cz = fma(-t, u[2], d[2]);
+    double D2 = fma(cz, cz, fma(cy, cy, cx * cx));
     *s_par = sp;
     return D2 < h * h;
 }

@@ -159,7 +159,8 @@ __host__ __device__ __forceinline__ uint32_t chunk_image_code(int sx, int sy, in
 
 // The canonical predicate (shared operation order with the FP64 reference):
 // d = (r_j - r_p) + s B ; s_par = d.u ; t = clamp(s_par, 0, L) ; c = d - t u ;
-// hit <=> |c|^2 < h^2.
+// hit <=> |c|^2 < h^2, with the dot products and c in fused multiply-adds as
+// written below (dot_u, norm2) and no other contraction.
 #pragma clang fp contract(off)
 // K/h^2 of one intersection: the chord integral of the kernel (eq. Gt) in
 // units of h, over h^2, C e^{-t^2 q^2} [erf(t z2) - erf(t z1)] / h^2.  sp = d.u
@@ -196,8 +197,21 @@ __device__ __forceinline__ float chord_factor(double sp, double b2, double h2, d
     return ih2 * (g * (e2 - e1));
 }
 
-// The pair's geometry in the canonical operation order: d = (r_j - r_p) + s B
-// and sp = d.u (the same arithmetic wherever a pair is evaluated).
+// The canonical operation order of the pair arithmetic (the same wherever a
+// pair is evaluated): a dot product with u, or a squared norm, starts with the
+// x product and adds y, then z, by fused multiply-add; a component of d - t u
+// is one fused multiply-add.  fma rounds once, as IEEE 754 defines it.
+__device__ __forceinline__ double dot_u(double d0, double d1, double d2, const double u[3])
+{
+    return fma(d2, u[2], fma(d1, u[1], d0 * u[0]));
+}
+
+__device__ __forceinline__ double norm2(double c0, double c1, double c2)
+{
+    return fma(c2, c2, fma(c1, c1, c0 * c0));
+}
+
+// The pair's geometry: d = (r_j - r_p) + s B and sp = d.u.
 struct PairGeom {
     double d0, d1, d2, sp;
 };
@@ -209,7 +223,7 @@ __device__ __forceinline__ PairGeom pair_geom(const float4 Q, double o0, double 
     pg.d0 = ((double)Q.x - o0) + sh[0];
     pg.d1 = ((double)Q.y - o1) + sh[1];
     pg.d2 = ((double)Q.z - o2) + sh[2];
-    pg.sp = pg.d0 * u[0] + pg.d1 * u[1] + pg.d2 * u[2];
+    pg.sp = dot_u(pg.d0, pg.d1, pg.d2, u);
     return pg;
 }
 
@@ -229,7 +243,7 @@ __device__ __forceinline__ PairGeom pair_geom_d(double qx, double qy, double qz,
         pg.d1 = pg.d1 + sh[1];
         pg.d2 = pg.d2 + sh[2];
     }
-    pg.sp = pg.d0 * u[0] + pg.d1 * u[1] + pg.d2 * u[2];
+    pg.sp = dot_u(pg.d0, pg.d1, pg.d2, u);
     return pg;
 }
 
@@ -238,9 +252,9 @@ __device__ __forceinline__ float hit_factor(const PairGeom& pg, const double u[3
                                             double L, const float4* __restrict__ t_erf,
                                             double gc, double ga)
 {
-    const double px = pg.d0 - pg.sp * u[0], py = pg.d1 - pg.sp * u[1],
-                 pz = pg.d2 - pg.sp * u[2];
-    const double b2 = px * px + py * py + pz * pz;
+    const double px = fma(-pg.sp, u[0], pg.d0), py = fma(-pg.sp, u[1], pg.d1),
+                 pz = fma(-pg.sp, u[2], pg.d2);
+    const double b2 = norm2(px, py, pz);
     const double hj = (double)hf;
     return chord_factor(pg.sp, b2, hj * hj, L, hf, t_erf, gc, ga);
 }
@@ -353,19 +367,20 @@ k_trace(const Node* __restrict__ nodes, const float4* __restrict__ p4,
                     double d0 = ((double)Q.x - rp[0]) + sh[0];
                     double d1 = ((double)Q.y - rp[1]) + sh[1];
                     double d2 = ((double)Q.z - rp[2]) + sh[2];
-                    double sp = d0 * u[0] + d1 * u[1] + d2 * u[2];
+                    double sp = dot_u(d0, d1, d2, u);
                     double tt = sp < 0.0 ? 0.0 : (sp > L ? L : sp);
-                    double c0 = d0 - tt * u[0];
-                    double c1 = d1 - tt * u[1];
-                    double c2 = d2 - tt * u[2];
-                    double D2 = c0 * c0 + c1 * c1 + c2 * c2;
+                    double c0 = fma(-tt, u[0], d0);
+                    double c1 = fma(-tt, u[1], d1);
+                    double c2 = fma(-tt, u[2], d2);
+                    double D2 = norm2(c0, c1, c2);
                     double hj = (double)Q.w;
                     double h2 = hj * hj;
                     if (!(D2 < h2)) continue;
                     ++cnt;
                     if (MODE == kModeCount || MODE == kModeStats) continue;
-                    double px = d0 - sp * u[0], py = d1 - sp * u[1], pz = d2 - sp * u[2];
-                    double b2 = px * px + py * py + pz * pz;
+                    double px = fma(-sp, u[0], d0), py = fma(-sp, u[1], d1),
+                           pz = fma(-sp, u[2], d2);
+                    double b2 = norm2(px, py, pz);
                     const float gk = chord_factor(sp, b2, h2, L, Q.w, t_erf, gc, ga);
                     if (MODE == kModeRecord) {
                         if (w < out.hit_cap) {
@@ -787,10 +802,10 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
                                                           s_o[64 + r], s_o[128 + r], sh, u);
                 // clamp to [0, L]; a zero's sign cannot change |c|^2
                 double tt = fmin(fmax(pg.sp, 0.0), Lc);
-                double c0 = pg.d0 - tt * u[0];
-                double c1 = pg.d1 - tt * u[1];
-                double c2 = pg.d2 - tt * u[2];
-                double D2 = c0 * c0 + c1 * c1 + c2 * c2;
+                double c0 = fma(-tt, u[0], pg.d0);
+                double c1 = fma(-tt, u[1], pg.d1);
+                double c2 = fma(-tt, u[2], pg.d2);
+                double D2 = norm2(c0, c1, c2);
                 double hj = pq[3];
                 double h2 = hj * hj;
                 const bool in = D2 < h2;
