@@ -791,8 +791,6 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
             // (a select per component would cost more than the adds it saves)
             auto pair_loop = [&](auto shifted_tag) {
             constexpr bool kShifted = decltype(shifted_tag)::value;
-            // canonical here, so the clamp below needs no canonicalisation per pair
-            const double Lc = __builtin_canonicalize(L);
             for (int t = lane; t < pairs; t += 64) {
                 const int q = (int)(((float)t + 0.5f) * rk);
                 const int r = t - q * k_hit;
@@ -801,7 +799,7 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
                 const PairGeom pg = pair_geom_d<kShifted>(pq[0], pq[1], pq[2], s_o[r],
                                                           s_o[64 + r], s_o[128 + r], sh, u);
                 // clamp to [0, L]; a zero's sign cannot change |c|^2
-                double tt = fmin(fmax(pg.sp, 0.0), Lc);
+                double tt = fmin(fmax(pg.sp, 0.0), L);
                 double c0 = fma(-tt, u[0], pg.d0);
                 double c1 = fma(-tt, u[1], pg.d1);
                 double c2 = fma(-tt, u[2], pg.d2);
