@@ -248,7 +248,7 @@ int rrt_update_equilibrium(rrt_ctx* ctx, double* x_out, double* max_dx_out);
  * per spectrum), in place of the paper's 4-D table of the same function.
  * Each ray's slab is lit by the ray's share, 1/n_ray of the far-attenuated
  * spectrum, and Gamma = sum_k Gamma_k (eq. gammashld with 4 pi inside w; the
- * weighting the paper's two-sided slab discussion of Sec. 5.2 implies).
+ * weighting the paper's two-sided slab discussion of Sec. 5.3 implies).
  * Recorded paths are dropped when the scheme changes; the near columns take
  * 8 bytes per ray more workspace.  While the near/far scheme is set,
  * rrt_forward, rrt_backward, rrt_iterate_halos and update rules other than

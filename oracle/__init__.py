@@ -595,7 +595,7 @@ def plane_slab_profile(sigma, w, nH, T, depth, n_points=4000):
 def two_sided_slab_profile(sigma, w, nH, T, depth, n_points=4000, tol=1e-12,
                            max_iter=10000):
     """Neutral fraction against height z (kpc) in a uniform plane slab lit
-    equally on both faces (the two-sided slab of Sec. 5.2): each height takes
+    equally on both faces (the two-sided slab of Sec. 5.3): each height takes
     half the rate the spectrum gives through the HI column below it and half
     through the column above, sum_b w_b sigma_b e^{-sigma_b N}, and x = x_- of
     that rate; iterated from the thin state (Jacobi, columns by the trapezoid
@@ -628,7 +628,7 @@ def two_sided_slab_profile(sigma, w, nH, T, depth, n_points=4000, tol=1e-12,
 
 
 # ---------------------------------------------------------------------------
-# spherically symmetric reference (the spherical solver of the halo test, Sec. 5.3)
+# spherically symmetric reference (the spherical solver of the halo test, Sec. 5.4)
 # ---------------------------------------------------------------------------
 def _lse(v, axis, wts=None):
     m = np.max(v, axis=axis, keepdims=True)

@@ -1,4 +1,4 @@
-"""Physics beyond parity: the paper's slab setting (Sec. 5.1, 5.2) with
+"""Physics beyond parity: the paper's slab setting (Sec. 5.2, 5.3) with
 synthetic inputs.  A jittered lattice stands in for the paper's glass, and a
 grey bin or eight power-law bins for its UV background; the reference is the
 plane-slab profile (the analytic slab of Appendix C.4 for one bin), not the
@@ -99,13 +99,13 @@ def _halo_errors(wl, scheme, r_ref, x_ref):
 def test_isothermal_halo_matches_spherical_profile():
     """The 262144-particle halo with its 12 rays and 128 bins against the
     spherically symmetric solution of the same cored sphere (the halo test's
-    spherical solver, Sec. 5.3: 120 shells, 32 directions, the same ray
+    spherical solver, Sec. 5.4: 120 shells, 32 directions, the same ray
     length), per radial bin of the median error of x:
       * the near/far scheme (each near slab lit by its ray's share of the
         spectrum, exact for beams): within 0.03 dex in the neutral core and
         the thin outskirts, more neutral than the sphere across the front,
         where each of the 12 slabs misses the other rays' light (the error the
-        paper describes for its halo test, Sec. 5.3);
+        paper describes for its halo test, Sec. 5.4);
       * the plain scheme: more neutral than the sphere at the front too, by
         less (measured +0.08 against +0.97 dex)."""
     wl = W.make_config(1)

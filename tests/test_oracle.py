@@ -989,7 +989,7 @@ def test_plane_slab_profile_power_law_is_monotone_and_harder():
 
 
 # ---------------------------------------------------------------------------
-# spherical reference (the halo test, Sec. 5.3)
+# spherical reference (the halo test, Sec. 5.4)
 # ---------------------------------------------------------------------------
 def test_sphere_columns_uniform_sphere_chords():
     """Columns through a uniform sphere with x = 1 are n_H times the chord from
@@ -1068,7 +1068,7 @@ def test_near_far_rays_light_their_slabs_with_their_share(bins):
     exactly; a ray that is blocked contributes nothing, and the other ray's
     slab is the one-sided slab lit by half the spectrum (the error the paper
     reads off its two-sided slab vanishes once one ray meets a high optical
-    depth, Sec. 5.2)."""
+    depth, Sec. 5.3)."""
     N = 3e20
     thin, *_ = _near_far_lnG(4, [0.0] * 4, [0.0] * 4, bins=bins)
     assert abs(thin - math.log(1e-12)) < 1e-12

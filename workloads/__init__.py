@@ -264,13 +264,13 @@ def one_sided_slab(n_xy: int = 24, n_z: int = 32, depth: float = 200.0, n_H: flo
                    max_iter: int = 400, name: str = "one_sided_slab",
                    faces: int = 1) -> Workload:
     """A slab of uniform n_H and T lit on one face: the setting of the paper's
-    slab tests (Sec. 5.1, 5.2), with a jittered lattice standing in for its
+    slab tests (Sec. 5.2, 5.3), with a jittered lattice standing in for its
     glass and a grey or power-law spectrum for its UV background.
 
     n_xy x n_xy x n_z particles with spacing depth / n_z fill 0 <= z <= depth
     (isolated: no periodic images).  Every particle casts one ray, along +z
     towards the lit face at z = depth, of length 2 depth; with faces = 2 a
-    second one along -z, so that both faces are lit (Sec. 5.2's two-sided
+    second one along -z, so that both faces are lit (Sec. 5.3's two-sided
     slab).  One bin at 13.6 eV (n_bins = 1), else n_bins power-law bins
     (J ~ nu^-1.5), each spectrum carrying the optically thin rate gamma_thin.
     """
