@@ -37,6 +37,11 @@ constexpr uint32_t kNoChunk = 0xffffffffu;
 constexpr int kPoolSlices = 1024;          // independent allocation counters
 constexpr int kCtrStride = 16;             // counters 128 bytes apart
 constexpr int kSliceTries = 16;            // slices a chunk request tries
+// Chunks a wave of the persistent recording walk takes from the pool at once;
+// what it holds when the walk ends stays unused, at most kCacheBlock chunks for
+// each of 256 CUs x 32 waves (kCacheAllowance, added to the pool).
+constexpr uint32_t kCacheBlock = 16;
+constexpr uint64_t kCacheAllowance = 256ull * 32 * kCacheBlock;
 // column evaluations over one set of recorded paths before its row tiles are
 // built (the build costs about as much as a few evaluations)
 constexpr int kTileAfter = 8;

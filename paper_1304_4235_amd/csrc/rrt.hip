@@ -311,7 +311,8 @@ void free_paths(Ctx& c)
 
 // Chunks of the one-walk pool for a recording expected to hold `entries`
 // entries over n_rows rays: pool_scale x entries plus half a chunk per ray,
-// rounded up to whole slices (or the tuned pool size).
+// plus what the walk's waves may hold unused in their caches, rounded up to
+// whole slices (or the tuned pool size).
 uint64_t pool_chunks_for(const Ctx& c, uint64_t entries, int64_t n_rows)
 {
     uint64_t chunks;
@@ -320,7 +321,7 @@ uint64_t pool_chunks_for(const Ctx& c, uint64_t entries, int64_t n_rows)
     } else {
         const uint64_t e = (uint64_t)((double)entries * c.pool_scale) +
                            (uint64_t)n_rows * (kChunkLen / 2);
-        chunks = (e + kChunkLen - 1) / kChunkLen;
+        chunks = (e + kChunkLen - 1) / kChunkLen + kCacheAllowance;
     }
     const uint64_t per_slice =
         std::min<uint64_t>((chunks + kPoolSlices - 1) / kPoolSlices, 0xfffffff0ull / kPoolSlices);

@@ -420,30 +420,53 @@ k_trace(const Node* __restrict__ nodes, const float4* __restrict__ p4,
 }
 // LDS written by some lanes of a wave and read by others: order the accesses
 // within the wave (no block barrier needed, the wave runs in lockstep)
-// One pool chunk for every lane with want: one allocation in the wave's slice,
-// then, for lanes it could not serve, in further slices (stride 97, odd, so
-// kSliceTries distinct ones) while any has room.  Returns whether this lane
-// got one (its index in nc).
+// One pool chunk for every lane with want, handed out from the wave's cache:
+// the range [c_next, c_end) of chunk indices the wave has taken and not yet
+// given out (wave-uniform; the persistent walk keeps it across packets).  An
+// empty cache takes a block of max(block, lanes still waiting) chunks with one
+// atomic, from the wave's slice first, then from further slices (stride 97,
+// odd, so kSliceTries distinct ones); a slice's last, partial block is used as
+// far as it goes.  Returns whether this lane got one (its index in nc).
 __device__ __forceinline__ bool take_chunk(bool want, uint32_t slice, int lane,
                                            uint64_t lt_mask, unsigned long long* pool_ctr,
-                                           uint64_t slice_chunks, uint32_t& nc)
+                                           uint64_t slice_chunks, uint32_t block,
+                                           uint32_t& c_next, uint32_t& c_end, uint32_t& nc)
 {
     uint64_t need = __builtin_amdgcn_ballot_w64(want);
     bool got = false;
-    for (int t = 0; t < kSliceTries && need; ++t) {
-        const uint32_t sl = (slice + 97u * (uint32_t)t) % kPoolSlices;
-        const int leader = __ffsll((unsigned long long)need) - 1;
-        unsigned long long base = 0;
-        if (lane == leader)
-            base = atomicAdd(pool_ctr + (size_t)sl * kCtrStride, (unsigned long long)__popcll(need));
-        base = __shfl(base, leader, 64);
+    int t = 0;
+    while (need) {
+        const uint32_t k = (uint32_t)__popcll(need);
+        const uint32_t avail = c_end - c_next;
+        if (avail == 0) {
+            if (t == kSliceTries) break;
+            const uint32_t sl = (slice + 97u * (uint32_t)t) % kPoolSlices;
+            ++t;
+            const uint32_t n_take = k > block ? k : block;
+            const int leader = __ffsll((unsigned long long)need) - 1;
+            unsigned long long base = 0;
+            if (lane == leader)
+                base = atomicAdd(pool_ctr + (size_t)sl * kCtrStride, (unsigned long long)n_take);
+            base = __shfl(base, leader, 64);
+            const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)base);
+            const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
+            const uint64_t b = ((uint64_t)hi << 32) | lo;
+            if (b < slice_chunks) {
+                const uint64_t room = slice_chunks - b;
+                c_next = (uint32_t)(sl * slice_chunks + b);
+                c_end = c_next + (uint32_t)(room < n_take ? room : n_take);
+            }
+            continue;
+        }
+        // the lowest-ranked waiting lanes take what the cache holds
         if (want && !got) {
-            const unsigned long long local = base + __popcll(need & lt_mask);
-            if (local < slice_chunks) {
+            const uint32_t r = (uint32_t)__popcll(need & lt_mask);
+            if (r < avail) {
                 got = true;
-                nc = (uint32_t)(sl * slice_chunks + local);
+                nc = c_next + r;
             }
         }
+        c_next += k < avail ? k : avail;
         need = __builtin_amdgcn_ballot_w64(want && !got);
     }
     return got;
@@ -568,6 +591,8 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
     const uint64_t lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
     const int64_t waves_per_dir = (g.n + 63) / 64;
     int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    // chunk mode: the wave's cache of pool chunks (empty to start)
+    uint32_t c_next = 0, c_end = 0;
     for (;;) {                                               // packets of this wave
     if (PQ) {
         unsigned long long w = 0;
@@ -742,7 +767,8 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
                 if (wave_ballot(want)) {
                     uint32_t nc = 0;
                     const bool got = take_chunk(want, slice, lane, lt_mask, out.pool_ctr,
-                                                out.slice_chunks, nc);
+                                                out.slice_chunks, PQ ? kCacheBlock : 1u,
+                                                c_next, c_end, nc);
                     if (want && got) {
                         if (cur == kNoChunk) {
                             out.row_first[gid] = nc;
