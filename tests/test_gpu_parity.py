@@ -611,8 +611,10 @@ def test_one_pass_recording_equals_two_passes(room):
     bit-identical columns over them and the same counts.  The pool is capped
     from the first recording's count so that the second recording takes one
     pass whatever the intersections per ray; a pool of about 2000 chunks runs
-    short at once, and the recording falls back to the second walk with the
-    counts it has.  The recording statistics say which walks ran: the first
+    short at once (two chunks per slice, so every block of chunks a wave takes
+    is a slice's partial last one), and the recording falls back to the second
+    walk with the counts it has.  The recording statistics say which walks
+    ran: the first
     recording follows the count the Solver makes to size its path buffer."""
     wl = W.isothermal_halo(n=16384, seed=21)
     x = np.minimum(oracle.x_thin(wl) * np.geomspace(1, 1e4, wl.n), 0.999)
