@@ -460,6 +460,7 @@ def run_batch(name, args, steps=1, warmup=1):
     n_halo = len(wl.halo_offsets) - 1
     say(f"workload {wl.name}: {n_halo} halos, n={wl.n}")
     tuned = autotune.tune(wl, verbose=True, reps=2) if args.tune else None
+    torch.cuda.empty_cache()            # the solver sizes its path buffer from free memory
     best = tuned["best"] if tuned else {}
     s = Solver.from_workload(wl, build=False)
     if best:

@@ -146,9 +146,10 @@ def test_batched_solve_over_row_tiles_matches_plain():
 
 
 def test_autotuner_picks_change_no_result(tmp_path):
-    """The autotuner times its knobs on a batch and caches the picks; the picks
-    change the launch shapes only: the same iterations per halo and the same
-    states (to summation order) as the defaults."""
+    """The autotuner times its knobs on a batch and caches the picks, keeping
+    the library's defaults instead when one solve of the whole batch is faster
+    with them; the picks change the launch shapes only: the same iterations per
+    halo and the same states (to summation order) as the defaults."""
     import json
     from paper_1304_4235_amd import autotune
     wl, parts = _batch(SIZES, PEAKS)
@@ -158,7 +159,11 @@ def test_autotuner_picks_change_no_result(tmp_path):
     res = autotune.tune(wl, space=space, reps=1, cache_path=cache, use_cache=False)
     best = res["best"]
     assert set(best) == {"leaf", "trace_block", "packet", "path_group", "per_launch"}
-    assert best["leaf"] in space["leaf"] and best["per_launch"] in space["per_launch"]
+    whole = res["whole"]
+    if whole["defaults_ms"] < whole["picks_ms"]:
+        assert best == autotune.DEFAULTS
+    else:
+        assert best["leaf"] in space["leaf"] and best["per_launch"] in space["per_launch"]
     again = autotune.tune(wl, space=space, cache_path=cache, use_cache=True)
     assert again == json.loads(json.dumps(res))                # served from the cache
     ref = _solver(wl).iterate_halos(200, 1e-3, per_launch=8)
