@@ -11,10 +11,9 @@ of each knob:
 * iterations per graph replay of the batched fixed point.
 
 The phases run on a sample of at most max_n particles, which need not rank
-the knobs as the whole workload does (on the 64-halo batch the sample's picks
-solved the whole batch in 8.25 s against 7.21 s with the defaults), so one
-solve of the whole workload with the picks and one with the library's
-defaults decide between them.
+the knobs as the whole workload does, so one solve of the whole workload with
+the picks and one with the library's defaults decide between them (on the
+64-halo batch: 7.25 s with the picks, 7.22 s with the defaults).
 
 None of the knobs changes a result.  Results are cached in a JSON file keyed
 by the device name and a coarse description of the workload.
