@@ -254,6 +254,25 @@ def test_workspace_grows_by_moving_the_context():
     np.testing.assert_array_equal(ra["x"].cpu().numpy(), rb["x"].cpu().numpy())
 
 
+def test_large_exports_grow_a_fragmented_workspace():
+    """Exporting the recorded paths and the hit lists of 4096 sources of the
+    full halo stages tens of MB in one piece: the binding grows the workspace
+    past its end when a request finds no piece large enough (the used blocks
+    are spread), and both exports agree on every ray's count."""
+    wl = W.make_config(1)
+    s = _solver(wl)
+    s.compute_columns()
+    src = s.tree()["perm"][:4096].astype(np.int64)
+    before = s.workspace_info()["ws_size"]
+    off_p, hj_p, hf_p = s.path_rows(src)
+    off_h, hj_h, hi_h, hf_h = s.hits_rows(src)
+    assert s.workspace_info()["ws_size"] > before
+    assert off_p.size == off_h.size == 4096 * wl.n_ray + 1
+    np.testing.assert_array_equal(off_p, off_h)
+    assert hj_p.size == off_p[-1] > 0
+    s.close()
+
+
 def test_too_small_workspace_is_an_error_not_a_fault():
     from paper_1304_4235_amd import RRTError, Solver, lib
     s = Solver(10.0)
