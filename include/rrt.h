@@ -214,6 +214,11 @@ int rrt_set_spectrum(rrt_ctx* ctx, int32_t n_bins, const double* sigma, const do
 int rrt_build_tree(rrt_ctx* ctx);
 
 /* Columns for the current state x (Sec. 4.1.1, eq. colden): N[p][k] in cm^-2.
+ * Ray k of source p meets particle j (and each periodic image s of it) when,
+ * with d = (r_j - r_p) + s B, s_par = d.u, t = clamp(s_par, 0, l_ray) and
+ * c = d - t u, |c|^2 < h_j^2 strictly; FP64, the two dot products as the x
+ * product followed by fused multiply-adds of y and z, each component of c one
+ * fused multiply-add, nothing else contracted, so the hit sets are exact.
  * N_out: device double[n][n_ray] in input particle order, or NULL to keep the
  * columns internal.  n_hits_out: host, total ray-particle intersections of this
  * call (counting each periodic image separately), or NULL (then no sync). */
