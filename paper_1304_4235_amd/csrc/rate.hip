@@ -26,6 +26,7 @@ namespace rrt {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kBlockWaves = kBlock / 64;
 
 __global__ void k_init_state(const int32_t* __restrict__ perm, const float* __restrict__ T,
                              const double* __restrict__ x_init, const float* __restrict__ nH_s,
@@ -194,13 +195,9 @@ k_gamma(const double* __restrict__ N, int64_t n, int n_ray, int n_bins,
         }
     }
     if (update_x) {
-        // one atomic per wave for each count, and for the flag
+        // the counts, the flag and the maximum are reduced per block, so each
+        // takes one atomic per block on its (single) global word
         const uint64_t ba = __ballot(conv_a), br = __ballot(conv_r), bb = __ballot(bad);
-        if ((threadIdx.x & 63) == 0) {
-            if (ba) atomicAdd(maxdx_bits + (kRedConvAbs - kRedMaxDx), (unsigned long long)__popcll(ba));
-            if (br) atomicAdd(maxdx_bits + (kRedConvRel - kRedMaxDx), (unsigned long long)__popcll(br));
-            if (bb) atomicOr(maxdx_bits + (kRedNumeric - kRedMaxDx), 1ull);
-        }
         if (seg_maxdx) {
             // per-halo maximum: one atomic per wave when the wave holds one halo
             const int h0 = __shfl(h, 0, 64);
@@ -214,8 +211,28 @@ k_gamma(const double* __restrict__ N, int64_t n, int n_ray, int n_bins,
             }
         }
         for (int off = 32; off > 0; off >>= 1) dx = fmax(dx, __shfl_xor(dx, off, 64));
-        if ((threadIdx.x & 63) == 0)
-            atomicMax(maxdx_bits, (unsigned long long)__double_as_longlong(dx));
+        __shared__ unsigned long long s_red[kBlockWaves][4];
+        const int wv = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0) {
+            s_red[wv][0] = (unsigned long long)__popcll(ba);
+            s_red[wv][1] = (unsigned long long)__popcll(br);
+            s_red[wv][2] = bb ? 1ull : 0ull;
+            s_red[wv][3] = (unsigned long long)__double_as_longlong(dx);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long na = 0, nr = 0, nb = 0, mx = 0;
+            for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+                na += s_red[w][0];
+                nr += s_red[w][1];
+                nb |= s_red[w][2];
+                mx = s_red[w][3] > mx ? s_red[w][3] : mx;      // dx >= 0: bits order as values
+            }
+            if (na) atomicAdd(maxdx_bits + (kRedConvAbs - kRedMaxDx), na);
+            if (nr) atomicAdd(maxdx_bits + (kRedConvRel - kRedMaxDx), nr);
+            if (nb) atomicOr(maxdx_bits + (kRedNumeric - kRedMaxDx), 1ull);
+            atomicMax(maxdx_bits, mx);
+        }
     }
 }
 
@@ -284,8 +301,15 @@ __global__ void k_update_x(const double* __restrict__ G, int64_t n, const float*
         mux[i] = (float)(mu_s[i] * xn);
     }
     for (int off = 32; off > 0; off >>= 1) dx = fmax(dx, __shfl_xor(dx, off, 64));
-    if ((threadIdx.x & 63) == 0)
-        atomicMax(maxdx_bits, (unsigned long long)__double_as_longlong(dx));
+    // one atomic per block on the single word
+    __shared__ unsigned long long s_mx[kBlockWaves];
+    if ((threadIdx.x & 63) == 0) s_mx[threadIdx.x >> 6] = (unsigned long long)__double_as_longlong(dx);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long mx = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) mx = s_mx[w] > mx ? s_mx[w] : mx;
+        atomicMax(maxdx_bits, mx);
+    }
 }
 
 __global__ void k_mux(const double* __restrict__ mu_s, const double* __restrict__ x_s, int64_t n,

@@ -593,6 +593,9 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
     int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     // chunk mode: the wave's cache of pool chunks (empty to start)
     uint32_t c_next = 0, c_end = 0;
+    // the wave's intersections over its packets, added to the total once (one
+    // atomic per wave rather than per packet on the single counter)
+    uint64_t hits_wave = 0;
     for (;;) {                                               // packets of this wave
     if (PQ) {
         unsigned long long w = 0;
@@ -601,7 +604,10 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
     }
     // the wave's direction and image range are uniform: scalar registers
     const int k = __builtin_amdgcn_readfirstlane((int)(wave / waves_per_dir));
-    if (k >= g.n_ray) return;                                // whole wave
+    if (k >= g.n_ray) {                                      // whole wave
+        if (lane == 0 && hits_wave) atomicAdd(out.hits_total, (unsigned long long)hits_wave);
+        return;
+    }
     const int ps = (int)((wave - (int64_t)k * waves_per_dir) * 64 + lane);
     // the ray's output row: the ray itself, or its sampled source's place
     int64_t slot = (int64_t)k * g.n + ps;
@@ -920,7 +926,7 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
     }
     uint64_t c64 = cnt;
     for (int off = 32; off > 0; off >>= 1) c64 += __shfl_xor(c64, off, 64);
-    if (lane == 0 && c64) atomicAdd(out.hits_total, (unsigned long long)c64);
+    hits_wave += c64;
     const uint64_t rays = MODE == kModeStats ? (uint64_t)__popcll(wave_ballot(active)) : 0;
     if (MODE == kModeStats && lane == 0) {
         atomicAdd(out.stats + 0, (unsigned long long)rays);
@@ -930,7 +936,10 @@ k_trace_wave(const Node* __restrict__ nodes, const float4* __restrict__ p4,
         atomicAdd(out.stats + 4, (unsigned long long)st_pairs);
         atomicAdd(out.stats + 5, (unsigned long long)c64);
     }
-    if (!PQ) return;
+    if (!PQ) {
+        if (lane == 0 && hits_wave) atomicAdd(out.hits_total, (unsigned long long)hits_wave);
+        return;
+    }
     }   // packets of this wave
 }
 
