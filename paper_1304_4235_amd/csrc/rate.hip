@@ -198,21 +198,25 @@ k_gamma(const double* __restrict__ N, int64_t n, int n_ray, int n_bins,
         // the counts, the flag and the maximum are reduced per block, so each
         // takes one atomic per block on its (single) global word
         const uint64_t ba = __ballot(conv_a), br = __ballot(conv_r), bb = __ballot(bad);
+        __shared__ unsigned long long s_red[kBlockWaves][4];
+        __shared__ int s_hw[kBlockWaves];
+        __shared__ unsigned long long s_hm[kBlockWaves];
+        const int wv = threadIdx.x >> 6;
         if (seg_maxdx) {
-            // per-halo maximum: one atomic per wave when the wave holds one halo
+            // per-halo maximum: a wave that holds one halo passes its maximum
+            // to the block (below); the lanes of a wave across halos add theirs
             const int h0 = __shfl(h, 0, 64);
-            if (h0 >= 0 && __ballot(h != h0 && h >= 0) == 0) {
-                double m = dx;
-                for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
-                if ((threadIdx.x & 63) == 0 && m > 0.0)
-                    atomicMax(seg_maxdx + h0, (unsigned long long)__double_as_longlong(m));
-            } else if (h >= 0 && dx > 0.0) {
+            const bool one = h0 >= 0 && __ballot(h != h0 && h >= 0) == 0;
+            double m = dx;
+            for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+            if (!one && h >= 0 && dx > 0.0)
                 atomicMax(seg_maxdx + h, (unsigned long long)__double_as_longlong(dx));
+            if ((threadIdx.x & 63) == 0) {
+                s_hw[wv] = one ? h0 : -1;
+                s_hm[wv] = (unsigned long long)__double_as_longlong(m);
             }
         }
         for (int off = 32; off > 0; off >>= 1) dx = fmax(dx, __shfl_xor(dx, off, 64));
-        __shared__ unsigned long long s_red[kBlockWaves][4];
-        const int wv = threadIdx.x >> 6;
         if ((threadIdx.x & 63) == 0) {
             s_red[wv][0] = (unsigned long long)__popcll(ba);
             s_red[wv][1] = (unsigned long long)__popcll(br);
@@ -220,6 +224,19 @@ k_gamma(const double* __restrict__ N, int64_t n, int n_ray, int n_bins,
             s_red[wv][3] = (unsigned long long)__double_as_longlong(dx);
         }
         __syncthreads();
+        if (seg_maxdx && threadIdx.x == 0) {
+            // one atomic per run of the block's waves in the same halo
+            const int nw = (int)(blockDim.x >> 6);
+            for (int w = 0; w < nw;) {
+                const int hh = s_hw[w];
+                unsigned long long mx = s_hm[w];
+                int v = w + 1;
+                for (; v < nw && s_hw[v] == hh; ++v) mx = s_hm[v] > mx ? s_hm[v] : mx;
+                if (hh >= 0 && __longlong_as_double((long long)mx) > 0.0)
+                    atomicMax(seg_maxdx + hh, mx);
+                w = v;
+            }
+        }
         if (threadIdx.x == 0) {
             unsigned long long na = 0, nr = 0, nb = 0, mx = 0;
             for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
